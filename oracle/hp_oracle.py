@@ -1,0 +1,458 @@
+"""Plain FP64 CPU oracle of the q-resolved DFPT Hubbard response.
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+Conventions (the paper defers these to its Ref. Timrov 2018; the readings
+are listed in the design notes of the repository):
+
+* lattice-periodic functions: u(r) = Omega^{-1/2} sum_G c(G) e^{iG.r};
+  on grid point r_j the dimensionless field psi(r_j) = sum_G c(G) e^{iG.r_j}
+  is N_r * ifftn of the coefficients scattered to (m mod N);
+* the local potential acts on the grid: (V c)(G) = fftn(V psi)/N_r at G, which
+  equals the matrix V_hat[(m - m') mod N] with V_hat = fftn(V)/N_r;
+* spin-unpolarized closed shell: occupations and densities carry a factor 2;
+* time reversal folds the -q partner into the +q term (paper, text after
+  Eq. 14), giving the factor 4 = 2 (spin) x 2 (time reversal) in the response
+  density and the two-term form of Eq. 13.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+import scipy.fft as sfft
+
+from . import pz81
+
+FOUR_PI = 4.0 * math.pi
+
+
+@dataclass
+class ScfParams:
+    """Controls of the self-consistent Sternheimer loop (the paper's inputhp
+    convergence keywords: conv_thr_chi, niter_max, alpha_mix, nmix)."""
+    cg_tol: float = 1e-12            # per band ||r|| / ||b||
+    conv_thr_chi: float = 1e-12      # max |chi(q)_it - chi(q)_it-1| (Ha^-1)
+    conv_thr_v: float = 1e-10        # ||dV_out - dV_in|| / ||dV_out||
+    niter_max: int = 100
+    alpha_mix: float = 0.3
+    nmix: int = 4
+    max_cg_iter: int = 2000
+    method: str = "cg"               # "cg" or "direct" (dense solve per band)
+    hxc: bool = True                 # False: frozen Hxc (then chi = chi0)
+    alpha_shift: Optional[float] = None   # override of the Eq. 15 shift
+
+
+def _fftfreq_int(n: int) -> np.ndarray:
+    j = np.arange(n)
+    return np.where(j < (n + 1) // 2, j, j - n)
+
+
+class Oracle:
+    """One ground state (synth.GroundState-like object) and the linear-response
+    machinery of Eqs. 12-18 on top of it."""
+
+    def __init__(self, gs, cache_limit_bytes: float = 2e9):
+        self.gs = gs
+        self.fft = tuple(int(x) for x in gs.fft)
+        self.nr = int(np.prod(self.fft))
+        self.cell = np.asarray(gs.cell, dtype=np.float64)
+        self.omega = float(abs(np.linalg.det(self.cell)))
+        self.bvec = 2.0 * math.pi * np.linalg.inv(self.cell).T
+        self.n_occ = int(gs.n_occ)
+        self.n_hub = int(gs.n_hub)
+        self.kpts = gs.kpts
+        self.n_mesh = int(gs.n_mesh)
+        self.fxc = pz81.f_xc(gs.rho0)
+        # alpha = 2 (max - min) over the occupied energies of every loaded entry
+        # (paper, text after Eq. 18); floor 0.01 Ha.
+        emax = max(float(e.eps.max()) for e in self.kpts)
+        emin = min(float(e.eps.min()) for e in self.kpts)
+        self.alpha = max(2.0 * (emax - emin), 0.01)
+        self._psi_cache: Dict[int, np.ndarray] = {}
+        self._cache_bytes = 0.0
+        self._cache_limit = cache_limit_bytes
+        self._dense: Dict[int, np.ndarray] = {}
+        self._kin: Dict[int, np.ndarray] = {}
+
+    # ------------------------------------------------------------------ grids
+    def grid_index(self, ie: int, g0=(0, 0, 0)) -> np.ndarray:
+        """Linear grid index of each plane wave of entry ie, Miller indices shifted by -g0."""
+        m = (self.kpts[ie].miller - np.asarray(g0, dtype=np.int64)[None, :]) % np.array(self.fft)
+        return np.ravel_multi_index(tuple(m.T), self.fft)
+
+    def to_real(self, c: np.ndarray, idx: np.ndarray) -> np.ndarray:
+        """psi(r_j) = sum_G c(G) e^{iG.r_j} for each row of c; returns (nb, N1, N2, N3)."""
+        c = np.atleast_2d(c)
+        g = np.zeros((c.shape[0], self.nr), dtype=np.complex128)
+        g[:, idx] = c
+        return sfft.ifftn(g.reshape((c.shape[0],) + self.fft), axes=(1, 2, 3), workers=-1) * self.nr
+
+    def to_recip(self, f: np.ndarray, idx: np.ndarray) -> np.ndarray:
+        """c(G) = (1/N_r) sum_j f(r_j) e^{-iG.r_j} at the plane waves idx; f is (nb, N1, N2, N3)."""
+        g = sfft.fftn(f, axes=(1, 2, 3), workers=-1).reshape(f.shape[0], self.nr) / self.nr
+        return g[:, idx]
+
+    def psi_r(self, ie: int) -> np.ndarray:
+        if ie in self._psi_cache:
+            return self._psi_cache[ie]
+        p = self.to_real(self.kpts[ie].u, self.grid_index(ie))
+        if self._cache_bytes + p.nbytes <= self._cache_limit:
+            self._psi_cache[ie] = p
+            self._cache_bytes += p.nbytes
+        return p
+
+    def kinetic(self, ie: int) -> np.ndarray:
+        if ie not in self._kin:
+            e = self.kpts[ie]
+            p = (e.miller + e.k_frac[None, :]) @ self.bvec
+            self._kin[ie] = 0.5 * np.einsum("ij,ij->i", p, p)
+        return self._kin[ie]
+
+    # ----------------------------------------------------- Hamiltonian (Eq. 15)
+    def h_apply(self, ie: int, X: np.ndarray) -> np.ndarray:
+        """H_k X for rows X on entry ie: kinetic + V_loc on the grid + sum_i D_i |beta_i><beta_i|
+        (norm-conserving pseudopotentials; the Hubbard potential is zero in the
+        unperturbed state used here)."""
+        e = self.kpts[ie]
+        idx = self.grid_index(ie)
+        out = self.kinetic(ie)[None, :] * X
+        out = out + self.to_recip(self.to_real(X, idx) * self.gs.vloc[None], idx)
+        proj = X @ e.beta.conj().T            # <beta_i|x> for every row
+        out = out + (proj * self.gs.d_kb[None, :]) @ e.beta
+        return out
+
+    def h_dense(self, ie: int) -> np.ndarray:
+        """Dense H_k built element by element from the same definition."""
+        if ie in self._dense:
+            return self._dense[ie]
+        e = self.kpts[ie]
+        vhat = np.fft.fftn(self.gs.vloc) / self.nr
+        dm = (e.miller[:, None, :] - e.miller[None, :, :]) % np.array(self.fft)
+        H = vhat[dm[..., 0], dm[..., 1], dm[..., 2]].astype(np.complex128)
+        H += np.diag(self.kinetic(ie))
+        H += (e.beta.T * self.gs.d_kb[None, :]) @ e.beta.conj()
+        self._dense[ie] = H
+        return H
+
+    # ------------------------------------------------------------ q mapping
+    def kq_entry(self, ik: int, q) -> Tuple[int, np.ndarray]:
+        """Entry j holding k+q and the integer shift g0 with k + q = k_j + g0."""
+        kq = self.kpts[ik].k_frac + np.asarray(q, dtype=np.float64)
+        for j, e in enumerate(self.kpts):
+            d = kq - e.k_frac
+            if np.all(np.abs(d - np.round(d)) < 1e-9):
+                return j, np.round(d).astype(np.int64)
+        raise KeyError(f"no entry for k+q = {kq}")
+
+    # ----------------------------------------------- Sternheimer, Eqs. 15-18
+    def rhs(self, ik: int, q, site: int, dv: Optional[np.ndarray]) -> np.ndarray:
+        """-P_c,k+q (dV_Hxc u_vk + V_pert u_vk) for every occupied v (Eq. 15 RHS,
+        V_pert from Eq. 16, P_c from Eq. 18)."""
+        j, g0 = self.kq_entry(ik, q)
+        ek, ej = self.kpts[ik], self.kpts[j]
+        b = np.zeros((self.n_occ, ej.npw), dtype=np.complex128)
+        if dv is not None:
+            b += self.to_recip(dv[None] * self.psi_r(ik), self.grid_index(j, g0))
+        sl = slice(5 * site, 5 * site + 5)
+        A = ek.phi[sl].conj() @ ek.u.T          # A[m, v] = <phi_{m,k}|u_vk>
+        b += A.T @ ej.phi[sl]                   # sum_m |phi_{m,k+q}> A[m, v]
+        b -= (b @ ej.u.conj().T) @ ej.u         # P_c = 1 - sum_v' |u_v',k+q><u_v',k+q|
+        return -b
+
+    def sternheimer_op(self, ik: int, q, X: np.ndarray, alpha: Optional[float] = None) -> np.ndarray:
+        """(H_k+q + alpha O_k+q - eps_vk) X, row v paired with eps_vk (Eq. 15 LHS, O from Eq. 17)."""
+        j, _ = self.kq_entry(ik, q)
+        ej = self.kpts[j]
+        a = self.alpha if alpha is None else alpha
+        out = self.h_apply(j, X)
+        out += a * (X @ ej.u.conj().T) @ ej.u
+        out -= self.kpts[ik].eps[:, None] * X
+        return out
+
+    def solve(self, ik: int, q, b: np.ndarray, x0: Optional[np.ndarray], p: ScfParams):
+        """Solve Eq. 15 for every occupied band of mesh point ik.  Returns (x, iterations)."""
+        a = self.alpha if p.alpha_shift is None else p.alpha_shift
+        if p.method == "direct":
+            j, _ = self.kq_entry(ik, q)
+            ej = self.kpts[j]
+            M0 = self.h_dense(j) + a * ej.u.T @ ej.u.conj()
+            x = np.empty_like(b)
+            for v in range(self.n_occ):
+                M = M0 - self.kpts[ik].eps[v] * np.eye(M0.shape[0])
+                x[v] = np.linalg.solve(M, b[v])
+            return x, 0
+        # preconditioned conjugate gradients, one independent recursion per band (rows),
+        # Jacobi preconditioner: the exact diagonal of the (positive definite) operator
+        j, _ = self.kq_entry(ik, q)
+        ej = self.kpts[j]
+        vhat0 = float(np.mean(self.gs.vloc))
+        diag = (self.kinetic(j) + vhat0 + (np.abs(ej.beta) ** 2 * self.gs.d_kb[:, None]).sum(0)
+                + a * (np.abs(ej.u) ** 2).sum(0))
+        dinv = 1.0 / (diag[None, :] - self.kpts[ik].eps[:, None])
+        x = np.zeros_like(b) if x0 is None else x0.copy()
+        r = b - self.sternheimer_op(ik, q, x, a)
+        bn = np.linalg.norm(b, axis=1)
+        bn = np.where(bn > 0, bn, 1.0)
+        z = dinv * r
+        pdir = z.copy()
+        rz = np.einsum("ij,ij->i", r.conj(), z).real
+        active = np.linalg.norm(r, axis=1) / bn > p.cg_tol
+        it = 0
+        while active.any() and it < p.max_cg_iter:
+            it += 1
+            Ap = self.sternheimer_op(ik, q, pdir, a)
+            pAp = np.einsum("ij,ij->i", pdir.conj(), Ap).real
+            step = np.where(active, rz / np.where(pAp != 0, pAp, 1.0), 0.0)
+            x += step[:, None] * pdir
+            r -= step[:, None] * Ap
+            z = dinv * r
+            rz_new = np.einsum("ij,ij->i", r.conj(), z).real
+            beta = np.where(active, rz_new / np.where(rz != 0, rz, 1.0), 0.0)
+            pdir = np.where(active[:, None], z + beta[:, None] * pdir, pdir)
+            rz = np.where(active, rz_new, rz)
+            active = active & (np.linalg.norm(r, axis=1) / bn > p.cg_tol)
+        if active.any():
+            raise RuntimeError(f"CG did not converge at k-entry {ik} after {it} iterations")
+        return x, it
+
+    # ------------------------------------------------ response density and Hxc
+    def drho_k(self, ik: int, q, du: np.ndarray) -> np.ndarray:
+        """Contribution of mesh point ik to the response density at q:
+        (4 w_k / Omega) sum_v conj(psi_vk(r)) dpsi_vk+q(r)  (spin x time reversal)."""
+        j, g0 = self.kq_entry(ik, q)
+        dpsi = self.to_real(du, self.grid_index(j, g0))
+        w = self.kpts[ik].weight
+        return (4.0 * w / self.omega) * np.einsum("vxyz,vxyz->xyz", self.psi_r(ik).conj(), dpsi)
+
+    def gvec_q(self, q) -> np.ndarray:
+        """|q+G|^2 over the FFT grid (G from the centred integer frequencies)."""
+        m = [_fftfreq_int(n) for n in self.fft]
+        M = np.stack(np.meshgrid(*m, indexing="ij"), -1).astype(np.float64)
+        p = (M + np.asarray(q, dtype=np.float64)) @ self.bvec
+        return np.einsum("...i,...i->...", p, p)
+
+    def dv_hxc(self, drho: np.ndarray, q, hxc: bool = True) -> np.ndarray:
+        """Response Hxc potential: Hartree 4 pi drho(G)/|q+G|^2 (zero at q+G = 0)
+        plus the local LDA kernel f_xc(r) drho(r)."""
+        if not hxc:
+            return np.zeros_like(drho)
+        g2 = self.gvec_q(q)
+        dg = np.fft.fftn(drho) / self.nr
+        vh = np.where(g2 > 1e-12, FOUR_PI * dg / np.where(g2 > 1e-12, g2, 1.0), 0.0)
+        return np.fft.ifftn(vh) * self.nr + self.fxc * drho
+
+    # ----------------------------------------------------- occupations, Eq. 13
+    def dn_k(self, ik: int, q, du: np.ndarray) -> np.ndarray:
+        """Contribution of mesh point ik to Delta_q n^s_{m1 m2} for every site s:
+        2 w_k sum_v [<u|phi_{m2,k}><phi_{m1,k+q}|du> + <u|phi_{m1,k}><phi_{m2,k+q}|du>]."""
+        j, _ = self.kq_entry(ik, q)
+        ek, ej = self.kpts[ik], self.kpts[j]
+        A = ek.phi.conj() @ ek.u.T               # (n_hub*5, n_occ)
+        B = ej.phi.conj() @ du.T                 # (n_hub*5, n_occ)
+        out = np.zeros((self.n_hub, 5, 5), dtype=np.complex128)
+        for s in range(self.n_hub):
+            sl = slice(5 * s, 5 * s + 5)
+            T = B[sl] @ A[sl].conj().T           # T[m1, m2] = sum_v B[m1,v] conj(A[m2,v])
+            out[s] = 2.0 * ek.weight * (T + T.T)
+        return out
+
+    def occupations(self) -> np.ndarray:
+        """Ground-state n^s_{m1 m2} = (2/N_k) sum_kv <u|phi_{m2}><phi_{m1}|u> (Eq. 3, on-site, spin 2)."""
+        out = np.zeros((self.n_hub, 5, 5), dtype=np.complex128)
+        for ik in range(self.n_mesh):
+            e = self.kpts[ik]
+            A = e.phi.conj() @ e.u.T
+            for s in range(self.n_hub):
+                sl = slice(5 * s, 5 * s + 5)
+                out[s] += 2.0 * e.weight * A[sl] @ A[sl].conj().T
+        return out
+
+    # ------------------------------------------------------------ SCF loop
+    def scf(self, site: int, q, p: ScfParams = ScfParams(), verbose: bool = False):
+        """Self-consistent solution of Eq. 15 for the perturbation of Hubbard site
+        `site` at wavevector q.  Returns a dict with dn0 (first iteration, Hxc
+        response not yet built up: the chi0 column, paper's linear-response
+        calculation section) and dn (self-consistent), each (n_hub, 5, 5)."""
+        q = np.asarray(q, dtype=np.float64)
+        dv_in = np.zeros(self.fft, dtype=np.complex128)
+        du = [None] * self.n_mesh
+        hist_df: List[np.ndarray] = []
+        hist_dv: List[np.ndarray] = []
+        prev = None
+        chi_prev = None
+        dn0 = None
+        dn = None
+        it_total = 0
+        converged = False
+        for it in range(1, p.niter_max + 1):
+            drho = np.zeros(self.fft, dtype=np.complex128)
+            dn = np.zeros((self.n_hub, 5, 5), dtype=np.complex128)
+            for ik in range(self.n_mesh):
+                b = self.rhs(ik, q, site, dv_in if it > 1 else None)
+                du[ik], nit = self.solve(ik, q, b, du[ik], p)
+                it_total += nit
+                drho += self.drho_k(ik, q, du[ik])
+                dn += self.dn_k(ik, q, du[ik])
+            chi = np.einsum("smm->s", dn)
+            if it == 1:
+                dn0 = dn.copy()
+            dv_out = self.dv_hxc(drho, q, p.hxc)
+            f = dv_out - dv_in
+            fn = np.linalg.norm(f)
+            vn = max(np.linalg.norm(dv_out), 1e-300)
+            if verbose:
+                dchi = np.nan if chi_prev is None else np.abs(chi - chi_prev).max()
+                print(f"  scf it {it}: |dchi| {dchi:.3e}  |f|/|v| {fn / vn:.3e}", flush=True)
+            if not p.hxc or fn == 0.0:
+                converged = True
+                break
+            if chi_prev is not None and np.abs(chi - chi_prev).max() < p.conv_thr_chi and fn / vn < p.conv_thr_v:
+                converged = True
+                break
+            chi_prev = chi
+            dv_new = self._mix(dv_in, f, prev, hist_df, hist_dv, p)
+            prev = (dv_in, f)
+            dv_in = dv_new
+        return {"dn0": dn0, "dn": dn, "iters": it, "cg_iters": it_total, "converged": converged}
+
+    def _mix(self, vin, f, prev, hist_df, hist_dv, p: ScfParams):
+        """Modified Broyden mixing of the response potential (Johnson 1988, with
+        unit weights and no w0 term, i.e. the Anderson form): the new input is
+        vin + a f - sum_i g_i (a df_i + dv_i), g = inv(<df_i|df_j>) <df_j|f>."""
+        if prev is not None:
+            vin_prev, f_prev = prev
+            df = f - f_prev
+            nrm = np.linalg.norm(df)
+            hist_df.append(df / nrm)
+            hist_dv.append((vin - vin_prev) / nrm)
+            if len(hist_df) > p.nmix:
+                hist_df.pop(0)
+                hist_dv.pop(0)
+        a = p.alpha_mix
+        if not hist_df:
+            return vin + a * f
+        n = len(hist_df)
+        G = np.array([[np.vdot(hist_df[i], hist_df[j]) for j in range(n)] for i in range(n)])
+        rhs = np.array([np.vdot(hist_df[i], f) for i in range(n)])
+        g = np.linalg.solve(G, rhs)
+        out = vin + a * f
+        for i in range(n):
+            out = out - g[i] * (a * hist_df[i] + hist_dv[i])
+        return out
+
+    # -------------------------------------------------------- full response
+    def response_matrix(self, p: ScfParams = ScfParams(), verbose: bool = False):
+        """chi0, chi over the N_H N_q sites of the q-supercell (Eq. 12 with Eq. 7)."""
+        qs = self.gs.qpoints()
+        chi0_q = np.zeros((len(qs), self.n_hub, self.n_hub), dtype=np.complex128)
+        chi_q = np.zeros_like(chi0_q)
+        for iq, q in enumerate(qs):
+            for sp in range(self.n_hub):
+                r = self.scf(sp, q, p, verbose=verbose)
+                chi0_q[iq, :, sp] = np.einsum("smm->s", r["dn0"])
+                chi_q[iq, :, sp] = np.einsum("smm->s", r["dn"])
+        chi0, im0 = assemble_chi(chi0_q, qs, self.gs.qmesh)
+        chi, im1 = assemble_chi(chi_q, qs, self.gs.qmesh)
+        return chi0, chi, max(im0, im1), chi0_q, chi_q
+
+    # ------------------------------------------------- independent references
+    def sos_solve(self, ik: int, q, b: np.ndarray) -> np.ndarray:
+        """Sum over all empty states of the full dense spectrum at k+q:
+        du_v = sum_c u_c <u_c|b_v> / (eps_c - eps_vk)  (Eq. 15 with P_c b = b)."""
+        j, _ = self.kq_entry(ik, q)
+        w, V = np.linalg.eigh(self.h_dense(j))
+        C = V[:, self.n_occ:]
+        coef = C.conj().T @ b.T                      # (n_c, n_v)
+        den = w[self.n_occ:, None] - self.kpts[ik].eps[None, :]
+        return (C @ (coef / den)).T
+
+    def fd_occupation_response(self, site: int, lam: float, hxc: bool = True, tol: float = 1e-13,
+                               maxit: int = 200) -> np.ndarray:
+        """Central finite difference [n^I(+lam) - n^I(-lam)] / 2 lam of the self-consistent
+        ground state under lam sum_m |phi^J_m><phi^J_m| (Eq. 7 by its definition).  Gamma-only
+        systems; with hxc=False the Hxc potential is frozen (chi0)."""
+        assert len(self.kpts) == 1 and np.allclose(self.kpts[0].k_frac, 0.0)
+        res = []
+        for sgn in (+1.0, -1.0):
+            res.append(self._perturbed_ground_state(site, sgn * lam, hxc, tol, maxit))
+        return (res[0] - res[1]) / (2.0 * lam)
+
+    def _perturbed_ground_state(self, site, lam, hxc, tol, maxit):
+        e = self.kpts[0]
+        H0 = self.h_dense(0)
+        sl = slice(5 * site, 5 * site + 5)
+        Pj = e.phi[sl].T @ e.phi[sl].conj()          # sum_m |phi_m><phi_m|
+        rho0 = self.gs.rho0
+        vxc0 = pz81.v_xc(rho0)
+        g2 = self.gvec_q(np.zeros(3))
+        idx = self.grid_index(0)
+        rho_in = rho0.copy()
+        hist_r, hist_f = [], []
+        for it in range(maxit):
+            if hxc:
+                dg = np.fft.fftn(rho_in - rho0) / self.nr
+                vh = np.where(g2 > 1e-12, FOUR_PI * dg / np.where(g2 > 1e-12, g2, 1.0), 0.0)
+                v = (np.fft.ifftn(vh) * self.nr).real + pz81.v_xc(rho_in) - vxc0
+            else:
+                v = np.zeros(self.fft)
+            vhat = np.fft.fftn(v) / self.nr
+            dm = (e.miller[:, None, :] - e.miller[None, :, :]) % np.array(self.fft)
+            H = H0 + lam * Pj + vhat[dm[..., 0], dm[..., 1], dm[..., 2]]
+            w, V = np.linalg.eigh(0.5 * (H + H.conj().T))
+            U = V[:, :self.n_occ].T
+            psi = self.to_real(U, idx)
+            rho_out = 2.0 * np.sum(np.abs(psi) ** 2, axis=0) / self.omega
+            f = rho_out - rho_in
+            if not hxc or np.abs(f).max() < tol:
+                break
+            # Anderson mixing of the density
+            hist_r.append(rho_in.copy())
+            hist_f.append(f.copy())
+            if len(hist_r) > 6:
+                hist_r.pop(0)
+                hist_f.pop(0)
+            n = len(hist_f)
+            if n > 1:
+                dF = [hist_f[i + 1] - hist_f[i] for i in range(n - 1)]
+                dR = [hist_r[i + 1] - hist_r[i] for i in range(n - 1)]
+                Gm = np.array([[np.vdot(a, b2).real for b2 in dF] for a in dF])
+                rh = np.array([np.vdot(a, f).real for a in dF])
+                g = np.linalg.lstsq(Gm, rh, rcond=None)[0]
+                r_opt = rho_in - sum(g[i] * dR[i] for i in range(n - 1))
+                f_opt = f - sum(g[i] * dF[i] for i in range(n - 1))
+                rho_in = r_opt + 0.3 * f_opt
+            else:
+                rho_in = rho_in + 0.3 * f
+        else:
+            raise RuntimeError("perturbed ground state did not converge")
+        A = e.phi.conj() @ U.T
+        n = np.array([2.0 * np.sum(np.abs(A[5 * s:5 * s + 5]) ** 2) for s in range(self.n_hub)])
+        return n
+
+
+def supercell_cells(qmesh) -> np.ndarray:
+    """Integer cell offsets l of the q-supercell, lexicographic with the last index fastest."""
+    n1, n2, n3 = qmesh
+    return np.array([(a, b, c) for a in range(n1) for b in range(n2) for c in range(n3)], dtype=np.float64)
+
+
+def assemble_chi(chi_q: np.ndarray, qs: np.ndarray, qmesh) -> Tuple[np.ndarray, float]:
+    """Eq. 12 traced over m: chi_{(s,l),(s',l')} = (1/N_q) sum_q e^{iq.(R_l - R_l')} chi(q)_{s s'}.
+    Site index = l * n_hub + s.  Returns the real part and max |imaginary part|."""
+    nq, nh, _ = chi_q.shape
+    cells = supercell_cells(qmesh)
+    nc = cells.shape[0]
+    out = np.zeros((nc * nh, nc * nh), dtype=np.complex128)
+    for l in range(nc):
+        for lp in range(nc):
+            ph = np.exp(2j * math.pi * (qs @ (cells[l] - cells[lp])))
+            blk = np.einsum("q,qab->ab", ph, chi_q) / nq
+            out[l * nh:(l + 1) * nh, lp * nh:(lp + 1) * nh] = blk
+    return out.real.copy(), float(np.abs(out.imag).max())
+
+
+def hubbard_params(chi0: np.ndarray, chi: np.ndarray) -> np.ndarray:
+    """U on the diagonal, V off the diagonal: chi0^-1 - chi^-1 (Eqs. 8-9)."""
+    return np.linalg.inv(chi0) - np.linalg.inv(chi)

@@ -1,0 +1,278 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test below checks the oracle against a reference that does not reuse the
+piece of oracle arithmetic it pins:
+  * eigen-residual of the generator's states under the oracle's Hamiltonian
+    (two independent Hamiltonian implementations);
+  * FFT Hamiltonian apply against the dense matrix built element by element;
+  * Sternheimer solves against a sum over all empty states of the full spectrum
+    and against a dense direct solve (Eq. 15);
+  * chi0 and chi against central finite differences of the perturbed ground
+    state (Eq. 7 by its definition: the paper states DFPT and finite
+    differences give the same values);
+  * the monochromatic q-sum (Eq. 12) against the direct supercell response;
+  * symmetry, time reversal, gauge and alpha invariances;
+  * the no-Hxc special case (chi = chi0, U = V = 0);
+  * the LDA kernel against a finite difference of the LDA potential.
+"""
+import functools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import pz81
+from conftest import ground_state
+
+TIGHT = oracle.ScfParams(cg_tol=1e-13, conv_thr_chi=1e-13, conv_thr_v=1e-11)
+MEDIUM = oracle.ScfParams(cg_tol=1e-11, conv_thr_chi=1e-10, conv_thr_v=1e-8)
+
+
+@functools.lru_cache(maxsize=None)
+def orc(name):
+    return oracle.Oracle(ground_state(name))
+
+
+@functools.lru_cache(maxsize=None)
+def scf_result(name, site, q, tight=True):
+    return orc(name).scf(site, np.array(q), TIGHT if tight else MEDIUM)
+
+
+@functools.lru_cache(maxsize=None)
+def response(name, tight=False):
+    return orc(name).response_matrix(TIGHT if tight else MEDIUM)
+
+
+# --------------------------------------------------------------- Hamiltonian
+
+@pytest.mark.parametrize("name", ["sc1_gamma", "sc1_k311", "duo_k221"])
+def test_generator_states_are_eigenstates_of_oracle_h(name):
+    o = orc(name)
+    for ie, e in enumerate(o.kpts):
+        HX = o.h_apply(ie, e.u)
+        assert np.abs(HX - e.eps[:, None] * e.u).max() < 1e-11
+
+
+@pytest.mark.parametrize("name", ["sc1_gamma", "duo_k221"])
+def test_fft_apply_matches_dense_matrix(name):
+    o = orc(name)
+    rng = np.random.default_rng(5)
+    for ie in range(len(o.kpts)):
+        n = o.kpts[ie].npw
+        X = rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))
+        np.testing.assert_allclose(o.h_apply(ie, X), (o.h_dense(ie) @ X.T).T, atol=1e-12)
+
+
+def test_dense_h_is_hermitian():
+    H = orc("duo_k221").h_dense(1)
+    assert np.abs(H - H.conj().T).max() < 1e-14
+
+
+# ----------------------------------------------------- Sternheimer (Eq. 15)
+
+@pytest.mark.parametrize("name,q", [("sc1_gamma", (0, 0, 0)), ("sc1_k211", (0.5, 0, 0)), ("sc1_k311", (1 / 3, 0, 0))])
+def test_sternheimer_cg_equals_sum_over_states(name, q):
+    o = orc(name)
+    rng = np.random.default_rng(11)
+    for ik in range(o.n_mesh):
+        j, g0 = o.kq_entry(ik, q)
+        npw = o.kpts[j].npw
+        dv = rng.standard_normal(o.fft) + 1j * rng.standard_normal(o.fft)
+        b = o.rhs(ik, q, 0, 0.01 * dv)
+        x_cg, _ = o.solve(ik, q, b, None, oracle.ScfParams(cg_tol=1e-14))
+        x_sos = o.sos_solve(ik, q, b)
+        x_dir, _ = o.solve(ik, q, b, None, oracle.ScfParams(method="direct"))
+        scale = np.abs(x_sos).max()
+        assert np.abs(x_cg - x_sos).max() < 1e-11 * scale
+        assert np.abs(x_dir - x_sos).max() < 1e-11 * scale
+        # the right-hand side lives in the conduction manifold; so does the solution (Eqs. 17-18)
+        U = o.kpts[j].u
+        assert np.abs(x_cg @ U.conj().T).max() < 1e-11 * scale
+
+
+def test_alpha_shift_does_not_change_the_solution():
+    o = orc("sc1_k211")
+    q = (0.5, 0, 0)
+    b = o.rhs(0, q, 0, None)
+    x1, _ = o.solve(0, q, b, None, oracle.ScfParams(cg_tol=1e-14))
+    x2, _ = o.solve(0, q, b, None, oracle.ScfParams(cg_tol=1e-14, alpha_shift=2 * o.alpha))
+    assert np.abs(x1 - x2).max() < 1e-11 * np.abs(x1).max()
+
+
+def test_rhs_is_projected_and_contains_vpert():
+    """With dV = 0 the RHS is -P_c sum_m |phi_m,k+q><phi_m,k|u> (Eqs. 16, 18), written here
+    with the projector built as an explicit dense matrix."""
+    o = orc("sc1_gamma")
+    e = o.kpts[0]
+    Pc = np.eye(e.npw) - e.u.T @ e.u.conj()
+    V = e.phi[0:5].T @ e.phi[0:5].conj()
+    ref = -(Pc @ V @ e.u.T).T
+    np.testing.assert_allclose(o.rhs(0, (0, 0, 0), 0, None), ref, atol=1e-13)
+
+
+# ------------------------------------------- Eq. 7 by finite differences (P3, P4)
+
+@functools.lru_cache(maxsize=None)
+def fd_chi(hxc):
+    o = orc("sc1_gamma")
+    lam = 1e-3
+    c1 = o.fd_occupation_response(0, lam, hxc=hxc)
+    c2 = o.fd_occupation_response(0, lam / 2, hxc=hxc)
+    return (4 * c2 - c1) / 3          # Richardson: O(lam^4)
+
+
+def test_chi_equals_finite_difference_of_scf_ground_state():
+    r = scf_result("sc1_gamma", 0, (0, 0, 0))
+    chi = np.trace(r["dn"][0])
+    assert abs(chi.imag) < 1e-12
+    assert abs(chi.real - fd_chi(True)[0]) < 2e-8 * abs(chi.real)
+
+
+def test_chi0_equals_finite_difference_with_frozen_hxc():
+    r = scf_result("sc1_gamma", 0, (0, 0, 0))
+    chi0 = np.trace(r["dn0"][0]).real
+    assert abs(chi0 - fd_chi(False)[0]) < 2e-8 * abs(chi0)
+
+
+def test_screening_reduces_response():
+    r = scf_result("sc1_gamma", 0, (0, 0, 0))
+    chi0 = np.trace(r["dn0"][0]).real
+    chi = np.trace(r["dn"][0]).real
+    assert chi0 < chi < 0
+    U = 1 / chi0 - 1 / chi
+    assert U > 0
+
+
+# -------------------------------------------------- Eq. 12 against a supercell (P5)
+
+@pytest.mark.slow
+def test_q_sum_reproduces_supercell_response():
+    chi0_q, chi_q = response("sc1_k211")[:2]
+    chi0_s, chi_s = response("sc1_super211")[:2]
+    assert np.abs(chi0_q - chi0_s).max() < 1e-8 * np.abs(chi0_s).max()
+    assert np.abs(chi_q - chi_s).max() < 1e-8 * np.abs(chi_s).max()
+
+
+# ------------------------------------------------------ symmetries (P6, P8, P9)
+
+def test_chi_real_symmetric_and_blocks_hermitian():
+    chi0, chi, im, chi0_q, chi_q = response("duo_k221")
+    assert im < 1e-9 * np.abs(chi).max()
+    assert np.abs(chi - chi.T).max() < 1e-8 * np.abs(chi).max()
+    assert np.abs(chi0 - chi0.T).max() < 1e-9 * np.abs(chi0).max()
+    for blk in list(chi_q) + list(chi0_q):
+        assert np.abs(blk - blk.conj().T).max() < 1e-8 * np.abs(chi).max()
+
+
+def test_response_at_minus_q_is_conjugate():
+    o = orc("sc1_k311")
+    a = scf_result("sc1_k311", 0, (1 / 3, 0, 0), tight=False)
+    b = scf_result("sc1_k311", 0, (2 / 3, 0, 0), tight=False)   # = -1/3 mod 1
+    for key in ("dn0", "dn"):
+        assert np.abs(a[key] - b[key].conj()).max() < 1e-8
+
+
+def test_two_term_density_equals_factor_four_form():
+    """Delta rho_q from the explicit +q and -q solutions, (2/N_k) sum [u* du(+q) + conj(du(-q)) u],
+    equals the time-reversal-folded (4/N_k) sum u* du(+q) (first iteration, dV = 0)."""
+    o = orc("sc1_k311")
+    q = np.array([1 / 3, 0, 0])
+    p = oracle.ScfParams(cg_tol=1e-14)
+    rho4 = np.zeros(o.fft, dtype=complex)
+    rho2 = np.zeros(o.fft, dtype=complex)
+    for ik in range(o.n_mesh):
+        dup, _ = o.solve(ik, q, o.rhs(ik, q, 0, None), None, p)
+        dum, _ = o.solve(ik, -q, o.rhs(ik, -q, 0, None), None, p)
+        rho4 += o.drho_k(ik, q, dup)
+        jp, gp = o.kq_entry(ik, q)
+        jm, gm = o.kq_entry(ik, -q)
+        psi = o.psi_r(ik)
+        fp = o.to_real(dup, o.grid_index(jp, gp))
+        fm = o.to_real(dum, o.grid_index(jm, gm))
+        w = o.kpts[ik].weight
+        rho2 += (2 * w / o.omega) * np.einsum("vxyz->xyz", psi.conj() * fp + fm.conj() * psi)
+    assert np.abs(rho4 - rho2).max() < 1e-11 * np.abs(rho4).max()
+
+
+def test_gauge_invariance_of_response():
+    """Random phases on the ground-state states leave Delta n unchanged (P8)."""
+    import copy
+    gs = copy.deepcopy(ground_state("sc1_k211"))
+    rng = np.random.default_rng(3)
+    for e in gs.kpts:
+        e.u = e.u * np.exp(2j * np.pi * rng.random(e.u.shape[0]))[:, None]
+    o2 = oracle.Oracle(gs)
+    q = (0.5, 0, 0)
+    p = oracle.ScfParams(cg_tol=1e-13, niter_max=1)
+    r1 = orc("sc1_k211").scf(0, np.array(q), p)
+    r2 = o2.scf(0, np.array(q), p)
+    assert np.abs(r1["dn0"] - r2["dn0"]).max() < 1e-11
+
+
+# ------------------------------------------------------------- P10, P11
+
+def test_without_hxc_chi_equals_chi0_and_u_vanishes():
+    o = orc("sc1_gamma")
+    r = o.scf(0, np.zeros(3), oracle.ScfParams(cg_tol=1e-13, hxc=False))
+    np.testing.assert_allclose(r["dn"], r["dn0"], atol=0)
+    c0 = np.array([[np.trace(r["dn0"][0]).real]])
+    assert np.abs(oracle.hubbard_params(c0, c0)).max() < 1e-14
+
+
+def test_block_circulant_inverse():
+    """Eq. 12 is a unitary change of basis: inverting the assembled matrix equals
+    assembling the per-q inverses."""
+    from synth.system import mesh_points
+    rng = np.random.default_rng(0)
+    qmesh = (1, 2, 2)
+    qs = mesh_points(qmesh)
+    nh = 3
+    M = rng.standard_normal((len(qs), nh, nh)) + 1j * rng.standard_normal((len(qs), nh, nh))
+    M = M + np.conj(np.transpose(M, (0, 2, 1))) + 10 * np.eye(nh)
+    # chi(-q) = conj(chi(q)) makes the assembled matrix real; on this mesh every q equals -q
+    for iq, q in enumerate(qs):
+        assert np.allclose(((2 * q) + 0.5) % 1 - 0.5, 0)
+        M[iq] = M[iq].real
+    full, im = oracle.assemble_chi(M, qs, qmesh)
+    full_inv, im2 = oracle.assemble_chi(np.linalg.inv(M), qs, qmesh)
+    assert im < 1e-12 and im2 < 1e-12
+    np.testing.assert_allclose(np.linalg.inv(full), full_inv, atol=1e-12)
+
+
+def test_hubbard_params_definition():
+    chi0 = np.array([[-2.0, 0.1], [0.1, -2.0]])
+    chi = np.array([[-1.5, 0.05], [0.05, -1.5]])
+    uv = oracle.hubbard_params(chi0, chi)
+    # 2x2 closed form of the inverse of [[a, b], [b, a]]: [[a, -b], [-b, a]] / (a^2 - b^2)
+    inv = lambda a, b: np.array([[a, -b], [-b, a]]) / (a * a - b * b)
+    np.testing.assert_allclose(uv, inv(-2.0, 0.1) - inv(-1.5, 0.05), atol=1e-15)
+
+
+# ---------------------------------------------------------------------- P13
+
+def test_fxc_is_derivative_of_vxc():
+    rho = np.array([1e-4, 3e-3, 0.02, 0.1, 0.5, 2.0, 10.0])
+    h = rho * 1e-5
+    fd = (pz81.v_xc(rho + h) - pz81.v_xc(rho - h)) / (2 * h)
+    np.testing.assert_allclose(pz81.f_xc(rho), fd, rtol=1e-8)
+
+
+def test_vxc_is_derivative_of_energy_density():
+    rho = np.array([1e-4, 3e-3, 0.02, 0.1, 0.5, 2.0, 10.0])
+    h = rho * 1e-5
+    e = lambda r: r * pz81.eps_xc(r)
+    fd = (e(rho + h) - e(rho - h)) / (2 * h)
+    np.testing.assert_allclose(pz81.v_xc(rho), fd, rtol=1e-8)
+
+
+def test_pz81_fit_is_continuous_at_rs_one_and_exchange_closed_form():
+    rho1 = 3.0 / (4 * math.pi)           # r_s = 1
+    ec_hi = pz81.GAMMA / (1 + pz81.BETA1 + pz81.BETA2)
+    ec_lo = pz81.B_ + pz81.D_
+    assert abs(ec_hi - ec_lo) < 1e-4      # the published fit joins to ~4 digits
+    ex = -0.75 * (3 * rho1 / math.pi) ** (1 / 3)
+    # at r_s = 1 the exchange energy per electron is -(3/4)(9/(4 pi^2))^(1/3) = -0.4582 Ha
+    assert abs(ex + 0.75 * (9 / (4 * math.pi ** 2)) ** (1 / 3)) < 1e-15
+    assert abs(ex + 0.458165) < 1e-6
+    assert pz81.f_xc(np.array([1e-12]))[0] == 0.0

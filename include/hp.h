@@ -1,0 +1,198 @@
+/*
+ * hp.h - C ABI of the MI355X Hubbard-response (DFPT) library.
+ *
+ * The library computes the linear response of the Hubbard-manifold occupations
+ * of a periodic, norm-conserving, non-magnetic insulator to monochromatic
+ * perturbations of those occupations, following Timrov, Marzari and
+ * Cococcioni, "HP - A code for the calculation of Hubbard parameters using
+ * density-functional perturbation theory":
+ *   - the q-specific Sternheimer equation (Eq. 15) with the perturbing
+ *     potential of Eq. 16 and the projectors of Eqs. 17-18,
+ *   - the response occupations of Eq. 13 and the q-sum of Eq. 12,
+ *   - the susceptibilities chi0, chi (Eq. 7) and U/V = chi0^-1 - chi^-1
+ *     (Eqs. 8-9).
+ *
+ * Conventions (shared by every entry point):
+ *   Units are Hartree atomic units.  The cell rows are the lattice vectors
+ *   a1, a2, a3 (bohr); b = 2 pi inv(A)^T.  A plane wave of the basis at k is
+ *   k + G with G = m . b for an integer Miller triple m; lattice-periodic
+ *   functions are stored by coefficients c(G), u(r) = Omega^-1/2 sum_G c(G)
+ *   e^{iG.r}.  Grid point (j1,j2,j3) is r = sum_i (j_i/N_i) a_i; Miller index
+ *   m lands on grid index m mod N.  Real-space arrays are row-major
+ *   [N1][N2][N3] (N3 fastest).  Complex arrays are interleaved (re, im) FP64.
+ *   The projector tables are the lattice-periodic Bloch sums
+ *   fbar_k(G) = Omega^-1/2 ftilde(k+G) e^{-i(k+G).tau}.
+ *   Closed shell: spin factor 2 in the occupations and densities.
+ *
+ * Status codes: every call returns hp_status.  0 = success; > 0 = warning,
+ * outputs written; < 0 = error, outputs untouched.  hp_last_error() gives a
+ * thread-local message for the last non-zero status.  Argument checks run
+ * before any GPU call, so argument errors are reported without a device.
+ *
+ * Ownership: input pointers are borrowed for the duration of a call only.
+ * hp_ground_state_load copies everything it needs into device memory owned by
+ * the returned context; outputs go to caller-allocated host arrays.  A context
+ * may be used by one host thread at a time; calls on one context are
+ * serialized on its stream.
+ */
+#ifndef HP_H
+#define HP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hp_status;
+
+enum {
+  HP_OK = 0,
+  HP_WARN_NOT_CONVERGED = 1,  /* SCF or CG stopped at its iteration limit      */
+  HP_ERR_ARG = -1,            /* NULL pointer, bad size or bad enum value       */
+  HP_ERR_SHAPE = -2,          /* inconsistent shapes (sphere vs grid, k+q ...)  */
+  HP_ERR_HIP = -3,            /* HIP runtime failure (message has the detail)   */
+  HP_ERR_OOM = -4,            /* device allocation failed                       */
+  HP_ERR_STATE = -5,          /* call not valid for the context's state         */
+  HP_ERR_SINGULAR = -6,       /* chi0 or chi not invertible                     */
+  HP_ERR_NUMERIC = -7         /* NaN or Inf met in an iterate                   */
+};
+
+enum { HP_FP64 = 0, HP_MIXED = 1 };   /* arithmetic of the Sternheimer solves */
+enum { HP_XC_LDA_PZ81 = 1 };          /* local xc kernel (Perdew-Zunger 1981)   */
+
+/* One k-entry: a point of the Gamma-centred k mesh, or an extra k+q point.
+ * The paper's ground-state hand-off (section "Ground-state calculation"):
+ * occupied lattice-periodic states and energies at k and k+q. */
+typedef struct hp_kpoint {
+  uint32_t struct_size;   /* sizeof(hp_kpoint)                                     */
+  double k_frac[3];       /* k in units of b                                       */
+  double weight;          /* 1/N_k for mesh points, 0 for k+q-only entries         */
+  int32_t npw;            /* number of plane waves of the sphere at k              */
+  const int32_t *miller;  /* [npw][3] Miller indices (any order)                   */
+  const double *eps;      /* [n_occ] occupied energies (Ha)                        */
+  const double *u;        /* [n_occ][npw] complex, orthonormal rows                */
+  const double *beta;     /* [n_beta][npw] complex, KB projector tables            */
+  const double *phi;      /* [n_hub*5][npw] complex, Hubbard d orbitals, per site  */
+} hp_kpoint;
+
+/* The unperturbed ground state (paper: ground-state calculation section). */
+typedef struct hp_ground_state {
+  uint32_t struct_size;   /* sizeof(hp_ground_state)                               */
+  double cell[3][3];      /* rows a1, a2, a3 (bohr)                                */
+  int32_t fft[3];         /* N1, N2, N3: each a product of 2, 3 and 5, <= 256      */
+  const double *v_loc;    /* [N1][N2][N3] total local KS potential (Ha)            */
+  const double *rho0;     /* [N1][N2][N3] ground-state density (electrons/bohr^3)  */
+  int32_t n_occ;          /* occupied bands (the same at every k)                  */
+  int32_t n_beta;         /* KB projectors                                         */
+  int32_t n_hub;          /* Hubbard sites (5 d orbitals each)                     */
+  const double *d_kb;     /* [n_beta] KB strengths (Ha)                            */
+  const double *hub_tau;  /* [n_hub][3] Hubbard site positions (bohr)              */
+  int32_t spin_factor;    /* must be 2 (closed shell)                              */
+  int32_t n_mesh;         /* the first n_mesh entries of kpts form the k mesh      */
+  int32_t n_kpts;         /* total entries (mesh + extra k+q)                      */
+  const hp_kpoint *kpts;  /* [n_kpts]                                              */
+  int32_t xc;             /* HP_XC_LDA_PZ81                                        */
+  int32_t reserved;       /* must be 0                                             */
+  void *stream;           /* hipStream_t to run on, or NULL for a private stream   */
+} hp_ground_state;
+
+/* Convergence controls (the paper's inputhp keywords conv_thr_chi, niter_max,
+ * alpha_mix, nmix; cg_tol plays the role of thresh_init for every iteration). */
+typedef struct hp_scf_params {
+  uint32_t struct_size;   /* sizeof(hp_scf_params)                                 */
+  double conv_thr_chi;    /* stop when max_s |chi(q)_it - chi(q)_it-1| < this (1/Ha)*/
+  double conv_thr_v;      /* ... and ||dV_out - dV_in|| / ||dV_out|| < this         */
+  double cg_tol;          /* per-band ||r|| / ||b|| of every Sternheimer solve     */
+  int32_t niter_max;      /* SCF iteration limit (paper default 100)               */
+  double alpha_mix;       /* mixing factor (paper default 0.3)                     */
+  int32_t nmix;           /* mixing history length (paper default 4), 1..8         */
+  int32_t max_cg_iter;    /* CG iteration limit per solve                          */
+  int32_t precision;      /* HP_FP64 or HP_MIXED                                   */
+  int32_t verbosity;      /* 0 silent, 1 one line per SCF iteration on stderr      */
+} hp_scf_params;
+
+/* Statistics of one call (all fields written when the pointer is not NULL). */
+typedef struct hp_scf_stats {
+  uint32_t struct_size;   /* sizeof(hp_scf_stats), set by the caller               */
+  int32_t scf_iters;      /* SCF iterations taken                                  */
+  int32_t converged;      /* 1 if the SCF met both thresholds                      */
+  int32_t cg_iters;       /* CG iterations summed over SCF iterations              */
+  int64_t h_applies_fp64; /* single-band H applications in FP64                    */
+  int64_t h_applies_lowp; /* single-band H applications in reduced precision       */
+  double wall_s;          /* host wall time of the call                            */
+  double chi_change;      /* last max |chi(q)_it - chi(q)_it-1|                     */
+  double v_residual;      /* last ||dV_out - dV_in|| / ||dV_out||                   */
+  double max_rel_resid;   /* largest final CG relative residual                    */
+  double stage_s[8];      /* GPU time per stage: rhs, cg, drho, hxc, mix, dn, -, - */
+} hp_scf_stats;
+
+typedef struct hp_ctx hp_ctx;  /* opaque; owns every device buffer */
+
+/* Copy the ground state to the GPU and precompute what every perturbation
+ * reuses: the LDA kernel f_xc(rho0), plane-wave/grid maps, kinetic energies,
+ * the shift alpha = 2 (max - min) of the occupied energies (text after
+ * Eq. 18), the projections <phi_k|u_vk> and the real-space occupied states.
+ * Errors: HP_ERR_ARG (NULL, bad sizes, spin_factor != 2, xc unknown),
+ * HP_ERR_SHAPE (sphere does not fit the grid, FFT size not 2^a 3^b 5^c),
+ * HP_ERR_OOM, HP_ERR_HIP.  On success *out owns all device memory. */
+hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **out);
+
+/* Self-consistent solution of Eq. 15 for a perturbation of Hubbard site
+ * pert_site (0-based) at wavevector q (units of b), for every occupied band of
+ * every mesh k (the entry holding k+q is found among the loaded entries,
+ * modulo a reciprocal lattice vector).  Writes the response occupations of
+ * Eq. 13 for every site s:
+ *   dn0_out [n_hub][5][5] complex : after the first iteration (dV_Hxc = 0,
+ *                                   the chi0 column of Eq. 7),
+ *   dn_out  [n_hub][5][5] complex : at self-consistency (the chi column).
+ * Index order [s][m1][m2]; Delta_q n^s_{m1 m2} is per Ha of perturbation and
+ * includes the spin factor.  Returns HP_WARN_NOT_CONVERGED when niter_max or
+ * max_cg_iter was reached (outputs hold the last iterate), HP_ERR_SHAPE when a
+ * k+q entry is missing, HP_ERR_NUMERIC on NaN/Inf. */
+hp_status hp_sternheimer_scf(hp_ctx *c, int32_t pert_site, const double q_frac[3],
+                             const hp_scf_params *p, double *dn0_out, double *dn_out,
+                             hp_scf_stats *st);
+
+/* chi0 and chi over the N_H * N_q sites of the q-supercell: runs
+ * hp_sternheimer_scf for every site and every q of the Gamma-centred nq mesh
+ * and sums with the phases of Eq. 12.  Site index = l * n_hub + s with l the
+ * cell of the q-supercell (l1, l2, l3 lexicographic, l3 fastest).
+ *   chi0_out, chi_out [(n_hub*Nq)^2] row-major real (1/Ha);
+ *   max_imag_out      largest |imaginary part| dropped by the q-sum (may be NULL);
+ *   st                accumulated statistics (may be NULL).
+ * Status as hp_sternheimer_scf (the worst over all pairs). */
+hp_status hp_response_matrix(hp_ctx *c, const int32_t nq[3], const hp_scf_params *p,
+                             double *chi0_out, double *chi_out, double *max_imag_out,
+                             hp_scf_stats *st);
+
+/* U/V matrix = chi0^-1 - chi^-1 (Eqs. 8-9): U on the diagonal, V off it (Ha).
+ * chi0, chi, uv_out are [n][n] row-major host arrays, n >= 1.  FP64 LU with
+ * partial pivoting; HP_ERR_SINGULAR when a pivot falls below 1e-14 times the
+ * largest |entry|.  Host-only: needs no context and no GPU. */
+hp_status hp_hubbard_params(int32_t n, const double *chi0, const double *chi, double *uv_out);
+
+/* Free every resource of the context.  NULL is accepted. */
+void hp_destroy(hp_ctx *c);
+
+/* Thread-local description of the last non-zero status (never NULL). */
+const char *hp_last_error(void);
+
+/* ---- Diagnostics: single steps of the path, for parity checks ------------ */
+
+/* y = H_k x for n vectors on entry `entry` (kinetic + local potential on the
+ * grid + KB projectors; the operator of Eq. 15 without the alpha shift).
+ * x, y: [n][npw] complex host arrays in the caller's plane-wave order. */
+hp_status hp_apply_h(hp_ctx *c, int32_t entry, int32_t n, const double *x, double *y);
+
+/* One linear solve of Eq. 15 at mesh point mesh_k for every occupied band,
+ * with a given response potential dv ([N1][N2][N3] complex host array, or NULL
+ * for dV_Hxc = 0): du_out [n_occ][npw(k+q)] complex, in the plane-wave order of
+ * the entry holding k+q.  Uses p->cg_tol, p->max_cg_iter, p->precision. */
+hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const double q_frac[3], int32_t mesh_k,
+                               const double *dv, const hp_scf_params *p, double *du_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HP_H */

@@ -1,0 +1,669 @@
+// Plane-wave <-> real-space transforms for gfx950.
+//
+// A band vector lives on a sphere of plane waves.  The 3D transform is split
+// into (1) z-sticks: a direct DFT along z of every (m1, m2) column that holds
+// sphere points, and (2) xy-planes: one workgroup per (band, z) keeps the whole
+// N1 x N2 plane in LDS and runs in-place mixed-radix FFTs along y (only the
+// columns that hold sticks) and x.  The inverse direction uses decimation in
+// frequency (natural in, digit-reversed out) and the forward direction the
+// exact reverse sequence (digit-reversed in, natural out), so the real-space
+// side is kept in digit-reversed x/y order and no permutation pass is needed:
+// the local potential, the cached occupied states, the response density and
+// potential are all stored in that order.
+#include "hp_internal.h"
+
+namespace hp {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kStickChunk = 32;  // sticks per workgroup in the z-DFT kernels
+constexpr int kMaxPerThread = 40;  // plane elements per thread kept in registers
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
+  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// multiply by sign * i
+__device__ __forceinline__ double2 cmul_si(double2 a, double sign) { return make_double2(-sign * a.y, sign * a.x); }
+
+// y_t = sum_u x_u exp(sign 2 pi i u t / R), in registers.
+template <int R>
+__device__ __forceinline__ void dft_small(double2 *x, double sign);
+
+template <>
+__device__ __forceinline__ void dft_small<2>(double2 *x, double) {
+  double2 a = x[0], b = x[1];
+  x[0] = cadd(a, b);
+  x[1] = csub(a, b);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<3>(double2 *x, double sign) {
+  const double h = 0.86602540378443864676;  // sqrt(3)/2
+  double2 s = cadd(x[1], x[2]);
+  double2 d = csub(x[1], x[2]);
+  double2 m = make_double2(x[0].x - 0.5 * s.x, x[0].y - 0.5 * s.y);
+  double2 t = cmul_si(cscale(d, h), sign);
+  x[0] = cadd(x[0], s);
+  x[1] = cadd(m, t);
+  x[2] = csub(m, t);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<4>(double2 *x, double sign) {
+  double2 a0 = cadd(x[0], x[2]), a1 = csub(x[0], x[2]);
+  double2 b0 = cadd(x[1], x[3]), b1 = cmul_si(csub(x[1], x[3]), sign);
+  x[0] = cadd(a0, b0);
+  x[2] = csub(a0, b0);
+  x[1] = cadd(a1, b1);
+  x[3] = csub(a1, b1);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<5>(double2 *x, double sign) {
+  const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
+  const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
+  double2 a1 = cadd(x[1], x[4]), b1 = csub(x[1], x[4]);
+  double2 a2 = cadd(x[2], x[3]), b2 = csub(x[2], x[3]);
+  double2 x0 = x[0];
+  double2 r1 = make_double2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+  double2 r2 = make_double2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+  double2 i1 = cmul_si(make_double2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y), sign);
+  double2 i2 = cmul_si(make_double2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y), sign);
+  x[0] = make_double2(x0.x + a1.x + a2.x, x0.y + a1.y + a2.y);
+  x[1] = cadd(r1, i1);
+  x[4] = csub(r1, i1);
+  x[2] = cadd(r2, i2);
+  x[3] = csub(r2, i2);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<8>(double2 *x, double sign) {
+  const double r = 0.70710678118654752440;
+  double2 e[4] = {x[0], x[2], x[4], x[6]};
+  double2 o[4] = {x[1], x[3], x[5], x[7]};
+  dft_small<4>(e, sign);
+  dft_small<4>(o, sign);
+  // o_t *= W8^t, W8 = exp(sign 2 pi i / 8)
+  o[1] = make_double2(r * (o[1].x - sign * o[1].y), r * (o[1].y + sign * o[1].x));
+  o[2] = cmul_si(o[2], sign);
+  o[3] = make_double2(r * (-o[3].x - sign * o[3].y), r * (-o[3].y + sign * o[3].x));
+  for (int t = 0; t < 4; ++t) {
+    x[t] = cadd(e[t], o[t]);
+    x[t + 4] = csub(e[t], o[t]);
+  }
+}
+
+__device__ __forceinline__ void dft_any(double2 *x, int R, double sign) {
+  switch (R) {
+    case 2: dft_small<2>(x, sign); break;
+    case 3: dft_small<3>(x, sign); break;
+    case 4: dft_small<4>(x, sign); break;
+    case 5: dft_small<5>(x, sign); break;
+    case 8: dft_small<8>(x, sign); break;
+    default: break;
+  }
+}
+
+// One in-place stage over `nlines` lines of length N stored in LDS.  Line i
+// starts at base_i = b0[i] (or i * bstride when b0 == nullptr) with element
+// stride es.  dif = true: butterfly then twiddle, sign +1; dif = false: conjugate
+// twiddle then butterfly with sign -1 (the inverse-order stage).
+__device__ __forceinline__ void fft_stage(double2 *P, int nlines, const int *lines, int lmul, int lmod,
+                                          int lshift, int lstride, int es, int N, int R, int L,
+                                          const double2 *tw, bool dif) {
+  const int nb = N / R;
+  const int B = R * L;
+  const int tstep = N / B;
+  const double sign = dif ? 1.0 : -1.0;
+  for (int w = threadIdx.x; w < nlines * nb; w += blockDim.x) {
+    const int line = w / nb;
+    const int b = w - line * nb;
+    const int blk = b / L;
+    const int j = b - blk * L;
+    int lb;
+    if (lines) {
+      int v = lines[line] - lshift;
+      v %= lmod;
+      if (v < 0) v += lmod;
+      lb = v * lmul;
+    } else {
+      lb = line * lstride;
+    }
+    const int base = lb + (blk * B + j) * es;
+    const int step = L * es;
+    double2 x[8];
+    for (int t = 0; t < R; ++t) x[t] = P[base + t * step];
+    if (dif) {
+      dft_any(x, R, sign);
+      for (int t = 1; t < R; ++t) {
+        double2 w_ = tw[(j * t * tstep) % N];
+        x[t] = cmul(x[t], w_);
+      }
+    } else {
+      for (int t = 1; t < R; ++t) {
+        double2 w_ = tw[(j * t * tstep) % N];
+        x[t] = cmulc(x[t], w_);
+      }
+      dft_any(x, R, sign);
+    }
+    for (int t = 0; t < R; ++t) P[base + t * step] = x[t];
+  }
+}
+
+// Full transform of a set of lines: decimation in frequency (dif) or its reverse.
+__device__ __forceinline__ void fft_lines(double2 *P, const Axis &a, int nlines, const int *lines, int lmul,
+                                          int lmod, int lshift, int lstride, int es, bool dif) {
+  if (dif) {
+    for (int s = 0; s < a.nst; ++s) {
+      fft_stage(P, nlines, lines, lmul, lmod, lshift, lstride, es, a.n, a.rad[s], a.span[s], a.tw, true);
+      __syncthreads();
+    }
+  } else {
+    for (int s = a.nst - 1; s >= 0; --s) {
+      fft_stage(P, nlines, lines, lmul, lmod, lshift, lstride, es, a.n, a.rad[s], a.span[s], a.tw, false);
+      __syncthreads();
+    }
+  }
+}
+
+__device__ __forceinline__ int wrap(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// y-lines (fixed x, contiguous) over the active x columns of a basis shifted by g0x.
+__device__ __forceinline__ void fft_y_active(double2 *P, const Plane &pl, const Sticks &sk, const EntryDev &E,
+                                             int g0x, bool dif) {
+  fft_lines(P, pl.ay, E.nxa, sk.xa + E.xa_off, pl.n2, pl.n1, g0x, 0, 1, dif);
+}
+__device__ __forceinline__ void fft_y_all(double2 *P, const Plane &pl, bool dif) {
+  fft_lines(P, pl.ay, pl.n1, nullptr, 0, 1, 0, pl.n2, 1, dif);
+}
+// x-lines (fixed y, stride N2) over every y.
+__device__ __forceinline__ void fft_x_all(double2 *P, const Plane &pl, bool dif) {
+  fft_lines(P, pl.ax, pl.n2, nullptr, 0, 1, 0, 1, pl.n2, dif);
+}
+
+__device__ __forceinline__ void plane_zero(double2 *P, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) P[i] = make_double2(0.0, 0.0);
+}
+
+__device__ __forceinline__ void basis_of(const KPair *kp, int k, int use_kq, int &e, int &g0x, int &g0y, int &g0z) {
+  const KPair P = kp[k];
+  if (use_kq) {
+    e = P.ej;
+    g0x = P.g0[0];
+    g0y = P.g0[1];
+    g0z = P.g0[2];
+  } else {
+    e = P.ek;
+    g0x = g0y = g0z = 0;
+  }
+}
+
+// ----------------------------------------------------------------- kernels
+
+__global__ void __launch_bounds__(kThreads) k_stick_inv(Sticks sk, const KPair *kp, int use_kq, int nb,
+                                                        const double2 *__restrict__ X, int ld,
+                                                        double2 *__restrict__ S, int ns_pad, int n3,
+                                                        const double2 *__restrict__ tw3) {
+  extern __shared__ double2 smem[];
+  const int item = blockIdx.y;
+  const int k = item / nb;
+  int e, g0x, g0y, g0z;
+  basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
+  const EntryDev E = sk.ent[e];
+  const int s0 = blockIdx.x * kStickChunk;
+  if (s0 >= E.ns) return;
+  const int s1 = min(s0 + kStickChunk, E.ns);
+  const int *sstart = sk.sstart + E.st_off;
+  const int *slen = sk.slen + E.st_off;
+  const int p0 = sstart[s0];
+  const int p1 = sstart[s1 - 1] + slen[s1 - 1];
+  double2 *c = smem;
+  int *zi = reinterpret_cast<int *>(smem + (p1 - p0));
+  const double2 *x = X + (size_t)item * ld;
+  for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    c[p - p0] = x[p];
+    zi[p - p0] = wrap(sk.iz[E.pw_off + p] - g0z, n3);
+  }
+  __syncthreads();
+  const int nsc = s1 - s0;
+  double2 *out = S + (size_t)item * n3 * ns_pad;
+  for (int idx = threadIdx.x; idx < nsc * n3; idx += blockDim.x) {
+    const int z = idx / nsc;
+    const int s = s0 + (idx - z * nsc);
+    const int a = sstart[s] - p0;
+    const int len = slen[s];
+    double2 acc = make_double2(0.0, 0.0);
+    for (int t = 0; t < len; ++t) {
+      const double2 w = tw3[(zi[a + t] * z) % n3];
+      acc = cadd(acc, cmul(c[a + t], w));
+    }
+    out[(size_t)z * ns_pad + s] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_stick_fwd(Sticks sk, const KPair *kp, int use_kq, int nb,
+                                                        const double2 *__restrict__ S, int ns_pad, int n3,
+                                                        const double2 *__restrict__ tw3, double scale,
+                                                        double2 *__restrict__ Y, int ld, int mode,
+                                                        const double *__restrict__ kin,
+                                                        const double *__restrict__ eps,
+                                                        const double2 *__restrict__ X, int eps_stride) {
+  extern __shared__ double2 smem[];
+  const int item = blockIdx.y;
+  const int k = item / nb;
+  const int v = item - k * nb;
+  int e, g0x, g0y, g0z;
+  basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
+  const EntryDev E = sk.ent[e];
+  const int s0 = blockIdx.x * kStickChunk;
+  if (s0 >= E.ns) return;
+  const int s1 = min(s0 + kStickChunk, E.ns);
+  const int nsc = s1 - s0;
+  const int *sstart = sk.sstart + E.st_off;
+  const int *slen = sk.slen + E.st_off;
+  const int p0 = sstart[s0];
+  const int p1 = sstart[s1 - 1] + slen[s1 - 1];
+  double2 *sl = smem;                                   // [n3][nsc]
+  int *own = reinterpret_cast<int *>(smem + n3 * nsc);  // [p1-p0] stick of each plane wave
+  if (S) {
+    const double2 *in = S + (size_t)item * n3 * ns_pad;
+    for (int idx = threadIdx.x; idx < nsc * n3; idx += blockDim.x) {
+      const int z = idx / nsc;
+      const int s = idx - z * nsc;
+      sl[idx] = in[(size_t)z * ns_pad + s0 + s];
+    }
+  }
+  for (int s = s0 + threadIdx.x; s < s1; s += blockDim.x)
+    for (int t = 0; t < slen[s]; ++t) own[sstart[s] - p0 + t] = s - s0;
+  __syncthreads();
+  double2 *y = Y + (size_t)item * ld;
+  const double2 *x = X ? X + (size_t)item * ld : nullptr;
+  const double ev = eps ? eps[(size_t)k * eps_stride + v] : 0.0;
+  for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    double2 acc = make_double2(0.0, 0.0);
+    if (S) {
+      const int s = own[p - p0];
+      const int zz = wrap(sk.iz[E.pw_off + p] - g0z, n3);
+      for (int z = 0; z < n3; ++z) {
+        const double2 w = tw3[(zz * z) % n3];
+        acc = cadd(acc, cmulc(sl[z * nsc + s], w));
+      }
+      acc = cscale(acc, scale);
+    }
+    if (mode == 0) {
+      const double2 xv = x[p];
+      const double d = kin[E.pw_off + p] - ev;
+      acc = make_double2(acc.x + d * xv.x, acc.y + d * xv.y);
+    }
+    y[p] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_plane_vloc(Plane pl, Sticks sk, const KPair *kp, int use_kq, int nb,
+                                                         const double2 *__restrict__ Sin,
+                                                         double2 *__restrict__ Sout, int ns_pad,
+                                                         const double *__restrict__ vp) {
+  extern __shared__ double2 P[];
+  const int z = blockIdx.x;
+  const int item = blockIdx.y;
+  const int k = item / nb;
+  int e, g0x, g0y, g0z;
+  basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
+  const EntryDev E = sk.ent[e];
+  const int np = pl.n1 * pl.n2;
+  plane_zero(P, np);
+  __syncthreads();
+  const int *sx = sk.sx + E.st_off;
+  const int *sy = sk.sy + E.st_off;
+  const size_t so = ((size_t)item * pl.n3 + z) * ns_pad;
+  for (int s = threadIdx.x; s < E.ns; s += blockDim.x)
+    P[wrap(sx[s] - g0x, pl.n1) * pl.n2 + wrap(sy[s] - g0y, pl.n2)] = Sin[so + s];
+  __syncthreads();
+  fft_y_active(P, pl, sk, E, g0x, true);
+  fft_x_all(P, pl, true);
+  const double *v = vp + (size_t)z * np;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = cscale(P[i], v[i]);
+  __syncthreads();
+  fft_x_all(P, pl, false);
+  fft_y_active(P, pl, sk, E, g0x, false);
+  for (int s = threadIdx.x; s < E.ns; s += blockDim.x)
+    Sout[so + s] = P[wrap(sx[s] - g0x, pl.n1) * pl.n2 + wrap(sy[s] - g0y, pl.n2)];
+}
+
+__global__ void __launch_bounds__(kThreads) k_plane_to_real(Plane pl, Sticks sk, const KPair *kp, int use_kq,
+                                                            int nb, const double2 *__restrict__ Sin, int ns_pad,
+                                                            double2 *__restrict__ R) {
+  extern __shared__ double2 P[];
+  const int z = blockIdx.x;
+  const int item = blockIdx.y;
+  const int k = item / nb;
+  int e, g0x, g0y, g0z;
+  basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
+  const EntryDev E = sk.ent[e];
+  const int np = pl.n1 * pl.n2;
+  plane_zero(P, np);
+  __syncthreads();
+  const int *sx = sk.sx + E.st_off;
+  const int *sy = sk.sy + E.st_off;
+  const size_t so = ((size_t)item * pl.n3 + z) * ns_pad;
+  for (int s = threadIdx.x; s < E.ns; s += blockDim.x)
+    P[wrap(sx[s] - g0x, pl.n1) * pl.n2 + wrap(sy[s] - g0y, pl.n2)] = Sin[so + s];
+  __syncthreads();
+  fft_y_active(P, pl, sk, E, g0x, true);
+  fft_x_all(P, pl, true);
+  double2 *out = R + ((size_t)item * pl.n3 + z) * np;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) out[i] = P[i];
+}
+
+__global__ void __launch_bounds__(kThreads) k_plane_mul_fwd(Plane pl, Sticks sk, const KPair *kp, int nb,
+                                                            const double2 *__restrict__ psi,
+                                                            const double2 *__restrict__ dv,
+                                                            double2 *__restrict__ Sout, int ns_pad) {
+  extern __shared__ double2 P[];
+  const int z = blockIdx.x;
+  const int item = blockIdx.y;
+  const int k = item / nb;
+  int e, g0x, g0y, g0z;
+  basis_of(kp, k, 1, e, g0x, g0y, g0z);
+  const EntryDev E = sk.ent[e];
+  const int np = pl.n1 * pl.n2;
+  const double2 *ps = psi + ((size_t)item * pl.n3 + z) * np;
+  const double2 *d = dv + (size_t)z * np;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = cmul(ps[i], d[i]);
+  __syncthreads();
+  fft_x_all(P, pl, false);
+  fft_y_active(P, pl, sk, E, g0x, false);
+  const int *sx = sk.sx + E.st_off;
+  const int *sy = sk.sy + E.st_off;
+  const size_t so = ((size_t)item * pl.n3 + z) * ns_pad;
+  for (int s = threadIdx.x; s < E.ns; s += blockDim.x)
+    Sout[so + s] = P[wrap(sx[s] - g0x, pl.n1) * pl.n2 + wrap(sy[s] - g0y, pl.n2)];
+}
+
+__global__ void __launch_bounds__(kThreads) k_plane_drho(Plane pl, Sticks sk, const KPair *kp, int nb,
+                                                         const double2 *__restrict__ Sdu, int ns_pad,
+                                                         const double2 *__restrict__ psi,
+                                                         double2 *__restrict__ part) {
+  extern __shared__ double2 P[];
+  const int z = blockIdx.x;
+  const int k = blockIdx.y;
+  int e, g0x, g0y, g0z;
+  basis_of(kp, k, 1, e, g0x, g0y, g0z);
+  const EntryDev E = sk.ent[e];
+  const int np = pl.n1 * pl.n2;
+  const int *sx = sk.sx + E.st_off;
+  const int *sy = sk.sy + E.st_off;
+  double2 acc[kMaxPerThread];
+  for (int j = 0; j < kMaxPerThread; ++j) acc[j] = make_double2(0.0, 0.0);
+  for (int v = 0; v < nb; ++v) {
+    const int item = k * nb + v;
+    plane_zero(P, np);
+    __syncthreads();
+    const size_t so = ((size_t)item * pl.n3 + z) * ns_pad;
+    for (int s = threadIdx.x; s < E.ns; s += blockDim.x)
+      P[wrap(sx[s] - g0x, pl.n1) * pl.n2 + wrap(sy[s] - g0y, pl.n2)] = Sdu[so + s];
+    __syncthreads();
+    fft_y_active(P, pl, sk, E, g0x, true);
+    fft_x_all(P, pl, true);
+    const double2 *ps = psi + ((size_t)item * pl.n3 + z) * np;
+#pragma unroll
+    for (int j = 0; j < kMaxPerThread; ++j) {
+      const int i = threadIdx.x + j * blockDim.x;
+      if (i < np) acc[j] = cadd(acc[j], cmulc(P[i], ps[i]));
+    }
+    __syncthreads();
+  }
+  double2 *out = part + ((size_t)k * pl.n3 + z) * np;
+#pragma unroll
+  for (int j = 0; j < kMaxPerThread; ++j) {
+    const int i = threadIdx.x + j * blockDim.x;
+    if (i < np) out[i] = acc[j];
+  }
+}
+
+__global__ void k_drho_reduce(const KPair *kp, int nk, const double2 *__restrict__ part, long nr, double inv_omega,
+                              double2 *__restrict__ drho) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= nr) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int k = 0; k < nk; ++k) {
+    const double w = 4.0 * kp[k].weight * inv_omega;
+    const double2 p = part[(size_t)k * nr + i];
+    acc.x += w * p.x;
+    acc.y += w * p.y;
+  }
+  drho[i] = acc;
+}
+
+// Hartree step 1: permuted real-space plane -> natural plane of G_x, G_y (forward).
+__global__ void __launch_bounds__(kThreads) k_hxc_planes_fwd(Plane pl, const double2 *__restrict__ drho,
+                                                             double2 *__restrict__ tmp) {
+  extern __shared__ double2 P[];
+  const int z = blockIdx.x;
+  const int np = pl.n1 * pl.n2;
+  const double2 *in = drho + (size_t)z * np;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = in[i];
+  __syncthreads();
+  fft_x_all(P, pl, false);
+  fft_y_all(P, pl, false);
+  double2 *out = tmp + (size_t)z * np;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) out[i] = P[i];
+}
+
+__device__ __forceinline__ int freq_of(int j, int n) { return j < (n + 1) / 2 ? j : j - n; }
+
+// Hartree step 2: along z, forward DFT, multiply by 4 pi / |q+G|^2 / N_r, inverse DFT.
+__global__ void k_hxc_columns(Plane pl, const double2 *__restrict__ tw3, const double *__restrict__ bvec,
+                              double q0, double q1, double q2, double2 *__restrict__ tmp) {
+  extern __shared__ double2 sm[];
+  const int n3 = pl.n3;
+  const int np = pl.n1 * pl.n2;
+  const int cols = blockDim.x;
+  const int c0 = blockIdx.x * cols;
+  const int c = c0 + threadIdx.x;
+  double2 *a = sm;               // [n3][cols]
+  double2 *f = sm + n3 * cols;   // [n3][cols]
+  if (c < np)
+    for (int z = 0; z < n3; ++z) a[z * cols + threadIdx.x] = tmp[(size_t)z * np + c];
+  __syncthreads();
+  if (c >= np) return;
+  const int x = c / pl.n2, y = c - x * pl.n2;
+  const double mx = freq_of(x, pl.n1) + q0, my = freq_of(y, pl.n2) + q1;
+  const double inv_nr = 1.0 / ((double)np * n3);
+  for (int zz = 0; zz < n3; ++zz) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int z = 0; z < n3; ++z) acc = cadd(acc, cmulc(a[z * cols + threadIdx.x], tw3[(z * zz) % n3]));
+    const double mz = freq_of(zz, n3) + q2;
+    const double gx = mx * bvec[0] + my * bvec[3] + mz * bvec[6];
+    const double gy = mx * bvec[1] + my * bvec[4] + mz * bvec[7];
+    const double gz = mx * bvec[2] + my * bvec[5] + mz * bvec[8];
+    const double g2 = gx * gx + gy * gy + gz * gz;
+    const double s = g2 > 1e-12 ? 4.0 * M_PI / g2 * inv_nr : 0.0;
+    f[zz * cols + threadIdx.x] = cscale(acc, s);
+  }
+  for (int z = 0; z < n3; ++z) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int zz = 0; zz < n3; ++zz) acc = cadd(acc, cmul(f[zz * cols + threadIdx.x], tw3[(z * zz) % n3]));
+    tmp[(size_t)z * np + c] = acc;
+  }
+}
+
+// Hartree step 3: natural plane -> permuted real space, plus f_xc * drho.
+__global__ void __launch_bounds__(kThreads) k_hxc_planes_inv(Plane pl, const double2 *__restrict__ tmp,
+                                                             const double *__restrict__ fxc,
+                                                             const double2 *__restrict__ drho,
+                                                             double2 *__restrict__ dvout) {
+  extern __shared__ double2 P[];
+  const int z = blockIdx.x;
+  const int np = pl.n1 * pl.n2;
+  const double2 *in = tmp + (size_t)z * np;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = in[i];
+  __syncthreads();
+  fft_y_all(P, pl, true);
+  fft_x_all(P, pl, true);
+  const size_t o = (size_t)z * np;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    const double fx = fxc[o + i];
+    const double2 d = drho[o + i];
+    dvout[o + i] = make_double2(P[i].x + fx * d.x, P[i].y + fx * d.y);
+  }
+}
+
+__global__ void k_permute_real(Plane pl, const int *__restrict__ px, const int *__restrict__ py,
+                               const double *__restrict__ in, double *__restrict__ out) {
+  // in: [N1][N2][N3] natural; out: [N3][xp][yp]
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long np = (long)pl.n1 * pl.n2;
+  if (i >= np * pl.n3) return;
+  const int z = (int)(i / np);
+  const int r = (int)(i - z * np);
+  const int xp = r / pl.n2, yp = r - xp * pl.n2;
+  out[i] = in[((long)px[xp] * pl.n2 + py[yp]) * pl.n3 + z];
+}
+
+__global__ void k_permute_complex(Plane pl, const int *__restrict__ px, const int *__restrict__ py,
+                                  const double2 *__restrict__ in, double2 *__restrict__ out, int inverse) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long np = (long)pl.n1 * pl.n2;
+  if (i >= np * pl.n3) return;
+  const int z = (int)(i / np);
+  const int r = (int)(i - z * np);
+  const int xp = r / pl.n2, yp = r - xp * pl.n2;
+  const long nat = ((long)px[xp] * pl.n2 + py[yp]) * pl.n3 + z;
+  if (inverse)
+    out[nat] = in[i];
+  else
+    out[i] = in[nat];
+}
+
+__global__ void k_fxc(const double *__restrict__ rho, double *__restrict__ fxc, long n) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double r = rho[i];
+  if (!(r > 1e-10)) {
+    fxc[i] = 0.0;
+    return;
+  }
+  // Perdew-Zunger 1981 LDA, spin unpolarized, Hartree units.
+  const double gamma = -0.1423, beta1 = 1.0529, beta2 = 0.3334;
+  const double A = 0.0311, C = 0.0020, D = -0.0116;
+  const double rs = cbrt(3.0 / (4.0 * M_PI * r));
+  const double fx = -(1.0 / 3.0) * cbrt(3.0 / M_PI) / cbrt(r * r);
+  double dv;
+  if (rs >= 1.0) {
+    const double sq = sqrt(rs);
+    const double num = 1.0 + 7.0 / 6.0 * beta1 * sq + 4.0 / 3.0 * beta2 * rs;
+    const double den = 1.0 + beta1 * sq + beta2 * rs;
+    const double dnum = 7.0 / 12.0 * beta1 / sq + 4.0 / 3.0 * beta2;
+    const double dden = 0.5 * beta1 / sq + beta2;
+    dv = gamma * (dnum * den - 2.0 * num * dden) / (den * den * den);
+  } else {
+    dv = A / rs + 2.0 / 3.0 * C * (log(rs) + 1.0) + (2.0 * D - C) / 3.0;
+  }
+  fxc[i] = fx + dv * (-rs / (3.0 * r));
+}
+
+int plane_lds(const Plane &pl) { return pl.n1 * pl.n2 * (int)sizeof(double2); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_stick_inv(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const double2 *X,
+                            int ld, double2 *S, int ns_pad, int n3, const double2 *tw3, int max_chunk_pw,
+                            int ns_max, hipStream_t st) {
+  dim3 grid((ns_max + kStickChunk - 1) / kStickChunk, nitems);
+  size_t lds = (size_t)max_chunk_pw * (sizeof(double2) + sizeof(int));
+  hipLaunchKernelGGL(k_stick_inv, grid, dim3(kThreads), lds, st, sk, kp, use_kq, nb, X, ld, S, ns_pad, n3, tw3);
+  return hipGetLastError();
+}
+
+hipError_t launch_stick_fwd(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const double2 *S,
+                            int ns_pad, int n3, const double2 *tw3, double scale, double2 *Y, int ld, int mode,
+                            const double *kin, const double *eps, const double2 *X, int eps_stride,
+                            int max_chunk_pw, int ns_max, hipStream_t st) {
+  dim3 grid((ns_max + kStickChunk - 1) / kStickChunk, nitems);
+  size_t lds = (size_t)n3 * kStickChunk * sizeof(double2) + (size_t)max_chunk_pw * sizeof(int);
+  hipLaunchKernelGGL(k_stick_fwd, grid, dim3(kThreads), lds, st, sk, kp, use_kq, nb, S, ns_pad, n3, tw3, scale, Y,
+                     ld, mode, kin, eps, X, eps_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_vloc(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
+                             const double2 *Sin, double2 *Sout, int ns_pad, const double *vp, hipStream_t st) {
+  hipLaunchKernelGGL(k_plane_vloc, dim3(pl.n3, nitems), dim3(kThreads), plane_lds(pl), st, pl, sk, kp, use_kq, nb,
+                     Sin, Sout, ns_pad, vp);
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_to_real(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
+                                const double2 *Sin, int ns_pad, double2 *R, hipStream_t st) {
+  hipLaunchKernelGGL(k_plane_to_real, dim3(pl.n3, nitems), dim3(kThreads), plane_lds(pl), st, pl, sk, kp, use_kq,
+                     nb, Sin, ns_pad, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_mul_fwd(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nitems,
+                                const double2 *psi, const double2 *dv, double2 *Sout, int ns_pad, hipStream_t st) {
+  hipLaunchKernelGGL(k_plane_mul_fwd, dim3(pl.n3, nitems), dim3(kThreads), plane_lds(pl), st, pl, sk, kp, nb, psi,
+                     dv, Sout, ns_pad);
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_drho(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nk, const double2 *Sdu,
+                             int ns_pad, const double2 *psi, double2 *part, hipStream_t st) {
+  if (pl.n1 * pl.n2 > kMaxPerThread * kThreads) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_plane_drho, dim3(pl.n3, nk), dim3(kThreads), plane_lds(pl), st, pl, sk, kp, nb, Sdu, ns_pad,
+                     psi, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_drho_reduce(const KPair *kp, int nk, const double2 *part, long nr, double inv_omega, double2 *drho,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_drho_reduce, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, kp, nk, part, nr,
+                     inv_omega, drho);
+  return hipGetLastError();
+}
+
+hipError_t launch_hxc(const Plane &pl, const Axis &az, const double *bvec, const double *q, const double2 *drho,
+                      const double *fxc, double2 *tmp, double2 *dvout, hipStream_t st) {
+  hipLaunchKernelGGL(k_hxc_planes_fwd, dim3(pl.n3), dim3(kThreads), plane_lds(pl), st, pl, drho, tmp);
+  const int cols = 32;
+  const int np = pl.n1 * pl.n2;
+  hipLaunchKernelGGL(k_hxc_columns, dim3((np + cols - 1) / cols), dim3(cols), 2 * pl.n3 * cols * sizeof(double2), st,
+                     pl, az.tw, bvec, q[0], q[1], q[2], tmp);
+  hipLaunchKernelGGL(k_hxc_planes_inv, dim3(pl.n3), dim3(kThreads), plane_lds(pl), st, pl, tmp, fxc, drho, dvout);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute_real(const Plane &pl, const int *px, const int *py, const double *in, double *out,
+                               hipStream_t st) {
+  long n = (long)pl.n1 * pl.n2 * pl.n3;
+  hipLaunchKernelGGL(k_permute_real, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pl, px, py, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute_complex(const Plane &pl, const int *px, const int *py, const double2 *in, double2 *out,
+                                  int inverse, hipStream_t st) {
+  long n = (long)pl.n1 * pl.n2 * pl.n3;
+  hipLaunchKernelGGL(k_permute_complex, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pl, px, py, in, out,
+                     inverse);
+  return hipGetLastError();
+}
+
+hipError_t launch_fxc(const double *rho, double *fxc, long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fxc, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rho, fxc, n);
+  return hipGetLastError();
+}
+
+}  // namespace hp

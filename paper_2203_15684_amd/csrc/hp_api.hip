@@ -1,0 +1,1122 @@
+// C ABI of the HIP Hubbard-response library: validation, device layout of the
+// ground state, the self-consistent Sternheimer driver and the assembly of
+// chi0 / chi / U,V.  See include/hp.h for the contract of each entry point.
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "hp_internal.h"
+
+using namespace hp;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+hp_status fail(hp_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HPCHK(expr)                                                                          \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(e_ == hipErrorOutOfMemory ? HP_ERR_OOM : HP_ERR_HIP, "%s failed: %s (%s:%d)", #expr, \
+                  hipGetErrorString(e_), __FILE__, __LINE__);                                \
+  } while (0)
+
+#define HPTRY(expr)                     \
+  do {                                  \
+    hp_status s_ = (expr);              \
+    if (s_ < 0) return s_;              \
+  } while (0)
+
+bool factor_235(int n, std::vector<int> &rad) {
+  rad.clear();
+  if (n < 1) return false;
+  while (n % 8 == 0) { rad.push_back(8); n /= 8; }
+  while (n % 4 == 0) { rad.push_back(4); n /= 4; }
+  while (n % 2 == 0) { rad.push_back(2); n /= 2; }
+  while (n % 3 == 0) { rad.push_back(3); n /= 3; }
+  while (n % 5 == 0) { rad.push_back(5); n /= 5; }
+  return n == 1 && rad.size() <= 8;
+}
+
+// Position p of a decimation-in-frequency output holds natural index perm[p].
+std::vector<int> dif_perm(int n, const std::vector<int> &rad) {
+  std::vector<int> span, perm(n);
+  int pr = 1;
+  for (int r : rad) { pr *= r; span.push_back(n / pr); }
+  for (int k = 0; k < n; ++k) {
+    int kk = k, p = 0;
+    for (size_t s = 0; s < rad.size(); ++s) { p += (kk % rad[s]) * span[s]; kk /= rad[s]; }
+    perm[p] = k;
+  }
+  return perm;
+}
+
+template <class T>
+hp_status dalloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? HP_ERR_OOM : HP_ERR_HIP, "hipMalloc of %zu bytes: %s",
+                                   count * sizeof(T), hipGetErrorString(e));
+  return HP_OK;
+}
+
+int wrapi(long v, int n) { long r = v % n; return (int)(r < 0 ? r + n : r); }
+
+struct HostEntry {
+  std::array<double, 3> k;
+  double weight;
+  int npw;
+  std::vector<int> order;  // internal position -> caller index
+};
+
+}  // namespace
+
+struct hp_ctx {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int n1 = 0, n2 = 0, n3 = 0;
+  long nr = 0, np = 0;
+  int n_occ = 0, n_beta = 0, n_hub = 0, n_mesh = 0, n_kpts = 0;
+  int ld = 0, ns_pad = 0, ns_max = 0, max_chunk_pw = 0, npw_max = 0, n_proj = 0;
+  double cell[9], bvec[9], omega = 0, alpha = 0;
+  std::vector<HostEntry> ent;
+  std::vector<int> px, py;
+  Plane pl{};
+  Axis az{};
+  Sticks sk{};
+  // device allocations (freed by hp_destroy)
+  std::vector<void *> allocs;
+  double2 *tw = nullptr;
+  int *d_px = nullptr, *d_py = nullptr;
+  double *d_vp = nullptr, *d_fxc = nullptr, *d_bvec = nullptr, *d_q = nullptr;
+  int *d_npw = nullptr;
+  double *d_kin = nullptr, *d_diag = nullptr, *d_rowscale = nullptr, *d_eps = nullptr;
+  double2 *d_T = nullptr, *d_phi = nullptr, *d_A = nullptr, *d_psi = nullptr;
+  KPair *d_kp = nullptr, *d_kself = nullptr;
+  // work
+  double2 *B = nullptr, *X = nullptr, *R = nullptr, *P = nullptr, *AP = nullptr;
+  double2 *S1 = nullptr, *S2 = nullptr, *Cpart = nullptr, *C = nullptr, *Cphi = nullptr;
+  double *rz = nullptr, *bn = nullptr, *rn = nullptr;
+  int *active = nullptr, *count = nullptr;
+  double2 *part = nullptr, *drho = nullptr, *dvin = nullptr, *dvout = nullptr, *f = nullptr, *tmp = nullptr;
+  double2 *fprev = nullptr, *dvprev = nullptr, *hdf = nullptr, *hdv = nullptr;
+  double2 *dots_part = nullptr, *dots = nullptr, *dn = nullptr, *coef = nullptr;
+  const double2 **ptrs = nullptr;
+  int nsplit_cap = 16;
+  long t_stride = 0, phi_stride = 0;
+  hipEvent_t ev[16];
+
+  template <class T>
+  hp_status alloc(T **p, size_t count) {
+    HPTRY(dalloc(p, count));
+    allocs.push_back((void *)*p);
+    return HP_OK;
+  }
+};
+
+namespace {
+
+constexpr int kNmixMax = 8;
+
+hp_status check_kpoint(const hp_kpoint &k, int i, const hp_ground_state *gs) {
+  if (k.struct_size != sizeof(hp_kpoint)) return fail(HP_ERR_ARG, "kpts[%d].struct_size mismatch", i);
+  if (k.npw < 1) return fail(HP_ERR_ARG, "kpts[%d].npw = %d", i, k.npw);
+  if (!k.miller || !k.eps || !k.u || !k.beta || !k.phi) return fail(HP_ERR_ARG, "kpts[%d] has a NULL array", i);
+  if (!(k.weight >= 0.0)) return fail(HP_ERR_ARG, "kpts[%d].weight < 0", i);
+  (void)gs;
+  return HP_OK;
+}
+
+// Host-side view of one k-entry after sorting plane waves into z-sticks.
+struct Layout {
+  std::vector<int> order;         // internal -> caller
+  std::vector<int> sx, sy, sstart, slen, iz, xa;
+};
+
+hp_status build_layout(const hp_kpoint &k, int n1, int n2, int n3, Layout &L, int idx) {
+  const int npw = k.npw;
+  std::vector<long> key(npw);
+  int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+  for (int p = 0; p < npw; ++p) {
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = std::min(mn[d], k.miller[3 * p + d]);
+      mx[d] = std::max(mx[d], k.miller[3 * p + d]);
+    }
+  }
+  const int N[3] = {n1, n2, n3};
+  for (int d = 0; d < 3; ++d)
+    if (mx[d] - mn[d] + 1 > N[d])
+      return fail(HP_ERR_SHAPE, "kpts[%d]: sphere spans %d along axis %d, grid has %d", idx, mx[d] - mn[d] + 1, d, N[d]);
+  for (int p = 0; p < npw; ++p) {
+    const int x = wrapi(k.miller[3 * p], n1), y = wrapi(k.miller[3 * p + 1], n2), z = wrapi(k.miller[3 * p + 2], n3);
+    key[p] = ((long)x * n2 + y) * n3 + z;
+  }
+  L.order.resize(npw);
+  std::iota(L.order.begin(), L.order.end(), 0);
+  std::sort(L.order.begin(), L.order.end(), [&](int a, int b) { return key[a] < key[b]; });
+  for (int p = 1; p < npw; ++p)
+    if (key[L.order[p]] == key[L.order[p - 1]]) return fail(HP_ERR_SHAPE, "kpts[%d]: repeated plane wave", idx);
+  long last_col = -1;
+  for (int p = 0; p < npw; ++p) {
+    const long kk = key[L.order[p]];
+    const long col = kk / n3;
+    if (col != last_col) {
+      L.sx.push_back((int)(col / n2));
+      L.sy.push_back((int)(col % n2));
+      L.sstart.push_back(p);
+      L.slen.push_back(0);
+      if (L.xa.empty() || L.xa.back() != (int)(col / n2)) L.xa.push_back((int)(col / n2));
+      last_col = col;
+    }
+    L.slen.back()++;
+    L.iz.push_back((int)(kk % n3));
+  }
+  return HP_OK;
+}
+
+struct Timer {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double s() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+hp_status sync(hp_ctx *c) {
+  HPCHK(hipStreamSynchronize(c->stream));
+  return HP_OK;
+}
+
+// nsplit for the projection GEMM so that a launch has enough workgroups.
+int choose_nsplit(int M, int nb, int nk, int npw_max) {
+  const int tiles = ((M + 31) / 32) * ((nb + 31) / 32) * nk;
+  int ns = (2048 + tiles - 1) / tiles;
+  ns = std::max(1, std::min(ns, 16));
+  while (ns > 1 && npw_max / ns < 256) --ns;
+  return ns;
+}
+
+// C[k][m][v] = scale_m * sum_G conj(T[m0+m][G]) X[k,v][G]
+hp_status proj(hp_ctx *c, const KPair *kp, int use_kq, int nk, const double2 *T, long tstride, int m0, int M,
+               const double2 *X, int nb, const double *row_scale, double gscale, double2 *Cout) {
+  const int ns = choose_nsplit(M, nb, nk, c->npw_max);
+  HPCHK(launch_zproj(kp, use_kq, nk, T, tstride, m0, M, X, c->ld, nb, c->d_npw, c->Cpart, ns, c->stream));
+  HPCHK(launch_zproj_reduce(nk, M, nb, ns, c->Cpart, row_scale, gscale, Cout, c->stream));
+  return HP_OK;
+}
+
+// Y = (H_{k+q} + alpha P_v - eps_v) X over nitems (or H_k X for diagnostics when eps == nullptr,
+// rows = n_beta only).
+hp_status apply_op(hp_ctx *c, const KPair *kp, int use_kq, int nk, int nb, const double2 *Xin, double2 *Y,
+                   const double *eps, int rows) {
+  const int nitems = nk * nb;
+  HPCHK(launch_stick_inv(c->sk, kp, use_kq, nb, nitems, Xin, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
+                         c->max_chunk_pw, c->ns_max, c->stream));
+  HPCHK(launch_plane_vloc(c->pl, c->sk, kp, use_kq, nb, nitems, c->S1, c->S2, c->ns_pad, c->d_vp, c->stream));
+  HPCHK(launch_stick_fwd(c->sk, kp, use_kq, nb, nitems, c->S2, c->ns_pad, c->n3, c->az.tw, 1.0 / (double)c->nr, Y,
+                         c->ld, 0, c->d_kin, eps, Xin, nb, c->max_chunk_pw, c->ns_max, c->stream));
+  HPTRY(proj(c, kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, Xin, nb, c->d_rowscale, 1.0, c->C));
+  HPCHK(launch_zexpand(kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, c->C, (long)rows * nb, 1.0, Y, c->ld, nb,
+                       c->d_npw, c->npw_max, c->stream));
+  return HP_OK;
+}
+
+// RHS of Eq. 15 for nk pairs: B = -P_c (dv psi + V_pert psi); dv may be null.
+hp_status build_rhs(hp_ctx *c, const KPair *kp, int nk, int site, const double2 *dv, const double2 *psi) {
+  const int nb = c->n_occ, nitems = nk * nb;
+  if (dv) {
+    HPCHK(launch_plane_mul_fwd(c->pl, c->sk, kp, nb, nitems, psi, dv, c->S1, c->ns_pad, c->stream));
+    HPCHK(launch_stick_fwd(c->sk, kp, 1, nb, nitems, c->S1, c->ns_pad, c->n3, c->az.tw, -1.0 / (double)c->nr, c->B,
+                           c->ld, 2, nullptr, nullptr, nullptr, nb, c->max_chunk_pw, c->ns_max, c->stream));
+  } else {
+    HPCHK(hipMemsetAsync(c->B, 0, sizeof(double2) * (size_t)nitems * c->ld, c->stream));
+  }
+  // - sum_m |phi_{m,k+q}> <phi_{m,k}|u_vk>   (Eq. 16)
+  HPCHK(launch_zexpand(kp, 1, nk, c->d_phi, c->phi_stride, 5 * site, 5, c->d_A + (size_t)5 * site * nb,
+                       (long)5 * c->n_hub * nb, -1.0, c->B, c->ld, nb, c->d_npw, c->npw_max, c->stream));
+  // P_c = 1 - sum_v' |u_v',k+q><u_v',k+q|   (Eq. 18)
+  HPTRY(proj(c, kp, 1, nk, c->d_T, c->t_stride, c->n_beta, c->n_occ, c->B, nb, nullptr, 1.0, c->C));
+  HPCHK(launch_zexpand(kp, 1, nk, c->d_T, c->t_stride, c->n_beta, c->n_occ, c->C, (long)c->n_occ * nb, -1.0, c->B,
+                       c->ld, c->n_occ, c->d_npw, c->npw_max, c->stream));
+  return HP_OK;
+}
+
+// Batched preconditioned CG on (H_{k+q} + alpha O_{k+q} - eps_vk) X = B (Eq. 15).
+hp_status cg_solve(hp_ctx *c, const KPair *kp, int nk, const double *eps_items, int warm, double tol, int max_it,
+                   int *iters, int *not_conv, double *max_rel, long *happ) {
+  const int nb = c->n_occ, nitems = nk * nb;
+  const int rows = c->n_beta + c->n_occ;
+  if (warm) HPTRY(apply_op(c, kp, 1, nk, nb, c->X, c->AP, eps_items, rows));
+  if (warm) *happ += nitems;
+  HPCHK(launch_cg_init(kp, nb, nitems, c->B, c->X, c->R, c->P, c->AP, warm, c->d_diag, eps_items, c->ld, c->d_npw,
+                       c->ld, c->rz, c->bn, c->rn, c->active, tol, c->stream));
+  int it = 0;
+  int h_count[2] = {0, 0};
+  // number of active items after init
+  HPCHK(hipMemsetAsync(c->count, 0, 2 * sizeof(int), c->stream));
+  {
+    std::vector<int> act(nitems);
+    HPCHK(hipMemcpyAsync(act.data(), c->active, sizeof(int) * nitems, hipMemcpyDeviceToHost, c->stream));
+    HPTRY(sync(c));
+    h_count[0] = 0;
+    for (int a : act) h_count[0] += a;
+  }
+  while (h_count[0] > 0 && it < max_it) {
+    ++it;
+    HPTRY(apply_op(c, kp, 1, nk, nb, c->P, c->AP, eps_items, rows));
+    *happ += nitems;
+    HPCHK(hipMemsetAsync(c->count, 0, 2 * sizeof(int), c->stream));
+    HPCHK(launch_cg_step(kp, nb, nitems, c->X, c->R, c->P, c->AP, c->d_diag, eps_items, c->ld, c->d_npw, c->ld, c->rz,
+                         c->bn, c->rn, c->active, tol, c->count, c->stream));
+    HPCHK(hipMemcpyAsync(h_count, c->count, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HPTRY(sync(c));
+    if (h_count[1] > 0) return fail(HP_ERR_NUMERIC, "non-finite residual in the Sternheimer solve");
+  }
+  *iters = it;
+  *not_conv = h_count[0];
+  std::vector<double> rn(nitems), bn(nitems);
+  HPCHK(hipMemcpyAsync(rn.data(), c->rn, sizeof(double) * nitems, hipMemcpyDeviceToHost, c->stream));
+  HPCHK(hipMemcpyAsync(bn.data(), c->bn, sizeof(double) * nitems, hipMemcpyDeviceToHost, c->stream));
+  HPTRY(sync(c));
+  double m = 0.0;
+  for (int i = 0; i < nitems; ++i)
+    if (bn[i] > 0) m = std::max(m, rn[i] / bn[i]);
+  *max_rel = m;
+  return HP_OK;
+}
+
+hp_status upload_pairs(hp_ctx *c, int site, const double q[3], std::vector<KPair> &pairs) {
+  (void)site;
+  pairs.clear();
+  for (int k = 0; k < c->n_mesh; ++k) {
+    KPair P{};
+    P.ek = k;
+    P.ej = -1;
+    P.weight = c->ent[k].weight;
+    for (int j = 0; j < c->n_kpts && P.ej < 0; ++j) {
+      double d[3];
+      bool ok = true;
+      for (int a = 0; a < 3; ++a) {
+        d[a] = c->ent[k].k[a] + q[a] - c->ent[j].k[a];
+        if (std::fabs(d[a] - std::round(d[a])) > 1e-9) ok = false;
+      }
+      if (ok) {
+        P.ej = j;
+        for (int a = 0; a < 3; ++a) P.g0[a] = (int)std::lround(d[a]);
+      }
+    }
+    if (P.ej < 0)
+      return fail(HP_ERR_SHAPE, "no loaded entry holds k+q for mesh point %d, q = (%g, %g, %g)", k, q[0], q[1], q[2]);
+    pairs.push_back(P);
+  }
+  HPCHK(hipMemcpyAsync(c->d_kp, pairs.data(), sizeof(KPair) * pairs.size(), hipMemcpyHostToDevice, c->stream));
+  return HP_OK;
+}
+
+// Small complex Hermitian solve (Gaussian elimination with partial pivoting).
+bool csolve(int n, std::vector<std::complex<double>> A, std::vector<std::complex<double>> &b) {
+  for (int i = 0; i < n; ++i) {
+    int p = i;
+    for (int r = i + 1; r < n; ++r)
+      if (std::abs(A[r * n + i]) > std::abs(A[p * n + i])) p = r;
+    if (std::abs(A[p * n + i]) == 0.0) return false;
+    if (p != i) {
+      for (int cc = 0; cc < n; ++cc) std::swap(A[i * n + cc], A[p * n + cc]);
+      std::swap(b[i], b[p]);
+    }
+    for (int r = i + 1; r < n; ++r) {
+      const std::complex<double> f = A[r * n + i] / A[i * n + i];
+      for (int cc = i; cc < n; ++cc) A[r * n + cc] -= f * A[i * n + cc];
+      b[r] -= f * b[i];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    std::complex<double> s = b[i];
+    for (int cc = i + 1; cc < n; ++cc) s -= A[i * n + cc] * b[cc];
+    b[i] = s / A[i * n + i];
+  }
+  return true;
+}
+
+hp_status zdots(hp_ctx *c, int nvec, const double2 *const *vecs, const double2 *b, long n,
+                std::vector<std::complex<double>> &out) {
+  HPCHK(hipMemcpyAsync(c->ptrs, vecs, sizeof(double2 *) * nvec, hipMemcpyHostToDevice, c->stream));
+  HPCHK(launch_zdots(nvec, c->ptrs, b, n, c->dots_part, c->dots, c->stream));
+  std::vector<double2> h(nvec);
+  HPCHK(hipMemcpyAsync(h.data(), c->dots, sizeof(double2) * nvec, hipMemcpyDeviceToHost, c->stream));
+  HPTRY(sync(c));
+  out.resize(nvec);
+  for (int i = 0; i < nvec; ++i) out[i] = {h[i].x, h[i].y};
+  return HP_OK;
+}
+
+hp_status check_params(const hp_scf_params *p) {
+  if (!p) return fail(HP_ERR_ARG, "params is NULL");
+  if (p->struct_size != sizeof(hp_scf_params)) return fail(HP_ERR_ARG, "hp_scf_params.struct_size mismatch");
+  if (!(p->cg_tol > 0.0) || !(p->conv_thr_chi > 0.0) || !(p->conv_thr_v > 0.0))
+    return fail(HP_ERR_ARG, "thresholds must be positive");
+  if (p->niter_max < 1 || p->max_cg_iter < 1) return fail(HP_ERR_ARG, "iteration limits must be >= 1");
+  if (p->nmix < 1 || p->nmix > kNmixMax) return fail(HP_ERR_ARG, "nmix must be in 1..%d", kNmixMax);
+  if (!(p->alpha_mix > 0.0 && p->alpha_mix <= 1.0)) return fail(HP_ERR_ARG, "alpha_mix must be in (0, 1]");
+  if (p->precision != HP_FP64 && p->precision != HP_MIXED) return fail(HP_ERR_ARG, "unknown precision %d", p->precision);
+  return HP_OK;
+}
+
+}  // namespace
+
+// =============================================================== ABI
+
+extern "C" const char *hp_last_error(void) { return g_err.c_str(); }
+
+extern "C" void hp_destroy(hp_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void *p : c->allocs) (void)hipFree(p);
+  for (int i = 0; i < 16; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+extern "C" hp_status hp_hubbard_params(int32_t n, const double *chi0, const double *chi, double *uv_out) {
+  if (n < 1) return fail(HP_ERR_ARG, "n = %d", n);
+  if (!chi0 || !chi || !uv_out) return fail(HP_ERR_ARG, "NULL argument");
+  std::vector<double> inv0, inv1;
+  for (int which = 0; which < 2; ++which) {
+    const double *M = which == 0 ? chi0 : chi;
+    double amax = 0.0;
+    for (long i = 0; i < (long)n * n; ++i) {
+      if (!std::isfinite(M[i])) return fail(HP_ERR_NUMERIC, "non-finite entry in %s", which ? "chi" : "chi0");
+      amax = std::max(amax, std::fabs(M[i]));
+    }
+    if (amax == 0.0) return fail(HP_ERR_SINGULAR, "%s is zero", which ? "chi" : "chi0");
+    // Gauss-Jordan inversion with partial pivoting, FP64
+    std::vector<double> A(M, M + (long)n * n), I((long)n * n, 0.0);
+    for (int i = 0; i < n; ++i) I[(long)i * n + i] = 1.0;
+    for (int col = 0; col < n; ++col) {
+      int p = col;
+      for (int r = col + 1; r < n; ++r)
+        if (std::fabs(A[(long)r * n + col]) > std::fabs(A[(long)p * n + col])) p = r;
+      if (std::fabs(A[(long)p * n + col]) < 1e-14 * amax)
+        return fail(HP_ERR_SINGULAR, "%s is singular (pivot %g)", which ? "chi" : "chi0", A[(long)p * n + col]);
+      if (p != col)
+        for (int cc = 0; cc < n; ++cc) {
+          std::swap(A[(long)p * n + cc], A[(long)col * n + cc]);
+          std::swap(I[(long)p * n + cc], I[(long)col * n + cc]);
+        }
+      const double d = A[(long)col * n + col];
+      for (int cc = 0; cc < n; ++cc) {
+        A[(long)col * n + cc] /= d;
+        I[(long)col * n + cc] /= d;
+      }
+      for (int r = 0; r < n; ++r) {
+        if (r == col) continue;
+        const double f = A[(long)r * n + col];
+        if (f == 0.0) continue;
+        for (int cc = 0; cc < n; ++cc) {
+          A[(long)r * n + cc] -= f * A[(long)col * n + cc];
+          I[(long)r * n + cc] -= f * I[(long)col * n + cc];
+        }
+      }
+    }
+    (which == 0 ? inv0 : inv1) = I;
+  }
+  for (long i = 0; i < (long)n * n; ++i) uv_out[i] = inv0[i] - inv1[i];
+  return HP_OK;
+}
+
+extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **out) {
+  if (!out) return fail(HP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!gs) return fail(HP_ERR_ARG, "gs is NULL");
+  if (gs->struct_size != sizeof(hp_ground_state)) return fail(HP_ERR_ARG, "hp_ground_state.struct_size mismatch");
+  if (gs->spin_factor != 2) return fail(HP_ERR_ARG, "spin_factor must be 2 (closed shell)");
+  if (gs->xc != HP_XC_LDA_PZ81) return fail(HP_ERR_ARG, "unknown xc %d", gs->xc);
+  if (gs->reserved != 0) return fail(HP_ERR_ARG, "reserved must be 0");
+  if (!gs->v_loc || !gs->rho0 || !gs->d_kb || !gs->hub_tau || !gs->kpts) return fail(HP_ERR_ARG, "NULL array");
+  if (gs->n_occ < 1 || gs->n_beta < 0 || gs->n_hub < 1) return fail(HP_ERR_ARG, "bad n_occ/n_beta/n_hub");
+  if (gs->n_mesh < 1 || gs->n_kpts < gs->n_mesh) return fail(HP_ERR_ARG, "bad n_mesh/n_kpts");
+  std::vector<int> rad[3];
+  for (int d = 0; d < 3; ++d) {
+    if (gs->fft[d] < 2 || gs->fft[d] > 256 || !factor_235(gs->fft[d], rad[d]))
+      return fail(HP_ERR_SHAPE, "fft[%d] = %d is not a product of 2, 3, 5 in [2, 256]", d, gs->fft[d]);
+  }
+  for (int i = 0; i < gs->n_kpts; ++i) HPTRY(check_kpoint(gs->kpts[i], i, gs));
+  const double det = gs->cell[0][0] * (gs->cell[1][1] * gs->cell[2][2] - gs->cell[1][2] * gs->cell[2][1]) -
+                     gs->cell[0][1] * (gs->cell[1][0] * gs->cell[2][2] - gs->cell[1][2] * gs->cell[2][0]) +
+                     gs->cell[0][2] * (gs->cell[1][0] * gs->cell[2][1] - gs->cell[1][1] * gs->cell[2][0]);
+  if (!(std::fabs(det) > 1e-8)) return fail(HP_ERR_ARG, "degenerate cell");
+  // plane-wave layouts (host), before any GPU call
+  std::vector<Layout> lay(gs->n_kpts);
+  for (int i = 0; i < gs->n_kpts; ++i)
+    HPTRY(build_layout(gs->kpts[i], gs->fft[0], gs->fft[1], gs->fft[2], lay[i], i));
+  for (int i = 0; i < gs->n_kpts; ++i) {
+    const hp_kpoint &k = gs->kpts[i];
+    for (int v = 0; v < gs->n_occ; ++v)
+      if (!std::isfinite(k.eps[v])) return fail(HP_ERR_NUMERIC, "kpts[%d].eps[%d] is not finite", i, v);
+  }
+  const long nrr = (long)gs->fft[0] * gs->fft[1] * gs->fft[2];
+  for (long i = 0; i < nrr; ++i)
+    if (!std::isfinite(gs->v_loc[i]) || !std::isfinite(gs->rho0[i])) return fail(HP_ERR_NUMERIC, "non-finite v_loc/rho0");
+
+  std::unique_ptr<hp_ctx> c(new hp_ctx());
+  for (int i = 0; i < 16; ++i) c->ev[i] = nullptr;
+  c->n1 = gs->fft[0];
+  c->n2 = gs->fft[1];
+  c->n3 = gs->fft[2];
+  c->np = (long)c->n1 * c->n2;
+  c->nr = c->np * c->n3;
+  c->n_occ = gs->n_occ;
+  c->n_beta = gs->n_beta;
+  c->n_hub = gs->n_hub;
+  c->n_mesh = gs->n_mesh;
+  c->n_kpts = gs->n_kpts;
+  c->n_proj = c->n_beta + c->n_occ;
+  for (int i = 0; i < 9; ++i) c->cell[i] = gs->cell[i / 3][i % 3];
+  c->omega = std::fabs(det);
+  {
+    // b = 2 pi inv(A)^T: rows b_i with a_i . b_j = 2 pi delta_ij
+    const double *a = c->cell;
+    double inv[9];
+    inv[0] = (a[4] * a[8] - a[5] * a[7]) / det;
+    inv[1] = (a[2] * a[7] - a[1] * a[8]) / det;
+    inv[2] = (a[1] * a[5] - a[2] * a[4]) / det;
+    inv[3] = (a[5] * a[6] - a[3] * a[8]) / det;
+    inv[4] = (a[0] * a[8] - a[2] * a[6]) / det;
+    inv[5] = (a[2] * a[3] - a[0] * a[5]) / det;
+    inv[6] = (a[3] * a[7] - a[4] * a[6]) / det;
+    inv[7] = (a[1] * a[6] - a[0] * a[7]) / det;
+    inv[8] = (a[0] * a[4] - a[1] * a[3]) / det;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) c->bvec[i * 3 + j] = 2.0 * M_PI * inv[j * 3 + i];
+  }
+  // alpha = 2 (max - min) over the occupied energies of every entry (text after Eq. 18)
+  double emax = -1e300, emin = 1e300;
+  for (int i = 0; i < gs->n_kpts; ++i)
+    for (int v = 0; v < gs->n_occ; ++v) {
+      emax = std::max(emax, gs->kpts[i].eps[v]);
+      emin = std::min(emin, gs->kpts[i].eps[v]);
+    }
+  c->alpha = std::max(2.0 * (emax - emin), 0.01);
+
+  int npw_max = 0, ns_max = 0, chunk_max = 0;
+  for (int i = 0; i < gs->n_kpts; ++i) {
+    npw_max = std::max(npw_max, gs->kpts[i].npw);
+    const int ns = (int)lay[i].sx.size();
+    ns_max = std::max(ns_max, ns);
+    for (int s0 = 0; s0 < ns; s0 += 32) {
+      const int s1 = std::min(s0 + 32, ns);
+      chunk_max = std::max(chunk_max, lay[i].sstart[s1 - 1] + lay[i].slen[s1 - 1] - lay[i].sstart[s0]);
+    }
+  }
+  c->npw_max = npw_max;
+  c->ld = (npw_max + 63) / 64 * 64;
+  c->ns_max = ns_max;
+  c->ns_pad = (ns_max + 31) / 32 * 32;
+  c->max_chunk_pw = chunk_max;
+  c->t_stride = (long)c->n_proj * c->ld;
+  c->phi_stride = (long)5 * c->n_hub * c->ld;
+
+  // -------- device from here on
+  if (gs->stream) {
+    c->stream = (hipStream_t)gs->stream;
+  } else {
+    HPCHK(hipStreamCreate(&c->stream));
+    c->own_stream = true;
+  }
+  hipStream_t st = c->stream;
+  for (int i = 0; i < 16; ++i) HPCHK(hipEventCreate(&c->ev[i]));
+
+  // FFT axes: twiddles and permutations
+  const int N[3] = {c->n1, c->n2, c->n3};
+  std::vector<double2> tw_h;
+  int tw_off[3];
+  for (int d = 0; d < 3; ++d) {
+    tw_off[d] = (int)tw_h.size();
+    for (int j = 0; j < N[d]; ++j)
+      tw_h.push_back(make_double2(std::cos(2.0 * M_PI * j / N[d]), std::sin(2.0 * M_PI * j / N[d])));
+  }
+  HPTRY(c->alloc(&c->tw, tw_h.size()));
+  HPCHK(hipMemcpyAsync(c->tw, tw_h.data(), sizeof(double2) * tw_h.size(), hipMemcpyHostToDevice, st));
+  Axis ax[3];
+  for (int d = 0; d < 3; ++d) {
+    ax[d] = Axis{};
+    ax[d].n = N[d];
+    ax[d].nst = (int)rad[d].size();
+    int pr = 1;
+    for (int s = 0; s < ax[d].nst; ++s) {
+      ax[d].rad[s] = rad[d][s];
+      pr *= rad[d][s];
+      ax[d].span[s] = N[d] / pr;
+    }
+    ax[d].tw = c->tw + tw_off[d];
+  }
+  c->pl.ax = ax[0];
+  c->pl.ay = ax[1];
+  c->pl.n1 = c->n1;
+  c->pl.n2 = c->n2;
+  c->pl.n3 = c->n3;
+  c->az = ax[2];
+  if (c->np * (long)sizeof(double2) > 160 * 1024) return fail(HP_ERR_SHAPE, "xy plane does not fit in LDS");
+  c->px = dif_perm(c->n1, rad[0]);
+  c->py = dif_perm(c->n2, rad[1]);
+  HPTRY(c->alloc(&c->d_px, c->n1));
+  HPTRY(c->alloc(&c->d_py, c->n2));
+  HPCHK(hipMemcpyAsync(c->d_px, c->px.data(), sizeof(int) * c->n1, hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(c->d_py, c->py.data(), sizeof(int) * c->n2, hipMemcpyHostToDevice, st));
+
+  // local potential and f_xc in the permuted real-space layout
+  double *d_nat = nullptr;
+  HPTRY(c->alloc(&d_nat, c->nr));
+  HPTRY(c->alloc(&c->d_vp, c->nr));
+  HPTRY(c->alloc(&c->d_fxc, c->nr));
+  HPCHK(hipMemcpyAsync(d_nat, gs->v_loc, sizeof(double) * c->nr, hipMemcpyHostToDevice, st));
+  HPCHK(launch_permute_real(c->pl, c->d_px, c->d_py, d_nat, c->d_vp, st));
+  HPTRY(sync(c.get()));
+  HPCHK(hipMemcpyAsync(d_nat, gs->rho0, sizeof(double) * c->nr, hipMemcpyHostToDevice, st));
+  double *d_rhop = nullptr;
+  HPTRY(c->alloc(&d_rhop, c->nr));
+  HPCHK(launch_permute_real(c->pl, c->d_px, c->d_py, d_nat, d_rhop, st));
+  HPCHK(launch_fxc(d_rhop, c->d_fxc, c->nr, st));
+  HPTRY(c->alloc(&c->d_bvec, 9));
+  HPCHK(hipMemcpyAsync(c->d_bvec, c->bvec, sizeof(double) * 9, hipMemcpyHostToDevice, st));
+  double vmean = 0.0;
+  for (long i = 0; i < c->nr; ++i) vmean += gs->v_loc[i];
+  vmean /= (double)c->nr;
+
+  // per-entry tables in the stick order
+  std::vector<int> h_sx, h_sy, h_ss, h_sl, h_iz, h_xa, h_npw(c->n_kpts);
+  std::vector<EntryDev> h_ent(c->n_kpts);
+  std::vector<double> h_kin, h_diag((size_t)c->n_kpts * c->ld, 0.0);
+  std::vector<double2> h_T((size_t)c->n_kpts * c->t_stride), h_phi((size_t)c->n_kpts * c->phi_stride);
+  int pw_off = 0;
+  c->ent.resize(c->n_kpts);
+  for (int i = 0; i < c->n_kpts; ++i) {
+    const hp_kpoint &k = gs->kpts[i];
+    const Layout &L = lay[i];
+    EntryDev E{};
+    E.npw = k.npw;
+    E.ns = (int)L.sx.size();
+    E.nxa = (int)L.xa.size();
+    E.pw_off = pw_off;
+    E.st_off = (int)h_sx.size();
+    E.xa_off = (int)h_xa.size();
+    h_ent[i] = E;
+    h_npw[i] = k.npw;
+    h_sx.insert(h_sx.end(), L.sx.begin(), L.sx.end());
+    h_sy.insert(h_sy.end(), L.sy.begin(), L.sy.end());
+    h_ss.insert(h_ss.end(), L.sstart.begin(), L.sstart.end());
+    h_sl.insert(h_sl.end(), L.slen.begin(), L.slen.end());
+    h_iz.insert(h_iz.end(), L.iz.begin(), L.iz.end());
+    h_xa.insert(h_xa.end(), L.xa.begin(), L.xa.end());
+    pw_off += k.npw;
+    HostEntry &he = c->ent[i];
+    for (int a = 0; a < 3; ++a) he.k[a] = k.k_frac[a];
+    he.weight = k.weight;
+    he.npw = k.npw;
+    he.order = L.order;
+    double2 *T = h_T.data() + (size_t)i * c->t_stride;
+    double2 *F = h_phi.data() + (size_t)i * c->phi_stride;
+    double *dg = h_diag.data() + (size_t)i * c->ld;
+    for (int p = 0; p < k.npw; ++p) {
+      const int q = L.order[p];
+      double kv[3];
+      for (int a = 0; a < 3; ++a) {
+        kv[a] = 0.0;
+        for (int b = 0; b < 3; ++b) kv[a] += (k.miller[3 * q + b] + k.k_frac[b]) * c->bvec[b * 3 + a];
+      }
+      const double kin = 0.5 * (kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2]);
+      h_kin.push_back(kin);
+      double d = kin + vmean;
+      for (int b = 0; b < c->n_beta; ++b) {
+        const double2 val = make_double2(k.beta[2 * ((size_t)b * k.npw + q)], k.beta[2 * ((size_t)b * k.npw + q) + 1]);
+        T[(size_t)b * c->ld + p] = val;
+        d += gs->d_kb[b] * (val.x * val.x + val.y * val.y);
+      }
+      for (int v = 0; v < c->n_occ; ++v) {
+        const double2 val = make_double2(k.u[2 * ((size_t)v * k.npw + q)], k.u[2 * ((size_t)v * k.npw + q) + 1]);
+        T[(size_t)(c->n_beta + v) * c->ld + p] = val;
+        d += c->alpha * (val.x * val.x + val.y * val.y);
+      }
+      for (int m = 0; m < 5 * c->n_hub; ++m)
+        F[(size_t)m * c->ld + p] =
+            make_double2(k.phi[2 * ((size_t)m * k.npw + q)], k.phi[2 * ((size_t)m * k.npw + q) + 1]);
+      dg[p] = d;
+    }
+    for (int p = k.npw; p < c->ld; ++p) dg[p] = 1.0;
+  }
+  int *d_sx, *d_sy, *d_ss, *d_sl, *d_iz, *d_xa;
+  EntryDev *d_ent;
+  HPTRY(c->alloc(&d_sx, h_sx.size()));
+  HPTRY(c->alloc(&d_sy, h_sy.size()));
+  HPTRY(c->alloc(&d_ss, h_ss.size()));
+  HPTRY(c->alloc(&d_sl, h_sl.size()));
+  HPTRY(c->alloc(&d_iz, h_iz.size()));
+  HPTRY(c->alloc(&d_xa, h_xa.size()));
+  HPTRY(c->alloc(&d_ent, h_ent.size()));
+  HPTRY(c->alloc(&c->d_npw, h_npw.size()));
+  HPTRY(c->alloc(&c->d_kin, h_kin.size()));
+  HPTRY(c->alloc(&c->d_diag, h_diag.size()));
+  HPTRY(c->alloc(&c->d_T, h_T.size()));
+  HPTRY(c->alloc(&c->d_phi, h_phi.size()));
+  HPCHK(hipMemcpyAsync(d_sx, h_sx.data(), sizeof(int) * h_sx.size(), hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(d_sy, h_sy.data(), sizeof(int) * h_sy.size(), hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(d_ss, h_ss.data(), sizeof(int) * h_ss.size(), hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(d_sl, h_sl.data(), sizeof(int) * h_sl.size(), hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(d_iz, h_iz.data(), sizeof(int) * h_iz.size(), hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(d_xa, h_xa.data(), sizeof(int) * h_xa.size(), hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(d_ent, h_ent.data(), sizeof(EntryDev) * h_ent.size(), hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(c->d_npw, h_npw.data(), sizeof(int) * h_npw.size(), hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(c->d_kin, h_kin.data(), sizeof(double) * h_kin.size(), hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(c->d_diag, h_diag.data(), sizeof(double) * h_diag.size(), hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(c->d_T, h_T.data(), sizeof(double2) * h_T.size(), hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(c->d_phi, h_phi.data(), sizeof(double2) * h_phi.size(), hipMemcpyHostToDevice, st));
+  c->sk.sx = d_sx;
+  c->sk.sy = d_sy;
+  c->sk.sstart = d_ss;
+  c->sk.slen = d_sl;
+  c->sk.iz = d_iz;
+  c->sk.xa = d_xa;
+  c->sk.ent = d_ent;
+  // row scales of the stacked projector table: D_i for beta rows, alpha for u rows
+  std::vector<double> rs(c->n_proj);
+  for (int b = 0; b < c->n_beta; ++b) rs[b] = gs->d_kb[b];
+  for (int v = 0; v < c->n_occ; ++v) rs[c->n_beta + v] = c->alpha;
+  HPTRY(c->alloc(&c->d_rowscale, rs.size()));
+  HPCHK(hipMemcpyAsync(c->d_rowscale, rs.data(), sizeof(double) * rs.size(), hipMemcpyHostToDevice, st));
+  // energies of the mesh items
+  const int nb = c->n_occ;
+  const long nitems = (long)c->n_mesh * nb;
+  std::vector<double> eps_items(nitems);
+  for (int k = 0; k < c->n_mesh; ++k)
+    for (int v = 0; v < nb; ++v) eps_items[(size_t)k * nb + v] = gs->kpts[k].eps[v];
+  HPTRY(c->alloc(&c->d_eps, nitems));
+  HPCHK(hipMemcpyAsync(c->d_eps, eps_items.data(), sizeof(double) * nitems, hipMemcpyHostToDevice, st));
+  // pairs
+  HPTRY(c->alloc(&c->d_kp, c->n_mesh));
+  HPTRY(c->alloc(&c->d_kself, c->n_kpts));
+  std::vector<KPair> self(c->n_kpts);
+  for (int i = 0; i < c->n_kpts; ++i) {
+    self[i] = KPair{};
+    self[i].ek = self[i].ej = i;
+    self[i].weight = c->ent[i].weight;
+  }
+  HPCHK(hipMemcpyAsync(c->d_kself, self.data(), sizeof(KPair) * self.size(), hipMemcpyHostToDevice, st));
+
+  // work buffers
+  const size_t vec = (size_t)nitems * c->ld;
+  HPTRY(c->alloc(&c->B, vec));
+  HPTRY(c->alloc(&c->X, vec));
+  HPTRY(c->alloc(&c->R, vec));
+  HPTRY(c->alloc(&c->P, vec));
+  HPTRY(c->alloc(&c->AP, vec));
+  HPTRY(c->alloc(&c->S1, (size_t)nitems * c->n3 * c->ns_pad));
+  HPTRY(c->alloc(&c->S2, (size_t)nitems * c->n3 * c->ns_pad));
+  const int mrow = std::max(c->n_proj, 5 * c->n_hub);
+  HPTRY(c->alloc(&c->Cpart, (size_t)c->nsplit_cap * c->n_mesh * mrow * nb));
+  HPTRY(c->alloc(&c->C, (size_t)c->n_mesh * mrow * nb));
+  HPTRY(c->alloc(&c->Cphi, (size_t)c->n_mesh * 5 * c->n_hub * nb));
+  HPTRY(c->alloc(&c->rz, nitems));
+  HPTRY(c->alloc(&c->bn, nitems));
+  HPTRY(c->alloc(&c->rn, nitems));
+  HPTRY(c->alloc(&c->active, nitems));
+  HPTRY(c->alloc(&c->count, 2));
+  HPTRY(c->alloc(&c->part, (size_t)c->n_mesh * c->nr));
+  HPTRY(c->alloc(&c->drho, c->nr));
+  HPTRY(c->alloc(&c->dvin, c->nr));
+  HPTRY(c->alloc(&c->dvout, c->nr));
+  HPTRY(c->alloc(&c->f, c->nr));
+  HPTRY(c->alloc(&c->tmp, c->nr));
+  HPTRY(c->alloc(&c->fprev, c->nr));
+  HPTRY(c->alloc(&c->dvprev, c->nr));
+  HPTRY(c->alloc(&c->hdf, (size_t)kNmixMax * c->nr));
+  HPTRY(c->alloc(&c->hdv, (size_t)kNmixMax * c->nr));
+  HPTRY(c->alloc(&c->dots_part, (size_t)256 * (2 * kNmixMax + 2)));
+  HPTRY(c->alloc(&c->dots, 2 * kNmixMax + 2));
+  HPTRY(c->alloc(&c->coef, 2 * kNmixMax + 2));
+  HPTRY(c->alloc(&c->ptrs, 2 * kNmixMax + 2));
+  HPTRY(c->alloc(&c->dn, (size_t)25 * c->n_hub));
+  HPTRY(c->alloc(&c->d_q, 3));
+
+  // A_k[m][v] = <phi_{m,k}|u_vk> for every entry (Eq. 13's ground-state factor)
+  HPTRY(c->alloc(&c->d_A, (size_t)c->n_kpts * 5 * c->n_hub * nb));
+  for (int i = 0; i < c->n_kpts; ++i) {
+    HPTRY(proj(c.get(), c->d_kself + i, 0, 1, c->d_phi, c->phi_stride, 0, 5 * c->n_hub,
+               c->d_T + (size_t)i * c->t_stride + (size_t)c->n_beta * c->ld, nb, nullptr, 1.0,
+               c->d_A + (size_t)i * 5 * c->n_hub * nb));
+  }
+  // occupied states on the grid (permuted layout), every mesh k: psi[k*nb+v][z][plane]
+  HPTRY(c->alloc(&c->d_psi, (size_t)nitems * c->nr));
+  for (int k = 0; k < c->n_mesh; ++k)
+    HPCHK(hipMemcpyAsync(c->X + (size_t)k * nb * c->ld, c->d_T + (size_t)k * c->t_stride + (size_t)c->n_beta * c->ld,
+                         sizeof(double2) * (size_t)nb * c->ld, hipMemcpyDeviceToDevice, st));
+  HPCHK(launch_stick_inv(c->sk, c->d_kself, 0, nb, (int)nitems, c->X, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
+                         c->max_chunk_pw, c->ns_max, st));
+  HPCHK(launch_plane_to_real(c->pl, c->sk, c->d_kself, 0, nb, (int)nitems, c->S1, c->ns_pad, c->d_psi, st));
+  HPTRY(sync(c.get()));
+  *out = c.release();
+  return HP_OK;
+}
+
+namespace {
+
+hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p, double *dn0_out, double *dn_out,
+                  hp_scf_stats *st) {
+  Timer wall;
+  const int nb = c->n_occ, nk = c->n_mesh, nitems = nk * nb;
+  std::vector<KPair> pairs;
+  HPTRY(upload_pairs(c, site, q, pairs));
+  HPCHK(hipMemcpyAsync(c->d_q, q, sizeof(double) * 3, hipMemcpyHostToDevice, c->stream));
+  const long nr = c->nr;
+  HPCHK(hipMemsetAsync(c->dvin, 0, sizeof(double2) * nr, c->stream));
+  int nhist = 0, hist_head = 0;
+  std::vector<std::complex<double>> gram((size_t)kNmixMax * kNmixMax);
+  std::vector<double2> dn((size_t)25 * c->n_hub), dn0((size_t)25 * c->n_hub);
+  std::vector<std::complex<double>> chi_prev;
+  bool have_prev = false, converged = false;
+  int it = 0, cg_total = 0, not_conv = 0;
+  long happ = 0;
+  double dchi = 0.0, vres = 1.0, max_rel = 0.0;
+  double stage[8] = {0};
+  for (it = 1; it <= p->niter_max; ++it) {
+    HPCHK(hipEventRecord(c->ev[0], c->stream));
+    HPTRY(build_rhs(c, c->d_kp, nk, site, it > 1 ? c->dvin : nullptr, c->d_psi));
+    HPCHK(hipEventRecord(c->ev[1], c->stream));
+    int iters = 0, nc = 0;
+    double mr = 0.0;
+    HPTRY(cg_solve(c, c->d_kp, nk, c->d_eps, it > 1, p->cg_tol, p->max_cg_iter, &iters, &nc, &mr, &happ));
+    HPCHK(hipEventRecord(c->ev[2], c->stream));
+    cg_total += iters;
+    not_conv = nc;
+    max_rel = mr;
+    // response density (spin x time reversal) and occupations (Eq. 13)
+    HPCHK(launch_stick_inv(c->sk, c->d_kp, 1, nb, nitems, c->X, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
+                           c->max_chunk_pw, c->ns_max, c->stream));
+    HPCHK(launch_plane_drho(c->pl, c->sk, c->d_kp, nb, nk, c->S1, c->ns_pad, c->d_psi, c->part, c->stream));
+    HPCHK(launch_drho_reduce(c->d_kp, nk, c->part, nr, 1.0 / c->omega, c->drho, c->stream));
+    HPCHK(hipEventRecord(c->ev[3], c->stream));
+    HPCHK(launch_hxc(c->pl, c->az, c->d_bvec, q, c->drho, c->d_fxc, c->tmp, c->dvout, c->stream));
+    HPCHK(hipEventRecord(c->ev[4], c->stream));
+    HPTRY(proj(c, c->d_kp, 1, nk, c->d_phi, c->phi_stride, 0, 5 * c->n_hub, c->X, nb, nullptr, 1.0, c->Cphi));
+    HPCHK(launch_dn(c->d_kp, nk, c->n_hub, nb, c->d_A, c->Cphi, c->dn, c->stream));
+    HPCHK(hipMemcpyAsync(dn.data(), c->dn, sizeof(double2) * dn.size(), hipMemcpyDeviceToHost, c->stream));
+    HPCHK(hipEventRecord(c->ev[5], c->stream));
+    HPTRY(sync(c));
+    for (double2 z : dn)
+      if (!std::isfinite(z.x) || !std::isfinite(z.y)) return fail(HP_ERR_NUMERIC, "non-finite response occupation");
+    std::vector<std::complex<double>> chi(c->n_hub);
+    for (int s = 0; s < c->n_hub; ++s) {
+      std::complex<double> t = 0;
+      for (int m = 0; m < 5; ++m) t += std::complex<double>(dn[s * 25 + m * 6].x, dn[s * 25 + m * 6].y);
+      chi[s] = t;
+    }
+    if (it == 1) dn0 = dn;
+    // mixing residual f = dV_out - dV_in
+    HPCHK(launch_zsub(nr, c->dvout, c->dvin, c->f, c->stream));
+    std::vector<std::complex<double>> nrm;
+    {
+      const double2 *v2[2] = {c->f, c->dvout};
+      std::vector<std::complex<double>> a, b;
+      HPTRY(zdots(c, 1, v2, c->f, nr, a));
+      HPTRY(zdots(c, 1, v2 + 1, c->dvout, nr, b));
+      const double fn = std::sqrt(std::max(0.0, a[0].real())), vn = std::sqrt(std::max(0.0, b[0].real()));
+      vres = vn > 0 ? fn / vn : 0.0;
+      if (!std::isfinite(vres)) return fail(HP_ERR_NUMERIC, "non-finite response potential");
+    }
+    if (have_prev) {
+      dchi = 0.0;
+      for (int s = 0; s < c->n_hub; ++s) dchi = std::max(dchi, std::abs(chi[s] - chi_prev[s]));
+    }
+    float ms[5];
+    for (int s = 0; s < 5; ++s) (void)hipEventElapsedTime(&ms[s], c->ev[s], c->ev[s + 1]);
+    for (int s = 0; s < 5; ++s) stage[s] += ms[s] * 1e-3;
+    if (p->verbosity > 0)
+      fprintf(stderr, "[hp] site %d q=(%.3f,%.3f,%.3f) it %d: dchi %.3e vres %.3e cg %d chi0/chi %.10f\n", site, q[0],
+              q[1], q[2], it, have_prev ? dchi : NAN, vres, iters, chi[site].real());
+    if (have_prev && dchi < p->conv_thr_chi && vres < p->conv_thr_v) {
+      converged = true;
+      break;
+    }
+    if (vres == 0.0) {  // no Hxc response at all
+      converged = true;
+      break;
+    }
+    chi_prev = chi;
+    have_prev = true;
+    if (it == p->niter_max) break;
+    // modified Broyden (Anderson form) update of dV_in
+    Timer tm;
+    const int nmix = p->nmix;
+    if (it > 1) {
+      // new history pair from (f - f_prev, dv_in - dv_prev)
+      double2 *df = c->hdf + (size_t)hist_head * nr;
+      double2 *dvh = c->hdv + (size_t)hist_head * nr;
+      HPCHK(launch_zsub(nr, c->f, c->fprev, df, c->stream));
+      HPCHK(launch_zsub(nr, c->dvin, c->dvprev, dvh, c->stream));
+      std::vector<std::complex<double>> d1;
+      const double2 *v1[1] = {df};
+      HPTRY(zdots(c, 1, v1, df, nr, d1));
+      const double nd = std::sqrt(std::max(d1[0].real(), 1e-300));
+      HPCHK(launch_zscale_copy(nr, df, 1.0 / nd, df, c->stream));
+      HPCHK(launch_zscale_copy(nr, dvh, 1.0 / nd, dvh, c->stream));
+      const int slot = hist_head;
+      hist_head = (hist_head + 1) % nmix;
+      nhist = std::min(nhist + 1, nmix);
+      // Gram row of the new vector
+      std::vector<const double2 *> vs;
+      std::vector<int> slots;
+      for (int h = 0; h < nhist; ++h) {
+        const int sidx = ((hist_head - nhist + h) % nmix + nmix) % nmix;
+        slots.push_back(sidx);
+        vs.push_back(c->hdf + (size_t)sidx * nr);
+      }
+      std::vector<std::complex<double>> row;
+      HPTRY(zdots(c, nhist, vs.data(), df, nr, row));  // <df_h | df_new>
+      for (int h = 0; h < nhist; ++h) {
+        gram[(size_t)slots[h] * kNmixMax + slot] = row[h];
+        gram[(size_t)slot * kNmixMax + slots[h]] = std::conj(row[h]);
+      }
+    }
+    HPCHK(hipMemcpyAsync(c->fprev, c->f, sizeof(double2) * nr, hipMemcpyDeviceToDevice, c->stream));
+    HPCHK(hipMemcpyAsync(c->dvprev, c->dvin, sizeof(double2) * nr, hipMemcpyDeviceToDevice, c->stream));
+    const double am = p->alpha_mix;
+    std::vector<const double2 *> xs;
+    std::vector<double2> cf;
+    xs.push_back(c->f);
+    cf.push_back(make_double2(am, 0.0));
+    if (nhist > 0) {
+      std::vector<int> slots;
+      std::vector<const double2 *> vs;
+      for (int h = 0; h < nhist; ++h) {
+        const int sidx = ((hist_head - nhist + h) % nmix + nmix) % nmix;
+        slots.push_back(sidx);
+        vs.push_back(c->hdf + (size_t)sidx * nr);
+      }
+      std::vector<std::complex<double>> rhs;
+      HPTRY(zdots(c, nhist, vs.data(), c->f, nr, rhs));  // <df_h | f>
+      std::vector<std::complex<double>> G((size_t)nhist * nhist);
+      for (int i = 0; i < nhist; ++i)
+        for (int j = 0; j < nhist; ++j) G[(size_t)i * nhist + j] = gram[(size_t)slots[i] * kNmixMax + slots[j]];
+      if (!csolve(nhist, G, rhs)) return fail(HP_ERR_NUMERIC, "singular mixing history");
+      for (int h = 0; h < nhist; ++h) {
+        const std::complex<double> g = rhs[h];
+        xs.push_back(c->hdf + (size_t)slots[h] * nr);
+        cf.push_back(make_double2(-am * g.real(), -am * g.imag()));
+        xs.push_back(c->hdv + (size_t)slots[h] * nr);
+        cf.push_back(make_double2(-g.real(), -g.imag()));
+      }
+    }
+    HPCHK(hipMemcpyAsync(c->ptrs, xs.data(), sizeof(double2 *) * xs.size(), hipMemcpyHostToDevice, c->stream));
+    HPCHK(hipMemcpyAsync(c->coef, cf.data(), sizeof(double2) * cf.size(), hipMemcpyHostToDevice, c->stream));
+    HPCHK(launch_zaxpy_list(nr, c->dvin, (int)xs.size(), c->ptrs, c->coef, c->stream));
+    HPTRY(sync(c));
+    stage[4] += tm.s();
+  }
+  if (dn0_out)
+    for (size_t i = 0; i < dn0.size(); ++i) {
+      dn0_out[2 * i] = dn0[i].x;
+      dn0_out[2 * i + 1] = dn0[i].y;
+    }
+  if (dn_out)
+    for (size_t i = 0; i < dn.size(); ++i) {
+      dn_out[2 * i] = dn[i].x;
+      dn_out[2 * i + 1] = dn[i].y;
+    }
+  if (st) {
+    st->scf_iters = std::min(it, p->niter_max);
+    st->converged = converged ? 1 : 0;
+    st->cg_iters = cg_total;
+    st->h_applies_fp64 = happ;
+    st->h_applies_lowp = 0;
+    st->wall_s = wall.s();
+    st->chi_change = dchi;
+    st->v_residual = vres;
+    st->max_rel_resid = max_rel;
+    for (int s = 0; s < 8; ++s) st->stage_s[s] = stage[s];
+  }
+  return (converged && not_conv == 0) ? HP_OK : HP_WARN_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" hp_status hp_sternheimer_scf(hp_ctx *c, int32_t pert_site, const double q_frac[3], const hp_scf_params *p,
+                                        double *dn0_out, double *dn_out, hp_scf_stats *st) {
+  if (!c) return fail(HP_ERR_ARG, "context is NULL");
+  if (!q_frac || !dn0_out || !dn_out) return fail(HP_ERR_ARG, "NULL argument");
+  HPTRY(check_params(p));
+  if (pert_site < 0 || pert_site >= c->n_hub) return fail(HP_ERR_ARG, "pert_site %d out of range", pert_site);
+  if (st && st->struct_size != sizeof(hp_scf_stats)) return fail(HP_ERR_ARG, "hp_scf_stats.struct_size mismatch");
+  if (p->precision != HP_FP64) return fail(HP_ERR_ARG, "precision %d not available", p->precision);
+  return run_scf(c, pert_site, q_frac, p, dn0_out, dn_out, st);
+}
+
+extern "C" hp_status hp_response_matrix(hp_ctx *c, const int32_t nq[3], const hp_scf_params *p, double *chi0_out,
+                                        double *chi_out, double *max_imag_out, hp_scf_stats *st) {
+  if (!c) return fail(HP_ERR_ARG, "context is NULL");
+  if (!nq || !chi0_out || !chi_out) return fail(HP_ERR_ARG, "NULL argument");
+  HPTRY(check_params(p));
+  if (nq[0] < 1 || nq[1] < 1 || nq[2] < 1) return fail(HP_ERR_ARG, "nq must be >= 1");
+  if (st && st->struct_size != sizeof(hp_scf_stats)) return fail(HP_ERR_ARG, "hp_scf_stats.struct_size mismatch");
+  if (p->precision != HP_FP64) return fail(HP_ERR_ARG, "precision %d not available", p->precision);
+  const int nh = c->n_hub;
+  const int Nq = nq[0] * nq[1] * nq[2];
+  std::vector<std::array<double, 3>> qs;
+  for (int a = 0; a < nq[0]; ++a)
+    for (int b = 0; b < nq[1]; ++b)
+      for (int d = 0; d < nq[2]; ++d) qs.push_back({(double)a / nq[0], (double)b / nq[1], (double)d / nq[2]});
+  // chi(q)[s][s'] for chi0 and chi
+  std::vector<std::complex<double>> c0q((size_t)Nq * nh * nh), c1q((size_t)Nq * nh * nh);
+  hp_status worst = HP_OK;
+  hp_scf_stats acc{};
+  acc.struct_size = sizeof(hp_scf_stats);
+  std::vector<double> dn0(50 * nh), dn1(50 * nh);
+  for (int iq = 0; iq < Nq; ++iq) {
+    for (int sp = 0; sp < nh; ++sp) {
+      hp_scf_stats one{};
+      one.struct_size = sizeof(hp_scf_stats);
+      hp_status s = run_scf(c, sp, qs[iq].data(), p, dn0.data(), dn1.data(), &one);
+      if (s < 0) return s;
+      if (s > worst) worst = s;
+      acc.scf_iters += one.scf_iters;
+      acc.cg_iters += one.cg_iters;
+      acc.h_applies_fp64 += one.h_applies_fp64;
+      acc.wall_s += one.wall_s;
+      acc.chi_change = std::max(acc.chi_change, one.chi_change);
+      acc.v_residual = std::max(acc.v_residual, one.v_residual);
+      acc.max_rel_resid = std::max(acc.max_rel_resid, one.max_rel_resid);
+      for (int t = 0; t < 8; ++t) acc.stage_s[t] += one.stage_s[t];
+      for (int s2 = 0; s2 < nh; ++s2) {
+        std::complex<double> t0 = 0, t1 = 0;
+        for (int m = 0; m < 5; ++m) {
+          const int o = s2 * 25 + m * 6;
+          t0 += std::complex<double>(dn0[2 * o], dn0[2 * o + 1]);
+          t1 += std::complex<double>(dn1[2 * o], dn1[2 * o + 1]);
+        }
+        c0q[((size_t)iq * nh + s2) * nh + sp] = t0;
+        c1q[((size_t)iq * nh + s2) * nh + sp] = t1;
+      }
+    }
+  }
+  // Eq. 12: chi_{(s,l),(s',l')} = (1/Nq) sum_q e^{i q.(R_l - R_l')} chi(q)_{s s'}
+  const int n = nh * Nq;
+  double mim = 0.0;
+  for (int l = 0; l < Nq; ++l)
+    for (int lp = 0; lp < Nq; ++lp)
+      for (int s = 0; s < nh; ++s)
+        for (int sp = 0; sp < nh; ++sp) {
+          std::complex<double> a0 = 0, a1 = 0;
+          for (int iq = 0; iq < Nq; ++iq) {
+            const double dl[3] = {qs[l][0] * nq[0] - qs[lp][0] * nq[0], qs[l][1] * nq[1] - qs[lp][1] * nq[1],
+                                  qs[l][2] * nq[2] - qs[lp][2] * nq[2]};
+            const double ph = 2.0 * M_PI * (qs[iq][0] * dl[0] + qs[iq][1] * dl[1] + qs[iq][2] * dl[2]);
+            const std::complex<double> e(std::cos(ph), std::sin(ph));
+            a0 += e * c0q[((size_t)iq * nh + s) * nh + sp];
+            a1 += e * c1q[((size_t)iq * nh + s) * nh + sp];
+          }
+          a0 /= (double)Nq;
+          a1 /= (double)Nq;
+          const int row = l * nh + s, col = lp * nh + sp;
+          chi0_out[(size_t)row * n + col] = a0.real();
+          chi_out[(size_t)row * n + col] = a1.real();
+          mim = std::max(mim, std::max(std::fabs(a0.imag()), std::fabs(a1.imag())));
+        }
+  if (max_imag_out) *max_imag_out = mim;
+  if (st) *st = acc;
+  return worst;
+}
+
+extern "C" hp_status hp_apply_h(hp_ctx *c, int32_t entry, int32_t n, const double *x, double *y) {
+  if (!c) return fail(HP_ERR_ARG, "context is NULL");
+  if (!x || !y) return fail(HP_ERR_ARG, "NULL argument");
+  if (entry < 0 || entry >= c->n_kpts) return fail(HP_ERR_ARG, "entry %d out of range", entry);
+  if (n < 1) return fail(HP_ERR_ARG, "n = %d out of range", n);
+  const HostEntry &E = c->ent[entry];
+  const int cap = c->n_mesh * c->n_occ;  // vectors per batch (work-buffer capacity)
+  std::vector<double2> h((size_t)cap * c->ld);
+  for (int v0 = 0; v0 < n; v0 += cap) {
+    const int nv = std::min(cap, n - v0);
+    std::fill(h.begin(), h.end(), make_double2(0.0, 0.0));
+    for (int v = 0; v < nv; ++v)
+      for (int p = 0; p < E.npw; ++p) {
+        const size_t q = (size_t)(v0 + v) * E.npw + E.order[p];
+        h[(size_t)v * c->ld + p] = make_double2(x[2 * q], x[2 * q + 1]);
+      }
+    HPCHK(hipMemcpyAsync(c->P, h.data(), sizeof(double2) * (size_t)nv * c->ld, hipMemcpyHostToDevice, c->stream));
+    HPTRY(apply_op(c, c->d_kself + entry, 0, 1, nv, c->P, c->AP, nullptr, c->n_beta));
+    HPCHK(hipMemcpyAsync(h.data(), c->AP, sizeof(double2) * (size_t)nv * c->ld, hipMemcpyDeviceToHost, c->stream));
+    HPTRY(sync(c));
+    for (int v = 0; v < nv; ++v)
+      for (int p = 0; p < E.npw; ++p) {
+        const size_t q = (size_t)(v0 + v) * E.npw + E.order[p];
+        y[2 * q] = h[(size_t)v * c->ld + p].x;
+        y[2 * q + 1] = h[(size_t)v * c->ld + p].y;
+      }
+  }
+  return HP_OK;
+}
+
+extern "C" hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const double q_frac[3], int32_t mesh_k,
+                                          const double *dv, const hp_scf_params *p, double *du_out) {
+  if (!c) return fail(HP_ERR_ARG, "context is NULL");
+  if (!q_frac || !du_out) return fail(HP_ERR_ARG, "NULL argument");
+  HPTRY(check_params(p));
+  if (pert_site < 0 || pert_site >= c->n_hub) return fail(HP_ERR_ARG, "pert_site out of range");
+  if (mesh_k < 0 || mesh_k >= c->n_mesh) return fail(HP_ERR_ARG, "mesh_k out of range");
+  if (p->precision != HP_FP64) return fail(HP_ERR_ARG, "precision %d not available", p->precision);
+  std::vector<KPair> pairs;
+  HPTRY(upload_pairs(c, pert_site, q_frac, pairs));
+  const KPair P = pairs[mesh_k];
+  HPCHK(hipMemcpyAsync(c->d_kp, &P, sizeof(KPair), hipMemcpyHostToDevice, c->stream));
+  const int nb = c->n_occ;
+  const double2 *psi = c->d_psi + (size_t)mesh_k * nb * c->nr;
+  const double *eps = c->d_eps + (size_t)mesh_k * nb;
+  if (dv) {
+    HPCHK(hipMemcpyAsync(c->tmp, dv, sizeof(double2) * c->nr, hipMemcpyHostToDevice, c->stream));
+    HPCHK(launch_permute_complex(c->pl, c->d_px, c->d_py, c->tmp, c->dvin, 0, c->stream));
+  }
+  // A for this k: build_rhs indexes d_A by pair index; use a shifted view
+  hp_status s = HP_OK;
+  {
+    // temporarily point the perturbation factor at entry mesh_k
+    double2 *saveA = c->d_A;
+    c->d_A = c->d_A + (size_t)mesh_k * 5 * c->n_hub * nb;
+    s = build_rhs(c, c->d_kp, 1, pert_site, dv ? c->dvin : nullptr, psi);
+    c->d_A = saveA;
+    if (s < 0) return s;
+  }
+  int iters = 0, nc = 0;
+  double mr = 0.0;
+  long happ = 0;
+  HPTRY(cg_solve(c, c->d_kp, 1, eps, 0, p->cg_tol, p->max_cg_iter, &iters, &nc, &mr, &happ));
+  const HostEntry &E = c->ent[P.ej];
+  std::vector<double2> h((size_t)nb * c->ld);
+  HPCHK(hipMemcpyAsync(h.data(), c->X, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  HPTRY(sync(c));
+  for (int v = 0; v < nb; ++v)
+    for (int p2 = 0; p2 < E.npw; ++p2) {
+      const int q = E.order[p2];
+      du_out[2 * ((size_t)v * E.npw + q)] = h[(size_t)v * c->ld + p2].x;
+      du_out[2 * ((size_t)v * E.npw + q) + 1] = h[(size_t)v * c->ld + p2].y;
+    }
+  return nc == 0 ? HP_OK : HP_WARN_NOT_CONVERGED;
+}

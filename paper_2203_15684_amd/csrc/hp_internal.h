@@ -1,0 +1,136 @@
+// Internal declarations of the HIP Hubbard-response library: device data
+// layout, kernel launchers and the context.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hp.h"
+
+namespace hp {
+
+// ---------------------------------------------------------------- FFT axes
+// In-place mixed-radix FFT along one grid axis: radices in decimation-in-
+// frequency order, span[s] = N / (rad[0] * ... * rad[s]).  tw[k] = e^{+2 pi i k/N}.
+struct Axis {
+  int n;
+  int nst;
+  int rad[8];
+  int span[8];
+  const double2 *tw;
+};
+
+// Plane geometry shared by every plane kernel: the xy plane (N1 x N2, y fastest)
+// of one z index.  Real-space arrays live as [N3][N1*N2] with x and y stored in
+// the digit-reversed order produced by the decimation-in-frequency transform.
+struct Plane {
+  Axis ax;   // x = first grid index, length N1, stride N2
+  Axis ay;   // y = second grid index, length N2, stride 1
+  int n1, n2, n3;
+};
+
+// Per k-entry geometry (device arrays, flat with offsets).
+struct EntryDev {
+  int npw;      // plane waves
+  int ns;       // z-sticks (distinct (m1, m2) columns)
+  int nxa;      // distinct x columns among the sticks
+  int pw_off;   // offset into per-plane-wave arrays
+  int st_off;   // offset into per-stick arrays
+  int xa_off;   // offset into the active-x array
+};
+
+// One mesh k of a (site, q) problem: its own entry, the entry holding k+q and the
+// reciprocal vector g0 with k + q = k_j + g0 (the k+q basis is entry j shifted by -g0).
+struct KPair {
+  int ek;
+  int ej;
+  int g0[3];
+  double weight;
+};
+
+// Stick tables of all entries (device).
+struct Sticks {
+  const int *sx;      // [st] grid x of the stick (m1 mod N1, unshifted)
+  const int *sy;      // [st] grid y
+  const int *sstart;  // [st] first plane wave of the stick (internal order)
+  const int *slen;    // [st] plane waves in the stick
+  const int *iz;      // [pw] m3 mod N3
+  const int *xa;      // [xa] active x columns
+  const EntryDev *ent;
+};
+
+// ----------------------------------------------------------------- launchers
+// Every launcher enqueues on `st` and returns hipGetLastError().
+// Items are (mesh k, band) pairs, item = k * nb + v; the basis of an item is entry
+// kp[k].ej shifted by -g0 (use_kq = 1) or entry kp[k].ek (use_kq = 0).
+
+// S[item][z][s] = sum_{G in stick s} X[item][G] e^{+i G_z z}
+hipError_t launch_stick_inv(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const double2 *X,
+                            int ld, double2 *S, int ns_pad, int n3, const double2 *tw3, int max_chunk_pw, int ns_max,
+                            hipStream_t st);
+// Y[item][G] = scale * sum_z S[item][z][s(G)] e^{-i G_z z}   (S may be null: 0)
+//   mode 0 adds (kin[G] - eps[k*eps_stride+v]) X[item][G] (eps may be null: 0)
+hipError_t launch_stick_fwd(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const double2 *S,
+                            int ns_pad, int n3, const double2 *tw3, double scale, double2 *Y, int ld, int mode,
+                            const double *kin, const double *eps, const double2 *X, int eps_stride, int max_chunk_pw,
+                            int ns_max, hipStream_t st);
+// Plane round trip for the local potential: sticks -> r (DIF) -> * vp -> sticks (reverse).
+hipError_t launch_plane_vloc(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
+                             const double2 *Sin, double2 *Sout, int ns_pad, const double *vp, hipStream_t st);
+// Sticks -> real-space plane (permuted layout), R[item][z][plane].
+hipError_t launch_plane_to_real(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
+                                const double2 *Sin, int ns_pad, double2 *R, hipStream_t st);
+// psi[item] (permuted) * dv (permuted) -> sticks of the k+q basis.
+hipError_t launch_plane_mul_fwd(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nitems,
+                                const double2 *psi, const double2 *dv, double2 *Sout, int ns_pad, hipStream_t st);
+// part[k][z][plane] = sum_v conj(psi[k*nb+v]) * (sticks of du -> r), k+q basis.
+hipError_t launch_plane_drho(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nk, const double2 *Sdu,
+                             int ns_pad, const double2 *psi, double2 *part, hipStream_t st);
+// drho = sum_k (4 w_k / Omega) part[k] in fixed order.
+hipError_t launch_drho_reduce(const KPair *kp, int nk, const double2 *part, long nr, double inv_omega, double2 *drho,
+                              hipStream_t st);
+// dvout = IFFT(4 pi FFT(drho) / |q+G|^2) + fxc * drho, permuted layout.
+hipError_t launch_hxc(const Plane &pl, const Axis &az, const double *bvec, const double *q, const double2 *drho,
+                      const double *fxc, double2 *tmp, double2 *dvout, hipStream_t st);
+// natural [N1][N2][N3] <-> permuted [N3][xp][yp]
+hipError_t launch_permute_real(const Plane &pl, const int *px, const int *py, const double *in, double *out,
+                               hipStream_t st);
+hipError_t launch_permute_complex(const Plane &pl, const int *px, const int *py, const double2 *in, double2 *out,
+                                  int inverse, hipStream_t st);
+// PZ81 LDA kernel f_xc(rho) (Ha bohr^3), zero where rho < 1e-10.
+hipError_t launch_fxc(const double *rho, double *fxc, long n, hipStream_t st);
+
+// proj:   Cpart -> C[k][m][v] = row_scale[m] * gscale * sum_G conj(T_e[m0+m][G]) X[k*nb+v][G]
+hipError_t launch_zproj(const KPair *kp, int use_kq, int nk, const double2 *T, long t_stride, int m0, int M,
+                        const double2 *X, int ld, int nb, const int *npw_of, double2 *Cpart, int nsplit,
+                        hipStream_t st);
+hipError_t launch_zproj_reduce(int nk, int M, int nb, int nsplit, const double2 *Cpart, const double *row_scale,
+                               double gscale, double2 *C, hipStream_t st);
+// expand: Y[k*nb+v][G] += cscale * sum_m T_e[m0+m][G] C[k*c_kstride + m*nb + v]
+hipError_t launch_zexpand(const KPair *kp, int use_kq, int nk, const double2 *T, long t_stride, int m0, int M,
+                          const double2 *C, long c_kstride, double cscale, double2 *Y, int ld, int nb,
+                          const int *npw_of, int npw_max, hipStream_t st);
+// preconditioned CG (one workgroup per item)
+hipError_t launch_cg_init(const KPair *kp, int nb, int nitems, const double2 *B, double2 *Xv, double2 *R, double2 *P,
+                          const double2 *AX, int have_x0, const double *diag, const double *eps, int ld,
+                          const int *npw_of, long diag_stride, double *rz, double *bn, double *rn, int *active,
+                          double tol, hipStream_t st);
+hipError_t launch_cg_step(const KPair *kp, int nb, int nitems, double2 *Xv, double2 *R, double2 *P, const double2 *AP,
+                          const double *diag, const double *eps, int ld, const int *npw_of, long diag_stride,
+                          double *rz, const double *bn, double *rn, int *active, double tol, int *count,
+                          hipStream_t st);
+// dn[s][m1][m2] = sum_k 2 w_k sum_v (B[k][5s+m1][v] conj(A[ek][5s+m2][v]) + (m1 <-> m2))
+hipError_t launch_dn(const KPair *kp, int nk, int nh, int nb, const double2 *A, const double2 *B, double2 *dn,
+                     hipStream_t st);
+// mixing helpers
+hipError_t launch_zdots(int nvec, const double2 *const *a, const double2 *b, long n, double2 *partial, double2 *out,
+                        hipStream_t st);
+hipError_t launch_zaxpy_list(long n, double2 *y, int nvec, const double2 *const *x, const double2 *coef,
+                             hipStream_t st);
+hipError_t launch_zsub(long n, const double2 *a, const double2 *b, double2 *out, hipStream_t st);
+hipError_t launch_zscale_copy(long n, const double2 *a, double s, double2 *out, hipStream_t st);
+
+}  // namespace hp

@@ -1,0 +1,264 @@
+"""Python binding of the C ABI in include/hp.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls.  All arithmetic
+runs in the HIP library libhp.so; this module only converts numpy arrays to the
+C structs and pointers and raises HpError on error statuses.  Importing it
+without a built library raises immediately: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhp.so")
+
+HP_OK = 0
+HP_WARN_NOT_CONVERGED = 1
+HP_ERR_ARG, HP_ERR_SHAPE, HP_ERR_HIP, HP_ERR_OOM, HP_ERR_STATE, HP_ERR_SINGULAR, HP_ERR_NUMERIC = -1, -2, -3, -4, -5, -6, -7
+HP_FP64, HP_MIXED = 0, 1
+HP_XC_LDA_PZ81 = 1
+
+
+class HpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hp status {status}: {msg}")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2203_15684_amd/build.py (hipcc, gfx950)")
+_lib = C.CDLL(LIB_PATH)
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class HpKpoint(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("k_frac", C.c_double * 3), ("weight", C.c_double),
+                ("npw", C.c_int32), ("miller", _ip), ("eps", _dp), ("u", _dp), ("beta", _dp), ("phi", _dp)]
+
+
+class HpGroundState(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("cell", (C.c_double * 3) * 3), ("fft", C.c_int32 * 3),
+                ("v_loc", _dp), ("rho0", _dp), ("n_occ", C.c_int32), ("n_beta", C.c_int32), ("n_hub", C.c_int32),
+                ("d_kb", _dp), ("hub_tau", _dp), ("spin_factor", C.c_int32), ("n_mesh", C.c_int32),
+                ("n_kpts", C.c_int32), ("kpts", C.POINTER(HpKpoint)), ("xc", C.c_int32), ("reserved", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class HpScfParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("conv_thr_chi", C.c_double), ("conv_thr_v", C.c_double),
+                ("cg_tol", C.c_double), ("niter_max", C.c_int32), ("alpha_mix", C.c_double), ("nmix", C.c_int32),
+                ("max_cg_iter", C.c_int32), ("precision", C.c_int32), ("verbosity", C.c_int32)]
+
+
+class HpScfStats(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("scf_iters", C.c_int32), ("converged", C.c_int32),
+                ("cg_iters", C.c_int32), ("h_applies_fp64", C.c_int64), ("h_applies_lowp", C.c_int64),
+                ("wall_s", C.c_double), ("chi_change", C.c_double), ("v_residual", C.c_double),
+                ("max_rel_resid", C.c_double), ("stage_s", C.c_double * 8)]
+
+    def as_dict(self):
+        return {f: (list(getattr(self, f)) if f == "stage_s" else getattr(self, f)) for f, _ in self._fields_
+                if f != "struct_size"}
+
+
+_lib.hp_ground_state_load.argtypes = [C.POINTER(HpGroundState), C.POINTER(C.c_void_p)]
+_lib.hp_ground_state_load.restype = C.c_int32
+_lib.hp_sternheimer_scf.argtypes = [C.c_void_p, C.c_int32, _dp, C.POINTER(HpScfParams), _dp, _dp,
+                                    C.POINTER(HpScfStats)]
+_lib.hp_sternheimer_scf.restype = C.c_int32
+_lib.hp_response_matrix.argtypes = [C.c_void_p, _ip, C.POINTER(HpScfParams), _dp, _dp, _dp, C.POINTER(HpScfStats)]
+_lib.hp_response_matrix.restype = C.c_int32
+_lib.hp_hubbard_params.argtypes = [C.c_int32, _dp, _dp, _dp]
+_lib.hp_hubbard_params.restype = C.c_int32
+_lib.hp_destroy.argtypes = [C.c_void_p]
+_lib.hp_destroy.restype = None
+_lib.hp_last_error.argtypes = []
+_lib.hp_last_error.restype = C.c_char_p
+_lib.hp_apply_h.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp]
+_lib.hp_apply_h.restype = C.c_int32
+_lib.hp_solve_first_order.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_int32, _dp, C.POINTER(HpScfParams), _dp]
+_lib.hp_solve_first_order.restype = C.c_int32
+
+EXPORTED = ["hp_ground_state_load", "hp_sternheimer_scf", "hp_response_matrix", "hp_hubbard_params",
+            "hp_destroy", "hp_last_error", "hp_apply_h", "hp_solve_first_order"]
+
+
+def hp_last_error() -> str:
+    return _lib.hp_last_error().decode()
+
+
+def _check(status: int, allow_warn: bool = True) -> int:
+    if status < 0 or (status > 0 and not allow_warn):
+        raise HpError(status, hp_last_error())
+    return status
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _c128_as_f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.complex128).view(np.float64)
+
+
+def _ptr(a: np.ndarray, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+@dataclass
+class ScfParams:
+    """Mirror of hp_scf_params (the paper's conv_thr_chi, niter_max, alpha_mix, nmix)."""
+    conv_thr_chi: float = 1e-5 * 27.211386245988  # the paper's default 1e-5 eV^-1, in Ha^-1
+    conv_thr_v: float = 1e-8
+    cg_tol: float = 1e-10
+    niter_max: int = 100
+    alpha_mix: float = 0.3
+    nmix: int = 4
+    max_cg_iter: int = 1000
+    precision: int = HP_FP64
+    verbosity: int = 0
+
+    def c(self) -> HpScfParams:
+        return HpScfParams(C.sizeof(HpScfParams), self.conv_thr_chi, self.conv_thr_v, self.cg_tol, self.niter_max,
+                           self.alpha_mix, self.nmix, self.max_cg_iter, self.precision, self.verbosity)
+
+
+class Context:
+    """Owns an hp_ctx; hp_destroy runs on close() or garbage collection."""
+
+    def __init__(self, handle: int, gs):
+        self.handle = C.c_void_p(handle)
+        self.n_occ = int(gs.n_occ)
+        self.n_hub = int(gs.n_hub)
+        self.npw = [int(e.miller.shape[0]) for e in gs.kpts]
+        self.fft = tuple(int(x) for x in gs.fft)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            _lib.hp_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hp_ground_state_load(gs, stream: Optional[int] = None) -> Context:
+    """gs: an object with cell, fft, vloc, rho0, n_occ, d_kb, hub_tau, n_hub, n_mesh, kpts
+    (each k-entry with k_frac, weight, miller, eps, u, beta, phi)."""
+    keep = []
+    kp = (HpKpoint * len(gs.kpts))()
+    for i, e in enumerate(gs.kpts):
+        mil = np.ascontiguousarray(e.miller, dtype=np.int32)
+        eps = _f64(e.eps)
+        u = _c128_as_f64(e.u)
+        beta = _c128_as_f64(e.beta)
+        phi = _c128_as_f64(e.phi)
+        keep += [mil, eps, u, beta, phi]
+        kp[i] = HpKpoint(C.sizeof(HpKpoint), (C.c_double * 3)(*[float(x) for x in e.k_frac]), float(e.weight),
+                         int(mil.shape[0]), _ptr(mil, _ip), _ptr(eps), _ptr(u), _ptr(beta), _ptr(phi))
+    vloc = _f64(gs.vloc)
+    rho0 = _f64(gs.rho0)
+    dkb = _f64(gs.d_kb)
+    htau = _f64(gs.hub_tau)
+    keep += [vloc, rho0, dkb, htau]
+    cell = ((C.c_double * 3) * 3)(*[(C.c_double * 3)(*[float(x) for x in row]) for row in np.asarray(gs.cell)])
+    g = HpGroundState()
+    g.struct_size = C.sizeof(HpGroundState)
+    g.cell = cell
+    g.fft = (C.c_int32 * 3)(*[int(x) for x in gs.fft])
+    g.v_loc = _ptr(vloc)
+    g.rho0 = _ptr(rho0)
+    g.n_occ = int(gs.n_occ)
+    g.n_beta = int(dkb.shape[0])
+    g.n_hub = int(gs.n_hub)
+    g.d_kb = _ptr(dkb)
+    g.hub_tau = _ptr(htau)
+    g.spin_factor = int(getattr(gs, "spin_factor", 2))
+    g.n_mesh = int(gs.n_mesh)
+    g.n_kpts = len(gs.kpts)
+    g.kpts = kp
+    g.xc = HP_XC_LDA_PZ81
+    g.reserved = 0
+    g.stream = C.c_void_p(stream) if stream else None
+    h = C.c_void_p()
+    _check(_lib.hp_ground_state_load(C.byref(g), C.byref(h)), allow_warn=False)
+    del keep
+    return Context(h.value, gs)
+
+
+def hp_sternheimer_scf(ctx: Context, pert_site: int, q_frac: Sequence[float], params: ScfParams):
+    """Returns (dn0, dn, stats, status); dn0/dn are complex (n_hub, 5, 5)."""
+    q = _f64(q_frac)
+    dn0 = np.zeros(ctx.n_hub * 50)
+    dn = np.zeros(ctx.n_hub * 50)
+    st = HpScfStats()
+    st.struct_size = C.sizeof(HpScfStats)
+    p = params.c()
+    s = _check(_lib.hp_sternheimer_scf(ctx.handle, int(pert_site), _ptr(q), C.byref(p), _ptr(dn0), _ptr(dn),
+                                       C.byref(st)))
+    return (dn0.view(np.complex128).reshape(ctx.n_hub, 5, 5), dn.view(np.complex128).reshape(ctx.n_hub, 5, 5),
+            st.as_dict(), s)
+
+
+def hp_response_matrix(ctx: Context, nq: Sequence[int], params: ScfParams):
+    """Returns (chi0, chi, max_imag, stats, status), chi0/chi real (n, n) with n = n_hub * prod(nq)."""
+    nqa = np.ascontiguousarray(nq, dtype=np.int32)
+    n = ctx.n_hub * int(np.prod(nqa))
+    chi0 = np.zeros((n, n))
+    chi = np.zeros((n, n))
+    mim = np.zeros(1)
+    st = HpScfStats()
+    st.struct_size = C.sizeof(HpScfStats)
+    p = params.c()
+    s = _check(_lib.hp_response_matrix(ctx.handle, _ptr(nqa, _ip), C.byref(p), _ptr(chi0), _ptr(chi), _ptr(mim),
+                                       C.byref(st)))
+    return chi0, chi, float(mim[0]), st.as_dict(), s
+
+
+def hp_hubbard_params(chi0: np.ndarray, chi: np.ndarray) -> np.ndarray:
+    a = _f64(chi0)
+    b = _f64(chi)
+    n = a.shape[0]
+    if a.shape != (n, n) or b.shape != (n, n):
+        raise ValueError("chi0 and chi must be square and of the same size")
+    out = np.zeros((n, n))
+    _check(_lib.hp_hubbard_params(n, _ptr(a), _ptr(b), _ptr(out)), allow_warn=False)
+    return out
+
+
+def hp_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def hp_apply_h(ctx: Context, entry: int, x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.complex128)
+    y = np.zeros_like(x)
+    _check(_lib.hp_apply_h(ctx.handle, int(entry), x.shape[0], _ptr(x.view(np.float64)), _ptr(y.view(np.float64))),
+           allow_warn=False)
+    return y
+
+
+def hp_solve_first_order(ctx: Context, pert_site: int, q_frac, mesh_k: int, dv: Optional[np.ndarray],
+                         params: ScfParams, npw_kq: int):
+    q = _f64(q_frac)
+    out = np.zeros((ctx.n_occ, npw_kq), dtype=np.complex128)
+    p = params.c()
+    dvp = None
+    if dv is not None:
+        dva = np.ascontiguousarray(dv, dtype=np.complex128)
+        if dva.shape != ctx.fft:
+            raise ValueError("dv must have the FFT grid shape")
+        dvp = _ptr(dva.view(np.float64))
+    s = _check(_lib.hp_solve_first_order(ctx.handle, int(pert_site), _ptr(q), int(mesh_k), dvp, C.byref(p),
+                                         _ptr(out.view(np.float64))))
+    return out, s

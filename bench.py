@@ -1,0 +1,211 @@
+"""Benchmark of the DFPT Hubbard-response Sternheimer path on one MI355X.
+
+One step = the whole hot path over one synthetic workload: the self-consistent
+Sternheimer solves (Eq. 15) for every Hubbard site and every q of the q-mesh
+(hp_response_matrix: RHS, batched PCG with H applies, response density,
+Hartree + LDA kernel, mixing, response occupations, the q-sum of Eq. 12) and the
+U/V inversion (Eqs. 8-9).  The default workload is the olivine-shaped cell
+(28 atoms, 4 d sites, ~10^4 plane waves, FFT 72x45x40, 112 bands, k 2x3x4,
+q 1x2x2).  Inputs are generated once and are resident in HBM before timing.
+
+Prints one JSON line: value = single-band H applications per second over the
+timed steps (whole job), ms_per_step = Sternheimer SCF wall time of one step.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Sternheimer SCF wall time + Hψ applies/s, mixed-batched vs FP64, at χ err"
+HA_EV = 27.211386245988
+PEAK = {"fp64_vector": 78.6e12, "fp64_mfma": 78.6e12, "hbm": 8.0e12}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="olivine28")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--cg-tol", type=float, default=1e-10)
+    ap.add_argument("--conv-thr-chi", type=float, default=1e-10)
+    ap.add_argument("--conv-thr-v", type=float, default=1e-8)
+    ap.add_argument("--cpu-baseline-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def fft_flops(n):
+    return 5.0 * n * math.log2(n)
+
+
+def plane_flops(gs, entry):
+    """Algorithmic flops of one xy-plane round trip for the local potential on the sphere of
+    `entry`: radix FFTs along y on the columns that hold sticks and along x on every row,
+    both directions, plus the real x complex product (5 N log2 N per complex FFT)."""
+    n1, n2, _ = gs.fft
+    m1 = set(int(m) % n1 for m in gs.kpts[entry].miller[:, 0])
+    return 2.0 * (len(m1) * fft_flops(n2) + n2 * fft_flops(n1)) + 2.0 * n1 * n2
+
+
+def kq_entries(gs, q):
+    import numpy as np
+    out = []
+    for ik in range(gs.n_mesh):
+        kq = gs.kpts[ik].k_frac + q
+        for j, e in enumerate(gs.kpts):
+            d = kq - e.k_frac
+            if np.all(np.abs(d - np.round(d)) < 1e-9):
+                out.append(j)
+                break
+    return out
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2203_15684_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2203_15684_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def roofline(gs, prof, nq_list):
+    """Roofline record of the kernel with the largest measured GPU time."""
+    import numpy as np
+    name, (calls, ms) = max(prof.items(), key=lambda kv: kv[1][1])
+    avg_s = ms / max(calls, 1) * 1e-3
+    n3 = gs.fft[2]
+    nb = gs.n_occ
+    # every operator launch covers all (mesh k, band) items of one (site, q) problem
+    qs = [np.array(q) for q in nq_list]
+    per_q = []
+    for q in qs:
+        ej = kq_entries(gs, q)
+        per_q.append(ej)
+    if name == "plane_vloc":
+        # average over q of the per-launch algorithmic flops
+        fl = np.mean([sum(plane_flops(gs, j) for j in ej) * nb * n3 for ej in per_q])
+        rec = {"bound": "alu", "achieved": fl / avg_s / 1e12, "peak": PEAK["fp64_vector"] / 1e12,
+               "unit": "TFLOP/s"}
+    elif name in ("zproj", "zexpand"):
+        m = gs.n_beta + gs.n_occ
+        fl = np.mean([sum(8.0 * m * nb * gs.kpts[j].npw for j in ej) for ej in per_q])
+        rec = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": PEAK["fp64_mfma"] / 1e12,
+               "unit": "TFLOP/s"}
+    else:
+        by = np.mean([sum(16.0 * 3 * nb * gs.kpts[j].npw for j in ej) for ej in per_q])
+        rec = {"bound": "hbm", "achieved": by / avg_s / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s"}
+    rec["frac"] = rec["achieved"] / rec["peak"]
+    rec["kernel"] = name
+    rec["avg_launch_ms"] = avg_s * 1e3
+    rec["launches"] = calls
+    rec["traffic"] = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{name}_{gs.spec.name}.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            t = json.load(fh)
+        if t.get("source_hash") == source_hash():
+            rec["traffic"] = t.get("bytes_per_launch")
+    return rec
+
+
+def cpu_baseline(gs, seconds):
+    """The FP64 oracle's H apply timed on the host cores on a bounded sample."""
+    import numpy as np
+    import oracle
+    from oracle.hp_oracle import _workers
+    o = oracle.Oracle(gs, cache_limit_bytes=0)
+    e = gs.kpts[0]
+    X = e.u
+    o.h_apply(0, X[:2])  # plan caches
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        o.h_apply(0, X)
+        reps += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": reps * X.shape[0] / dt, "unit": "Hpsi/s", "cores": _workers(), "kind": "oracle",
+            "sample": f"oracle H apply (FFT local potential + KB projectors), {X.shape[0]} bands x {reps} "
+                      f"repetitions at one k-point of {gs.spec.name} ({e.npw} plane waves), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the (site, q) problems would be "
+              "sharded across GPUs with no collective, see the design notes.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from synth import cache
+    from paper_2203_15684_amd import hp
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t0 = time.time()
+    gs = cache.get(args.config)
+    t_gen = time.time() - t0
+    ctx = hp.hp_ground_state_load(gs)
+    prec = hp.HP_FP64 if args.precision == "fp64" else hp.HP_MIXED
+    p = hp.ScfParams(conv_thr_chi=args.conv_thr_chi, conv_thr_v=args.conv_thr_v, cg_tol=args.cg_tol,
+                     niter_max=100, max_cg_iter=2000, precision=prec)
+    nq = gs.qmesh
+    nq_list = [tuple(q) for q in gs.qpoints()]
+
+    def step():
+        chi0, chi, mim, st, status = hp.hp_response_matrix(ctx, nq, p)
+        uv = hp.hp_hubbard_params(chi0, chi)
+        return chi0, chi, uv, st, status
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    hp.hp_profile_start(ctx)
+    t_start = time.perf_counter()
+    results = []
+    for _ in range(args.steps):
+        results.append(step())
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    prof = hp.hp_profile_stop(ctx)
+    chi0, chi, uv, st, status = results[-1]
+    happ = sum(r[3]["h_applies_fp64"] + r[3]["h_applies_lowp"] for r in results)
+    value = happ / t_total
+    rec = roofline(gs, prof, nq_list)
+    npws = [e.npw for e in gs.kpts]
+    out = {
+        "metric": METRIC, "value": value, "unit": "Hpsi/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_total / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == hp.HP_FP64 else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"{gs.spec.name}: olivine-shaped cell {gs.spec.cell} bohr, {gs.spec.n_atoms} atoms, "
+                               f"{gs.n_hub} d sites, {gs.n_occ} bands, FFT {'x'.join(map(str, gs.fft))}, "
+                               f"k {'x'.join(map(str, gs.kmesh))}, q {'x'.join(map(str, gs.qmesh))}",
+                   "npw_min": min(npws), "npw_max": max(npws), "k_entries": len(npws),
+                   "precision": args.precision, "cg_tol": args.cg_tol, "conv_thr_chi": args.conv_thr_chi,
+                   "conv_thr_v": args.conv_thr_v, "site_q_pairs": gs.n_hub * len(nq_list)},
+        "scf": {"status": status, "scf_iters": st["scf_iters"], "cg_iters": st["cg_iters"],
+                "h_applies": happ / args.steps, "stage_s": st["stage_s"][:5],
+                "max_imag_chi": None},
+        "chi0_diag": [float(x) for x in np.diag(chi0)], "chi_diag": [float(x) for x in np.diag(chi)],
+        "U_eV": [float(x) * HA_EV for x in np.diag(uv)],
+        "kernel_ms": {k: round(v[1], 3) for k, v in prof.items()},
+        "roofline": rec,
+        "setup_s": {"ground_state": round(t_gen, 1)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(gs, args.cpu_baseline_seconds)
+    print(json.dumps(out), flush=True)
+    hp.hp_destroy(ctx)
+
+
+if __name__ == "__main__":
+    main()

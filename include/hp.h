@@ -192,6 +192,20 @@ hp_status hp_apply_h(hp_ctx *c, int32_t entry, int32_t n, const double *x, doubl
 hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const double q_frac[3], int32_t mesh_k,
                                const double *dv, const hp_scf_params *p, double *du_out);
 
+/* ---- Per-kernel timing ------------------------------------------------------
+ * hp_profile_start enables and resets per-kernel GPU timing on the context's
+ * stream (HIP events around each launch of the main kernels); hp_profile_stop
+ * synchronizes, disables timing and writes up to `max` records (kernel name,
+ * launches, summed GPU milliseconds).  *n_out receives the number written. */
+typedef struct hp_kernel_time {
+  const char *name;       /* static string owned by the library */
+  int64_t calls;
+  double total_ms;
+} hp_kernel_time;
+
+hp_status hp_profile_start(hp_ctx *c);
+hp_status hp_profile_stop(hp_ctx *c, hp_kernel_time *out, int32_t max, int32_t *n_out);
+
 #ifdef __cplusplus
 }
 #endif

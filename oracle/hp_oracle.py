@@ -28,6 +28,18 @@ from . import pz81
 FOUR_PI = 4.0 * math.pi
 
 
+def _workers() -> int:
+    """Host threads for the oracle's FFTs: HP_ORACLE_WORKERS, else the CPUs this process may use."""
+    import os
+    v = os.environ.get("HP_ORACLE_WORKERS")
+    if v:
+        return max(1, int(v))
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return max(1, os.cpu_count() or 1)
+
+
 @dataclass
 class ScfParams:
     """Controls of the self-consistent Sternheimer loop (the paper's inputhp
@@ -87,11 +99,11 @@ class Oracle:
         c = np.atleast_2d(c)
         g = np.zeros((c.shape[0], self.nr), dtype=np.complex128)
         g[:, idx] = c
-        return sfft.ifftn(g.reshape((c.shape[0],) + self.fft), axes=(1, 2, 3), workers=-1) * self.nr
+        return sfft.ifftn(g.reshape((c.shape[0],) + self.fft), axes=(1, 2, 3), workers=_workers()) * self.nr
 
     def to_recip(self, f: np.ndarray, idx: np.ndarray) -> np.ndarray:
         """c(G) = (1/N_r) sum_j f(r_j) e^{-iG.r_j} at the plane waves idx; f is (nb, N1, N2, N3)."""
-        g = sfft.fftn(f, axes=(1, 2, 3), workers=-1).reshape(f.shape[0], self.nr) / self.nr
+        g = sfft.fftn(f, axes=(1, 2, 3), workers=_workers()).reshape(f.shape[0], self.nr) / self.nr
         return g[:, idx]
 
     def psi_r(self, ie: int) -> np.ndarray:

@@ -100,6 +100,36 @@ __device__ __forceinline__ void dft_small<8>(double2 *x, double sign) {
   }
 }
 
+template <>
+__device__ __forceinline__ void dft_small<9>(double2 *x, double sign) {
+  // 9 = 3 x 3: DFT3 over each residue class b of u = 3a + b, twiddle W9^{bc}, DFT3 over b.
+  const double c1 = 0.76604444311897803520, s1 = 0.64278760968653932632;  // cos, sin 2pi/9
+  const double c2 = 0.17364817766693034885, s2 = 0.98480775301220805936;  // cos, sin 4pi/9
+  const double c4 = -0.93969262078590838405, s4 = 0.34202014332566873304;  // cos, sin 8pi/9
+  double2 y[3][3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    double2 t[3] = {x[b], x[b + 3], x[b + 6]};
+    dft_small<3>(t, sign);
+    y[b][0] = t[0];
+    y[b][1] = t[1];
+    y[b][2] = t[2];
+  }
+  const double2 w1 = make_double2(c1, sign * s1), w2 = make_double2(c2, sign * s2), w4 = make_double2(c4, sign * s4);
+  y[1][1] = cmul(y[1][1], w1);
+  y[1][2] = cmul(y[1][2], w2);
+  y[2][1] = cmul(y[2][1], w2);
+  y[2][2] = cmul(y[2][2], w4);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double2 t[3] = {y[0][c], y[1][c], y[2][c]};
+    dft_small<3>(t, sign);
+    x[c] = t[0];
+    x[c + 3] = t[1];
+    x[c + 6] = t[2];
+  }
+}
+
 __device__ __forceinline__ void dft_any(double2 *x, int R, double sign) {
   switch (R) {
     case 2: dft_small<2>(x, sign); break;
@@ -107,6 +137,7 @@ __device__ __forceinline__ void dft_any(double2 *x, int R, double sign) {
     case 4: dft_small<4>(x, sign); break;
     case 5: dft_small<5>(x, sign); break;
     case 8: dft_small<8>(x, sign); break;
+    case 9: dft_small<9>(x, sign); break;
     default: break;
   }
 }
@@ -138,7 +169,7 @@ __device__ __forceinline__ void fft_stage(double2 *P, int nlines, const int *lin
     }
     const int base = lb + (blk * B + j) * es;
     const int step = L * es;
-    double2 x[8];
+    double2 x[9];
     for (int t = 0; t < R; ++t) x[t] = P[base + t * step];
     if (dif) {
       dft_any(x, R, sign);
@@ -178,19 +209,6 @@ __device__ __forceinline__ int wrap(int v, int n) {
   return v < 0 ? v + n : v;
 }
 
-// y-lines (fixed x, contiguous) over the active x columns of a basis shifted by g0x.
-__device__ __forceinline__ void fft_y_active(double2 *P, const Plane &pl, const Sticks &sk, const EntryDev &E,
-                                             int g0x, bool dif) {
-  fft_lines(P, pl.ay, E.nxa, sk.xa + E.xa_off, pl.n2, pl.n1, g0x, 0, 1, dif);
-}
-__device__ __forceinline__ void fft_y_all(double2 *P, const Plane &pl, bool dif) {
-  fft_lines(P, pl.ay, pl.n1, nullptr, 0, 1, 0, pl.n2, 1, dif);
-}
-// x-lines (fixed y, stride N2) over every y.
-__device__ __forceinline__ void fft_x_all(double2 *P, const Plane &pl, bool dif) {
-  fft_lines(P, pl.ax, pl.n2, nullptr, 0, 1, 0, 1, pl.n2, dif);
-}
-
 __device__ __forceinline__ void plane_zero(double2 *P, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) P[i] = make_double2(0.0, 0.0);
 }
@@ -208,14 +226,160 @@ __device__ __forceinline__ void basis_of(const KPair *kp, int k, int use_kq, int
   }
 }
 
+// ------------------------------------------------- compile-time transforms
+// Radix order must match the host's factorization: at each step the first of
+// 8, 9, 4, 2, 3, 5 that divides.
+constexpr int crad(int n, int s) {
+  for (int i = 0;; ++i) {
+    const int r = (n % 8 == 0)   ? 8
+                  : (n % 9 == 0) ? 9
+                  : (n % 4 == 0) ? 4
+                  : (n % 2 == 0) ? 2
+                  : (n % 3 == 0) ? 3
+                  : (n % 5 == 0) ? 5
+                                 : 1;
+    if (i == s || r == 1) return r;
+    n /= r;
+  }
+}
+constexpr int cnst(int n) {
+  int k = 0;
+  while (n > 1) {
+    const int r = crad(n, 0);
+    if (r == 1) return -1;
+    n /= r;
+    ++k;
+  }
+  return k;
+}
+constexpr int cspan(int n, int s) {
+  int p = 1;
+  for (int i = 0; i <= s; ++i) p *= crad(n, i);
+  return n / p;
+}
+
+struct BaseList {  // line l starts at xs[l] * mul (xs already shifted and wrapped)
+  const int *xs;
+  int mul;
+  __device__ __forceinline__ int operator()(int l) const { return xs[l] * mul; }
+};
+struct BaseAffine {  // line l starts at l * stride
+  int stride;
+  __device__ __forceinline__ int operator()(int l) const { return l * stride; }
+};
+
+template <int N, int S, bool DIF, class BaseF>
+__device__ __forceinline__ void cstage(double2 *__restrict__ P, const double2 *__restrict__ tw, int nlines,
+                                       const BaseF &base, int es) {
+  constexpr int R = crad(N, S), L = cspan(N, S), B = R * L, NB = N / R, TSTEP = N / B;
+  const int total = nlines * NB;
+  for (int w = threadIdx.x; w < total; w += blockDim.x) {
+    const int line = w / NB;
+    const int b = w - line * NB;
+    const int blk = b / L;
+    const int j = b - blk * L;
+    const int o = base(line) + (blk * B + j) * es;
+    double2 x[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) x[t] = P[o + t * L * es];
+    if constexpr (DIF) {
+      dft_small<R>(x, 1.0);
+      if constexpr (L > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) x[t] = cmul(x[t], tw[j * t * TSTEP]);
+      }
+    } else {
+      if constexpr (L > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) x[t] = cmulc(x[t], tw[j * t * TSTEP]);
+      }
+      dft_small<R>(x, -1.0);
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) P[o + t * L * es] = x[t];
+  }
+  __syncthreads();
+}
+
+template <int N, bool DIF, int I, class BaseF>
+__device__ __forceinline__ void cfft(double2 *P, const double2 *tw, int nlines, const BaseF &base, int es) {
+  constexpr int NS = cnst(N);
+  static_assert(NS > 0, "FFT length must be a product of 2, 3 and 5");
+  if constexpr (I < NS) {
+    cstage<N, DIF ? I : NS - 1 - I, DIF>(P, tw, nlines, base, es);
+    cfft<N, DIF, I + 1>(P, tw, nlines, base, es);
+  }
+}
+
+// Per-block plane context: LDS tables and the transforms of one xy plane.
+// N1 = N2 = 0 selects the runtime-size path.
+template <int N1, int N2>
+struct PlaneCtx {
+  const Plane &pl;
+  double2 *P;      // [n1*n2]
+  double2 *twx;    // [n1] (LDS copy)
+  double2 *twy;    // [n2]
+  int *xs;         // [n1] active x columns, shifted and wrapped
+  int nxa;
+  __device__ __forceinline__ int n1() const { return N1 > 0 ? N1 : pl.n1; }
+  __device__ __forceinline__ int n2() const { return N2 > 0 ? N2 : pl.n2; }
+  __device__ __forceinline__ int np() const { return n1() * n2(); }
+  __device__ __forceinline__ PlaneCtx(const Plane &p, double2 *lds) : pl(p) {
+    P = lds;
+    twx = P + np();
+    twy = twx + n1();
+    xs = reinterpret_cast<int *>(twy + n2());
+    nxa = 0;
+    for (int i = threadIdx.x; i < n1(); i += blockDim.x) twx[i] = pl.ax.tw[i];
+    for (int i = threadIdx.x; i < n2(); i += blockDim.x) twy[i] = pl.ay.tw[i];
+  }
+  // active x list of a stick set shifted by g0x (call from every thread; ends with a barrier)
+  __device__ __forceinline__ void set_active(const int *xa, int n, int g0x) {
+    nxa = n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) xs[i] = wrap(xa[i] - g0x, n1());
+    __syncthreads();
+  }
+  __device__ __forceinline__ void set_all_x() {
+    nxa = n1();
+    for (int i = threadIdx.x; i < n1(); i += blockDim.x) xs[i] = i;
+    __syncthreads();
+  }
+  template <bool DIF>
+  __device__ __forceinline__ void y_lines() {  // lines at the listed x, contiguous, length N2
+    if constexpr (N2 > 0) {
+      cfft<N2, DIF, 0>(P, twy, nxa, BaseList{xs, N2}, 1);
+    } else {
+      fft_lines(P, pl.ay, nxa, xs, pl.n2, pl.n1, 0, 0, 1, DIF);
+    }
+  }
+  template <bool DIF>
+  __device__ __forceinline__ void x_lines() {  // every y, stride N2, length N1
+    if constexpr (N1 > 0) {
+      cfft<N1, DIF, 0>(P, twx, N2, BaseAffine{1}, N2);
+    } else {
+      fft_lines(P, pl.ax, pl.n2, nullptr, 0, 1, 0, 1, pl.n2, DIF);
+    }
+  }
+  __device__ __forceinline__ int pos(int x, int y, int g0x, int g0y) const {
+    return wrap(x - g0x, n1()) * n2() + wrap(y - g0y, n2());
+  }
+};
+
+int plane_lds_t(const Plane &pl) {
+  return pl.n1 * pl.n2 * (int)sizeof(double2) + (pl.n1 + pl.n2) * (int)sizeof(double2) + pl.n1 * (int)sizeof(int);
+}
+
 // ----------------------------------------------------------------- kernels
 
+template <int N3>
 __global__ void __launch_bounds__(kThreads) k_stick_inv(Sticks sk, const KPair *kp, int use_kq, int nb,
                                                         const double2 *__restrict__ X, int ld,
-                                                        double2 *__restrict__ S, int ns_pad, int n3,
-                                                        const double2 *__restrict__ tw3) {
+                                                        double2 *__restrict__ S, int ns_pad, int n3_rt,
+                                                        const double2 *__restrict__ tw3, const int *active) {
   extern __shared__ double2 smem[];
+  const int n3 = N3 > 0 ? N3 : n3_rt;
   const int item = blockIdx.y;
+  if (active && !active[item]) return;
   const int k = item / nb;
   int e, g0x, g0y, g0z;
   basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
@@ -227,8 +391,10 @@ __global__ void __launch_bounds__(kThreads) k_stick_inv(Sticks sk, const KPair *
   const int *slen = sk.slen + E.st_off;
   const int p0 = sstart[s0];
   const int p1 = sstart[s1 - 1] + slen[s1 - 1];
-  double2 *c = smem;
-  int *zi = reinterpret_cast<int *>(smem + (p1 - p0));
+  double2 *tw = smem;             // [n3]
+  double2 *c = smem + n3;         // [p1 - p0]
+  int *zi = reinterpret_cast<int *>(c + (p1 - p0));
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) tw[i] = tw3[i];
   const double2 *x = X + (size_t)item * ld;
   for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
     c[p - p0] = x[p];
@@ -243,23 +409,24 @@ __global__ void __launch_bounds__(kThreads) k_stick_inv(Sticks sk, const KPair *
     const int a = sstart[s] - p0;
     const int len = slen[s];
     double2 acc = make_double2(0.0, 0.0);
-    for (int t = 0; t < len; ++t) {
-      const double2 w = tw3[(zi[a + t] * z) % n3];
-      acc = cadd(acc, cmul(c[a + t], w));
-    }
+    for (int t = 0; t < len; ++t) acc = cadd(acc, cmul(c[a + t], tw[(zi[a + t] * z) % n3]));
     out[(size_t)z * ns_pad + s] = acc;
   }
 }
 
+template <int N3>
 __global__ void __launch_bounds__(kThreads) k_stick_fwd(Sticks sk, const KPair *kp, int use_kq, int nb,
-                                                        const double2 *__restrict__ S, int ns_pad, int n3,
+                                                        const double2 *__restrict__ S, int ns_pad, int n3_rt,
                                                         const double2 *__restrict__ tw3, double scale,
                                                         double2 *__restrict__ Y, int ld, int mode,
                                                         const double *__restrict__ kin,
                                                         const double *__restrict__ eps,
-                                                        const double2 *__restrict__ X, int eps_stride) {
+                                                        const double2 *__restrict__ X, int eps_stride,
+                                                        const int *active) {
   extern __shared__ double2 smem[];
+  const int n3 = N3 > 0 ? N3 : n3_rt;
   const int item = blockIdx.y;
+  if (active && !active[item]) return;
   const int k = item / nb;
   const int v = item - k * nb;
   int e, g0x, g0y, g0z;
@@ -273,8 +440,10 @@ __global__ void __launch_bounds__(kThreads) k_stick_fwd(Sticks sk, const KPair *
   const int *slen = sk.slen + E.st_off;
   const int p0 = sstart[s0];
   const int p1 = sstart[s1 - 1] + slen[s1 - 1];
-  double2 *sl = smem;                                   // [n3][nsc]
-  int *own = reinterpret_cast<int *>(smem + n3 * nsc);  // [p1-p0] stick of each plane wave
+  double2 *tw = smem;                                   // [n3]
+  double2 *sl = smem + n3;                              // [n3][nsc]
+  int *own = reinterpret_cast<int *>(sl + n3 * nsc);    // [p1-p0] stick of each plane wave
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) tw[i] = tw3[i];
   if (S) {
     const double2 *in = S + (size_t)item * n3 * ns_pad;
     for (int idx = threadIdx.x; idx < nsc * n3; idx += blockDim.x) {
@@ -294,9 +463,11 @@ __global__ void __launch_bounds__(kThreads) k_stick_fwd(Sticks sk, const KPair *
     if (S) {
       const int s = own[p - p0];
       const int zz = wrap(sk.iz[E.pw_off + p] - g0z, n3);
+      int ix = 0;
       for (int z = 0; z < n3; ++z) {
-        const double2 w = tw3[(zz * z) % n3];
-        acc = cadd(acc, cmulc(sl[z * nsc + s], w));
+        acc = cadd(acc, cmulc(sl[z * nsc + s], tw[ix]));
+        ix += zz;
+        if (ix >= n3) ix -= n3;
       }
       acc = cscale(acc, scale);
     }
@@ -309,115 +480,125 @@ __global__ void __launch_bounds__(kThreads) k_stick_fwd(Sticks sk, const KPair *
   }
 }
 
+template <int N1, int N2>
 __global__ void __launch_bounds__(kThreads) k_plane_vloc(Plane pl, Sticks sk, const KPair *kp, int use_kq, int nb,
                                                          const double2 *__restrict__ Sin,
                                                          double2 *__restrict__ Sout, int ns_pad,
-                                                         const double *__restrict__ vp) {
-  extern __shared__ double2 P[];
-  const int z = blockIdx.x;
+                                                         const double *__restrict__ vp, const int *active) {
+  extern __shared__ double2 lds[];
   const int item = blockIdx.y;
+  if (active && !active[item]) return;
+  PlaneCtx<N1, N2> pc(pl, lds);
+  const int z = blockIdx.x;
   const int k = item / nb;
   int e, g0x, g0y, g0z;
   basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
   const EntryDev E = sk.ent[e];
-  const int np = pl.n1 * pl.n2;
+  const int np = pc.np();
+  double2 *P = pc.P;
   plane_zero(P, np);
-  __syncthreads();
+  pc.set_active(sk.xa + E.xa_off, E.nxa, g0x);
   const int *sx = sk.sx + E.st_off;
   const int *sy = sk.sy + E.st_off;
   const size_t so = ((size_t)item * pl.n3 + z) * ns_pad;
-  for (int s = threadIdx.x; s < E.ns; s += blockDim.x)
-    P[wrap(sx[s] - g0x, pl.n1) * pl.n2 + wrap(sy[s] - g0y, pl.n2)] = Sin[so + s];
+  for (int s = threadIdx.x; s < E.ns; s += blockDim.x) P[pc.pos(sx[s], sy[s], g0x, g0y)] = Sin[so + s];
   __syncthreads();
-  fft_y_active(P, pl, sk, E, g0x, true);
-  fft_x_all(P, pl, true);
+  pc.template y_lines<true>();
+  pc.template x_lines<true>();
   const double *v = vp + (size_t)z * np;
   for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = cscale(P[i], v[i]);
   __syncthreads();
-  fft_x_all(P, pl, false);
-  fft_y_active(P, pl, sk, E, g0x, false);
-  for (int s = threadIdx.x; s < E.ns; s += blockDim.x)
-    Sout[so + s] = P[wrap(sx[s] - g0x, pl.n1) * pl.n2 + wrap(sy[s] - g0y, pl.n2)];
+  pc.template x_lines<false>();
+  pc.template y_lines<false>();
+  for (int s = threadIdx.x; s < E.ns; s += blockDim.x) Sout[so + s] = P[pc.pos(sx[s], sy[s], g0x, g0y)];
 }
 
+template <int N1, int N2>
 __global__ void __launch_bounds__(kThreads) k_plane_to_real(Plane pl, Sticks sk, const KPair *kp, int use_kq,
                                                             int nb, const double2 *__restrict__ Sin, int ns_pad,
                                                             double2 *__restrict__ R) {
-  extern __shared__ double2 P[];
+  extern __shared__ double2 lds[];
+  PlaneCtx<N1, N2> pc(pl, lds);
   const int z = blockIdx.x;
   const int item = blockIdx.y;
   const int k = item / nb;
   int e, g0x, g0y, g0z;
   basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
   const EntryDev E = sk.ent[e];
-  const int np = pl.n1 * pl.n2;
+  const int np = pc.np();
+  double2 *P = pc.P;
   plane_zero(P, np);
-  __syncthreads();
+  pc.set_active(sk.xa + E.xa_off, E.nxa, g0x);
   const int *sx = sk.sx + E.st_off;
   const int *sy = sk.sy + E.st_off;
   const size_t so = ((size_t)item * pl.n3 + z) * ns_pad;
-  for (int s = threadIdx.x; s < E.ns; s += blockDim.x)
-    P[wrap(sx[s] - g0x, pl.n1) * pl.n2 + wrap(sy[s] - g0y, pl.n2)] = Sin[so + s];
+  for (int s = threadIdx.x; s < E.ns; s += blockDim.x) P[pc.pos(sx[s], sy[s], g0x, g0y)] = Sin[so + s];
   __syncthreads();
-  fft_y_active(P, pl, sk, E, g0x, true);
-  fft_x_all(P, pl, true);
+  pc.template y_lines<true>();
+  pc.template x_lines<true>();
   double2 *out = R + ((size_t)item * pl.n3 + z) * np;
   for (int i = threadIdx.x; i < np; i += blockDim.x) out[i] = P[i];
 }
 
+template <int N1, int N2>
 __global__ void __launch_bounds__(kThreads) k_plane_mul_fwd(Plane pl, Sticks sk, const KPair *kp, int nb,
                                                             const double2 *__restrict__ psi,
                                                             const double2 *__restrict__ dv,
                                                             double2 *__restrict__ Sout, int ns_pad) {
-  extern __shared__ double2 P[];
+  extern __shared__ double2 lds[];
+  PlaneCtx<N1, N2> pc(pl, lds);
   const int z = blockIdx.x;
   const int item = blockIdx.y;
   const int k = item / nb;
   int e, g0x, g0y, g0z;
   basis_of(kp, k, 1, e, g0x, g0y, g0z);
   const EntryDev E = sk.ent[e];
-  const int np = pl.n1 * pl.n2;
+  const int np = pc.np();
+  double2 *P = pc.P;
   const double2 *ps = psi + ((size_t)item * pl.n3 + z) * np;
   const double2 *d = dv + (size_t)z * np;
   for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = cmul(ps[i], d[i]);
-  __syncthreads();
-  fft_x_all(P, pl, false);
-  fft_y_active(P, pl, sk, E, g0x, false);
+  pc.set_active(sk.xa + E.xa_off, E.nxa, g0x);
+  pc.template x_lines<false>();
+  pc.template y_lines<false>();
   const int *sx = sk.sx + E.st_off;
   const int *sy = sk.sy + E.st_off;
   const size_t so = ((size_t)item * pl.n3 + z) * ns_pad;
-  for (int s = threadIdx.x; s < E.ns; s += blockDim.x)
-    Sout[so + s] = P[wrap(sx[s] - g0x, pl.n1) * pl.n2 + wrap(sy[s] - g0y, pl.n2)];
+  for (int s = threadIdx.x; s < E.ns; s += blockDim.x) Sout[so + s] = P[pc.pos(sx[s], sy[s], g0x, g0y)];
 }
 
+template <int N1, int N2>
 __global__ void __launch_bounds__(kThreads) k_plane_drho(Plane pl, Sticks sk, const KPair *kp, int nb,
                                                          const double2 *__restrict__ Sdu, int ns_pad,
                                                          const double2 *__restrict__ psi,
                                                          double2 *__restrict__ part) {
-  extern __shared__ double2 P[];
+  extern __shared__ double2 lds[];
+  PlaneCtx<N1, N2> pc(pl, lds);
   const int z = blockIdx.x;
   const int k = blockIdx.y;
   int e, g0x, g0y, g0z;
   basis_of(kp, k, 1, e, g0x, g0y, g0z);
   const EntryDev E = sk.ent[e];
-  const int np = pl.n1 * pl.n2;
+  const int np = pc.np();
+  double2 *P = pc.P;
   const int *sx = sk.sx + E.st_off;
   const int *sy = sk.sy + E.st_off;
-  double2 acc[kMaxPerThread];
-  for (int j = 0; j < kMaxPerThread; ++j) acc[j] = make_double2(0.0, 0.0);
+  pc.set_active(sk.xa + E.xa_off, E.nxa, g0x);
+  constexpr int PER = N1 > 0 ? (N1 * N2 + kThreads - 1) / kThreads : kMaxPerThread;
+  double2 acc[PER];
+  for (int j = 0; j < PER; ++j) acc[j] = make_double2(0.0, 0.0);
   for (int v = 0; v < nb; ++v) {
     const int item = k * nb + v;
     plane_zero(P, np);
     __syncthreads();
     const size_t so = ((size_t)item * pl.n3 + z) * ns_pad;
-    for (int s = threadIdx.x; s < E.ns; s += blockDim.x)
-      P[wrap(sx[s] - g0x, pl.n1) * pl.n2 + wrap(sy[s] - g0y, pl.n2)] = Sdu[so + s];
+    for (int s = threadIdx.x; s < E.ns; s += blockDim.x) P[pc.pos(sx[s], sy[s], g0x, g0y)] = Sdu[so + s];
     __syncthreads();
-    fft_y_active(P, pl, sk, E, g0x, true);
-    fft_x_all(P, pl, true);
+    pc.template y_lines<true>();
+    pc.template x_lines<true>();
     const double2 *ps = psi + ((size_t)item * pl.n3 + z) * np;
 #pragma unroll
-    for (int j = 0; j < kMaxPerThread; ++j) {
+    for (int j = 0; j < PER; ++j) {
       const int i = threadIdx.x + j * blockDim.x;
       if (i < np) acc[j] = cadd(acc[j], cmulc(P[i], ps[i]));
     }
@@ -425,7 +606,7 @@ __global__ void __launch_bounds__(kThreads) k_plane_drho(Plane pl, Sticks sk, co
   }
   double2 *out = part + ((size_t)k * pl.n3 + z) * np;
 #pragma unroll
-  for (int j = 0; j < kMaxPerThread; ++j) {
+  for (int j = 0; j < PER; ++j) {
     const int i = threadIdx.x + j * blockDim.x;
     if (i < np) out[i] = acc[j];
   }
@@ -446,16 +627,19 @@ __global__ void k_drho_reduce(const KPair *kp, int nk, const double2 *__restrict
 }
 
 // Hartree step 1: permuted real-space plane -> natural plane of G_x, G_y (forward).
+template <int N1, int N2>
 __global__ void __launch_bounds__(kThreads) k_hxc_planes_fwd(Plane pl, const double2 *__restrict__ drho,
                                                              double2 *__restrict__ tmp) {
-  extern __shared__ double2 P[];
+  extern __shared__ double2 lds[];
+  PlaneCtx<N1, N2> pc(pl, lds);
   const int z = blockIdx.x;
-  const int np = pl.n1 * pl.n2;
+  const int np = pc.np();
+  double2 *P = pc.P;
   const double2 *in = drho + (size_t)z * np;
   for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = in[i];
-  __syncthreads();
-  fft_x_all(P, pl, false);
-  fft_y_all(P, pl, false);
+  pc.set_all_x();
+  pc.template x_lines<false>();
+  pc.template y_lines<false>();
   double2 *out = tmp + (size_t)z * np;
   for (int i = threadIdx.x; i < np; i += blockDim.x) out[i] = P[i];
 }
@@ -499,18 +683,21 @@ __global__ void k_hxc_columns(Plane pl, const double2 *__restrict__ tw3, const d
 }
 
 // Hartree step 3: natural plane -> permuted real space, plus f_xc * drho.
+template <int N1, int N2>
 __global__ void __launch_bounds__(kThreads) k_hxc_planes_inv(Plane pl, const double2 *__restrict__ tmp,
                                                              const double *__restrict__ fxc,
                                                              const double2 *__restrict__ drho,
                                                              double2 *__restrict__ dvout) {
-  extern __shared__ double2 P[];
+  extern __shared__ double2 lds[];
+  PlaneCtx<N1, N2> pc(pl, lds);
   const int z = blockIdx.x;
-  const int np = pl.n1 * pl.n2;
+  const int np = pc.np();
+  double2 *P = pc.P;
   const double2 *in = tmp + (size_t)z * np;
   for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = in[i];
-  __syncthreads();
-  fft_y_all(P, pl, true);
-  fft_x_all(P, pl, true);
+  pc.set_all_x();
+  pc.template y_lines<true>();
+  pc.template x_lines<true>();
   const size_t o = (size_t)z * np;
   for (int i = threadIdx.x; i < np; i += blockDim.x) {
     const double fx = fxc[o + i];
@@ -573,58 +760,81 @@ __global__ void k_fxc(const double *__restrict__ rho, double *__restrict__ fxc, 
   fxc[i] = fx + dv * (-rs / (3.0 * r));
 }
 
-int plane_lds(const Plane &pl) { return pl.n1 * pl.n2 * (int)sizeof(double2); }
-
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
 
+// Grid sizes with compile-time transforms; other sizes take the runtime path.
+#define HP_PLANE_DISPATCH(KERNEL, GRID, LDS, ST, ...)                                                   \
+  do {                                                                                                 \
+    const int key_ = pl.n1 * 1000 + pl.n2;                                                            \
+    switch (key_) {                                                                                    \
+      case 24024: hipLaunchKernelGGL((KERNEL<24, 24>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break; \
+      case 30024: hipLaunchKernelGGL((KERNEL<30, 24>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break; \
+      case 48024: hipLaunchKernelGGL((KERNEL<48, 24>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break; \
+      case 48048: hipLaunchKernelGGL((KERNEL<48, 48>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break; \
+      case 72045: hipLaunchKernelGGL((KERNEL<72, 45>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break; \
+      case 144045: hipLaunchKernelGGL((KERNEL<144, 45>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL((KERNEL<0, 0>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;      \
+    }                                                                                                  \
+  } while (0)
+
+#define HP_STICK_DISPATCH(KERNEL, GRID, LDS, ST, N3, ...)                                                \
+  do {                                                                                                 \
+    switch (N3) {                                                                                      \
+      case 24: hipLaunchKernelGGL((KERNEL<24>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;      \
+      case 40: hipLaunchKernelGGL((KERNEL<40>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;      \
+      default: hipLaunchKernelGGL((KERNEL<0>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;       \
+    }                                                                                                  \
+  } while (0)
+
 hipError_t launch_stick_inv(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const double2 *X,
-                            int ld, double2 *S, int ns_pad, int n3, const double2 *tw3, int max_chunk_pw,
-                            int ns_max, hipStream_t st) {
+                            int ld, double2 *S, int ns_pad, int n3, const double2 *tw3, int max_chunk_pw, int ns_max,
+                            const int *active, hipStream_t st) {
   dim3 grid((ns_max + kStickChunk - 1) / kStickChunk, nitems);
-  size_t lds = (size_t)max_chunk_pw * (sizeof(double2) + sizeof(int));
-  hipLaunchKernelGGL(k_stick_inv, grid, dim3(kThreads), lds, st, sk, kp, use_kq, nb, X, ld, S, ns_pad, n3, tw3);
+  size_t lds = (size_t)n3 * sizeof(double2) + (size_t)max_chunk_pw * (sizeof(double2) + sizeof(int));
+  HP_STICK_DISPATCH(k_stick_inv, grid, lds, st, n3, sk, kp, use_kq, nb, X, ld, S, ns_pad, n3, tw3, active);
   return hipGetLastError();
 }
 
 hipError_t launch_stick_fwd(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const double2 *S,
                             int ns_pad, int n3, const double2 *tw3, double scale, double2 *Y, int ld, int mode,
                             const double *kin, const double *eps, const double2 *X, int eps_stride,
-                            int max_chunk_pw, int ns_max, hipStream_t st) {
+                            int max_chunk_pw, int ns_max, const int *active, hipStream_t st) {
   dim3 grid((ns_max + kStickChunk - 1) / kStickChunk, nitems);
-  size_t lds = (size_t)n3 * kStickChunk * sizeof(double2) + (size_t)max_chunk_pw * sizeof(int);
-  hipLaunchKernelGGL(k_stick_fwd, grid, dim3(kThreads), lds, st, sk, kp, use_kq, nb, S, ns_pad, n3, tw3, scale, Y,
-                     ld, mode, kin, eps, X, eps_stride);
+  size_t lds = (size_t)n3 * sizeof(double2) + (size_t)n3 * kStickChunk * sizeof(double2) +
+               (size_t)max_chunk_pw * sizeof(int);
+  HP_STICK_DISPATCH(k_stick_fwd, grid, lds, st, n3, sk, kp, use_kq, nb, S, ns_pad, n3, tw3, scale, Y, ld, mode, kin,
+                    eps, X, eps_stride, active);
   return hipGetLastError();
 }
 
 hipError_t launch_plane_vloc(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
-                             const double2 *Sin, double2 *Sout, int ns_pad, const double *vp, hipStream_t st) {
-  hipLaunchKernelGGL(k_plane_vloc, dim3(pl.n3, nitems), dim3(kThreads), plane_lds(pl), st, pl, sk, kp, use_kq, nb,
-                     Sin, Sout, ns_pad, vp);
+                             const double2 *Sin, double2 *Sout, int ns_pad, const double *vp, const int *active,
+                             hipStream_t st) {
+  HP_PLANE_DISPATCH(k_plane_vloc, dim3(pl.n3, nitems), plane_lds_t(pl), st, pl, sk, kp, use_kq, nb, Sin, Sout,
+                    ns_pad, vp, active);
   return hipGetLastError();
 }
 
 hipError_t launch_plane_to_real(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
                                 const double2 *Sin, int ns_pad, double2 *R, hipStream_t st) {
-  hipLaunchKernelGGL(k_plane_to_real, dim3(pl.n3, nitems), dim3(kThreads), plane_lds(pl), st, pl, sk, kp, use_kq,
-                     nb, Sin, ns_pad, R);
+  HP_PLANE_DISPATCH(k_plane_to_real, dim3(pl.n3, nitems), plane_lds_t(pl), st, pl, sk, kp, use_kq, nb, Sin, ns_pad,
+                    R);
   return hipGetLastError();
 }
 
 hipError_t launch_plane_mul_fwd(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nitems,
                                 const double2 *psi, const double2 *dv, double2 *Sout, int ns_pad, hipStream_t st) {
-  hipLaunchKernelGGL(k_plane_mul_fwd, dim3(pl.n3, nitems), dim3(kThreads), plane_lds(pl), st, pl, sk, kp, nb, psi,
-                     dv, Sout, ns_pad);
+  HP_PLANE_DISPATCH(k_plane_mul_fwd, dim3(pl.n3, nitems), plane_lds_t(pl), st, pl, sk, kp, nb, psi, dv, Sout,
+                    ns_pad);
   return hipGetLastError();
 }
 
 hipError_t launch_plane_drho(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nk, const double2 *Sdu,
                              int ns_pad, const double2 *psi, double2 *part, hipStream_t st) {
   if (pl.n1 * pl.n2 > kMaxPerThread * kThreads) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_plane_drho, dim3(pl.n3, nk), dim3(kThreads), plane_lds(pl), st, pl, sk, kp, nb, Sdu, ns_pad,
-                     psi, part);
+  HP_PLANE_DISPATCH(k_plane_drho, dim3(pl.n3, nk), plane_lds_t(pl), st, pl, sk, kp, nb, Sdu, ns_pad, psi, part);
   return hipGetLastError();
 }
 
@@ -637,12 +847,12 @@ hipError_t launch_drho_reduce(const KPair *kp, int nk, const double2 *part, long
 
 hipError_t launch_hxc(const Plane &pl, const Axis &az, const double *bvec, const double *q, const double2 *drho,
                       const double *fxc, double2 *tmp, double2 *dvout, hipStream_t st) {
-  hipLaunchKernelGGL(k_hxc_planes_fwd, dim3(pl.n3), dim3(kThreads), plane_lds(pl), st, pl, drho, tmp);
+  HP_PLANE_DISPATCH(k_hxc_planes_fwd, dim3(pl.n3), plane_lds_t(pl), st, pl, drho, tmp);
   const int cols = 32;
   const int np = pl.n1 * pl.n2;
   hipLaunchKernelGGL(k_hxc_columns, dim3((np + cols - 1) / cols), dim3(cols), 2 * pl.n3 * cols * sizeof(double2), st,
                      pl, az.tw, bvec, q[0], q[1], q[2], tmp);
-  hipLaunchKernelGGL(k_hxc_planes_inv, dim3(pl.n3), dim3(kThreads), plane_lds(pl), st, pl, tmp, fxc, drho, dvout);
+  HP_PLANE_DISPATCH(k_hxc_planes_inv, dim3(pl.n3), plane_lds_t(pl), st, pl, tmp, fxc, drho, dvout);
   return hipGetLastError();
 }
 

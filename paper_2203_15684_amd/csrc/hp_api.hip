@@ -47,15 +47,23 @@ hp_status fail(hp_status code, const char *fmt, ...) {
     if (s_ < 0) return s_;              \
   } while (0)
 
+// Radices in decimation-in-frequency order: at each step the first of 8, 9, 4, 2, 3, 5
+// that divides (the device code derives the same sequence at compile time).
 bool factor_235(int n, std::vector<int> &rad) {
   rad.clear();
   if (n < 1) return false;
-  while (n % 8 == 0) { rad.push_back(8); n /= 8; }
-  while (n % 4 == 0) { rad.push_back(4); n /= 4; }
-  while (n % 2 == 0) { rad.push_back(2); n /= 2; }
-  while (n % 3 == 0) { rad.push_back(3); n /= 3; }
-  while (n % 5 == 0) { rad.push_back(5); n /= 5; }
-  return n == 1 && rad.size() <= 8;
+  while (n > 1) {
+    int r = 0;
+    for (int c : {8, 9, 4, 2, 3, 5})
+      if (n % c == 0) {
+        r = c;
+        break;
+      }
+    if (r == 0) return false;
+    rad.push_back(r);
+    n /= r;
+  }
+  return rad.size() <= 8;
 }
 
 // Position p of a decimation-in-frequency output holds natural index perm[p].
@@ -126,6 +134,16 @@ struct hp_ctx {
   int nsplit_cap = 16;
   long t_stride = 0, phi_stride = 0;
   hipEvent_t ev[16];
+  // per-kernel timing (hp_profile_start / hp_profile_stop)
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Pending {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  long prof_calls[16] = {0};
+  double prof_ms[16] = {0};
 
   template <class T>
   hp_status alloc(T **p, size_t count) {
@@ -138,6 +156,56 @@ struct hp_ctx {
 namespace {
 
 constexpr int kNmixMax = 8;
+
+enum KernelId {
+  K_STICK_INV = 0,
+  K_PLANE_VLOC,
+  K_STICK_FWD,
+  K_ZPROJ,
+  K_ZEXPAND,
+  K_CG_STEP,
+  K_PLANE_DRHO,
+  K_PLANE_MUL,
+  K_COUNT
+};
+const char *const kKernelNames[K_COUNT] = {"stick_inv", "plane_vloc", "stick_fwd", "zproj",
+                                           "zexpand",   "cg_step",    "plane_drho", "plane_mul_fwd"};
+
+hipEvent_t prof_event(hp_ctx *c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Enqueue `launch` bracketed by events when profiling is on.
+template <class F>
+hipError_t timed(hp_ctx *c, int id, F launch) {
+  if (!c->prof_on) return launch();
+  hipEvent_t a = prof_event(c), b = prof_event(c);
+  if (a) (void)hipEventRecord(a, c->stream);
+  hipError_t e = launch();
+  if (b) (void)hipEventRecord(b, c->stream);
+  if (a && b) c->pending.push_back({id, a, b});
+  return e;
+}
+
+void prof_harvest(hp_ctx *c) {
+  for (auto &p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->prof_calls[p.id] += 1;
+      c->prof_ms[p.id] += ms;
+    }
+    c->ev_pool.push_back(p.a);
+    c->ev_pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
 
 hp_status check_kpoint(const hp_kpoint &k, int i, const hp_ground_state *gs) {
   if (k.struct_size != sizeof(hp_kpoint)) return fail(HP_ERR_ARG, "kpts[%d].struct_size mismatch", i);
@@ -204,6 +272,7 @@ struct Timer {
 
 hp_status sync(hp_ctx *c) {
   HPCHK(hipStreamSynchronize(c->stream));
+  if (!c->pending.empty()) prof_harvest(c);
   return HP_OK;
 }
 
@@ -218,9 +287,12 @@ int choose_nsplit(int M, int nb, int nk, int npw_max) {
 
 // C[k][m][v] = scale_m * sum_G conj(T[m0+m][G]) X[k,v][G]
 hp_status proj(hp_ctx *c, const KPair *kp, int use_kq, int nk, const double2 *T, long tstride, int m0, int M,
-               const double2 *X, int nb, const double *row_scale, double gscale, double2 *Cout) {
+               const double2 *X, int nb, const double *row_scale, double gscale, double2 *Cout,
+               const int *active = nullptr) {
   const int ns = choose_nsplit(M, nb, nk, c->npw_max);
-  HPCHK(launch_zproj(kp, use_kq, nk, T, tstride, m0, M, X, c->ld, nb, c->d_npw, c->Cpart, ns, c->stream));
+  HPCHK(timed(c, K_ZPROJ, [&] {
+    return launch_zproj(kp, use_kq, nk, T, tstride, m0, M, X, c->ld, nb, c->d_npw, c->Cpart, ns, active, c->stream);
+  }));
   HPCHK(launch_zproj_reduce(nk, M, nb, ns, c->Cpart, row_scale, gscale, Cout, c->stream));
   return HP_OK;
 }
@@ -228,16 +300,25 @@ hp_status proj(hp_ctx *c, const KPair *kp, int use_kq, int nk, const double2 *T,
 // Y = (H_{k+q} + alpha P_v - eps_v) X over nitems (or H_k X for diagnostics when eps == nullptr,
 // rows = n_beta only).
 hp_status apply_op(hp_ctx *c, const KPair *kp, int use_kq, int nk, int nb, const double2 *Xin, double2 *Y,
-                   const double *eps, int rows) {
+                   const double *eps, int rows, const int *active = nullptr) {
   const int nitems = nk * nb;
-  HPCHK(launch_stick_inv(c->sk, kp, use_kq, nb, nitems, Xin, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
-                         c->max_chunk_pw, c->ns_max, c->stream));
-  HPCHK(launch_plane_vloc(c->pl, c->sk, kp, use_kq, nb, nitems, c->S1, c->S2, c->ns_pad, c->d_vp, c->stream));
-  HPCHK(launch_stick_fwd(c->sk, kp, use_kq, nb, nitems, c->S2, c->ns_pad, c->n3, c->az.tw, 1.0 / (double)c->nr, Y,
-                         c->ld, 0, c->d_kin, eps, Xin, nb, c->max_chunk_pw, c->ns_max, c->stream));
-  HPTRY(proj(c, kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, Xin, nb, c->d_rowscale, 1.0, c->C));
-  HPCHK(launch_zexpand(kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, c->C, (long)rows * nb, 1.0, Y, c->ld, nb,
-                       c->d_npw, c->npw_max, c->stream));
+  HPCHK(timed(c, K_STICK_INV, [&] {
+    return launch_stick_inv(c->sk, kp, use_kq, nb, nitems, Xin, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
+                            c->max_chunk_pw, c->ns_max, active, c->stream);
+  }));
+  HPCHK(timed(c, K_PLANE_VLOC, [&] {
+    return launch_plane_vloc(c->pl, c->sk, kp, use_kq, nb, nitems, c->S1, c->S2, c->ns_pad, c->d_vp, active,
+                             c->stream);
+  }));
+  HPCHK(timed(c, K_STICK_FWD, [&] {
+    return launch_stick_fwd(c->sk, kp, use_kq, nb, nitems, c->S2, c->ns_pad, c->n3, c->az.tw, 1.0 / (double)c->nr, Y,
+                            c->ld, 0, c->d_kin, eps, Xin, nb, c->max_chunk_pw, c->ns_max, active, c->stream);
+  }));
+  HPTRY(proj(c, kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, Xin, nb, c->d_rowscale, 1.0, c->C, active));
+  HPCHK(timed(c, K_ZEXPAND, [&] {
+    return launch_zexpand(kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, c->C, (long)rows * nb, 1.0, Y, c->ld, nb,
+                          c->d_npw, c->npw_max, active, c->stream);
+  }));
   return HP_OK;
 }
 
@@ -245,19 +326,21 @@ hp_status apply_op(hp_ctx *c, const KPair *kp, int use_kq, int nk, int nb, const
 hp_status build_rhs(hp_ctx *c, const KPair *kp, int nk, int site, const double2 *dv, const double2 *psi) {
   const int nb = c->n_occ, nitems = nk * nb;
   if (dv) {
-    HPCHK(launch_plane_mul_fwd(c->pl, c->sk, kp, nb, nitems, psi, dv, c->S1, c->ns_pad, c->stream));
+    HPCHK(timed(c, K_PLANE_MUL, [&] {
+      return launch_plane_mul_fwd(c->pl, c->sk, kp, nb, nitems, psi, dv, c->S1, c->ns_pad, c->stream);
+    }));
     HPCHK(launch_stick_fwd(c->sk, kp, 1, nb, nitems, c->S1, c->ns_pad, c->n3, c->az.tw, -1.0 / (double)c->nr, c->B,
-                           c->ld, 2, nullptr, nullptr, nullptr, nb, c->max_chunk_pw, c->ns_max, c->stream));
+                           c->ld, 2, nullptr, nullptr, nullptr, nb, c->max_chunk_pw, c->ns_max, nullptr, c->stream));
   } else {
     HPCHK(hipMemsetAsync(c->B, 0, sizeof(double2) * (size_t)nitems * c->ld, c->stream));
   }
   // - sum_m |phi_{m,k+q}> <phi_{m,k}|u_vk>   (Eq. 16)
   HPCHK(launch_zexpand(kp, 1, nk, c->d_phi, c->phi_stride, 5 * site, 5, c->d_A + (size_t)5 * site * nb,
-                       (long)5 * c->n_hub * nb, -1.0, c->B, c->ld, nb, c->d_npw, c->npw_max, c->stream));
+                       (long)5 * c->n_hub * nb, -1.0, c->B, c->ld, nb, c->d_npw, c->npw_max, nullptr, c->stream));
   // P_c = 1 - sum_v' |u_v',k+q><u_v',k+q|   (Eq. 18)
   HPTRY(proj(c, kp, 1, nk, c->d_T, c->t_stride, c->n_beta, c->n_occ, c->B, nb, nullptr, 1.0, c->C));
   HPCHK(launch_zexpand(kp, 1, nk, c->d_T, c->t_stride, c->n_beta, c->n_occ, c->C, (long)c->n_occ * nb, -1.0, c->B,
-                       c->ld, c->n_occ, c->d_npw, c->npw_max, c->stream));
+                       c->ld, c->n_occ, c->d_npw, c->npw_max, nullptr, c->stream));
   return HP_OK;
 }
 
@@ -283,11 +366,13 @@ hp_status cg_solve(hp_ctx *c, const KPair *kp, int nk, const double *eps_items, 
   }
   while (h_count[0] > 0 && it < max_it) {
     ++it;
-    HPTRY(apply_op(c, kp, 1, nk, nb, c->P, c->AP, eps_items, rows));
-    *happ += nitems;
+    HPTRY(apply_op(c, kp, 1, nk, nb, c->P, c->AP, eps_items, rows, c->active));
+    *happ += h_count[0];  // converged items are skipped by the operator kernels
     HPCHK(hipMemsetAsync(c->count, 0, 2 * sizeof(int), c->stream));
-    HPCHK(launch_cg_step(kp, nb, nitems, c->X, c->R, c->P, c->AP, c->d_diag, eps_items, c->ld, c->d_npw, c->ld, c->rz,
-                         c->bn, c->rn, c->active, tol, c->count, c->stream));
+    HPCHK(timed(c, K_CG_STEP, [&] {
+      return launch_cg_step(kp, nb, nitems, c->X, c->R, c->P, c->AP, c->d_diag, eps_items, c->ld, c->d_npw, c->ld,
+                            c->rz, c->bn, c->rn, c->active, tol, c->count, c->stream);
+    }));
     HPCHK(hipMemcpyAsync(h_count, c->count, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HPTRY(sync(c));
     if (h_count[1] > 0) return fail(HP_ERR_NUMERIC, "non-finite residual in the Sternheimer solve");
@@ -392,6 +477,11 @@ extern "C" void hp_destroy(hp_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (void *p : c->allocs) (void)hipFree(p);
+  for (auto &p : c->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   for (int i = 0; i < 16; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -771,7 +861,7 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
     HPCHK(hipMemcpyAsync(c->X + (size_t)k * nb * c->ld, c->d_T + (size_t)k * c->t_stride + (size_t)c->n_beta * c->ld,
                          sizeof(double2) * (size_t)nb * c->ld, hipMemcpyDeviceToDevice, st));
   HPCHK(launch_stick_inv(c->sk, c->d_kself, 0, nb, (int)nitems, c->X, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
-                         c->max_chunk_pw, c->ns_max, st));
+                         c->max_chunk_pw, c->ns_max, nullptr, st));
   HPCHK(launch_plane_to_real(c->pl, c->sk, c->d_kself, 0, nb, (int)nitems, c->S1, c->ns_pad, c->d_psi, st));
   HPTRY(sync(c.get()));
   *out = c.release();
@@ -811,8 +901,10 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
     max_rel = mr;
     // response density (spin x time reversal) and occupations (Eq. 13)
     HPCHK(launch_stick_inv(c->sk, c->d_kp, 1, nb, nitems, c->X, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
-                           c->max_chunk_pw, c->ns_max, c->stream));
-    HPCHK(launch_plane_drho(c->pl, c->sk, c->d_kp, nb, nk, c->S1, c->ns_pad, c->d_psi, c->part, c->stream));
+                           c->max_chunk_pw, c->ns_max, nullptr, c->stream));
+    HPCHK(timed(c, K_PLANE_DRHO, [&] {
+      return launch_plane_drho(c->pl, c->sk, c->d_kp, nb, nk, c->S1, c->ns_pad, c->d_psi, c->part, c->stream);
+    }));
     HPCHK(launch_drho_reduce(c->d_kp, nk, c->part, nr, 1.0 / c->omega, c->drho, c->stream));
     HPCHK(hipEventRecord(c->ev[3], c->stream));
     HPCHK(launch_hxc(c->pl, c->az, c->d_bvec, q, c->drho, c->d_fxc, c->tmp, c->dvout, c->stream));
@@ -1119,4 +1211,32 @@ extern "C" hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const do
       du_out[2 * ((size_t)v * E.npw + q) + 1] = h[(size_t)v * c->ld + p2].y;
     }
   return nc == 0 ? HP_OK : HP_WARN_NOT_CONVERGED;
+}
+
+extern "C" hp_status hp_profile_start(hp_ctx *c) {
+  if (!c) return fail(HP_ERR_ARG, "context is NULL");
+  HPTRY(sync(c));
+  c->prof_on = true;
+  for (int i = 0; i < 16; ++i) {
+    c->prof_calls[i] = 0;
+    c->prof_ms[i] = 0.0;
+  }
+  return HP_OK;
+}
+
+extern "C" hp_status hp_profile_stop(hp_ctx *c, hp_kernel_time *out, int32_t max, int32_t *n_out) {
+  if (!c) return fail(HP_ERR_ARG, "context is NULL");
+  HPTRY(sync(c));
+  c->prof_on = false;
+  int n = 0;
+  for (int i = 0; i < K_COUNT; ++i) {
+    if (out && n < max) {
+      out[n].name = kKernelNames[i];
+      out[n].calls = c->prof_calls[i];
+      out[n].total_ms = c->prof_ms[i];
+    }
+    ++n;
+  }
+  if (n_out) *n_out = std::min(n, max);
+  return HP_OK;
 }

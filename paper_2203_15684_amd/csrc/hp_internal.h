@@ -70,16 +70,17 @@ struct Sticks {
 // S[item][z][s] = sum_{G in stick s} X[item][G] e^{+i G_z z}
 hipError_t launch_stick_inv(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const double2 *X,
                             int ld, double2 *S, int ns_pad, int n3, const double2 *tw3, int max_chunk_pw, int ns_max,
-                            hipStream_t st);
+                            const int *active, hipStream_t st);
 // Y[item][G] = scale * sum_z S[item][z][s(G)] e^{-i G_z z}   (S may be null: 0)
 //   mode 0 adds (kin[G] - eps[k*eps_stride+v]) X[item][G] (eps may be null: 0)
 hipError_t launch_stick_fwd(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const double2 *S,
                             int ns_pad, int n3, const double2 *tw3, double scale, double2 *Y, int ld, int mode,
                             const double *kin, const double *eps, const double2 *X, int eps_stride, int max_chunk_pw,
-                            int ns_max, hipStream_t st);
+                            int ns_max, const int *active, hipStream_t st);
 // Plane round trip for the local potential: sticks -> r (DIF) -> * vp -> sticks (reverse).
 hipError_t launch_plane_vloc(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
-                             const double2 *Sin, double2 *Sout, int ns_pad, const double *vp, hipStream_t st);
+                             const double2 *Sin, double2 *Sout, int ns_pad, const double *vp, const int *active,
+                             hipStream_t st);
 // Sticks -> real-space plane (permuted layout), R[item][z][plane].
 hipError_t launch_plane_to_real(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
                                 const double2 *Sin, int ns_pad, double2 *R, hipStream_t st);
@@ -106,13 +107,14 @@ hipError_t launch_fxc(const double *rho, double *fxc, long n, hipStream_t st);
 // proj:   Cpart -> C[k][m][v] = row_scale[m] * gscale * sum_G conj(T_e[m0+m][G]) X[k*nb+v][G]
 hipError_t launch_zproj(const KPair *kp, int use_kq, int nk, const double2 *T, long t_stride, int m0, int M,
                         const double2 *X, int ld, int nb, const int *npw_of, double2 *Cpart, int nsplit,
-                        hipStream_t st);
+                        const int *active, hipStream_t st);
 hipError_t launch_zproj_reduce(int nk, int M, int nb, int nsplit, const double2 *Cpart, const double *row_scale,
                                double gscale, double2 *C, hipStream_t st);
 // expand: Y[k*nb+v][G] += cscale * sum_m T_e[m0+m][G] C[k*c_kstride + m*nb + v]
 hipError_t launch_zexpand(const KPair *kp, int use_kq, int nk, const double2 *T, long t_stride, int m0, int M,
                           const double2 *C, long c_kstride, double cscale, double2 *Y, int ld, int nb,
-                          const int *npw_of, int npw_max, hipStream_t st);
+                          const int *npw_of, int npw_max, const int *active, hipStream_t st);
+// The `active` arguments (nullable) skip items, or 32-band tiles, whose flag is 0.
 // preconditioned CG (one workgroup per item)
 hipError_t launch_cg_init(const KPair *kp, int nb, int nitems, const double2 *B, double2 *Xv, double2 *R, double2 *P,
                           const double2 *AX, int have_x0, const double *diag, const double *eps, int ld,

@@ -27,11 +27,16 @@ constexpr int kPad = 1;     // LDS row padding (complex elements)
 __global__ void __launch_bounds__(256) k_zproj(const KPair *kp, int use_kq, const double2 *__restrict__ T,
                                                long t_stride, int m0, int M, const double2 *__restrict__ X, int ld,
                                                int nb, const int *__restrict__ npw_of, int nsplit,
-                                               double2 *__restrict__ Cpart, int nk) {
+                                               double2 *__restrict__ Cpart, int nk, const int *active) {
   __shared__ double2 At[kTile][kKb + kPad];
   __shared__ double2 Bt[kTile][kKb + kPad];
   const int k = blockIdx.z / nsplit;
   const int split = blockIdx.z - k * nsplit;
+  if (active) {  // skip tiles whose 32 bands are all converged (their outputs are not used)
+    const int v = blockIdx.y * kTile + (threadIdx.x & 31);
+    const int a = (threadIdx.x < 32 && v < nb) ? active[k * nb + v] : 0;
+    if (!__syncthreads_or(a)) return;
+  }
   const KPair P = kp[k];
   const int e = use_kq ? P.ej : P.ek;
   const int npw = npw_of[e];
@@ -96,10 +101,15 @@ __global__ void k_zproj_reduce(int total, int M, int nb, int nsplit, const doubl
 __global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, const double2 *__restrict__ T,
                                                  long t_stride, int m0, int M, const double2 *__restrict__ C,
                                                  long c_kstride, double cscale, double2 *__restrict__ Y, int ld,
-                                                 int nb, const int *__restrict__ npw_of) {
+                                                 int nb, const int *__restrict__ npw_of, const int *active) {
   __shared__ double2 Ct[32][kKb + kPad];   // [v][m]
   __shared__ double2 Tt[kKb][64 + kPad];   // [m][G]
   const int k = blockIdx.z;
+  if (active) {
+    const int v = blockIdx.y * 32 + (threadIdx.x & 31);
+    const int a = (threadIdx.x < 32 && v < nb) ? active[k * nb + v] : 0;
+    if (!__syncthreads_or(a)) return;
+  }
   const KPair P = kp[k];
   const int e = use_kq ? P.ej : P.ek;
   const int npw = npw_of[e];
@@ -364,10 +374,10 @@ __global__ void k_zscale_copy(long n, const double2 *a, double s, double2 *out) 
 
 hipError_t launch_zproj(const KPair *kp, int use_kq, int nk, const double2 *T, long t_stride, int m0, int M,
                         const double2 *X, int ld, int nb, const int *npw_of, double2 *Cpart, int nsplit,
-                        hipStream_t st) {
+                        const int *active, hipStream_t st) {
   dim3 grid((M + kTile - 1) / kTile, (nb + kTile - 1) / kTile, nk * nsplit);
   hipLaunchKernelGGL(k_zproj, grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, X, ld, nb, npw_of, nsplit,
-                     Cpart, nk);
+                     Cpart, nk, active);
   return hipGetLastError();
 }
 
@@ -381,10 +391,10 @@ hipError_t launch_zproj_reduce(int nk, int M, int nb, int nsplit, const double2 
 
 hipError_t launch_zexpand(const KPair *kp, int use_kq, int nk, const double2 *T, long t_stride, int m0, int M,
                           const double2 *C, long c_kstride, double cscale, double2 *Y, int ld, int nb,
-                          const int *npw_of, int npw_max, hipStream_t st) {
+                          const int *npw_of, int npw_max, const int *active, hipStream_t st) {
   dim3 grid((npw_max + 63) / 64, (nb + 31) / 32, nk);
   hipLaunchKernelGGL(k_zexpand, grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride, cscale, Y, ld,
-                     nb, npw_of);
+                     nb, npw_of, active);
   return hipGetLastError();
 }
 

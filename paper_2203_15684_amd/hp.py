@@ -86,8 +86,20 @@ _lib.hp_apply_h.restype = C.c_int32
 _lib.hp_solve_first_order.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_int32, _dp, C.POINTER(HpScfParams), _dp]
 _lib.hp_solve_first_order.restype = C.c_int32
 
+
+
+class HpKernelTime(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("calls", C.c_int64), ("total_ms", C.c_double)]
+
+
+_lib.hp_profile_start.argtypes = [C.c_void_p]
+_lib.hp_profile_start.restype = C.c_int32
+_lib.hp_profile_stop.argtypes = [C.c_void_p, C.POINTER(HpKernelTime), C.c_int32, C.POINTER(C.c_int32)]
+_lib.hp_profile_stop.restype = C.c_int32
+
 EXPORTED = ["hp_ground_state_load", "hp_sternheimer_scf", "hp_response_matrix", "hp_hubbard_params",
-            "hp_destroy", "hp_last_error", "hp_apply_h", "hp_solve_first_order"]
+            "hp_destroy", "hp_last_error", "hp_apply_h", "hp_solve_first_order", "hp_profile_start",
+            "hp_profile_stop"]
 
 
 def hp_last_error() -> str:
@@ -262,3 +274,15 @@ def hp_solve_first_order(ctx: Context, pert_site: int, q_frac, mesh_k: int, dv: 
     s = _check(_lib.hp_solve_first_order(ctx.handle, int(pert_site), _ptr(q), int(mesh_k), dvp, C.byref(p),
                                          _ptr(out.view(np.float64))))
     return out, s
+
+
+def hp_profile_start(ctx: Context) -> None:
+    _check(_lib.hp_profile_start(ctx.handle), allow_warn=False)
+
+
+def hp_profile_stop(ctx: Context) -> dict:
+    """{kernel name: (launches, summed GPU ms)} since hp_profile_start."""
+    out = (HpKernelTime * 32)()
+    n = C.c_int32(0)
+    _check(_lib.hp_profile_stop(ctx.handle, out, 32, C.byref(n)), allow_warn=False)
+    return {out[i].name.decode(): (int(out[i].calls), float(out[i].total_ms)) for i in range(n.value)}

@@ -638,6 +638,7 @@ def _solve_all(spec, at, vloc, rj, backend, device, tol, verbose, forced_gap_che
     nb = spec.n_occ + spec.n_guard
     entries = []
     solved = {}
+    last_full = None
     for i, k in enumerate(ks):
         ecut = spec.ecut * (1.0 + jit.get(_pair_key(k), 0.0))
         miller = sphere(at.cell, k, ecut, spec.fft)
@@ -670,8 +671,12 @@ def _solve_all(spec, at, vloc, rj, backend, device, tol, verbose, forced_gap_che
                 res = float(resid.max())
             else:
                 ham = _Ham(shell, vloc, k, miller, beta, d_kb, xp="torch", device=device)
-                X0 = _initial_guess(shell, vloc, k, miller, beta, d_kb, nb, spec)
+                if last_full is not None:
+                    X0 = _map_guess(last_full, miller)
+                else:
+                    X0 = _initial_guess(shell, vloc, k, miller, beta, d_kb, nb, spec)
                 eps_all, U, rn, nit = _lobpcg_torch(ham, X0, spec.n_occ + 1, tol, 400)
+                last_full = (miller, U)
                 res = float(rn[:spec.n_occ].max())
                 if verbose:
                     print(f"  k={k} npw={npw} lobpcg iters={nit} resid={res:.2e}", flush=True)
@@ -715,6 +720,18 @@ def _initial_guess(shell, vloc, k, miller, beta, d_kb, nb, spec):
     w, V = np.linalg.eigh(H)
     X = np.zeros((nb, miller.shape[0]), dtype=np.complex128)
     X[:, :nsub] = V[:, :nb].T
+    return X
+
+
+def _map_guess(last, miller):
+    """Previous k-point's states carried over plane wave by plane wave (Miller index match)."""
+    m_old, U_old = last
+    lut = {tuple(m): j for j, m in enumerate(m_old)}
+    X = np.zeros((U_old.shape[0], miller.shape[0]), dtype=np.complex128)
+    for j, m in enumerate(miller):
+        i = lut.get(tuple(m))
+        if i is not None:
+            X[:, j] = U_old[:, i]
     return X
 
 

@@ -1,0 +1,117 @@
+"""Parity at the full olivine-shaped size (28 atoms, 4 d sites, ~10^4 plane waves,
+FFT 72x45x40, 112 bands, k 2x3x4 + 24 extra k+q entries, q 1x2x2), in the launch
+configuration the benchmark uses (all mesh k x bands in one batch).
+
+The oracle cannot run the whole self-consistent response at this size in test
+time, so the checks are on outputs it computes one by one (H applies on sampled
+vectors and entries, one k-point's linear solve) and on properties that hold at
+any size (the GPU solution satisfies the oracle's Sternheimer equation, lies in
+the conduction manifold; chi is real symmetric after the q-sum; screening).
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+NAME = "olivine28"
+
+
+@functools.lru_cache(maxsize=None)
+def gs():
+    from synth import cache
+    return cache.get(NAME)
+
+
+@functools.lru_cache(maxsize=None)
+def ctx():
+    from paper_2203_15684_amd import hp
+    return hp.hp_ground_state_load(gs())
+
+
+@functools.lru_cache(maxsize=None)
+def orc():
+    return oracle.Oracle(gs(), cache_limit_bytes=1.0e9)
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def test_fullsize_shapes():
+    g = gs()
+    npw = [e.npw for e in g.kpts]
+    assert g.n_occ == 112 and g.n_hub == 4 and g.fft == (72, 45, 40)
+    assert 9500 <= min(npw) and max(npw) <= 10500
+    assert len(g.kpts) == 48 and g.n_mesh == 24
+    assert g.gap > 0.02
+
+
+@pytest.mark.parametrize("entry", [0, 13, 23, 24, 47])
+def test_fullsize_apply_h_sampled(entry):
+    from paper_2203_15684_amd import hp
+    e = gs().kpts[entry]
+    rng = np.random.default_rng(entry)
+    X = rng.standard_normal((3, e.npw)) + 1j * rng.standard_normal((3, e.npw))
+    X = np.vstack([X, e.u[[0, 57, 111]]])
+    Y = hp.hp_apply_h(ctx(), entry, X)
+    assert rel(Y, orc().h_apply(entry, X)) < 1e-13
+
+
+def test_fullsize_first_order_solve_one_k():
+    """One k-point (mesh index 7, q = (0, 1/2, 0): k+q is an extra entry) of the first SCF
+    iteration, all 112 bands: GPU solution against the oracle's CG solution."""
+    from paper_2203_15684_amd import hp
+    o = orc()
+    q = (0.0, 0.5, 0.0)
+    ik = 7
+    j, _ = o.kq_entry(ik, q)
+    p = hp.ScfParams(cg_tol=1e-12, max_cg_iter=2000)
+    du, st = hp.hp_solve_first_order(ctx(), 2, q, ik, None, p, gs().kpts[j].npw)
+    assert st == 0
+    b = o.rhs(ik, q, 2, None)
+    # the GPU solution solves the oracle's equation ...
+    r = o.sternheimer_op(ik, q, du) - b
+    assert np.linalg.norm(r, axis=1).max() / np.linalg.norm(b, axis=1).max() < 1e-10
+    # ... lies in the conduction manifold of k+q ...
+    U = gs().kpts[j].u
+    assert np.abs(du @ U.conj().T).max() < 1e-10 * np.abs(du).max()
+    # ... and equals the oracle's own solve
+    x_ref, _ = o.solve(ik, q, b, None, oracle.ScfParams(cg_tol=1e-12))
+    assert rel(du, x_ref) < 1e-9
+
+
+def test_fullsize_first_order_with_response_potential():
+    """Same k with a smooth random response potential on the grid (the Hxc part of the RHS)."""
+    from paper_2203_15684_amd import hp
+    o = orc()
+    q = (0.0, 0.0, 0.5)
+    ik = 3
+    j, _ = o.kq_entry(ik, q)
+    rng = np.random.default_rng(11)
+    dv = 0.01 * (rng.standard_normal(o.fft) + 1j * rng.standard_normal(o.fft))
+    p = hp.ScfParams(cg_tol=1e-12, max_cg_iter=2000)
+    du, st = hp.hp_solve_first_order(ctx(), 0, q, ik, dv, p, gs().kpts[j].npw)
+    assert st == 0
+    b = o.rhs(ik, q, 0, dv)
+    r = o.sternheimer_op(ik, q, du) - b
+    assert np.linalg.norm(r, axis=1).max() / np.linalg.norm(b, axis=1).max() < 1e-10
+
+
+def test_fullsize_response_matrix_properties():
+    """All 16 (site, q) SCF solves in the benchmark configuration: chi0 and chi real symmetric,
+    negative diagonal, screening |chi| < |chi0| on the diagonal, U > 0."""
+    from paper_2203_15684_amd import hp
+    p = hp.ScfParams(conv_thr_chi=1e-10, conv_thr_v=1e-8, cg_tol=1e-10, niter_max=100, max_cg_iter=2000)
+    chi0, chi, mim, st, status = hp.hp_response_matrix(ctx(), gs().qmesh, p)
+    assert status == 0
+    assert mim < 1e-8 * np.abs(chi).max()
+    assert np.abs(chi0 - chi0.T).max() < 1e-8 * np.abs(chi0).max()
+    assert np.abs(chi - chi.T).max() < 1e-6 * np.abs(chi).max()
+    d0, d = np.diag(chi0), np.diag(chi)
+    assert np.all(d0 < 0) and np.all(d < 0) and np.all(np.abs(d) < np.abs(d0))
+    uv = hp.hp_hubbard_params(chi0, chi)
+    assert np.all(np.diag(uv) > 0)

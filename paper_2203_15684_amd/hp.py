@@ -32,6 +32,13 @@ class HpError(RuntimeError):
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2203_15684_amd/build.py (hipcc, gfx950)")
+# One HIP runtime per process: PyTorch ships its own libamdhip64.so.7.  Loading it
+# first makes the library's dependency resolve to that same copy, so device memory
+# and streams from torch and from this library share one runtime.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = C.CDLL(LIB_PATH)
 
 _dp = C.POINTER(C.c_double)
@@ -180,6 +187,9 @@ def hp_ground_state_load(gs, stream: Optional[int] = None) -> Context:
                          int(mil.shape[0]), _ptr(mil, _ip), _ptr(eps), _ptr(u), _ptr(beta), _ptr(phi))
     vloc = _f64(gs.vloc)
     rho0 = _f64(gs.rho0)
+    nr = int(np.prod([int(x) for x in gs.fft]))
+    if vloc.size != nr or rho0.size != nr:
+        raise ValueError(f"v_loc/rho0 hold {vloc.size}/{rho0.size} values, the grid {tuple(gs.fft)} has {nr}")
     dkb = _f64(gs.d_kb)
     htau = _f64(gs.hub_tau)
     keep += [vloc, rho0, dkb, htau]

@@ -1,0 +1,80 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every
+declared symbol, validates arguments before any device call, and the host-only
+U/V inversion follows Eqs. 8-9."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_path():
+    return os.path.join(ROOT, "paper_2203_15684_amd", "libhp.so")
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hp.h")).read()
+    return sorted(set(re.findall(r"^(?:hp_status|void|const char \*)\s*\**\s*(hp_\w+)\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def hp():
+    if not os.path.exists(_lib_path()):
+        import __graft_entry__
+        __graft_entry__.build()
+    from paper_2203_15684_amd import hp
+    return hp
+
+
+def test_all_declared_symbols_exported(hp):
+    lib = ctypes.CDLL(_lib_path())
+    names = _declared()
+    assert {"hp_ground_state_load", "hp_sternheimer_scf", "hp_response_matrix", "hp_hubbard_params",
+            "hp_destroy", "hp_last_error"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(hp.EXPORTED)
+
+
+def test_hubbard_params_host(hp):
+    chi0 = np.array([[-2.0, 0.3, 0.1], [0.3, -1.7, 0.2], [0.1, 0.2, -2.2]])
+    chi = np.array([[-1.5, 0.2, 0.05], [0.2, -1.4, 0.1], [0.05, 0.1, -1.6]])
+    uv = hp.hp_hubbard_params(chi0, chi)
+    np.testing.assert_allclose(uv, np.linalg.inv(chi0) - np.linalg.inv(chi), atol=1e-14)
+
+
+def test_hubbard_params_errors(hp):
+    with pytest.raises(hp.HpError) as e:
+        hp.hp_hubbard_params(np.array([[1.0, 2.0], [2.0, 4.0]]), np.eye(2))
+    assert e.value.status == hp.HP_ERR_SINGULAR
+    with pytest.raises(hp.HpError) as e:
+        hp.hp_hubbard_params(np.array([[np.nan]]), np.eye(1))
+    assert e.value.status == hp.HP_ERR_NUMERIC
+
+
+def test_load_validation_runs_before_device(hp):
+    import copy
+    from conftest import ground_state
+    gs = ground_state("sc1_gamma")
+    for field, val, code in [("spin_factor", 1, hp.HP_ERR_ARG), ("n_occ", 0, hp.HP_ERR_ARG),
+                             ("fft", (24, 24, 7), hp.HP_ERR_SHAPE), ("fft", (24, 24, 10), hp.HP_ERR_SHAPE)]:
+        g = copy.copy(gs)
+        setattr(g, field, val)
+        if field == "fft":  # grid arrays consistent with the (too small) grid
+            g.vloc = np.ascontiguousarray(gs.vloc[:, :, :val[2]])
+            g.rho0 = np.ascontiguousarray(gs.rho0[:, :, :val[2]])
+        with pytest.raises(hp.HpError) as e:
+            hp.hp_ground_state_load(g)
+        assert e.value.status == code, (field, val, e.value)
+    g = copy.deepcopy(gs)
+    g.kpts[0].eps[3] = np.nan
+    with pytest.raises(hp.HpError) as e:
+        hp.hp_ground_state_load(g)
+    assert e.value.status == hp.HP_ERR_NUMERIC
+
+
+def test_last_error_is_a_string(hp):
+    assert isinstance(hp.hp_last_error(), str)

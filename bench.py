@@ -8,8 +8,13 @@ U/V inversion (Eqs. 8-9).  The default workload is the olivine-shaped cell
 (28 atoms, 4 d sites, ~10^4 plane waves, FFT 72x45x40, 112 bands, k 2x3x4,
 q 1x2x2).  Inputs are generated once and are resident in HBM before timing.
 
-Prints one JSON line: value = single-band H applications per second over the
-timed steps (whole job), ms_per_step = Sternheimer SCF wall time of one step.
+Both forms run in the same invocation on the same resident inputs: the
+mixed-precision batched form (FP32 FFTs and FP32 MFMA projections inside the PCG,
+FP64 residual refinement, FP64 orthogonalization, scalars, chi and inversion) and
+the plain FP64 form.  Prints one JSON line: value = single-band H applications per
+second of the --precision form over its timed steps (whole job), ms_per_step = its
+Sternheimer SCF wall time per step; "forms" holds both forms, and the chi / U,V
+difference of the mixed form against the FP64 form is reported.
 """
 import argparse
 import hashlib
@@ -24,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Sternheimer SCF wall time + Hψ applies/s, mixed-batched vs FP64, at χ err"
 HA_EV = 27.211386245988
-PEAK = {"fp64_vector": 78.6e12, "fp64_mfma": 78.6e12, "hbm": 8.0e12}
+PEAK = {"fp64_vector": 78.6e12, "fp64_mfma": 78.6e12, "fp32_vector": 157.3e12, "fp32_mfma": 157.3e12, "hbm": 8.0e12}
 
 
 def parse():
@@ -33,7 +38,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="olivine28")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--cg-tol", type=float, default=1e-10)
     ap.add_argument("--conv-thr-chi", type=float, default=1e-10)
     ap.add_argument("--conv-thr-v", type=float, default=1e-8)
@@ -77,6 +83,7 @@ def source_hash(files):
 
 
 def roofline(gs, prof, nq_list, h_applies):
+    """h_applies: single-band applies of the precision the dominant kernel runs in."""
     """Roofline record of the kernel with the largest measured GPU time.
 
     Every H apply of the batched CG launches the operator kernels once over all
@@ -90,17 +97,22 @@ def roofline(gs, prof, nq_list, h_applies):
     nb = gs.n_occ
     items_per_launch = h_applies / max(calls, 1)
     ej_all = [j for q in nq_list for j in kq_entries(gs, np.array(q))]
-    if name == "plane_vloc":
+    lowp = name.endswith("32")
+    base = name[:-2] if lowp else name
+    bytes_c = 8.0 if lowp else 16.0
+    if base == "plane_vloc":
         per_item = float(np.mean([plane_flops(gs, j) for j in ej_all])) * n3
-        rec = {"bound": "alu", "achieved": per_item * items_per_launch / avg_s / 1e12,
-               "peak": PEAK["fp64_vector"] / 1e12, "unit": "TFLOP/s"}
-    elif name in ("zproj", "zexpand"):
+        peak = PEAK["fp32_vector" if lowp else "fp64_vector"]
+        rec = {"bound": "alu", "achieved": per_item * items_per_launch / avg_s / 1e12, "peak": peak / 1e12,
+               "unit": "TFLOP/s"}
+    elif base in ("zproj", "zexpand"):
         m = gs.n_beta + gs.n_occ
         per_item = float(np.mean([8.0 * m * gs.kpts[j].npw for j in ej_all]))
-        rec = {"bound": "mfma", "achieved": per_item * items_per_launch / avg_s / 1e12,
-               "peak": PEAK["fp64_mfma"] / 1e12, "unit": "TFLOP/s"}
+        peak = PEAK["fp32_mfma" if lowp else "fp64_mfma"]
+        rec = {"bound": "mfma", "achieved": per_item * items_per_launch / avg_s / 1e12, "peak": peak / 1e12,
+               "unit": "TFLOP/s"}
     else:
-        per_item = float(np.mean([16.0 * 3 * gs.kpts[j].npw for j in ej_all]))
+        per_item = float(np.mean([bytes_c * 3 * gs.kpts[j].npw for j in ej_all]))
         rec = {"bound": "hbm", "achieved": per_item * items_per_launch / avg_s / 1e9,
                "peak": PEAK["hbm"] / 1e9, "unit": "GB/s"}
     rec["frac"] = rec["achieved"] / rec["peak"]
@@ -158,50 +170,81 @@ def main():
     gs = cache.get(args.config)
     t_gen = time.time() - t0
     ctx = hp.hp_ground_state_load(gs)
-    prec = hp.HP_FP64 if args.precision == "fp64" else hp.HP_MIXED
-    p = hp.ScfParams(conv_thr_chi=args.conv_thr_chi, conv_thr_v=args.conv_thr_v, cg_tol=args.cg_tol,
-                     niter_max=100, max_cg_iter=2000, precision=prec)
     nq = gs.qmesh
     nq_list = [tuple(q) for q in gs.qpoints()]
 
-    def step():
+    def params(prec):
+        return hp.ScfParams(conv_thr_chi=args.conv_thr_chi, conv_thr_v=args.conv_thr_v, cg_tol=args.cg_tol,
+                            niter_max=100, max_cg_iter=2000, inner_tol=args.inner_tol,
+                            precision=hp.HP_FP64 if prec == "fp64" else hp.HP_MIXED)
+
+    def step(p):
         chi0, chi, mim, st, status = hp.hp_response_matrix(ctx, nq, p)
         uv = hp.hp_hubbard_params(chi0, chi)
         return chi0, chi, uv, st, status
 
+    def timed(prec, steps):
+        p = params(prec)
+        torch.cuda.synchronize()
+        hp.hp_profile_start(ctx)
+        t_start = time.perf_counter()
+        res = [step(p) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t_start
+        prof = hp.hp_profile_stop(ctx)
+        return t, res, prof
+
+    forms = [args.precision] + [f for f in ("mixed", "fp64") if f != args.precision]
     for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    hp.hp_profile_start(ctx)
-    t_start = time.perf_counter()
-    results = []
-    for _ in range(args.steps):
-        results.append(step())
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    prof = hp.hp_profile_stop(ctx)
+        step(params(args.precision))
+    runs = {}
+    for f in forms:
+        runs[f] = timed(f, args.steps if f == args.precision else 1)
+    t_total, results, prof = runs[args.precision]
     chi0, chi, uv, st, status = results[-1]
-    happ = sum(r[3]["h_applies_fp64"] + r[3]["h_applies_lowp"] for r in results)
-    value = happ / t_total
-    rec = roofline(gs, prof, nq_list, happ)
+    h64 = sum(r[3]["h_applies_fp64"] for r in results)
+    h32 = sum(r[3]["h_applies_lowp"] for r in results)
+    value = (h64 + h32) / t_total
+    dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    rec = roofline(gs, prof, nq_list, h32 if dom.endswith("32") else h64)
+    summary = {}
+    for f, (t, res, pr) in runs.items():
+        c0, c1, u, s_, stat = res[-1]
+        a64 = sum(r[3]["h_applies_fp64"] for r in res)
+        a32 = sum(r[3]["h_applies_lowp"] for r in res)
+        d = max(pr.items(), key=lambda kv: kv[1][1])[0]
+        summary[f] = {"scf_wall_s_per_step": t / len(res), "hpsi_per_s": (a64 + a32) / t,
+                      "h_applies_fp64": a64 / len(res), "h_applies_fp32": a32 / len(res),
+                      "scf_iters": s_["scf_iters"], "cg_iters": s_["cg_iters"], "status": stat,
+                      "kernel_ms": {k: round(v[1], 1) for k, v in pr.items() if v[0]},
+                      "roofline": roofline(gs, pr, nq_list, a32 if d.endswith("32") else a64)}
+    chi_err = None
+    uv_err_mev = None
+    if "fp64" in runs and "mixed" in runs:
+        r64, rmx = runs["fp64"][1][-1], runs["mixed"][1][-1]
+        chi_err = max(float(np.abs(rmx[0] - r64[0]).max() / np.abs(r64[0]).max()),
+                      float(np.abs(rmx[1] - r64[1]).max() / np.abs(r64[1]).max()))
+        uv_err_mev = float(np.abs(rmx[2] - r64[2]).max() * HA_EV * 1e3)
     npws = [e.npw for e in gs.kpts]
     out = {
         "metric": METRIC, "value": value, "unit": "Hpsi/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": t_total / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == hp.HP_FP64 else "f64+f32",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": f"{gs.spec.name}: olivine-shaped cell {gs.spec.cell} bohr, {gs.spec.n_atoms} atoms, "
                                f"{gs.n_hub} d sites, {gs.n_occ} bands, FFT {'x'.join(map(str, gs.fft))}, "
                                f"k {'x'.join(map(str, gs.kmesh))}, q {'x'.join(map(str, gs.qmesh))}",
                    "npw_min": min(npws), "npw_max": max(npws), "k_entries": len(npws),
                    "precision": args.precision, "cg_tol": args.cg_tol, "conv_thr_chi": args.conv_thr_chi,
-                   "conv_thr_v": args.conv_thr_v, "site_q_pairs": gs.n_hub * len(nq_list)},
-        "scf": {"status": status, "scf_iters": st["scf_iters"], "cg_iters": st["cg_iters"],
-                "h_applies": happ / args.steps, "stage_s": st["stage_s"][:5],
-                "max_imag_chi": None},
-        "chi0_diag": [float(x) for x in np.diag(chi0)], "chi_diag": [float(x) for x in np.diag(chi)],
-        "U_eV": [float(x) * HA_EV for x in np.diag(uv)],
-        "kernel_ms": {k: round(v[1], 3) for k, v in prof.items()},
+                   "conv_thr_v": args.conv_thr_v, "inner_tol": args.inner_tol,
+                   "site_q_pairs": gs.n_hub * len(nq_list)},
+        "chi_rel_err_mixed_vs_fp64": chi_err, "uv_err_meV_mixed_vs_fp64": uv_err_mev,
+        "speedup_mixed_vs_fp64": (runs["fp64"][0] / len(runs["fp64"][1])) / (runs["mixed"][0] / len(runs["mixed"][1]))
+        if ("fp64" in runs and "mixed" in runs) else None,
+        "forms": summary,
+        "chi0_diag": [float(x) for x in np.diag(chi0)[:gs.n_hub]],
+        "chi_diag": [float(x) for x in np.diag(chi)[:gs.n_hub]],
+        "U_eV": [float(x) * HA_EV for x in np.diag(uv)[:gs.n_hub]],
         "roofline": rec,
         "setup_s": {"ground_state": round(t_gen, 1)},
     }

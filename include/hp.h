@@ -110,6 +110,8 @@ typedef struct hp_scf_params {
   int32_t max_cg_iter;    /* CG iteration limit per solve                          */
   int32_t precision;      /* HP_FP64 or HP_MIXED                                   */
   int32_t verbosity;      /* 0 silent, 1 one line per SCF iteration on stderr      */
+  double inner_tol;       /* HP_MIXED: relative tolerance of each FP32 inner solve */
+  int32_t max_refine;     /* HP_MIXED: FP64 refinement rounds per solve (>= 1)      */
 } hp_scf_params;
 
 /* Statistics of one call (all fields written when the pointer is not NULL). */

@@ -20,117 +20,168 @@ constexpr int kThreads = 256;
 constexpr int kStickChunk = 32;  // sticks per workgroup in the z-DFT kernels
 constexpr int kMaxPerThread = 40;  // plane elements per thread kept in registers
 
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+// Complex helpers for double2 (FP64 path) and float2 (FP32 path).
+template <class C>
+__device__ __forceinline__ C mkc(double x, double y);
+template <>
+__device__ __forceinline__ double2 mkc<double2>(double x, double y) {
+  return make_double2(x, y);
 }
-__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
-  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+template <>
+__device__ __forceinline__ float2 mkc<float2>(double x, double y) {
+  return make_float2((float)x, (float)y);
 }
-__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+template <class C>
+__device__ __forceinline__ C czero() {
+  C r;
+  r.x = 0;
+  r.y = 0;
+  return r;
+}
+template <class C>
+__device__ __forceinline__ C cadd(C a, C b) {
+  a.x += b.x;
+  a.y += b.y;
+  return a;
+}
+template <class C>
+__device__ __forceinline__ C csub(C a, C b) {
+  a.x -= b.x;
+  a.y -= b.y;
+  return a;
+}
+template <class C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <class C>
+__device__ __forceinline__ C cmulc(C a, C b) {  // a * conj(b)
+  C r;
+  r.x = a.x * b.x + a.y * b.y;
+  r.y = a.y * b.x - a.x * b.y;
+  return r;
+}
+template <class C, class S>
+__device__ __forceinline__ C cscale(C a, S s) {
+  using R = decltype(a.x);
+  a.x *= (R)s;
+  a.y *= (R)s;
+  return a;
+}
 // multiply by sign * i
-__device__ __forceinline__ double2 cmul_si(double2 a, double sign) { return make_double2(-sign * a.y, sign * a.x); }
+template <class C, class S>
+__device__ __forceinline__ C cmul_si(C a, S sign) {
+  using R = decltype(a.x);
+  C r;
+  r.x = -(R)sign * a.y;
+  r.y = (R)sign * a.x;
+  return r;
+}
 
 // y_t = sum_u x_u exp(sign 2 pi i u t / R), in registers.
-template <int R>
-__device__ __forceinline__ void dft_small(double2 *x, double sign);
-
-template <>
-__device__ __forceinline__ void dft_small<2>(double2 *x, double) {
-  double2 a = x[0], b = x[1];
-  x[0] = cadd(a, b);
-  x[1] = csub(a, b);
-}
-
-template <>
-__device__ __forceinline__ void dft_small<3>(double2 *x, double sign) {
-  const double h = 0.86602540378443864676;  // sqrt(3)/2
-  double2 s = cadd(x[1], x[2]);
-  double2 d = csub(x[1], x[2]);
-  double2 m = make_double2(x[0].x - 0.5 * s.x, x[0].y - 0.5 * s.y);
-  double2 t = cmul_si(cscale(d, h), sign);
-  x[0] = cadd(x[0], s);
-  x[1] = cadd(m, t);
-  x[2] = csub(m, t);
-}
-
-template <>
-__device__ __forceinline__ void dft_small<4>(double2 *x, double sign) {
-  double2 a0 = cadd(x[0], x[2]), a1 = csub(x[0], x[2]);
-  double2 b0 = cadd(x[1], x[3]), b1 = cmul_si(csub(x[1], x[3]), sign);
-  x[0] = cadd(a0, b0);
-  x[2] = csub(a0, b0);
-  x[1] = cadd(a1, b1);
-  x[3] = csub(a1, b1);
-}
-
-template <>
-__device__ __forceinline__ void dft_small<5>(double2 *x, double sign) {
-  const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
-  const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
-  double2 a1 = cadd(x[1], x[4]), b1 = csub(x[1], x[4]);
-  double2 a2 = cadd(x[2], x[3]), b2 = csub(x[2], x[3]);
-  double2 x0 = x[0];
-  double2 r1 = make_double2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
-  double2 r2 = make_double2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
-  double2 i1 = cmul_si(make_double2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y), sign);
-  double2 i2 = cmul_si(make_double2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y), sign);
-  x[0] = make_double2(x0.x + a1.x + a2.x, x0.y + a1.y + a2.y);
-  x[1] = cadd(r1, i1);
-  x[4] = csub(r1, i1);
-  x[2] = cadd(r2, i2);
-  x[3] = csub(r2, i2);
-}
-
-template <>
-__device__ __forceinline__ void dft_small<8>(double2 *x, double sign) {
-  const double r = 0.70710678118654752440;
-  double2 e[4] = {x[0], x[2], x[4], x[6]};
-  double2 o[4] = {x[1], x[3], x[5], x[7]};
-  dft_small<4>(e, sign);
-  dft_small<4>(o, sign);
-  // o_t *= W8^t, W8 = exp(sign 2 pi i / 8)
-  o[1] = make_double2(r * (o[1].x - sign * o[1].y), r * (o[1].y + sign * o[1].x));
-  o[2] = cmul_si(o[2], sign);
-  o[3] = make_double2(r * (-o[3].x - sign * o[3].y), r * (-o[3].y + sign * o[3].x));
-  for (int t = 0; t < 4; ++t) {
-    x[t] = cadd(e[t], o[t]);
-    x[t + 4] = csub(e[t], o[t]);
-  }
-}
-
-template <>
-__device__ __forceinline__ void dft_small<9>(double2 *x, double sign) {
-  // 9 = 3 x 3: DFT3 over each residue class b of u = 3a + b, twiddle W9^{bc}, DFT3 over b.
-  const double c1 = 0.76604444311897803520, s1 = 0.64278760968653932632;  // cos, sin 2pi/9
-  const double c2 = 0.17364817766693034885, s2 = 0.98480775301220805936;  // cos, sin 4pi/9
-  const double c4 = -0.93969262078590838405, s4 = 0.34202014332566873304;  // cos, sin 8pi/9
-  double2 y[3][3];
+template <int RDX, class C>
+__device__ __forceinline__ void dft_small(C *x, double sign_d) {
+  using R = decltype(x[0].x);
+  const R sign = (R)sign_d;
+  if constexpr (RDX == 2) {
+    C a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  } else if constexpr (RDX == 3) {
+    const R h = (R)0.86602540378443864676;  // sqrt(3)/2
+    C s = cadd(x[1], x[2]);
+    C d = csub(x[1], x[2]);
+    C m;
+    m.x = x[0].x - (R)0.5 * s.x;
+    m.y = x[0].y - (R)0.5 * s.y;
+    C t = cmul_si(cscale(d, h), sign);
+    x[0] = cadd(x[0], s);
+    x[1] = cadd(m, t);
+    x[2] = csub(m, t);
+  } else if constexpr (RDX == 4) {
+    C a0 = cadd(x[0], x[2]), a1 = csub(x[0], x[2]);
+    C b0 = cadd(x[1], x[3]), b1 = cmul_si(csub(x[1], x[3]), sign);
+    x[0] = cadd(a0, b0);
+    x[2] = csub(a0, b0);
+    x[1] = cadd(a1, b1);
+    x[3] = csub(a1, b1);
+  } else if constexpr (RDX == 5) {
+    const R c1 = (R)0.30901699437494742410, c2 = (R)-0.80901699437494742410;
+    const R s1 = (R)0.95105651629515357212, s2 = (R)0.58778525229247312917;
+    C a1 = cadd(x[1], x[4]), b1 = csub(x[1], x[4]);
+    C a2 = cadd(x[2], x[3]), b2 = csub(x[2], x[3]);
+    C x0 = x[0];
+    C r1, r2, u1, u2;
+    r1.x = x0.x + c1 * a1.x + c2 * a2.x;
+    r1.y = x0.y + c1 * a1.y + c2 * a2.y;
+    r2.x = x0.x + c2 * a1.x + c1 * a2.x;
+    r2.y = x0.y + c2 * a1.y + c1 * a2.y;
+    u1.x = s1 * b1.x + s2 * b2.x;
+    u1.y = s1 * b1.y + s2 * b2.y;
+    u2.x = s2 * b1.x - s1 * b2.x;
+    u2.y = s2 * b1.y - s1 * b2.y;
+    C i1 = cmul_si(u1, sign), i2 = cmul_si(u2, sign);
+    x[0].x = x0.x + a1.x + a2.x;
+    x[0].y = x0.y + a1.y + a2.y;
+    x[1] = cadd(r1, i1);
+    x[4] = csub(r1, i1);
+    x[2] = cadd(r2, i2);
+    x[3] = csub(r2, i2);
+  } else if constexpr (RDX == 8) {
+    const R r = (R)0.70710678118654752440;
+    C e[4] = {x[0], x[2], x[4], x[6]};
+    C o[4] = {x[1], x[3], x[5], x[7]};
+    dft_small<4>(e, sign_d);
+    dft_small<4>(o, sign_d);
+    // o_t *= W8^t, W8 = exp(sign 2 pi i / 8)
+    C t1, t3;
+    t1.x = r * (o[1].x - sign * o[1].y);
+    t1.y = r * (o[1].y + sign * o[1].x);
+    t3.x = r * (-o[3].x - sign * o[3].y);
+    t3.y = r * (-o[3].y + sign * o[3].x);
+    o[1] = t1;
+    o[2] = cmul_si(o[2], sign);
+    o[3] = t3;
 #pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    double2 t[3] = {x[b], x[b + 3], x[b + 6]};
-    dft_small<3>(t, sign);
-    y[b][0] = t[0];
-    y[b][1] = t[1];
-    y[b][2] = t[2];
-  }
-  const double2 w1 = make_double2(c1, sign * s1), w2 = make_double2(c2, sign * s2), w4 = make_double2(c4, sign * s4);
-  y[1][1] = cmul(y[1][1], w1);
-  y[1][2] = cmul(y[1][2], w2);
-  y[2][1] = cmul(y[2][1], w2);
-  y[2][2] = cmul(y[2][2], w4);
+    for (int t = 0; t < 4; ++t) {
+      x[t] = cadd(e[t], o[t]);
+      x[t + 4] = csub(e[t], o[t]);
+    }
+  } else if constexpr (RDX == 9) {
+    // 9 = 3 x 3: DFT3 over each residue class b of u = 3a + b, twiddle W9^{bc}, DFT3 over b.
+    const double c1 = 0.76604444311897803520, s1 = 0.64278760968653932632;   // 2 pi / 9
+    const double c2 = 0.17364817766693034885, s2 = 0.98480775301220805936;   // 4 pi / 9
+    const double c4 = -0.93969262078590838405, s4 = 0.34202014332566873304;  // 8 pi / 9
+    C y[3][3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    double2 t[3] = {y[0][c], y[1][c], y[2][c]};
-    dft_small<3>(t, sign);
-    x[c] = t[0];
-    x[c + 3] = t[1];
-    x[c + 6] = t[2];
+    for (int b = 0; b < 3; ++b) {
+      C t[3] = {x[b], x[b + 3], x[b + 6]};
+      dft_small<3>(t, sign_d);
+      y[b][0] = t[0];
+      y[b][1] = t[1];
+      y[b][2] = t[2];
+    }
+    const C w1 = mkc<C>(c1, sign_d * s1), w2 = mkc<C>(c2, sign_d * s2), w4 = mkc<C>(c4, sign_d * s4);
+    y[1][1] = cmul(y[1][1], w1);
+    y[1][2] = cmul(y[1][2], w2);
+    y[2][1] = cmul(y[2][1], w2);
+    y[2][2] = cmul(y[2][2], w4);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      C t[3] = {y[0][c], y[1][c], y[2][c]};
+      dft_small<3>(t, sign_d);
+      x[c] = t[0];
+      x[c + 3] = t[1];
+      x[c + 6] = t[2];
+    }
   }
 }
 
-__device__ __forceinline__ void dft_any(double2 *x, int R, double sign) {
+template <class C>
+__device__ __forceinline__ void dft_any(C *x, int R, double sign) {
   switch (R) {
     case 2: dft_small<2>(x, sign); break;
     case 3: dft_small<3>(x, sign); break;
@@ -146,9 +197,9 @@ __device__ __forceinline__ void dft_any(double2 *x, int R, double sign) {
 // starts at base_i = b0[i] (or i * bstride when b0 == nullptr) with element
 // stride es.  dif = true: butterfly then twiddle, sign +1; dif = false: conjugate
 // twiddle then butterfly with sign -1 (the inverse-order stage).
-__device__ __forceinline__ void fft_stage(double2 *P, int nlines, const int *lines, int lmul, int lmod,
-                                          int lshift, int lstride, int es, int N, int R, int L,
-                                          const double2 *tw, bool dif) {
+template <class C>
+__device__ __forceinline__ void fft_stage(C *P, int nlines, const int *lines, int lmul, int lmod, int lshift,
+                                          int lstride, int es, int N, int R, int L, const C *tw, bool dif) {
   const int nb = N / R;
   const int B = R * L;
   const int tstep = N / B;
@@ -169,19 +220,13 @@ __device__ __forceinline__ void fft_stage(double2 *P, int nlines, const int *lin
     }
     const int base = lb + (blk * B + j) * es;
     const int step = L * es;
-    double2 x[9];
+    C x[9];
     for (int t = 0; t < R; ++t) x[t] = P[base + t * step];
     if (dif) {
       dft_any(x, R, sign);
-      for (int t = 1; t < R; ++t) {
-        double2 w_ = tw[(j * t * tstep) % N];
-        x[t] = cmul(x[t], w_);
-      }
+      for (int t = 1; t < R; ++t) x[t] = cmul(x[t], tw[(j * t * tstep) % N]);
     } else {
-      for (int t = 1; t < R; ++t) {
-        double2 w_ = tw[(j * t * tstep) % N];
-        x[t] = cmulc(x[t], w_);
-      }
+      for (int t = 1; t < R; ++t) x[t] = cmulc(x[t], tw[(j * t * tstep) % N]);
       dft_any(x, R, sign);
     }
     for (int t = 0; t < R; ++t) P[base + t * step] = x[t];
@@ -189,16 +234,17 @@ __device__ __forceinline__ void fft_stage(double2 *P, int nlines, const int *lin
 }
 
 // Full transform of a set of lines: decimation in frequency (dif) or its reverse.
-__device__ __forceinline__ void fft_lines(double2 *P, const Axis &a, int nlines, const int *lines, int lmul,
+template <class C>
+__device__ __forceinline__ void fft_lines(C *P, const C *tw, const Axis &a, int nlines, const int *lines, int lmul,
                                           int lmod, int lshift, int lstride, int es, bool dif) {
   if (dif) {
     for (int s = 0; s < a.nst; ++s) {
-      fft_stage(P, nlines, lines, lmul, lmod, lshift, lstride, es, a.n, a.rad[s], a.span[s], a.tw, true);
+      fft_stage(P, nlines, lines, lmul, lmod, lshift, lstride, es, a.n, a.rad[s], a.span[s], tw, true);
       __syncthreads();
     }
   } else {
     for (int s = a.nst - 1; s >= 0; --s) {
-      fft_stage(P, nlines, lines, lmul, lmod, lshift, lstride, es, a.n, a.rad[s], a.span[s], a.tw, false);
+      fft_stage(P, nlines, lines, lmul, lmod, lshift, lstride, es, a.n, a.rad[s], a.span[s], tw, false);
       __syncthreads();
     }
   }
@@ -209,8 +255,9 @@ __device__ __forceinline__ int wrap(int v, int n) {
   return v < 0 ? v + n : v;
 }
 
-__device__ __forceinline__ void plane_zero(double2 *P, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) P[i] = make_double2(0.0, 0.0);
+template <class C>
+__device__ __forceinline__ void plane_zero(C *P, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) P[i] = czero<C>();
 }
 
 __device__ __forceinline__ void basis_of(const KPair *kp, int k, int use_kq, int &e, int &g0x, int &g0y, int &g0z) {
@@ -268,9 +315,9 @@ struct BaseAffine {  // line l starts at l * stride
   __device__ __forceinline__ int operator()(int l) const { return l * stride; }
 };
 
-template <int N, int S, bool DIF, class BaseF>
-__device__ __forceinline__ void cstage(double2 *__restrict__ P, const double2 *__restrict__ tw, int nlines,
-                                       const BaseF &base, int es) {
+template <int N, int S, bool DIF, class BaseF, class C>
+__device__ __forceinline__ void cstage(C *__restrict__ P, const C *__restrict__ tw, int nlines, const BaseF &base,
+                                       int es) {
   constexpr int R = crad(N, S), L = cspan(N, S), B = R * L, NB = N / R, TSTEP = N / B;
   const int total = nlines * NB;
   for (int w = threadIdx.x; w < total; w += blockDim.x) {
@@ -279,7 +326,7 @@ __device__ __forceinline__ void cstage(double2 *__restrict__ P, const double2 *_
     const int blk = b / L;
     const int j = b - blk * L;
     const int o = base(line) + (blk * B + j) * es;
-    double2 x[R];
+    C x[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) x[t] = P[o + t * L * es];
     if constexpr (DIF) {
@@ -301,8 +348,8 @@ __device__ __forceinline__ void cstage(double2 *__restrict__ P, const double2 *_
   __syncthreads();
 }
 
-template <int N, bool DIF, int I, class BaseF>
-__device__ __forceinline__ void cfft(double2 *P, const double2 *tw, int nlines, const BaseF &base, int es) {
+template <int N, bool DIF, int I, class BaseF, class C>
+__device__ __forceinline__ void cfft(C *P, const C *tw, int nlines, const BaseF &base, int es) {
   constexpr int NS = cnst(N);
   static_assert(NS > 0, "FFT length must be a product of 2, 3 and 5");
   if constexpr (I < NS) {
@@ -312,26 +359,38 @@ __device__ __forceinline__ void cfft(double2 *P, const double2 *tw, int nlines, 
 }
 
 // Per-block plane context: LDS tables and the transforms of one xy plane.
-// N1 = N2 = 0 selects the runtime-size path.
-template <int N1, int N2>
+// N1 = N2 = 0 selects the runtime-size path; C is double2 (FP64) or float2 (FP32).
+template <class C>
+__device__ __forceinline__ const C *axis_tw(const Axis &a);
+template <>
+__device__ __forceinline__ const double2 *axis_tw<double2>(const Axis &a) {
+  return a.tw;
+}
+template <>
+__device__ __forceinline__ const float2 *axis_tw<float2>(const Axis &a) {
+  return a.tw32;
+}
+
+template <int N1, int N2, class C = double2>
 struct PlaneCtx {
   const Plane &pl;
-  double2 *P;      // [n1*n2]
-  double2 *twx;    // [n1] (LDS copy)
-  double2 *twy;    // [n2]
-  int *xs;         // [n1] active x columns, shifted and wrapped
+  C *P;      // [n1*n2]
+  C *twx;    // [n1] (LDS copy)
+  C *twy;    // [n2]
+  int *xs;   // [n1] active x columns, shifted and wrapped
   int nxa;
   __device__ __forceinline__ int n1() const { return N1 > 0 ? N1 : pl.n1; }
   __device__ __forceinline__ int n2() const { return N2 > 0 ? N2 : pl.n2; }
   __device__ __forceinline__ int np() const { return n1() * n2(); }
-  __device__ __forceinline__ PlaneCtx(const Plane &p, double2 *lds) : pl(p) {
-    P = lds;
+  __device__ __forceinline__ PlaneCtx(const Plane &p, void *lds) : pl(p) {
+    P = reinterpret_cast<C *>(lds);
     twx = P + np();
     twy = twx + n1();
     xs = reinterpret_cast<int *>(twy + n2());
     nxa = 0;
-    for (int i = threadIdx.x; i < n1(); i += blockDim.x) twx[i] = pl.ax.tw[i];
-    for (int i = threadIdx.x; i < n2(); i += blockDim.x) twy[i] = pl.ay.tw[i];
+    const C *tx = axis_tw<C>(pl.ax), *ty = axis_tw<C>(pl.ay);
+    for (int i = threadIdx.x; i < n1(); i += blockDim.x) twx[i] = tx[i];
+    for (int i = threadIdx.x; i < n2(); i += blockDim.x) twy[i] = ty[i];
   }
   // active x list of a stick set shifted by g0x (call from every thread; ends with a barrier)
   __device__ __forceinline__ void set_active(const int *xa, int n, int g0x) {
@@ -349,7 +408,7 @@ struct PlaneCtx {
     if constexpr (N2 > 0) {
       cfft<N2, DIF, 0>(P, twy, nxa, BaseList{xs, N2}, 1);
     } else {
-      fft_lines(P, pl.ay, nxa, xs, pl.n2, pl.n1, 0, 0, 1, DIF);
+      fft_lines(P, twy, pl.ay, nxa, xs, pl.n2, pl.n1, 0, 0, 1, DIF);
     }
   }
   template <bool DIF>
@@ -357,7 +416,7 @@ struct PlaneCtx {
     if constexpr (N1 > 0) {
       cfft<N1, DIF, 0>(P, twx, N2, BaseAffine{1}, N2);
     } else {
-      fft_lines(P, pl.ax, pl.n2, nullptr, 0, 1, 0, 1, pl.n2, DIF);
+      fft_lines(P, twx, pl.ax, pl.n2, nullptr, 0, 1, 0, 1, pl.n2, DIF);
     }
   }
   __device__ __forceinline__ int pos(int x, int y, int g0x, int g0y) const {
@@ -365,18 +424,22 @@ struct PlaneCtx {
   }
 };
 
-int plane_lds_t(const Plane &pl) {
-  return pl.n1 * pl.n2 * (int)sizeof(double2) + (pl.n1 + pl.n2) * (int)sizeof(double2) + pl.n1 * (int)sizeof(int);
+int plane_lds_t(const Plane &pl, int csize = (int)sizeof(double2)) {
+  return pl.n1 * pl.n2 * csize + (pl.n1 + pl.n2) * csize + pl.n1 * (int)sizeof(int);
 }
 
 // ----------------------------------------------------------------- kernels
 
-template <int N3>
+template <class C>
+using RealOf = decltype(C{}.x);
+
+template <int N3, class C>
 __global__ void __launch_bounds__(kThreads) k_stick_inv(Sticks sk, const KPair *kp, int use_kq, int nb,
-                                                        const double2 *__restrict__ X, int ld,
-                                                        double2 *__restrict__ S, int ns_pad, int n3_rt,
-                                                        const double2 *__restrict__ tw3, const int *active) {
-  extern __shared__ double2 smem[];
+                                                        const C *__restrict__ X, int ld, C *__restrict__ S,
+                                                        int ns_pad, int n3_rt, const C *__restrict__ tw3,
+                                                        const int *active) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *smem = reinterpret_cast<C *>(smem_raw);
   const int n3 = N3 > 0 ? N3 : n3_rt;
   const int item = blockIdx.y;
   if (active && !active[item]) return;
@@ -391,39 +454,41 @@ __global__ void __launch_bounds__(kThreads) k_stick_inv(Sticks sk, const KPair *
   const int *slen = sk.slen + E.st_off;
   const int p0 = sstart[s0];
   const int p1 = sstart[s1 - 1] + slen[s1 - 1];
-  double2 *tw = smem;             // [n3]
-  double2 *c = smem + n3;         // [p1 - p0]
+  C *tw = smem;          // [n3]
+  C *c = smem + n3;      // [p1 - p0]
   int *zi = reinterpret_cast<int *>(c + (p1 - p0));
   for (int i = threadIdx.x; i < n3; i += blockDim.x) tw[i] = tw3[i];
-  const double2 *x = X + (size_t)item * ld;
+  const C *x = X + (size_t)item * ld;
   for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
     c[p - p0] = x[p];
     zi[p - p0] = wrap(sk.iz[E.pw_off + p] - g0z, n3);
   }
   __syncthreads();
   const int nsc = s1 - s0;
-  double2 *out = S + (size_t)item * n3 * ns_pad;
+  C *out = S + (size_t)item * n3 * ns_pad;
   for (int idx = threadIdx.x; idx < nsc * n3; idx += blockDim.x) {
     const int z = idx / nsc;
     const int s = s0 + (idx - z * nsc);
     const int a = sstart[s] - p0;
     const int len = slen[s];
-    double2 acc = make_double2(0.0, 0.0);
+    C acc = czero<C>();
     for (int t = 0; t < len; ++t) acc = cadd(acc, cmul(c[a + t], tw[(zi[a + t] * z) % n3]));
     out[(size_t)z * ns_pad + s] = acc;
   }
 }
 
-template <int N3>
+template <int N3, class C>
 __global__ void __launch_bounds__(kThreads) k_stick_fwd(Sticks sk, const KPair *kp, int use_kq, int nb,
-                                                        const double2 *__restrict__ S, int ns_pad, int n3_rt,
-                                                        const double2 *__restrict__ tw3, double scale,
-                                                        double2 *__restrict__ Y, int ld, int mode,
+                                                        const C *__restrict__ S, int ns_pad, int n3_rt,
+                                                        const C *__restrict__ tw3, double scale,
+                                                        C *__restrict__ Y, int ld, int mode,
                                                         const double *__restrict__ kin,
                                                         const double *__restrict__ eps,
-                                                        const double2 *__restrict__ X, int eps_stride,
+                                                        const C *__restrict__ X, int eps_stride,
                                                         const int *active) {
-  extern __shared__ double2 smem[];
+  using R = RealOf<C>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *smem = reinterpret_cast<C *>(smem_raw);
   const int n3 = N3 > 0 ? N3 : n3_rt;
   const int item = blockIdx.y;
   if (active && !active[item]) return;
@@ -440,12 +505,12 @@ __global__ void __launch_bounds__(kThreads) k_stick_fwd(Sticks sk, const KPair *
   const int *slen = sk.slen + E.st_off;
   const int p0 = sstart[s0];
   const int p1 = sstart[s1 - 1] + slen[s1 - 1];
-  double2 *tw = smem;                                   // [n3]
-  double2 *sl = smem + n3;                              // [n3][nsc]
-  int *own = reinterpret_cast<int *>(sl + n3 * nsc);    // [p1-p0] stick of each plane wave
+  C *tw = smem;                                       // [n3]
+  C *sl = smem + n3;                                  // [n3][nsc]
+  int *own = reinterpret_cast<int *>(sl + n3 * nsc);  // [p1-p0] stick of each plane wave
   for (int i = threadIdx.x; i < n3; i += blockDim.x) tw[i] = tw3[i];
   if (S) {
-    const double2 *in = S + (size_t)item * n3 * ns_pad;
+    const C *in = S + (size_t)item * n3 * ns_pad;
     for (int idx = threadIdx.x; idx < nsc * n3; idx += blockDim.x) {
       const int z = idx / nsc;
       const int s = idx - z * nsc;
@@ -455,11 +520,11 @@ __global__ void __launch_bounds__(kThreads) k_stick_fwd(Sticks sk, const KPair *
   for (int s = s0 + threadIdx.x; s < s1; s += blockDim.x)
     for (int t = 0; t < slen[s]; ++t) own[sstart[s] - p0 + t] = s - s0;
   __syncthreads();
-  double2 *y = Y + (size_t)item * ld;
-  const double2 *x = X ? X + (size_t)item * ld : nullptr;
+  C *y = Y + (size_t)item * ld;
+  const C *x = X ? X + (size_t)item * ld : nullptr;
   const double ev = eps ? eps[(size_t)k * eps_stride + v] : 0.0;
   for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-    double2 acc = make_double2(0.0, 0.0);
+    C acc = czero<C>();
     if (S) {
       const int s = own[p - p0];
       const int zz = wrap(sk.iz[E.pw_off + p] - g0z, n3);
@@ -472,30 +537,31 @@ __global__ void __launch_bounds__(kThreads) k_stick_fwd(Sticks sk, const KPair *
       acc = cscale(acc, scale);
     }
     if (mode == 0) {
-      const double2 xv = x[p];
-      const double d = kin[E.pw_off + p] - ev;
-      acc = make_double2(acc.x + d * xv.x, acc.y + d * xv.y);
+      const C xv = x[p];
+      const R d = (R)(kin[E.pw_off + p] - ev);
+      acc.x += d * xv.x;
+      acc.y += d * xv.y;
     }
     y[p] = acc;
   }
 }
 
-template <int N1, int N2>
+template <int N1, int N2, class C>
 __global__ void __launch_bounds__(kThreads) k_plane_vloc(Plane pl, Sticks sk, const KPair *kp, int use_kq, int nb,
-                                                         const double2 *__restrict__ Sin,
-                                                         double2 *__restrict__ Sout, int ns_pad,
-                                                         const double *__restrict__ vp, const int *active) {
-  extern __shared__ double2 lds[];
+                                                         const C *__restrict__ Sin, C *__restrict__ Sout,
+                                                         int ns_pad, const RealOf<C> *__restrict__ vp,
+                                                         const int *active) {
+  extern __shared__ __align__(16) unsigned char lds[];
   const int item = blockIdx.y;
   if (active && !active[item]) return;
-  PlaneCtx<N1, N2> pc(pl, lds);
+  PlaneCtx<N1, N2, C> pc(pl, lds);
   const int z = blockIdx.x;
   const int k = item / nb;
   int e, g0x, g0y, g0z;
   basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
   const EntryDev E = sk.ent[e];
   const int np = pc.np();
-  double2 *P = pc.P;
+  C *P = pc.P;
   plane_zero(P, np);
   pc.set_active(sk.xa + E.xa_off, E.nxa, g0x);
   const int *sx = sk.sx + E.st_off;
@@ -505,7 +571,7 @@ __global__ void __launch_bounds__(kThreads) k_plane_vloc(Plane pl, Sticks sk, co
   __syncthreads();
   pc.template y_lines<true>();
   pc.template x_lines<true>();
-  const double *v = vp + (size_t)z * np;
+  const RealOf<C> *v = vp + (size_t)z * np;
   for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = cscale(P[i], v[i]);
   __syncthreads();
   pc.template x_lines<false>();
@@ -517,7 +583,7 @@ template <int N1, int N2>
 __global__ void __launch_bounds__(kThreads) k_plane_to_real(Plane pl, Sticks sk, const KPair *kp, int use_kq,
                                                             int nb, const double2 *__restrict__ Sin, int ns_pad,
                                                             double2 *__restrict__ R) {
-  extern __shared__ double2 lds[];
+  extern __shared__ __align__(16) unsigned char lds[];
   PlaneCtx<N1, N2> pc(pl, lds);
   const int z = blockIdx.x;
   const int item = blockIdx.y;
@@ -545,7 +611,7 @@ __global__ void __launch_bounds__(kThreads) k_plane_mul_fwd(Plane pl, Sticks sk,
                                                             const double2 *__restrict__ psi,
                                                             const double2 *__restrict__ dv,
                                                             double2 *__restrict__ Sout, int ns_pad) {
-  extern __shared__ double2 lds[];
+  extern __shared__ __align__(16) unsigned char lds[];
   PlaneCtx<N1, N2> pc(pl, lds);
   const int z = blockIdx.x;
   const int item = blockIdx.y;
@@ -572,7 +638,7 @@ __global__ void __launch_bounds__(kThreads) k_plane_drho(Plane pl, Sticks sk, co
                                                          const double2 *__restrict__ Sdu, int ns_pad,
                                                          const double2 *__restrict__ psi,
                                                          double2 *__restrict__ part) {
-  extern __shared__ double2 lds[];
+  extern __shared__ __align__(16) unsigned char lds[];
   PlaneCtx<N1, N2> pc(pl, lds);
   const int z = blockIdx.x;
   const int k = blockIdx.y;
@@ -630,7 +696,7 @@ __global__ void k_drho_reduce(const KPair *kp, int nk, const double2 *__restrict
 template <int N1, int N2>
 __global__ void __launch_bounds__(kThreads) k_hxc_planes_fwd(Plane pl, const double2 *__restrict__ drho,
                                                              double2 *__restrict__ tmp) {
-  extern __shared__ double2 lds[];
+  extern __shared__ __align__(16) unsigned char lds[];
   PlaneCtx<N1, N2> pc(pl, lds);
   const int z = blockIdx.x;
   const int np = pc.np();
@@ -655,7 +721,7 @@ __global__ void k_hxc_columns(Plane pl, const double2 *__restrict__ tw3, const d
   const int cols = blockDim.x;
   const int c0 = blockIdx.x * cols;
   const int c = c0 + threadIdx.x;
-  double2 *a = sm;               // [n3][cols]
+  double2 *a = sm;               // [n3][cols] 
   double2 *f = sm + n3 * cols;   // [n3][cols]
   if (c < np)
     for (int z = 0; z < n3; ++z) a[z * cols + threadIdx.x] = tmp[(size_t)z * np + c];
@@ -688,7 +754,7 @@ __global__ void __launch_bounds__(kThreads) k_hxc_planes_inv(Plane pl, const dou
                                                              const double *__restrict__ fxc,
                                                              const double2 *__restrict__ drho,
                                                              double2 *__restrict__ dvout) {
-  extern __shared__ double2 lds[];
+  extern __shared__ __align__(16) unsigned char lds[];
   PlaneCtx<N1, N2> pc(pl, lds);
   const int z = blockIdx.x;
   const int np = pc.np();
@@ -765,55 +831,91 @@ __global__ void k_fxc(const double *__restrict__ rho, double *__restrict__ fxc, 
 // ---------------------------------------------------------------- launchers
 
 // Grid sizes with compile-time transforms; other sizes take the runtime path.
-#define HP_PLANE_DISPATCH(KERNEL, GRID, LDS, ST, ...)                                                   \
-  do {                                                                                                 \
-    const int key_ = pl.n1 * 1000 + pl.n2;                                                            \
-    switch (key_) {                                                                                    \
-      case 24024: hipLaunchKernelGGL((KERNEL<24, 24>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break; \
-      case 30024: hipLaunchKernelGGL((KERNEL<30, 24>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break; \
-      case 48024: hipLaunchKernelGGL((KERNEL<48, 24>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break; \
-      case 48048: hipLaunchKernelGGL((KERNEL<48, 48>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break; \
-      case 72045: hipLaunchKernelGGL((KERNEL<72, 45>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break; \
-      case 144045: hipLaunchKernelGGL((KERNEL<144, 45>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break; \
-      default: hipLaunchKernelGGL((KERNEL<0, 0>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;      \
-    }                                                                                                  \
+#define COMMA ,
+#define HP_PLANE_DISPATCH_T(KERNEL, CT, GRID, LDS, ST, ...)                                                   \
+  do {                                                                                                       \
+    const int key_ = pl.n1 * 1000 + pl.n2;                                                                  \
+    switch (key_) {                                                                                          \
+      case 24024: hipLaunchKernelGGL((KERNEL<24, 24 CT>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;   \
+      case 30024: hipLaunchKernelGGL((KERNEL<30, 24 CT>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;   \
+      case 48024: hipLaunchKernelGGL((KERNEL<48, 24 CT>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;   \
+      case 48048: hipLaunchKernelGGL((KERNEL<48, 48 CT>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;   \
+      case 72045: hipLaunchKernelGGL((KERNEL<72, 45 CT>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;   \
+      case 144045: hipLaunchKernelGGL((KERNEL<144, 45 CT>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL((KERNEL<0, 0 CT>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;        \
+    }                                                                                                        \
+  } while (0)
+#define HP_PLANE_DISPATCH(KERNEL, GRID, LDS, ST, ...) HP_PLANE_DISPATCH_T(KERNEL, , GRID, LDS, ST, __VA_ARGS__)
+
+#define HP_STICK_DISPATCH(KERNEL, CT, GRID, LDS, ST, N3, ...)                                             \
+  do {                                                                                                  \
+    switch (N3) {                                                                                       \
+      case 24: hipLaunchKernelGGL((KERNEL<24, CT>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;   \
+      case 40: hipLaunchKernelGGL((KERNEL<40, CT>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;   \
+      default: hipLaunchKernelGGL((KERNEL<0, CT>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;    \
+    }                                                                                                   \
   } while (0)
 
-#define HP_STICK_DISPATCH(KERNEL, GRID, LDS, ST, N3, ...)                                                \
-  do {                                                                                                 \
-    switch (N3) {                                                                                      \
-      case 24: hipLaunchKernelGGL((KERNEL<24>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;      \
-      case 40: hipLaunchKernelGGL((KERNEL<40>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;      \
-      default: hipLaunchKernelGGL((KERNEL<0>), GRID, dim3(kThreads), LDS, ST, __VA_ARGS__); break;       \
-    }                                                                                                  \
-  } while (0)
+template <class C>
+hipError_t stick_inv_t(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const C *X, int ld, C *S,
+                       int ns_pad, int n3, const C *tw3, int max_chunk_pw, int ns_max, const int *active,
+                       hipStream_t st) {
+  dim3 grid((ns_max + kStickChunk - 1) / kStickChunk, nitems);
+  size_t lds = (size_t)n3 * sizeof(C) + (size_t)max_chunk_pw * (sizeof(C) + sizeof(int));
+  HP_STICK_DISPATCH(k_stick_inv, C, grid, lds, st, n3, sk, kp, use_kq, nb, X, ld, S, ns_pad, n3, tw3, active);
+  return hipGetLastError();
+}
+
+template <class C>
+hipError_t stick_fwd_t(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const C *S, int ns_pad,
+                       int n3, const C *tw3, double scale, C *Y, int ld, int mode, const double *kin,
+                       const double *eps, const C *X, int eps_stride, int max_chunk_pw, int ns_max,
+                       const int *active, hipStream_t st) {
+  dim3 grid((ns_max + kStickChunk - 1) / kStickChunk, nitems);
+  size_t lds = (size_t)n3 * sizeof(C) + (size_t)n3 * kStickChunk * sizeof(C) + (size_t)max_chunk_pw * sizeof(int);
+  HP_STICK_DISPATCH(k_stick_fwd, C, grid, lds, st, n3, sk, kp, use_kq, nb, S, ns_pad, n3, tw3, scale, Y, ld, mode,
+                    kin, eps, X, eps_stride, active);
+  return hipGetLastError();
+}
 
 hipError_t launch_stick_inv(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const double2 *X,
                             int ld, double2 *S, int ns_pad, int n3, const double2 *tw3, int max_chunk_pw, int ns_max,
                             const int *active, hipStream_t st) {
-  dim3 grid((ns_max + kStickChunk - 1) / kStickChunk, nitems);
-  size_t lds = (size_t)n3 * sizeof(double2) + (size_t)max_chunk_pw * (sizeof(double2) + sizeof(int));
-  HP_STICK_DISPATCH(k_stick_inv, grid, lds, st, n3, sk, kp, use_kq, nb, X, ld, S, ns_pad, n3, tw3, active);
-  return hipGetLastError();
+  return stick_inv_t(sk, kp, use_kq, nb, nitems, X, ld, S, ns_pad, n3, tw3, max_chunk_pw, ns_max, active, st);
+}
+hipError_t launch_stick_inv32(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const float2 *X,
+                              int ld, float2 *S, int ns_pad, int n3, const float2 *tw3, int max_chunk_pw, int ns_max,
+                              const int *active, hipStream_t st) {
+  return stick_inv_t(sk, kp, use_kq, nb, nitems, X, ld, S, ns_pad, n3, tw3, max_chunk_pw, ns_max, active, st);
 }
 
 hipError_t launch_stick_fwd(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const double2 *S,
                             int ns_pad, int n3, const double2 *tw3, double scale, double2 *Y, int ld, int mode,
                             const double *kin, const double *eps, const double2 *X, int eps_stride,
                             int max_chunk_pw, int ns_max, const int *active, hipStream_t st) {
-  dim3 grid((ns_max + kStickChunk - 1) / kStickChunk, nitems);
-  size_t lds = (size_t)n3 * sizeof(double2) + (size_t)n3 * kStickChunk * sizeof(double2) +
-               (size_t)max_chunk_pw * sizeof(int);
-  HP_STICK_DISPATCH(k_stick_fwd, grid, lds, st, n3, sk, kp, use_kq, nb, S, ns_pad, n3, tw3, scale, Y, ld, mode, kin,
-                    eps, X, eps_stride, active);
-  return hipGetLastError();
+  return stick_fwd_t(sk, kp, use_kq, nb, nitems, S, ns_pad, n3, tw3, scale, Y, ld, mode, kin, eps, X, eps_stride,
+                     max_chunk_pw, ns_max, active, st);
+}
+hipError_t launch_stick_fwd32(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const float2 *S,
+                              int ns_pad, int n3, const float2 *tw3, double scale, float2 *Y, int ld, int mode,
+                              const double *kin, const double *eps, const float2 *X, int eps_stride,
+                              int max_chunk_pw, int ns_max, const int *active, hipStream_t st) {
+  return stick_fwd_t(sk, kp, use_kq, nb, nitems, S, ns_pad, n3, tw3, scale, Y, ld, mode, kin, eps, X, eps_stride,
+                     max_chunk_pw, ns_max, active, st);
 }
 
 hipError_t launch_plane_vloc(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
                              const double2 *Sin, double2 *Sout, int ns_pad, const double *vp, const int *active,
                              hipStream_t st) {
-  HP_PLANE_DISPATCH(k_plane_vloc, dim3(pl.n3, nitems), plane_lds_t(pl), st, pl, sk, kp, use_kq, nb, Sin, Sout,
-                    ns_pad, vp, active);
+  HP_PLANE_DISPATCH_T(k_plane_vloc, COMMA double2, dim3(pl.n3, nitems), plane_lds_t(pl, sizeof(double2)), st, pl, sk,
+                      kp, use_kq, nb, Sin, Sout, ns_pad, vp, active);
+  return hipGetLastError();
+}
+hipError_t launch_plane_vloc32(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
+                               const float2 *Sin, float2 *Sout, int ns_pad, const float *vp, const int *active,
+                               hipStream_t st) {
+  HP_PLANE_DISPATCH_T(k_plane_vloc, COMMA float2, dim3(pl.n3, nitems), plane_lds_t(pl, sizeof(float2)), st, pl, sk,
+                      kp, use_kq, nb, Sin, Sout, ns_pad, vp, active);
   return hipGetLastError();
 }
 

@@ -131,6 +131,15 @@ struct hp_ctx {
   double2 *fprev = nullptr, *dvprev = nullptr, *hdf = nullptr, *hdv = nullptr;
   double2 *dots_part = nullptr, *dots = nullptr, *dn = nullptr, *coef = nullptr;
   const double2 **ptrs = nullptr;
+  // FP32 copies and work buffers of the mixed-precision inner solves (allocated on first use)
+  bool have32 = false;
+  float2 *tw32 = nullptr, *T32 = nullptr;
+  float *vp32 = nullptr;
+  float2 *X32 = nullptr, *R32 = nullptr, *B32 = nullptr, *P32 = nullptr, *AP32 = nullptr;
+  double *bn_in = nullptr, *rn_in = nullptr, *rz_in = nullptr, *floor_in = nullptr;
+  int *act_in = nullptr, *act_out = nullptr;
+  Plane pl32{};
+  Axis az32{};
   int nsplit_cap = 16;
   long t_stride = 0, phi_stride = 0;
   hipEvent_t ev[16];
@@ -156,6 +165,10 @@ struct hp_ctx {
 namespace {
 
 constexpr int kNmixMax = 8;
+// Sternheimer tolerance of SCF iteration i > 1: kAdaptiveTol x (mixing residual of i-1).
+constexpr double kAdaptiveTol = 1e-2;
+// Mixed precision: outer tolerances at or above this are met by the FP32 inner solve alone.
+constexpr double kFp32TrustTol = 1e-6;
 
 enum KernelId {
   K_STICK_INV = 0,
@@ -166,10 +179,18 @@ enum KernelId {
   K_CG_STEP,
   K_PLANE_DRHO,
   K_PLANE_MUL,
+  K_STICK_INV32,
+  K_PLANE_VLOC32,
+  K_STICK_FWD32,
+  K_ZPROJ32,
+  K_ZEXPAND32,
+  K_CG_STEP32,
   K_COUNT
 };
-const char *const kKernelNames[K_COUNT] = {"stick_inv", "plane_vloc", "stick_fwd", "zproj",
-                                           "zexpand",   "cg_step",    "plane_drho", "plane_mul_fwd"};
+const char *const kKernelNames[K_COUNT] = {"stick_inv",     "plane_vloc",   "stick_fwd",    "zproj",
+                                           "zexpand",       "cg_step",      "plane_drho",   "plane_mul_fwd",
+                                           "stick_inv32",   "plane_vloc32", "stick_fwd32",  "zproj32",
+                                           "zexpand32",     "cg_step32"};
 
 hipEvent_t prof_event(hp_ctx *c) {
   if (!c->ev_pool.empty()) {
@@ -390,6 +411,141 @@ hp_status cg_solve(hp_ctx *c, const KPair *kp, int nk, const double *eps_items, 
   return HP_OK;
 }
 
+// FP32 tables and buffers for the mixed-precision inner solves (once per context).
+hp_status setup32(hp_ctx *c) {
+  if (c->have32) return HP_OK;
+  const long nitems = (long)c->n_mesh * c->n_occ;
+  const size_t vec = (size_t)nitems * c->ld;
+  const long ntw = c->n1 + c->n2 + c->n3;
+  HPTRY(c->alloc(&c->tw32, ntw));
+  HPCHK(launch_to_f32((const double *)c->tw, (float *)c->tw32, 2 * ntw, c->stream));
+  HPTRY(c->alloc(&c->T32, (size_t)c->n_kpts * c->t_stride));
+  HPCHK(launch_to_f32((const double *)c->d_T, (float *)c->T32, 2L * c->n_kpts * c->t_stride, c->stream));
+  HPTRY(c->alloc(&c->vp32, c->nr));
+  HPCHK(launch_to_f32(c->d_vp, c->vp32, c->nr, c->stream));
+  for (float2 **b : {&c->X32, &c->R32, &c->B32, &c->P32, &c->AP32}) {
+    HPTRY(c->alloc(b, vec));
+    HPCHK(hipMemsetAsync(*b, 0, sizeof(float2) * vec, c->stream));
+  }
+  HPTRY(c->alloc(&c->bn_in, nitems));
+  HPTRY(c->alloc(&c->rn_in, nitems));
+  HPTRY(c->alloc(&c->rz_in, nitems));
+  HPTRY(c->alloc(&c->floor_in, nitems));
+  HPTRY(c->alloc(&c->act_in, nitems));
+  HPTRY(c->alloc(&c->act_out, nitems));
+  c->pl32 = c->pl;
+  c->pl32.ax.tw32 = c->tw32;
+  c->pl32.ay.tw32 = c->tw32 + c->n1;
+  c->az32 = c->az;
+  c->az32.tw32 = c->tw32 + c->n1 + c->n2;
+  HPTRY(sync(c));
+  c->have32 = true;
+  return HP_OK;
+}
+
+// Y = (H_{k+q} + alpha P_v - eps_v) X in FP32 (FP32 FFTs, FP32 MFMA GEMMs with FP32 accumulation).
+hp_status apply_op32(hp_ctx *c, const KPair *kp, int nk, int nb, const float2 *Xin, float2 *Y, const double *eps,
+                     int rows, const int *active) {
+  const int nitems = nk * nb;
+  float2 *S1 = reinterpret_cast<float2 *>(c->S1), *S2 = reinterpret_cast<float2 *>(c->S2);
+  float2 *Cpart = reinterpret_cast<float2 *>(c->Cpart), *C = reinterpret_cast<float2 *>(c->C);
+  HPCHK(timed(c, K_STICK_INV32, [&] {
+    return launch_stick_inv32(c->sk, kp, 1, nb, nitems, Xin, c->ld, S1, c->ns_pad, c->n3, c->az32.tw32,
+                              c->max_chunk_pw, c->ns_max, active, c->stream);
+  }));
+  HPCHK(timed(c, K_PLANE_VLOC32, [&] {
+    return launch_plane_vloc32(c->pl32, c->sk, kp, 1, nb, nitems, S1, S2, c->ns_pad, c->vp32, active, c->stream);
+  }));
+  HPCHK(timed(c, K_STICK_FWD32, [&] {
+    return launch_stick_fwd32(c->sk, kp, 1, nb, nitems, S2, c->ns_pad, c->n3, c->az32.tw32, 1.0 / (double)c->nr, Y,
+                              c->ld, 0, c->d_kin, eps, Xin, nb, c->max_chunk_pw, c->ns_max, active, c->stream);
+  }));
+  const int ns = choose_nsplit(rows, nb, nk, c->npw_max);
+  HPCHK(timed(c, K_ZPROJ32, [&] {
+    return launch_zproj32(kp, 1, nk, c->T32, c->t_stride, 0, rows, Xin, c->ld, nb, c->d_npw, Cpart, ns, active,
+                          c->stream);
+  }));
+  HPCHK(launch_zproj_reduce32(nk, rows, nb, ns, Cpart, c->d_rowscale, 1.0, C, c->stream));
+  HPCHK(timed(c, K_ZEXPAND32, [&] {
+    return launch_zexpand32(kp, 1, nk, c->T32, c->t_stride, 0, rows, C, (long)rows * nb, 1.0, Y, c->ld, nb,
+                            c->d_npw, c->npw_max, active, c->stream);
+  }));
+  return HP_OK;
+}
+
+// Mixed precision: FP64 residual refinement around FP32 PCG inner solves.
+//   r = B - A64 X ; while some ||r|| > tol ||B||: solve A32 d = r to inner_tol in FP32, X += d, recompute r.
+hp_status cg_solve_mixed(hp_ctx *c, const KPair *kp, int nk, const double *eps_items, int warm, double tol,
+                         int max_it, double inner_tol, int max_refine, int *iters, int *not_conv, double *max_rel,
+                         long *happ64, long *happ32, int *refines) {
+  const int nb = c->n_occ, nitems = nk * nb;
+  const int rows = c->n_beta + c->n_occ;
+  HPTRY(setup32(c));
+  int it_in = 0, nact = 0, ref = 0;
+  bool trusted = false;
+  int h_count[2] = {0, 0};
+  for (ref = 0; ref <= max_refine; ++ref) {
+    const int have_x = warm || ref > 0;
+    if (have_x) {
+      HPTRY(apply_op(c, kp, 1, nk, nb, c->X, c->AP, eps_items, rows));
+      *happ64 += nitems;
+    }
+    HPCHK(hipMemsetAsync(c->count, 0, 2 * sizeof(int), c->stream));
+    HPCHK(launch_residual64(kp, nb, nitems, c->B, c->AP, have_x, c->R, c->B32, c->ld, c->d_npw, c->bn, c->rn,
+                            c->act_out, tol, c->count, c->floor_in, c->stream));
+    HPCHK(hipMemcpyAsync(h_count, c->count, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HPTRY(sync(c));
+    if (h_count[1] > 0) return fail(HP_ERR_NUMERIC, "non-finite residual in the Sternheimer solve");
+    nact = h_count[0];
+    if (nact == 0 || ref == max_refine) break;
+    // inner FP32 PCG on the refined items
+    HPCHK(launch_cg_init32(kp, nb, nitems, c->B32, c->X32, c->R32, c->P32, c->d_diag, eps_items, c->ld, c->d_npw,
+                           c->ld, c->rz_in, c->bn_in, c->rn_in, c->act_in, inner_tol, c->act_out, c->floor_in,
+                           c->stream));
+    int inner_active = nact;
+    int k_in = 0;
+    while (inner_active > 0 && k_in < max_it) {
+      ++k_in;
+      HPTRY(apply_op32(c, kp, nk, nb, c->P32, c->AP32, eps_items, rows, c->act_in));
+      *happ32 += inner_active;
+      HPCHK(hipMemsetAsync(c->count, 0, 2 * sizeof(int), c->stream));
+      HPCHK(timed(c, K_CG_STEP32, [&] {
+        return launch_cg_step32(kp, nb, nitems, c->X32, c->R32, c->P32, c->AP32, c->d_diag, eps_items, c->ld,
+                                c->d_npw, c->ld, c->rz_in, c->bn_in, c->rn_in, c->act_in, inner_tol, c->count,
+                                c->floor_in, c->stream);
+      }));
+      HPCHK(hipMemcpyAsync(h_count, c->count, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      HPTRY(sync(c));
+      if (h_count[1] > 0) return fail(HP_ERR_NUMERIC, "non-finite residual in the FP32 inner solve");
+      inner_active = h_count[0];
+    }
+    it_in += k_in;
+    HPCHK(launch_refine_update(nb, nitems, c->X, c->X32, c->ld, c->act_out, have_x, c->stream));
+    // Above ~1e-6 the FP32 operator is exact enough that the inner solve's own residual
+    // stands for the FP64 one; the next SCF iteration starts from an FP64 residual anyway.
+    if (tol >= kFp32TrustTol && inner_active == 0) {
+      nact = 0;
+      ++ref;
+      trusted = true;
+      break;
+    }
+  }
+  *iters = it_in;
+  *refines = ref;
+  *not_conv = nact;
+  std::vector<double> rn(nitems), bn(nitems);
+  // the last residual is the FP64 one, or the inner solve's when the FP32 result was trusted
+  HPCHK(hipMemcpyAsync(rn.data(), trusted ? c->rn_in : c->rn, sizeof(double) * nitems, hipMemcpyDeviceToHost,
+                       c->stream));
+  HPCHK(hipMemcpyAsync(bn.data(), c->bn, sizeof(double) * nitems, hipMemcpyDeviceToHost, c->stream));
+  HPTRY(sync(c));
+  double m = 0.0;
+  for (int i = 0; i < nitems; ++i)
+    if (bn[i] > 0) m = std::max(m, rn[i] / bn[i]);
+  *max_rel = m;
+  return HP_OK;
+}
+
 hp_status upload_pairs(hp_ctx *c, int site, const double q[3], std::vector<KPair> &pairs) {
   (void)site;
   pairs.clear();
@@ -464,6 +620,8 @@ hp_status check_params(const hp_scf_params *p) {
   if (p->nmix < 1 || p->nmix > kNmixMax) return fail(HP_ERR_ARG, "nmix must be in 1..%d", kNmixMax);
   if (!(p->alpha_mix > 0.0 && p->alpha_mix <= 1.0)) return fail(HP_ERR_ARG, "alpha_mix must be in (0, 1]");
   if (p->precision != HP_FP64 && p->precision != HP_MIXED) return fail(HP_ERR_ARG, "unknown precision %d", p->precision);
+  if (p->precision == HP_MIXED && (!(p->inner_tol > 0.0 && p->inner_tol < 1.0) || p->max_refine < 1))
+    return fail(HP_ERR_ARG, "inner_tol must be in (0, 1) and max_refine >= 1");
   return HP_OK;
 }
 
@@ -885,16 +1043,25 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
   std::vector<std::complex<double>> chi_prev;
   bool have_prev = false, converged = false;
   int it = 0, cg_total = 0, not_conv = 0;
-  long happ = 0;
+  long happ = 0, happ32 = 0;
   double dchi = 0.0, vres = 1.0, max_rel = 0.0;
   double stage[8] = {0};
   for (it = 1; it <= p->niter_max; ++it) {
     HPCHK(hipEventRecord(c->ev[0], c->stream));
     HPTRY(build_rhs(c, c->d_kp, nk, site, it > 1 ? c->dvin : nullptr, c->d_psi));
     HPCHK(hipEventRecord(c->ev[1], c->stream));
-    int iters = 0, nc = 0;
+    int iters = 0, nc = 0, nref = 0;
     double mr = 0.0;
-    HPTRY(cg_solve(c, c->d_kp, nk, c->d_eps, it > 1, p->cg_tol, p->max_cg_iter, &iters, &nc, &mr, &happ));
+    // The first iteration gives chi0 and is solved to cg_tol; later iterations only need
+    // the accuracy the response potential has reached (a fixed fraction of the last
+    // mixing residual), never looser than 1e-3 nor tighter than cg_tol.
+    const double tol_it = it == 1 ? p->cg_tol : std::max(p->cg_tol, std::min(1e-3, kAdaptiveTol * vres));
+    if (p->precision == HP_MIXED) {
+      HPTRY(cg_solve_mixed(c, c->d_kp, nk, c->d_eps, it > 1, tol_it, p->max_cg_iter, p->inner_tol, p->max_refine,
+                           &iters, &nc, &mr, &happ, &happ32, &nref));
+    } else {
+      HPTRY(cg_solve(c, c->d_kp, nk, c->d_eps, it > 1, tol_it, p->max_cg_iter, &iters, &nc, &mr, &happ));
+    }
     HPCHK(hipEventRecord(c->ev[2], c->stream));
     cg_total += iters;
     not_conv = nc;
@@ -1039,7 +1206,7 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
     st->converged = converged ? 1 : 0;
     st->cg_iters = cg_total;
     st->h_applies_fp64 = happ;
-    st->h_applies_lowp = 0;
+    st->h_applies_lowp = happ32;
     st->wall_s = wall.s();
     st->chi_change = dchi;
     st->v_residual = vres;
@@ -1058,7 +1225,6 @@ extern "C" hp_status hp_sternheimer_scf(hp_ctx *c, int32_t pert_site, const doub
   HPTRY(check_params(p));
   if (pert_site < 0 || pert_site >= c->n_hub) return fail(HP_ERR_ARG, "pert_site %d out of range", pert_site);
   if (st && st->struct_size != sizeof(hp_scf_stats)) return fail(HP_ERR_ARG, "hp_scf_stats.struct_size mismatch");
-  if (p->precision != HP_FP64) return fail(HP_ERR_ARG, "precision %d not available", p->precision);
   return run_scf(c, pert_site, q_frac, p, dn0_out, dn_out, st);
 }
 
@@ -1069,7 +1235,6 @@ extern "C" hp_status hp_response_matrix(hp_ctx *c, const int32_t nq[3], const hp
   HPTRY(check_params(p));
   if (nq[0] < 1 || nq[1] < 1 || nq[2] < 1) return fail(HP_ERR_ARG, "nq must be >= 1");
   if (st && st->struct_size != sizeof(hp_scf_stats)) return fail(HP_ERR_ARG, "hp_scf_stats.struct_size mismatch");
-  if (p->precision != HP_FP64) return fail(HP_ERR_ARG, "precision %d not available", p->precision);
   const int nh = c->n_hub;
   const int Nq = nq[0] * nq[1] * nq[2];
   std::vector<std::array<double, 3>> qs;
@@ -1092,6 +1257,7 @@ extern "C" hp_status hp_response_matrix(hp_ctx *c, const int32_t nq[3], const hp
       acc.scf_iters += one.scf_iters;
       acc.cg_iters += one.cg_iters;
       acc.h_applies_fp64 += one.h_applies_fp64;
+      acc.h_applies_lowp += one.h_applies_lowp;
       acc.wall_s += one.wall_s;
       acc.chi_change = std::max(acc.chi_change, one.chi_change);
       acc.v_residual = std::max(acc.v_residual, one.v_residual);
@@ -1174,7 +1340,6 @@ extern "C" hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const do
   HPTRY(check_params(p));
   if (pert_site < 0 || pert_site >= c->n_hub) return fail(HP_ERR_ARG, "pert_site out of range");
   if (mesh_k < 0 || mesh_k >= c->n_mesh) return fail(HP_ERR_ARG, "mesh_k out of range");
-  if (p->precision != HP_FP64) return fail(HP_ERR_ARG, "precision %d not available", p->precision);
   std::vector<KPair> pairs;
   HPTRY(upload_pairs(c, pert_site, q_frac, pairs));
   const KPair P = pairs[mesh_k];
@@ -1196,10 +1361,15 @@ extern "C" hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const do
     c->d_A = saveA;
     if (s < 0) return s;
   }
-  int iters = 0, nc = 0;
+  int iters = 0, nc = 0, nref = 0;
   double mr = 0.0;
-  long happ = 0;
-  HPTRY(cg_solve(c, c->d_kp, 1, eps, 0, p->cg_tol, p->max_cg_iter, &iters, &nc, &mr, &happ));
+  long happ = 0, happ32 = 0;
+  if (p->precision == HP_MIXED) {
+    HPTRY(cg_solve_mixed(c, c->d_kp, 1, eps, 0, p->cg_tol, p->max_cg_iter, p->inner_tol, p->max_refine, &iters, &nc,
+                         &mr, &happ, &happ32, &nref));
+  } else {
+    HPTRY(cg_solve(c, c->d_kp, 1, eps, 0, p->cg_tol, p->max_cg_iter, &iters, &nc, &mr, &happ));
+  }
   const HostEntry &E = c->ent[P.ej];
   std::vector<double2> h((size_t)nb * c->ld);
   HPCHK(hipMemcpyAsync(h.data(), c->X, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, c->stream));

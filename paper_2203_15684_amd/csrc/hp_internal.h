@@ -21,6 +21,7 @@ struct Axis {
   int rad[8];
   int span[8];
   const double2 *tw;
+  const float2 *tw32;  // the same table rounded to FP32
 };
 
 // Plane geometry shared by every plane kernel: the xy plane (N1 x N2, y fastest)
@@ -77,6 +78,17 @@ hipError_t launch_stick_fwd(const Sticks &sk, const KPair *kp, int use_kq, int n
                             int ns_pad, int n3, const double2 *tw3, double scale, double2 *Y, int ld, int mode,
                             const double *kin, const double *eps, const double2 *X, int eps_stride, int max_chunk_pw,
                             int ns_max, const int *active, hipStream_t st);
+// FP32 variants of the three operator kernels (mixed-precision inner solves).
+hipError_t launch_stick_inv32(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const float2 *X,
+                              int ld, float2 *S, int ns_pad, int n3, const float2 *tw3, int max_chunk_pw, int ns_max,
+                              const int *active, hipStream_t st);
+hipError_t launch_stick_fwd32(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const float2 *S,
+                              int ns_pad, int n3, const float2 *tw3, double scale, float2 *Y, int ld, int mode,
+                              const double *kin, const double *eps, const float2 *X, int eps_stride,
+                              int max_chunk_pw, int ns_max, const int *active, hipStream_t st);
+hipError_t launch_plane_vloc32(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
+                               const float2 *Sin, float2 *Sout, int ns_pad, const float *vp, const int *active,
+                               hipStream_t st);
 // Plane round trip for the local potential: sticks -> r (DIF) -> * vp -> sticks (reverse).
 hipError_t launch_plane_vloc(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
                              const double2 *Sin, double2 *Sout, int ns_pad, const double *vp, const int *active,
@@ -124,6 +136,32 @@ hipError_t launch_cg_step(const KPair *kp, int nb, int nitems, double2 *Xv, doub
                           const double *diag, const double *eps, int ld, const int *npw_of, long diag_stride,
                           double *rz, const double *bn, double *rn, int *active, double tol, int *count,
                           hipStream_t st);
+// FP32 variants (mixed-precision inner solves; scalars and reductions stay FP64).
+hipError_t launch_zproj32(const KPair *kp, int use_kq, int nk, const float2 *T, long t_stride, int m0, int M,
+                          const float2 *X, int ld, int nb, const int *npw_of, float2 *Cpart, int nsplit,
+                          const int *active, hipStream_t st);
+hipError_t launch_zproj_reduce32(int nk, int M, int nb, int nsplit, const float2 *Cpart, const double *row_scale,
+                                 double gscale, float2 *C, hipStream_t st);
+hipError_t launch_zexpand32(const KPair *kp, int use_kq, int nk, const float2 *T, long t_stride, int m0, int M,
+                            const float2 *C, long c_kstride, double cscale, float2 *Y, int ld, int nb,
+                            const int *npw_of, int npw_max, const int *active, hipStream_t st);
+hipError_t launch_cg_init32(const KPair *kp, int nb, int nitems, const float2 *B, float2 *Xv, float2 *R, float2 *P,
+                            const double *diag, const double *eps, int ld, const int *npw_of, long diag_stride,
+                            double *rz, double *bn, double *rn, int *active, double tol, const int *only,
+                            const double *floor_abs, hipStream_t st);
+hipError_t launch_cg_step32(const KPair *kp, int nb, int nitems, float2 *Xv, float2 *R, float2 *P, const float2 *AP,
+                            const double *diag, const double *eps, int ld, const int *npw_of, long diag_stride,
+                            double *rz, const double *bn, double *rn, int *active, double tol, int *count,
+                            const double *floor_abs, hipStream_t st);
+// R = B - AX (FP64; AX ignored when !have_x), R32 = (float) R, per-item norms and active flags.
+hipError_t launch_residual64(const KPair *kp, int nb, int nitems, const double2 *B, const double2 *AX, int have_x,
+                             double2 *R, float2 *R32, int ld, const int *npw_of, double *bn, double *rn, int *active,
+                             double tol, int *count, double *floor_abs, hipStream_t st);
+// (floor_abs, nullable: per-item absolute residual below which an inner solve stops)
+// X (+)= (double) D for refined items.
+hipError_t launch_refine_update(int nb, int nitems, double2 *X, const float2 *D, int ld, const int *refined,
+                                int have_x, hipStream_t st);
+hipError_t launch_to_f32(const double *in, float *out, long n, hipStream_t st);
 // dn[s][m1][m2] = sum_k 2 w_k sum_v (B[k][5s+m1][v] conj(A[ek][5s+m2][v]) + (m1 <-> m2))
 hipError_t launch_dn(const KPair *kp, int nk, int nh, int nb, const double2 *A, const double2 *B, double2 *dn,
                      hipStream_t st);

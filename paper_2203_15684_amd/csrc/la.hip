@@ -10,13 +10,38 @@ namespace hp {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
-// Lane layout of v_mfma_f64_16x16x4f64 (measured on gfx950):
-//   A operand: lane l holds A[l % 16][l / 16]   (16 rows x 4 k)
-//   B operand: lane l holds B[l / 16][l % 16]   (4 k x 16 cols)
-//   D        : lane l, element r holds D[l / 16 + 4 r][l % 16]
+// Lane layouts (measured on gfx950):
+//   v_mfma_f64_16x16x4f64: A lane l -> A[l%16][l/16], B lane l -> B[l/16][l%16],
+//                          D lane l, element r -> D[l/16 + 4r][l%16]
+//   v_mfma_f32_16x16x4f32: same A and B; D lane l, element r -> D[4(l/16) + r][l%16]
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <class T>
+struct Mf;
+template <>
+struct Mf<double> {
+  using acc = d4;
+  using c2 = double2;
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct Mf<float> {
+  using acc = f4;
+  using c2 = float2;
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <class C>
+__device__ __forceinline__ C zc() {
+  C r;
+  r.x = 0;
+  r.y = 0;
+  return r;
 }
 
 constexpr int kTile = 32;   // output tile (rows x cols) of the projection GEMM
@@ -24,12 +49,16 @@ constexpr int kKb = 16;     // K step staged through LDS
 constexpr int kPad = 1;     // LDS row padding (complex elements)
 
 // C[k][m][v] (partial over a K split) = sum_G conj(T[m0+m][G]) X[v][G].
-__global__ void __launch_bounds__(256) k_zproj(const KPair *kp, int use_kq, const double2 *__restrict__ T,
-                                               long t_stride, int m0, int M, const double2 *__restrict__ X, int ld,
-                                               int nb, const int *__restrict__ npw_of, int nsplit,
-                                               double2 *__restrict__ Cpart, int nk, const int *active) {
-  __shared__ double2 At[kTile][kKb + kPad];
-  __shared__ double2 Bt[kTile][kKb + kPad];
+template <class T>
+__global__ void __launch_bounds__(256) k_zproj(const KPair *kp, int use_kq, const typename Mf<T>::c2 *__restrict__ Tb,
+                                               long t_stride, int m0, int M,
+                                               const typename Mf<T>::c2 *__restrict__ X, int ld, int nb,
+                                               const int *__restrict__ npw_of, int nsplit,
+                                               typename Mf<T>::c2 *__restrict__ Cpart, int nk, const int *active) {
+  using C2 = typename Mf<T>::c2;
+  using A4 = typename Mf<T>::acc;
+  __shared__ C2 At[kTile][kKb + kPad];
+  __shared__ C2 Bt[kTile][kKb + kPad];
   const int k = blockIdx.z / nsplit;
   const int split = blockIdx.z - k * nsplit;
   if (active) {  // skip tiles whose 32 bands are all converged (their outputs are not used)
@@ -45,27 +74,27 @@ __global__ void __launch_bounds__(256) k_zproj(const KPair *kp, int use_kq, cons
   const int g_end = min(npw, g_begin + chunk);
   const int mt = blockIdx.x * kTile;
   const int nt = blockIdx.y * kTile;
-  const double2 *Te = T + (size_t)e * t_stride + (size_t)m0 * ld;
-  const double2 *Xk = X + (size_t)k * nb * ld;
+  const C2 *Te = Tb + (size_t)e * t_stride + (size_t)m0 * ld;
+  const C2 *Xk = X + (size_t)k * nb * ld;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  d4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+  A4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
   const int lr = threadIdx.x >> 3;       // 0..31 row for loads
   const int lc = (threadIdx.x & 7) * 2;  // 0..14 column pair
   for (int g0 = g_begin; g0 < g_end; g0 += kKb) {
     for (int c = 0; c < 2; ++c) {
       const int g = g0 + lc + c;
       const int row = mt + lr;
-      At[lr][lc + c] = (row < M && g < g_end) ? Te[(size_t)row * ld + g] : make_double2(0.0, 0.0);
+      At[lr][lc + c] = (row < M && g < g_end) ? Te[(size_t)row * ld + g] : zc<C2>();
       const int col = nt + lr;
-      Bt[lr][lc + c] = (col < nb && g < g_end) ? Xk[(size_t)col * ld + g] : make_double2(0.0, 0.0);
+      Bt[lr][lc + c] = (col < nb && g < g_end) ? Xk[(size_t)col * ld + g] : zc<C2>();
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < kKb; kk += 4) {
-      const double2 a = At[wm * 16 + (lane & 15)][kk + (lane >> 4)];
-      const double2 b = Bt[wn * 16 + (lane & 15)][kk + (lane >> 4)];
+      const C2 a = At[wm * 16 + (lane & 15)][kk + (lane >> 4)];
+      const C2 b = Bt[wn * 16 + (lane & 15)][kk + (lane >> 4)];
       // conj(a) * b
       cr = mfma(a.x, b.x, cr);
       cr = mfma(a.y, b.y, cr);
@@ -74,36 +103,49 @@ __global__ void __launch_bounds__(256) k_zproj(const KPair *kp, int use_kq, cons
     }
     __syncthreads();
   }
-  double2 *Cp = Cpart + ((size_t)split * nk + k) * (size_t)M * nb;
+  C2 *Cp = Cpart + ((size_t)split * nk + k) * (size_t)M * nb;
   for (int r = 0; r < 4; ++r) {
-    const int m = mt + wm * 16 + (lane >> 4) + 4 * r;
+    const int m = mt + wm * 16 + Mf<T>::row(lane, r);
     const int v = nt + wn * 16 + (lane & 15);
-    if (m < M && v < nb) Cp[(size_t)m * nb + v] = make_double2(cr[r], ci[r]);
+    if (m < M && v < nb) {
+      C2 o;
+      o.x = cr[r];
+      o.y = ci[r];
+      Cp[(size_t)m * nb + v] = o;
+    }
   }
 }
 
-__global__ void k_zproj_reduce(int total, int M, int nb, int nsplit, const double2 *__restrict__ Cpart,
-                               const double *__restrict__ row_scale, double gscale, double2 *__restrict__ C) {
+template <class C2>
+__global__ void k_zproj_reduce(int total, int M, int nb, int nsplit, const C2 *__restrict__ Cpart,
+                               const double *__restrict__ row_scale, double gscale, C2 *__restrict__ C) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
-  double2 acc = make_double2(0.0, 0.0);
+  double ax = 0.0, ay = 0.0;
   for (int s = 0; s < nsplit; ++s) {
-    const double2 p = Cpart[(size_t)s * total + i];
-    acc.x += p.x;
-    acc.y += p.y;
+    const C2 p = Cpart[(size_t)s * total + i];
+    ax += p.x;
+    ay += p.y;
   }
   double sc = gscale;
   if (row_scale) sc *= row_scale[(i / nb) % M];
-  C[i] = make_double2(acc.x * sc, acc.y * sc);
+  C2 o;
+  o.x = ax * sc;
+  o.y = ay * sc;
+  C[i] = o;
 }
 
 // Y[v][G] += sum_m T[m0+m][G] C[k][m][v]; tile 32 bands x 64 plane waves.
-__global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, const double2 *__restrict__ T,
-                                                 long t_stride, int m0, int M, const double2 *__restrict__ C,
-                                                 long c_kstride, double cscale, double2 *__restrict__ Y, int ld,
-                                                 int nb, const int *__restrict__ npw_of, const int *active) {
-  __shared__ double2 Ct[32][kKb + kPad];   // [v][m]
-  __shared__ double2 Tt[kKb][64 + kPad];   // [m][G]
+template <class T>
+__global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, const typename Mf<T>::c2 *__restrict__ Tb,
+                                                 long t_stride, int m0, int M,
+                                                 const typename Mf<T>::c2 *__restrict__ C, long c_kstride,
+                                                 double cscale, typename Mf<T>::c2 *__restrict__ Y, int ld, int nb,
+                                                 const int *__restrict__ npw_of, const int *active) {
+  using C2 = typename Mf<T>::c2;
+  using A4 = typename Mf<T>::acc;
+  __shared__ C2 Ct[32][kKb + kPad];   // [v][m]
+  __shared__ C2 Tt[kKb][64 + kPad];   // [m][G]
   const int k = blockIdx.z;
   if (active) {
     const int v = blockIdx.y * 32 + (threadIdx.x & 31);
@@ -116,34 +158,40 @@ __global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, co
   const int gt = blockIdx.x * 64;
   if (gt >= npw) return;
   const int vt = blockIdx.y * 32;
-  const double2 *Te = T + (size_t)e * t_stride + (size_t)m0 * ld;
-  const double2 *Ck = C + (size_t)k * c_kstride;
+  const C2 *Te = Tb + (size_t)e * t_stride + (size_t)m0 * ld;
+  const C2 *Ck = C + (size_t)k * c_kstride;
+  const T cs = (T)cscale;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wv = wave >> 1, wg = wave & 1;
-  d4 yr0 = {0, 0, 0, 0}, yi0 = {0, 0, 0, 0}, yr1 = {0, 0, 0, 0}, yi1 = {0, 0, 0, 0};
+  A4 yr0 = {0, 0, 0, 0}, yi0 = {0, 0, 0, 0}, yr1 = {0, 0, 0, 0}, yi1 = {0, 0, 0, 0};
   for (int mb = 0; mb < M; mb += kKb) {
     // C tile: 32 v x 16 m  (512 values, 2 per thread)
     for (int c = 0; c < 2; ++c) {
       const int idx = threadIdx.x * 2 + c;
       const int vv = idx >> 4, mm = idx & 15;
       const int m = mb + mm, v = vt + vv;
-      Ct[vv][mm] = (m < M && v < nb) ? make_double2(cscale * Ck[(size_t)m * nb + v].x, cscale * Ck[(size_t)m * nb + v].y)
-                                     : make_double2(0.0, 0.0);
+      C2 val = zc<C2>();
+      if (m < M && v < nb) {
+        val = Ck[(size_t)m * nb + v];
+        val.x *= cs;
+        val.y *= cs;
+      }
+      Ct[vv][mm] = val;
     }
     // T tile: 16 m x 64 G (1024 values, 4 per thread)
     for (int c = 0; c < 4; ++c) {
       const int idx = threadIdx.x + c * 256;
       const int mm = idx >> 6, gg = idx & 63;
       const int m = mb + mm, g = gt + gg;
-      Tt[mm][gg] = (m < M && g < npw) ? Te[(size_t)m * ld + g] : make_double2(0.0, 0.0);
+      Tt[mm][gg] = (m < M && g < npw) ? Te[(size_t)m * ld + g] : zc<C2>();
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < kKb; kk += 4) {
-      const double2 a = Ct[wv * 16 + (lane & 15)][kk + (lane >> 4)];
-      const double2 b0 = Tt[kk + (lane >> 4)][wg * 32 + (lane & 15)];
-      const double2 b1 = Tt[kk + (lane >> 4)][wg * 32 + 16 + (lane & 15)];
+      const C2 a = Ct[wv * 16 + (lane & 15)][kk + (lane >> 4)];
+      const C2 b0 = Tt[kk + (lane >> 4)][wg * 32 + (lane & 15)];
+      const C2 b1 = Tt[kk + (lane >> 4)][wg * 32 + 16 + (lane & 15)];
       yr0 = mfma(a.x, b0.x, yr0);
       yr0 = mfma(-a.y, b0.y, yr0);
       yi0 = mfma(a.x, b0.y, yi0);
@@ -155,18 +203,22 @@ __global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, co
     }
     __syncthreads();
   }
-  double2 *Yk = Y + (size_t)k * nb * ld;
+  C2 *Yk = Y + (size_t)k * nb * ld;
   for (int r = 0; r < 4; ++r) {
-    const int v = vt + wv * 16 + (lane >> 4) + 4 * r;
+    const int v = vt + wv * 16 + Mf<T>::row(lane, r);
     if (v >= nb) continue;
     const int g = gt + wg * 32 + (lane & 15);
     if (g < npw) {
-      double2 y = Yk[(size_t)v * ld + g];
-      Yk[(size_t)v * ld + g] = make_double2(y.x + yr0[r], y.y + yi0[r]);
+      C2 y = Yk[(size_t)v * ld + g];
+      y.x += yr0[r];
+      y.y += yi0[r];
+      Yk[(size_t)v * ld + g] = y;
     }
     if (g + 16 < npw) {
-      double2 y = Yk[(size_t)v * ld + g + 16];
-      Yk[(size_t)v * ld + g + 16] = make_double2(y.x + yr1[r], y.y + yi1[r]);
+      C2 y = Yk[(size_t)v * ld + g + 16];
+      y.x += yr1[r];
+      y.y += yi1[r];
+      Yk[(size_t)v * ld + g + 16] = y;
     }
   }
 }
@@ -189,15 +241,20 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return s;
 }
 
-__global__ void __launch_bounds__(256) k_cg_init(const KPair *kp, int nb, const double2 *__restrict__ B,
-                                                 double2 *__restrict__ Xv, double2 *__restrict__ R,
-                                                 double2 *__restrict__ P, const double2 *__restrict__ AX,
-                                                 int have_x0, const double *__restrict__ diag,
+template <class C2>
+__global__ void __launch_bounds__(256) k_cg_init(const KPair *kp, int nb, const C2 *__restrict__ B,
+                                                 C2 *__restrict__ Xv, C2 *__restrict__ R, C2 *__restrict__ P,
+                                                 const C2 *__restrict__ AX, int have_x0, const double *__restrict__ diag,
                                                  const double *__restrict__ eps, int ld,
                                                  const int *__restrict__ npw_of, long diag_stride, double *rz,
-                                                 double *bn, double *rn, int *active, double tol) {
+                                                 double *bn, double *rn, int *active, double tol,
+                                                 const int *only, const double *floor_abs) {
   __shared__ double red[8];
   const int item = blockIdx.x;
+  if (only && !only[item]) {
+    if (threadIdx.x == 0) active[item] = 0;
+    return;
+  }
   const int k = item / nb;
   const int e = kp[k].ej;
   const int npw = npw_of[e];
@@ -206,20 +263,26 @@ __global__ void __launch_bounds__(256) k_cg_init(const KPair *kp, int nb, const 
   const size_t o = (size_t)item * ld;
   double sb = 0.0, sr = 0.0, srz = 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
-    const double2 b = B[o + g];
-    double2 r = b;
+    const C2 b = B[o + g];
+    double rx = b.x, ry = b.y;
     if (have_x0) {
-      const double2 ax = AX[o + g];
-      r = make_double2(b.x - ax.x, b.y - ax.y);
+      const C2 ax = AX[o + g];
+      rx -= ax.x;
+      ry -= ax.y;
     } else {
-      Xv[o + g] = make_double2(0.0, 0.0);
+      Xv[o + g] = zc<C2>();
     }
     const double m = 1.0 / (dg[g] - ev);
+    C2 r, pz;
+    r.x = rx;
+    r.y = ry;
+    pz.x = m * rx;
+    pz.y = m * ry;
     R[o + g] = r;
-    P[o + g] = make_double2(m * r.x, m * r.y);
-    sb += b.x * b.x + b.y * b.y;
-    sr += r.x * r.x + r.y * r.y;
-    srz += m * (r.x * r.x + r.y * r.y);
+    P[o + g] = pz;
+    sb += (double)b.x * b.x + (double)b.y * b.y;
+    sr += rx * rx + ry * ry;
+    srz += m * (rx * rx + ry * ry);
   }
   sb = block_sum(sb, red);
   sr = block_sum(sr, red);
@@ -229,17 +292,18 @@ __global__ void __launch_bounds__(256) k_cg_init(const KPair *kp, int nb, const 
     bn[item] = nb_;
     rn[item] = sqrt(sr);
     rz[item] = srz;
-    active[item] = (nb_ > 0.0 && sqrt(sr) > tol * nb_) ? 1 : 0;
+    const double thr = floor_abs ? fmax(tol * nb_, floor_abs[item]) : tol * nb_;
+    active[item] = (nb_ > 0.0 && sqrt(sr) > thr) ? 1 : 0;
   }
 }
 
-__global__ void __launch_bounds__(256) k_cg_step(const KPair *kp, int nb, double2 *__restrict__ Xv,
-                                                 double2 *__restrict__ R, double2 *__restrict__ P,
-                                                 const double2 *__restrict__ AP, const double *__restrict__ diag,
-                                                 const double *__restrict__ eps, int ld,
-                                                 const int *__restrict__ npw_of, long diag_stride, double *rz,
-                                                 const double *bn, double *rn, int *active, double tol,
-                                                 int *count) {
+template <class C2>
+__global__ void __launch_bounds__(256) k_cg_step(const KPair *kp, int nb, C2 *__restrict__ Xv, C2 *__restrict__ R,
+                                                 C2 *__restrict__ P, const C2 *__restrict__ AP,
+                                                 const double *__restrict__ diag, const double *__restrict__ eps,
+                                                 int ld, const int *__restrict__ npw_of, long diag_stride,
+                                                 double *rz, const double *bn, double *rn, int *active, double tol,
+                                                 int *count, const double *floor_abs) {
   __shared__ double red[8];
   const int item = blockIdx.x;
   if (!active[item]) return;
@@ -251,16 +315,16 @@ __global__ void __launch_bounds__(256) k_cg_step(const KPair *kp, int nb, double
   const size_t o = (size_t)item * ld;
   double pap = 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
-    const double2 p = P[o + g], a = AP[o + g];
-    pap += p.x * a.x + p.y * a.y;
+    const C2 p = P[o + g], a = AP[o + g];
+    pap += (double)p.x * a.x + (double)p.y * a.y;
   }
   pap = block_sum(pap, red);
   const double rz_old = rz[item];
   const double alpha = rz_old / pap;
   double srz = 0.0, srr = 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
-    const double2 p = P[o + g], a = AP[o + g];
-    double2 x = Xv[o + g], r = R[o + g];
+    const C2 p = P[o + g], a = AP[o + g];
+    C2 x = Xv[o + g], r = R[o + g];
     x.x += alpha * p.x;
     x.y += alpha * p.y;
     r.x -= alpha * a.x;
@@ -268,7 +332,7 @@ __global__ void __launch_bounds__(256) k_cg_step(const KPair *kp, int nb, double
     Xv[o + g] = x;
     R[o + g] = r;
     const double m = 1.0 / (dg[g] - ev);
-    const double rr = r.x * r.x + r.y * r.y;
+    const double rr = (double)r.x * r.x + (double)r.y * r.y;
     srr += rr;
     srz += m * rr;
   }
@@ -276,19 +340,78 @@ __global__ void __launch_bounds__(256) k_cg_step(const KPair *kp, int nb, double
   srr = block_sum(srr, red);
   const double beta = srz / rz_old;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
-    const double2 p = P[o + g], r = R[o + g];
+    const C2 p = P[o + g], r = R[o + g];
     const double m = 1.0 / (dg[g] - ev);
-    P[o + g] = make_double2(m * r.x + beta * p.x, m * r.y + beta * p.y);
+    C2 pn;
+    pn.x = m * r.x + beta * p.x;
+    pn.y = m * r.y + beta * p.y;
+    P[o + g] = pn;
   }
   if (threadIdx.x == 0) {
     rz[item] = srz;
     const double r_ = sqrt(srr);
     rn[item] = r_;
-    const int still = (r_ > tol * bn[item] && isfinite(r_)) ? 1 : 0;
+    const double thr = floor_abs ? fmax(tol * bn[item], floor_abs[item]) : tol * bn[item];
+    const int still = (r_ > thr && isfinite(r_)) ? 1 : 0;
     active[item] = still;
     if (still) atomicAdd(count, 1);
     if (!isfinite(r_)) atomicAdd(count + 1, 1);
   }
+}
+
+// Mixed precision: R = B - AX (FP64) with per-item norms and flags; r32 = (float) R.
+__global__ void __launch_bounds__(256) k_residual64(const KPair *kp, int nb, const double2 *__restrict__ B,
+                                                    const double2 *__restrict__ AX, int have_x,
+                                                    double2 *__restrict__ R, float2 *__restrict__ R32, int ld,
+                                                    const int *__restrict__ npw_of, double *bn, double *rn,
+                                                    int *active, double tol, int *count, double *floor_abs) {
+  __shared__ double red[8];
+  const int item = blockIdx.x;
+  const int k = item / nb;
+  const int npw = npw_of[kp[k].ej];
+  const size_t o = (size_t)item * ld;
+  double sb = 0.0, sr = 0.0;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) {
+    const double2 b = B[o + g];
+    double2 r = b;
+    if (have_x) {
+      const double2 a = AX[o + g];
+      r.x -= a.x;
+      r.y -= a.y;
+    }
+    R[o + g] = r;
+    R32[o + g] = make_float2((float)r.x, (float)r.y);
+    sb += b.x * b.x + b.y * b.y;
+    sr += r.x * r.x + r.y * r.y;
+  }
+  sb = block_sum(sb, red);
+  sr = block_sum(sr, red);
+  if (threadIdx.x == 0) {
+    const double b_ = sqrt(sb), r_ = sqrt(sr);
+    bn[item] = b_;
+    rn[item] = r_;
+    if (floor_abs) floor_abs[item] = 0.5 * tol * b_;  // the inner solve need not go below this
+    const int a = (b_ > 0.0 && r_ > tol * b_ && isfinite(r_)) ? 1 : 0;
+    active[item] = a;
+    if (a) atomicAdd(count, 1);
+    if (!isfinite(r_)) atomicAdd(count + 1, 1);
+  }
+}
+
+// X += (double) D32 for the items that were refined (X is zero-initialized when !have_x).
+__global__ void k_refine_update(int nb, double2 *__restrict__ X, const float2 *__restrict__ D, int ld,
+                                const int *__restrict__ npw_item, const int *refined, int have_x) {
+  const int item = blockIdx.y;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ld) return;
+  const size_t o = (size_t)item * ld + g;
+  double2 x = have_x ? X[o] : make_double2(0.0, 0.0);
+  if (refined[item]) {
+    const float2 d = D[o];
+    x.x += (double)d.x;
+    x.y += (double)d.y;
+  }
+  X[o] = x;
 }
 
 // dn[s][m1][m2] = sum_k 2 w_k sum_v (B[k][5s+m1][v] conj(A[k][5s+m2][v]) + B[k][5s+m2][v] conj(A[k][5s+m1][v]))
@@ -376,16 +499,31 @@ hipError_t launch_zproj(const KPair *kp, int use_kq, int nk, const double2 *T, l
                         const double2 *X, int ld, int nb, const int *npw_of, double2 *Cpart, int nsplit,
                         const int *active, hipStream_t st) {
   dim3 grid((M + kTile - 1) / kTile, (nb + kTile - 1) / kTile, nk * nsplit);
-  hipLaunchKernelGGL(k_zproj, grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, X, ld, nb, npw_of, nsplit,
-                     Cpart, nk, active);
+  hipLaunchKernelGGL(k_zproj<double>, grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, X, ld, nb, npw_of,
+                     nsplit, Cpart, nk, active);
+  return hipGetLastError();
+}
+hipError_t launch_zproj32(const KPair *kp, int use_kq, int nk, const float2 *T, long t_stride, int m0, int M,
+                          const float2 *X, int ld, int nb, const int *npw_of, float2 *Cpart, int nsplit,
+                          const int *active, hipStream_t st) {
+  dim3 grid((M + kTile - 1) / kTile, (nb + kTile - 1) / kTile, nk * nsplit);
+  hipLaunchKernelGGL(k_zproj<float>, grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, X, ld, nb, npw_of,
+                     nsplit, Cpart, nk, active);
   return hipGetLastError();
 }
 
 hipError_t launch_zproj_reduce(int nk, int M, int nb, int nsplit, const double2 *Cpart, const double *row_scale,
                                double gscale, double2 *C, hipStream_t st) {
   const int total = nk * M * nb;
-  hipLaunchKernelGGL(k_zproj_reduce, dim3((total + 255) / 256), dim3(256), 0, st, total, M, nb, nsplit, Cpart,
-                     row_scale, gscale, C);
+  hipLaunchKernelGGL(k_zproj_reduce<double2>, dim3((total + 255) / 256), dim3(256), 0, st, total, M, nb, nsplit,
+                     Cpart, row_scale, gscale, C);
+  return hipGetLastError();
+}
+hipError_t launch_zproj_reduce32(int nk, int M, int nb, int nsplit, const float2 *Cpart, const double *row_scale,
+                                 double gscale, float2 *C, hipStream_t st) {
+  const int total = nk * M * nb;
+  hipLaunchKernelGGL(k_zproj_reduce<float2>, dim3((total + 255) / 256), dim3(256), 0, st, total, M, nb, nsplit,
+                     Cpart, row_scale, gscale, C);
   return hipGetLastError();
 }
 
@@ -393,8 +531,16 @@ hipError_t launch_zexpand(const KPair *kp, int use_kq, int nk, const double2 *T,
                           const double2 *C, long c_kstride, double cscale, double2 *Y, int ld, int nb,
                           const int *npw_of, int npw_max, const int *active, hipStream_t st) {
   dim3 grid((npw_max + 63) / 64, (nb + 31) / 32, nk);
-  hipLaunchKernelGGL(k_zexpand, grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride, cscale, Y, ld,
-                     nb, npw_of, active);
+  hipLaunchKernelGGL(k_zexpand<double>, grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride, cscale,
+                     Y, ld, nb, npw_of, active);
+  return hipGetLastError();
+}
+hipError_t launch_zexpand32(const KPair *kp, int use_kq, int nk, const float2 *T, long t_stride, int m0, int M,
+                            const float2 *C, long c_kstride, double cscale, float2 *Y, int ld, int nb,
+                            const int *npw_of, int npw_max, const int *active, hipStream_t st) {
+  dim3 grid((npw_max + 63) / 64, (nb + 31) / 32, nk);
+  hipLaunchKernelGGL(k_zexpand<float>, grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride, cscale,
+                     Y, ld, nb, npw_of, active);
   return hipGetLastError();
 }
 
@@ -402,8 +548,16 @@ hipError_t launch_cg_init(const KPair *kp, int nb, int nitems, const double2 *B,
                           double2 *P, const double2 *AX, int have_x0, const double *diag, const double *eps, int ld,
                           const int *npw_of, long diag_stride, double *rz, double *bn, double *rn, int *active,
                           double tol, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_init, dim3(nitems), dim3(256), 0, st, kp, nb, B, Xv, R, P, AX, have_x0, diag, eps, ld,
-                     npw_of, diag_stride, rz, bn, rn, active, tol);
+  hipLaunchKernelGGL(k_cg_init<double2>, dim3(nitems), dim3(256), 0, st, kp, nb, B, Xv, R, P, AX, have_x0, diag, eps,
+                     ld, npw_of, diag_stride, rz, bn, rn, active, tol, (const int *)nullptr, (const double *)nullptr);
+  return hipGetLastError();
+}
+hipError_t launch_cg_init32(const KPair *kp, int nb, int nitems, const float2 *B, float2 *Xv, float2 *R, float2 *P,
+                            const double *diag, const double *eps, int ld, const int *npw_of, long diag_stride,
+                            double *rz, double *bn, double *rn, int *active, double tol, const int *only,
+                            const double *floor_abs, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_init<float2>, dim3(nitems), dim3(256), 0, st, kp, nb, B, Xv, R, P, (const float2 *)nullptr,
+                     0, diag, eps, ld, npw_of, diag_stride, rz, bn, rn, active, tol, only, floor_abs);
   return hipGetLastError();
 }
 
@@ -411,8 +565,41 @@ hipError_t launch_cg_step(const KPair *kp, int nb, int nitems, double2 *Xv, doub
                           const double2 *AP, const double *diag, const double *eps, int ld, const int *npw_of,
                           long diag_stride, double *rz, const double *bn, double *rn, int *active, double tol,
                           int *count, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_step, dim3(nitems), dim3(256), 0, st, kp, nb, Xv, R, P, AP, diag, eps, ld, npw_of,
-                     diag_stride, rz, bn, rn, active, tol, count);
+  hipLaunchKernelGGL(k_cg_step<double2>, dim3(nitems), dim3(256), 0, st, kp, nb, Xv, R, P, AP, diag, eps, ld, npw_of,
+                     diag_stride, rz, bn, rn, active, tol, count, (const double *)nullptr);
+  return hipGetLastError();
+}
+hipError_t launch_cg_step32(const KPair *kp, int nb, int nitems, float2 *Xv, float2 *R, float2 *P, const float2 *AP,
+                            const double *diag, const double *eps, int ld, const int *npw_of, long diag_stride,
+                            double *rz, const double *bn, double *rn, int *active, double tol, int *count,
+                            const double *floor_abs, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_step<float2>, dim3(nitems), dim3(256), 0, st, kp, nb, Xv, R, P, AP, diag, eps, ld, npw_of,
+                     diag_stride, rz, bn, rn, active, tol, count, floor_abs);
+  return hipGetLastError();
+}
+
+__global__ void k_to_f32(const double *__restrict__ in, float *__restrict__ out, long n) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
+hipError_t launch_to_f32(const double *in, float *out, long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual64(const KPair *kp, int nb, int nitems, const double2 *B, const double2 *AX, int have_x,
+                             double2 *R, float2 *R32, int ld, const int *npw_of, double *bn, double *rn, int *active,
+                             double tol, int *count, double *floor_abs, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual64, dim3(nitems), dim3(256), 0, st, kp, nb, B, AX, have_x, R, R32, ld, npw_of, bn, rn,
+                     active, tol, count, floor_abs);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_update(int nb, int nitems, double2 *X, const float2 *D, int ld, const int *refined,
+                                int have_x, hipStream_t st) {
+  hipLaunchKernelGGL(k_refine_update, dim3((ld + 255) / 256, nitems), dim3(256), 0, st, nb, X, D, ld,
+                     (const int *)nullptr, refined, have_x);
   return hipGetLastError();
 }
 

@@ -61,7 +61,8 @@ class HpGroundState(C.Structure):
 class HpScfParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("conv_thr_chi", C.c_double), ("conv_thr_v", C.c_double),
                 ("cg_tol", C.c_double), ("niter_max", C.c_int32), ("alpha_mix", C.c_double), ("nmix", C.c_int32),
-                ("max_cg_iter", C.c_int32), ("precision", C.c_int32), ("verbosity", C.c_int32)]
+                ("max_cg_iter", C.c_int32), ("precision", C.c_int32), ("verbosity", C.c_int32),
+                ("inner_tol", C.c_double), ("max_refine", C.c_int32)]
 
 
 class HpScfStats(C.Structure):
@@ -143,10 +144,13 @@ class ScfParams:
     max_cg_iter: int = 1000
     precision: int = HP_FP64
     verbosity: int = 0
+    inner_tol: float = 1e-4
+    max_refine: int = 12
 
     def c(self) -> HpScfParams:
         return HpScfParams(C.sizeof(HpScfParams), self.conv_thr_chi, self.conv_thr_v, self.cg_tol, self.niter_max,
-                           self.alpha_mix, self.nmix, self.max_cg_iter, self.precision, self.verbosity)
+                           self.alpha_mix, self.nmix, self.max_cg_iter, self.precision, self.verbosity,
+                           self.inner_tol, self.max_refine)
 
 
 class Context:

@@ -115,3 +115,19 @@ def test_fullsize_response_matrix_properties():
     assert np.all(d0 < 0) and np.all(d < 0) and np.all(np.abs(d) < np.abs(d0))
     uv = hp.hp_hubbard_params(chi0, chi)
     assert np.all(np.diag(uv) > 0)
+
+
+def test_fullsize_mixed_matches_fp64_one_pair():
+    """One (site, q) SCF at full size in both precisions: the mixed form (FP32 inner PCG,
+    FP64 refinement) reproduces the FP64 chi(q) column within 1e-6 relative."""
+    from paper_2203_15684_amd import hp
+    base = dict(conv_thr_chi=1e-10, conv_thr_v=1e-8, cg_tol=1e-10, niter_max=100, max_cg_iter=2000)
+    q = (0.0, 0.5, 0.5)
+    d64 = hp.hp_sternheimer_scf(ctx(), 1, q, hp.ScfParams(**base, precision=hp.HP_FP64))
+    d32 = hp.hp_sternheimer_scf(ctx(), 1, q, hp.ScfParams(**base, precision=hp.HP_MIXED))
+    assert d64[3] == 0 and d32[3] == 0
+    assert d32[2]["h_applies_lowp"] > 0
+    for i in (0, 1):
+        c64 = np.einsum("smm->s", d64[i])
+        c32 = np.einsum("smm->s", d32[i])
+        assert np.abs(c32 - c64).max() < 1e-6 * np.abs(c64).max()

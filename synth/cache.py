@@ -8,6 +8,7 @@ from their closed forms on load.
 from __future__ import annotations
 
 import os
+import sys
 import time
 
 import numpy as np
@@ -65,11 +66,14 @@ def load(name: str):
                          qmesh=tuple(spec.qmesh), kpts=kpts, n_mesh=n_mesh, gap=gap)
 
 
-def get(name: str, device: str = "auto", verbose: bool = False):
-    """Cached ground state of a named workload, generated on first use."""
+def get(name: str, device: str = "auto", verbose: bool = None):
+    """Cached ground state of a named workload, generated on first use (progress on stderr
+    for the large systems)."""
     gs = load(name)
     if gs is not None:
         return gs
+    if verbose is None:
+        verbose = S.SPECS[name].n_occ >= 100
     if device == "auto":
         try:
             import torch
@@ -77,8 +81,15 @@ def get(name: str, device: str = "auto", verbose: bool = False):
         except Exception:
             device = "cpu"
     t = time.time()
-    gs = S.build_ground_state(name, device=device, verbose=verbose)
     if verbose:
-        print(f"[synth] built {name} on {device} in {time.time() - t:.1f} s", flush=True)
+        _stdout = sys.stdout
+        sys.stdout = sys.stderr  # progress lines go to stderr
+    try:
+        gs = S.build_ground_state(name, device=device, verbose=verbose)
+    finally:
+        if verbose:
+            sys.stdout = _stdout
+    if verbose:
+        print(f"[synth] built {name} on {device} in {time.time() - t:.1f} s", file=sys.stderr, flush=True)
     save(gs)
     return gs

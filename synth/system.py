@@ -107,8 +107,10 @@ OLIVINE = _reg(SystemSpec(name="olivine28", cfg_id=1, cell=(19.6, 11.3, 8.9), n_
 OLIVINE_K442 = _reg(replace(OLIVINE, name="olivine28_k442", cfg_id=3, kmesh=(4, 4, 2),
                             ecut_jitter=0.0265, base=None))
 # 2x1x1 supercell of the olivine-shaped cell: 56 atoms, 8 d sites, ~2x10^4 PWs.
+# (the cutoff stays the base cell's 22.45 Ha so that the supercell is an exact replica:
+# ~2x10^4 plane waves)
 OLIVINE_SC = _reg(replace(OLIVINE, name="olivine56_sc211", cfg_id=4, cell=(39.2, 11.3, 8.9),
-                          n_atoms=56, n_hub=8, fft=(144, 45, 40), ecut=22.42, n_occ=224,
+                          n_atoms=56, n_hub=8, fft=(144, 45, 40), ecut=22.45, n_occ=224,
                           base="olivine28", rep=(2, 1, 1)))
 
 
@@ -623,6 +625,73 @@ def build_ground_state(spec: SystemSpec | str, *, backend: str = "auto", device:
     raise RuntimeError(f"{spec.name}: no gapped system within {spec.max_attempts} seeds ({last_err})")
 
 
+class _KSolver:
+    """Occupied (plus guard) eigenpairs at arbitrary k for one system; reuses time-reversal
+    partners (c_{-k}(G) = conj(c_k(-G)), same energies) and carries the last solution over
+    as the initial subspace of the next k."""
+
+    def __init__(self, shell, vloc, d_kb, nb, nconv, backend, device, tol, verbose, fft, spec):
+        self.shell, self.vloc, self.d_kb = shell, vloc, d_kb
+        self.nb, self.nconv = nb, nconv
+        self.backend, self.device, self.tol, self.verbose = backend, device, tol, verbose
+        self.fft, self.spec = fft, spec
+        self.solved = {}
+        self.last_full = None
+
+    def solve(self, k, miller, beta):
+        """Returns (eps_all[nb], U[nb, npw], max residual of the first nconv-1 states)."""
+        for kk, (m_p, e_p, u_p, r_p) in self.solved.items():
+            kp = np.array(kk)
+            s = k + kp
+            if np.all(np.abs(s - np.round(s)) < 1e-9):
+                g0 = np.round(k + kp).astype(np.int64)   # k = -kp + g0
+                lut = {tuple(m): j for j, m in enumerate(m_p)}
+                src = np.array([lut[tuple(-m - g0)] for m in miller])
+                return e_p, np.conj(u_p[:, src]), r_p
+        npw = miller.shape[0]
+        use_dense = self.backend == "dense" or (self.backend == "auto" and npw <= 3000)
+        if use_dense:
+            H = _dense_h(self.shell, self.vloc, k, miller, beta, self.d_kb)
+            w, V = np.linalg.eigh(H)
+            eps_all = w[:self.nb]
+            U = V[:, :self.nb].T.copy()
+            m = self.nconv - 1
+            res = float(np.linalg.norm(H @ U[:m].T - U[:m].T * eps_all[:m], axis=0).max())
+        else:
+            ham = _Ham(self.shell, self.vloc, k, miller, beta, self.d_kb, xp="torch", device=self.device)
+            if self.last_full is not None:
+                X0 = _map_guess(self.last_full, miller)
+            else:
+                X0 = _initial_guess(self.shell, self.vloc, k, miller, beta, self.d_kb, self.nb, self.spec)
+            eps_all, U, rn, nit = _lobpcg_torch(ham, X0, self.nconv, self.tol, 400)
+            self.last_full = (miller, U)
+            res = float(rn[:self.nconv - 1].max())
+            if self.verbose:
+                print(f"  k={np.round(k, 4)} npw={npw} lobpcg iters={nit} resid={res:.2e}", flush=True)
+        self.solved[tuple(np.asarray(k, dtype=np.float64))] = (miller, eps_all, U, res)
+        return eps_all, U, res
+
+
+def _d_kb_of(at):
+    return np.concatenate([[at.kb_d[a, 0], at.kb_d[a, 1], at.kb_d[a, 1], at.kb_d[a, 1]]
+                           for a in range(at.tau.shape[0])])
+
+
+def _finish(spec, at, vloc, entries, n_mesh, forced_gap_check, verbose, d_kb):
+    homo = max(float(e.eps.max()) for e in entries)
+    lumo = min(e.eps_next for e in entries)
+    gap = lumo - homo
+    if verbose:
+        print(f"{spec.name} attempt {at.seed_used}: gap {gap:.4f} Ha", flush=True)
+    if forced_gap_check and gap < spec.gap_min:
+        return None
+    rho0 = _density(spec, at.cell, vloc.shape, entries[:n_mesh])
+    return GroundState(spec=spec, seed_used=at.seed_used, cell=at.cell, fft=tuple(spec.fft), vloc=vloc,
+                       rho0=rho0, tau=at.tau, hub_atoms=at.hub_atoms, hub_zeta=at.hub_zeta,
+                       kb_s=at.kb_s, kb_d=at.kb_d, d_kb=d_kb, n_occ=spec.n_occ, kmesh=tuple(spec.kmesh),
+                       qmesh=tuple(spec.qmesh), kpts=entries, n_mesh=n_mesh, gap=gap)
+
+
 def _solve_all(spec, at, vloc, rj, backend, device, tol, verbose, forced_gap_check=True):
     mesh, extra = _k_entries(spec)
     ks = list(mesh) + list(extra)
@@ -631,76 +700,21 @@ def _solve_all(spec, at, vloc, rj, backend, device, tol, verbose, forced_gap_che
         keys = sorted({_pair_key(k) for k in ks})
         vals = rj.uniform(-spec.ecut_jitter, spec.ecut_jitter, len(keys))
         jit = dict(zip(keys, vals))
-    n_beta = 4 * at.tau.shape[0]
-    d_kb = np.repeat(at.kb_d, [1, 3], axis=1).reshape(-1) if False else np.concatenate(
-        [[at.kb_d[a, 0], at.kb_d[a, 1], at.kb_d[a, 1], at.kb_d[a, 1]] for a in range(at.tau.shape[0])])
+    d_kb = _d_kb_of(at)
     shell = _Shell(at.cell, at.tau, at.hub_atoms, at.hub_zeta, at.kb_s, at.kb_d)
     nb = spec.n_occ + spec.n_guard
+    solver = _KSolver(shell, vloc, d_kb, nb, spec.n_occ + 1, backend, device, tol, verbose, spec.fft, spec)
     entries = []
-    solved = {}
-    last_full = None
     for i, k in enumerate(ks):
         ecut = spec.ecut * (1.0 + jit.get(_pair_key(k), 0.0))
         miller = sphere(at.cell, k, ecut, spec.fft)
         beta, phi = projector_tables(shell, k, miller)
-        # time-reversal partner already solved?
-        partner = None
-        for (kk, data) in solved.items():
-            kp = np.array(kk)
-            s = k + kp
-            if np.all(np.abs(s - np.round(s)) < 1e-9):
-                partner = (kp, data)
-                break
-        if partner is not None:
-            kp, (m_p, e_p, u_p, en_p, r_p) = partner
-            g0 = np.round(k + kp).astype(np.int64)   # k = -kp + g0
-            # c_k(G) = conj(c_kp(-G - g0))
-            lut = {tuple(m): j for j, m in enumerate(m_p)}
-            src = np.array([lut[tuple(-m - g0)] for m in miller])
-            u = np.conj(u_p[:, src])
-            eps, eps_next, res = e_p, en_p, r_p
-        else:
-            npw = miller.shape[0]
-            use_dense = backend == "dense" or (backend == "auto" and npw <= 3000)
-            if use_dense:
-                H = _dense_h(shell, vloc, k, miller, beta, d_kb)
-                w, V = np.linalg.eigh(H)
-                eps_all = w[:nb]
-                U = V[:, :nb].T.copy()
-                resid = np.linalg.norm(H @ U[:spec.n_occ].T - U[:spec.n_occ].T * eps_all[:spec.n_occ], axis=0)
-                res = float(resid.max())
-            else:
-                ham = _Ham(shell, vloc, k, miller, beta, d_kb, xp="torch", device=device)
-                if last_full is not None:
-                    X0 = _map_guess(last_full, miller)
-                else:
-                    X0 = _initial_guess(shell, vloc, k, miller, beta, d_kb, nb, spec)
-                eps_all, U, rn, nit = _lobpcg_torch(ham, X0, spec.n_occ + 1, tol, 400)
-                last_full = (miller, U)
-                res = float(rn[:spec.n_occ].max())
-                if verbose:
-                    print(f"  k={k} npw={npw} lobpcg iters={nit} resid={res:.2e}", flush=True)
-            eps = eps_all[:spec.n_occ].copy()
-            eps_next = float(eps_all[spec.n_occ])
-            u = U[:spec.n_occ].copy()
-            solved[tuple(k)] = (miller, eps, u, eps_next, res)
+        eps_all, U, res = solver.solve(np.asarray(k, dtype=np.float64), miller, beta)
         w = 1.0 / len(mesh) if i < len(mesh) else 0.0
-        entries.append(KEntry(k_frac=np.array(k, dtype=np.float64), weight=w, ecut=ecut,
-                              miller=miller, eps=np.array(eps), u=np.ascontiguousarray(u),
-                              beta=beta, phi=phi, eps_next=eps_next, resid=res))
-    homo = max(float(e.eps.max()) for e in entries)
-    lumo = min(e.eps_next for e in entries)
-    gap = lumo - homo
-    if verbose:
-        print(f"{spec.name} attempt {at.seed_used}: gap {gap:.4f} Ha", flush=True)
-    if forced_gap_check and gap < spec.gap_min:
-        return None
-    rho0 = _density(spec, at.cell, vloc.shape, entries[:len(mesh)])
-    gs = GroundState(spec=spec, seed_used=at.seed_used, cell=at.cell, fft=tuple(spec.fft), vloc=vloc,
-                     rho0=rho0, tau=at.tau, hub_atoms=at.hub_atoms, hub_zeta=at.hub_zeta,
-                     kb_s=at.kb_s, kb_d=at.kb_d, d_kb=d_kb, n_occ=spec.n_occ, kmesh=tuple(spec.kmesh),
-                     qmesh=tuple(spec.qmesh), kpts=entries, n_mesh=len(mesh), gap=gap)
-    return gs
+        entries.append(KEntry(k_frac=np.array(k, dtype=np.float64), weight=w, ecut=ecut, miller=miller,
+                              eps=np.array(eps_all[:spec.n_occ]), u=np.ascontiguousarray(U[:spec.n_occ]),
+                              beta=beta, phi=phi, eps_next=float(eps_all[spec.n_occ]), resid=res))
+    return _finish(spec, at, vloc, entries, len(mesh), forced_gap_check, verbose, d_kb)
 
 
 @dataclass
@@ -752,20 +766,27 @@ def _density(spec, cell, fft, mesh_entries):
 
 
 def _build_replicated(spec, *, backend, device, tol, verbose):
+    """Supercell made of spec.rep copies of the base cell (atoms, potential grid, projector
+    parameters replicated exactly).  Its occupied states at a supercell k are the base cell's
+    states at the folded k_p = (k + j) / rep (j over the folds), with the same coefficients on
+    the supercell Miller indices m_sc = rep * m_p + j (same cutoff, so the supercell sphere is
+    the union of the folded primitive spheres): no supercell eigensolve is needed."""
     base_spec = SPECS[spec.base]
-    base = build_ground_state(base_spec, backend=backend, device=device, tol=tol, verbose=False)
+    from . import cache  # the base cell of a large supercell is usually cached already
+    base = cache.load(base_spec.name) if base_spec.n_occ >= 100 else None
+    if base is None:
+        base = build_ground_state(base_spec, backend=backend, device=device, tol=tol, verbose=verbose)
+    rep = np.array(spec.rep, dtype=np.int64)
     r1, r2, r3 = spec.rep
     cell = np.diag(np.array(spec.cell, dtype=np.float64))
     bcell = base.cell
+    if abs(spec.ecut - base_spec.ecut) > 1e-12 or spec.ecut_jitter or base_spec.ecut_jitter:
+        raise ValueError("a replicated supercell must keep the base cutoff")
     taus, hubs, zetas, kbs, kbd = [], [], [], [], []
-    # atoms ordered: all Hubbard sites of every image first, then the others
     nat = base.tau.shape[0]
     imgs = [(i, j, l) for i in range(r1) for j in range(r2) for l in range(r3)]
-    order = []
-    for a in list(base.hub_atoms) + [a for a in range(nat) if a not in set(base.hub_atoms.tolist())]:
-        for (i, j, l) in imgs:
-            order.append((a, (i, j, l)))
     hub_set = set(base.hub_atoms.tolist())
+    order = [(a, im) for a in list(base.hub_atoms) + [a for a in range(nat) if a not in hub_set] for im in imgs]
     for n, (a, (i, j, l)) in enumerate(order):
         taus.append(base.tau[a] + i * bcell[0] + j * bcell[1] + l * bcell[2])
         kbs.append(base.kb_s[a])
@@ -777,6 +798,41 @@ def _build_replicated(spec, *, backend, device, tol, verbose):
                 np.array(kbs), np.array(kbd), [], base.seed_used)
     vloc = np.tile(base.vloc, (r1, r2, r3))
     assert vloc.shape == tuple(spec.fft)
-    gs = _solve_all(spec, at, vloc, np.random.default_rng(0), backend, device, tol, verbose,
-                    forced_gap_check=False)
+    # primitive solver on the base system
+    bshell = _Shell(base.cell, base.tau, base.hub_atoms, base.hub_zeta, base.kb_s, base.kb_d)
+    nb_p = base_spec.n_occ + base_spec.n_guard
+    psolver = _KSolver(bshell, base.vloc, base.d_kb, nb_p, base_spec.n_occ + 1, backend, device, tol, verbose,
+                       base_spec.fft, base_spec)
+    d_kb = _d_kb_of(at)
+    shell = _Shell(at.cell, at.tau, at.hub_atoms, at.hub_zeta, at.kb_s, at.kb_d)
+    mesh, extra = _k_entries(spec)
+    entries = []
+    folds = [np.array(f) for f in imgs]
+    for i, k in enumerate(list(mesh) + list(extra)):
+        k = np.asarray(k, dtype=np.float64)
+        miller = sphere(cell, k, spec.ecut, spec.fft)
+        lut = {tuple(m): idx for idx, m in enumerate(miller)}
+        cand_e, cand_u = [], []
+        res = 0.0
+        for j in folds:
+            kp = (k + j) / rep
+            mp = sphere(bcell, kp, base_spec.ecut, base_spec.fft)
+            bp, _ = projector_tables(bshell, kp, mp)
+            e_all, U, r = psolver.solve(kp, mp, bp)
+            res = max(res, r)
+            cols = np.array([lut[tuple(rep * m + j)] for m in mp])
+            full = np.zeros((U.shape[0], miller.shape[0]), dtype=np.complex128)
+            full[:, cols] = U
+            cand_e.append(e_all)
+            cand_u.append(full)
+        e = np.concatenate(cand_e)
+        U = np.concatenate(cand_u)
+        o = np.argsort(e, kind="stable")
+        e, U = e[o], U[o]
+        beta, phi = projector_tables(shell, k, miller)
+        w = 1.0 / len(mesh) if i < len(mesh) else 0.0
+        entries.append(KEntry(k_frac=k, weight=w, ecut=spec.ecut, miller=miller, eps=e[:spec.n_occ].copy(),
+                              u=np.ascontiguousarray(U[:spec.n_occ]), beta=beta, phi=phi,
+                              eps_next=float(e[spec.n_occ]), resid=res))
+    gs = _finish(spec, at, vloc, entries, len(mesh), False, verbose, d_kb)
     return gs

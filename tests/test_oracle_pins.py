@@ -46,7 +46,7 @@ def response(name, tight=False):
 
 # --------------------------------------------------------------- Hamiltonian
 
-@pytest.mark.parametrize("name", ["sc1_gamma", "sc1_k311", "duo_k221"])
+@pytest.mark.parametrize("name", ["sc1_gamma", "sc1_k311", "duo_k221", "sc1_super211"])
 def test_generator_states_are_eigenstates_of_oracle_h(name):
     o = orc(name)
     for ie, e in enumerate(o.kpts):

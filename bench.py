@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--conv-thr-v", type=float, default=1e-8)
     ap.add_argument("--cpu-baseline-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph-chunk", type=int, default=8,
+                    help="CG iterations per captured hipGraph launch (0: launch kernels one by one)")
     return ap.parse_args()
 
 
@@ -175,7 +177,7 @@ def main():
 
     def params(prec):
         return hp.ScfParams(conv_thr_chi=args.conv_thr_chi, conv_thr_v=args.conv_thr_v, cg_tol=args.cg_tol,
-                            niter_max=100, max_cg_iter=2000, inner_tol=args.inner_tol,
+                            niter_max=100, max_cg_iter=2000, inner_tol=args.inner_tol, graph_chunk=args.graph_chunk,
                             precision=hp.HP_FP64 if prec == "fp64" else hp.HP_MIXED)
 
     def step(p):

@@ -112,6 +112,10 @@ typedef struct hp_scf_params {
   int32_t verbosity;      /* 0 silent, 1 one line per SCF iteration on stderr      */
   double inner_tol;       /* HP_MIXED: relative tolerance of each FP32 inner solve */
   int32_t max_refine;     /* HP_MIXED: FP64 refinement rounds per solve (>= 1)      */
+  int32_t graph_chunk;    /* 0: CG kernels launched one by one; 1..8: CG iterations  */
+                          /* are captured once as hipGraphs of up to this many       */
+                          /* iterations and replayed (same results, fewer launches   */
+                          /* and host round trips)                                   */
 } hp_scf_params;
 
 /* Statistics of one call (all fields written when the pointer is not NULL). */

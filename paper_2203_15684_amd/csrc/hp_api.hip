@@ -153,6 +153,30 @@ struct hp_ctx {
   std::vector<Pending> pending;
   long prof_calls[16] = {0};
   double prof_ms[16] = {0};
+  // CG iterations captured as hipGraphs: one executable graph per (operator precision,
+  // iterations per launch, profiling on/off, batch).  Every kernel of a captured iteration
+  // reads its tolerance and writes its counters through the fixed device pointers below.
+  struct CgGraph {
+    int kind, len, prof, nk;
+    const KPair *kp;
+    const double *eps;
+    hipGraphExec_t exec;
+    struct Stamp {
+      int step, id, slot;  // iteration in the chunk, kernel, stamp pair
+    };
+    std::vector<Stamp> stamps;
+  };
+  std::vector<CgGraph> graphs;
+  bool capturing = false;
+  int capture_step = 0;
+  std::vector<CgGraph::Stamp> capture_stamps;
+  // Timing inside graphs: events recorded by graph nodes cannot be queried, so a one-thread
+  // kernel writes the constant-rate device clock before and after each timed kernel.
+  unsigned long long *d_stamps = nullptr;
+  double clock_khz = 0.0;
+  double *d_tol = nullptr;  // [0] tolerance of the FP64 CG, [1] of the FP32 inner CG
+  int graph_chunk = 0;      // 0: kernels are launched one by one
+  int prev_iters[2] = {0, 0};
 
   template <class T>
   hp_status alloc(T **p, size_t count) {
@@ -203,16 +227,35 @@ hipEvent_t prof_event(hp_ctx *c) {
   return e;
 }
 
-// Enqueue `launch` bracketed by events when profiling is on.
+constexpr int kMaxStamps = 256;  // stamp pairs per captured chunk
+
+// Enqueue `launch` bracketed by events (eager) or device-clock stamps (under graph
+// capture) when profiling is on.
 template <class F>
 hipError_t timed(hp_ctx *c, int id, F launch) {
   if (!c->prof_on) return launch();
+  if (c->capturing) {
+    const int slot = (int)c->capture_stamps.size();
+    if (slot >= kMaxStamps) return launch();
+    hipError_t e = launch_clock_stamp(c->d_stamps + 2 * slot, c->stream);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = launch_clock_stamp(c->d_stamps + 2 * slot + 1, c->stream);
+    if (e != hipSuccess) return e;
+    c->capture_stamps.push_back({c->capture_step, id, slot});
+    return hipSuccess;
+  }
   hipEvent_t a = prof_event(c), b = prof_event(c);
-  if (a) (void)hipEventRecord(a, c->stream);
-  hipError_t e = launch();
-  if (b) (void)hipEventRecord(b, c->stream);
-  if (a && b) c->pending.push_back({id, a, b});
-  return e;
+  if (!a || !b) return launch();
+  hipError_t e = hipEventRecord(a, c->stream);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, c->stream);
+  if (e != hipSuccess) return e;
+  c->pending.push_back({id, a, b});
+  return hipSuccess;
 }
 
 void prof_harvest(hp_ctx *c) {
@@ -365,6 +408,139 @@ hp_status build_rhs(hp_ctx *c, const KPair *kp, int nk, int site, const double2 
   return HP_OK;
 }
 
+hp_status apply_op32(hp_ctx *c, const KPair *kp, int nk, int nb, const float2 *Xin, float2 *Y, const double *eps,
+                     int rows, const int *active);
+
+constexpr int kMaxChunk = 8;  // CG iterations per captured graph at most
+
+// Counter slots in c->count: [1] items with a non-finite residual (whole chunk),
+// [2] / [3] items above tolerance / non-finite after the mixed-precision FP64 residual,
+// [4 + i] items still above tolerance after iteration i of the chunk.
+constexpr int kCntBad = 1, kCntResid = 2, kCntStep = 4;
+
+// Enqueue `len` CG iterations of one precision (kind 0: FP64 operator and vectors,
+// kind 1: FP32 inner solve) on c->stream. Items that have converged are skipped by every
+// kernel, so iterations past convergence change nothing.
+hp_status cg_enqueue_chunk(hp_ctx *c, int kind, int len, const KPair *kp, int nk, const double *eps_items) {
+  const int nb = c->n_occ, nitems = nk * nb, rows = c->n_beta + c->n_occ;
+  HPCHK(launch_fill_int(c->count, kCntStep + len, 0, c->stream));
+  for (int i = 0; i < len; ++i) {
+    c->capture_step = i;
+    if (kind == 0) {
+      HPTRY(apply_op(c, kp, 1, nk, nb, c->P, c->AP, eps_items, rows, c->active));
+      HPCHK(timed(c, K_CG_STEP, [&] {
+        return launch_cg_step(kp, nb, nitems, c->X, c->R, c->P, c->AP, c->d_diag, eps_items, c->ld, c->d_npw, c->ld,
+                              c->rz, c->bn, c->rn, c->active, c->d_tol, c->count + kCntStep + i, c->count + kCntBad,
+                              c->stream);
+      }));
+    } else {
+      HPTRY(apply_op32(c, kp, nk, nb, c->P32, c->AP32, eps_items, rows, c->act_in));
+      HPCHK(timed(c, K_CG_STEP32, [&] {
+        return launch_cg_step32(kp, nb, nitems, c->X32, c->R32, c->P32, c->AP32, c->d_diag, eps_items, c->ld,
+                                c->d_npw, c->ld, c->rz_in, c->bn_in, c->rn_in, c->act_in, c->d_tol + 1,
+                                c->count + kCntStep + i, c->count + kCntBad, c->floor_in, c->stream);
+      }));
+    }
+  }
+  c->capture_step = 0;
+  return HP_OK;
+}
+
+// The executable graph of a chunk, captured on first use.
+hp_status cg_graph(hp_ctx *c, int kind, int len, const KPair *kp, int nk, const double *eps_items,
+                   hp_ctx::CgGraph **out) {
+  const int prof = c->prof_on ? 1 : 0;
+  for (auto &g : c->graphs)
+    if (g.kind == kind && g.len == len && g.prof == prof && g.nk == nk && g.kp == kp && g.eps == eps_items) {
+      *out = &g;
+      return HP_OK;
+    }
+  if (c->graphs.size() >= 24) {  // bounded cache: drop the oldest
+    (void)hipGraphExecDestroy(c->graphs.front().exec);
+    c->graphs.erase(c->graphs.begin());
+  }
+  HPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;
+  c->capture_stamps.clear();
+  const hp_status st = cg_enqueue_chunk(c, kind, len, kp, nk, eps_items);
+  c->capturing = false;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+  if (st != HP_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    c->capture_stamps.clear();
+    if (st != HP_OK) return st;
+    HPCHK(e);
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HPCHK(ei);
+  c->graphs.push_back({kind, len, prof, nk, kp, eps_items, exec, std::move(c->capture_stamps)});
+  c->capture_stamps.clear();
+  *out = &c->graphs.back();
+  return HP_OK;
+}
+
+// Run one chunk of up to `len` iterations, eagerly or from its graph. On return: *steps =
+// iterations that had work (the eager loop would have run exactly these), *stepped = items
+// those iterations processed, *left = items still above tolerance.
+hp_status cg_run_chunk(hp_ctx *c, int kind, int len, const KPair *kp, int nk, const double *eps_items, int active0,
+                       int *steps, long *stepped, int *left) {
+  hp_ctx::CgGraph *g = nullptr;
+  if (c->graph_chunk > 0) {
+    HPTRY(cg_graph(c, kind, len, kp, nk, eps_items, &g));
+    HPCHK(hipGraphLaunch(g->exec, c->stream));
+  } else {
+    HPTRY(cg_enqueue_chunk(c, kind, len, kp, nk, eps_items));
+  }
+  int h[kCntStep + kMaxChunk];
+  HPCHK(hipMemcpyAsync(h, c->count, sizeof(int) * (kCntStep + len), hipMemcpyDeviceToHost, c->stream));
+  std::vector<unsigned long long> stamps;
+  if (g && g->prof && !g->stamps.empty()) {
+    stamps.resize(2 * g->stamps.size());
+    HPCHK(hipMemcpyAsync(stamps.data(), c->d_stamps, sizeof(unsigned long long) * stamps.size(),
+                         hipMemcpyDeviceToHost, c->stream));
+  }
+  HPTRY(sync(c));
+  if (h[kCntBad] > 0) return fail(HP_ERR_NUMERIC, "non-finite residual in the Sternheimer solve");
+  int n = 0, entry = active0;
+  long done = 0;
+  for (int i = 0; i < len && entry > 0; ++i) {
+    ++n;
+    done += entry;
+    entry = h[kCntStep + i];
+  }
+  if (!stamps.empty()) {  // per-kernel times of the iterations that had work
+    for (const auto &t : g->stamps) {
+      if (t.step >= n) continue;
+      const unsigned long long a = stamps[2 * t.slot], b = stamps[2 * t.slot + 1];
+      c->prof_calls[t.id] += 1;
+      c->prof_ms[t.id] += b > a ? (double)(b - a) / c->clock_khz : 0.0;
+    }
+  }
+  *steps = n;
+  *stepped = done;
+  *left = entry;
+  return HP_OK;
+}
+
+// Iterations for the next chunk: a power of two no larger than graph_chunk, the iterations
+// left to max_it, or what the previous solve of this kind suggests is still to come.
+int chunk_len(hp_ctx *c, int kind, int it, int max_it) {
+  if (c->graph_chunk <= 0) return 1;
+  int want = c->prev_iters[kind] > 0 ? c->prev_iters[kind] - it : c->graph_chunk;
+  want = std::max(1, std::min(want, std::min(max_it - it, c->graph_chunk)));
+  int len = 1;
+  while (len * 2 <= want) len *= 2;
+  return len;
+}
+
+hp_status set_tol(hp_ctx *c, int slot, double tol) {
+  HPCHK(launch_fill_double(c->d_tol + slot, 1, tol, c->stream));
+  return HP_OK;
+}
+
 // Batched preconditioned CG on (H_{k+q} + alpha O_{k+q} - eps_vk) X = B (Eq. 15).
 hp_status cg_solve(hp_ctx *c, const KPair *kp, int nk, const double *eps_items, int warm, double tol, int max_it,
                    int *iters, int *not_conv, double *max_rel, long *happ) {
@@ -374,32 +550,24 @@ hp_status cg_solve(hp_ctx *c, const KPair *kp, int nk, const double *eps_items, 
   if (warm) *happ += nitems;
   HPCHK(launch_cg_init(kp, nb, nitems, c->B, c->X, c->R, c->P, c->AP, warm, c->d_diag, eps_items, c->ld, c->d_npw,
                        c->ld, c->rz, c->bn, c->rn, c->active, tol, c->stream));
-  int it = 0;
-  int h_count[2] = {0, 0};
-  // number of active items after init
-  HPCHK(hipMemsetAsync(c->count, 0, 2 * sizeof(int), c->stream));
+  HPTRY(set_tol(c, 0, tol));
+  int it = 0, left = 0;
   {
     std::vector<int> act(nitems);
     HPCHK(hipMemcpyAsync(act.data(), c->active, sizeof(int) * nitems, hipMemcpyDeviceToHost, c->stream));
     HPTRY(sync(c));
-    h_count[0] = 0;
-    for (int a : act) h_count[0] += a;
+    for (int a : act) left += a;
   }
-  while (h_count[0] > 0 && it < max_it) {
-    ++it;
-    HPTRY(apply_op(c, kp, 1, nk, nb, c->P, c->AP, eps_items, rows, c->active));
-    *happ += h_count[0];  // converged items are skipped by the operator kernels
-    HPCHK(hipMemsetAsync(c->count, 0, 2 * sizeof(int), c->stream));
-    HPCHK(timed(c, K_CG_STEP, [&] {
-      return launch_cg_step(kp, nb, nitems, c->X, c->R, c->P, c->AP, c->d_diag, eps_items, c->ld, c->d_npw, c->ld,
-                            c->rz, c->bn, c->rn, c->active, tol, c->count, c->stream);
-    }));
-    HPCHK(hipMemcpyAsync(h_count, c->count, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HPTRY(sync(c));
-    if (h_count[1] > 0) return fail(HP_ERR_NUMERIC, "non-finite residual in the Sternheimer solve");
+  while (left > 0 && it < max_it) {
+    int steps = 0;
+    long stepped = 0;
+    HPTRY(cg_run_chunk(c, 0, chunk_len(c, 0, it, max_it), kp, nk, eps_items, left, &steps, &stepped, &left));
+    it += steps;
+    *happ += stepped;  // converged items are skipped by the operator kernels
   }
+  c->prev_iters[0] = it;
   *iters = it;
-  *not_conv = h_count[0];
+  *not_conv = left;
   std::vector<double> rn(nitems), bn(nitems);
   HPCHK(hipMemcpyAsync(rn.data(), c->rn, sizeof(double) * nitems, hipMemcpyDeviceToHost, c->stream));
   HPCHK(hipMemcpyAsync(bn.data(), c->bn, sizeof(double) * nitems, hipMemcpyDeviceToHost, c->stream));
@@ -483,42 +651,37 @@ hp_status cg_solve_mixed(hp_ctx *c, const KPair *kp, int nk, const double *eps_i
   HPTRY(setup32(c));
   int it_in = 0, nact = 0, ref = 0;
   bool trusted = false;
-  int h_count[2] = {0, 0};
+  int h_count[kCntStep] = {0};
   for (ref = 0; ref <= max_refine; ++ref) {
     const int have_x = warm || ref > 0;
     if (have_x) {
       HPTRY(apply_op(c, kp, 1, nk, nb, c->X, c->AP, eps_items, rows));
       *happ64 += nitems;
     }
-    HPCHK(hipMemsetAsync(c->count, 0, 2 * sizeof(int), c->stream));
+    HPCHK(launch_fill_int(c->count, kCntStep, 0, c->stream));
     HPCHK(launch_residual64(kp, nb, nitems, c->B, c->AP, have_x, c->R, c->B32, c->ld, c->d_npw, c->bn, c->rn,
-                            c->act_out, tol, c->count, c->floor_in, c->stream));
-    HPCHK(hipMemcpyAsync(h_count, c->count, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+                            c->act_out, tol, c->count + kCntResid, c->floor_in, c->stream));
+    HPCHK(hipMemcpyAsync(h_count, c->count, kCntStep * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HPTRY(sync(c));
-    if (h_count[1] > 0) return fail(HP_ERR_NUMERIC, "non-finite residual in the Sternheimer solve");
-    nact = h_count[0];
+    if (h_count[kCntResid + 1] > 0) return fail(HP_ERR_NUMERIC, "non-finite residual in the Sternheimer solve");
+    nact = h_count[kCntResid];
     if (nact == 0 || ref == max_refine) break;
     // inner FP32 PCG on the refined items
     HPCHK(launch_cg_init32(kp, nb, nitems, c->B32, c->X32, c->R32, c->P32, c->d_diag, eps_items, c->ld, c->d_npw,
                            c->ld, c->rz_in, c->bn_in, c->rn_in, c->act_in, inner_tol, c->act_out, c->floor_in,
                            c->stream));
-    int inner_active = nact;
+    HPTRY(set_tol(c, 1, inner_tol));
+    int inner_active = nact;  // at most the refined items
     int k_in = 0;
     while (inner_active > 0 && k_in < max_it) {
-      ++k_in;
-      HPTRY(apply_op32(c, kp, nk, nb, c->P32, c->AP32, eps_items, rows, c->act_in));
-      *happ32 += inner_active;
-      HPCHK(hipMemsetAsync(c->count, 0, 2 * sizeof(int), c->stream));
-      HPCHK(timed(c, K_CG_STEP32, [&] {
-        return launch_cg_step32(kp, nb, nitems, c->X32, c->R32, c->P32, c->AP32, c->d_diag, eps_items, c->ld,
-                                c->d_npw, c->ld, c->rz_in, c->bn_in, c->rn_in, c->act_in, inner_tol, c->count,
-                                c->floor_in, c->stream);
-      }));
-      HPCHK(hipMemcpyAsync(h_count, c->count, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-      HPTRY(sync(c));
-      if (h_count[1] > 0) return fail(HP_ERR_NUMERIC, "non-finite residual in the FP32 inner solve");
-      inner_active = h_count[0];
+      int steps = 0;
+      long stepped = 0;
+      HPTRY(cg_run_chunk(c, 1, chunk_len(c, 1, k_in, max_it), kp, nk, eps_items, inner_active, &steps, &stepped,
+                         &inner_active));
+      k_in += steps;
+      *happ32 += stepped;
     }
+    c->prev_iters[1] = k_in;
     it_in += k_in;
     HPCHK(launch_refine_update(nb, nitems, c->X, c->X32, c->ld, c->act_out, have_x, c->stream));
     // Above ~1e-6 the FP32 operator is exact enough that the inner solve's own residual
@@ -622,6 +785,8 @@ hp_status check_params(const hp_scf_params *p) {
   if (p->precision != HP_FP64 && p->precision != HP_MIXED) return fail(HP_ERR_ARG, "unknown precision %d", p->precision);
   if (p->precision == HP_MIXED && (!(p->inner_tol > 0.0 && p->inner_tol < 1.0) || p->max_refine < 1))
     return fail(HP_ERR_ARG, "inner_tol must be in (0, 1) and max_refine >= 1");
+  if (p->graph_chunk < 0 || p->graph_chunk > kMaxChunk)
+    return fail(HP_ERR_ARG, "graph_chunk must be in 0..%d", kMaxChunk);
   return HP_OK;
 }
 
@@ -634,6 +799,7 @@ extern "C" const char *hp_last_error(void) { return g_err.c_str(); }
 extern "C" void hp_destroy(hp_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   for (void *p : c->allocs) (void)hipFree(p);
   for (auto &p : c->pending) {
     (void)hipEventDestroy(p.a);
@@ -727,7 +893,8 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   for (long i = 0; i < nrr; ++i)
     if (!std::isfinite(gs->v_loc[i]) || !std::isfinite(gs->rho0[i])) return fail(HP_ERR_NUMERIC, "non-finite v_loc/rho0");
 
-  std::unique_ptr<hp_ctx> c(new hp_ctx());
+  // on an early error return the partly built context, device memory included, is destroyed
+  std::unique_ptr<hp_ctx, void (*)(hp_ctx *)> c(new hp_ctx(), hp_destroy);
   for (int i = 0; i < 16; ++i) c->ev[i] = nullptr;
   c->n1 = gs->fft[0];
   c->n2 = gs->fft[1];
@@ -988,7 +1155,16 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   HPTRY(c->alloc(&c->bn, nitems));
   HPTRY(c->alloc(&c->rn, nitems));
   HPTRY(c->alloc(&c->active, nitems));
-  HPTRY(c->alloc(&c->count, 2));
+  HPTRY(c->alloc(&c->count, kCntStep + kMaxChunk));
+  HPTRY(c->alloc(&c->d_tol, 2));
+  HPTRY(c->alloc(&c->d_stamps, 2 * kMaxStamps));
+  {
+    int dev = 0, khz = 0;
+    HPCHK(hipGetDevice(&dev));
+    HPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) return fail(HP_ERR_HIP, "device reports no wall-clock rate");
+    c->clock_khz = (double)khz;
+  }
   HPTRY(c->alloc(&c->part, (size_t)c->n_mesh * c->nr));
   HPTRY(c->alloc(&c->drho, c->nr));
   HPTRY(c->alloc(&c->dvin, c->nr));
@@ -1223,6 +1399,7 @@ extern "C" hp_status hp_sternheimer_scf(hp_ctx *c, int32_t pert_site, const doub
   if (!c) return fail(HP_ERR_ARG, "context is NULL");
   if (!q_frac || !dn0_out || !dn_out) return fail(HP_ERR_ARG, "NULL argument");
   HPTRY(check_params(p));
+  c->graph_chunk = p->graph_chunk;
   if (pert_site < 0 || pert_site >= c->n_hub) return fail(HP_ERR_ARG, "pert_site %d out of range", pert_site);
   if (st && st->struct_size != sizeof(hp_scf_stats)) return fail(HP_ERR_ARG, "hp_scf_stats.struct_size mismatch");
   return run_scf(c, pert_site, q_frac, p, dn0_out, dn_out, st);
@@ -1338,6 +1515,7 @@ extern "C" hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const do
   if (!c) return fail(HP_ERR_ARG, "context is NULL");
   if (!q_frac || !du_out) return fail(HP_ERR_ARG, "NULL argument");
   HPTRY(check_params(p));
+  c->graph_chunk = p->graph_chunk;
   if (pert_site < 0 || pert_site >= c->n_hub) return fail(HP_ERR_ARG, "pert_site out of range");
   if (mesh_k < 0 || mesh_k >= c->n_mesh) return fail(HP_ERR_ARG, "mesh_k out of range");
   std::vector<KPair> pairs;

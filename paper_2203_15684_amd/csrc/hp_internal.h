@@ -134,8 +134,10 @@ hipError_t launch_cg_init(const KPair *kp, int nb, int nitems, const double2 *B,
                           double tol, hipStream_t st);
 hipError_t launch_cg_step(const KPair *kp, int nb, int nitems, double2 *Xv, double2 *R, double2 *P, const double2 *AP,
                           const double *diag, const double *eps, int ld, const int *npw_of, long diag_stride,
-                          double *rz, const double *bn, double *rn, int *active, double tol, int *count,
-                          hipStream_t st);
+                          double *rz, const double *bn, double *rn, int *active, const double *tol, int *n_active,
+                          int *n_bad, hipStream_t st);
+// (tol is read from device memory, so a captured CG iteration serves every tolerance;
+//  n_active / n_bad count the items still above tolerance / with a non-finite residual)
 // FP32 variants (mixed-precision inner solves; scalars and reductions stay FP64).
 hipError_t launch_zproj32(const KPair *kp, int use_kq, int nk, const float2 *T, long t_stride, int m0, int M,
                           const float2 *X, int ld, int nb, const int *npw_of, float2 *Cpart, int nsplit,
@@ -151,8 +153,13 @@ hipError_t launch_cg_init32(const KPair *kp, int nb, int nitems, const float2 *B
                             const double *floor_abs, hipStream_t st);
 hipError_t launch_cg_step32(const KPair *kp, int nb, int nitems, float2 *Xv, float2 *R, float2 *P, const float2 *AP,
                             const double *diag, const double *eps, int ld, const int *npw_of, long diag_stride,
-                            double *rz, const double *bn, double *rn, int *active, double tol, int *count,
-                            const double *floor_abs, hipStream_t st);
+                            double *rz, const double *bn, double *rn, int *active, const double *tol,
+                            int *n_active, int *n_bad, const double *floor_abs, hipStream_t st);
+// p[0..n) = v (a kernel, so that it can sit inside a captured graph)
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t st);
+hipError_t launch_fill_double(double *p, int n, double v, hipStream_t st);
+// *p = device wall clock (constant rate, hipDeviceAttributeWallClockRate kHz)
+hipError_t launch_clock_stamp(unsigned long long *p, hipStream_t st);
 // R = B - AX (FP64; AX ignored when !have_x), R32 = (float) R, per-item norms and active flags.
 hipError_t launch_residual64(const KPair *kp, int nb, int nitems, const double2 *B, const double2 *AX, int have_x,
                              double2 *R, float2 *R32, int ld, const int *npw_of, double *bn, double *rn, int *active,

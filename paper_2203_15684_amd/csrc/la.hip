@@ -302,11 +302,13 @@ __global__ void __launch_bounds__(256) k_cg_step(const KPair *kp, int nb, C2 *__
                                                  C2 *__restrict__ P, const C2 *__restrict__ AP,
                                                  const double *__restrict__ diag, const double *__restrict__ eps,
                                                  int ld, const int *__restrict__ npw_of, long diag_stride,
-                                                 double *rz, const double *bn, double *rn, int *active, double tol,
-                                                 int *count, const double *floor_abs) {
+                                                 double *rz, const double *bn, double *rn, int *active,
+                                                 const double *tol_p, int *n_active, int *n_bad,
+                                                 const double *floor_abs) {
   __shared__ double red[8];
   const int item = blockIdx.x;
   if (!active[item]) return;
+  const double tol = *tol_p;
   const int k = item / nb;
   const int e = kp[k].ej;
   const int npw = npw_of[e];
@@ -354,8 +356,8 @@ __global__ void __launch_bounds__(256) k_cg_step(const KPair *kp, int nb, C2 *__
     const double thr = floor_abs ? fmax(tol * bn[item], floor_abs[item]) : tol * bn[item];
     const int still = (r_ > thr && isfinite(r_)) ? 1 : 0;
     active[item] = still;
-    if (still) atomicAdd(count, 1);
-    if (!isfinite(r_)) atomicAdd(count + 1, 1);
+    if (still) atomicAdd(n_active, 1);
+    if (!isfinite(r_)) atomicAdd(n_bad, 1);
   }
 }
 
@@ -563,18 +565,47 @@ hipError_t launch_cg_init32(const KPair *kp, int nb, int nitems, const float2 *B
 
 hipError_t launch_cg_step(const KPair *kp, int nb, int nitems, double2 *Xv, double2 *R, double2 *P,
                           const double2 *AP, const double *diag, const double *eps, int ld, const int *npw_of,
-                          long diag_stride, double *rz, const double *bn, double *rn, int *active, double tol,
-                          int *count, hipStream_t st) {
+                          long diag_stride, double *rz, const double *bn, double *rn, int *active, const double *tol,
+                          int *n_active, int *n_bad, hipStream_t st) {
   hipLaunchKernelGGL(k_cg_step<double2>, dim3(nitems), dim3(256), 0, st, kp, nb, Xv, R, P, AP, diag, eps, ld, npw_of,
-                     diag_stride, rz, bn, rn, active, tol, count, (const double *)nullptr);
+                     diag_stride, rz, bn, rn, active, tol, n_active, n_bad, (const double *)nullptr);
   return hipGetLastError();
 }
 hipError_t launch_cg_step32(const KPair *kp, int nb, int nitems, float2 *Xv, float2 *R, float2 *P, const float2 *AP,
                             const double *diag, const double *eps, int ld, const int *npw_of, long diag_stride,
-                            double *rz, const double *bn, double *rn, int *active, double tol, int *count,
-                            const double *floor_abs, hipStream_t st) {
+                            double *rz, const double *bn, double *rn, int *active, const double *tol, int *n_active,
+                            int *n_bad, const double *floor_abs, hipStream_t st) {
   hipLaunchKernelGGL(k_cg_step<float2>, dim3(nitems), dim3(256), 0, st, kp, nb, Xv, R, P, AP, diag, eps, ld, npw_of,
-                     diag_stride, rz, bn, rn, active, tol, count, floor_abs);
+                     diag_stride, rz, bn, rn, active, tol, n_active, n_bad, floor_abs);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_int(int *p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_double(double *p, int n, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_double(double *p, int n, double v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_double, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+// One thread stores the constant-rate device clock (a vector store: the address depends on
+// the thread index).
+__global__ void k_clock_stamp(unsigned long long *p) { p[threadIdx.x] = (unsigned long long)wall_clock64(); }
+
+hipError_t launch_clock_stamp(unsigned long long *p, hipStream_t st) {
+  hipLaunchKernelGGL(k_clock_stamp, dim3(1), dim3(1), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
 

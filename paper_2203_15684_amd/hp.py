@@ -62,7 +62,7 @@ class HpScfParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("conv_thr_chi", C.c_double), ("conv_thr_v", C.c_double),
                 ("cg_tol", C.c_double), ("niter_max", C.c_int32), ("alpha_mix", C.c_double), ("nmix", C.c_int32),
                 ("max_cg_iter", C.c_int32), ("precision", C.c_int32), ("verbosity", C.c_int32),
-                ("inner_tol", C.c_double), ("max_refine", C.c_int32)]
+                ("inner_tol", C.c_double), ("max_refine", C.c_int32), ("graph_chunk", C.c_int32)]
 
 
 class HpScfStats(C.Structure):
@@ -146,11 +146,12 @@ class ScfParams:
     verbosity: int = 0
     inner_tol: float = 1e-4
     max_refine: int = 12
+    graph_chunk: int = 8   # CG iterations per captured hipGraph launch; 0 launches kernels one by one
 
     def c(self) -> HpScfParams:
         return HpScfParams(C.sizeof(HpScfParams), self.conv_thr_chi, self.conv_thr_v, self.cg_tol, self.niter_max,
                            self.alpha_mix, self.nmix, self.max_cg_iter, self.precision, self.verbosity,
-                           self.inner_tol, self.max_refine)
+                           self.inner_tol, self.max_refine, self.graph_chunk)
 
 
 class Context:

@@ -116,6 +116,10 @@ typedef struct hp_scf_params {
                           /* are captured once as hipGraphs of up to this many       */
                           /* iterations and replayed (same results, fewer launches   */
                           /* and host round trips)                                   */
+  int32_t autotune;       /* 1: on first use of a launch shape, time the candidate    */
+                          /* GEMM tiles / K splits and FFT plane batches on this      */
+                          /* device and keep the fastest (cached in the context);    */
+                          /* 0: fixed default shapes                                  */
 } hp_scf_params;
 
 /* Statistics of one call (all fields written when the pointer is not NULL). */
@@ -200,9 +204,12 @@ hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const double q_frac
 
 /* ---- Per-kernel timing ------------------------------------------------------
  * hp_profile_start enables and resets per-kernel GPU timing on the context's
- * stream (HIP events around each launch of the main kernels); hp_profile_stop
- * synchronizes, disables timing and writes up to `max` records (kernel name,
- * launches, summed GPU milliseconds).  *n_out receives the number written. */
+ * stream (HIP events around each launch; inside CG iterations replayed from
+ * hipGraphs, device-clock stamps written by one-thread kernels before and after
+ * each timed kernel, since events recorded by graph nodes cannot be queried);
+ * hp_profile_stop synchronizes, disables timing and writes up to `max` records
+ * (kernel name, launches, summed GPU milliseconds).  *n_out receives the number
+ * written. */
 typedef struct hp_kernel_time {
   const char *name;       /* static string owned by the library */
   int64_t calls;
@@ -211,6 +218,28 @@ typedef struct hp_kernel_time {
 
 hp_status hp_profile_start(hp_ctx *c);
 hp_status hp_profile_stop(hp_ctx *c, hp_kernel_time *out, int32_t max, int32_t *n_out);
+
+/* ---- Autotuner report --------------------------------------------------------
+ * JSON text (NUL-terminated, into buf of len bytes) of the launch shapes the
+ * autotuner chose in this context: per GEMM shape (precision, rows, batch) the
+ * projection tile, K split and expansion band tile with the measured and the
+ * default times (ms), and per precision the chosen plane-batch variant of the
+ * local-potential FFT with every variant's time.  HP_ERR_ARG if buf is too small. */
+hp_status hp_tuning_report(hp_ctx *c, char *buf, int32_t len);
+
+/* Pin launch shapes instead of timing them (used when hp_scf_params.autotune = 1;
+ * a pinned shape is never re-tuned).  GEMM shape key: prec (64 or 32), rows of the
+ * projector table (n_beta + n_occ for H, n_occ for P_c, 5 n_hub and 5 for the
+ * Hubbard terms), batch (mesh points per launch, 1..n_mesh).  tile 0..3 =
+ * projection workgroup tile 32x32, 64x32, 32x64, 64x64 (rows x bands); nsplit =
+ * K split of the projection, 1..16; expand_bands = 32, 64 or 128 bands per
+ * expansion workgroup.  Plane variant 0..2 of the local-potential FFT round trip
+ * (0: one z plane per 256-thread workgroup, 1: two per 256, 2: two per 512; only
+ * 0 unless N3 is even, the plane is 72x45, 144x45 or 30x24 and two planes fit in
+ * LDS).  Errors: HP_ERR_ARG for values out of range. */
+hp_status hp_set_gemm_shape(hp_ctx *c, int32_t prec, int32_t rows, int32_t batch, int32_t tile, int32_t nsplit,
+                            int32_t expand_bands);
+hp_status hp_set_plane_variant(hp_ctx *c, int32_t prec, int32_t variant);
 
 #ifdef __cplusplus
 }

@@ -314,6 +314,22 @@ struct BaseAffine {  // line l starts at l * stride
   int stride;
   __device__ __forceinline__ int operator()(int l) const { return l * stride; }
 };
+// Batches of planes (np points each): line l is line l % n of plane l / n.
+struct BaseListB {
+  const int *xs;
+  int mul, n, np;
+  __device__ __forceinline__ int operator()(int l) const {
+    const int p = l / n;
+    return p * np + xs[l - p * n] * mul;
+  }
+};
+template <int N, int NP>
+struct BaseAffineB {
+  __device__ __forceinline__ int operator()(int l) const {
+    const int p = l / N;
+    return p * NP + (l - p * N);
+  }
+};
 
 template <int N, int S, bool DIF, class BaseF, class C>
 __device__ __forceinline__ void cstage(C *__restrict__ P, const C *__restrict__ tw, int nlines, const BaseF &base,
@@ -371,10 +387,11 @@ __device__ __forceinline__ const float2 *axis_tw<float2>(const Axis &a) {
   return a.tw32;
 }
 
-template <int N1, int N2, class C = double2>
+template <int N1, int N2, class C = double2, int PB = 1>
 struct PlaneCtx {
+  static_assert(PB == 1 || (N1 > 0 && N2 > 0), "plane batches need compile-time plane sizes");
   const Plane &pl;
-  C *P;      // [n1*n2]
+  C *P;      // [PB][n1*n2]
   C *twx;    // [n1] (LDS copy)
   C *twy;    // [n2]
   int *xs;   // [n1] active x columns, shifted and wrapped
@@ -384,7 +401,7 @@ struct PlaneCtx {
   __device__ __forceinline__ int np() const { return n1() * n2(); }
   __device__ __forceinline__ PlaneCtx(const Plane &p, void *lds) : pl(p) {
     P = reinterpret_cast<C *>(lds);
-    twx = P + np();
+    twx = P + PB * np();
     twy = twx + n1();
     xs = reinterpret_cast<int *>(twy + n2());
     nxa = 0;
@@ -405,7 +422,9 @@ struct PlaneCtx {
   }
   template <bool DIF>
   __device__ __forceinline__ void y_lines() {  // lines at the listed x, contiguous, length N2
-    if constexpr (N2 > 0) {
+    if constexpr (PB > 1) {
+      cfft<N2, DIF, 0>(P, twy, nxa * PB, BaseListB{xs, N2, nxa, N1 * N2}, 1);
+    } else if constexpr (N2 > 0) {
       cfft<N2, DIF, 0>(P, twy, nxa, BaseList{xs, N2}, 1);
     } else {
       fft_lines(P, twy, pl.ay, nxa, xs, pl.n2, pl.n1, 0, 0, 1, DIF);
@@ -413,7 +432,9 @@ struct PlaneCtx {
   }
   template <bool DIF>
   __device__ __forceinline__ void x_lines() {  // every y, stride N2, length N1
-    if constexpr (N1 > 0) {
+    if constexpr (PB > 1) {
+      cfft<N1, DIF, 0>(P, twx, N2 * PB, BaseAffineB<N2, N1 * N2>{}, N2);
+    } else if constexpr (N1 > 0) {
       cfft<N1, DIF, 0>(P, twx, N2, BaseAffine{1}, N2);
     } else {
       fft_lines(P, twx, pl.ax, pl.n2, nullptr, 0, 1, 0, 1, pl.n2, DIF);
@@ -424,8 +445,8 @@ struct PlaneCtx {
   }
 };
 
-int plane_lds_t(const Plane &pl, int csize = (int)sizeof(double2)) {
-  return pl.n1 * pl.n2 * csize + (pl.n1 + pl.n2) * csize + pl.n1 * (int)sizeof(int);
+int plane_lds_t(const Plane &pl, int csize = (int)sizeof(double2), int pb = 1) {
+  return pb * pl.n1 * pl.n2 * csize + (pl.n1 + pl.n2) * csize + pl.n1 * (int)sizeof(int);
 }
 
 // ----------------------------------------------------------------- kernels
@@ -577,6 +598,46 @@ __global__ void __launch_bounds__(kThreads) k_plane_vloc(Plane pl, Sticks sk, co
   pc.template x_lines<false>();
   pc.template y_lines<false>();
   for (int s = threadIdx.x; s < E.ns; s += blockDim.x) Sout[so + s] = P[pc.pos(sx[s], sy[s], g0x, g0y)];
+}
+
+// The same round trip for PB consecutive z planes of one item per workgroup of NT threads
+// (the transform stages then run over PB times as many lines per barrier).
+template <int N1, int N2, class C, int PB, int NT>
+__global__ void __launch_bounds__(NT) k_plane_vloc_b(Plane pl, Sticks sk, const KPair *kp, int use_kq, int nb,
+                                                     const C *__restrict__ Sin, C *__restrict__ Sout, int ns_pad,
+                                                     const RealOf<C> *__restrict__ vp, const int *active) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int item = blockIdx.y;
+  if (active && !active[item]) return;
+  PlaneCtx<N1, N2, C, PB> pc(pl, lds);
+  constexpr int np = N1 * N2;
+  const int z0 = blockIdx.x * PB;
+  const int k = item / nb;
+  int e, g0x, g0y, g0z;
+  basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
+  const EntryDev E = sk.ent[e];
+  C *P = pc.P;
+  plane_zero(P, PB * np);
+  pc.set_active(sk.xa + E.xa_off, E.nxa, g0x);
+  const int *sx = sk.sx + E.st_off;
+  const int *sy = sk.sy + E.st_off;
+  const size_t so = ((size_t)item * pl.n3 + z0) * ns_pad;
+  for (int w = threadIdx.x; w < PB * E.ns; w += NT) {
+    const int p = w / E.ns, s = w - p * E.ns;
+    P[p * np + pc.pos(sx[s], sy[s], g0x, g0y)] = Sin[so + (size_t)p * ns_pad + s];
+  }
+  __syncthreads();
+  pc.template y_lines<true>();
+  pc.template x_lines<true>();
+  const RealOf<C> *v = vp + (size_t)z0 * np;
+  for (int i = threadIdx.x; i < PB * np; i += NT) P[i] = cscale(P[i], v[i]);
+  __syncthreads();
+  pc.template x_lines<false>();
+  pc.template y_lines<false>();
+  for (int w = threadIdx.x; w < PB * E.ns; w += NT) {
+    const int p = w / E.ns, s = w - p * E.ns;
+    Sout[so + (size_t)p * ns_pad + s] = P[p * np + pc.pos(sx[s], sy[s], g0x, g0y)];
+  }
 }
 
 template <int N1, int N2>
@@ -904,19 +965,67 @@ hipError_t launch_stick_fwd32(const Sticks &sk, const KPair *kp, int use_kq, int
                      max_chunk_pw, ns_max, active, st);
 }
 
+constexpr int kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
+
+int plane_vloc_variants(const Plane &pl, int csize) {
+  const int key = pl.n1 * 1000 + pl.n2;
+  const bool ok = pl.n3 % 2 == 0 && (key == 72045 || key == 144045 || key == 30024) &&
+                  plane_lds_t(pl, csize, 2) <= kLdsBytes;
+  return ok ? 3 : 1;
+}
+
+// Plane-batch variants of the local-potential round trip: 0 = one plane per 256 threads,
+// 1 = two planes per 256 threads, 2 = two planes per 512 threads.
+namespace {
+template <int N1, int N2, class C>
+hipError_t plane_vloc_batched(int variant, const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb,
+                              int nitems, const C *Sin, C *Sout, int ns_pad, const RealOf<C> *vp, const int *active,
+                              hipStream_t st) {
+  const size_t lds = plane_lds_t(pl, sizeof(C), 2);
+  if (variant == 1)
+    hipLaunchKernelGGL((k_plane_vloc_b<N1, N2, C, 2, 256>), dim3(pl.n3 / 2, nitems), dim3(256), lds, st, pl, sk, kp,
+                       use_kq, nb, Sin, Sout, ns_pad, vp, active);
+  else
+    hipLaunchKernelGGL((k_plane_vloc_b<N1, N2, C, 2, 512>), dim3(pl.n3 / 2, nitems), dim3(512), lds, st, pl, sk, kp,
+                       use_kq, nb, Sin, Sout, ns_pad, vp, active);
+  return hipGetLastError();
+}
+
+template <class C>
+hipError_t plane_vloc_t(int variant, const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb,
+                        int nitems, const C *Sin, C *Sout, int ns_pad, const RealOf<C> *vp, const int *active,
+                        hipStream_t st) {
+  if (variant > 0 && plane_vloc_variants(pl, sizeof(C)) > 1) {
+    switch (pl.n1 * 1000 + pl.n2) {
+      case 72045:
+        return plane_vloc_batched<72, 45, C>(variant, pl, sk, kp, use_kq, nb, nitems, Sin, Sout, ns_pad, vp, active,
+                                             st);
+      case 144045:
+        return plane_vloc_batched<144, 45, C>(variant, pl, sk, kp, use_kq, nb, nitems, Sin, Sout, ns_pad, vp,
+                                              active, st);
+      case 30024:
+        return plane_vloc_batched<30, 24, C>(variant, pl, sk, kp, use_kq, nb, nitems, Sin, Sout, ns_pad, vp, active,
+                                             st);
+      default:
+        break;
+    }
+  }
+  HP_PLANE_DISPATCH_T(k_plane_vloc, COMMA C, dim3(pl.n3, nitems), plane_lds_t(pl, sizeof(C)), st, pl, sk, kp, use_kq,
+                      nb, Sin, Sout, ns_pad, vp, active);
+  return hipGetLastError();
+}
+}  // namespace
+
+
 hipError_t launch_plane_vloc(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
                              const double2 *Sin, double2 *Sout, int ns_pad, const double *vp, const int *active,
-                             hipStream_t st) {
-  HP_PLANE_DISPATCH_T(k_plane_vloc, COMMA double2, dim3(pl.n3, nitems), plane_lds_t(pl, sizeof(double2)), st, pl, sk,
-                      kp, use_kq, nb, Sin, Sout, ns_pad, vp, active);
-  return hipGetLastError();
+                             int variant, hipStream_t st) {
+  return plane_vloc_t<double2>(variant, pl, sk, kp, use_kq, nb, nitems, Sin, Sout, ns_pad, vp, active, st);
 }
 hipError_t launch_plane_vloc32(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
                                const float2 *Sin, float2 *Sout, int ns_pad, const float *vp, const int *active,
-                               hipStream_t st) {
-  HP_PLANE_DISPATCH_T(k_plane_vloc, COMMA float2, dim3(pl.n3, nitems), plane_lds_t(pl, sizeof(float2)), st, pl, sk,
-                      kp, use_kq, nb, Sin, Sout, ns_pad, vp, active);
-  return hipGetLastError();
+                               int variant, hipStream_t st) {
+  return plane_vloc_t<float2>(variant, pl, sk, kp, use_kq, nb, nitems, Sin, Sout, ns_pad, vp, active, st);
 }
 
 hipError_t launch_plane_to_real(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,

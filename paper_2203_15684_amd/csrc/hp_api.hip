@@ -151,8 +151,8 @@ struct hp_ctx {
     hipEvent_t a, b;
   };
   std::vector<Pending> pending;
-  long prof_calls[16] = {0};
-  double prof_ms[16] = {0};
+  long prof_calls[32] = {0};
+  double prof_ms[32] = {0};
   // CG iterations captured as hipGraphs: one executable graph per (operator precision,
   // iterations per launch, profiling on/off, batch).  Every kernel of a captured iteration
   // reads its tolerance and writes its counters through the fixed device pointers below.
@@ -174,6 +174,20 @@ struct hp_ctx {
   // kernel writes the constant-rate device clock before and after each timed kernel.
   unsigned long long *d_stamps = nullptr;
   double clock_khz = 0.0;
+  // Launch shapes chosen by timing candidates on this device (tune_* below): per GEMM
+  // shape (precision, rows, batch) the projection tile, its K split and the expansion band
+  // tile; per precision the plane-batch variant of the local-potential FFT round trip.
+  struct GemmChoice {
+    int prec, M, nk;
+    int tile, ns, bv;
+    float proj_ms, expand_ms, proj_default_ms, expand_default_ms;
+  };
+  std::vector<GemmChoice> gemm_tuned;
+  int plane_var[2] = {0, 0};  // [0] FP64, [1] FP32
+  int plane_nvar[2] = {0, 0};
+  float plane_ms[2][4] = {};
+  bool plane_tuned[2] = {false, false};
+  int use_tuned = 0;  // hp_scf_params.autotune of the current call
   double *d_tol = nullptr;  // [0] tolerance of the FP64 CG, [1] of the FP32 inner CG
   int graph_chunk = 0;      // 0: kernels are launched one by one
   int prev_iters[2] = {0, 0};
@@ -209,12 +223,24 @@ enum KernelId {
   K_ZPROJ32,
   K_ZEXPAND32,
   K_CG_STEP32,
+  K_ZPROJ_REDUCE,
+  K_CG_INIT,
+  K_RESIDUAL64,
+  K_REFINE,
+  K_RHS,
+  K_DRHO_STICKS,
+  K_DRHO_REDUCE,
+  K_HXC,
+  K_DN,
+  K_MIX,
   K_COUNT
 };
-const char *const kKernelNames[K_COUNT] = {"stick_inv",     "plane_vloc",   "stick_fwd",    "zproj",
-                                           "zexpand",       "cg_step",      "plane_drho",   "plane_mul_fwd",
-                                           "stick_inv32",   "plane_vloc32", "stick_fwd32",  "zproj32",
-                                           "zexpand32",     "cg_step32"};
+static_assert(K_COUNT <= 32, "profile slots");
+const char *const kKernelNames[K_COUNT] = {
+    "stick_inv",   "plane_vloc",   "stick_fwd",   "zproj",       "zexpand",     "cg_step",
+    "plane_drho",  "plane_mul_fwd", "stick_inv32", "plane_vloc32", "stick_fwd32", "zproj32",
+    "zexpand32",   "cg_step32",    "zproj_reduce", "cg_init",     "residual64",  "refine_update",
+    "rhs_other",   "drho_sticks",  "drho_reduce", "hxc",         "dn",          "mixing"};
 
 hipEvent_t prof_event(hp_ctx *c) {
   if (!c->ev_pool.empty()) {
@@ -349,15 +375,32 @@ int choose_nsplit(int M, int nb, int nk, int npw_max) {
   return ns;
 }
 
+// Launch shape of a GEMM: the tuned one when tuning is on and the shape has been tuned,
+// else 32x32 projection tiles, the K split of choose_nsplit and 32-band expansion tiles.
+struct GemmShape {
+  int tile, ns, bv;
+};
+GemmShape gemm_shape(const hp_ctx *c, int prec, int M, int nk) {
+  if (c->use_tuned)
+    for (const auto &g : c->gemm_tuned)
+      if (g.prec == prec && g.M == M && g.nk == nk) return {g.tile, g.ns, g.bv};
+  return {0, choose_nsplit(M, c->n_occ, nk, c->npw_max), 1};
+}
+int plane_variant(const hp_ctx *c, int prec) { return c->use_tuned ? c->plane_var[prec == 32 ? 1 : 0] : 0; }
+
 // C[k][m][v] = scale_m * sum_G conj(T[m0+m][G]) X[k,v][G]
 hp_status proj(hp_ctx *c, const KPair *kp, int use_kq, int nk, const double2 *T, long tstride, int m0, int M,
                const double2 *X, int nb, const double *row_scale, double gscale, double2 *Cout,
                const int *active = nullptr) {
-  const int ns = choose_nsplit(M, nb, nk, c->npw_max);
+  const GemmShape gs = gemm_shape(c, 64, M, nk);
+  const int ns = gs.ns;
   HPCHK(timed(c, K_ZPROJ, [&] {
-    return launch_zproj(kp, use_kq, nk, T, tstride, m0, M, X, c->ld, nb, c->d_npw, c->Cpart, ns, active, c->stream);
+    return launch_zproj(kp, use_kq, nk, T, tstride, m0, M, X, c->ld, nb, c->d_npw, c->Cpart, ns, active, gs.tile,
+                        c->stream);
   }));
-  HPCHK(launch_zproj_reduce(nk, M, nb, ns, c->Cpart, row_scale, gscale, Cout, c->stream));
+  HPCHK(timed(c, K_ZPROJ_REDUCE, [&] {
+    return launch_zproj_reduce(nk, M, nb, ns, c->Cpart, row_scale, gscale, Cout, c->stream);
+  }));
   return HP_OK;
 }
 
@@ -372,7 +415,7 @@ hp_status apply_op(hp_ctx *c, const KPair *kp, int use_kq, int nk, int nb, const
   }));
   HPCHK(timed(c, K_PLANE_VLOC, [&] {
     return launch_plane_vloc(c->pl, c->sk, kp, use_kq, nb, nitems, c->S1, c->S2, c->ns_pad, c->d_vp, active,
-                             c->stream);
+                             plane_variant(c, 64), c->stream);
   }));
   HPCHK(timed(c, K_STICK_FWD, [&] {
     return launch_stick_fwd(c->sk, kp, use_kq, nb, nitems, c->S2, c->ns_pad, c->n3, c->az.tw, 1.0 / (double)c->nr, Y,
@@ -381,7 +424,7 @@ hp_status apply_op(hp_ctx *c, const KPair *kp, int use_kq, int nk, int nb, const
   HPTRY(proj(c, kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, Xin, nb, c->d_rowscale, 1.0, c->C, active));
   HPCHK(timed(c, K_ZEXPAND, [&] {
     return launch_zexpand(kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, c->C, (long)rows * nb, 1.0, Y, c->ld, nb,
-                          c->d_npw, c->npw_max, active, c->stream);
+                          c->d_npw, c->npw_max, active, gemm_shape(c, 64, rows, nk).bv, c->stream);
   }));
   return HP_OK;
 }
@@ -393,18 +436,26 @@ hp_status build_rhs(hp_ctx *c, const KPair *kp, int nk, int site, const double2 
     HPCHK(timed(c, K_PLANE_MUL, [&] {
       return launch_plane_mul_fwd(c->pl, c->sk, kp, nb, nitems, psi, dv, c->S1, c->ns_pad, c->stream);
     }));
-    HPCHK(launch_stick_fwd(c->sk, kp, 1, nb, nitems, c->S1, c->ns_pad, c->n3, c->az.tw, -1.0 / (double)c->nr, c->B,
-                           c->ld, 2, nullptr, nullptr, nullptr, nb, c->max_chunk_pw, c->ns_max, nullptr, c->stream));
+    HPCHK(timed(c, K_RHS, [&] {
+      return launch_stick_fwd(c->sk, kp, 1, nb, nitems, c->S1, c->ns_pad, c->n3, c->az.tw, -1.0 / (double)c->nr, c->B,
+                              c->ld, 2, nullptr, nullptr, nullptr, nb, c->max_chunk_pw, c->ns_max, nullptr, c->stream);
+    }));
   } else {
     HPCHK(hipMemsetAsync(c->B, 0, sizeof(double2) * (size_t)nitems * c->ld, c->stream));
   }
   // - sum_m |phi_{m,k+q}> <phi_{m,k}|u_vk>   (Eq. 16)
-  HPCHK(launch_zexpand(kp, 1, nk, c->d_phi, c->phi_stride, 5 * site, 5, c->d_A + (size_t)5 * site * nb,
-                       (long)5 * c->n_hub * nb, -1.0, c->B, c->ld, nb, c->d_npw, c->npw_max, nullptr, c->stream));
+  HPCHK(timed(c, K_RHS, [&] {
+    return launch_zexpand(kp, 1, nk, c->d_phi, c->phi_stride, 5 * site, 5, c->d_A + (size_t)5 * site * nb,
+                          (long)5 * c->n_hub * nb, -1.0, c->B, c->ld, nb, c->d_npw, c->npw_max, nullptr,
+                          gemm_shape(c, 64, 5, nk).bv, c->stream);
+  }));
   // P_c = 1 - sum_v' |u_v',k+q><u_v',k+q|   (Eq. 18)
   HPTRY(proj(c, kp, 1, nk, c->d_T, c->t_stride, c->n_beta, c->n_occ, c->B, nb, nullptr, 1.0, c->C));
-  HPCHK(launch_zexpand(kp, 1, nk, c->d_T, c->t_stride, c->n_beta, c->n_occ, c->C, (long)c->n_occ * nb, -1.0, c->B,
-                       c->ld, c->n_occ, c->d_npw, c->npw_max, nullptr, c->stream));
+  HPCHK(timed(c, K_RHS, [&] {
+    return launch_zexpand(kp, 1, nk, c->d_T, c->t_stride, c->n_beta, c->n_occ, c->C, (long)c->n_occ * nb, -1.0, c->B,
+                          c->ld, c->n_occ, c->d_npw, c->npw_max, nullptr, gemm_shape(c, 64, c->n_occ, nk).bv,
+                          c->stream);
+  }));
   return HP_OK;
 }
 
@@ -548,8 +599,10 @@ hp_status cg_solve(hp_ctx *c, const KPair *kp, int nk, const double *eps_items, 
   const int rows = c->n_beta + c->n_occ;
   if (warm) HPTRY(apply_op(c, kp, 1, nk, nb, c->X, c->AP, eps_items, rows));
   if (warm) *happ += nitems;
-  HPCHK(launch_cg_init(kp, nb, nitems, c->B, c->X, c->R, c->P, c->AP, warm, c->d_diag, eps_items, c->ld, c->d_npw,
-                       c->ld, c->rz, c->bn, c->rn, c->active, tol, c->stream));
+  HPCHK(timed(c, K_CG_INIT, [&] {
+    return launch_cg_init(kp, nb, nitems, c->B, c->X, c->R, c->P, c->AP, warm, c->d_diag, eps_items, c->ld, c->d_npw,
+                          c->ld, c->rz, c->bn, c->rn, c->active, tol, c->stream);
+  }));
   HPTRY(set_tol(c, 0, tol));
   int it = 0, left = 0;
   {
@@ -622,22 +675,153 @@ hp_status apply_op32(hp_ctx *c, const KPair *kp, int nk, int nb, const float2 *X
                               c->max_chunk_pw, c->ns_max, active, c->stream);
   }));
   HPCHK(timed(c, K_PLANE_VLOC32, [&] {
-    return launch_plane_vloc32(c->pl32, c->sk, kp, 1, nb, nitems, S1, S2, c->ns_pad, c->vp32, active, c->stream);
+    return launch_plane_vloc32(c->pl32, c->sk, kp, 1, nb, nitems, S1, S2, c->ns_pad, c->vp32, active,
+                               plane_variant(c, 32), c->stream);
   }));
   HPCHK(timed(c, K_STICK_FWD32, [&] {
     return launch_stick_fwd32(c->sk, kp, 1, nb, nitems, S2, c->ns_pad, c->n3, c->az32.tw32, 1.0 / (double)c->nr, Y,
                               c->ld, 0, c->d_kin, eps, Xin, nb, c->max_chunk_pw, c->ns_max, active, c->stream);
   }));
-  const int ns = choose_nsplit(rows, nb, nk, c->npw_max);
+  const GemmShape gs = gemm_shape(c, 32, rows, nk);
+  const int ns = gs.ns;
   HPCHK(timed(c, K_ZPROJ32, [&] {
     return launch_zproj32(kp, 1, nk, c->T32, c->t_stride, 0, rows, Xin, c->ld, nb, c->d_npw, Cpart, ns, active,
-                          c->stream);
+                          gs.tile, c->stream);
   }));
-  HPCHK(launch_zproj_reduce32(nk, rows, nb, ns, Cpart, c->d_rowscale, 1.0, C, c->stream));
+  HPCHK(timed(c, K_ZPROJ_REDUCE, [&] {
+    return launch_zproj_reduce32(nk, rows, nb, ns, Cpart, c->d_rowscale, 1.0, C, c->stream);
+  }));
   HPCHK(timed(c, K_ZEXPAND32, [&] {
     return launch_zexpand32(kp, 1, nk, c->T32, c->t_stride, 0, rows, C, (long)rows * nb, 1.0, Y, c->ld, nb,
-                            c->d_npw, c->npw_max, active, c->stream);
+                            c->d_npw, c->npw_max, active, gs.bv, c->stream);
   }));
+  return HP_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Candidates are timed on this device with the context's own buffers at the start of a
+// call, before any of them holds state: the GEMMs write the K-split partials (Cpart), the
+// projections (C) and the operator outputs (AP / AP32), the plane kernels the stick buffers
+// (S1 / S2). The tile and plane-batch choices do not change any arithmetic; the K split
+// changes the order of the partial sums (last-bit differences).
+
+template <class F>
+hp_status time_launch(hp_ctx *c, F launch, int reps, float *ms) {
+  HPCHK(launch());  // warm-up (code load, caches)
+  HPCHK(hipEventRecord(c->ev[10], c->stream));
+  for (int r = 0; r < reps; ++r) HPCHK(launch());
+  HPCHK(hipEventRecord(c->ev[11], c->stream));
+  HPCHK(hipEventSynchronize(c->ev[11]));
+  float t = 0.f;
+  HPCHK(hipEventElapsedTime(&t, c->ev[10], c->ev[11]));
+  *ms = t / (float)reps;
+  return HP_OK;
+}
+
+hp_status tune_gemm(hp_ctx *c, int prec, int M, int nk) {
+  for (const auto &g : c->gemm_tuned)
+    if (g.prec == prec && g.M == M && g.nk == nk) return HP_OK;
+  if (M > c->n_proj) return HP_OK;  // timed against the first M rows of the stacked table
+  const int nb = c->n_occ;
+  const KPair *kp = c->d_kp;
+  const int ns_default = choose_nsplit(M, nb, nk, c->npw_max);
+  hp_ctx::GemmChoice best{prec, M, nk, 0, ns_default, 1, 1e30f, 1e30f, 0.f, 0.f};
+  std::vector<int> splits{ns_default};  // the default first, then powers of two
+  for (int ns = 1; ns <= c->nsplit_cap && (ns == 1 || c->npw_max / ns >= 256); ns *= 2)
+    if (ns != ns_default) splits.push_back(ns);
+  for (int tile = 0; tile < 4; ++tile)
+    for (int ns : splits) {
+      float ms = 0.f;
+      if (prec == 64) {
+        HPTRY(time_launch(c, [&] {
+          hipError_t e = launch_zproj(kp, 1, nk, c->d_T, c->t_stride, 0, M, c->X, c->ld, nb, c->d_npw, c->Cpart, ns,
+                                      nullptr, tile, c->stream);
+          if (e != hipSuccess) return e;
+          return launch_zproj_reduce(nk, M, nb, ns, c->Cpart, nullptr, 1.0, c->C, c->stream);
+        }, 2, &ms));
+      } else {
+        float2 *Cpart = reinterpret_cast<float2 *>(c->Cpart), *C = reinterpret_cast<float2 *>(c->C);
+        HPTRY(time_launch(c, [&] {
+          hipError_t e = launch_zproj32(kp, 1, nk, c->T32, c->t_stride, 0, M, c->X32, c->ld, nb, c->d_npw, Cpart, ns,
+                                        nullptr, tile, c->stream);
+          if (e != hipSuccess) return e;
+          return launch_zproj_reduce32(nk, M, nb, ns, Cpart, nullptr, 1.0, C, c->stream);
+        }, 2, &ms));
+      }
+      if (tile == 0 && ns == ns_default) best.proj_default_ms = ms;
+      if (ms < best.proj_ms) {
+        best.proj_ms = ms;
+        best.tile = tile;
+        best.ns = ns;
+      }
+    }
+  for (int bv = 1; bv <= 4; bv *= 2) {
+    float ms = 0.f;
+    if (prec == 64) {
+      HPTRY(time_launch(c, [&] {
+        return launch_zexpand(kp, 1, nk, c->d_T, c->t_stride, 0, M, c->C, (long)M * nb, 1.0, c->AP, c->ld, nb,
+                              c->d_npw, c->npw_max, nullptr, bv, c->stream);
+      }, 2, &ms));
+    } else {
+      const float2 *C = reinterpret_cast<const float2 *>(c->C);
+      HPTRY(time_launch(c, [&] {
+        return launch_zexpand32(kp, 1, nk, c->T32, c->t_stride, 0, M, C, (long)M * nb, 1.0, c->AP32, c->ld, nb,
+                                c->d_npw, c->npw_max, nullptr, bv, c->stream);
+      }, 2, &ms));
+    }
+    if (bv == 1) best.expand_default_ms = ms;
+    if (ms < best.expand_ms) {
+      best.expand_ms = ms;
+      best.bv = bv;
+    }
+  }
+  c->gemm_tuned.push_back(best);
+  return HP_OK;
+}
+
+hp_status tune_plane(hp_ctx *c, int prec, int nk) {
+  const int slot = prec == 32 ? 1 : 0;
+  if (c->plane_tuned[slot]) return HP_OK;
+  const int nb = c->n_occ, nitems = nk * nb;
+  const int nv = plane_vloc_variants(prec == 32 ? c->pl32 : c->pl, prec == 32 ? (int)sizeof(float2)
+                                                                              : (int)sizeof(double2));
+  float best = 1e30f;
+  for (int v = 0; v < nv; ++v) {
+    float ms = 0.f;
+    if (prec == 64) {
+      HPTRY(time_launch(c, [&] {
+        return launch_plane_vloc(c->pl, c->sk, c->d_kp, 1, nb, nitems, c->S1, c->S2, c->ns_pad, c->d_vp, nullptr, v,
+                                 c->stream);
+      }, 2, &ms));
+    } else {
+      float2 *S1 = reinterpret_cast<float2 *>(c->S1), *S2 = reinterpret_cast<float2 *>(c->S2);
+      HPTRY(time_launch(c, [&] {
+        return launch_plane_vloc32(c->pl32, c->sk, c->d_kp, 1, nb, nitems, S1, S2, c->ns_pad, c->vp32, nullptr, v,
+                                   c->stream);
+      }, 2, &ms));
+    }
+    c->plane_ms[slot][v] = ms;
+    if (ms < best) {
+      best = ms;
+      c->plane_var[slot] = v;
+    }
+  }
+  c->plane_nvar[slot] = nv;
+  c->plane_tuned[slot] = true;
+  return HP_OK;
+}
+
+// Tune every launch shape a call on nk mesh points will use (c->d_kp must hold its pairs).
+hp_status autotune(hp_ctx *c, int nk, int mixed) {
+  if (!c->use_tuned) return HP_OK;
+  const int rows = c->n_beta + c->n_occ;
+  for (int M : {rows, c->n_occ, 5 * c->n_hub, 5}) HPTRY(tune_gemm(c, 64, M, nk));
+  HPTRY(tune_plane(c, 64, nk));
+  if (mixed) {
+    HPTRY(setup32(c));
+    HPTRY(tune_gemm(c, 32, rows, nk));
+    HPTRY(tune_plane(c, 32, nk));
+  }
   return HP_OK;
 }
 
@@ -659,17 +843,21 @@ hp_status cg_solve_mixed(hp_ctx *c, const KPair *kp, int nk, const double *eps_i
       *happ64 += nitems;
     }
     HPCHK(launch_fill_int(c->count, kCntStep, 0, c->stream));
-    HPCHK(launch_residual64(kp, nb, nitems, c->B, c->AP, have_x, c->R, c->B32, c->ld, c->d_npw, c->bn, c->rn,
-                            c->act_out, tol, c->count + kCntResid, c->floor_in, c->stream));
+    HPCHK(timed(c, K_RESIDUAL64, [&] {
+      return launch_residual64(kp, nb, nitems, c->B, c->AP, have_x, c->R, c->B32, c->ld, c->d_npw, c->bn, c->rn,
+                               c->act_out, tol, c->count + kCntResid, c->floor_in, c->stream);
+    }));
     HPCHK(hipMemcpyAsync(h_count, c->count, kCntStep * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HPTRY(sync(c));
     if (h_count[kCntResid + 1] > 0) return fail(HP_ERR_NUMERIC, "non-finite residual in the Sternheimer solve");
     nact = h_count[kCntResid];
     if (nact == 0 || ref == max_refine) break;
     // inner FP32 PCG on the refined items
-    HPCHK(launch_cg_init32(kp, nb, nitems, c->B32, c->X32, c->R32, c->P32, c->d_diag, eps_items, c->ld, c->d_npw,
-                           c->ld, c->rz_in, c->bn_in, c->rn_in, c->act_in, inner_tol, c->act_out, c->floor_in,
-                           c->stream));
+    HPCHK(timed(c, K_CG_INIT, [&] {
+      return launch_cg_init32(kp, nb, nitems, c->B32, c->X32, c->R32, c->P32, c->d_diag, eps_items, c->ld, c->d_npw,
+                              c->ld, c->rz_in, c->bn_in, c->rn_in, c->act_in, inner_tol, c->act_out, c->floor_in,
+                              c->stream);
+    }));
     HPTRY(set_tol(c, 1, inner_tol));
     int inner_active = nact;  // at most the refined items
     int k_in = 0;
@@ -683,7 +871,9 @@ hp_status cg_solve_mixed(hp_ctx *c, const KPair *kp, int nk, const double *eps_i
     }
     c->prev_iters[1] = k_in;
     it_in += k_in;
-    HPCHK(launch_refine_update(nb, nitems, c->X, c->X32, c->ld, c->act_out, have_x, c->stream));
+    HPCHK(timed(c, K_REFINE, [&] {
+      return launch_refine_update(nb, nitems, c->X, c->X32, c->ld, c->act_out, have_x, c->stream);
+    }));
     // Above ~1e-6 the FP32 operator is exact enough that the inner solve's own residual
     // stands for the FP64 one; the next SCF iteration starts from an FP64 residual anyway.
     if (tol >= kFp32TrustTol && inner_active == 0) {
@@ -765,7 +955,9 @@ bool csolve(int n, std::vector<std::complex<double>> A, std::vector<std::complex
 hp_status zdots(hp_ctx *c, int nvec, const double2 *const *vecs, const double2 *b, long n,
                 std::vector<std::complex<double>> &out) {
   HPCHK(hipMemcpyAsync(c->ptrs, vecs, sizeof(double2 *) * nvec, hipMemcpyHostToDevice, c->stream));
-  HPCHK(launch_zdots(nvec, c->ptrs, b, n, c->dots_part, c->dots, c->stream));
+  HPCHK(timed(c, K_MIX, [&] {
+    return launch_zdots(nvec, c->ptrs, b, n, c->dots_part, c->dots, c->stream);
+  }));
   std::vector<double2> h(nvec);
   HPCHK(hipMemcpyAsync(h.data(), c->dots, sizeof(double2) * nvec, hipMemcpyDeviceToHost, c->stream));
   HPTRY(sync(c));
@@ -787,6 +979,7 @@ hp_status check_params(const hp_scf_params *p) {
     return fail(HP_ERR_ARG, "inner_tol must be in (0, 1) and max_refine >= 1");
   if (p->graph_chunk < 0 || p->graph_chunk > kMaxChunk)
     return fail(HP_ERR_ARG, "graph_chunk must be in 0..%d", kMaxChunk);
+  if (p->autotune != 0 && p->autotune != 1) return fail(HP_ERR_ARG, "autotune must be 0 or 1");
   return HP_OK;
 }
 
@@ -1210,6 +1403,7 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
   const int nb = c->n_occ, nk = c->n_mesh, nitems = nk * nb;
   std::vector<KPair> pairs;
   HPTRY(upload_pairs(c, site, q, pairs));
+  HPTRY(autotune(c, nk, p->precision == HP_MIXED));
   HPCHK(hipMemcpyAsync(c->d_q, q, sizeof(double) * 3, hipMemcpyHostToDevice, c->stream));
   const long nr = c->nr;
   HPCHK(hipMemsetAsync(c->dvin, 0, sizeof(double2) * nr, c->stream));
@@ -1243,17 +1437,25 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
     not_conv = nc;
     max_rel = mr;
     // response density (spin x time reversal) and occupations (Eq. 13)
-    HPCHK(launch_stick_inv(c->sk, c->d_kp, 1, nb, nitems, c->X, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
-                           c->max_chunk_pw, c->ns_max, nullptr, c->stream));
+    HPCHK(timed(c, K_DRHO_STICKS, [&] {
+      return launch_stick_inv(c->sk, c->d_kp, 1, nb, nitems, c->X, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
+                              c->max_chunk_pw, c->ns_max, nullptr, c->stream);
+    }));
     HPCHK(timed(c, K_PLANE_DRHO, [&] {
       return launch_plane_drho(c->pl, c->sk, c->d_kp, nb, nk, c->S1, c->ns_pad, c->d_psi, c->part, c->stream);
     }));
-    HPCHK(launch_drho_reduce(c->d_kp, nk, c->part, nr, 1.0 / c->omega, c->drho, c->stream));
+    HPCHK(timed(c, K_DRHO_REDUCE, [&] {
+      return launch_drho_reduce(c->d_kp, nk, c->part, nr, 1.0 / c->omega, c->drho, c->stream);
+    }));
     HPCHK(hipEventRecord(c->ev[3], c->stream));
-    HPCHK(launch_hxc(c->pl, c->az, c->d_bvec, q, c->drho, c->d_fxc, c->tmp, c->dvout, c->stream));
+    HPCHK(timed(c, K_HXC, [&] {
+      return launch_hxc(c->pl, c->az, c->d_bvec, q, c->drho, c->d_fxc, c->tmp, c->dvout, c->stream);
+    }));
     HPCHK(hipEventRecord(c->ev[4], c->stream));
     HPTRY(proj(c, c->d_kp, 1, nk, c->d_phi, c->phi_stride, 0, 5 * c->n_hub, c->X, nb, nullptr, 1.0, c->Cphi));
-    HPCHK(launch_dn(c->d_kp, nk, c->n_hub, nb, c->d_A, c->Cphi, c->dn, c->stream));
+    HPCHK(timed(c, K_DN, [&] {
+      return launch_dn(c->d_kp, nk, c->n_hub, nb, c->d_A, c->Cphi, c->dn, c->stream);
+    }));
     HPCHK(hipMemcpyAsync(dn.data(), c->dn, sizeof(double2) * dn.size(), hipMemcpyDeviceToHost, c->stream));
     HPCHK(hipEventRecord(c->ev[5], c->stream));
     HPTRY(sync(c));
@@ -1267,7 +1469,9 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
     }
     if (it == 1) dn0 = dn;
     // mixing residual f = dV_out - dV_in
-    HPCHK(launch_zsub(nr, c->dvout, c->dvin, c->f, c->stream));
+    HPCHK(timed(c, K_MIX, [&] {
+      return launch_zsub(nr, c->dvout, c->dvin, c->f, c->stream);
+    }));
     std::vector<std::complex<double>> nrm;
     {
       const double2 *v2[2] = {c->f, c->dvout};
@@ -1306,14 +1510,22 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
       // new history pair from (f - f_prev, dv_in - dv_prev)
       double2 *df = c->hdf + (size_t)hist_head * nr;
       double2 *dvh = c->hdv + (size_t)hist_head * nr;
-      HPCHK(launch_zsub(nr, c->f, c->fprev, df, c->stream));
-      HPCHK(launch_zsub(nr, c->dvin, c->dvprev, dvh, c->stream));
+      HPCHK(timed(c, K_MIX, [&] {
+        return launch_zsub(nr, c->f, c->fprev, df, c->stream);
+      }));
+      HPCHK(timed(c, K_MIX, [&] {
+        return launch_zsub(nr, c->dvin, c->dvprev, dvh, c->stream);
+      }));
       std::vector<std::complex<double>> d1;
       const double2 *v1[1] = {df};
       HPTRY(zdots(c, 1, v1, df, nr, d1));
       const double nd = std::sqrt(std::max(d1[0].real(), 1e-300));
-      HPCHK(launch_zscale_copy(nr, df, 1.0 / nd, df, c->stream));
-      HPCHK(launch_zscale_copy(nr, dvh, 1.0 / nd, dvh, c->stream));
+      HPCHK(timed(c, K_MIX, [&] {
+        return launch_zscale_copy(nr, df, 1.0 / nd, df, c->stream);
+      }));
+      HPCHK(timed(c, K_MIX, [&] {
+        return launch_zscale_copy(nr, dvh, 1.0 / nd, dvh, c->stream);
+      }));
       const int slot = hist_head;
       hist_head = (hist_head + 1) % nmix;
       nhist = std::min(nhist + 1, nmix);
@@ -1363,7 +1575,9 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
     }
     HPCHK(hipMemcpyAsync(c->ptrs, xs.data(), sizeof(double2 *) * xs.size(), hipMemcpyHostToDevice, c->stream));
     HPCHK(hipMemcpyAsync(c->coef, cf.data(), sizeof(double2) * cf.size(), hipMemcpyHostToDevice, c->stream));
-    HPCHK(launch_zaxpy_list(nr, c->dvin, (int)xs.size(), c->ptrs, c->coef, c->stream));
+    HPCHK(timed(c, K_MIX, [&] {
+      return launch_zaxpy_list(nr, c->dvin, (int)xs.size(), c->ptrs, c->coef, c->stream);
+    }));
     HPTRY(sync(c));
     stage[4] += tm.s();
   }
@@ -1400,6 +1614,7 @@ extern "C" hp_status hp_sternheimer_scf(hp_ctx *c, int32_t pert_site, const doub
   if (!q_frac || !dn0_out || !dn_out) return fail(HP_ERR_ARG, "NULL argument");
   HPTRY(check_params(p));
   c->graph_chunk = p->graph_chunk;
+  c->use_tuned = p->autotune;
   if (pert_site < 0 || pert_site >= c->n_hub) return fail(HP_ERR_ARG, "pert_site %d out of range", pert_site);
   if (st && st->struct_size != sizeof(hp_scf_stats)) return fail(HP_ERR_ARG, "hp_scf_stats.struct_size mismatch");
   return run_scf(c, pert_site, q_frac, p, dn0_out, dn_out, st);
@@ -1516,12 +1731,14 @@ extern "C" hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const do
   if (!q_frac || !du_out) return fail(HP_ERR_ARG, "NULL argument");
   HPTRY(check_params(p));
   c->graph_chunk = p->graph_chunk;
+  c->use_tuned = p->autotune;
   if (pert_site < 0 || pert_site >= c->n_hub) return fail(HP_ERR_ARG, "pert_site out of range");
   if (mesh_k < 0 || mesh_k >= c->n_mesh) return fail(HP_ERR_ARG, "mesh_k out of range");
   std::vector<KPair> pairs;
   HPTRY(upload_pairs(c, pert_site, q_frac, pairs));
   const KPair P = pairs[mesh_k];
   HPCHK(hipMemcpyAsync(c->d_kp, &P, sizeof(KPair), hipMemcpyHostToDevice, c->stream));
+  HPTRY(autotune(c, 1, p->precision == HP_MIXED));
   const int nb = c->n_occ;
   const double2 *psi = c->d_psi + (size_t)mesh_k * nb * c->nr;
   const double *eps = c->d_eps + (size_t)mesh_k * nb;
@@ -1565,7 +1782,7 @@ extern "C" hp_status hp_profile_start(hp_ctx *c) {
   if (!c) return fail(HP_ERR_ARG, "context is NULL");
   HPTRY(sync(c));
   c->prof_on = true;
-  for (int i = 0; i < 16; ++i) {
+  for (int i = 0; i < K_COUNT; ++i) {
     c->prof_calls[i] = 0;
     c->prof_ms[i] = 0.0;
   }
@@ -1586,5 +1803,71 @@ extern "C" hp_status hp_profile_stop(hp_ctx *c, hp_kernel_time *out, int32_t max
     ++n;
   }
   if (n_out) *n_out = std::min(n, max);
+  return HP_OK;
+}
+
+extern "C" hp_status hp_tuning_report(hp_ctx *c, char *buf, int32_t len) {
+  if (!c || !buf || len < 1) return fail(HP_ERR_ARG, "NULL argument or len < 1");
+  static const char *const kTile[4] = {"32x32", "64x32", "32x64", "64x64"};
+  std::string o = "{\"gemm\": [";
+  char line[512];
+  for (size_t i = 0; i < c->gemm_tuned.size(); ++i) {
+    const auto &g = c->gemm_tuned[i];
+    snprintf(line, sizeof line,
+             "%s{\"prec\": %d, \"rows\": %d, \"batch\": %d, \"proj_tile\": \"%s\", \"nsplit\": %d, "
+             "\"expand_bands\": %d, \"proj_ms\": %.4f, \"proj_default_ms\": %.4f, \"expand_ms\": %.4f, "
+             "\"expand_default_ms\": %.4f}",
+             i ? ", " : "", g.prec, g.M, g.nk, kTile[g.tile & 3], g.ns, 32 * g.bv, g.proj_ms, g.proj_default_ms,
+             g.expand_ms, g.expand_default_ms);
+    o += line;
+  }
+  o += "], \"plane\": [";
+  bool first = true;
+  for (int slot = 0; slot < 2; ++slot) {
+    if (!c->plane_tuned[slot]) continue;
+    snprintf(line, sizeof line, "%s{\"prec\": %d, \"variant\": %d, \"ms\": [", first ? "" : ", ",
+             slot ? 32 : 64, c->plane_var[slot]);
+    o += line;
+    for (int v = 0; v < c->plane_nvar[slot]; ++v) {
+      snprintf(line, sizeof line, "%s%.4f", v ? ", " : "", c->plane_ms[slot][v]);
+      o += line;
+    }
+    o += "]}";
+    first = false;
+  }
+  o += "]}";
+  if ((int32_t)o.size() + 1 > len) return fail(HP_ERR_ARG, "buffer too small (%d bytes needed)", (int)o.size() + 1);
+  memcpy(buf, o.c_str(), o.size() + 1);
+  return HP_OK;
+}
+
+extern "C" hp_status hp_set_gemm_shape(hp_ctx *c, int32_t prec, int32_t rows, int32_t batch, int32_t tile,
+                                       int32_t nsplit, int32_t expand_bands) {
+  if (!c) return fail(HP_ERR_ARG, "context is NULL");
+  if (prec != 64 && prec != 32) return fail(HP_ERR_ARG, "prec must be 64 or 32");
+  if (rows < 1 || batch < 1 || batch > c->n_mesh) return fail(HP_ERR_ARG, "bad rows/batch");
+  if (tile < 0 || tile > 3) return fail(HP_ERR_ARG, "tile must be in 0..3");
+  if (nsplit < 1 || nsplit > c->nsplit_cap) return fail(HP_ERR_ARG, "nsplit must be in 1..%d", c->nsplit_cap);
+  if (expand_bands != 32 && expand_bands != 64 && expand_bands != 128)
+    return fail(HP_ERR_ARG, "expand_bands must be 32, 64 or 128");
+  hp_ctx::GemmChoice g{prec, rows, batch, tile, nsplit, expand_bands / 32, 0.f, 0.f, 0.f, 0.f};
+  for (auto &e : c->gemm_tuned)
+    if (e.prec == prec && e.M == rows && e.nk == batch) {
+      e = g;
+      return HP_OK;
+    }
+  c->gemm_tuned.push_back(g);
+  return HP_OK;
+}
+
+extern "C" hp_status hp_set_plane_variant(hp_ctx *c, int32_t prec, int32_t variant) {
+  if (!c) return fail(HP_ERR_ARG, "context is NULL");
+  if (prec != 64 && prec != 32) return fail(HP_ERR_ARG, "prec must be 64 or 32");
+  const int slot = prec == 32 ? 1 : 0;
+  const int nv = plane_vloc_variants(c->pl, prec == 32 ? (int)sizeof(float2) : (int)sizeof(double2));
+  if (variant < 0 || variant >= nv) return fail(HP_ERR_ARG, "variant must be in 0..%d for this grid", nv - 1);
+  c->plane_var[slot] = variant;
+  c->plane_nvar[slot] = nv;
+  c->plane_tuned[slot] = true;
   return HP_OK;
 }

@@ -88,11 +88,14 @@ hipError_t launch_stick_fwd32(const Sticks &sk, const KPair *kp, int use_kq, int
                               int max_chunk_pw, int ns_max, const int *active, hipStream_t st);
 hipError_t launch_plane_vloc32(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
                                const float2 *Sin, float2 *Sout, int ns_pad, const float *vp, const int *active,
-                               hipStream_t st);
+                               int variant, hipStream_t st);
 // Plane round trip for the local potential: sticks -> r (DIF) -> * vp -> sticks (reverse).
+// variant (0 .. plane_vloc_variants(pl) - 1): 0 = one z plane per 256-thread workgroup,
+// 1 = two planes per 256 threads, 2 = two planes per 512 threads (even N3, some plane sizes).
 hipError_t launch_plane_vloc(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
                              const double2 *Sin, double2 *Sout, int ns_pad, const double *vp, const int *active,
-                             hipStream_t st);
+                             int variant, hipStream_t st);
+int plane_vloc_variants(const Plane &pl, int complex_bytes);
 // Sticks -> real-space plane (permuted layout), R[item][z][plane].
 hipError_t launch_plane_to_real(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
                                 const double2 *Sin, int ns_pad, double2 *R, hipStream_t st);
@@ -119,13 +122,15 @@ hipError_t launch_fxc(const double *rho, double *fxc, long n, hipStream_t st);
 // proj:   Cpart -> C[k][m][v] = row_scale[m] * gscale * sum_G conj(T_e[m0+m][G]) X[k*nb+v][G]
 hipError_t launch_zproj(const KPair *kp, int use_kq, int nk, const double2 *T, long t_stride, int m0, int M,
                         const double2 *X, int ld, int nb, const int *npw_of, double2 *Cpart, int nsplit,
-                        const int *active, hipStream_t st);
+                        const int *active, int tile, hipStream_t st);
 hipError_t launch_zproj_reduce(int nk, int M, int nb, int nsplit, const double2 *Cpart, const double *row_scale,
                                double gscale, double2 *C, hipStream_t st);
 // expand: Y[k*nb+v][G] += cscale * sum_m T_e[m0+m][G] C[k*c_kstride + m*nb + v]
 hipError_t launch_zexpand(const KPair *kp, int use_kq, int nk, const double2 *T, long t_stride, int m0, int M,
                           const double2 *C, long c_kstride, double cscale, double2 *Y, int ld, int nb,
-                          const int *npw_of, int npw_max, const int *active, hipStream_t st);
+                          const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st);
+// tile (projection): workgroup tile 0 = 32x32, 1 = 64 rows x 32 bands, 2 = 32 x 64, 3 = 64 x 64;
+// bv (expansion): 32 bv bands x 64 plane waves per workgroup, bv in {1, 2, 4}.
 // The `active` arguments (nullable) skip items, or 32-band tiles, whose flag is 0.
 // preconditioned CG (one workgroup per item)
 hipError_t launch_cg_init(const KPair *kp, int nb, int nitems, const double2 *B, double2 *Xv, double2 *R, double2 *P,
@@ -141,12 +146,12 @@ hipError_t launch_cg_step(const KPair *kp, int nb, int nitems, double2 *Xv, doub
 // FP32 variants (mixed-precision inner solves; scalars and reductions stay FP64).
 hipError_t launch_zproj32(const KPair *kp, int use_kq, int nk, const float2 *T, long t_stride, int m0, int M,
                           const float2 *X, int ld, int nb, const int *npw_of, float2 *Cpart, int nsplit,
-                          const int *active, hipStream_t st);
+                          const int *active, int tile, hipStream_t st);
 hipError_t launch_zproj_reduce32(int nk, int M, int nb, int nsplit, const float2 *Cpart, const double *row_scale,
                                  double gscale, float2 *C, hipStream_t st);
 hipError_t launch_zexpand32(const KPair *kp, int use_kq, int nk, const float2 *T, long t_stride, int m0, int M,
                             const float2 *C, long c_kstride, double cscale, float2 *Y, int ld, int nb,
-                            const int *npw_of, int npw_max, const int *active, hipStream_t st);
+                            const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st);
 hipError_t launch_cg_init32(const KPair *kp, int nb, int nitems, const float2 *B, float2 *Xv, float2 *R, float2 *P,
                             const double *diag, const double *eps, int ld, const int *npw_of, long diag_stride,
                             double *rz, double *bn, double *rn, int *active, double tol, const int *only,

@@ -44,12 +44,14 @@ __device__ __forceinline__ C zc() {
   return r;
 }
 
-constexpr int kTile = 32;   // output tile (rows x cols) of the projection GEMM
 constexpr int kKb = 16;     // K step staged through LDS
 constexpr int kPad = 1;     // LDS row padding (complex elements)
 
 // C[k][m][v] (partial over a K split) = sum_G conj(T[m0+m][G]) X[v][G].
-template <class T>
+// Workgroup tile (32 WM rows) x (32 WN bands), four waves in a 2 x 2 arrangement, each
+// holding WM x WN 16x16 MFMA blocks; the next K slab is prefetched into registers while
+// the current one is multiplied out of LDS.
+template <class T, int WM, int WN>
 __global__ void __launch_bounds__(256) k_zproj(const KPair *kp, int use_kq, const typename Mf<T>::c2 *__restrict__ Tb,
                                                long t_stride, int m0, int M,
                                                const typename Mf<T>::c2 *__restrict__ X, int ld, int nb,
@@ -57,13 +59,16 @@ __global__ void __launch_bounds__(256) k_zproj(const KPair *kp, int use_kq, cons
                                                typename Mf<T>::c2 *__restrict__ Cpart, int nk, const int *active) {
   using C2 = typename Mf<T>::c2;
   using A4 = typename Mf<T>::acc;
-  __shared__ C2 At[kTile][kKb + kPad];
-  __shared__ C2 Bt[kTile][kKb + kPad];
+  constexpr int TM = 32 * WM, TN = 32 * WN;
+  __shared__ C2 At[TM][kKb + kPad];
+  __shared__ C2 Bt[TN][kKb + kPad];
   const int k = blockIdx.z / nsplit;
   const int split = blockIdx.z - k * nsplit;
-  if (active) {  // skip tiles whose 32 bands are all converged (their outputs are not used)
-    const int v = blockIdx.y * kTile + (threadIdx.x & 31);
-    const int a = (threadIdx.x < 32 && v < nb) ? active[k * nb + v] : 0;
+  const int mt = blockIdx.x * TM;
+  const int nt = blockIdx.y * TN;
+  if (active) {  // skip tiles whose bands are all converged (their outputs are not used)
+    int a = 0;
+    for (int i = threadIdx.x; i < TN; i += 256) a |= (nt + i < nb) ? active[k * nb + nt + i] : 0;
     if (!__syncthreads_or(a)) return;
   }
   const KPair P = kp[k];
@@ -72,48 +77,78 @@ __global__ void __launch_bounds__(256) k_zproj(const KPair *kp, int use_kq, cons
   const int chunk = ((npw + nsplit - 1) / nsplit + kKb - 1) / kKb * kKb;
   const int g_begin = split * chunk;
   const int g_end = min(npw, g_begin + chunk);
-  const int mt = blockIdx.x * kTile;
-  const int nt = blockIdx.y * kTile;
   const C2 *Te = Tb + (size_t)e * t_stride + (size_t)m0 * ld;
   const C2 *Xk = X + (size_t)k * nb * ld;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  A4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-  const int lr = threadIdx.x >> 3;       // 0..31 row for loads
-  const int lc = (threadIdx.x & 7) * 2;  // 0..14 column pair
-  for (int g0 = g_begin; g0 < g_end; g0 += kKb) {
-    for (int c = 0; c < 2; ++c) {
-      const int g = g0 + lc + c;
-      const int row = mt + lr;
-      At[lr][lc + c] = (row < M && g < g_end) ? Te[(size_t)row * ld + g] : zc<C2>();
-      const int col = nt + lr;
-      Bt[lr][lc + c] = (col < nb && g < g_end) ? Xk[(size_t)col * ld + g] : zc<C2>();
+  A4 cr[WM][WN], ci[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      cr[i][j] = A4{0, 0, 0, 0};
+      ci[i][j] = A4{0, 0, 0, 0};
     }
+  const int lr = threadIdx.x >> 4;  // 0..15: row within a 16-row group
+  const int lc = threadIdx.x & 15;  // 0..15: K column
+  C2 ra[2 * WM], rb[2 * WN];
+  auto load = [&](int g0) {
+    const int g = g0 + lc;
+#pragma unroll
+    for (int i = 0; i < 2 * WM; ++i) {
+      const int row = mt + lr + 16 * i;
+      ra[i] = (row < M && g < g_end) ? Te[(size_t)row * ld + g] : zc<C2>();
+    }
+#pragma unroll
+    for (int i = 0; i < 2 * WN; ++i) {
+      const int col = nt + lr + 16 * i;
+      rb[i] = (col < nb && g < g_end) ? Xk[(size_t)col * ld + g] : zc<C2>();
+    }
+  };
+  if (g_begin < g_end) load(g_begin);
+  for (int g0 = g_begin; g0 < g_end; g0 += kKb) {
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < kKb; kk += 4) {
-      const C2 a = At[wm * 16 + (lane & 15)][kk + (lane >> 4)];
-      const C2 b = Bt[wn * 16 + (lane & 15)][kk + (lane >> 4)];
-      // conj(a) * b
-      cr = mfma(a.x, b.x, cr);
-      cr = mfma(a.y, b.y, cr);
-      ci = mfma(a.x, b.y, ci);
-      ci = mfma(-a.y, b.x, ci);
-    }
+    for (int i = 0; i < 2 * WM; ++i) At[lr + 16 * i][lc] = ra[i];
+#pragma unroll
+    for (int i = 0; i < 2 * WN; ++i) Bt[lr + 16 * i][lc] = rb[i];
     __syncthreads();
+    if (g0 + kKb < g_end) load(g0 + kKb);
+#pragma unroll
+    for (int kk = 0; kk < kKb; kk += 4) {
+      C2 a[WM], b[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) a[i] = At[(wm * WM + i) * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < WN; ++j) b[j] = Bt[(wn * WN + j) * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {  // conj(a) * b
+          cr[i][j] = mfma(a[i].x, b[j].x, cr[i][j]);
+          cr[i][j] = mfma(a[i].y, b[j].y, cr[i][j]);
+          ci[i][j] = mfma(a[i].x, b[j].y, ci[i][j]);
+          ci[i][j] = mfma(-a[i].y, b[j].x, ci[i][j]);
+        }
+    }
   }
   C2 *Cp = Cpart + ((size_t)split * nk + k) * (size_t)M * nb;
-  for (int r = 0; r < 4; ++r) {
-    const int m = mt + wm * 16 + Mf<T>::row(lane, r);
-    const int v = nt + wn * 16 + (lane & 15);
-    if (m < M && v < nb) {
-      C2 o;
-      o.x = cr[r];
-      o.y = ci[r];
-      Cp[(size_t)m * nb + v] = o;
-    }
-  }
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = mt + (wm * WM + i) * 16 + Mf<T>::row(lane, r);
+        const int v = nt + (wn * WN + j) * 16 + (lane & 15);
+        if (m < M && v < nb) {
+          C2 o;
+          o.x = cr[i][j][r];
+          o.y = ci[i][j][r];
+          Cp[(size_t)m * nb + v] = o;
+        }
+      }
 }
 
 template <class C2>
@@ -135,8 +170,10 @@ __global__ void k_zproj_reduce(int total, int M, int nb, int nsplit, const C2 *_
   C[i] = o;
 }
 
-// Y[v][G] += sum_m T[m0+m][G] C[k][m][v]; tile 32 bands x 64 plane waves.
-template <class T>
+// Y[v][G] += sum_m T[m0+m][G] C[k][m][v]; workgroup tile (32 BV bands) x 64 plane waves,
+// four waves in a 2 x 2 arrangement (16 BV bands x 32 plane waves each), the next m slab
+// prefetched into registers.
+template <class T, int BV>
 __global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, const typename Mf<T>::c2 *__restrict__ Tb,
                                                  long t_stride, int m0, int M,
                                                  const typename Mf<T>::c2 *__restrict__ C, long c_kstride,
@@ -144,12 +181,14 @@ __global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, co
                                                  const int *__restrict__ npw_of, const int *active) {
   using C2 = typename Mf<T>::c2;
   using A4 = typename Mf<T>::acc;
-  __shared__ C2 Ct[32][kKb + kPad];   // [v][m]
-  __shared__ C2 Tt[kKb][64 + kPad];   // [m][G]
+  constexpr int TV = 32 * BV;
+  __shared__ C2 Ct[TV][kKb + kPad];  // [v][m]
+  __shared__ C2 Tt[kKb][64 + kPad];  // [m][G]
   const int k = blockIdx.z;
+  const int vt = blockIdx.y * TV;
   if (active) {
-    const int v = blockIdx.y * 32 + (threadIdx.x & 31);
-    const int a = (threadIdx.x < 32 && v < nb) ? active[k * nb + v] : 0;
+    int a = 0;
+    for (int i = threadIdx.x; i < TV; i += 256) a |= (vt + i < nb) ? active[k * nb + vt + i] : 0;
     if (!__syncthreads_or(a)) return;
   }
   const KPair P = kp[k];
@@ -157,19 +196,26 @@ __global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, co
   const int npw = npw_of[e];
   const int gt = blockIdx.x * 64;
   if (gt >= npw) return;
-  const int vt = blockIdx.y * 32;
   const C2 *Te = Tb + (size_t)e * t_stride + (size_t)m0 * ld;
   const C2 *Ck = C + (size_t)k * c_kstride;
   const T cs = (T)cscale;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wv = wave >> 1, wg = wave & 1;
-  A4 yr0 = {0, 0, 0, 0}, yi0 = {0, 0, 0, 0}, yr1 = {0, 0, 0, 0}, yi1 = {0, 0, 0, 0};
-  for (int mb = 0; mb < M; mb += kKb) {
-    // C tile: 32 v x 16 m  (512 values, 2 per thread)
-    for (int c = 0; c < 2; ++c) {
-      const int idx = threadIdx.x * 2 + c;
-      const int vv = idx >> 4, mm = idx & 15;
+  A4 yr[BV][2], yi[BV][2];
+#pragma unroll
+  for (int i = 0; i < BV; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      yr[i][j] = A4{0, 0, 0, 0};
+      yi[i][j] = A4{0, 0, 0, 0};
+    }
+  C2 rc[2 * BV], rt[4];
+  auto load = [&](int mb) {
+#pragma unroll
+    for (int c = 0; c < 2 * BV; ++c) {  // C slab: TV bands x 16 m
+      const int idx = threadIdx.x + 256 * c;
+      const int vv = idx % TV, mm = idx / TV;
       const int m = mb + mm, v = vt + vv;
       C2 val = zc<C2>();
       if (m < M && v < nb) {
@@ -177,50 +223,70 @@ __global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, co
         val.x *= cs;
         val.y *= cs;
       }
-      Ct[vv][mm] = val;
+      rc[c] = val;
     }
-    // T tile: 16 m x 64 G (1024 values, 4 per thread)
-    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {  // T slab: 16 m x 64 G
       const int idx = threadIdx.x + c * 256;
       const int mm = idx >> 6, gg = idx & 63;
       const int m = mb + mm, g = gt + gg;
-      Tt[mm][gg] = (m < M && g < npw) ? Te[(size_t)m * ld + g] : zc<C2>();
+      rt[c] = (m < M && g < npw) ? Te[(size_t)m * ld + g] : zc<C2>();
     }
+  };
+  load(0);
+  for (int mb = 0; mb < M; mb += kKb) {
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < kKb; kk += 4) {
-      const C2 a = Ct[wv * 16 + (lane & 15)][kk + (lane >> 4)];
-      const C2 b0 = Tt[kk + (lane >> 4)][wg * 32 + (lane & 15)];
-      const C2 b1 = Tt[kk + (lane >> 4)][wg * 32 + 16 + (lane & 15)];
-      yr0 = mfma(a.x, b0.x, yr0);
-      yr0 = mfma(-a.y, b0.y, yr0);
-      yi0 = mfma(a.x, b0.y, yi0);
-      yi0 = mfma(a.y, b0.x, yi0);
-      yr1 = mfma(a.x, b1.x, yr1);
-      yr1 = mfma(-a.y, b1.y, yr1);
-      yi1 = mfma(a.x, b1.y, yi1);
-      yi1 = mfma(a.y, b1.x, yi1);
+    for (int c = 0; c < 2 * BV; ++c) {
+      const int idx = threadIdx.x + 256 * c;
+      Ct[idx % TV][idx / TV] = rc[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int idx = threadIdx.x + c * 256;
+      Tt[idx >> 6][idx & 63] = rt[c];
     }
     __syncthreads();
+    if (mb + kKb < M) load(mb + kKb);
+#pragma unroll
+    for (int kk = 0; kk < kKb; kk += 4) {
+      const C2 b0 = Tt[kk + (lane >> 4)][wg * 32 + (lane & 15)];
+      const C2 b1 = Tt[kk + (lane >> 4)][wg * 32 + 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < BV; ++i) {
+        const C2 a = Ct[(wv * BV + i) * 16 + (lane & 15)][kk + (lane >> 4)];
+        yr[i][0] = mfma(a.x, b0.x, yr[i][0]);
+        yr[i][0] = mfma(-a.y, b0.y, yr[i][0]);
+        yi[i][0] = mfma(a.x, b0.y, yi[i][0]);
+        yi[i][0] = mfma(a.y, b0.x, yi[i][0]);
+        yr[i][1] = mfma(a.x, b1.x, yr[i][1]);
+        yr[i][1] = mfma(-a.y, b1.y, yr[i][1]);
+        yi[i][1] = mfma(a.x, b1.y, yi[i][1]);
+        yi[i][1] = mfma(a.y, b1.x, yi[i][1]);
+      }
+    }
   }
   C2 *Yk = Y + (size_t)k * nb * ld;
-  for (int r = 0; r < 4; ++r) {
-    const int v = vt + wv * 16 + Mf<T>::row(lane, r);
-    if (v >= nb) continue;
-    const int g = gt + wg * 32 + (lane & 15);
-    if (g < npw) {
-      C2 y = Yk[(size_t)v * ld + g];
-      y.x += yr0[r];
-      y.y += yi0[r];
-      Yk[(size_t)v * ld + g] = y;
+#pragma unroll
+  for (int i = 0; i < BV; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int v = vt + (wv * BV + i) * 16 + Mf<T>::row(lane, r);
+      if (v >= nb) continue;
+      const int g = gt + wg * 32 + (lane & 15);
+      if (g < npw) {
+        C2 y = Yk[(size_t)v * ld + g];
+        y.x += yr[i][0][r];
+        y.y += yi[i][0][r];
+        Yk[(size_t)v * ld + g] = y;
+      }
+      if (g + 16 < npw) {
+        C2 y = Yk[(size_t)v * ld + g + 16];
+        y.x += yr[i][1][r];
+        y.y += yi[i][1][r];
+        Yk[(size_t)v * ld + g + 16] = y;
+      }
     }
-    if (g + 16 < npw) {
-      C2 y = Yk[(size_t)v * ld + g + 16];
-      y.x += yr1[r];
-      y.y += yi1[r];
-      Yk[(size_t)v * ld + g + 16] = y;
-    }
-  }
 }
 
 // ------------------------------------------------------------ reductions
@@ -497,21 +563,67 @@ __global__ void k_zscale_copy(long n, const double2 *a, double s, double2 *out) 
 
 }  // namespace
 
+namespace {
+template <class T>
+hipError_t zproj_t(const KPair *kp, int use_kq, int nk, const typename Mf<T>::c2 *Tm, long t_stride, int m0, int M,
+                   const typename Mf<T>::c2 *X, int ld, int nb, const int *npw_of, typename Mf<T>::c2 *Cpart,
+                   int nsplit, const int *active, int tile, hipStream_t st) {
+  const int wm = (tile & 1) ? 2 : 1, wn = (tile & 2) ? 2 : 1;
+  dim3 grid((M + 32 * wm - 1) / (32 * wm), (nb + 32 * wn - 1) / (32 * wn), nk * nsplit);
+  switch (tile) {
+    case 1:
+      hipLaunchKernelGGL((k_zproj<T, 2, 1>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, X, ld, nb,
+                         npw_of, nsplit, Cpart, nk, active);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_zproj<T, 1, 2>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, X, ld, nb,
+                         npw_of, nsplit, Cpart, nk, active);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_zproj<T, 2, 2>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, X, ld, nb,
+                         npw_of, nsplit, Cpart, nk, active);
+      break;
+    default:
+      hipLaunchKernelGGL((k_zproj<T, 1, 1>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, X, ld, nb,
+                         npw_of, nsplit, Cpart, nk, active);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t zexpand_t(const KPair *kp, int use_kq, int nk, const typename Mf<T>::c2 *Tm, long t_stride, int m0, int M,
+                     const typename Mf<T>::c2 *C, long c_kstride, double cscale, typename Mf<T>::c2 *Y, int ld,
+                     int nb, const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st) {
+  bv = (bv == 2 || bv == 4) ? bv : 1;
+  dim3 grid((npw_max + 63) / 64, (nb + 32 * bv - 1) / (32 * bv), nk);
+  switch (bv) {
+    case 2:
+      hipLaunchKernelGGL((k_zexpand<T, 2>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, C, c_kstride,
+                         cscale, Y, ld, nb, npw_of, active);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_zexpand<T, 4>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, C, c_kstride,
+                         cscale, Y, ld, nb, npw_of, active);
+      break;
+    default:
+      hipLaunchKernelGGL((k_zexpand<T, 1>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, C, c_kstride,
+                         cscale, Y, ld, nb, npw_of, active);
+      break;
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_zproj(const KPair *kp, int use_kq, int nk, const double2 *T, long t_stride, int m0, int M,
                         const double2 *X, int ld, int nb, const int *npw_of, double2 *Cpart, int nsplit,
-                        const int *active, hipStream_t st) {
-  dim3 grid((M + kTile - 1) / kTile, (nb + kTile - 1) / kTile, nk * nsplit);
-  hipLaunchKernelGGL(k_zproj<double>, grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, X, ld, nb, npw_of,
-                     nsplit, Cpart, nk, active);
-  return hipGetLastError();
+                        const int *active, int tile, hipStream_t st) {
+  return zproj_t<double>(kp, use_kq, nk, T, t_stride, m0, M, X, ld, nb, npw_of, Cpart, nsplit, active, tile, st);
 }
 hipError_t launch_zproj32(const KPair *kp, int use_kq, int nk, const float2 *T, long t_stride, int m0, int M,
                           const float2 *X, int ld, int nb, const int *npw_of, float2 *Cpart, int nsplit,
-                          const int *active, hipStream_t st) {
-  dim3 grid((M + kTile - 1) / kTile, (nb + kTile - 1) / kTile, nk * nsplit);
-  hipLaunchKernelGGL(k_zproj<float>, grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, X, ld, nb, npw_of,
-                     nsplit, Cpart, nk, active);
-  return hipGetLastError();
+                          const int *active, int tile, hipStream_t st) {
+  return zproj_t<float>(kp, use_kq, nk, T, t_stride, m0, M, X, ld, nb, npw_of, Cpart, nsplit, active, tile, st);
 }
 
 hipError_t launch_zproj_reduce(int nk, int M, int nb, int nsplit, const double2 *Cpart, const double *row_scale,
@@ -531,19 +643,15 @@ hipError_t launch_zproj_reduce32(int nk, int M, int nb, int nsplit, const float2
 
 hipError_t launch_zexpand(const KPair *kp, int use_kq, int nk, const double2 *T, long t_stride, int m0, int M,
                           const double2 *C, long c_kstride, double cscale, double2 *Y, int ld, int nb,
-                          const int *npw_of, int npw_max, const int *active, hipStream_t st) {
-  dim3 grid((npw_max + 63) / 64, (nb + 31) / 32, nk);
-  hipLaunchKernelGGL(k_zexpand<double>, grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride, cscale,
-                     Y, ld, nb, npw_of, active);
-  return hipGetLastError();
+                          const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st) {
+  return zexpand_t<double>(kp, use_kq, nk, T, t_stride, m0, M, C, c_kstride, cscale, Y, ld, nb, npw_of, npw_max,
+                           active, bv, st);
 }
 hipError_t launch_zexpand32(const KPair *kp, int use_kq, int nk, const float2 *T, long t_stride, int m0, int M,
                             const float2 *C, long c_kstride, double cscale, float2 *Y, int ld, int nb,
-                            const int *npw_of, int npw_max, const int *active, hipStream_t st) {
-  dim3 grid((npw_max + 63) / 64, (nb + 31) / 32, nk);
-  hipLaunchKernelGGL(k_zexpand<float>, grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride, cscale,
-                     Y, ld, nb, npw_of, active);
-  return hipGetLastError();
+                            const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st) {
+  return zexpand_t<float>(kp, use_kq, nk, T, t_stride, m0, M, C, c_kstride, cscale, Y, ld, nb, npw_of, npw_max,
+                          active, bv, st);
 }
 
 hipError_t launch_cg_init(const KPair *kp, int nb, int nitems, const double2 *B, double2 *Xv, double2 *R,

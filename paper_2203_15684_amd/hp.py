@@ -62,7 +62,8 @@ class HpScfParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("conv_thr_chi", C.c_double), ("conv_thr_v", C.c_double),
                 ("cg_tol", C.c_double), ("niter_max", C.c_int32), ("alpha_mix", C.c_double), ("nmix", C.c_int32),
                 ("max_cg_iter", C.c_int32), ("precision", C.c_int32), ("verbosity", C.c_int32),
-                ("inner_tol", C.c_double), ("max_refine", C.c_int32), ("graph_chunk", C.c_int32)]
+                ("inner_tol", C.c_double), ("max_refine", C.c_int32), ("graph_chunk", C.c_int32),
+                ("autotune", C.c_int32)]
 
 
 class HpScfStats(C.Structure):
@@ -104,10 +105,16 @@ _lib.hp_profile_start.argtypes = [C.c_void_p]
 _lib.hp_profile_start.restype = C.c_int32
 _lib.hp_profile_stop.argtypes = [C.c_void_p, C.POINTER(HpKernelTime), C.c_int32, C.POINTER(C.c_int32)]
 _lib.hp_profile_stop.restype = C.c_int32
+_lib.hp_tuning_report.argtypes = [C.c_void_p, C.c_char_p, C.c_int32]
+_lib.hp_tuning_report.restype = C.c_int32
+_lib.hp_set_gemm_shape.argtypes = [C.c_void_p] + [C.c_int32] * 6
+_lib.hp_set_gemm_shape.restype = C.c_int32
+_lib.hp_set_plane_variant.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+_lib.hp_set_plane_variant.restype = C.c_int32
 
 EXPORTED = ["hp_ground_state_load", "hp_sternheimer_scf", "hp_response_matrix", "hp_hubbard_params",
             "hp_destroy", "hp_last_error", "hp_apply_h", "hp_solve_first_order", "hp_profile_start",
-            "hp_profile_stop"]
+            "hp_profile_stop", "hp_tuning_report", "hp_set_gemm_shape", "hp_set_plane_variant"]
 
 
 def hp_last_error() -> str:
@@ -147,11 +154,12 @@ class ScfParams:
     inner_tol: float = 1e-4
     max_refine: int = 12
     graph_chunk: int = 8   # CG iterations per captured hipGraph launch; 0 launches kernels one by one
+    autotune: int = 1      # time candidate GEMM tiles / FFT plane batches on first use of a shape
 
     def c(self) -> HpScfParams:
         return HpScfParams(C.sizeof(HpScfParams), self.conv_thr_chi, self.conv_thr_v, self.cg_tol, self.niter_max,
                            self.alpha_mix, self.nmix, self.max_cg_iter, self.precision, self.verbosity,
-                           self.inner_tol, self.max_refine, self.graph_chunk)
+                           self.inner_tol, self.max_refine, self.graph_chunk, self.autotune)
 
 
 class Context:
@@ -301,3 +309,19 @@ def hp_profile_stop(ctx: Context) -> dict:
     n = C.c_int32(0)
     _check(_lib.hp_profile_stop(ctx.handle, out, 32, C.byref(n)), allow_warn=False)
     return {out[i].name.decode(): (int(out[i].calls), float(out[i].total_ms)) for i in range(n.value)}
+
+
+def hp_tuning_report(ctx: Context) -> dict:
+    """Launch shapes the autotuner chose in this context, with measured and default times."""
+    import json
+    buf = C.create_string_buffer(1 << 16)
+    _check(_lib.hp_tuning_report(ctx.handle, buf, len(buf)), allow_warn=False)
+    return json.loads(buf.value.decode())
+
+
+def hp_set_gemm_shape(ctx: Context, prec: int, rows: int, batch: int, tile: int, nsplit: int, expand_bands: int):
+    _check(_lib.hp_set_gemm_shape(ctx.handle, prec, rows, batch, tile, nsplit, expand_bands), allow_warn=False)
+
+
+def hp_set_plane_variant(ctx: Context, prec: int, variant: int):
+    _check(_lib.hp_set_plane_variant(ctx.handle, prec, variant), allow_warn=False)

@@ -1,0 +1,106 @@
+"""The autotuner and the launch-shape variants it chooses among.
+
+Projection tiles, expansion band tiles and plane-batch FFT variants compute the same sums
+in the same order, so with the K split pinned every combination must give bit-identical
+results (the default shapes are held to the oracle by the parity tests, so every variant
+is too). The tuner keeps the fastest candidate, never slower than the default it timed,
+and tuned runs (whose K split may differ) agree with untuned ones to rounding."""
+import itertools
+
+import numpy as np
+import pytest
+
+from conftest import ground_state
+
+pytestmark = pytest.mark.gpu
+
+
+def _scf(ctx, prec, autotune=1, site=1, q=(0.0, 0.5, 0.0)):
+    from paper_2203_15684_amd import hp
+    p = hp.ScfParams(conv_thr_chi=1e-12, conv_thr_v=1e-10, cg_tol=1e-11, niter_max=60, max_cg_iter=2000,
+                     precision=prec, autotune=autotune)
+    return hp.hp_sternheimer_scf(ctx, site, q, p)
+
+
+def _pin(ctx, gs, prec_list, batch, tile, nsplit, bands, pv):
+    from paper_2203_15684_amd import hp
+    rows = gs.n_beta + gs.n_occ
+    for prec in prec_list:
+        for m in (rows, gs.n_occ, 5 * gs.n_hub, 5):
+            hp.hp_set_gemm_shape(ctx, prec, m, batch, tile, nsplit, bands)
+        hp.hp_set_plane_variant(ctx, prec, pv)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_shape_variants_bitwise(prec):
+    from paper_2203_15684_amd import hp
+    gs = ground_state("duo_k221")
+    ctx = hp.hp_ground_state_load(gs)
+    pr = hp.HP_FP64 if prec == "fp64" else hp.HP_MIXED
+    precs = [64] if prec == "fp64" else [64, 32]
+    ref = None
+    for i, (tile, bands) in enumerate(itertools.product(range(4), (32, 64, 128))):
+        _pin(ctx, gs, precs, gs.n_mesh, tile, 2, bands, i % 3)   # the 30x24 plane has three variants
+        out = _scf(ctx, pr)
+        assert out[3] == 0
+        if ref is None:
+            ref = out
+            continue
+        assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), (tile, bands)
+        assert out[2]["cg_iters"] == ref[2]["cg_iters"]
+
+
+def test_shape_variants_bitwise_fullsize_solve():
+    """At the olivine size (72x45 planes, 224 projector rows, 112 bands) on one k-point."""
+    from paper_2203_15684_amd import hp
+    from synth import cache
+    gs = cache.get("olivine28")
+    ctx = hp.hp_ground_state_load(gs)
+    q, ik = (0.0, 0.5, 0.5), 5
+    k = gs.kpts[ik].k_frac + np.asarray(q)
+    npw = next(e.npw for e in gs.kpts if np.allclose(k - e.k_frac, np.round(k - e.k_frac)))
+    ref = None
+    for tile, bands, pv in [(0, 32, 0), (3, 128, 1), (1, 64, 2), (2, 128, 0), (3, 32, 2)]:
+        for prec in ("fp64", "mixed"):
+            _pin(ctx, gs, [64, 32], 1, tile, 4, bands, pv)
+            p = hp.ScfParams(cg_tol=1e-11, max_cg_iter=2000, precision=hp.HP_FP64 if prec == "fp64" else hp.HP_MIXED)
+            du, st = hp.hp_solve_first_order(ctx, 3, q, ik, None, p, npw)
+            assert st == 0
+            if ref is None or prec not in ref:
+                ref = (ref or {}) | {prec: du}
+            else:
+                assert np.array_equal(du, ref[prec]), (tile, bands, pv, prec)
+
+
+def test_tuner_report_and_agreement():
+    from paper_2203_15684_amd import hp
+    gs = ground_state("duo_k221")
+    tuned = hp.hp_ground_state_load(gs)
+    plain = hp.hp_ground_state_load(gs)
+    a = _scf(tuned, hp.HP_MIXED, autotune=1)
+    b = _scf(plain, hp.HP_MIXED, autotune=0)
+    assert a[3] == b[3] == 0
+    assert np.abs(a[1] - b[1]).max() < 1e-12 * np.abs(b[1]).max()
+    rep = hp.hp_tuning_report(tuned)
+    rows = gs.n_beta + gs.n_occ
+    shapes = {(g["prec"], g["rows"], g["batch"]) for g in rep["gemm"]}
+    assert {(64, rows, gs.n_mesh), (64, gs.n_occ, gs.n_mesh), (32, rows, gs.n_mesh)} <= shapes
+    for g in rep["gemm"]:
+        assert g["proj_tile"] in ("32x32", "64x32", "32x64", "64x64") and g["expand_bands"] in (32, 64, 128)
+        assert g["proj_ms"] <= g["proj_default_ms"] and g["expand_ms"] <= g["expand_default_ms"]
+    assert {p["prec"] for p in rep["plane"]} == {64, 32}
+    for p in rep["plane"]:
+        assert p["ms"][p["variant"]] == min(p["ms"])
+    assert hp.hp_tuning_report(plain) == {"gemm": [], "plane": []}
+
+
+def test_pinning_rejects_bad_shapes():
+    from paper_2203_15684_amd import hp
+    gs = ground_state("sc1_gamma")
+    ctx = hp.hp_ground_state_load(gs)
+    for args in [(16, 8, 1, 0, 1, 32), (64, 8, 1, 4, 1, 32), (64, 8, 1, 0, 0, 32), (64, 8, 1, 0, 1, 48),
+                 (64, 8, 2, 0, 1, 32)]:
+        with pytest.raises(hp.HpError):
+            hp.hp_set_gemm_shape(ctx, *args)
+    with pytest.raises(hp.HpError):
+        hp.hp_set_plane_variant(ctx, 64, 1)   # 24x24 planes: only variant 0

@@ -46,7 +46,10 @@ def parse():
     ap.add_argument("--cpu-baseline-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--relaxed-cg-tol", type=float, default=1e-7,
-                    help="cg_tol of the relaxed FP64 / mixed forms (0: skip them)")
+                    help="cg_tol of the relaxed FP64 / mixed forms")
+    ap.add_argument("--forms", default="mixed,fp64,fp64_relaxed,mixed_relaxed,mixed_bf16,mixed_bf16_pv32",
+                    help="comma-separated forms to time (must include fp64 and --precision)")
+    ap.add_argument("--verbosity", type=int, default=0, help="1: one line per SCF iteration on stderr")
     ap.add_argument("--graph-chunk", type=int, default=8,
                     help="CG iterations per captured hipGraph launch (0: launch kernels one by one)")
     return ap.parse_args()
@@ -173,6 +176,7 @@ def main():
     t0 = time.time()
     gs = cache.get(args.config)
     t_gen = time.time() - t0
+    free_before_load = torch.cuda.mem_get_info()[0]
     ctx = hp.hp_ground_state_load(gs)
     nq = gs.qmesh
     nq_list = [tuple(q) for q in gs.qpoints()]
@@ -180,16 +184,27 @@ def main():
     # forms: name -> (precision, cg_tol). The relaxed forms separate the gain of the precision
     # from the gain of a looser Sternheimer tolerance: the loosest cg_tol that still keeps chi
     # within 1e-6 of the FP64 form at the configured tolerance.
-    form_def = {"mixed": ("mixed", args.cg_tol), "fp64": ("fp64", args.cg_tol)}
-    if args.relaxed_cg_tol > 0:
-        form_def["fp64_relaxed"] = ("fp64", args.relaxed_cg_tol)
-        form_def["mixed_relaxed"] = ("mixed", args.relaxed_cg_tol)
+    # (the BF16 forms put the KB and P_v projections of the inner solves on BF16 MFMA, or
+    # only the KB ones with P_v kept in FP32)
+    form_def = {"mixed": ("mixed", args.cg_tol, hp.HP_GEMM_FP32), "fp64": ("fp64", args.cg_tol, 0),
+                "fp64_relaxed": ("fp64", args.relaxed_cg_tol, 0),
+                "mixed_relaxed": ("mixed", args.relaxed_cg_tol, hp.HP_GEMM_FP32),
+                "mixed_bf16": ("mixed", args.cg_tol, hp.HP_GEMM_BF16),
+                "mixed_bf16_pv32": ("mixed", args.cg_tol, hp.HP_GEMM_BF16_PV32)}
+    wanted = args.forms.split(",")
+    for f in wanted:
+        if f not in form_def:
+            raise SystemExit(f"unknown form {f}; choose from {', '.join(form_def)}")
+    if args.precision not in wanted or "fp64" not in wanted:
+        raise SystemExit("--forms must include fp64 and the --precision form")
+    form_def = {f: form_def[f] for f in wanted}
 
     def params(form):
-        prec, tol = form_def[form]
+        prec, tol, lowp = form_def[form]
         return hp.ScfParams(conv_thr_chi=args.conv_thr_chi, conv_thr_v=args.conv_thr_v, cg_tol=tol,
                             niter_max=100, max_cg_iter=2000, inner_tol=args.inner_tol, graph_chunk=args.graph_chunk,
-                            precision=hp.HP_FP64 if prec == "fp64" else hp.HP_MIXED)
+                            precision=hp.HP_FP64 if prec == "fp64" else hp.HP_MIXED, lowp_gemm=lowp,
+                            verbosity=args.verbosity)
 
     def step(p):
         chi0, chi, mim, st, status = hp.hp_response_matrix(ctx, nq, p)
@@ -208,11 +223,15 @@ def main():
         return t, res, prof
 
     forms = [args.precision] + [f for f in form_def if f != args.precision]
+    free0 = torch.cuda.mem_get_info()[0]
     for _ in range(args.warmup):
         step(params(args.precision))
+        print(f"[bench] warm-up step done", file=sys.stderr, flush=True)
     runs = {}
     for f in forms:
         runs[f] = timed(f, args.steps if f == args.precision else 1)
+        print(f"[bench] form {f}: {runs[f][0]:.2f} s", file=sys.stderr, flush=True)
+    hbm_used = free_before_load - torch.cuda.mem_get_info()[0]
     t_total, results, prof = runs[args.precision]
     chi0, chi, uv, st, status = results[-1]
     h64 = sum(r[3]["h_applies_fp64"] for r in results)
@@ -227,6 +246,8 @@ def main():
         a32 = sum(r[3]["h_applies_lowp"] for r in res)
         d = max(pr.items(), key=lambda kv: kv[1][1])[0]
         summary[f] = {"precision": form_def[f][0], "cg_tol": form_def[f][1],
+                      "projection_gemms": {0: "fp32", 1: "bf16", 2: "bf16 (KB), fp32 (P_v)"}[form_def[f][2]]
+                      if form_def[f][0] == "mixed" else "fp64",
                       "scf_wall_s_per_step": t / len(res), "hpsi_per_s": (a64 + a32) / t,
                       "ms_per_scf_iteration": t / sum(r[3]["scf_iters"] for r in res) * 1e3,
                       "h_applies_fp64": a64 / len(res), "h_applies_fp32": a32 / len(res),
@@ -264,6 +285,8 @@ def main():
         "roofline": rec,
         "setup_s": {"ground_state": round(t_gen, 1)},
         "autotune": hp.hp_tuning_report(ctx),
+        "hbm_footprint_gb": {"context_after_all_forms": round(hbm_used / 1e9, 2),
+                             "loaded_ground_state": round((free_before_load - free0) / 1e9, 2)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(gs, args.cpu_baseline_seconds)

@@ -59,6 +59,9 @@ enum {
 };
 
 enum { HP_FP64 = 0, HP_MIXED = 1 };   /* arithmetic of the Sternheimer solves */
+/* HP_MIXED: number type of the projection GEMMs inside the low-precision inner solves
+ * (FP32 accumulation in every case; the FFTs and V_loc psi are FP32). */
+enum { HP_GEMM_FP32 = 0, HP_GEMM_BF16 = 1, HP_GEMM_BF16_PV32 = 2 };
 enum { HP_XC_LDA_PZ81 = 1 };          /* local xc kernel (Perdew-Zunger 1981)   */
 
 /* One k-entry: a point of the Gamma-centred k mesh, or an extra k+q point.
@@ -120,6 +123,10 @@ typedef struct hp_scf_params {
                           /* GEMM tiles / K splits and FFT plane batches on this      */
                           /* device and keep the fastest (cached in the context);    */
                           /* 0: fixed default shapes                                  */
+  int32_t lowp_gemm;      /* HP_MIXED: HP_GEMM_FP32 (KB and alpha P_v GEMMs in FP32), */
+                          /* HP_GEMM_BF16 (both in BF16), HP_GEMM_BF16_PV32 (KB in    */
+                          /* BF16, alpha P_v in FP32).  Below BF16 accuracy every     */
+                          /* solve is finished by FP64 residual refinement.          */
 } hp_scf_params;
 
 /* Statistics of one call (all fields written when the pointer is not NULL). */
@@ -228,9 +235,10 @@ hp_status hp_profile_stop(hp_ctx *c, hp_kernel_time *out, int32_t max, int32_t *
 hp_status hp_tuning_report(hp_ctx *c, char *buf, int32_t len);
 
 /* Pin launch shapes instead of timing them (used when hp_scf_params.autotune = 1;
- * a pinned shape is never re-tuned).  GEMM shape key: prec (64 or 32), rows of the
- * projector table (n_beta + n_occ for H, n_occ for P_c, 5 n_hub and 5 for the
- * Hubbard terms), batch (mesh points per launch, 1..n_mesh).  tile 0..3 =
+ * a pinned shape is never re-tuned).  GEMM shape key: prec (64, 32, or 16 for
+ * BF16), rows of the projector table (n_beta + n_occ for H, n_occ for P_c,
+ * n_beta for the BF16 KB part, 5 n_hub and 5 for the Hubbard terms), batch (mesh
+ * points per launch, 1..n_mesh).  tile 0..3 (BF16: 0 or 3) =
  * projection workgroup tile 32x32, 64x32, 32x64, 64x64 (rows x bands); nsplit =
  * K split of the projection, 1..16; expand_bands = 32, 64 or 128 bands per
  * expansion workgroup.  Plane variant 0..2 of the local-potential FFT round trip

@@ -134,6 +134,8 @@ struct hp_ctx {
   // FP32 copies and work buffers of the mixed-precision inner solves (allocated on first use)
   bool have32 = false;
   float2 *tw32 = nullptr, *T32 = nullptr;
+  unsigned *T16 = nullptr;  // the stacked table in packed bfloat16 (allocated on first use)
+  int lowp_gemm = 0;        // hp_scf_params.lowp_gemm of the current call
   float *vp32 = nullptr;
   float2 *X32 = nullptr, *R32 = nullptr, *B32 = nullptr, *P32 = nullptr, *AP32 = nullptr;
   double *bn_in = nullptr, *rn_in = nullptr, *rz_in = nullptr, *floor_in = nullptr;
@@ -157,7 +159,7 @@ struct hp_ctx {
   // iterations per launch, profiling on/off, batch).  Every kernel of a captured iteration
   // reads its tolerance and writes its counters through the fixed device pointers below.
   struct CgGraph {
-    int kind, len, prof, nk;
+    int kind, len, prof, nk, lowp, tuned;
     const KPair *kp;
     const double *eps;
     hipGraphExec_t exec;
@@ -233,6 +235,8 @@ enum KernelId {
   K_HXC,
   K_DN,
   K_MIX,
+  K_ZPROJ16,
+  K_ZEXPAND16,
   K_COUNT
 };
 static_assert(K_COUNT <= 32, "profile slots");
@@ -240,7 +244,8 @@ const char *const kKernelNames[K_COUNT] = {
     "stick_inv",   "plane_vloc",   "stick_fwd",   "zproj",       "zexpand",     "cg_step",
     "plane_drho",  "plane_mul_fwd", "stick_inv32", "plane_vloc32", "stick_fwd32", "zproj32",
     "zexpand32",   "cg_step32",    "zproj_reduce", "cg_init",     "residual64",  "refine_update",
-    "rhs_other",   "drho_sticks",  "drho_reduce", "hxc",         "dn",          "mixing"};
+    "rhs_other",   "drho_sticks",  "drho_reduce", "hxc",         "dn",          "mixing",
+    "zproj16",     "zexpand16"};
 
 hipEvent_t prof_event(hp_ctx *c) {
   if (!c->ev_pool.empty()) {
@@ -502,7 +507,8 @@ hp_status cg_graph(hp_ctx *c, int kind, int len, const KPair *kp, int nk, const 
                    hp_ctx::CgGraph **out) {
   const int prof = c->prof_on ? 1 : 0;
   for (auto &g : c->graphs)
-    if (g.kind == kind && g.len == len && g.prof == prof && g.nk == nk && g.kp == kp && g.eps == eps_items) {
+    if (g.kind == kind && g.len == len && g.prof == prof && g.nk == nk && g.lowp == c->lowp_gemm &&
+        g.tuned == c->use_tuned && g.kp == kp && g.eps == eps_items) {
       *out = &g;
       return HP_OK;
     }
@@ -527,7 +533,8 @@ hp_status cg_graph(hp_ctx *c, int kind, int len, const KPair *kp, int nk, const 
   const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   HPCHK(ei);
-  c->graphs.push_back({kind, len, prof, nk, kp, eps_items, exec, std::move(c->capture_stamps)});
+  c->graphs.push_back(
+      {kind, len, prof, nk, c->lowp_gemm, c->use_tuned, kp, eps_items, exec, std::move(c->capture_stamps)});
   c->capture_stamps.clear();
   *out = &c->graphs.back();
   return HP_OK;
@@ -664,7 +671,18 @@ hp_status setup32(hp_ctx *c) {
   return HP_OK;
 }
 
-// Y = (H_{k+q} + alpha P_v - eps_v) X in FP32 (FP32 FFTs, FP32 MFMA GEMMs with FP32 accumulation).
+// Packed-bfloat16 copy of the stacked projector table (once per context).
+hp_status setup16(hp_ctx *c) {
+  if (c->T16) return HP_OK;
+  unsigned *t = nullptr;
+  HPTRY(c->alloc(&t, (size_t)c->n_kpts * c->t_stride));
+  HPCHK(launch_to_bf16_pairs(c->d_T, t, (long)c->n_kpts * c->t_stride, c->stream));
+  HPTRY(sync(c));
+  c->T16 = t;
+  return HP_OK;
+}
+
+// Y = (H_{k+q} + alpha P_v - eps_v) X in FP32 (FP32 FFTs; FP32 or BF16 MFMA GEMMs with FP32 accumulation).
 hp_status apply_op32(hp_ctx *c, const KPair *kp, int nk, int nb, const float2 *Xin, float2 *Y, const double *eps,
                      int rows, const int *active) {
   const int nitems = nk * nb;
@@ -682,19 +700,37 @@ hp_status apply_op32(hp_ctx *c, const KPair *kp, int nk, int nb, const float2 *X
     return launch_stick_fwd32(c->sk, kp, 1, nb, nitems, S2, c->ns_pad, c->n3, c->az32.tw32, 1.0 / (double)c->nr, Y,
                               c->ld, 0, c->d_kin, eps, Xin, nb, c->max_chunk_pw, c->ns_max, active, c->stream);
   }));
-  const GemmShape gs = gemm_shape(c, 32, rows, nk);
-  const int ns = gs.ns;
-  HPCHK(timed(c, K_ZPROJ32, [&] {
-    return launch_zproj32(kp, 1, nk, c->T32, c->t_stride, 0, rows, Xin, c->ld, nb, c->d_npw, Cpart, ns, active,
-                          gs.tile, c->stream);
-  }));
-  HPCHK(timed(c, K_ZPROJ_REDUCE, [&] {
-    return launch_zproj_reduce32(nk, rows, nb, ns, Cpart, c->d_rowscale, 1.0, C, c->stream);
-  }));
-  HPCHK(timed(c, K_ZEXPAND32, [&] {
-    return launch_zexpand32(kp, 1, nk, c->T32, c->t_stride, 0, rows, C, (long)rows * nb, 1.0, Y, c->ld, nb,
-                            c->d_npw, c->npw_max, active, gs.bv, c->stream);
-  }));
+  // rows [0, m16) of the stacked table in BF16, rows [m16, rows) in FP32
+  const int m16 = c->lowp_gemm == HP_GEMM_BF16 ? rows : c->lowp_gemm == HP_GEMM_BF16_PV32 ? c->n_beta : 0;
+  if (m16 > 0) {
+    const GemmShape g16 = gemm_shape(c, 16, m16, nk);
+    HPCHK(timed(c, K_ZPROJ16, [&] {
+      return launch_zproj16(kp, 1, nk, c->T16, c->t_stride, 0, m16, Xin, c->ld, nb, c->d_npw, Cpart, g16.ns, active,
+                            g16.tile, c->stream);
+    }));
+    HPCHK(timed(c, K_ZPROJ_REDUCE, [&] {
+      return launch_zproj_reduce32(nk, m16, nb, g16.ns, Cpart, c->d_rowscale, 1.0, C, c->stream);
+    }));
+    HPCHK(timed(c, K_ZEXPAND16, [&] {
+      return launch_zexpand16(kp, 1, nk, c->T16, c->t_stride, 0, m16, C, (long)m16 * nb, 1.0, Y, c->ld, nb,
+                              c->d_npw, c->npw_max, active, g16.bv, c->stream);
+    }));
+  }
+  if (m16 < rows) {
+    const int M = rows - m16;
+    const GemmShape gs = gemm_shape(c, 32, M, nk);
+    HPCHK(timed(c, K_ZPROJ32, [&] {
+      return launch_zproj32(kp, 1, nk, c->T32, c->t_stride, m16, M, Xin, c->ld, nb, c->d_npw, Cpart, gs.ns, active,
+                            gs.tile, c->stream);
+    }));
+    HPCHK(timed(c, K_ZPROJ_REDUCE, [&] {
+      return launch_zproj_reduce32(nk, M, nb, gs.ns, Cpart, c->d_rowscale + m16, 1.0, C, c->stream);
+    }));
+    HPCHK(timed(c, K_ZEXPAND32, [&] {
+      return launch_zexpand32(kp, 1, nk, c->T32, c->t_stride, m16, M, C, (long)M * nb, 1.0, Y, c->ld, nb, c->d_npw,
+                              c->npw_max, active, gs.bv, c->stream);
+    }));
+  }
   return HP_OK;
 }
 
@@ -721,6 +757,7 @@ hp_status time_launch(hp_ctx *c, F launch, int reps, float *ms) {
 hp_status tune_gemm(hp_ctx *c, int prec, int M, int nk) {
   for (const auto &g : c->gemm_tuned)
     if (g.prec == prec && g.M == M && g.nk == nk) return HP_OK;
+  if (prec == 16) HPTRY(setup16(c));
   if (M > c->n_proj) return HP_OK;  // timed against the first M rows of the stacked table
   const int nb = c->n_occ;
   const KPair *kp = c->d_kp;
@@ -732,12 +769,21 @@ hp_status tune_gemm(hp_ctx *c, int prec, int M, int nk) {
   for (int tile = 0; tile < 4; ++tile)
     for (int ns : splits) {
       float ms = 0.f;
+      if (prec == 16 && tile != 0 && tile != 3) continue;  // BF16 tiles: 32x32 and 64x64
       if (prec == 64) {
         HPTRY(time_launch(c, [&] {
           hipError_t e = launch_zproj(kp, 1, nk, c->d_T, c->t_stride, 0, M, c->X, c->ld, nb, c->d_npw, c->Cpart, ns,
                                       nullptr, tile, c->stream);
           if (e != hipSuccess) return e;
           return launch_zproj_reduce(nk, M, nb, ns, c->Cpart, nullptr, 1.0, c->C, c->stream);
+        }, 2, &ms));
+      } else if (prec == 16) {
+        float2 *Cpart = reinterpret_cast<float2 *>(c->Cpart), *C = reinterpret_cast<float2 *>(c->C);
+        HPTRY(time_launch(c, [&] {
+          hipError_t e = launch_zproj16(kp, 1, nk, c->T16, c->t_stride, 0, M, c->X32, c->ld, nb, c->d_npw, Cpart, ns,
+                                        nullptr, tile, c->stream);
+          if (e != hipSuccess) return e;
+          return launch_zproj_reduce32(nk, M, nb, ns, Cpart, nullptr, 1.0, C, c->stream);
         }, 2, &ms));
       } else {
         float2 *Cpart = reinterpret_cast<float2 *>(c->Cpart), *C = reinterpret_cast<float2 *>(c->C);
@@ -761,6 +807,12 @@ hp_status tune_gemm(hp_ctx *c, int prec, int M, int nk) {
       HPTRY(time_launch(c, [&] {
         return launch_zexpand(kp, 1, nk, c->d_T, c->t_stride, 0, M, c->C, (long)M * nb, 1.0, c->AP, c->ld, nb,
                               c->d_npw, c->npw_max, nullptr, bv, c->stream);
+      }, 2, &ms));
+    } else if (prec == 16) {
+      const float2 *C = reinterpret_cast<const float2 *>(c->C);
+      HPTRY(time_launch(c, [&] {
+        return launch_zexpand16(kp, 1, nk, c->T16, c->t_stride, 0, M, C, (long)M * nb, 1.0, c->AP32, c->ld, nb,
+                                c->d_npw, c->npw_max, nullptr, bv, c->stream);
       }, 2, &ms));
     } else {
       const float2 *C = reinterpret_cast<const float2 *>(c->C);
@@ -819,7 +871,12 @@ hp_status autotune(hp_ctx *c, int nk, int mixed) {
   HPTRY(tune_plane(c, 64, nk));
   if (mixed) {
     HPTRY(setup32(c));
-    HPTRY(tune_gemm(c, 32, rows, nk));
+    if (c->lowp_gemm == HP_GEMM_FP32) HPTRY(tune_gemm(c, 32, rows, nk));
+    if (c->lowp_gemm == HP_GEMM_BF16) HPTRY(tune_gemm(c, 16, rows, nk));
+    if (c->lowp_gemm == HP_GEMM_BF16_PV32) {
+      HPTRY(tune_gemm(c, 16, c->n_beta, nk));
+      HPTRY(tune_gemm(c, 32, c->n_occ, nk));
+    }
     HPTRY(tune_plane(c, 32, nk));
   }
   return HP_OK;
@@ -833,6 +890,7 @@ hp_status cg_solve_mixed(hp_ctx *c, const KPair *kp, int nk, const double *eps_i
   const int nb = c->n_occ, nitems = nk * nb;
   const int rows = c->n_beta + c->n_occ;
   HPTRY(setup32(c));
+  if (c->lowp_gemm != HP_GEMM_FP32) HPTRY(setup16(c));
   int it_in = 0, nact = 0, ref = 0;
   bool trusted = false;
   int h_count[kCntStep] = {0};
@@ -876,7 +934,7 @@ hp_status cg_solve_mixed(hp_ctx *c, const KPair *kp, int nk, const double *eps_i
     }));
     // Above ~1e-6 the FP32 operator is exact enough that the inner solve's own residual
     // stands for the FP64 one; the next SCF iteration starts from an FP64 residual anyway.
-    if (tol >= kFp32TrustTol && inner_active == 0) {
+    if (c->lowp_gemm == HP_GEMM_FP32 && tol >= kFp32TrustTol && inner_active == 0) {
       nact = 0;
       ++ref;
       trusted = true;
@@ -980,6 +1038,8 @@ hp_status check_params(const hp_scf_params *p) {
   if (p->graph_chunk < 0 || p->graph_chunk > kMaxChunk)
     return fail(HP_ERR_ARG, "graph_chunk must be in 0..%d", kMaxChunk);
   if (p->autotune != 0 && p->autotune != 1) return fail(HP_ERR_ARG, "autotune must be 0 or 1");
+  if (p->lowp_gemm < HP_GEMM_FP32 || p->lowp_gemm > HP_GEMM_BF16_PV32)
+    return fail(HP_ERR_ARG, "unknown lowp_gemm %d", p->lowp_gemm);
   return HP_OK;
 }
 
@@ -1615,6 +1675,7 @@ extern "C" hp_status hp_sternheimer_scf(hp_ctx *c, int32_t pert_site, const doub
   HPTRY(check_params(p));
   c->graph_chunk = p->graph_chunk;
   c->use_tuned = p->autotune;
+  c->lowp_gemm = p->lowp_gemm;
   if (pert_site < 0 || pert_site >= c->n_hub) return fail(HP_ERR_ARG, "pert_site %d out of range", pert_site);
   if (st && st->struct_size != sizeof(hp_scf_stats)) return fail(HP_ERR_ARG, "hp_scf_stats.struct_size mismatch");
   return run_scf(c, pert_site, q_frac, p, dn0_out, dn_out, st);
@@ -1732,6 +1793,7 @@ extern "C" hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const do
   HPTRY(check_params(p));
   c->graph_chunk = p->graph_chunk;
   c->use_tuned = p->autotune;
+  c->lowp_gemm = p->lowp_gemm;
   if (pert_site < 0 || pert_site >= c->n_hub) return fail(HP_ERR_ARG, "pert_site out of range");
   if (mesh_k < 0 || mesh_k >= c->n_mesh) return fail(HP_ERR_ARG, "mesh_k out of range");
   std::vector<KPair> pairs;
@@ -1841,16 +1903,24 @@ extern "C" hp_status hp_tuning_report(hp_ctx *c, char *buf, int32_t len) {
   return HP_OK;
 }
 
+// Captured graphs bake in launch shapes: drop them when a shape is pinned.
+static void drop_graphs(hp_ctx *c) {
+  (void)hipStreamSynchronize(c->stream);
+  for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
 extern "C" hp_status hp_set_gemm_shape(hp_ctx *c, int32_t prec, int32_t rows, int32_t batch, int32_t tile,
                                        int32_t nsplit, int32_t expand_bands) {
   if (!c) return fail(HP_ERR_ARG, "context is NULL");
-  if (prec != 64 && prec != 32) return fail(HP_ERR_ARG, "prec must be 64 or 32");
+  if (prec != 64 && prec != 32 && prec != 16) return fail(HP_ERR_ARG, "prec must be 64, 32 or 16");
   if (rows < 1 || batch < 1 || batch > c->n_mesh) return fail(HP_ERR_ARG, "bad rows/batch");
   if (tile < 0 || tile > 3) return fail(HP_ERR_ARG, "tile must be in 0..3");
   if (nsplit < 1 || nsplit > c->nsplit_cap) return fail(HP_ERR_ARG, "nsplit must be in 1..%d", c->nsplit_cap);
   if (expand_bands != 32 && expand_bands != 64 && expand_bands != 128)
     return fail(HP_ERR_ARG, "expand_bands must be 32, 64 or 128");
   hp_ctx::GemmChoice g{prec, rows, batch, tile, nsplit, expand_bands / 32, 0.f, 0.f, 0.f, 0.f};
+  drop_graphs(c);
   for (auto &e : c->gemm_tuned)
     if (e.prec == prec && e.M == rows && e.nk == batch) {
       e = g;
@@ -1869,5 +1939,6 @@ extern "C" hp_status hp_set_plane_variant(hp_ctx *c, int32_t prec, int32_t varia
   c->plane_var[slot] = variant;
   c->plane_nvar[slot] = nv;
   c->plane_tuned[slot] = true;
+  drop_graphs(c);
   return HP_OK;
 }

@@ -152,6 +152,16 @@ hipError_t launch_zproj_reduce32(int nk, int M, int nb, int nsplit, const float2
 hipError_t launch_zexpand32(const KPair *kp, int use_kq, int nk, const float2 *T, long t_stride, int m0, int M,
                             const float2 *C, long c_kstride, double cscale, float2 *Y, int ld, int nb,
                             const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st);
+// BF16 variants (tables as packed bfloat16 complex, 32 bits each; vectors, outputs and
+// accumulation FP32). tile: 0 = 32x32, 3 = 64x64 (others fall back to 32x32).
+hipError_t launch_zproj16(const KPair *kp, int use_kq, int nk, const unsigned *T, long t_stride, int m0, int M,
+                          const float2 *X, int ld, int nb, const int *npw_of, float2 *Cpart, int nsplit,
+                          const int *active, int tile, hipStream_t st);
+hipError_t launch_zexpand16(const KPair *kp, int use_kq, int nk, const unsigned *T, long t_stride, int m0, int M,
+                            const float2 *C, long c_kstride, double cscale, float2 *Y, int ld, int nb,
+                            const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st);
+// out[i] = bf16(re) | bf16(im) << 16, round to nearest even
+hipError_t launch_to_bf16_pairs(const double2 *in, unsigned *out, long n, hipStream_t st);
 hipError_t launch_cg_init32(const KPair *kp, int nb, int nitems, const float2 *B, float2 *Xv, float2 *R, float2 *P,
                             const double *diag, const double *eps, int ld, const int *npw_of, long diag_stride,
                             double *rz, double *bn, double *rn, int *active, double tol, const int *only,

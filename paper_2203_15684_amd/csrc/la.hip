@@ -289,6 +289,269 @@ __global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, co
     }
 }
 
+// ---------------------------------------------------------------- BF16 GEMMs
+// Projector tables in bfloat16 (one 32-bit word per complex: real part in the low half),
+// vectors and accumulation in FP32, on v_mfma_f32_16x16x16_bf16 (measured on gfx950:
+// A lane l, value j -> A[l%16][4(l/16)+j]; B lane l, value j -> B[4(l/16)+j][l%16];
+// D as for the FP32 instruction).
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {  // round to nearest even
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ f4 mfma16(s4 a, s4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ s4 neg4(s4 a) {
+  s4 r;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) r[j] = (short)(a[j] ^ (short)0x8000);
+  return r;
+}
+constexpr int kKb16 = 32;        // K step per LDS stage (two MFMA k-blocks)
+constexpr int kLd16 = kKb16 + 4; // LDS row length in bf16 (8-byte aligned reads of 4 values)
+
+// C[k][m][v] (partial over a K split) = sum_G conj(T16[m0+m][G]) X[v][G], X FP32.
+template <int WM, int WN>
+__global__ void __launch_bounds__(256) k_zproj16(const KPair *kp, int use_kq, const unsigned *__restrict__ Tb,
+                                                 long t_stride, int m0, int M, const float2 *__restrict__ X, int ld,
+                                                 int nb, const int *__restrict__ npw_of, int nsplit,
+                                                 float2 *__restrict__ Cpart, int nk, const int *active) {
+  constexpr int TM = 32 * WM, TN = 32 * WN;
+  __shared__ __align__(8) short Ar[TM][kLd16], Ai[TM][kLd16], Br[TN][kLd16], Bi[TN][kLd16];
+  const int k = blockIdx.z / nsplit;
+  const int split = blockIdx.z - k * nsplit;
+  const int mt = blockIdx.x * TM;
+  const int nt = blockIdx.y * TN;
+  if (active) {
+    int a = 0;
+    for (int i = threadIdx.x; i < TN; i += 256) a |= (nt + i < nb) ? active[k * nb + nt + i] : 0;
+    if (!__syncthreads_or(a)) return;
+  }
+  const KPair P = kp[k];
+  const int e = use_kq ? P.ej : P.ek;
+  const int npw = npw_of[e];
+  const int chunk = ((npw + nsplit - 1) / nsplit + kKb16 - 1) / kKb16 * kKb16;
+  const int g_begin = split * chunk;
+  const int g_end = min(npw, g_begin + chunk);
+  const unsigned *Te = Tb + (size_t)e * t_stride + (size_t)m0 * ld;
+  const float2 *Xk = X + (size_t)k * nb * ld;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  f4 cr[WM][WN], ci[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      cr[i][j] = f4{0, 0, 0, 0};
+      ci[i][j] = f4{0, 0, 0, 0};
+    }
+  const int lr = threadIdx.x >> 5;  // 0..7
+  const int lc = threadIdx.x & 31;  // K column
+  unsigned ra[4 * WM];
+  float2 rb[4 * WN];
+  auto load = [&](int g0) {
+    const int g = g0 + lc;
+#pragma unroll
+    for (int i = 0; i < 4 * WM; ++i) {
+      const int row = mt + lr + 8 * i;
+      ra[i] = (row < M && g < g_end) ? Te[(size_t)row * ld + g] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < 4 * WN; ++i) {
+      const int col = nt + lr + 8 * i;
+      rb[i] = (col < nb && g < g_end) ? Xk[(size_t)col * ld + g] : make_float2(0.f, 0.f);
+    }
+  };
+  if (g_begin < g_end) load(g_begin);
+  for (int g0 = g_begin; g0 < g_end; g0 += kKb16) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4 * WM; ++i) {
+      Ar[lr + 8 * i][lc] = (short)(ra[i] & 0xFFFFu);
+      Ai[lr + 8 * i][lc] = (short)(ra[i] >> 16);
+    }
+#pragma unroll
+    for (int i = 0; i < 4 * WN; ++i) {
+      Br[lr + 8 * i][lc] = (short)bf16_rne(rb[i].x);
+      Bi[lr + 8 * i][lc] = (short)bf16_rne(rb[i].y);
+    }
+    __syncthreads();
+    if (g0 + kKb16 < g_end) load(g0 + kKb16);
+#pragma unroll
+    for (int kk = 0; kk < kKb16; kk += 16) {
+      const int kc = kk + 4 * (lane >> 4);
+      s4 ar[WM], ai[WM], br[WN], bi[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        const int row = (wm * WM + i) * 16 + (lane & 15);
+        ar[i] = *reinterpret_cast<const s4 *>(&Ar[row][kc]);
+        ai[i] = *reinterpret_cast<const s4 *>(&Ai[row][kc]);
+      }
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const int col = (wn * WN + j) * 16 + (lane & 15);
+        br[j] = *reinterpret_cast<const s4 *>(&Br[col][kc]);
+        bi[j] = *reinterpret_cast<const s4 *>(&Bi[col][kc]);
+      }
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        const s4 nai = neg4(ai[i]);
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {  // conj(a) * b
+          cr[i][j] = mfma16(ar[i], br[j], cr[i][j]);
+          cr[i][j] = mfma16(ai[i], bi[j], cr[i][j]);
+          ci[i][j] = mfma16(ar[i], bi[j], ci[i][j]);
+          ci[i][j] = mfma16(nai, br[j], ci[i][j]);
+        }
+      }
+    }
+  }
+  float2 *Cp = Cpart + ((size_t)split * nk + k) * (size_t)M * nb;
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = mt + (wm * WM + i) * 16 + 4 * (lane >> 4) + r;
+        const int v = nt + (wn * WN + j) * 16 + (lane & 15);
+        if (m < M && v < nb) Cp[(size_t)m * nb + v] = make_float2(cr[i][j][r], ci[i][j][r]);
+      }
+}
+
+// Y[v][G] += sum_m T16[m0+m][G] C[k][m][v] (C, Y FP32); tile (32 BV bands) x 64 plane waves.
+template <int BV>
+__global__ void __launch_bounds__(256) k_zexpand16(const KPair *kp, int use_kq, const unsigned *__restrict__ Tb,
+                                                   long t_stride, int m0, int M, const float2 *__restrict__ C,
+                                                   long c_kstride, double cscale, float2 *__restrict__ Y, int ld,
+                                                   int nb, const int *__restrict__ npw_of, const int *active) {
+  constexpr int TV = 32 * BV;
+  __shared__ __align__(8) short Cr[TV][kLd16], Ci[TV][kLd16];  // [v][m]
+  __shared__ __align__(8) short Tr[64][kLd16], Ti[64][kLd16];  // [G][m]
+  const int k = blockIdx.z;
+  const int vt = blockIdx.y * TV;
+  if (active) {
+    int a = 0;
+    for (int i = threadIdx.x; i < TV; i += 256) a |= (vt + i < nb) ? active[k * nb + vt + i] : 0;
+    if (!__syncthreads_or(a)) return;
+  }
+  const KPair P = kp[k];
+  const int e = use_kq ? P.ej : P.ek;
+  const int npw = npw_of[e];
+  const int gt = blockIdx.x * 64;
+  if (gt >= npw) return;
+  const unsigned *Te = Tb + (size_t)e * t_stride + (size_t)m0 * ld;
+  const float2 *Ck = C + (size_t)k * c_kstride;
+  const float cs = (float)cscale;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wv = wave >> 1, wg = wave & 1;
+  f4 yr[BV][2], yi[BV][2];
+#pragma unroll
+  for (int i = 0; i < BV; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      yr[i][j] = f4{0, 0, 0, 0};
+      yi[i][j] = f4{0, 0, 0, 0};
+    }
+  float2 rc[4 * BV];
+  unsigned rt[8];
+  auto load = [&](int mb) {
+#pragma unroll
+    for (int c = 0; c < 4 * BV; ++c) {  // C slab: TV bands x 32 m (consecutive threads: consecutive bands)
+      const int idx = threadIdx.x + 256 * c;
+      const int vv = idx % TV, mm = idx / TV;
+      const int m = mb + mm, v = vt + vv;
+      float2 val = make_float2(0.f, 0.f);
+      if (m < M && v < nb) {
+        val = Ck[(size_t)m * nb + v];
+        val.x *= cs;
+        val.y *= cs;
+      }
+      rc[c] = val;
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {  // T slab: 32 m x 64 G
+      const int idx = threadIdx.x + c * 256;
+      const int mm = idx >> 6, gg = idx & 63;
+      const int m = mb + mm, g = gt + gg;
+      rt[c] = (m < M && g < npw) ? Te[(size_t)m * ld + g] : 0u;
+    }
+  };
+  load(0);
+  for (int mb = 0; mb < M; mb += kKb16) {
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 4 * BV; ++c) {
+      const int idx = threadIdx.x + 256 * c;
+      Cr[idx % TV][idx / TV] = (short)bf16_rne(rc[c].x);
+      Ci[idx % TV][idx / TV] = (short)bf16_rne(rc[c].y);
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int idx = threadIdx.x + c * 256;
+      Tr[idx & 63][idx >> 6] = (short)(rt[c] & 0xFFFFu);
+      Ti[idx & 63][idx >> 6] = (short)(rt[c] >> 16);
+    }
+    __syncthreads();
+    if (mb + kKb16 < M) load(mb + kKb16);
+#pragma unroll
+    for (int kk = 0; kk < kKb16; kk += 16) {
+      const int kc = kk + 4 * (lane >> 4);
+      s4 br[2], bi[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int g = wg * 32 + 16 * j + (lane & 15);
+        br[j] = *reinterpret_cast<const s4 *>(&Tr[g][kc]);
+        bi[j] = *reinterpret_cast<const s4 *>(&Ti[g][kc]);
+      }
+#pragma unroll
+      for (int i = 0; i < BV; ++i) {
+        const int v = (wv * BV + i) * 16 + (lane & 15);
+        const s4 ar = *reinterpret_cast<const s4 *>(&Cr[v][kc]);
+        const s4 ai = *reinterpret_cast<const s4 *>(&Ci[v][kc]);
+        const s4 nai = neg4(ai);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {  // c * t
+          yr[i][j] = mfma16(ar, br[j], yr[i][j]);
+          yr[i][j] = mfma16(nai, bi[j], yr[i][j]);
+          yi[i][j] = mfma16(ar, bi[j], yi[i][j]);
+          yi[i][j] = mfma16(ai, br[j], yi[i][j]);
+        }
+      }
+    }
+  }
+  float2 *Yk = Y + (size_t)k * nb * ld;
+#pragma unroll
+  for (int i = 0; i < BV; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int v = vt + (wv * BV + i) * 16 + 4 * (lane >> 4) + r;
+      if (v >= nb) continue;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int g = gt + wg * 32 + 16 * j + (lane & 15);
+        if (g < npw) {
+          float2 y = Yk[(size_t)v * ld + g];
+          y.x += yr[i][j][r];
+          y.y += yi[i][j][r];
+          Yk[(size_t)v * ld + g] = y;
+        }
+      }
+    }
+}
+
+__global__ void k_to_bf16_pairs(const double2 *__restrict__ in, unsigned *__restrict__ out, long n) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 z = in[i];
+  out[i] = (unsigned)bf16_rne((float)z.x) | ((unsigned)bf16_rne((float)z.y) << 16);
+}
+
 // ------------------------------------------------------------ reductions
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -638,6 +901,47 @@ hipError_t launch_zproj_reduce32(int nk, int M, int nb, int nsplit, const float2
   const int total = nk * M * nb;
   hipLaunchKernelGGL(k_zproj_reduce<float2>, dim3((total + 255) / 256), dim3(256), 0, st, total, M, nb, nsplit,
                      Cpart, row_scale, gscale, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_zproj16(const KPair *kp, int use_kq, int nk, const unsigned *T, long t_stride, int m0, int M,
+                          const float2 *X, int ld, int nb, const int *npw_of, float2 *Cpart, int nsplit,
+                          const int *active, int tile, hipStream_t st) {
+  const int w = tile == 3 ? 2 : 1;
+  dim3 grid((M + 32 * w - 1) / (32 * w), (nb + 32 * w - 1) / (32 * w), nk * nsplit);
+  if (w == 2)
+    hipLaunchKernelGGL((k_zproj16<2, 2>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, X, ld, nb, npw_of,
+                       nsplit, Cpart, nk, active);
+  else
+    hipLaunchKernelGGL((k_zproj16<1, 1>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, X, ld, nb, npw_of,
+                       nsplit, Cpart, nk, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_zexpand16(const KPair *kp, int use_kq, int nk, const unsigned *T, long t_stride, int m0, int M,
+                            const float2 *C, long c_kstride, double cscale, float2 *Y, int ld, int nb,
+                            const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st) {
+  bv = (bv == 2 || bv == 4) ? bv : 1;
+  dim3 grid((npw_max + 63) / 64, (nb + 32 * bv - 1) / (32 * bv), nk);
+  switch (bv) {
+    case 2:
+      hipLaunchKernelGGL((k_zexpand16<2>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride,
+                         cscale, Y, ld, nb, npw_of, active);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_zexpand16<4>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride,
+                         cscale, Y, ld, nb, npw_of, active);
+      break;
+    default:
+      hipLaunchKernelGGL((k_zexpand16<1>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride,
+                         cscale, Y, ld, nb, npw_of, active);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_to_bf16_pairs(const double2 *in, unsigned *out, long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_bf16_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n);
   return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ HP_OK = 0
 HP_WARN_NOT_CONVERGED = 1
 HP_ERR_ARG, HP_ERR_SHAPE, HP_ERR_HIP, HP_ERR_OOM, HP_ERR_STATE, HP_ERR_SINGULAR, HP_ERR_NUMERIC = -1, -2, -3, -4, -5, -6, -7
 HP_FP64, HP_MIXED = 0, 1
+HP_GEMM_FP32, HP_GEMM_BF16, HP_GEMM_BF16_PV32 = 0, 1, 2
 HP_XC_LDA_PZ81 = 1
 
 
@@ -63,7 +64,7 @@ class HpScfParams(C.Structure):
                 ("cg_tol", C.c_double), ("niter_max", C.c_int32), ("alpha_mix", C.c_double), ("nmix", C.c_int32),
                 ("max_cg_iter", C.c_int32), ("precision", C.c_int32), ("verbosity", C.c_int32),
                 ("inner_tol", C.c_double), ("max_refine", C.c_int32), ("graph_chunk", C.c_int32),
-                ("autotune", C.c_int32)]
+                ("autotune", C.c_int32), ("lowp_gemm", C.c_int32)]
 
 
 class HpScfStats(C.Structure):
@@ -155,11 +156,13 @@ class ScfParams:
     max_refine: int = 12
     graph_chunk: int = 8   # CG iterations per captured hipGraph launch; 0 launches kernels one by one
     autotune: int = 1      # time candidate GEMM tiles / FFT plane batches on first use of a shape
+    lowp_gemm: int = 0     # HP_MIXED: HP_GEMM_FP32, HP_GEMM_BF16 or HP_GEMM_BF16_PV32
 
     def c(self) -> HpScfParams:
         return HpScfParams(C.sizeof(HpScfParams), self.conv_thr_chi, self.conv_thr_v, self.cg_tol, self.niter_max,
                            self.alpha_mix, self.nmix, self.max_cg_iter, self.precision, self.verbosity,
-                           self.inner_tol, self.max_refine, self.graph_chunk, self.autotune)
+                           self.inner_tol, self.max_refine, self.graph_chunk, self.autotune,
+                           self.lowp_gemm)
 
 
 class Context:

@@ -29,6 +29,7 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--max-refine", type=int, default=12)
     ap.add_argument("--graph-chunk", type=int, default=8)
+    ap.add_argument("--lowp-gemm", type=int, default=0, help="0 FP32, 1 BF16, 2 BF16 with P_v in FP32")
     a = ap.parse_args()
     from synth import cache
     from paper_2203_15684_amd import hp
@@ -37,7 +38,8 @@ def main():
     p = hp.ScfParams(conv_thr_chi=a.conv_thr_chi, conv_thr_v=a.conv_thr_v, cg_tol=a.cg_tol,
                      niter_max=a.niter_max, max_cg_iter=2000, verbosity=a.verbosity,
                      precision=hp.HP_FP64 if a.precision == "fp64" else hp.HP_MIXED,
-                     inner_tol=a.inner_tol, max_refine=a.max_refine, graph_chunk=a.graph_chunk)
+                     inner_tol=a.inner_tol, max_refine=a.max_refine, graph_chunk=a.graph_chunk,
+                     lowp_gemm=a.lowp_gemm)
     hp.hp_profile_start(ctx)
     dn0, dn, st, status = hp.hp_sternheimer_scf(ctx, a.site, a.q, p)
     prof = hp.hp_profile_stop(ctx)

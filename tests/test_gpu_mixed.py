@@ -1,6 +1,8 @@
-"""Mixed-precision path (FP32 FFTs and FP32 MFMA projections inside the PCG, FP64
-residual refinement of every Sternheimer solve, FP64 orthogonalization, scalars,
-chi assembly and inversion) against the FP64 oracle and the FP64 GPU path.
+"""Mixed-precision path (FP32 FFTs and FP32 or BF16 MFMA projections inside the PCG,
+FP64 residual refinement of every Sternheimer solve, FP64 orthogonalization, scalars,
+chi assembly and inversion) against the FP64 oracle and the FP64 GPU path. Every test
+runs with each projection number type: FP32, BF16 for the KB and P_v GEMMs, and BF16
+for the KB GEMMs with P_v in FP32.
 
 Bar (stated for this form): chi within 1e-6 relative and U/V within 5 meV of the
 FP64 reference; with a tight solve tolerance the refinement reaches FP64 accuracy.
@@ -36,14 +38,18 @@ def rel(a, b):
     return np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max()
 
 
-def mixed(cg_tol, thr=1e-12):
+LOWP = [0, 1, 2]   # HP_GEMM_FP32, HP_GEMM_BF16, HP_GEMM_BF16_PV32
+
+
+def mixed(cg_tol, thr=1e-12, lowp=0):
     hp = _hp()
     return hp.ScfParams(conv_thr_chi=thr, conv_thr_v=1e-10, cg_tol=cg_tol, niter_max=100, max_cg_iter=2000,
-                        precision=hp.HP_MIXED)
+                        precision=hp.HP_MIXED, lowp_gemm=lowp)
 
 
+@pytest.mark.parametrize("lowp", LOWP)
 @pytest.mark.parametrize("name,q", [("sc1_gamma", (0, 0, 0)), ("duo_k221", (0, 0.5, 0))])
-def test_mixed_first_order_solve_refines_to_fp64(name, q):
+def test_mixed_first_order_solve_refines_to_fp64(name, q, lowp):
     hp = _hp()
     o = orc(name)
     rng = np.random.default_rng(3)
@@ -51,27 +57,34 @@ def test_mixed_first_order_solve_refines_to_fp64(name, q):
     for ik in range(o.n_mesh):
         j, _ = o.kq_entry(ik, q)
         x_ref, _ = o.solve(ik, q, o.rhs(ik, q, 0, dv), None, oracle.ScfParams(cg_tol=1e-14))
-        du, st = hp.hp_solve_first_order(ctx(name), 0, q, ik, dv, mixed(1e-12), o.kpts[j].npw)
+        du, st = hp.hp_solve_first_order(ctx(name), 0, q, ik, dv, mixed(1e-12, lowp=lowp), o.kpts[j].npw)
         assert st == 0
         assert rel(du, x_ref) < 1e-10, f"k {ik}"
 
 
+@pytest.mark.parametrize("lowp", LOWP)
 @pytest.mark.parametrize("name,site,q", [("sc1_gamma", 0, (0, 0, 0)), ("duo_k221", 1, (0, 0.5, 0))])
-def test_mixed_scf_matches_oracle(name, site, q):
+def test_mixed_scf_matches_oracle(name, site, q, lowp):
     hp = _hp()
     ref = orc(name).scf(site, np.array(q), oracle.ScfParams(cg_tol=1e-13, conv_thr_chi=1e-13, conv_thr_v=1e-11))
-    dn0, dn, st, status = hp.hp_sternheimer_scf(ctx(name), site, q, mixed(1e-10, 1e-10))
+    dn0, dn, st, status = hp.hp_sternheimer_scf(ctx(name), site, q, mixed(1e-10, 1e-10, lowp))
     assert status == 0
     assert st["h_applies_lowp"] > 0
     assert rel(dn0, ref["dn0"]) < 1e-6
     assert rel(dn, ref["dn"]) < 1e-6
 
 
-def test_mixed_response_matrix_and_uv():
+@functools.lru_cache(maxsize=None)
+def _orc_response(name):
+    return orc(name).response_matrix(oracle.ScfParams(cg_tol=1e-13, conv_thr_chi=1e-13, conv_thr_v=1e-11))
+
+
+@pytest.mark.parametrize("lowp", LOWP)
+def test_mixed_response_matrix_and_uv(lowp):
     hp = _hp()
     name = "duo_k221"
-    c0, c1, _, _, _ = orc(name).response_matrix(oracle.ScfParams(cg_tol=1e-13, conv_thr_chi=1e-13, conv_thr_v=1e-11))
-    chi0, chi, mim, st, status = hp.hp_response_matrix(ctx(name), (1, 2, 1), mixed(1e-10, 1e-10))
+    c0, c1, _, _, _ = _orc_response(name)
+    chi0, chi, mim, st, status = hp.hp_response_matrix(ctx(name), (1, 2, 1), mixed(1e-10, 1e-10, lowp))
     assert status == 0
     assert rel(chi0, c0) < 1e-6 and rel(chi, c1) < 1e-6
     uv = hp.hp_hubbard_params(chi0, chi)

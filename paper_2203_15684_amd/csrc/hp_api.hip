@@ -1024,6 +1024,13 @@ hp_status zdots(hp_ctx *c, int nvec, const double2 *const *vecs, const double2 *
   return HP_OK;
 }
 
+// Per-call controls that the kernels' launch paths read from the context.
+void apply_call_params(hp_ctx *c, const hp_scf_params *p) {
+  c->graph_chunk = p->graph_chunk;
+  c->use_tuned = p->autotune;
+  c->lowp_gemm = p->lowp_gemm;
+}
+
 hp_status check_params(const hp_scf_params *p) {
   if (!p) return fail(HP_ERR_ARG, "params is NULL");
   if (p->struct_size != sizeof(hp_scf_params)) return fail(HP_ERR_ARG, "hp_scf_params.struct_size mismatch");
@@ -1673,9 +1680,7 @@ extern "C" hp_status hp_sternheimer_scf(hp_ctx *c, int32_t pert_site, const doub
   if (!c) return fail(HP_ERR_ARG, "context is NULL");
   if (!q_frac || !dn0_out || !dn_out) return fail(HP_ERR_ARG, "NULL argument");
   HPTRY(check_params(p));
-  c->graph_chunk = p->graph_chunk;
-  c->use_tuned = p->autotune;
-  c->lowp_gemm = p->lowp_gemm;
+  apply_call_params(c, p);
   if (pert_site < 0 || pert_site >= c->n_hub) return fail(HP_ERR_ARG, "pert_site %d out of range", pert_site);
   if (st && st->struct_size != sizeof(hp_scf_stats)) return fail(HP_ERR_ARG, "hp_scf_stats.struct_size mismatch");
   return run_scf(c, pert_site, q_frac, p, dn0_out, dn_out, st);
@@ -1686,6 +1691,7 @@ extern "C" hp_status hp_response_matrix(hp_ctx *c, const int32_t nq[3], const hp
   if (!c) return fail(HP_ERR_ARG, "context is NULL");
   if (!nq || !chi0_out || !chi_out) return fail(HP_ERR_ARG, "NULL argument");
   HPTRY(check_params(p));
+  apply_call_params(c, p);
   if (nq[0] < 1 || nq[1] < 1 || nq[2] < 1) return fail(HP_ERR_ARG, "nq must be >= 1");
   if (st && st->struct_size != sizeof(hp_scf_stats)) return fail(HP_ERR_ARG, "hp_scf_stats.struct_size mismatch");
   const int nh = c->n_hub;
@@ -1791,9 +1797,7 @@ extern "C" hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const do
   if (!c) return fail(HP_ERR_ARG, "context is NULL");
   if (!q_frac || !du_out) return fail(HP_ERR_ARG, "NULL argument");
   HPTRY(check_params(p));
-  c->graph_chunk = p->graph_chunk;
-  c->use_tuned = p->autotune;
-  c->lowp_gemm = p->lowp_gemm;
+  apply_call_params(c, p);
   if (pert_site < 0 || pert_site >= c->n_hub) return fail(HP_ERR_ARG, "pert_site out of range");
   if (mesh_k < 0 || mesh_k >= c->n_mesh) return fail(HP_ERR_ARG, "mesh_k out of range");
   std::vector<KPair> pairs;

@@ -47,6 +47,17 @@ __device__ __forceinline__ C zc() {
 constexpr int kKb = 16;     // K step staged through LDS
 constexpr int kPad = 1;     // LDS row padding (complex elements)
 
+// Workgroups go to the eight XCDs round robin (linear id mod 8), each XCD with its own L2.
+// The GEMM grids are one-dimensional: the tiles of a group, which read the same operand
+// slabs, take consecutive slots on one XCD, so each slab comes from HBM once into that L2.
+__device__ __forceinline__ bool xcd_tile(int n_inner, int n_groups, int &inner, int &group) {
+  const int L = blockIdx.x, xcd = L & 7, s = L >> 3;
+  inner = s % n_inner;
+  group = (s / n_inner) * 8 + xcd;
+  return group < n_groups;
+}
+inline unsigned xcd_grid(int n_inner, int n_groups) { return 8u * (unsigned)n_inner * ((n_groups + 7) / 8); }
+
 // C[k][m][v] (partial over a K split) = sum_G conj(T[m0+m][G]) X[v][G].
 // Workgroup tile (32 WM rows) x (32 WN bands), four waves in a 2 x 2 arrangement, each
 // holding WM x WN 16x16 MFMA blocks; the next K slab is prefetched into registers while
@@ -56,16 +67,19 @@ __global__ void __launch_bounds__(256) k_zproj(const KPair *kp, int use_kq, cons
                                                long t_stride, int m0, int M,
                                                const typename Mf<T>::c2 *__restrict__ X, int ld, int nb,
                                                const int *__restrict__ npw_of, int nsplit,
-                                               typename Mf<T>::c2 *__restrict__ Cpart, int nk, const int *active) {
+                                               typename Mf<T>::c2 *__restrict__ Cpart, int nk, const int *active,
+                                               int nmt, int nnt) {
   using C2 = typename Mf<T>::c2;
   using A4 = typename Mf<T>::acc;
   constexpr int TM = 32 * WM, TN = 32 * WN;
   __shared__ C2 At[TM][kKb + kPad];
   __shared__ C2 Bt[TN][kKb + kPad];
-  const int k = blockIdx.z / nsplit;
-  const int split = blockIdx.z - k * nsplit;
-  const int mt = blockIdx.x * TM;
-  const int nt = blockIdx.y * TN;
+  int inner, group;  // group: (k, K split); inner: (row tile, band tile)
+  if (!xcd_tile(nmt * nnt, nk * nsplit, inner, group)) return;
+  const int k = group / nsplit;
+  const int split = group - k * nsplit;
+  const int mt = (inner % nmt) * TM;
+  const int nt = (inner / nmt) * TN;
   if (active) {  // skip tiles whose bands are all converged (their outputs are not used)
     int a = 0;
     for (int i = threadIdx.x; i < TN; i += 256) a |= (nt + i < nb) ? active[k * nb + nt + i] : 0;
@@ -178,14 +192,17 @@ __global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, co
                                                  long t_stride, int m0, int M,
                                                  const typename Mf<T>::c2 *__restrict__ C, long c_kstride,
                                                  double cscale, typename Mf<T>::c2 *__restrict__ Y, int ld, int nb,
-                                                 const int *__restrict__ npw_of, const int *active) {
+                                                 const int *__restrict__ npw_of, const int *active, int nk, int ngt,
+                                                 int nvt) {
   using C2 = typename Mf<T>::c2;
   using A4 = typename Mf<T>::acc;
   constexpr int TV = 32 * BV;
   __shared__ C2 Ct[TV][kKb + kPad];  // [v][m]
   __shared__ C2 Tt[kKb][64 + kPad];  // [m][G]
-  const int k = blockIdx.z;
-  const int vt = blockIdx.y * TV;
+  int inner, group;  // group: (k, plane-wave tile); inner: band tile
+  if (!xcd_tile(nvt, nk * ngt, inner, group)) return;
+  const int k = group / ngt;
+  const int vt = inner * TV;
   if (active) {
     int a = 0;
     for (int i = threadIdx.x; i < TV; i += 256) a |= (vt + i < nb) ? active[k * nb + vt + i] : 0;
@@ -194,7 +211,7 @@ __global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, co
   const KPair P = kp[k];
   const int e = use_kq ? P.ej : P.ek;
   const int npw = npw_of[e];
-  const int gt = blockIdx.x * 64;
+  const int gt = (group - k * ngt) * 64;
   if (gt >= npw) return;
   const C2 *Te = Tb + (size_t)e * t_stride + (size_t)m0 * ld;
   const C2 *Ck = C + (size_t)k * c_kstride;
@@ -318,13 +335,16 @@ template <int WM, int WN>
 __global__ void __launch_bounds__(256) k_zproj16(const KPair *kp, int use_kq, const unsigned *__restrict__ Tb,
                                                  long t_stride, int m0, int M, const float2 *__restrict__ X, int ld,
                                                  int nb, const int *__restrict__ npw_of, int nsplit,
-                                                 float2 *__restrict__ Cpart, int nk, const int *active) {
+                                                 float2 *__restrict__ Cpart, int nk, const int *active, int nmt,
+                                                 int nnt) {
   constexpr int TM = 32 * WM, TN = 32 * WN;
   __shared__ __align__(8) short Ar[TM][kLd16], Ai[TM][kLd16], Br[TN][kLd16], Bi[TN][kLd16];
-  const int k = blockIdx.z / nsplit;
-  const int split = blockIdx.z - k * nsplit;
-  const int mt = blockIdx.x * TM;
-  const int nt = blockIdx.y * TN;
+  int inner, group;  // group: (k, K split); inner: (row tile, band tile)
+  if (!xcd_tile(nmt * nnt, nk * nsplit, inner, group)) return;
+  const int k = group / nsplit;
+  const int split = group - k * nsplit;
+  const int mt = (inner % nmt) * TM;
+  const int nt = (inner / nmt) * TN;
   if (active) {
     int a = 0;
     for (int i = threadIdx.x; i < TN; i += 256) a |= (nt + i < nb) ? active[k * nb + nt + i] : 0;
@@ -428,12 +448,15 @@ template <int BV>
 __global__ void __launch_bounds__(256) k_zexpand16(const KPair *kp, int use_kq, const unsigned *__restrict__ Tb,
                                                    long t_stride, int m0, int M, const float2 *__restrict__ C,
                                                    long c_kstride, double cscale, float2 *__restrict__ Y, int ld,
-                                                   int nb, const int *__restrict__ npw_of, const int *active) {
+                                                   int nb, const int *__restrict__ npw_of, const int *active,
+                                                   int nk, int ngt, int nvt) {
   constexpr int TV = 32 * BV;
   __shared__ __align__(8) short Cr[TV][kLd16], Ci[TV][kLd16];  // [v][m]
   __shared__ __align__(8) short Tr[64][kLd16], Ti[64][kLd16];  // [G][m]
-  const int k = blockIdx.z;
-  const int vt = blockIdx.y * TV;
+  int inner, group;  // group: (k, plane-wave tile); inner: band tile
+  if (!xcd_tile(nvt, nk * ngt, inner, group)) return;
+  const int k = group / ngt;
+  const int vt = inner * TV;
   if (active) {
     int a = 0;
     for (int i = threadIdx.x; i < TV; i += 256) a |= (vt + i < nb) ? active[k * nb + vt + i] : 0;
@@ -442,7 +465,7 @@ __global__ void __launch_bounds__(256) k_zexpand16(const KPair *kp, int use_kq, 
   const KPair P = kp[k];
   const int e = use_kq ? P.ej : P.ek;
   const int npw = npw_of[e];
-  const int gt = blockIdx.x * 64;
+  const int gt = (group - k * ngt) * 64;
   if (gt >= npw) return;
   const unsigned *Te = Tb + (size_t)e * t_stride + (size_t)m0 * ld;
   const float2 *Ck = C + (size_t)k * c_kstride;
@@ -832,23 +855,24 @@ hipError_t zproj_t(const KPair *kp, int use_kq, int nk, const typename Mf<T>::c2
                    const typename Mf<T>::c2 *X, int ld, int nb, const int *npw_of, typename Mf<T>::c2 *Cpart,
                    int nsplit, const int *active, int tile, hipStream_t st) {
   const int wm = (tile & 1) ? 2 : 1, wn = (tile & 2) ? 2 : 1;
-  dim3 grid((M + 32 * wm - 1) / (32 * wm), (nb + 32 * wn - 1) / (32 * wn), nk * nsplit);
+  const int nmt = (M + 32 * wm - 1) / (32 * wm), nnt = (nb + 32 * wn - 1) / (32 * wn);
+  dim3 grid(xcd_grid(nmt * nnt, nk * nsplit));
   switch (tile) {
     case 1:
       hipLaunchKernelGGL((k_zproj<T, 2, 1>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, X, ld, nb,
-                         npw_of, nsplit, Cpart, nk, active);
+                         npw_of, nsplit, Cpart, nk, active, nmt, nnt);
       break;
     case 2:
       hipLaunchKernelGGL((k_zproj<T, 1, 2>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, X, ld, nb,
-                         npw_of, nsplit, Cpart, nk, active);
+                         npw_of, nsplit, Cpart, nk, active, nmt, nnt);
       break;
     case 3:
       hipLaunchKernelGGL((k_zproj<T, 2, 2>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, X, ld, nb,
-                         npw_of, nsplit, Cpart, nk, active);
+                         npw_of, nsplit, Cpart, nk, active, nmt, nnt);
       break;
     default:
       hipLaunchKernelGGL((k_zproj<T, 1, 1>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, X, ld, nb,
-                         npw_of, nsplit, Cpart, nk, active);
+                         npw_of, nsplit, Cpart, nk, active, nmt, nnt);
       break;
   }
   return hipGetLastError();
@@ -859,19 +883,20 @@ hipError_t zexpand_t(const KPair *kp, int use_kq, int nk, const typename Mf<T>::
                      const typename Mf<T>::c2 *C, long c_kstride, double cscale, typename Mf<T>::c2 *Y, int ld,
                      int nb, const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st) {
   bv = (bv == 2 || bv == 4) ? bv : 1;
-  dim3 grid((npw_max + 63) / 64, (nb + 32 * bv - 1) / (32 * bv), nk);
+  const int ngt = (npw_max + 63) / 64, nvt = (nb + 32 * bv - 1) / (32 * bv);
+  dim3 grid(xcd_grid(nvt, nk * ngt));
   switch (bv) {
     case 2:
       hipLaunchKernelGGL((k_zexpand<T, 2>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, C, c_kstride,
-                         cscale, Y, ld, nb, npw_of, active);
+                         cscale, Y, ld, nb, npw_of, active, nk, ngt, nvt);
       break;
     case 4:
       hipLaunchKernelGGL((k_zexpand<T, 4>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, C, c_kstride,
-                         cscale, Y, ld, nb, npw_of, active);
+                         cscale, Y, ld, nb, npw_of, active, nk, ngt, nvt);
       break;
     default:
       hipLaunchKernelGGL((k_zexpand<T, 1>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, C, c_kstride,
-                         cscale, Y, ld, nb, npw_of, active);
+                         cscale, Y, ld, nb, npw_of, active, nk, ngt, nvt);
       break;
   }
   return hipGetLastError();
@@ -908,13 +933,14 @@ hipError_t launch_zproj16(const KPair *kp, int use_kq, int nk, const unsigned *T
                           const float2 *X, int ld, int nb, const int *npw_of, float2 *Cpart, int nsplit,
                           const int *active, int tile, hipStream_t st) {
   const int w = tile == 3 ? 2 : 1;
-  dim3 grid((M + 32 * w - 1) / (32 * w), (nb + 32 * w - 1) / (32 * w), nk * nsplit);
+  const int nmt = (M + 32 * w - 1) / (32 * w), nnt = (nb + 32 * w - 1) / (32 * w);
+  dim3 grid(xcd_grid(nmt * nnt, nk * nsplit));
   if (w == 2)
     hipLaunchKernelGGL((k_zproj16<2, 2>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, X, ld, nb, npw_of,
-                       nsplit, Cpart, nk, active);
+                       nsplit, Cpart, nk, active, nmt, nnt);
   else
     hipLaunchKernelGGL((k_zproj16<1, 1>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, X, ld, nb, npw_of,
-                       nsplit, Cpart, nk, active);
+                       nsplit, Cpart, nk, active, nmt, nnt);
   return hipGetLastError();
 }
 
@@ -922,19 +948,20 @@ hipError_t launch_zexpand16(const KPair *kp, int use_kq, int nk, const unsigned 
                             const float2 *C, long c_kstride, double cscale, float2 *Y, int ld, int nb,
                             const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st) {
   bv = (bv == 2 || bv == 4) ? bv : 1;
-  dim3 grid((npw_max + 63) / 64, (nb + 32 * bv - 1) / (32 * bv), nk);
+  const int ngt = (npw_max + 63) / 64, nvt = (nb + 32 * bv - 1) / (32 * bv);
+  dim3 grid(xcd_grid(nvt, nk * ngt));
   switch (bv) {
     case 2:
       hipLaunchKernelGGL((k_zexpand16<2>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride,
-                         cscale, Y, ld, nb, npw_of, active);
+                         cscale, Y, ld, nb, npw_of, active, nk, ngt, nvt);
       break;
     case 4:
       hipLaunchKernelGGL((k_zexpand16<4>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride,
-                         cscale, Y, ld, nb, npw_of, active);
+                         cscale, Y, ld, nb, npw_of, active, nk, ngt, nvt);
       break;
     default:
       hipLaunchKernelGGL((k_zexpand16<1>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride,
-                         cscale, Y, ld, nb, npw_of, active);
+                         cscale, Y, ld, nb, npw_of, active, nk, ngt, nvt);
       break;
   }
   return hipGetLastError();

@@ -84,8 +84,17 @@ def test_mixed_response_matrix_and_uv(lowp):
     hp = _hp()
     name = "duo_k221"
     c0, c1, _, _, _ = _orc_response(name)
-    chi0, chi, mim, st, status = hp.hp_response_matrix(ctx(name), (1, 2, 1), mixed(1e-10, 1e-10, lowp))
+    c = hp.hp_ground_state_load(ground_state(name))
+    hp.hp_profile_start(c)
+    chi0, chi, mim, st, status = hp.hp_response_matrix(c, (1, 2, 1), mixed(1e-10, 1e-10, lowp))
+    prof = hp.hp_profile_stop(c)
     assert status == 0
+    # the whole-response entry point runs the requested projection type and tunes its shapes
+    calls = {k: v[0] for k, v in prof.items()}
+    assert (calls.get("zproj16", 0) > 0) == (lowp in (1, 2))
+    assert (calls.get("zproj32", 0) > 0) == (lowp in (0, 2))
+    rep = hp.hp_tuning_report(c)
+    assert {g["prec"] for g in rep["gemm"]} == ({64, 32} if lowp == 0 else {64, 16} if lowp == 1 else {64, 32, 16})
     assert rel(chi0, c0) < 1e-6 and rel(chi, c1) < 1e-6
     uv = hp.hp_hubbard_params(chi0, chi)
     assert np.abs(uv - oracle.hubbard_params(c0, c1)).max() * HA_MEV < 5.0

@@ -98,7 +98,7 @@ def test_pinning_rejects_bad_shapes():
     from paper_2203_15684_amd import hp
     gs = ground_state("sc1_gamma")
     ctx = hp.hp_ground_state_load(gs)
-    for args in [(16, 8, 1, 0, 1, 32), (64, 8, 1, 4, 1, 32), (64, 8, 1, 0, 0, 32), (64, 8, 1, 0, 1, 48),
+    for args in [(8, 8, 1, 0, 1, 32), (64, 8, 1, 4, 1, 32), (64, 8, 1, 0, 0, 32), (64, 8, 1, 0, 1, 48),
                  (64, 8, 2, 0, 1, 32)]:
         with pytest.raises(hp.HpError):
             hp.hp_set_gemm_shape(ctx, *args)

@@ -282,6 +282,8 @@ def main():
         "chi0_diag": [float(x) for x in np.diag(chi0)[:gs.n_hub]],
         "chi_diag": [float(x) for x in np.diag(chi)[:gs.n_hub]],
         "U_eV": [float(x) * HA_EV for x in np.diag(uv)[:gs.n_hub]],
+        "V_nearest_neighbours_eV": [{"I": i, "J": j, "d_bohr": round(d, 4), "V": float(uv[i, j]) * HA_EV}
+                                    for i, j, d in hp.hp_neighbours(gs.cell, gs.hub_tau, gs.qmesh)],
         "roofline": rec,
         "setup_s": {"ground_state": round(t_gen, 1)},
         "autotune": hp.hp_tuning_report(ctx),

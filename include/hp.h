@@ -189,6 +189,22 @@ hp_status hp_response_matrix(hp_ctx *c, const int32_t nq[3], const hp_scf_params
  * largest |entry|.  Host-only: needs no context and no GPU. */
 hp_status hp_hubbard_params(int32_t n, const double *chi0, const double *chi, double *uv_out);
 
+/* Nearest-neighbour pairs for the inter-site V of Eq. 9 in the periodic
+ * supercell that the q mesh images (Eq. 12).  Sites are numbered as in
+ * hp_response_matrix: site (s, l) -> l * n_hub + s, cell l enumerating the
+ * nq[0] x nq[1] x nq[2] offsets R_l (last index fastest), at hub_tau[s] + R_l . cell.
+ * For each primitive site I = s (cell 0), every other supercell site J whose
+ * minimum-image distance (over translations of the supercell) is within
+ * dist_thr (bohr) of I's smallest such distance is a nearest neighbour; the
+ * pair's V is uv[I][J] of hp_hubbard_params.  cell: rows a1, a2, a3 (bohr);
+ * hub_tau [n_hub][3] (bohr).  Writes up to max_pairs (I, J, distance) triples,
+ * I ascending, then J ascending; *n_pairs = total found (HP_ERR_ARG if it
+ * exceeds max_pairs, or for NULL pointers, n_hub < 1, nq < 1, dist_thr < 0).
+ * Host-only: needs no context and no GPU. */
+hp_status hp_neighbours(const double cell[9], int32_t n_hub, const double *hub_tau, const int32_t nq[3],
+                        double dist_thr, int32_t max_pairs, int32_t *pair_i, int32_t *pair_j, double *dist,
+                        int32_t *n_pairs);
+
 /* Free every resource of the context.  NULL is accepted. */
 void hp_destroy(hp_ctx *c);
 

@@ -14,7 +14,7 @@ perturbation theory"): Eqs. 7-9 (susceptibilities and U/V), Eq. 12
 conduction projectors, the alpha shift).  Each function cites the passage it
 follows.
 """
-from .hp_oracle import Oracle, ScfParams, hubbard_params, assemble_chi
+from .hp_oracle import Oracle, ScfParams, hubbard_params, assemble_chi, nearest_neighbours
 from . import pz81
 
-__all__ = ["Oracle", "ScfParams", "hubbard_params", "assemble_chi", "pz81"]
+__all__ = ["Oracle", "ScfParams", "hubbard_params", "assemble_chi", "nearest_neighbours", "pz81"]

@@ -465,6 +465,32 @@ def assemble_chi(chi_q: np.ndarray, qs: np.ndarray, qmesh) -> Tuple[np.ndarray, 
     return out.real.copy(), float(np.abs(out.imag).max())
 
 
+def nearest_neighbours(cell, hub_tau, qmesh, dist_thr: float = 6e-4):
+    """Nearest-neighbour pairs for the inter-site V of Eq. 9 in the q-supercell of Eq. 12
+    (site index l * n_hub + s as in assemble_chi): for each primitive site I, every other
+    supercell site at I's smallest minimum-image distance (within dist_thr, bohr).
+    Brute force over all sites and supercell images two shells out.  Returns (I, J, d)."""
+    A = np.asarray(cell, dtype=np.float64).reshape(3, 3)
+    tau = np.asarray(hub_tau, dtype=np.float64).reshape(-1, 3)
+    nh = tau.shape[0]
+    cells = supercell_cells(qmesh)
+    pos = (cells @ A)[:, None, :] + tau[None, :, :]
+    pos = pos.reshape(-1, 3)
+    a_sc = np.diag(np.asarray(qmesh, dtype=np.float64)) @ A
+    rng = np.arange(-2, 3)
+    shifts = np.array(np.meshgrid(rng, rng, rng, indexing="ij")).reshape(3, -1).T @ a_sc
+    out = []
+    for i in range(nh):
+        d = np.linalg.norm(pos[None, :, :] - pos[i][None, None, :] + shifts[:, None, :], axis=2).min(axis=0)
+        d[i] = np.inf
+        dmin = d.min()
+        if not np.isfinite(dmin):  # a lone site in a one-cell supercell has no neighbours
+            continue
+        for j in np.nonzero(d <= dmin + dist_thr)[0]:
+            out.append((i, int(j), float(d[j])))
+    return out
+
+
 def hubbard_params(chi0: np.ndarray, chi: np.ndarray) -> np.ndarray:
     """U on the diagonal, V off the diagonal: chi0^-1 - chi^-1 (Eqs. 8-9)."""
     return np.linalg.inv(chi0) - np.linalg.inv(chi)

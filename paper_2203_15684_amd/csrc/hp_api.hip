@@ -1072,6 +1072,62 @@ extern "C" void hp_destroy(hp_ctx *c) {
   delete c;
 }
 
+extern "C" hp_status hp_neighbours(const double cell[9], int32_t n_hub, const double *hub_tau, const int32_t nq[3],
+                                   double dist_thr, int32_t max_pairs, int32_t *pair_i, int32_t *pair_j, double *dist,
+                                   int32_t *n_pairs) {
+  if (!cell || !hub_tau || !nq || !n_pairs || (max_pairs > 0 && (!pair_i || !pair_j || !dist)))
+    return fail(HP_ERR_ARG, "NULL argument");
+  if (n_hub < 1 || nq[0] < 1 || nq[1] < 1 || nq[2] < 1 || !(dist_thr >= 0.0))
+    return fail(HP_ERR_ARG, "need n_hub >= 1, nq >= 1, dist_thr >= 0");
+  const int nc = nq[0] * nq[1] * nq[2], n = n_hub * nc;
+  // positions of every supercell site
+  std::vector<std::array<double, 3>> pos(n);
+  for (int a = 0, l = 0; a < nq[0]; ++a)
+    for (int b = 0; b < nq[1]; ++b)
+      for (int d = 0; d < nq[2]; ++d, ++l)
+        for (int s2 = 0; s2 < n_hub; ++s2)
+          for (int x = 0; x < 3; ++x)
+            pos[l * n_hub + s2][x] = hub_tau[3 * s2 + x] + a * cell[x] + b * cell[3 + x] + d * cell[6 + x];
+  // minimum image over supercell translations (two shells cover strongly sheared cells)
+  auto min_image = [&](int i, int j) {
+    double best = 1e300;
+    for (int u = -2; u <= 2; ++u)
+      for (int v = -2; v <= 2; ++v)
+        for (int w = -2; w <= 2; ++w) {
+          double r2 = 0.0;
+          for (int x = 0; x < 3; ++x) {
+            const double t = u * nq[0] * cell[x] + v * nq[1] * cell[3 + x] + w * nq[2] * cell[6 + x];
+            const double dx = pos[j][x] - pos[i][x] + t;
+            r2 += dx * dx;
+          }
+          best = std::min(best, r2);
+        }
+    return std::sqrt(best);
+  };
+  int found = 0;
+  for (int i = 0; i < n_hub; ++i) {
+    std::vector<double> dj(n, 0.0);
+    double dmin = 1e300;
+    for (int j = 0; j < n; ++j)
+      if (j != i) {
+        dj[j] = min_image(i, j);
+        dmin = std::min(dmin, dj[j]);
+      }
+    for (int j = 0; j < n; ++j)
+      if (j != i && dj[j] <= dmin + dist_thr) {
+        if (found < max_pairs) {
+          pair_i[found] = i;
+          pair_j[found] = j;
+          dist[found] = dj[j];
+        }
+        ++found;
+      }
+  }
+  *n_pairs = found;
+  if (found > max_pairs) return fail(HP_ERR_ARG, "%d pairs found, max_pairs = %d", found, max_pairs);
+  return HP_OK;
+}
+
 extern "C" hp_status hp_hubbard_params(int32_t n, const double *chi0, const double *chi, double *uv_out) {
   if (n < 1) return fail(HP_ERR_ARG, "n = %d", n);
   if (!chi0 || !chi || !uv_out) return fail(HP_ERR_ARG, "NULL argument");

@@ -106,6 +106,8 @@ _lib.hp_profile_start.argtypes = [C.c_void_p]
 _lib.hp_profile_start.restype = C.c_int32
 _lib.hp_profile_stop.argtypes = [C.c_void_p, C.POINTER(HpKernelTime), C.c_int32, C.POINTER(C.c_int32)]
 _lib.hp_profile_stop.restype = C.c_int32
+_lib.hp_neighbours.argtypes = [_dp, C.c_int32, _dp, _ip, C.c_double, C.c_int32, _ip, _ip, _dp, _ip]
+_lib.hp_neighbours.restype = C.c_int32
 _lib.hp_tuning_report.argtypes = [C.c_void_p, C.c_char_p, C.c_int32]
 _lib.hp_tuning_report.restype = C.c_int32
 _lib.hp_set_gemm_shape.argtypes = [C.c_void_p] + [C.c_int32] * 6
@@ -115,7 +117,8 @@ _lib.hp_set_plane_variant.restype = C.c_int32
 
 EXPORTED = ["hp_ground_state_load", "hp_sternheimer_scf", "hp_response_matrix", "hp_hubbard_params",
             "hp_destroy", "hp_last_error", "hp_apply_h", "hp_solve_first_order", "hp_profile_start",
-            "hp_profile_stop", "hp_tuning_report", "hp_set_gemm_shape", "hp_set_plane_variant"]
+            "hp_profile_stop", "hp_tuning_report", "hp_set_gemm_shape", "hp_set_plane_variant",
+            "hp_neighbours"]
 
 
 def hp_last_error() -> str:
@@ -328,3 +331,19 @@ def hp_set_gemm_shape(ctx: Context, prec: int, rows: int, batch: int, tile: int,
 
 def hp_set_plane_variant(ctx: Context, prec: int, variant: int):
     _check(_lib.hp_set_plane_variant(ctx.handle, prec, variant), allow_warn=False)
+
+
+def hp_neighbours(cell, hub_tau, nq, dist_thr: float = 6e-4):
+    """Nearest-neighbour (I, J, distance) triples of the q-supercell (see hp.h); V_IJ = uv[I, J]."""
+    cell = np.ascontiguousarray(cell, dtype=np.float64).reshape(9)
+    tau = np.ascontiguousarray(hub_tau, dtype=np.float64)
+    nqa = np.ascontiguousarray(nq, dtype=np.int32)
+    n_hub = tau.shape[0]
+    cap = 64 * n_hub
+    pi, pj = np.zeros(cap, np.int32), np.zeros(cap, np.int32)
+    d = np.zeros(cap)
+    n = C.c_int32(0)
+    _check(_lib.hp_neighbours(_ptr(cell), n_hub, _ptr(tau), _ptr(nqa, _ip), float(dist_thr), cap, _ptr(pi, _ip),
+                              _ptr(pj, _ip), _ptr(d), C.byref(n)), allow_warn=False)
+    k = n.value
+    return [(int(pi[i]), int(pj[i]), float(d[i])) for i in range(k)]

@@ -374,6 +374,43 @@ __device__ __forceinline__ void cfft(C *P, const C *tw, int nlines, const BaseF 
   }
 }
 
+// Stages I..E-1 of the transform (DIF order for DIF, reverse order otherwise).
+template <int N, bool DIF, int I, int E, class BaseF, class C>
+__device__ __forceinline__ void cfft_range(C *P, const C *tw, int nlines, const BaseF &base, int es) {
+  constexpr int NS = cnst(N);
+  if constexpr (I < E) {
+    cstage<N, DIF ? I : NS - 1 - I, DIF>(P, tw, nlines, base, es);
+    cfft_range<N, DIF, I + 1, E>(P, tw, nlines, base, es);
+  }
+}
+
+// The last forward (DIF) stage, a pointwise multiply by v and the first inverse stage in
+// one pass: both stages have span 1 and visit the same R elements per work item, so the
+// values stay in registers (the same operations as the three separate passes).
+template <int N, class BaseF, class C, class V>
+__device__ __forceinline__ void cstage_mul(C *__restrict__ P, int nlines, const BaseF &base, int es,
+                                           const V *__restrict__ v) {
+  constexpr int NS = cnst(N);
+  constexpr int R = crad(N, NS - 1), L = cspan(N, NS - 1), B = R * L, NB = N / R;
+  static_assert(L == 1, "the last stage has span 1");
+  const int total = nlines * NB;
+  for (int w = threadIdx.x; w < total; w += blockDim.x) {
+    const int line = w / NB;
+    const int b = w - line * NB;
+    const int o = base(line) + b * B * es;
+    C x[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) x[t] = P[o + t * es];
+    dft_small<R>(x, 1.0);
+#pragma unroll
+    for (int t = 0; t < R; ++t) x[t] = cscale(x[t], v[o + t * es]);
+    dft_small<R>(x, -1.0);
+#pragma unroll
+    for (int t = 0; t < R; ++t) P[o + t * es] = x[t];
+  }
+  __syncthreads();
+}
+
 // Per-block plane context: LDS tables and the transforms of one xy plane.
 // N1 = N2 = 0 selects the runtime-size path; C is double2 (FP64) or float2 (FP32).
 template <class C>
@@ -438,6 +475,29 @@ struct PlaneCtx {
       cfft<N1, DIF, 0>(P, twx, N2, BaseAffine{1}, N2);
     } else {
       fft_lines(P, twx, pl.ax, pl.n2, nullptr, 0, 1, 0, 1, pl.n2, DIF);
+    }
+  }
+  // x_lines<true>, multiply by v (same layout as the plane batch), x_lines<false>
+  template <class V>
+  __device__ __forceinline__ void x_round_trip_mul(const V *__restrict__ v) {
+    if constexpr (N1 > 0) {
+      constexpr int NS = cnst(N1);
+      if constexpr (PB > 1) {
+        const BaseAffineB<N2, N1 * N2> base{};
+        cfft_range<N1, true, 0, NS - 1>(P, twx, N2 * PB, base, N2);
+        cstage_mul<N1>(P, N2 * PB, base, N2, v);
+        cfft_range<N1, false, 1, NS>(P, twx, N2 * PB, base, N2);
+      } else {
+        const BaseAffine base{1};
+        cfft_range<N1, true, 0, NS - 1>(P, twx, N2, base, N2);
+        cstage_mul<N1>(P, N2, base, N2, v);
+        cfft_range<N1, false, 1, NS>(P, twx, N2, base, N2);
+      }
+    } else {
+      x_lines<true>();
+      for (int i = threadIdx.x; i < np(); i += blockDim.x) P[i] = cscale(P[i], v[i]);
+      __syncthreads();
+      x_lines<false>();
     }
   }
   __device__ __forceinline__ int pos(int x, int y, int g0x, int g0y) const {
@@ -591,11 +651,7 @@ __global__ void __launch_bounds__(kThreads) k_plane_vloc(Plane pl, Sticks sk, co
   for (int s = threadIdx.x; s < E.ns; s += blockDim.x) P[pc.pos(sx[s], sy[s], g0x, g0y)] = Sin[so + s];
   __syncthreads();
   pc.template y_lines<true>();
-  pc.template x_lines<true>();
-  const RealOf<C> *v = vp + (size_t)z * np;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = cscale(P[i], v[i]);
-  __syncthreads();
-  pc.template x_lines<false>();
+  pc.x_round_trip_mul(vp + (size_t)z * np);
   pc.template y_lines<false>();
   for (int s = threadIdx.x; s < E.ns; s += blockDim.x) Sout[so + s] = P[pc.pos(sx[s], sy[s], g0x, g0y)];
 }
@@ -628,11 +684,7 @@ __global__ void __launch_bounds__(NT) k_plane_vloc_b(Plane pl, Sticks sk, const 
   }
   __syncthreads();
   pc.template y_lines<true>();
-  pc.template x_lines<true>();
-  const RealOf<C> *v = vp + (size_t)z0 * np;
-  for (int i = threadIdx.x; i < PB * np; i += NT) P[i] = cscale(P[i], v[i]);
-  __syncthreads();
-  pc.template x_lines<false>();
+  pc.x_round_trip_mul(vp + (size_t)z0 * np);
   pc.template y_lines<false>();
   for (int w = threadIdx.x; w < PB * E.ns; w += NT) {
     const int p = w / E.ns, s = w - p * E.ns;

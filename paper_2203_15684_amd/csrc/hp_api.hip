@@ -894,14 +894,26 @@ hp_status cg_solve_mixed(hp_ctx *c, const KPair *kp, int nk, const double *eps_i
   int it_in = 0, nact = 0, ref = 0;
   bool trusted = false;
   int h_count[kCntStep] = {0};
+  // Above kFp32TrustTol the FP32 operator (FP32 GEMMs) is accurate to ~1e-7 of |A X| ~ |B|,
+  // far below the tolerance: the warm-start residual then comes from it, and the inner
+  // solve's own residual stands for the final one (no FP64 operator apply at all).
+  const bool trust = c->lowp_gemm == HP_GEMM_FP32 && tol >= kFp32TrustTol;
   for (ref = 0; ref <= max_refine; ++ref) {
     const int have_x = warm || ref > 0;
-    if (have_x) {
+    const bool ax32 = have_x && trust && ref == 0;
+    if (ax32) {
+      HPCHK(launch_to_f32((const double *)c->X, (float *)c->X32, 2L * nitems * c->ld, c->stream));
+      HPTRY(apply_op32(c, kp, nk, nb, c->X32, c->AP32, eps_items, rows, nullptr));
+      *happ32 += nitems;
+    } else if (have_x) {
       HPTRY(apply_op(c, kp, 1, nk, nb, c->X, c->AP, eps_items, rows));
       *happ64 += nitems;
     }
     HPCHK(launch_fill_int(c->count, kCntStep, 0, c->stream));
     HPCHK(timed(c, K_RESIDUAL64, [&] {
+      if (ax32)
+        return launch_residual64_ax32(kp, nb, nitems, c->B, c->AP32, c->R, c->B32, c->ld, c->d_npw, c->bn, c->rn,
+                                      c->act_out, tol, c->count + kCntResid, c->floor_in, c->stream);
       return launch_residual64(kp, nb, nitems, c->B, c->AP, have_x, c->R, c->B32, c->ld, c->d_npw, c->bn, c->rn,
                                c->act_out, tol, c->count + kCntResid, c->floor_in, c->stream);
     }));
@@ -934,7 +946,7 @@ hp_status cg_solve_mixed(hp_ctx *c, const KPair *kp, int nk, const double *eps_i
     }));
     // Above ~1e-6 the FP32 operator is exact enough that the inner solve's own residual
     // stands for the FP64 one; the next SCF iteration starts from an FP64 residual anyway.
-    if (c->lowp_gemm == HP_GEMM_FP32 && tol >= kFp32TrustTol && inner_active == 0) {
+    if (trust && inner_active == 0) {
       nact = 0;
       ++ref;
       trusted = true;

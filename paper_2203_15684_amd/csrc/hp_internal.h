@@ -180,6 +180,10 @@ hipError_t launch_residual64(const KPair *kp, int nb, int nitems, const double2 
                              double2 *R, float2 *R32, int ld, const int *npw_of, double *bn, double *rn, int *active,
                              double tol, int *count, double *floor_abs, hipStream_t st);
 // (floor_abs, nullable: per-item absolute residual below which an inner solve stops)
+// The same with A X from the FP32 operator (used where the FP32 operator is accurate enough).
+hipError_t launch_residual64_ax32(const KPair *kp, int nb, int nitems, const double2 *B, const float2 *AX, double2 *R,
+                                  float2 *R32, int ld, const int *npw_of, double *bn, double *rn, int *active,
+                                  double tol, int *count, double *floor_abs, hipStream_t st);
 // X (+)= (double) D for refined items.
 hipError_t launch_refine_update(int nb, int nitems, double2 *X, const float2 *D, int ld, const int *refined,
                                 int have_x, hipStream_t st);

@@ -714,8 +714,9 @@ __global__ void __launch_bounds__(256) k_cg_step(const KPair *kp, int nb, C2 *__
 }
 
 // Mixed precision: R = B - AX (FP64) with per-item norms and flags; r32 = (float) R.
+template <class AXT>
 __global__ void __launch_bounds__(256) k_residual64(const KPair *kp, int nb, const double2 *__restrict__ B,
-                                                    const double2 *__restrict__ AX, int have_x,
+                                                    const AXT *__restrict__ AX, int have_x,
                                                     double2 *__restrict__ R, float2 *__restrict__ R32, int ld,
                                                     const int *__restrict__ npw_of, double *bn, double *rn,
                                                     int *active, double tol, int *count, double *floor_abs) {
@@ -729,9 +730,9 @@ __global__ void __launch_bounds__(256) k_residual64(const KPair *kp, int nb, con
     const double2 b = B[o + g];
     double2 r = b;
     if (have_x) {
-      const double2 a = AX[o + g];
-      r.x -= a.x;
-      r.y -= a.y;
+      const AXT a = AX[o + g];
+      r.x -= (double)a.x;
+      r.y -= (double)a.y;
     }
     R[o + g] = r;
     R32[o + g] = make_float2((float)r.x, (float)r.y);
@@ -1061,8 +1062,15 @@ hipError_t launch_to_f32(const double *in, float *out, long n, hipStream_t st) {
 hipError_t launch_residual64(const KPair *kp, int nb, int nitems, const double2 *B, const double2 *AX, int have_x,
                              double2 *R, float2 *R32, int ld, const int *npw_of, double *bn, double *rn, int *active,
                              double tol, int *count, double *floor_abs, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual64, dim3(nitems), dim3(256), 0, st, kp, nb, B, AX, have_x, R, R32, ld, npw_of, bn, rn,
-                     active, tol, count, floor_abs);
+  hipLaunchKernelGGL(k_residual64<double2>, dim3(nitems), dim3(256), 0, st, kp, nb, B, AX, have_x, R, R32, ld, npw_of,
+                     bn, rn, active, tol, count, floor_abs);
+  return hipGetLastError();
+}
+hipError_t launch_residual64_ax32(const KPair *kp, int nb, int nitems, const double2 *B, const float2 *AX, double2 *R,
+                                  float2 *R32, int ld, const int *npw_of, double *bn, double *rn, int *active,
+                                  double tol, int *count, double *floor_abs, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual64<float2>, dim3(nitems), dim3(256), 0, st, kp, nb, B, AX, 1, R, R32, ld, npw_of, bn,
+                     rn, active, tol, count, floor_abs);
   return hipGetLastError();
 }
 

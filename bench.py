@@ -47,11 +47,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--relaxed-cg-tol", type=float, default=1e-7,
                     help="cg_tol of the relaxed FP64 / mixed forms")
-    ap.add_argument("--forms", default="mixed,fp64,fp64_relaxed,mixed_relaxed,mixed_bf16,mixed_bf16_pv32",
+    ap.add_argument("--forms", default="mixed,fp64,fp64_relaxed,mixed_relaxed,mixed_bf16,mixed_bf16_pv32,mixed_graphs",
                     help="comma-separated forms to time (must include fp64 and --precision)")
     ap.add_argument("--verbosity", type=int, default=0, help="1: one line per SCF iteration on stderr")
-    ap.add_argument("--graph-chunk", type=int, default=8,
-                    help="CG iterations per captured hipGraph launch (0: launch kernels one by one)")
+    ap.add_argument("--graph-chunk", type=int, default=0,
+                    help="CG iterations per captured hipGraph launch in the main forms (0: launch kernels one by "
+                         "one, timed with HIP events)")
     return ap.parse_args()
 
 
@@ -186,11 +187,15 @@ def main():
     # within 1e-6 of the FP64 form at the configured tolerance.
     # (the BF16 forms put the KB and P_v projections of the inner solves on BF16 MFMA, or
     # only the KB ones with P_v kept in FP32)
-    form_def = {"mixed": ("mixed", args.cg_tol, hp.HP_GEMM_FP32), "fp64": ("fp64", args.cg_tol, 0),
-                "fp64_relaxed": ("fp64", args.relaxed_cg_tol, 0),
-                "mixed_relaxed": ("mixed", args.relaxed_cg_tol, hp.HP_GEMM_FP32),
-                "mixed_bf16": ("mixed", args.cg_tol, hp.HP_GEMM_BF16),
-                "mixed_bf16_pv32": ("mixed", args.cg_tol, hp.HP_GEMM_BF16_PV32)}
+    # (mixed_graphs replays the CG iterations from captured hipGraphs; its per-kernel times
+    # come from device-clock stamps, every other form's from HIP events)
+    g = args.graph_chunk
+    form_def = {"mixed": ("mixed", args.cg_tol, hp.HP_GEMM_FP32, g), "fp64": ("fp64", args.cg_tol, 0, g),
+                "fp64_relaxed": ("fp64", args.relaxed_cg_tol, 0, g),
+                "mixed_relaxed": ("mixed", args.relaxed_cg_tol, hp.HP_GEMM_FP32, g),
+                "mixed_bf16": ("mixed", args.cg_tol, hp.HP_GEMM_BF16, g),
+                "mixed_bf16_pv32": ("mixed", args.cg_tol, hp.HP_GEMM_BF16_PV32, g),
+                "mixed_graphs": ("mixed", args.cg_tol, hp.HP_GEMM_FP32, 8)}
     wanted = args.forms.split(",")
     for f in wanted:
         if f not in form_def:
@@ -200,9 +205,9 @@ def main():
     form_def = {f: form_def[f] for f in wanted}
 
     def params(form):
-        prec, tol, lowp = form_def[form]
+        prec, tol, lowp, chunk = form_def[form]
         return hp.ScfParams(conv_thr_chi=args.conv_thr_chi, conv_thr_v=args.conv_thr_v, cg_tol=tol,
-                            niter_max=100, max_cg_iter=2000, inner_tol=args.inner_tol, graph_chunk=args.graph_chunk,
+                            niter_max=100, max_cg_iter=2000, inner_tol=args.inner_tol, graph_chunk=chunk,
                             precision=hp.HP_FP64 if prec == "fp64" else hp.HP_MIXED, lowp_gemm=lowp,
                             verbosity=args.verbosity)
 
@@ -245,7 +250,8 @@ def main():
         a64 = sum(r[3]["h_applies_fp64"] for r in res)
         a32 = sum(r[3]["h_applies_lowp"] for r in res)
         d = max(pr.items(), key=lambda kv: kv[1][1])[0]
-        summary[f] = {"precision": form_def[f][0], "cg_tol": form_def[f][1],
+        summary[f] = {"precision": form_def[f][0], "cg_tol": form_def[f][1], "graph_chunk": form_def[f][3],
+                      "kernel_timing": "device-clock stamps in graphs" if form_def[f][3] else "hip events",
                       "projection_gemms": {0: "fp32", 1: "bf16", 2: "bf16 (KB), fp32 (P_v)"}[form_def[f][2]]
                       if form_def[f][0] == "mixed" else "fp64",
                       "scf_wall_s_per_step": t / len(res), "hpsi_per_s": (a64 + a32) / t,

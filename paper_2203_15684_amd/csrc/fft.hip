@@ -331,14 +331,17 @@ struct BaseAffineB {
   }
 };
 
-template <int N, int S, bool DIF, class BaseF, class C>
+// One radix-R stage over nlines lines. LF: consecutive threads take consecutive lines
+// (for lines that are adjacent in LDS, strided elements), else consecutive butterflies
+// of one line (for contiguous lines): either way neighbouring lanes hit neighbouring banks.
+template <int N, int S, bool DIF, bool LF = false, class BaseF, class C>
 __device__ __forceinline__ void cstage(C *__restrict__ P, const C *__restrict__ tw, int nlines, const BaseF &base,
                                        int es) {
   constexpr int R = crad(N, S), L = cspan(N, S), B = R * L, NB = N / R, TSTEP = N / B;
   const int total = nlines * NB;
   for (int w = threadIdx.x; w < total; w += blockDim.x) {
-    const int line = w / NB;
-    const int b = w - line * NB;
+    const int line = LF ? w % nlines : w / NB;
+    const int b = LF ? w / nlines : w - line * NB;
     const int blk = b / L;
     const int j = b - blk * L;
     const int o = base(line) + (blk * B + j) * es;
@@ -364,30 +367,30 @@ __device__ __forceinline__ void cstage(C *__restrict__ P, const C *__restrict__ 
   __syncthreads();
 }
 
-template <int N, bool DIF, int I, class BaseF, class C>
+template <int N, bool DIF, int I, bool LF = false, class BaseF, class C>
 __device__ __forceinline__ void cfft(C *P, const C *tw, int nlines, const BaseF &base, int es) {
   constexpr int NS = cnst(N);
   static_assert(NS > 0, "FFT length must be a product of 2, 3 and 5");
   if constexpr (I < NS) {
-    cstage<N, DIF ? I : NS - 1 - I, DIF>(P, tw, nlines, base, es);
-    cfft<N, DIF, I + 1>(P, tw, nlines, base, es);
+    cstage<N, DIF ? I : NS - 1 - I, DIF, LF>(P, tw, nlines, base, es);
+    cfft<N, DIF, I + 1, LF>(P, tw, nlines, base, es);
   }
 }
 
 // Stages I..E-1 of the transform (DIF order for DIF, reverse order otherwise).
-template <int N, bool DIF, int I, int E, class BaseF, class C>
+template <int N, bool DIF, int I, int E, bool LF = false, class BaseF, class C>
 __device__ __forceinline__ void cfft_range(C *P, const C *tw, int nlines, const BaseF &base, int es) {
   constexpr int NS = cnst(N);
   if constexpr (I < E) {
-    cstage<N, DIF ? I : NS - 1 - I, DIF>(P, tw, nlines, base, es);
-    cfft_range<N, DIF, I + 1, E>(P, tw, nlines, base, es);
+    cstage<N, DIF ? I : NS - 1 - I, DIF, LF>(P, tw, nlines, base, es);
+    cfft_range<N, DIF, I + 1, E, LF>(P, tw, nlines, base, es);
   }
 }
 
 // The last forward (DIF) stage, a pointwise multiply by v and the first inverse stage in
 // one pass: both stages have span 1 and visit the same R elements per work item, so the
 // values stay in registers (the same operations as the three separate passes).
-template <int N, class BaseF, class C, class V>
+template <int N, bool LF, class BaseF, class C, class V>
 __device__ __forceinline__ void cstage_mul(C *__restrict__ P, int nlines, const BaseF &base, int es,
                                            const V *__restrict__ v) {
   constexpr int NS = cnst(N);
@@ -395,8 +398,8 @@ __device__ __forceinline__ void cstage_mul(C *__restrict__ P, int nlines, const 
   static_assert(L == 1, "the last stage has span 1");
   const int total = nlines * NB;
   for (int w = threadIdx.x; w < total; w += blockDim.x) {
-    const int line = w / NB;
-    const int b = w - line * NB;
+    const int line = LF ? w % nlines : w / NB;
+    const int b = LF ? w / nlines : w - line * NB;
     const int o = base(line) + b * B * es;
     C x[R];
 #pragma unroll
@@ -470,9 +473,9 @@ struct PlaneCtx {
   template <bool DIF>
   __device__ __forceinline__ void x_lines() {  // every y, stride N2, length N1
     if constexpr (PB > 1) {
-      cfft<N1, DIF, 0>(P, twx, N2 * PB, BaseAffineB<N2, N1 * N2>{}, N2);
+      cfft<N1, DIF, 0, true>(P, twx, N2 * PB, BaseAffineB<N2, N1 * N2>{}, N2);
     } else if constexpr (N1 > 0) {
-      cfft<N1, DIF, 0>(P, twx, N2, BaseAffine{1}, N2);
+      cfft<N1, DIF, 0, true>(P, twx, N2, BaseAffine{1}, N2);
     } else {
       fft_lines(P, twx, pl.ax, pl.n2, nullptr, 0, 1, 0, 1, pl.n2, DIF);
     }
@@ -484,14 +487,14 @@ struct PlaneCtx {
       constexpr int NS = cnst(N1);
       if constexpr (PB > 1) {
         const BaseAffineB<N2, N1 * N2> base{};
-        cfft_range<N1, true, 0, NS - 1>(P, twx, N2 * PB, base, N2);
-        cstage_mul<N1>(P, N2 * PB, base, N2, v);
-        cfft_range<N1, false, 1, NS>(P, twx, N2 * PB, base, N2);
+        cfft_range<N1, true, 0, NS - 1, true>(P, twx, N2 * PB, base, N2);
+        cstage_mul<N1, true>(P, N2 * PB, base, N2, v);
+        cfft_range<N1, false, 1, NS, true>(P, twx, N2 * PB, base, N2);
       } else {
         const BaseAffine base{1};
-        cfft_range<N1, true, 0, NS - 1>(P, twx, N2, base, N2);
-        cstage_mul<N1>(P, N2, base, N2, v);
-        cfft_range<N1, false, 1, NS>(P, twx, N2, base, N2);
+        cfft_range<N1, true, 0, NS - 1, true>(P, twx, N2, base, N2);
+        cstage_mul<N1, true>(P, N2, base, N2, v);
+        cfft_range<N1, false, 1, NS, true>(P, twx, N2, base, N2);
       }
     } else {
       x_lines<true>();
@@ -750,11 +753,14 @@ template <int N1, int N2>
 __global__ void __launch_bounds__(kThreads) k_plane_drho(Plane pl, Sticks sk, const KPair *kp, int nb,
                                                          const double2 *__restrict__ Sdu, int ns_pad,
                                                          const double2 *__restrict__ psi,
-                                                         double2 *__restrict__ part) {
+                                                         double2 *__restrict__ part, int nsplit) {
   extern __shared__ __align__(16) unsigned char lds[];
   PlaneCtx<N1, N2> pc(pl, lds);
   const int z = blockIdx.x;
   const int k = blockIdx.y;
+  const int split = blockIdx.z;  // bands [v0, v1) of this workgroup
+  const int per = (nb + nsplit - 1) / nsplit;
+  const int v0 = split * per, v1 = min(nb, v0 + per);
   int e, g0x, g0y, g0z;
   basis_of(kp, k, 1, e, g0x, g0y, g0z);
   const EntryDev E = sk.ent[e];
@@ -766,7 +772,7 @@ __global__ void __launch_bounds__(kThreads) k_plane_drho(Plane pl, Sticks sk, co
   constexpr int PER = N1 > 0 ? (N1 * N2 + kThreads - 1) / kThreads : kMaxPerThread;
   double2 acc[PER];
   for (int j = 0; j < PER; ++j) acc[j] = make_double2(0.0, 0.0);
-  for (int v = 0; v < nb; ++v) {
+  for (int v = v0; v < v1; ++v) {
     const int item = k * nb + v;
     plane_zero(P, np);
     __syncthreads();
@@ -783,7 +789,7 @@ __global__ void __launch_bounds__(kThreads) k_plane_drho(Plane pl, Sticks sk, co
     }
     __syncthreads();
   }
-  double2 *out = part + ((size_t)k * pl.n3 + z) * np;
+  double2 *out = part + (((size_t)k * nsplit + split) * pl.n3 + z) * np;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int i = threadIdx.x + j * blockDim.x;
@@ -791,14 +797,19 @@ __global__ void __launch_bounds__(kThreads) k_plane_drho(Plane pl, Sticks sk, co
   }
 }
 
-__global__ void k_drho_reduce(const KPair *kp, int nk, const double2 *__restrict__ part, long nr, double inv_omega,
-                              double2 *__restrict__ drho) {
+__global__ void k_drho_reduce(const KPair *kp, int nk, int nsplit, const double2 *__restrict__ part, long nr,
+                              double inv_omega, double2 *__restrict__ drho) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i >= nr) return;
   double2 acc = make_double2(0.0, 0.0);
   for (int k = 0; k < nk; ++k) {
     const double w = 4.0 * kp[k].weight * inv_omega;
-    const double2 p = part[(size_t)k * nr + i];
+    double2 p = make_double2(0.0, 0.0);
+    for (int s = 0; s < nsplit; ++s) {
+      const double2 t = part[((size_t)k * nsplit + s) * nr + i];
+      p.x += t.x;
+      p.y += t.y;
+    }
     acc.x += w * p.x;
     acc.y += w * p.y;
   }
@@ -1095,15 +1106,16 @@ hipError_t launch_plane_mul_fwd(const Plane &pl, const Sticks &sk, const KPair *
 }
 
 hipError_t launch_plane_drho(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nk, const double2 *Sdu,
-                             int ns_pad, const double2 *psi, double2 *part, hipStream_t st) {
-  if (pl.n1 * pl.n2 > kMaxPerThread * kThreads) return hipErrorInvalidValue;
-  HP_PLANE_DISPATCH(k_plane_drho, dim3(pl.n3, nk), plane_lds_t(pl), st, pl, sk, kp, nb, Sdu, ns_pad, psi, part);
+                             int ns_pad, const double2 *psi, double2 *part, int nsplit, hipStream_t st) {
+  if (pl.n1 * pl.n2 > kMaxPerThread * kThreads || nsplit < 1) return hipErrorInvalidValue;
+  HP_PLANE_DISPATCH(k_plane_drho, dim3(pl.n3, nk, nsplit), plane_lds_t(pl), st, pl, sk, kp, nb, Sdu, ns_pad, psi,
+                    part, nsplit);
   return hipGetLastError();
 }
 
-hipError_t launch_drho_reduce(const KPair *kp, int nk, const double2 *part, long nr, double inv_omega, double2 *drho,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(k_drho_reduce, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, kp, nk, part, nr,
+hipError_t launch_drho_reduce(const KPair *kp, int nk, int nsplit, const double2 *part, long nr, double inv_omega,
+                              double2 *drho, hipStream_t st) {
+  hipLaunchKernelGGL(k_drho_reduce, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, kp, nk, nsplit, part, nr,
                      inv_omega, drho);
   return hipGetLastError();
 }

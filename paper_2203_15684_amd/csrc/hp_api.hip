@@ -143,6 +143,7 @@ struct hp_ctx {
   Plane pl32{};
   Axis az32{};
   int nsplit_cap = 16;
+  int drho_split = 1;
   long t_stride = 0, phi_stride = 0;
   hipEvent_t ev[16];
   // per-kernel timing (hp_profile_start / hp_profile_stop)
@@ -1493,7 +1494,10 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
     if (khz <= 0) return fail(HP_ERR_HIP, "device reports no wall-clock rate");
     c->clock_khz = (double)khz;
   }
-  HPTRY(c->alloc(&c->part, (size_t)c->n_mesh * c->nr));
+  // response density: the band loop of each (z plane, k) is split over drho_split workgroups
+  // so that a launch has a few thousand of them
+  c->drho_split = std::max(1, std::min(std::min(8, c->n_occ), (4096 + c->n3 * c->n_mesh - 1) / (c->n3 * c->n_mesh)));
+  HPTRY(c->alloc(&c->part, (size_t)c->n_mesh * c->drho_split * c->nr));
   HPTRY(c->alloc(&c->drho, c->nr));
   HPTRY(c->alloc(&c->dvin, c->nr));
   HPTRY(c->alloc(&c->dvout, c->nr));
@@ -1577,10 +1581,11 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
                               c->max_chunk_pw, c->ns_max, nullptr, c->stream);
     }));
     HPCHK(timed(c, K_PLANE_DRHO, [&] {
-      return launch_plane_drho(c->pl, c->sk, c->d_kp, nb, nk, c->S1, c->ns_pad, c->d_psi, c->part, c->stream);
+      return launch_plane_drho(c->pl, c->sk, c->d_kp, nb, nk, c->S1, c->ns_pad, c->d_psi, c->part, c->drho_split,
+                               c->stream);
     }));
     HPCHK(timed(c, K_DRHO_REDUCE, [&] {
-      return launch_drho_reduce(c->d_kp, nk, c->part, nr, 1.0 / c->omega, c->drho, c->stream);
+      return launch_drho_reduce(c->d_kp, nk, c->drho_split, c->part, nr, 1.0 / c->omega, c->drho, c->stream);
     }));
     HPCHK(hipEventRecord(c->ev[3], c->stream));
     HPCHK(timed(c, K_HXC, [&] {

@@ -102,12 +102,13 @@ hipError_t launch_plane_to_real(const Plane &pl, const Sticks &sk, const KPair *
 // psi[item] (permuted) * dv (permuted) -> sticks of the k+q basis.
 hipError_t launch_plane_mul_fwd(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nitems,
                                 const double2 *psi, const double2 *dv, double2 *Sout, int ns_pad, hipStream_t st);
-// part[k][z][plane] = sum_v conj(psi[k*nb+v]) * (sticks of du -> r), k+q basis.
+// part[k][s][z][plane] = sum over the s-th of nsplit band ranges of conj(psi[k*nb+v]) *
+// (sticks of du -> r), k+q basis.
 hipError_t launch_plane_drho(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nk, const double2 *Sdu,
-                             int ns_pad, const double2 *psi, double2 *part, hipStream_t st);
-// drho = sum_k (4 w_k / Omega) part[k] in fixed order.
-hipError_t launch_drho_reduce(const KPair *kp, int nk, const double2 *part, long nr, double inv_omega, double2 *drho,
-                              hipStream_t st);
+                             int ns_pad, const double2 *psi, double2 *part, int nsplit, hipStream_t st);
+// drho = sum_k (4 w_k / Omega) sum_s part[k][s] in fixed order.
+hipError_t launch_drho_reduce(const KPair *kp, int nk, int nsplit, const double2 *part, long nr, double inv_omega,
+                              double2 *drho, hipStream_t st);
 // dvout = IFFT(4 pi FFT(drho) / |q+G|^2) + fxc * drho, permuted layout.
 hipError_t launch_hxc(const Plane &pl, const Axis &az, const double *bvec, const double *q, const double2 *drho,
                       const double *fxc, double2 *tmp, double2 *dvout, hipStream_t st);

@@ -86,7 +86,7 @@ def traffic(a):
         return max(vals)
 
     copy_bytes = float(a.copy_bytes)
-    fs = 2 * copy_bytes / 1024 / max_of(a.copy_fetch, "FETCH_SIZE", "copy")   # a copy reads its size once
+    fs = copy_bytes / 1024 / max_of(a.copy_fetch, "FETCH_SIZE", "copy")   # a copy reads its size once
     ws = copy_bytes / 1024 / max_of(a.copy_write, "WRITE_SIZE", "copy")       # ... and writes it once
     fetch = max_of(a.fetch, "FETCH_SIZE", a.match)
     write = max_of(a.write, "WRITE_SIZE", a.match)

@@ -246,8 +246,10 @@ hp_status hp_profile_stop(hp_ctx *c, hp_kernel_time *out, int32_t max, int32_t *
  * JSON text (NUL-terminated, into buf of len bytes) of the launch shapes the
  * autotuner chose in this context: per GEMM shape (precision, rows, batch) the
  * projection tile, K split and expansion band tile with the measured and the
- * default times (ms), and per precision the chosen plane-batch variant of the
- * local-potential FFT with every variant's time.  HP_ERR_ARG if buf is too small. */
+ * default times (ms), per precision the chosen plane-batch variant of the
+ * local-potential FFT with every variant's time, and per precision the chosen
+ * z-transform variants (a workgroup per 32 sticks, or a thread per stick) with
+ * their times.  HP_ERR_ARG if buf is too small. */
 hp_status hp_tuning_report(hp_ctx *c, char *buf, int32_t len);
 
 /* Pin launch shapes instead of timing them (used when hp_scf_params.autotune = 1;
@@ -264,6 +266,9 @@ hp_status hp_tuning_report(hp_ctx *c, char *buf, int32_t len);
 hp_status hp_set_gemm_shape(hp_ctx *c, int32_t prec, int32_t rows, int32_t batch, int32_t tile, int32_t nsplit,
                             int32_t expand_bands);
 hp_status hp_set_plane_variant(hp_ctx *c, int32_t prec, int32_t variant);
+/* z-transform variants (inverse: sphere -> sticks, forward: sticks -> sphere):
+ * 0 = a workgroup per 32 sticks, 1 = a thread per stick (N3 = 24 or 40 only). */
+hp_status hp_set_stick_variant(hp_ctx *c, int32_t prec, int32_t inverse_variant, int32_t forward_variant);
 
 #ifdef __cplusplus
 }

@@ -630,6 +630,104 @@ __global__ void __launch_bounds__(kThreads) k_stick_fwd(Sticks sk, const KPair *
   }
 }
 
+// The z transforms with one thread per stick: the stick's N3 values stay in registers
+// while its plane waves are visited once.  The sums run over the same terms in the same
+// order as in k_stick_inv / k_stick_fwd, so the results are the same.
+template <int N3, class C>
+__global__ void __launch_bounds__(kThreads) k_stick_inv_s(Sticks sk, const KPair *kp, int use_kq, int nb,
+                                                          const C *__restrict__ X, int ld, C *__restrict__ S,
+                                                          int ns_pad, const C *__restrict__ tw3, const int *active) {
+  __shared__ C tw[N3];
+  const int item = blockIdx.y;
+  if (active && !active[item]) return;
+  const int k = item / nb;
+  int e, g0x, g0y, g0z;
+  basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
+  const EntryDev E = sk.ent[e];
+  if ((int)(blockIdx.x * blockDim.x) >= E.ns) return;
+  for (int i = threadIdx.x; i < N3; i += blockDim.x) tw[i] = tw3[i];
+  __syncthreads();
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= E.ns) return;
+  const int a = sk.sstart[E.st_off + s], len = sk.slen[E.st_off + s];
+  const C *x = X + (size_t)item * ld + a;
+  const int *izp = sk.iz + E.pw_off + a;
+  C acc[N3];
+#pragma unroll
+  for (int z = 0; z < N3; ++z) acc[z] = czero<C>();
+  for (int t = 0; t < len; ++t) {
+    const C c = x[t];
+    const int zi = wrap(izp[t] - g0z, N3);
+    int ix = 0;
+#pragma unroll
+    for (int z = 0; z < N3; ++z) {
+      acc[z] = cadd(acc[z], cmul(c, tw[ix]));
+      ix += zi;
+      if (ix >= N3) ix -= N3;
+    }
+  }
+  C *out = S + (size_t)item * N3 * ns_pad + s;
+#pragma unroll
+  for (int z = 0; z < N3; ++z) out[(size_t)z * ns_pad] = acc[z];
+}
+
+template <int N3, class C>
+__global__ void __launch_bounds__(kThreads) k_stick_fwd_s(Sticks sk, const KPair *kp, int use_kq, int nb,
+                                                          const C *__restrict__ S, int ns_pad,
+                                                          const C *__restrict__ tw3, double scale,
+                                                          C *__restrict__ Y, int ld, int mode,
+                                                          const double *__restrict__ kin,
+                                                          const double *__restrict__ eps,
+                                                          const C *__restrict__ X, int eps_stride,
+                                                          const int *active) {
+  using R = RealOf<C>;
+  __shared__ C tw[N3];
+  const int item = blockIdx.y;
+  if (active && !active[item]) return;
+  const int k = item / nb;
+  const int v = item - k * nb;
+  int e, g0x, g0y, g0z;
+  basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
+  const EntryDev E = sk.ent[e];
+  if ((int)(blockIdx.x * blockDim.x) >= E.ns) return;
+  for (int i = threadIdx.x; i < N3; i += blockDim.x) tw[i] = tw3[i];
+  __syncthreads();
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= E.ns) return;
+  const int a = sk.sstart[E.st_off + s], len = sk.slen[E.st_off + s];
+  C sv[N3];
+  if (S) {
+    const C *in = S + (size_t)item * N3 * ns_pad + s;
+#pragma unroll
+    for (int z = 0; z < N3; ++z) sv[z] = in[(size_t)z * ns_pad];
+  }
+  C *y = Y + (size_t)item * ld;
+  const C *x = X ? X + (size_t)item * ld : nullptr;
+  const double ev = eps ? eps[(size_t)k * eps_stride + v] : 0.0;
+  for (int t = 0; t < len; ++t) {
+    const int p = a + t;
+    C acc = czero<C>();
+    if (S) {
+      const int zz = wrap(sk.iz[E.pw_off + p] - g0z, N3);
+      int ix = 0;
+#pragma unroll
+      for (int z = 0; z < N3; ++z) {
+        acc = cadd(acc, cmulc(sv[z], tw[ix]));
+        ix += zz;
+        if (ix >= N3) ix -= N3;
+      }
+      acc = cscale(acc, scale);
+    }
+    if (mode == 0) {
+      const C xv = x[p];
+      const R d = (R)(kin[E.pw_off + p] - ev);
+      acc.x += d * xv.x;
+      acc.y += d * xv.y;
+    }
+    y[p] = acc;
+  }
+}
+
 template <int N1, int N2, class C>
 __global__ void __launch_bounds__(kThreads) k_plane_vloc(Plane pl, Sticks sk, const KPair *kp, int use_kq, int nb,
                                                          const C *__restrict__ Sin, C *__restrict__ Sout,
@@ -982,8 +1080,18 @@ __global__ void k_fxc(const double *__restrict__ rho, double *__restrict__ fxc, 
 
 template <class C>
 hipError_t stick_inv_t(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const C *X, int ld, C *S,
-                       int ns_pad, int n3, const C *tw3, int max_chunk_pw, int ns_max, const int *active,
+                       int ns_pad, int n3, const C *tw3, int max_chunk_pw, int ns_max, const int *active, int variant,
                        hipStream_t st) {
+  if (variant == 1 && (n3 == 24 || n3 == 40)) {
+    dim3 g((ns_max + kThreads - 1) / kThreads, nitems);
+    if (n3 == 24)
+      hipLaunchKernelGGL((k_stick_inv_s<24, C>), g, dim3(kThreads), 0, st, sk, kp, use_kq, nb, X, ld, S, ns_pad, tw3,
+                         active);
+    else
+      hipLaunchKernelGGL((k_stick_inv_s<40, C>), g, dim3(kThreads), 0, st, sk, kp, use_kq, nb, X, ld, S, ns_pad, tw3,
+                         active);
+    return hipGetLastError();
+  }
   dim3 grid((ns_max + kStickChunk - 1) / kStickChunk, nitems);
   size_t lds = (size_t)n3 * sizeof(C) + (size_t)max_chunk_pw * (sizeof(C) + sizeof(int));
   HP_STICK_DISPATCH(k_stick_inv, C, grid, lds, st, n3, sk, kp, use_kq, nb, X, ld, S, ns_pad, n3, tw3, active);
@@ -994,7 +1102,17 @@ template <class C>
 hipError_t stick_fwd_t(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const C *S, int ns_pad,
                        int n3, const C *tw3, double scale, C *Y, int ld, int mode, const double *kin,
                        const double *eps, const C *X, int eps_stride, int max_chunk_pw, int ns_max,
-                       const int *active, hipStream_t st) {
+                       const int *active, int variant, hipStream_t st) {
+  if (variant == 1 && (n3 == 24 || n3 == 40)) {
+    dim3 g((ns_max + kThreads - 1) / kThreads, nitems);
+    if (n3 == 24)
+      hipLaunchKernelGGL((k_stick_fwd_s<24, C>), g, dim3(kThreads), 0, st, sk, kp, use_kq, nb, S, ns_pad, tw3, scale,
+                         Y, ld, mode, kin, eps, X, eps_stride, active);
+    else
+      hipLaunchKernelGGL((k_stick_fwd_s<40, C>), g, dim3(kThreads), 0, st, sk, kp, use_kq, nb, S, ns_pad, tw3, scale,
+                         Y, ld, mode, kin, eps, X, eps_stride, active);
+    return hipGetLastError();
+  }
   dim3 grid((ns_max + kStickChunk - 1) / kStickChunk, nitems);
   size_t lds = (size_t)n3 * sizeof(C) + (size_t)n3 * kStickChunk * sizeof(C) + (size_t)max_chunk_pw * sizeof(int);
   HP_STICK_DISPATCH(k_stick_fwd, C, grid, lds, st, n3, sk, kp, use_kq, nb, S, ns_pad, n3, tw3, scale, Y, ld, mode,
@@ -1004,28 +1122,30 @@ hipError_t stick_fwd_t(const Sticks &sk, const KPair *kp, int use_kq, int nb, in
 
 hipError_t launch_stick_inv(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const double2 *X,
                             int ld, double2 *S, int ns_pad, int n3, const double2 *tw3, int max_chunk_pw, int ns_max,
-                            const int *active, hipStream_t st) {
-  return stick_inv_t(sk, kp, use_kq, nb, nitems, X, ld, S, ns_pad, n3, tw3, max_chunk_pw, ns_max, active, st);
+                            const int *active, int variant, hipStream_t st) {
+  return stick_inv_t(sk, kp, use_kq, nb, nitems, X, ld, S, ns_pad, n3, tw3, max_chunk_pw, ns_max, active, variant,
+                     st);
 }
 hipError_t launch_stick_inv32(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const float2 *X,
                               int ld, float2 *S, int ns_pad, int n3, const float2 *tw3, int max_chunk_pw, int ns_max,
-                              const int *active, hipStream_t st) {
-  return stick_inv_t(sk, kp, use_kq, nb, nitems, X, ld, S, ns_pad, n3, tw3, max_chunk_pw, ns_max, active, st);
+                              const int *active, int variant, hipStream_t st) {
+  return stick_inv_t(sk, kp, use_kq, nb, nitems, X, ld, S, ns_pad, n3, tw3, max_chunk_pw, ns_max, active, variant,
+                     st);
 }
 
 hipError_t launch_stick_fwd(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const double2 *S,
                             int ns_pad, int n3, const double2 *tw3, double scale, double2 *Y, int ld, int mode,
                             const double *kin, const double *eps, const double2 *X, int eps_stride,
-                            int max_chunk_pw, int ns_max, const int *active, hipStream_t st) {
+                            int max_chunk_pw, int ns_max, const int *active, int variant, hipStream_t st) {
   return stick_fwd_t(sk, kp, use_kq, nb, nitems, S, ns_pad, n3, tw3, scale, Y, ld, mode, kin, eps, X, eps_stride,
-                     max_chunk_pw, ns_max, active, st);
+                     max_chunk_pw, ns_max, active, variant, st);
 }
 hipError_t launch_stick_fwd32(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const float2 *S,
                               int ns_pad, int n3, const float2 *tw3, double scale, float2 *Y, int ld, int mode,
                               const double *kin, const double *eps, const float2 *X, int eps_stride,
-                              int max_chunk_pw, int ns_max, const int *active, hipStream_t st) {
+                              int max_chunk_pw, int ns_max, const int *active, int variant, hipStream_t st) {
   return stick_fwd_t(sk, kp, use_kq, nb, nitems, S, ns_pad, n3, tw3, scale, Y, ld, mode, kin, eps, X, eps_stride,
-                     max_chunk_pw, ns_max, active, st);
+                     max_chunk_pw, ns_max, active, variant, st);
 }
 
 constexpr int kLdsBytes = 160 * 1024;  // LDS per CU on gfx950

@@ -187,6 +187,9 @@ struct hp_ctx {
   };
   std::vector<GemmChoice> gemm_tuned;
   int plane_var[2] = {0, 0};  // [0] FP64, [1] FP32
+  int stick_var[2][2] = {{0, 0}, {0, 0}};  // [precision][inverse, forward] z-transform variant
+  float stick_ms[2][2][2] = {};
+  bool stick_tuned[2] = {false, false};
   int plane_nvar[2] = {0, 0};
   float plane_ms[2][4] = {};
   bool plane_tuned[2] = {false, false};
@@ -393,6 +396,7 @@ GemmShape gemm_shape(const hp_ctx *c, int prec, int M, int nk) {
   return {0, choose_nsplit(M, c->n_occ, nk, c->npw_max), 1};
 }
 int plane_variant(const hp_ctx *c, int prec) { return c->use_tuned ? c->plane_var[prec == 32 ? 1 : 0] : 0; }
+int stick_variant(const hp_ctx *c, int prec, int fwd) { return c->use_tuned ? c->stick_var[prec == 32][fwd] : 0; }
 
 // C[k][m][v] = scale_m * sum_G conj(T[m0+m][G]) X[k,v][G]
 hp_status proj(hp_ctx *c, const KPair *kp, int use_kq, int nk, const double2 *T, long tstride, int m0, int M,
@@ -417,7 +421,7 @@ hp_status apply_op(hp_ctx *c, const KPair *kp, int use_kq, int nk, int nb, const
   const int nitems = nk * nb;
   HPCHK(timed(c, K_STICK_INV, [&] {
     return launch_stick_inv(c->sk, kp, use_kq, nb, nitems, Xin, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
-                            c->max_chunk_pw, c->ns_max, active, c->stream);
+                            c->max_chunk_pw, c->ns_max, active, stick_variant(c, 64, 0), c->stream);
   }));
   HPCHK(timed(c, K_PLANE_VLOC, [&] {
     return launch_plane_vloc(c->pl, c->sk, kp, use_kq, nb, nitems, c->S1, c->S2, c->ns_pad, c->d_vp, active,
@@ -425,7 +429,8 @@ hp_status apply_op(hp_ctx *c, const KPair *kp, int use_kq, int nk, int nb, const
   }));
   HPCHK(timed(c, K_STICK_FWD, [&] {
     return launch_stick_fwd(c->sk, kp, use_kq, nb, nitems, c->S2, c->ns_pad, c->n3, c->az.tw, 1.0 / (double)c->nr, Y,
-                            c->ld, 0, c->d_kin, eps, Xin, nb, c->max_chunk_pw, c->ns_max, active, c->stream);
+                            c->ld, 0, c->d_kin, eps, Xin, nb, c->max_chunk_pw, c->ns_max, active,
+                            stick_variant(c, 64, 1), c->stream);
   }));
   HPTRY(proj(c, kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, Xin, nb, c->d_rowscale, 1.0, c->C, active));
   HPCHK(timed(c, K_ZEXPAND, [&] {
@@ -444,7 +449,8 @@ hp_status build_rhs(hp_ctx *c, const KPair *kp, int nk, int site, const double2 
     }));
     HPCHK(timed(c, K_RHS, [&] {
       return launch_stick_fwd(c->sk, kp, 1, nb, nitems, c->S1, c->ns_pad, c->n3, c->az.tw, -1.0 / (double)c->nr, c->B,
-                              c->ld, 2, nullptr, nullptr, nullptr, nb, c->max_chunk_pw, c->ns_max, nullptr, c->stream);
+                              c->ld, 2, nullptr, nullptr, nullptr, nb, c->max_chunk_pw, c->ns_max, nullptr,
+                              stick_variant(c, 64, 1), c->stream);
     }));
   } else {
     HPCHK(hipMemsetAsync(c->B, 0, sizeof(double2) * (size_t)nitems * c->ld, c->stream));
@@ -691,7 +697,7 @@ hp_status apply_op32(hp_ctx *c, const KPair *kp, int nk, int nb, const float2 *X
   float2 *Cpart = reinterpret_cast<float2 *>(c->Cpart), *C = reinterpret_cast<float2 *>(c->C);
   HPCHK(timed(c, K_STICK_INV32, [&] {
     return launch_stick_inv32(c->sk, kp, 1, nb, nitems, Xin, c->ld, S1, c->ns_pad, c->n3, c->az32.tw32,
-                              c->max_chunk_pw, c->ns_max, active, c->stream);
+                              c->max_chunk_pw, c->ns_max, active, stick_variant(c, 32, 0), c->stream);
   }));
   HPCHK(timed(c, K_PLANE_VLOC32, [&] {
     return launch_plane_vloc32(c->pl32, c->sk, kp, 1, nb, nitems, S1, S2, c->ns_pad, c->vp32, active,
@@ -699,7 +705,8 @@ hp_status apply_op32(hp_ctx *c, const KPair *kp, int nk, int nb, const float2 *X
   }));
   HPCHK(timed(c, K_STICK_FWD32, [&] {
     return launch_stick_fwd32(c->sk, kp, 1, nb, nitems, S2, c->ns_pad, c->n3, c->az32.tw32, 1.0 / (double)c->nr, Y,
-                              c->ld, 0, c->d_kin, eps, Xin, nb, c->max_chunk_pw, c->ns_max, active, c->stream);
+                              c->ld, 0, c->d_kin, eps, Xin, nb, c->max_chunk_pw, c->ns_max, active,
+                              stick_variant(c, 32, 1), c->stream);
   }));
   // rows [0, m16) of the stacked table in BF16, rows [m16, rows) in FP32
   const int m16 = c->lowp_gemm == HP_GEMM_BF16 ? rows : c->lowp_gemm == HP_GEMM_BF16_PV32 ? c->n_beta : 0;
@@ -864,12 +871,53 @@ hp_status tune_plane(hp_ctx *c, int prec, int nk) {
   return HP_OK;
 }
 
+// z transforms: a workgroup per 32 sticks, or a thread per stick (same sums, same order).
+hp_status tune_stick(hp_ctx *c, int prec, int nk) {
+  const int slot = prec == 32 ? 1 : 0;
+  if (c->stick_tuned[slot]) return HP_OK;
+  const int nb = c->n_occ, nitems = nk * nb;
+  const int nv = (c->n3 == 24 || c->n3 == 40) ? 2 : 1;
+  for (int fwd = 0; fwd < 2; ++fwd) {
+    float best = 1e30f;
+    for (int v = 0; v < nv; ++v) {
+      float ms = 0.f;
+      if (prec == 64) {
+        HPTRY(time_launch(c, [&] {
+          if (!fwd)
+            return launch_stick_inv(c->sk, c->d_kp, 1, nb, nitems, c->X, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
+                                    c->max_chunk_pw, c->ns_max, nullptr, v, c->stream);
+          return launch_stick_fwd(c->sk, c->d_kp, 1, nb, nitems, c->S2, c->ns_pad, c->n3, c->az.tw, 1.0, c->AP, c->ld,
+                                  2, nullptr, nullptr, nullptr, nb, c->max_chunk_pw, c->ns_max, nullptr, v, c->stream);
+        }, 2, &ms));
+      } else {
+        float2 *S1 = reinterpret_cast<float2 *>(c->S1), *S2 = reinterpret_cast<float2 *>(c->S2);
+        HPTRY(time_launch(c, [&] {
+          if (!fwd)
+            return launch_stick_inv32(c->sk, c->d_kp, 1, nb, nitems, c->X32, c->ld, S1, c->ns_pad, c->n3,
+                                      c->az32.tw32, c->max_chunk_pw, c->ns_max, nullptr, v, c->stream);
+          return launch_stick_fwd32(c->sk, c->d_kp, 1, nb, nitems, S2, c->ns_pad, c->n3, c->az32.tw32, 1.0, c->AP32,
+                                    c->ld, 2, nullptr, nullptr, nullptr, nb, c->max_chunk_pw, c->ns_max, nullptr, v,
+                                    c->stream);
+        }, 2, &ms));
+      }
+      c->stick_ms[slot][fwd][v] = ms;
+      if (ms < best) {
+        best = ms;
+        c->stick_var[slot][fwd] = v;
+      }
+    }
+  }
+  c->stick_tuned[slot] = true;
+  return HP_OK;
+}
+
 // Tune every launch shape a call on nk mesh points will use (c->d_kp must hold its pairs).
 hp_status autotune(hp_ctx *c, int nk, int mixed) {
   if (!c->use_tuned) return HP_OK;
   const int rows = c->n_beta + c->n_occ;
   for (int M : {rows, c->n_occ, 5 * c->n_hub, 5}) HPTRY(tune_gemm(c, 64, M, nk));
   HPTRY(tune_plane(c, 64, nk));
+  HPTRY(tune_stick(c, 64, nk));
   if (mixed) {
     HPTRY(setup32(c));
     if (c->lowp_gemm == HP_GEMM_FP32) HPTRY(tune_gemm(c, 32, rows, nk));
@@ -879,6 +927,7 @@ hp_status autotune(hp_ctx *c, int nk, int mixed) {
       HPTRY(tune_gemm(c, 32, c->n_occ, nk));
     }
     HPTRY(tune_plane(c, 32, nk));
+    HPTRY(tune_stick(c, 32, nk));
   }
   return HP_OK;
 }
@@ -1527,7 +1576,7 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
     HPCHK(hipMemcpyAsync(c->X + (size_t)k * nb * c->ld, c->d_T + (size_t)k * c->t_stride + (size_t)c->n_beta * c->ld,
                          sizeof(double2) * (size_t)nb * c->ld, hipMemcpyDeviceToDevice, st));
   HPCHK(launch_stick_inv(c->sk, c->d_kself, 0, nb, (int)nitems, c->X, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
-                         c->max_chunk_pw, c->ns_max, nullptr, st));
+                         c->max_chunk_pw, c->ns_max, nullptr, 0, st));
   HPCHK(launch_plane_to_real(c->pl, c->sk, c->d_kself, 0, nb, (int)nitems, c->S1, c->ns_pad, c->d_psi, st));
   HPTRY(sync(c.get()));
   *out = c.release();
@@ -1578,7 +1627,7 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
     // response density (spin x time reversal) and occupations (Eq. 13)
     HPCHK(timed(c, K_DRHO_STICKS, [&] {
       return launch_stick_inv(c->sk, c->d_kp, 1, nb, nitems, c->X, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
-                              c->max_chunk_pw, c->ns_max, nullptr, c->stream);
+                              c->max_chunk_pw, c->ns_max, nullptr, stick_variant(c, 64, 0), c->stream);
     }));
     HPCHK(timed(c, K_PLANE_DRHO, [&] {
       return launch_plane_drho(c->pl, c->sk, c->d_kp, nb, nk, c->S1, c->ns_pad, c->d_psi, c->part, c->drho_split,
@@ -1974,6 +2023,18 @@ extern "C" hp_status hp_tuning_report(hp_ctx *c, char *buf, int32_t len) {
     o += "]}";
     first = false;
   }
+  o += "], \"sticks\": [";
+  first = true;
+  for (int slot = 0; slot < 2; ++slot) {
+    if (!c->stick_tuned[slot]) continue;
+    snprintf(line, sizeof line,
+             "%s{\"prec\": %d, \"inverse_variant\": %d, \"inverse_ms\": [%.4f, %.4f], \"forward_variant\": %d, "
+             "\"forward_ms\": [%.4f, %.4f]}",
+             first ? "" : ", ", slot ? 32 : 64, c->stick_var[slot][0], c->stick_ms[slot][0][0], c->stick_ms[slot][0][1],
+             c->stick_var[slot][1], c->stick_ms[slot][1][0], c->stick_ms[slot][1][1]);
+    o += line;
+    first = false;
+  }
   o += "]}";
   if ((int32_t)o.size() + 1 > len) return fail(HP_ERR_ARG, "buffer too small (%d bytes needed)", (int)o.size() + 1);
   memcpy(buf, o.c_str(), o.size() + 1);
@@ -2016,6 +2077,20 @@ extern "C" hp_status hp_set_plane_variant(hp_ctx *c, int32_t prec, int32_t varia
   c->plane_var[slot] = variant;
   c->plane_nvar[slot] = nv;
   c->plane_tuned[slot] = true;
+  drop_graphs(c);
+  return HP_OK;
+}
+
+extern "C" hp_status hp_set_stick_variant(hp_ctx *c, int32_t prec, int32_t inverse_variant, int32_t forward_variant) {
+  if (!c) return fail(HP_ERR_ARG, "context is NULL");
+  if (prec != 64 && prec != 32) return fail(HP_ERR_ARG, "prec must be 64 or 32");
+  const int nv = (c->n3 == 24 || c->n3 == 40) ? 2 : 1;
+  if (inverse_variant < 0 || inverse_variant >= nv || forward_variant < 0 || forward_variant >= nv)
+    return fail(HP_ERR_ARG, "variants must be in 0..%d for this grid", nv - 1);
+  const int slot = prec == 32 ? 1 : 0;
+  c->stick_var[slot][0] = inverse_variant;
+  c->stick_var[slot][1] = forward_variant;
+  c->stick_tuned[slot] = true;
   drop_graphs(c);
   return HP_OK;
 }

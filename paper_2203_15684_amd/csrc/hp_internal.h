@@ -71,21 +71,23 @@ struct Sticks {
 // S[item][z][s] = sum_{G in stick s} X[item][G] e^{+i G_z z}
 hipError_t launch_stick_inv(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const double2 *X,
                             int ld, double2 *S, int ns_pad, int n3, const double2 *tw3, int max_chunk_pw, int ns_max,
-                            const int *active, hipStream_t st);
+                            const int *active, int variant, hipStream_t st);
 // Y[item][G] = scale * sum_z S[item][z][s(G)] e^{-i G_z z}   (S may be null: 0)
 //   mode 0 adds (kin[G] - eps[k*eps_stride+v]) X[item][G] (eps may be null: 0)
 hipError_t launch_stick_fwd(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const double2 *S,
                             int ns_pad, int n3, const double2 *tw3, double scale, double2 *Y, int ld, int mode,
                             const double *kin, const double *eps, const double2 *X, int eps_stride, int max_chunk_pw,
-                            int ns_max, const int *active, hipStream_t st);
+                            int ns_max, const int *active, int variant, hipStream_t st);
+// variant (both z transforms): 0 = a workgroup per 32 sticks, threads over (z, stick);
+// 1 = a thread per stick with its N3 values in registers (N3 = 24 or 40; else as 0).
 // FP32 variants of the three operator kernels (mixed-precision inner solves).
 hipError_t launch_stick_inv32(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const float2 *X,
                               int ld, float2 *S, int ns_pad, int n3, const float2 *tw3, int max_chunk_pw, int ns_max,
-                              const int *active, hipStream_t st);
+                              const int *active, int variant, hipStream_t st);
 hipError_t launch_stick_fwd32(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const float2 *S,
                               int ns_pad, int n3, const float2 *tw3, double scale, float2 *Y, int ld, int mode,
                               const double *kin, const double *eps, const float2 *X, int eps_stride,
-                              int max_chunk_pw, int ns_max, const int *active, hipStream_t st);
+                              int max_chunk_pw, int ns_max, const int *active, int variant, hipStream_t st);
 hipError_t launch_plane_vloc32(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
                                const float2 *Sin, float2 *Sout, int ns_pad, const float *vp, const int *active,
                                int variant, hipStream_t st);

@@ -114,11 +114,13 @@ _lib.hp_set_gemm_shape.argtypes = [C.c_void_p] + [C.c_int32] * 6
 _lib.hp_set_gemm_shape.restype = C.c_int32
 _lib.hp_set_plane_variant.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
 _lib.hp_set_plane_variant.restype = C.c_int32
+_lib.hp_set_stick_variant.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+_lib.hp_set_stick_variant.restype = C.c_int32
 
 EXPORTED = ["hp_ground_state_load", "hp_sternheimer_scf", "hp_response_matrix", "hp_hubbard_params",
             "hp_destroy", "hp_last_error", "hp_apply_h", "hp_solve_first_order", "hp_profile_start",
             "hp_profile_stop", "hp_tuning_report", "hp_set_gemm_shape", "hp_set_plane_variant",
-            "hp_neighbours"]
+            "hp_neighbours", "hp_set_stick_variant"]
 
 
 def hp_last_error() -> str:
@@ -347,3 +349,7 @@ def hp_neighbours(cell, hub_tau, nq, dist_thr: float = 6e-4):
                               _ptr(pj, _ip), _ptr(d), C.byref(n)), allow_warn=False)
     k = n.value
     return [(int(pi[i]), int(pj[i]), float(d[i])) for i in range(k)]
+
+
+def hp_set_stick_variant(ctx: Context, prec: int, inverse_variant: int, forward_variant: int):
+    _check(_lib.hp_set_stick_variant(ctx.handle, prec, inverse_variant, forward_variant), allow_warn=False)

@@ -102,9 +102,10 @@ DUO = _reg(SystemSpec(name="duo_k221", cfg_id=7, cell=(10.0, 7.5, 7.0), n_atoms=
 OLIVINE = _reg(SystemSpec(name="olivine28", cfg_id=1, cell=(19.6, 11.3, 8.9), n_atoms=28, n_hub=4,
                           fft=(72, 45, 40), ecut=22.45, n_occ=112, kmesh=(2, 3, 4), qmesh=(1, 2, 2),
                           depth=(5.5, 6.5), width=(0.55, 0.65), center_jitter=0.15, kb_d=(0.2, 0.6)))
-# The same cell with a 4x4x2 k-mesh (k+q stays on the mesh) and a cutoff jittered
-# per {k,-k} pair so that PW counts spread over ~9,600-10,400.
-OLIVINE_K442 = _reg(replace(OLIVINE, name="olivine28_k442", cfg_id=3, kmesh=(4, 4, 2),
+# The same system (same seed: atoms, wells, noise, projectors) with a 4x4x2 k-mesh
+# (k+q stays on the mesh) and a cutoff jittered per {k,-k} pair so that PW counts spread
+# over ~9,600-10,400.
+OLIVINE_K442 = _reg(replace(OLIVINE, name="olivine28_k442", cfg_id=1, kmesh=(4, 4, 2),
                             ecut_jitter=0.0265, base=None))
 # 2x1x1 supercell of the olivine-shaped cell: 56 atoms, 8 d sites, ~2x10^4 PWs.
 # (the cutoff stays the base cell's 22.45 Ha so that the supercell is an exact replica:

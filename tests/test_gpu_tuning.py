@@ -22,13 +22,14 @@ def _scf(ctx, prec, autotune=1, site=1, q=(0.0, 0.5, 0.0)):
     return hp.hp_sternheimer_scf(ctx, site, q, p)
 
 
-def _pin(ctx, gs, prec_list, batch, tile, nsplit, bands, pv):
+def _pin(ctx, gs, prec_list, batch, tile, nsplit, bands, pv, sv=(0, 0)):
     from paper_2203_15684_amd import hp
     rows = gs.n_beta + gs.n_occ
     for prec in prec_list:
         for m in (rows, gs.n_occ, 5 * gs.n_hub, 5):
             hp.hp_set_gemm_shape(ctx, prec, m, batch, tile, nsplit, bands)
         hp.hp_set_plane_variant(ctx, prec, pv)
+        hp.hp_set_stick_variant(ctx, prec, *sv)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -40,7 +41,8 @@ def test_shape_variants_bitwise(prec):
     precs = [64] if prec == "fp64" else [64, 32]
     ref = None
     for i, (tile, bands) in enumerate(itertools.product(range(4), (32, 64, 128))):
-        _pin(ctx, gs, precs, gs.n_mesh, tile, 2, bands, i % 3)   # the 30x24 plane has three variants
+        # the 30x24 plane has three variants; N3 = 24 both z-transform variants
+        _pin(ctx, gs, precs, gs.n_mesh, tile, 2, bands, i % 3, (i % 2, (i // 2) % 2))
         out = _scf(ctx, pr)
         assert out[3] == 0
         if ref is None:
@@ -60,9 +62,10 @@ def test_shape_variants_bitwise_fullsize_solve():
     k = gs.kpts[ik].k_frac + np.asarray(q)
     npw = next(e.npw for e in gs.kpts if np.allclose(k - e.k_frac, np.round(k - e.k_frac)))
     ref = None
-    for tile, bands, pv in [(0, 32, 0), (3, 128, 1), (1, 64, 2), (2, 128, 0), (3, 32, 2)]:
+    for tile, bands, pv, sv in [(0, 32, 0, (0, 0)), (3, 128, 1, (1, 1)), (1, 64, 2, (1, 0)), (2, 128, 0, (0, 1)),
+                                (3, 32, 2, (1, 1))]:
         for prec in ("fp64", "mixed"):
-            _pin(ctx, gs, [64, 32], 1, tile, 4, bands, pv)
+            _pin(ctx, gs, [64, 32], 1, tile, 4, bands, pv, sv)
             p = hp.ScfParams(cg_tol=1e-11, max_cg_iter=2000, precision=hp.HP_FP64 if prec == "fp64" else hp.HP_MIXED)
             du, st = hp.hp_solve_first_order(ctx, 3, q, ik, None, p, npw)
             assert st == 0
@@ -91,7 +94,11 @@ def test_tuner_report_and_agreement():
     assert {p["prec"] for p in rep["plane"]} == {64, 32}
     for p in rep["plane"]:
         assert p["ms"][p["variant"]] == min(p["ms"])
-    assert hp.hp_tuning_report(plain) == {"gemm": [], "plane": []}
+    assert {p["prec"] for p in rep["sticks"]} == {64, 32}
+    for p in rep["sticks"]:
+        assert p["inverse_ms"][p["inverse_variant"]] == min(p["inverse_ms"])
+        assert p["forward_ms"][p["forward_variant"]] == min(p["forward_ms"])
+    assert hp.hp_tuning_report(plain) == {"gemm": [], "plane": [], "sticks": []}
 
 
 def test_pinning_rejects_bad_shapes():
@@ -104,3 +111,5 @@ def test_pinning_rejects_bad_shapes():
             hp.hp_set_gemm_shape(ctx, *args)
     with pytest.raises(hp.HpError):
         hp.hp_set_plane_variant(ctx, 64, 1)   # 24x24 planes: only variant 0
+    with pytest.raises(hp.HpError):
+        hp.hp_set_stick_variant(ctx, 64, 2, 0)

@@ -820,13 +820,12 @@ __global__ void __launch_bounds__(kThreads) k_plane_to_real(Plane pl, Sticks sk,
   for (int i = threadIdx.x; i < np; i += blockDim.x) out[i] = P[i];
 }
 
-template <int N1, int N2>
+template <int N1, int N2, class C = double2>
 __global__ void __launch_bounds__(kThreads) k_plane_mul_fwd(Plane pl, Sticks sk, const KPair *kp, int nb,
-                                                            const double2 *__restrict__ psi,
-                                                            const double2 *__restrict__ dv,
-                                                            double2 *__restrict__ Sout, int ns_pad) {
+                                                            const C *__restrict__ psi, const C *__restrict__ dv,
+                                                            C *__restrict__ Sout, int ns_pad) {
   extern __shared__ __align__(16) unsigned char lds[];
-  PlaneCtx<N1, N2> pc(pl, lds);
+  PlaneCtx<N1, N2, C> pc(pl, lds);
   const int z = blockIdx.x;
   const int item = blockIdx.y;
   const int k = item / nb;
@@ -834,9 +833,9 @@ __global__ void __launch_bounds__(kThreads) k_plane_mul_fwd(Plane pl, Sticks sk,
   basis_of(kp, k, 1, e, g0x, g0y, g0z);
   const EntryDev E = sk.ent[e];
   const int np = pc.np();
-  double2 *P = pc.P;
-  const double2 *ps = psi + ((size_t)item * pl.n3 + z) * np;
-  const double2 *d = dv + (size_t)z * np;
+  C *P = pc.P;
+  const C *ps = psi + ((size_t)item * pl.n3 + z) * np;
+  const C *d = dv + (size_t)z * np;
   for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = cmul(ps[i], d[i]);
   pc.set_active(sk.xa + E.xa_off, E.nxa, g0x);
   pc.template x_lines<false>();
@@ -847,13 +846,13 @@ __global__ void __launch_bounds__(kThreads) k_plane_mul_fwd(Plane pl, Sticks sk,
   for (int s = threadIdx.x; s < E.ns; s += blockDim.x) Sout[so + s] = P[pc.pos(sx[s], sy[s], g0x, g0y)];
 }
 
-template <int N1, int N2>
+template <int N1, int N2, class C = double2>
 __global__ void __launch_bounds__(kThreads) k_plane_drho(Plane pl, Sticks sk, const KPair *kp, int nb,
-                                                         const double2 *__restrict__ Sdu, int ns_pad,
-                                                         const double2 *__restrict__ psi,
-                                                         double2 *__restrict__ part, int nsplit) {
+                                                         const C *__restrict__ Sdu, int ns_pad,
+                                                         const C *__restrict__ psi, double2 *__restrict__ part,
+                                                         int nsplit) {
   extern __shared__ __align__(16) unsigned char lds[];
-  PlaneCtx<N1, N2> pc(pl, lds);
+  PlaneCtx<N1, N2, C> pc(pl, lds);
   const int z = blockIdx.x;
   const int k = blockIdx.y;
   const int split = blockIdx.z;  // bands [v0, v1) of this workgroup
@@ -863,7 +862,7 @@ __global__ void __launch_bounds__(kThreads) k_plane_drho(Plane pl, Sticks sk, co
   basis_of(kp, k, 1, e, g0x, g0y, g0z);
   const EntryDev E = sk.ent[e];
   const int np = pc.np();
-  double2 *P = pc.P;
+  C *P = pc.P;
   const int *sx = sk.sx + E.st_off;
   const int *sy = sk.sy + E.st_off;
   pc.set_active(sk.xa + E.xa_off, E.nxa, g0x);
@@ -879,11 +878,15 @@ __global__ void __launch_bounds__(kThreads) k_plane_drho(Plane pl, Sticks sk, co
     __syncthreads();
     pc.template y_lines<true>();
     pc.template x_lines<true>();
-    const double2 *ps = psi + ((size_t)item * pl.n3 + z) * np;
+    const C *ps = psi + ((size_t)item * pl.n3 + z) * np;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       const int i = threadIdx.x + j * blockDim.x;
-      if (i < np) acc[j] = cadd(acc[j], cmulc(P[i], ps[i]));
+      if (i < np) {  // product in C, accumulation in FP64
+        const C pr = cmulc(P[i], ps[i]);
+        acc[j].x += (double)pr.x;
+        acc[j].y += (double)pr.y;
+      }
     }
     __syncthreads();
   }
@@ -1224,12 +1227,25 @@ hipError_t launch_plane_mul_fwd(const Plane &pl, const Sticks &sk, const KPair *
                     ns_pad);
   return hipGetLastError();
 }
+hipError_t launch_plane_mul_fwd32(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nitems,
+                                  const float2 *psi, const float2 *dv, float2 *Sout, int ns_pad, hipStream_t st) {
+  HP_PLANE_DISPATCH_T(k_plane_mul_fwd, COMMA float2, dim3(pl.n3, nitems), plane_lds_t(pl, sizeof(float2)), st, pl,
+                      sk, kp, nb, psi, dv, Sout, ns_pad);
+  return hipGetLastError();
+}
 
 hipError_t launch_plane_drho(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nk, const double2 *Sdu,
                              int ns_pad, const double2 *psi, double2 *part, int nsplit, hipStream_t st) {
   if (pl.n1 * pl.n2 > kMaxPerThread * kThreads || nsplit < 1) return hipErrorInvalidValue;
   HP_PLANE_DISPATCH(k_plane_drho, dim3(pl.n3, nk, nsplit), plane_lds_t(pl), st, pl, sk, kp, nb, Sdu, ns_pad, psi,
                     part, nsplit);
+  return hipGetLastError();
+}
+hipError_t launch_plane_drho32(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nk, const float2 *Sdu,
+                               int ns_pad, const float2 *psi, double2 *part, int nsplit, hipStream_t st) {
+  if (pl.n1 * pl.n2 > kMaxPerThread * kThreads || nsplit < 1) return hipErrorInvalidValue;
+  HP_PLANE_DISPATCH_T(k_plane_drho, COMMA float2, dim3(pl.n3, nk, nsplit), plane_lds_t(pl, sizeof(float2)), st, pl,
+                      sk, kp, nb, Sdu, ns_pad, psi, part, nsplit);
   return hipGetLastError();
 }
 

@@ -135,6 +135,7 @@ struct hp_ctx {
   bool have32 = false;
   float2 *tw32 = nullptr, *T32 = nullptr;
   unsigned *T16 = nullptr;  // the stacked table in packed bfloat16 (allocated on first use)
+  float2 *psi32 = nullptr, *dv32 = nullptr;  // FP32 occupied states on the grid, response potential
   int lowp_gemm = 0;        // hp_scf_params.lowp_gemm of the current call
   float *vp32 = nullptr;
   float2 *X32 = nullptr, *R32 = nullptr, *B32 = nullptr, *P32 = nullptr, *AP32 = nullptr;
@@ -241,6 +242,8 @@ enum KernelId {
   K_MIX,
   K_ZPROJ16,
   K_ZEXPAND16,
+  K_PLANE_MUL32,
+  K_PLANE_DRHO32,
   K_COUNT
 };
 static_assert(K_COUNT <= 32, "profile slots");
@@ -249,7 +252,7 @@ const char *const kKernelNames[K_COUNT] = {
     "plane_drho",  "plane_mul_fwd", "stick_inv32", "plane_vloc32", "stick_fwd32", "zproj32",
     "zexpand32",   "cg_step32",    "zproj_reduce", "cg_init",     "residual64",  "refine_update",
     "rhs_other",   "drho_sticks",  "drho_reduce", "hxc",         "dn",          "mixing",
-    "zproj16",     "zexpand16"};
+    "zproj16",     "zexpand16",    "plane_mul_fwd32", "plane_drho32"};
 
 hipEvent_t prof_event(hp_ctx *c) {
   if (!c->ev_pool.empty()) {
@@ -440,10 +443,24 @@ hp_status apply_op(hp_ctx *c, const KPair *kp, int use_kq, int nk, int nb, const
   return HP_OK;
 }
 
-// RHS of Eq. 15 for nk pairs: B = -P_c (dv psi + V_pert psi); dv may be null.
-hp_status build_rhs(hp_ctx *c, const KPair *kp, int nk, int site, const double2 *dv, const double2 *psi) {
+// RHS of Eq. 15 for nk pairs: B = -P_c (dv psi + V_pert psi); dv may be null.  lowp: the
+// product dv psi and its transform in FP32 (psi from the FP32 copy), the rest in FP64.
+hp_status build_rhs(hp_ctx *c, const KPair *kp, int nk, int site, const double2 *dv, const double2 *psi,
+                    bool lowp = false) {
   const int nb = c->n_occ, nitems = nk * nb;
-  if (dv) {
+  if (dv && lowp) {
+    float2 *S1 = reinterpret_cast<float2 *>(c->S1);
+    HPCHK(launch_to_f32((const double *)dv, (float *)c->dv32, 2L * c->nr, c->stream));
+    HPCHK(timed(c, K_PLANE_MUL32, [&] {
+      return launch_plane_mul_fwd32(c->pl32, c->sk, kp, nb, nitems, c->psi32, c->dv32, S1, c->ns_pad, c->stream);
+    }));
+    HPCHK(timed(c, K_RHS, [&] {
+      return launch_stick_fwd32(c->sk, kp, 1, nb, nitems, S1, c->ns_pad, c->n3, c->az32.tw32, -1.0 / (double)c->nr,
+                                c->AP32, c->ld, 2, nullptr, nullptr, nullptr, nb, c->max_chunk_pw, c->ns_max, nullptr,
+                                stick_variant(c, 32, 1), c->stream);
+    }));
+    HPCHK(launch_to_f64((const float *)c->AP32, (double *)c->B, 2L * nitems * c->ld, c->stream));
+  } else if (dv) {
     HPCHK(timed(c, K_PLANE_MUL, [&] {
       return launch_plane_mul_fwd(c->pl, c->sk, kp, nb, nitems, psi, dv, c->S1, c->ns_pad, c->stream);
     }));
@@ -668,6 +685,11 @@ hp_status setup32(hp_ctx *c) {
   HPTRY(c->alloc(&c->floor_in, nitems));
   HPTRY(c->alloc(&c->act_in, nitems));
   HPTRY(c->alloc(&c->act_out, nitems));
+  // FP32 copy of the occupied states on the grid and a response-potential buffer: the
+  // RHS product and the response density of iterations solved to >= 1e-6 run in FP32
+  HPTRY(c->alloc(&c->psi32, (size_t)c->n_mesh * c->n_occ * c->nr));
+  HPCHK(launch_to_f32((const double *)c->d_psi, (float *)c->psi32, 2L * c->n_mesh * c->n_occ * c->nr, c->stream));
+  HPTRY(c->alloc(&c->dv32, (size_t)c->nr));
   c->pl32 = c->pl;
   c->pl32.ax.tw32 = c->tw32;
   c->pl32.ay.tw32 = c->tw32 + c->n1;
@@ -1592,6 +1614,7 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
   std::vector<KPair> pairs;
   HPTRY(upload_pairs(c, site, q, pairs));
   HPTRY(autotune(c, nk, p->precision == HP_MIXED));
+  if (p->precision == HP_MIXED) HPTRY(setup32(c));
   HPCHK(hipMemcpyAsync(c->d_q, q, sizeof(double) * 3, hipMemcpyHostToDevice, c->stream));
   const long nr = c->nr;
   HPCHK(hipMemsetAsync(c->dvin, 0, sizeof(double2) * nr, c->stream));
@@ -1605,15 +1628,18 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
   double dchi = 0.0, vres = 1.0, max_rel = 0.0;
   double stage[8] = {0};
   for (it = 1; it <= p->niter_max; ++it) {
-    HPCHK(hipEventRecord(c->ev[0], c->stream));
-    HPTRY(build_rhs(c, c->d_kp, nk, site, it > 1 ? c->dvin : nullptr, c->d_psi));
-    HPCHK(hipEventRecord(c->ev[1], c->stream));
-    int iters = 0, nc = 0, nref = 0;
-    double mr = 0.0;
     // The first iteration gives chi0 and is solved to cg_tol; later iterations only need
     // the accuracy the response potential has reached (a fixed fraction of the last
     // mixing residual), never looser than 1e-3 nor tighter than cg_tol.
     const double tol_it = it == 1 ? p->cg_tol : std::max(p->cg_tol, std::min(1e-3, kAdaptiveTol * vres));
+    // Mixed form, iterations solved no tighter than kFp32TrustTol: the RHS product and the
+    // response density are accurate enough in FP32 (~1e-7 relative).
+    const bool lowp_it = p->precision == HP_MIXED && tol_it >= kFp32TrustTol;
+    HPCHK(hipEventRecord(c->ev[0], c->stream));
+    HPTRY(build_rhs(c, c->d_kp, nk, site, it > 1 ? c->dvin : nullptr, c->d_psi, lowp_it));
+    HPCHK(hipEventRecord(c->ev[1], c->stream));
+    int iters = 0, nc = 0, nref = 0;
+    double mr = 0.0;
     if (p->precision == HP_MIXED) {
       HPTRY(cg_solve_mixed(c, c->d_kp, nk, c->d_eps, it > 1, tol_it, p->max_cg_iter, p->inner_tol, p->max_refine,
                            &iters, &nc, &mr, &happ, &happ32, &nref));
@@ -1625,14 +1651,27 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
     not_conv = nc;
     max_rel = mr;
     // response density (spin x time reversal) and occupations (Eq. 13)
-    HPCHK(timed(c, K_DRHO_STICKS, [&] {
-      return launch_stick_inv(c->sk, c->d_kp, 1, nb, nitems, c->X, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
-                              c->max_chunk_pw, c->ns_max, nullptr, stick_variant(c, 64, 0), c->stream);
-    }));
-    HPCHK(timed(c, K_PLANE_DRHO, [&] {
-      return launch_plane_drho(c->pl, c->sk, c->d_kp, nb, nk, c->S1, c->ns_pad, c->d_psi, c->part, c->drho_split,
-                               c->stream);
-    }));
+    if (lowp_it) {
+      float2 *S1 = reinterpret_cast<float2 *>(c->S1);
+      HPCHK(launch_to_f32((const double *)c->X, (float *)c->X32, 2L * nitems * c->ld, c->stream));
+      HPCHK(timed(c, K_DRHO_STICKS, [&] {
+        return launch_stick_inv32(c->sk, c->d_kp, 1, nb, nitems, c->X32, c->ld, S1, c->ns_pad, c->n3, c->az32.tw32,
+                                  c->max_chunk_pw, c->ns_max, nullptr, stick_variant(c, 32, 0), c->stream);
+      }));
+      HPCHK(timed(c, K_PLANE_DRHO32, [&] {
+        return launch_plane_drho32(c->pl32, c->sk, c->d_kp, nb, nk, S1, c->ns_pad, c->psi32, c->part, c->drho_split,
+                                   c->stream);
+      }));
+    } else {
+      HPCHK(timed(c, K_DRHO_STICKS, [&] {
+        return launch_stick_inv(c->sk, c->d_kp, 1, nb, nitems, c->X, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
+                                c->max_chunk_pw, c->ns_max, nullptr, stick_variant(c, 64, 0), c->stream);
+      }));
+      HPCHK(timed(c, K_PLANE_DRHO, [&] {
+        return launch_plane_drho(c->pl, c->sk, c->d_kp, nb, nk, c->S1, c->ns_pad, c->d_psi, c->part, c->drho_split,
+                                 c->stream);
+      }));
+    }
     HPCHK(timed(c, K_DRHO_REDUCE, [&] {
       return launch_drho_reduce(c->d_kp, nk, c->drho_split, c->part, nr, 1.0 / c->omega, c->drho, c->stream);
     }));

@@ -108,6 +108,13 @@ hipError_t launch_plane_mul_fwd(const Plane &pl, const Sticks &sk, const KPair *
 // (sticks of du -> r), k+q basis.
 hipError_t launch_plane_drho(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nk, const double2 *Sdu,
                              int ns_pad, const double2 *psi, double2 *part, int nsplit, hipStream_t st);
+// FP32 transforms and products (FP64 accumulation of the density), for the mixed form.
+hipError_t launch_plane_mul_fwd32(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nitems,
+                                  const float2 *psi, const float2 *dv, float2 *Sout, int ns_pad, hipStream_t st);
+hipError_t launch_plane_drho32(const Plane &pl, const Sticks &sk, const KPair *kp, int nb, int nk, const float2 *Sdu,
+                               int ns_pad, const float2 *psi, double2 *part, int nsplit, hipStream_t st);
+// out[i] = (double) in[i]
+hipError_t launch_to_f64(const float *in, double *out, long n, hipStream_t st);
 // drho = sum_k (4 w_k / Omega) sum_s part[k][s] in fixed order.
 hipError_t launch_drho_reduce(const KPair *kp, int nk, int nsplit, const double2 *part, long nr, double inv_omega,
                               double2 *drho, hipStream_t st);

@@ -1054,6 +1054,16 @@ __global__ void k_to_f32(const double *__restrict__ in, float *__restrict__ out,
   if (i < n) out[i] = (float)in[i];
 }
 
+__global__ void k_to_f64(const float *__restrict__ in, double *__restrict__ out, long n) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)in[i];
+}
+
+hipError_t launch_to_f64(const float *in, double *out, long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_to_f32(const double *in, float *out, long n, hipStream_t st) {
   hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n);
   return hipGetLastError();

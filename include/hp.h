@@ -246,8 +246,8 @@ hp_status hp_profile_stop(hp_ctx *c, hp_kernel_time *out, int32_t max, int32_t *
  * JSON text (NUL-terminated, into buf of len bytes) of the launch shapes the
  * autotuner chose in this context: per GEMM shape (precision, rows, batch) the
  * projection tile, K split and expansion band tile with the measured and the
- * default times (ms), per precision the chosen plane-batch variant of the
- * local-potential FFT with every variant's time, and per precision the chosen
+ * default times (ms), per precision the chosen plane variant of the local-potential
+ * FFT with every variant's time (-1: not available for the grid), and per precision the chosen
  * z-transform variants (a workgroup per 32 sticks, or a thread per stick) with
  * their times.  HP_ERR_ARG if buf is too small. */
 hp_status hp_tuning_report(hp_ctx *c, char *buf, int32_t len);
@@ -259,10 +259,11 @@ hp_status hp_tuning_report(hp_ctx *c, char *buf, int32_t len);
  * points per launch, 1..n_mesh).  tile 0..3 (BF16: 0 or 3) =
  * projection workgroup tile 32x32, 64x32, 32x64, 64x64 (rows x bands); nsplit =
  * K split of the projection, 1..16; expand_bands = 32, 64 or 128 bands per
- * expansion workgroup.  Plane variant 0..2 of the local-potential FFT round trip
- * (0: one z plane per 256-thread workgroup, 1: two per 256, 2: two per 512; only
- * 0 unless N3 is even, the plane is 72x45, 144x45 or 30x24 and two planes fit in
- * LDS).  Errors: HP_ERR_ARG for values out of range. */
+ * expansion workgroup.  Plane variant 0..3 of the local-potential FFT round trip
+ * (0: one z plane per 256-thread workgroup, 1: two per 256, 2: two per 512, 3: one
+ * plane with the twiddles read from global memory; 1-3 only for 72x45, 144x45 and
+ * 30x24 planes, 1-2 only for even N3 with two planes fitting in LDS).  Errors:
+ * HP_ERR_ARG for values out of range or variants not available for the grid. */
 hp_status hp_set_gemm_shape(hp_ctx *c, int32_t prec, int32_t rows, int32_t batch, int32_t tile, int32_t nsplit,
                             int32_t expand_bands);
 hp_status hp_set_plane_variant(hp_ctx *c, int32_t prec, int32_t variant);

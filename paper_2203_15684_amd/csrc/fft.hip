@@ -427,27 +427,37 @@ __device__ __forceinline__ const float2 *axis_tw<float2>(const Axis &a) {
   return a.tw32;
 }
 
-template <int N1, int N2, class C = double2, int PB = 1>
+// TG: the twiddle tables are read from global memory (cached) instead of LDS copies,
+// which leaves more of the LDS for planes of other workgroups.
+template <int N1, int N2, class C = double2, int PB = 1, bool TG = false>
 struct PlaneCtx {
   static_assert(PB == 1 || (N1 > 0 && N2 > 0), "plane batches need compile-time plane sizes");
   const Plane &pl;
-  C *P;      // [PB][n1*n2]
-  C *twx;    // [n1] (LDS copy)
-  C *twy;    // [n2]
-  int *xs;   // [n1] active x columns, shifted and wrapped
+  C *P;            // [PB][n1*n2]
+  const C *twx;    // [n1] (LDS copy, or the global table when TG)
+  const C *twy;    // [n2]
+  int *xs;         // [n1] active x columns, shifted and wrapped
   int nxa;
   __device__ __forceinline__ int n1() const { return N1 > 0 ? N1 : pl.n1; }
   __device__ __forceinline__ int n2() const { return N2 > 0 ? N2 : pl.n2; }
   __device__ __forceinline__ int np() const { return n1() * n2(); }
   __device__ __forceinline__ PlaneCtx(const Plane &p, void *lds) : pl(p) {
     P = reinterpret_cast<C *>(lds);
-    twx = P + PB * np();
-    twy = twx + n1();
-    xs = reinterpret_cast<int *>(twy + n2());
     nxa = 0;
     const C *tx = axis_tw<C>(pl.ax), *ty = axis_tw<C>(pl.ay);
-    for (int i = threadIdx.x; i < n1(); i += blockDim.x) twx[i] = tx[i];
-    for (int i = threadIdx.x; i < n2(); i += blockDim.x) twy[i] = ty[i];
+    if constexpr (TG) {
+      twx = tx;
+      twy = ty;
+      xs = reinterpret_cast<int *>(P + PB * np());
+    } else {
+      C *lx = P + PB * np();
+      C *ly = lx + n1();
+      for (int i = threadIdx.x; i < n1(); i += blockDim.x) lx[i] = tx[i];
+      for (int i = threadIdx.x; i < n2(); i += blockDim.x) ly[i] = ty[i];
+      twx = lx;
+      twy = ly;
+      xs = reinterpret_cast<int *>(ly + n2());
+    }
   }
   // active x list of a stick set shifted by g0x (call from every thread; ends with a barrier)
   __device__ __forceinline__ void set_active(const int *xa, int n, int g0x) {
@@ -508,8 +518,8 @@ struct PlaneCtx {
   }
 };
 
-int plane_lds_t(const Plane &pl, int csize = (int)sizeof(double2), int pb = 1) {
-  return pb * pl.n1 * pl.n2 * csize + (pl.n1 + pl.n2) * csize + pl.n1 * (int)sizeof(int);
+int plane_lds_t(const Plane &pl, int csize = (int)sizeof(double2), int pb = 1, bool tw_global = false) {
+  return pb * pl.n1 * pl.n2 * csize + (tw_global ? 0 : (pl.n1 + pl.n2) * csize) + pl.n1 * (int)sizeof(int);
 }
 
 // ----------------------------------------------------------------- kernels
@@ -759,14 +769,14 @@ __global__ void __launch_bounds__(kThreads) k_plane_vloc(Plane pl, Sticks sk, co
 
 // The same round trip for PB consecutive z planes of one item per workgroup of NT threads
 // (the transform stages then run over PB times as many lines per barrier).
-template <int N1, int N2, class C, int PB, int NT>
+template <int N1, int N2, class C, int PB, int NT, bool TG = false>
 __global__ void __launch_bounds__(NT) k_plane_vloc_b(Plane pl, Sticks sk, const KPair *kp, int use_kq, int nb,
                                                      const C *__restrict__ Sin, C *__restrict__ Sout, int ns_pad,
                                                      const RealOf<C> *__restrict__ vp, const int *active) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int item = blockIdx.y;
   if (active && !active[item]) return;
-  PlaneCtx<N1, N2, C, PB> pc(pl, lds);
+  PlaneCtx<N1, N2, C, PB, TG> pc(pl, lds);
   constexpr int np = N1 * N2;
   const int z0 = blockIdx.x * PB;
   const int k = item / nb;
@@ -1153,20 +1163,29 @@ hipError_t launch_stick_fwd32(const Sticks &sk, const KPair *kp, int use_kq, int
 
 constexpr int kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 
-int plane_vloc_variants(const Plane &pl, int csize) {
+bool plane_vloc_variant_ok(const Plane &pl, int csize, int variant) {
   const int key = pl.n1 * 1000 + pl.n2;
-  const bool ok = pl.n3 % 2 == 0 && (key == 72045 || key == 144045 || key == 30024) &&
-                  plane_lds_t(pl, csize, 2) <= kLdsBytes;
-  return ok ? 3 : 1;
+  const bool shape = key == 72045 || key == 144045 || key == 30024;
+  if (variant == 0) return true;
+  if (variant == 1 || variant == 2) return shape && pl.n3 % 2 == 0 && plane_lds_t(pl, csize, 2) <= kLdsBytes;
+  if (variant == 3) return shape;
+  return false;
 }
 
-// Plane-batch variants of the local-potential round trip: 0 = one plane per 256 threads,
-// 1 = two planes per 256 threads, 2 = two planes per 512 threads.
+// Variants of the local-potential round trip: 0 = one plane per 256 threads,
+// 1 = two planes per 256 threads, 2 = two planes per 512 threads, 3 = one plane per 256
+// threads with the twiddles read from global memory.
 namespace {
 template <int N1, int N2, class C>
 hipError_t plane_vloc_batched(int variant, const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb,
                               int nitems, const C *Sin, C *Sout, int ns_pad, const RealOf<C> *vp, const int *active,
                               hipStream_t st) {
+  if (variant == 3) {
+    hipLaunchKernelGGL((k_plane_vloc_b<N1, N2, C, 1, 256, true>), dim3(pl.n3, nitems), dim3(256),
+                       plane_lds_t(pl, sizeof(C), 1, true), st, pl, sk, kp, use_kq, nb, Sin, Sout, ns_pad, vp,
+                       active);
+    return hipGetLastError();
+  }
   const size_t lds = plane_lds_t(pl, sizeof(C), 2);
   if (variant == 1)
     hipLaunchKernelGGL((k_plane_vloc_b<N1, N2, C, 2, 256>), dim3(pl.n3 / 2, nitems), dim3(256), lds, st, pl, sk, kp,
@@ -1181,7 +1200,7 @@ template <class C>
 hipError_t plane_vloc_t(int variant, const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb,
                         int nitems, const C *Sin, C *Sout, int ns_pad, const RealOf<C> *vp, const int *active,
                         hipStream_t st) {
-  if (variant > 0 && plane_vloc_variants(pl, sizeof(C)) > 1) {
+  if (variant > 0 && plane_vloc_variant_ok(pl, sizeof(C), variant)) {
     switch (pl.n1 * 1000 + pl.n2) {
       case 72045:
         return plane_vloc_batched<72, 45, C>(variant, pl, sk, kp, use_kq, nb, nitems, Sin, Sout, ns_pad, vp, active,

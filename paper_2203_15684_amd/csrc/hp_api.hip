@@ -865,10 +865,12 @@ hp_status tune_plane(hp_ctx *c, int prec, int nk) {
   const int slot = prec == 32 ? 1 : 0;
   if (c->plane_tuned[slot]) return HP_OK;
   const int nb = c->n_occ, nitems = nk * nb;
-  const int nv = plane_vloc_variants(prec == 32 ? c->pl32 : c->pl, prec == 32 ? (int)sizeof(float2)
-                                                                              : (int)sizeof(double2));
+  const int csize = prec == 32 ? (int)sizeof(float2) : (int)sizeof(double2);
+  const int nv = 4;
   float best = 1e30f;
   for (int v = 0; v < nv; ++v) {
+    c->plane_ms[slot][v] = -1.f;  // not available for this grid
+    if (!plane_vloc_variant_ok(c->pl, csize, v)) continue;
     float ms = 0.f;
     if (prec == 64) {
       HPTRY(time_launch(c, [&] {
@@ -2111,8 +2113,9 @@ extern "C" hp_status hp_set_plane_variant(hp_ctx *c, int32_t prec, int32_t varia
   if (!c) return fail(HP_ERR_ARG, "context is NULL");
   if (prec != 64 && prec != 32) return fail(HP_ERR_ARG, "prec must be 64 or 32");
   const int slot = prec == 32 ? 1 : 0;
-  const int nv = plane_vloc_variants(c->pl, prec == 32 ? (int)sizeof(float2) : (int)sizeof(double2));
-  if (variant < 0 || variant >= nv) return fail(HP_ERR_ARG, "variant must be in 0..%d for this grid", nv - 1);
+  if (!plane_vloc_variant_ok(c->pl, prec == 32 ? (int)sizeof(float2) : (int)sizeof(double2), variant))
+    return fail(HP_ERR_ARG, "plane variant %d is not available for this grid", variant);
+  const int nv = 4;
   c->plane_var[slot] = variant;
   c->plane_nvar[slot] = nv;
   c->plane_tuned[slot] = true;

@@ -92,12 +92,13 @@ hipError_t launch_plane_vloc32(const Plane &pl, const Sticks &sk, const KPair *k
                                const float2 *Sin, float2 *Sout, int ns_pad, const float *vp, const int *active,
                                int variant, hipStream_t st);
 // Plane round trip for the local potential: sticks -> r (DIF) -> * vp -> sticks (reverse).
-// variant (0 .. plane_vloc_variants(pl) - 1): 0 = one z plane per 256-thread workgroup,
-// 1 = two planes per 256 threads, 2 = two planes per 512 threads (even N3, some plane sizes).
+// variant: 0 = one z plane per 256-thread workgroup, 1 = two planes per 256 threads,
+// 2 = two planes per 512 threads (even N3, two planes in LDS), 3 = one plane with the
+// twiddles read from global memory (less LDS per workgroup); 1-3 for some plane sizes.
 hipError_t launch_plane_vloc(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
                              const double2 *Sin, double2 *Sout, int ns_pad, const double *vp, const int *active,
                              int variant, hipStream_t st);
-int plane_vloc_variants(const Plane &pl, int complex_bytes);
+bool plane_vloc_variant_ok(const Plane &pl, int complex_bytes, int variant);
 // Sticks -> real-space plane (permuted layout), R[item][z][plane].
 hipError_t launch_plane_to_real(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
                                 const double2 *Sin, int ns_pad, double2 *R, hipStream_t st);

@@ -1,6 +1,8 @@
 // C ABI of the HIP Hubbard-response library: validation, device layout of the
-// ground state, the self-consistent Sternheimer driver and the assembly of
-// chi0 / chi / U,V.  See include/hp.h for the contract of each entry point.
+// ground state, the self-consistent Sternheimer driver (FP64, or FP32/BF16 inner
+// solves with FP64 residual refinement), CG iterations captured as hipGraphs, the
+// launch-shape autotuner, and the assembly of chi0 / chi / U,V.  See include/hp.h for
+// the contract of each entry point.
 #include <algorithm>
 #include <array>
 #include <chrono>

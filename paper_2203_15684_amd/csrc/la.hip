@@ -1,8 +1,10 @@
-// Dense linear algebra of the Sternheimer path on gfx950: complex FP64
-// projection / expansion GEMMs on the FP64 matrix cores (v_mfma_f64_16x16x4),
-// the batched preconditioned CG vector updates with per-band FP64 wavefront
-// reductions, the response-occupation contraction and the mixing reductions.
-// Every reduction runs in a fixed order, so results are bitwise reproducible.
+// Dense linear algebra of the Sternheimer path on gfx950: complex projection /
+// expansion GEMMs on the matrix cores (FP64 v_mfma_f64_16x16x4, FP32
+// v_mfma_f32_16x16x4, BF16 v_mfma_f32_16x16x16_bf16 with FP32 accumulation), the
+// batched preconditioned CG vector updates with per-band FP64 wavefront reductions,
+// the mixed-precision residual and refinement kernels, the response-occupation
+// contraction and the mixing reductions.  Every reduction runs in a fixed order, so
+// results are bitwise reproducible for a given launch shape.
 #include "hp_internal.h"
 
 namespace hp {

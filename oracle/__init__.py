@@ -9,12 +9,14 @@ in common is the seeded input generator in ``synth``.
 The oracle is written from the paper (Timrov, Marzari, Cococcioni, "HP - A code
 for the calculation of Hubbard parameters using density-functional
 perturbation theory"): Eqs. 7-9 (susceptibilities and U/V), Eq. 12
-(monochromatic sum over q), Eq. 13 (response occupations), Eqs. 14-18
+(monochromatic sum over q), Eq. 13 (response occupations), Eq. 6 (ortho-atomic
+projectors by Loewdin orthogonalization), Eqs. 14-18
 (q-specific Sternheimer equation, perturbing potential, valence and
 conduction projectors, the alpha shift).  Each function cites the passage it
 follows.
 """
-from .hp_oracle import Oracle, ScfParams, hubbard_params, assemble_chi, nearest_neighbours
+from .hp_oracle import Oracle, ScfParams, hubbard_params, assemble_chi, nearest_neighbours, loewdin, ortho_atomic_phi
 from . import pz81
 
-__all__ = ["Oracle", "ScfParams", "hubbard_params", "assemble_chi", "nearest_neighbours", "pz81"]
+__all__ = ["Oracle", "ScfParams", "hubbard_params", "assemble_chi", "nearest_neighbours", "loewdin",
+           "ortho_atomic_phi", "pz81"]

@@ -65,8 +65,16 @@ class Oracle:
     """One ground state (synth.GroundState-like object) and the linear-response
     machinery of Eqs. 12-18 on top of it."""
 
-    def __init__(self, gs, cache_limit_bytes: float = 2e9):
+    def __init__(self, gs, cache_limit_bytes: float = 2e9, projectors: str = "atomic"):
+        """projectors: "atomic" (the d orbitals as given) or "ortho-atomic" (Loewdin-orthogonalized
+        over every atomic orbital of the system, Eq. 6)."""
         self.gs = gs
+        if projectors == "atomic":
+            self.phi = [e.phi for e in gs.kpts]
+        elif projectors == "ortho-atomic":
+            self.phi = [ortho_atomic_phi(gs, e) for e in gs.kpts]
+        else:
+            raise ValueError(projectors)
         self.fft = tuple(int(x) for x in gs.fft)
         self.nr = int(np.prod(self.fft))
         self.cell = np.asarray(gs.cell, dtype=np.float64)
@@ -168,8 +176,8 @@ class Oracle:
         if dv is not None:
             b += self.to_recip(dv[None] * self.psi_r(ik), self.grid_index(j, g0))
         sl = slice(5 * site, 5 * site + 5)
-        A = ek.phi[sl].conj() @ ek.u.T          # A[m, v] = <phi_{m,k}|u_vk>
-        b += A.T @ ej.phi[sl]                   # sum_m |phi_{m,k+q}> A[m, v]
+        A = self.phi[ik][sl].conj() @ ek.u.T    # A[m, v] = <phi_{m,k}|u_vk>
+        b += A.T @ self.phi[j][sl]              # sum_m |phi_{m,k+q}> A[m, v]
         b -= (b @ ej.u.conj().T) @ ej.u         # P_c = 1 - sum_v' |u_v',k+q><u_v',k+q|
         return -b
 
@@ -261,8 +269,8 @@ class Oracle:
         2 w_k sum_v [<u|phi_{m2,k}><phi_{m1,k+q}|du> + <u|phi_{m1,k}><phi_{m2,k+q}|du>]."""
         j, _ = self.kq_entry(ik, q)
         ek, ej = self.kpts[ik], self.kpts[j]
-        A = ek.phi.conj() @ ek.u.T               # (n_hub*5, n_occ)
-        B = ej.phi.conj() @ du.T                 # (n_hub*5, n_occ)
+        A = self.phi[ik].conj() @ ek.u.T         # (n_hub*5, n_occ)
+        B = self.phi[j].conj() @ du.T            # (n_hub*5, n_occ)
         out = np.zeros((self.n_hub, 5, 5), dtype=np.complex128)
         for s in range(self.n_hub):
             sl = slice(5 * s, 5 * s + 5)
@@ -275,7 +283,7 @@ class Oracle:
         out = np.zeros((self.n_hub, 5, 5), dtype=np.complex128)
         for ik in range(self.n_mesh):
             e = self.kpts[ik]
-            A = e.phi.conj() @ e.u.T
+            A = self.phi[ik].conj() @ e.u.T
             for s in range(self.n_hub):
                 sl = slice(5 * s, 5 * s + 5)
                 out[s] += 2.0 * e.weight * A[sl] @ A[sl].conj().T
@@ -395,7 +403,7 @@ class Oracle:
         e = self.kpts[0]
         H0 = self.h_dense(0)
         sl = slice(5 * site, 5 * site + 5)
-        Pj = e.phi[sl].T @ e.phi[sl].conj()          # sum_m |phi_m><phi_m|
+        Pj = self.phi[0][sl].T @ self.phi[0][sl].conj()   # sum_m |phi_m><phi_m|
         rho0 = self.gs.rho0
         vxc0 = pz81.v_xc(rho0)
         g2 = self.gvec_q(np.zeros(3))
@@ -439,9 +447,26 @@ class Oracle:
                 rho_in = rho_in + 0.3 * f
         else:
             raise RuntimeError("perturbed ground state did not converge")
-        A = e.phi.conj() @ U.T
+        A = self.phi[0].conj() @ U.T
         n = np.array([2.0 * np.sum(np.abs(A[5 * s:5 * s + 5]) ** 2) for s in range(self.n_hub)])
         return n
+
+
+def loewdin(rows: np.ndarray) -> np.ndarray:
+    """Symmetric (Loewdin) orthonormalization of a set of plane-wave rows (Eq. 6):
+    phi~_i = sum_j (O^-1/2)_ji phi_j with O_ij = <phi_i|phi_j>."""
+    O = rows.conj() @ rows.T
+    w, U = np.linalg.eigh(O)
+    X = (U * w ** -0.5) @ U.conj().T
+    return X.T @ rows
+
+
+def ortho_atomic_phi(gs, e) -> np.ndarray:
+    """Ortho-atomic Hubbard projectors of k-entry e (Eq. 6): every atomic orbital of the system
+    (synth.atomic_orbitals, an input) Loewdin-orthogonalized, then the Hubbard d rows."""
+    from synth.system import atomic_orbitals
+    rows, hub_rows = atomic_orbitals(gs, e.k_frac, e.miller)
+    return loewdin(rows)[hub_rows]
 
 
 def supercell_cells(qmesh) -> np.ndarray:

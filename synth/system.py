@@ -281,6 +281,14 @@ def kb_radial_ft(p: np.ndarray, l: int, s: float) -> np.ndarray:
     raise ValueError(l)
 
 
+def sto_radial_ft(p: np.ndarray, l: int, zeta: float) -> np.ndarray:
+    """4 pi int r^2 j_l(p r) R(r) dr for the Slater-type R = N r^l exp(-zeta r) of unit norm:
+    int r^(l+2) j_l(p r) exp(-zeta r) dr = 2^(l+1) (l+1)! zeta p^l / (p^2 + zeta^2)^(l+2) and
+    N^2 = (2 zeta)^(2l+3) / (2l+2)!  (l = 2 is d_radial_ft)."""
+    nrm = math.sqrt((2 * zeta) ** (2 * l + 3) / math.factorial(2 * l + 2))
+    return 4 * math.pi * nrm * (2 ** (l + 1)) * math.factorial(l + 1) * zeta * p ** l / (p * p + zeta * zeta) ** (l + 2)
+
+
 def projector_tables(gs_like, k_frac: np.ndarray, miller: np.ndarray):
     """beta (n_beta, npw) and phi (n_hub*5, npw) at k.  beta rows: per atom, l=0 then the
     three l=1 components; phi rows: per Hubbard site, the five d components."""
@@ -316,6 +324,57 @@ def projector_tables(gs_like, k_frac: np.ndarray, miller: np.ndarray):
 def _children(cfg_id: int, attempt: int):
     ss = np.random.SeedSequence([2203, 15684, cfg_id + 1000 * attempt])
     return [np.random.default_rng(c) for c in ss.spawn(6)]
+
+
+def _orbital_zeta_draw(spec: SystemSpec, attempt: int, n_atoms: int) -> np.ndarray:
+    # a seventh child of the system's seed sequence (the first six are untouched)
+    ss = np.random.SeedSequence([2203, 15684, spec.cfg_id + 1000 * attempt])
+    return np.random.default_rng(ss.spawn(7)[6]).uniform(1.0, 1.5, (n_atoms, 2))
+
+
+def orbital_zeta(gs) -> np.ndarray:
+    """(n_atoms, 2) exponents of every atom's s and p Slater-type orbitals (a replicated
+    supercell repeats its base cell's, atom by atom)."""
+    spec = gs.spec
+    if spec.base is None:
+        return _orbital_zeta_draw(spec, gs.seed_used, gs.tau.shape[0])
+    base_spec = SPECS[spec.base]
+    bat, _, _ = _draw_atoms(base_spec, gs.seed_used)
+    nat = bat.tau.shape[0]
+    zb = _orbital_zeta_draw(base_spec, gs.seed_used, nat)
+    nimg = int(np.prod(spec.rep))
+    hub_set = set(bat.hub_atoms.tolist())
+    order = [a for a in list(bat.hub_atoms) + [a for a in range(nat) if a not in hub_set] for _ in range(nimg)]
+    return zb[order]
+
+
+def atomic_orbitals(gs, k_frac: np.ndarray, miller: np.ndarray):
+    """All atomic orbitals at k, the set whose Loewdin orthogonalization gives the ortho-atomic
+    Hubbard projectors (Eq. 6): per atom an s and three p Slater-type orbitals, then on Hubbard
+    atoms the five d orbitals of the atomic projectors.  Returns (rows (n_atwfc, npw),
+    hub_rows (n_hub*5,): the row of d orbital m of Hubbard site s at 5 s + m)."""
+    cell, tau = gs.cell, gs.tau
+    omega = abs(np.linalg.det(cell))
+    p = (miller + np.asarray(k_frac)[None, :]) @ recip(cell)
+    pn = np.linalg.norm(p, axis=1)
+    zsp = orbital_zeta(gs)
+    site_of = {int(a): s for s, a in enumerate(gs.hub_atoms)}
+    rows = []
+    hub_rows = np.zeros(5 * len(site_of), dtype=np.int32)
+    y0, y1, y2 = real_ylm(0, p), real_ylm(1, p), real_ylm(2, p)
+    for a in range(tau.shape[0]):
+        ph = np.exp(-1j * (p @ tau[a]))
+        rows.append(y0[0] * sto_radial_ft(pn, 0, zsp[a, 0]) * ph)
+        rad = sto_radial_ft(pn, 1, zsp[a, 1])
+        for m in range(3):
+            rows.append(-1j * y1[m] * rad * ph)
+        if a in site_of:
+            s = site_of[a]
+            rad = d_radial_ft(pn, gs.hub_zeta[s])
+            for m in range(5):
+                hub_rows[5 * s + m] = len(rows)
+                rows.append(-1.0 * y2[m] * rad * ph)
+    return np.array(rows, dtype=np.complex128) / math.sqrt(omega), hub_rows
 
 
 def _min_image_dist(cell, f1, f2):

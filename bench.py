@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="olivine28")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    ap.add_argument("--projectors", default="atomic", choices=["atomic", "ortho-atomic"],
+                    help="Hubbard projectors: the atomic d orbitals, or Loewdin ortho-atomic ones built at load")
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--cg-tol", type=float, default=1e-10)
     ap.add_argument("--conv-thr-chi", type=float, default=1e-10)
@@ -178,9 +180,17 @@ def main():
     t0 = time.time()
     gs = cache.get(args.config)
     t_gen = time.time() - t0
+    load_kw = {}
+    if args.projectors == "ortho-atomic":
+        import synth
+        t0 = time.time()
+        atw, hub_rows = synth.atomic_orbital_tables(gs)
+        t_gen += time.time() - t0
+        load_kw = {"atwfc": atw, "hub_rows": hub_rows}
     free_before_load = torch.cuda.mem_get_info()[0]
     t0 = time.perf_counter()
-    ctx = hp.hp_ground_state_load(gs)
+    ctx = hp.hp_ground_state_load(gs, **load_kw)
+    load_kw = None
     torch.cuda.synchronize()
     t_load = time.perf_counter() - t0
     nq = gs.qmesh
@@ -299,7 +309,7 @@ def main():
                    "npw_min": min(npws), "npw_max": max(npws), "k_entries": len(npws),
                    "precision": args.precision, "cg_tol": args.cg_tol, "conv_thr_chi": args.conv_thr_chi,
                    "conv_thr_v": args.conv_thr_v, "inner_tol": args.inner_tol,
-                   "site_q_pairs": gs.n_hub * len(nq_list)},
+                   "site_q_pairs": gs.n_hub * len(nq_list), "projectors": args.projectors},
         "chi_rel_err_mixed_vs_fp64": chi_err, "uv_err_meV_mixed_vs_fp64": uv_err_mev,
         "speedup_mixed_vs_fp64": summary["mixed"]["speedup_vs_fp64"],
         "forms": summary,

@@ -59,6 +59,9 @@ enum {
 };
 
 enum { HP_FP64 = 0, HP_MIXED = 1 };   /* arithmetic of the Sternheimer solves */
+/* Hubbard projectors: the given atomic d orbitals, or the ortho-atomic ones
+ * phi~_i = sum_j (O^-1/2)_ji phi_j over every atomic orbital, O_ij = <phi_i|phi_j> (Eq. 6). */
+enum { HP_PROJ_ATOMIC = 0, HP_PROJ_ORTHO_ATOMIC = 1 };
 /* HP_MIXED: number type of the projection GEMMs inside the low-precision inner solves
  * (FP32 accumulation in every case; the FFTs and V_loc psi are FP32). */
 enum { HP_GEMM_FP32 = 0, HP_GEMM_BF16 = 1, HP_GEMM_BF16_PV32 = 2 };
@@ -77,6 +80,8 @@ typedef struct hp_kpoint {
   const double *u;        /* [n_occ][npw] complex, orthonormal rows                */
   const double *beta;     /* [n_beta][npw] complex, KB projector tables            */
   const double *phi;      /* [n_hub*5][npw] complex, Hubbard d orbitals, per site  */
+  const double *atwfc;    /* HP_PROJ_ORTHO_ATOMIC: [n_atwfc][npw] complex, every   */
+                          /* atomic orbital of the system; else may be NULL        */
 } hp_kpoint;
 
 /* The unperturbed ground state (paper: ground-state calculation section). */
@@ -98,6 +103,11 @@ typedef struct hp_ground_state {
   int32_t xc;             /* HP_XC_LDA_PZ81                                        */
   int32_t reserved;       /* must be 0                                             */
   void *stream;           /* hipStream_t to run on, or NULL for a private stream   */
+  int32_t projectors;     /* HP_PROJ_ATOMIC: phi as given; HP_PROJ_ORTHO_ATOMIC:   */
+                          /* Loewdin-orthogonalized over all atomic orbitals (Eq. 6)*/
+  int32_t n_atwfc;        /* HP_PROJ_ORTHO_ATOMIC: atomic orbitals per entry        */
+  const int32_t *hub_rows;/* HP_PROJ_ORTHO_ATOMIC: [n_hub*5] row of atwfc that is d */
+                          /* orbital m of Hubbard site s, at 5 s + m                */
 } hp_ground_state;
 
 /* Convergence controls (the paper's inputhp keywords conv_thr_chi, niter_max,
@@ -150,9 +160,14 @@ typedef struct hp_ctx hp_ctx;  /* opaque; owns every device buffer */
  * reuses: the LDA kernel f_xc(rho0), plane-wave/grid maps, kinetic energies,
  * the shift alpha = 2 (max - min) of the occupied energies (text after
  * Eq. 18), the projections <phi_k|u_vk> and the real-space occupied states.
- * Errors: HP_ERR_ARG (NULL, bad sizes, spin_factor != 2, xc unknown),
- * HP_ERR_SHAPE (sphere does not fit the grid, FFT size not 2^a 3^b 5^c),
- * HP_ERR_OOM, HP_ERR_HIP.  On success *out owns all device memory. */
+ * With HP_PROJ_ORTHO_ATOMIC the Hubbard projectors of every entry are first
+ * built from its atomic orbitals: the overlaps O_k on the matrix cores, O_k^-1/2
+ * on the host (Jacobi), the rows hub_rows of O_k^-1/2 applied on the matrix
+ * cores (Eq. 6); phi is then not read.
+ * Errors: HP_ERR_ARG (NULL, bad sizes, spin_factor != 2, xc unknown, bad
+ * projector settings), HP_ERR_SHAPE (sphere does not fit the grid, FFT size not
+ * 2^a 3^b 5^c), HP_ERR_SINGULAR (linearly dependent atomic orbitals), HP_ERR_OOM,
+ * HP_ERR_HIP.  On success *out owns all device memory. */
 hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **out);
 
 /* Self-consistent solution of Eq. 15 for a perturbation of Hubbard site

@@ -15,6 +15,7 @@
 #include <memory>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hp_internal.h"
@@ -314,10 +315,85 @@ void prof_harvest(hp_ctx *c) {
 hp_status check_kpoint(const hp_kpoint &k, int i, const hp_ground_state *gs) {
   if (k.struct_size != sizeof(hp_kpoint)) return fail(HP_ERR_ARG, "kpts[%d].struct_size mismatch", i);
   if (k.npw < 1) return fail(HP_ERR_ARG, "kpts[%d].npw = %d", i, k.npw);
-  if (!k.miller || !k.eps || !k.u || !k.beta || !k.phi) return fail(HP_ERR_ARG, "kpts[%d] has a NULL array", i);
+  if (!k.miller || !k.eps || !k.u || !k.beta) return fail(HP_ERR_ARG, "kpts[%d] has a NULL array", i);
+  if (gs->projectors == HP_PROJ_ATOMIC && !k.phi) return fail(HP_ERR_ARG, "kpts[%d].phi is NULL", i);
+  if (gs->projectors == HP_PROJ_ORTHO_ATOMIC && !k.atwfc) return fail(HP_ERR_ARG, "kpts[%d].atwfc is NULL", i);
   if (!(k.weight >= 0.0)) return fail(HP_ERR_ARG, "kpts[%d].weight < 0", i);
-  (void)gs;
   return HP_OK;
+}
+
+// Eigen-decomposition of a real symmetric n x n matrix by cyclic Jacobi rotations: on
+// return a is diagonal (the eigenvalues) and the columns of v are the eigenvectors.
+bool jacobi_eigen(int n, std::vector<double> &a, std::vector<double> &v) {
+  v.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) v[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) (i == j ? diag : off) += a[(size_t)i * n + j] * a[(size_t)i * n + j];
+    if (off <= 1e-30 * diag) return true;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[(size_t)p * n + q];
+        if (apq == 0.0) continue;
+        // rotation in the (p, q) plane that zeroes a_pq: t = tan of the angle, the smaller
+        // root of t^2 + 2 theta t - 1 = 0
+        const double theta = (a[(size_t)q * n + q] - a[(size_t)p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
+          a[(size_t)k * n + p] = cs * akp - sn * akq;
+          a[(size_t)k * n + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
+          a[(size_t)p * n + k] = cs * apk - sn * aqk;
+          a[(size_t)q * n + k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = v[(size_t)k * n + p], vkq = v[(size_t)k * n + q];
+          v[(size_t)k * n + p] = cs * vkp - sn * vkq;
+          v[(size_t)k * n + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+  return false;
+}
+
+// X = O^-1/2 of a Hermitian positive-definite n x n matrix (row-major complex), through
+// its real symmetric embedding [[Re O, -Im O], [Im O, Re O]], on which functions act
+// as on O.  Returns false if O is not positive definite to working precision.
+bool inv_sqrt_hermitian(int n, const std::complex<double> *O, std::complex<double> *X) {
+  const int m = 2 * n;
+  std::vector<double> a((size_t)m * m), v;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const std::complex<double> z = O[(size_t)i * n + j];
+      a[(size_t)i * m + j] = z.real();
+      a[(size_t)(i + n) * m + j + n] = z.real();
+      a[(size_t)i * m + j + n] = -z.imag();
+      a[(size_t)(i + n) * m + j] = z.imag();
+    }
+  if (!jacobi_eigen(m, a, v)) return false;
+  double lmax = 0.0, lmin = 1e300;
+  for (int i = 0; i < m; ++i) {
+    lmax = std::max(lmax, a[(size_t)i * m + i]);
+    lmin = std::min(lmin, a[(size_t)i * m + i]);
+  }
+  if (!(lmin > 1e-12 * lmax)) return false;
+  std::vector<double> f(m);
+  for (int i = 0; i < m; ++i) f[i] = 1.0 / std::sqrt(a[(size_t)i * m + i]);
+  for (int i = 0; i < n; ++i)  // F = V f(L) V^T; X = F[:n,:n] + i F[n:,:n]
+    for (int j = 0; j < n; ++j) {
+      double re = 0.0, im = 0.0;
+      for (int k = 0; k < m; ++k) {
+        re += v[(size_t)i * m + k] * f[k] * v[(size_t)j * m + k];
+        im += v[(size_t)(i + n) * m + k] * f[k] * v[(size_t)j * m + k];
+      }
+      X[(size_t)i * n + j] = {re, im};
+    }
+  return true;
 }
 
 // Host-side view of one k-entry after sorting plane waves into z-sticks.
@@ -1119,6 +1195,87 @@ void apply_call_params(hp_ctx *c, const hp_scf_params *p) {
   c->lowp_gemm = p->lowp_gemm;
 }
 
+// Ortho-atomic Hubbard projectors (Eq. 6) into c->d_phi: every entry's atomic orbitals in
+// the stick order, their overlaps O_k on the matrix cores (one launch over all entries),
+// O_k^-1/2 on the host (one thread per entry), then phi~_{5s+m} = sum_j (O^-1/2)_{j,r}
+// phi_j with r = hub_rows[5s+m] on the matrix cores (one launch).
+hp_status ortho_atomic_projectors(hp_ctx *c, const hp_ground_state *gs, const std::vector<Layout> &lay) {
+  const int na = gs->n_atwfc, nh5 = 5 * c->n_hub, ne = c->n_kpts;
+  const long at_stride = (long)na * c->ld;
+  std::vector<double2> h_at((size_t)ne * at_stride, make_double2(0.0, 0.0));
+  for (int i = 0; i < ne; ++i) {
+    const hp_kpoint &k = gs->kpts[i];
+    double2 *A = h_at.data() + (size_t)i * at_stride;
+    for (int p = 0; p < k.npw; ++p) {
+      const int q = lay[i].order[p];
+      for (int j = 0; j < na; ++j)
+        A[(size_t)j * c->ld + p] =
+            make_double2(k.atwfc[2 * ((size_t)j * k.npw + q)], k.atwfc[2 * ((size_t)j * k.npw + q) + 1]);
+    }
+  }
+  const int ns = std::max(1, std::min(8, c->npw_max / 512));
+  double2 *d_at = nullptr, *d_part = nullptr, *d_O = nullptr, *d_X = nullptr;
+  HPTRY(dalloc(&d_at, h_at.size()));
+  hp_status st = HP_OK;
+  auto cleanup = [&] {
+    (void)hipStreamSynchronize(c->stream);
+    for (double2 *ptr : {d_at, d_part, d_O, d_X})
+      if (ptr) (void)hipFree(ptr);
+  };
+  std::vector<std::complex<double>> O((size_t)ne * na * na), X((size_t)ne * na * nh5);
+  do {
+    if ((st = dalloc(&d_part, (size_t)ns * ne * na * na)) != HP_OK) break;
+    if ((st = dalloc(&d_O, (size_t)ne * na * na)) != HP_OK) break;
+    if ((st = dalloc(&d_X, (size_t)ne * na * nh5)) != HP_OK) break;
+    hipError_t e = hipMemcpyAsync(d_at, h_at.data(), sizeof(double2) * h_at.size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+      e = launch_zproj(c->d_kself, 0, ne, d_at, at_stride, 0, na, d_at, c->ld, na, c->d_npw, d_part, ns, nullptr, 0,
+                       c->stream);
+    if (e == hipSuccess) e = launch_zproj_reduce(ne, na, na, ns, d_part, nullptr, 1.0, d_O, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(O.data(), d_O, sizeof(double2) * O.size(), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      st = fail(HP_ERR_HIP, "ortho-atomic overlaps: %s", hipGetErrorString(e));
+      break;
+    }
+    // O^-1/2 per entry; keep the columns of the Hubbard rows: X[e][j][v] = (O^-1/2)_{j, hub_rows[v]}
+    std::vector<int> bad(ne, 0);
+    const int nthreads = std::max(1, std::min(ne, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nthreads; ++t)
+      pool.emplace_back([&, t] {
+        std::vector<std::complex<double>> full((size_t)na * na);
+        for (int i = t; i < ne; i += nthreads) {
+          if (!inv_sqrt_hermitian(na, O.data() + (size_t)i * na * na, full.data())) {
+            bad[i] = 1;
+            continue;
+          }
+          for (int j = 0; j < na; ++j)
+            for (int v = 0; v < nh5; ++v)
+              X[((size_t)i * na + j) * nh5 + v] = full[(size_t)j * na + gs->hub_rows[v]];
+        }
+      });
+    for (auto &th : pool) th.join();
+    for (int i = 0; i < ne; ++i)
+      if (bad[i]) {
+        st = fail(HP_ERR_SINGULAR, "kpts[%d]: atomic orbitals are linearly dependent", i);
+        break;
+      }
+    if (st != HP_OK) break;
+    e = hipMemcpyAsync(d_X, X.data(), sizeof(double2) * X.size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemsetAsync(c->d_phi, 0, sizeof(double2) * (size_t)ne * c->phi_stride, c->stream);
+    if (e == hipSuccess)
+      e = launch_zexpand(c->d_kself, 0, ne, d_at, at_stride, 0, na, d_X, (long)na * nh5, 1.0, c->d_phi, c->ld, nh5,
+                         c->d_npw, c->npw_max, nullptr, 1, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) st = fail(HP_ERR_HIP, "ortho-atomic projectors: %s", hipGetErrorString(e));
+  } while (false);
+  cleanup();
+  return st;
+}
+
 hp_status check_params(const hp_scf_params *p) {
   if (!p) return fail(HP_ERR_ARG, "params is NULL");
   if (p->struct_size != sizeof(hp_scf_params)) return fail(HP_ERR_ARG, "hp_scf_params.struct_size mismatch");
@@ -1271,8 +1428,19 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   if (gs->spin_factor != 2) return fail(HP_ERR_ARG, "spin_factor must be 2 (closed shell)");
   if (gs->xc != HP_XC_LDA_PZ81) return fail(HP_ERR_ARG, "unknown xc %d", gs->xc);
   if (gs->reserved != 0) return fail(HP_ERR_ARG, "reserved must be 0");
+  if (gs->projectors != HP_PROJ_ATOMIC && gs->projectors != HP_PROJ_ORTHO_ATOMIC)
+    return fail(HP_ERR_ARG, "unknown projectors %d", gs->projectors);
   if (!gs->v_loc || !gs->rho0 || !gs->d_kb || !gs->hub_tau || !gs->kpts) return fail(HP_ERR_ARG, "NULL array");
   if (gs->n_occ < 1 || gs->n_beta < 0 || gs->n_hub < 1) return fail(HP_ERR_ARG, "bad n_occ/n_beta/n_hub");
+  if (gs->projectors == HP_PROJ_ORTHO_ATOMIC) {
+    if (gs->n_atwfc < 5 * gs->n_hub || !gs->hub_rows) return fail(HP_ERR_ARG, "need n_atwfc >= 5 n_hub and hub_rows");
+    std::vector<char> seen(gs->n_atwfc, 0);
+    for (int v = 0; v < 5 * gs->n_hub; ++v) {
+      const int r = gs->hub_rows[v];
+      if (r < 0 || r >= gs->n_atwfc || seen[r]) return fail(HP_ERR_ARG, "hub_rows[%d] = %d invalid or repeated", v, r);
+      seen[r] = 1;
+    }
+  }
   if (gs->n_mesh < 1 || gs->n_kpts < gs->n_mesh) return fail(HP_ERR_ARG, "bad n_mesh/n_kpts");
   std::vector<int> rad[3];
   for (int d = 0; d < 3; ++d) {
@@ -1477,9 +1645,10 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
         T[(size_t)(c->n_beta + v) * c->ld + p] = val;
         d += c->alpha * (val.x * val.x + val.y * val.y);
       }
-      for (int m = 0; m < 5 * c->n_hub; ++m)
-        F[(size_t)m * c->ld + p] =
-            make_double2(k.phi[2 * ((size_t)m * k.npw + q)], k.phi[2 * ((size_t)m * k.npw + q) + 1]);
+      if (gs->projectors == HP_PROJ_ATOMIC)
+        for (int m = 0; m < 5 * c->n_hub; ++m)
+          F[(size_t)m * c->ld + p] =
+              make_double2(k.phi[2 * ((size_t)m * k.npw + q)], k.phi[2 * ((size_t)m * k.npw + q) + 1]);
       dg[p] = d;
     }
     for (int p = k.npw; p < c->ld; ++p) dg[p] = 1.0;
@@ -1588,6 +1757,8 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   HPTRY(c->alloc(&c->ptrs, 2 * kNmixMax + 2));
   HPTRY(c->alloc(&c->dn, (size_t)25 * c->n_hub));
   HPTRY(c->alloc(&c->d_q, 3));
+
+  if (gs->projectors == HP_PROJ_ORTHO_ATOMIC) HPTRY(ortho_atomic_projectors(c.get(), gs, lay));
 
   // A_k[m][v] = <phi_{m,k}|u_vk> for every entry (Eq. 13's ground-state factor)
   HPTRY(c->alloc(&c->d_A, (size_t)c->n_kpts * 5 * c->n_hub * nb));

@@ -23,6 +23,7 @@ HP_ERR_ARG, HP_ERR_SHAPE, HP_ERR_HIP, HP_ERR_OOM, HP_ERR_STATE, HP_ERR_SINGULAR,
 HP_FP64, HP_MIXED = 0, 1
 HP_GEMM_FP32, HP_GEMM_BF16, HP_GEMM_BF16_PV32 = 0, 1, 2
 HP_XC_LDA_PZ81 = 1
+HP_PROJ_ATOMIC, HP_PROJ_ORTHO_ATOMIC = 0, 1
 
 
 class HpError(RuntimeError):
@@ -48,7 +49,8 @@ _ip = C.POINTER(C.c_int32)
 
 class HpKpoint(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("k_frac", C.c_double * 3), ("weight", C.c_double),
-                ("npw", C.c_int32), ("miller", _ip), ("eps", _dp), ("u", _dp), ("beta", _dp), ("phi", _dp)]
+                ("npw", C.c_int32), ("miller", _ip), ("eps", _dp), ("u", _dp), ("beta", _dp), ("phi", _dp),
+                ("atwfc", _dp)]
 
 
 class HpGroundState(C.Structure):
@@ -56,7 +58,7 @@ class HpGroundState(C.Structure):
                 ("v_loc", _dp), ("rho0", _dp), ("n_occ", C.c_int32), ("n_beta", C.c_int32), ("n_hub", C.c_int32),
                 ("d_kb", _dp), ("hub_tau", _dp), ("spin_factor", C.c_int32), ("n_mesh", C.c_int32),
                 ("n_kpts", C.c_int32), ("kpts", C.POINTER(HpKpoint)), ("xc", C.c_int32), ("reserved", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("projectors", C.c_int32), ("n_atwfc", C.c_int32), ("hub_rows", _ip)]
 
 
 class HpScfParams(C.Structure):
@@ -192,20 +194,36 @@ class Context:
             pass
 
 
-def hp_ground_state_load(gs, stream: Optional[int] = None) -> Context:
+def hp_ground_state_load(gs, stream: Optional[int] = None, atwfc: Optional[Sequence[np.ndarray]] = None,
+                         hub_rows: Optional[np.ndarray] = None) -> Context:
     """gs: an object with cell, fft, vloc, rho0, n_occ, d_kb, hub_tau, n_hub, n_mesh, kpts
-    (each k-entry with k_frac, weight, miller, eps, u, beta, phi)."""
+    (each k-entry with k_frac, weight, miller, eps, u, beta, phi).  With atwfc (one
+    (n_atwfc, npw) complex array per k-entry: every atomic orbital) and hub_rows (the row of
+    d orbital m of Hubbard site s at 5 s + m) the library builds ortho-atomic projectors and
+    the entries' phi are not read."""
+    ortho = atwfc is not None
+    if ortho and (hub_rows is None or len(atwfc) != len(gs.kpts)):
+        raise ValueError("ortho-atomic projectors need one atwfc table per k-entry and hub_rows")
     keep = []
     kp = (HpKpoint * len(gs.kpts))()
+    n_atwfc = 0
     for i, e in enumerate(gs.kpts):
         mil = np.ascontiguousarray(e.miller, dtype=np.int32)
         eps = _f64(e.eps)
         u = _c128_as_f64(e.u)
         beta = _c128_as_f64(e.beta)
-        phi = _c128_as_f64(e.phi)
-        keep += [mil, eps, u, beta, phi]
+        phi = None if ortho else _c128_as_f64(e.phi)
+        at = None
+        if ortho:
+            a = np.asarray(atwfc[i])
+            if a.ndim != 2 or a.shape[1] != mil.shape[0] or (i and a.shape[0] != n_atwfc):
+                raise ValueError(f"atwfc[{i}] has shape {a.shape}, entry {i} has {mil.shape[0]} plane waves")
+            n_atwfc = a.shape[0]
+            at = _c128_as_f64(a)
+        keep += [mil, eps, u, beta, phi, at]
         kp[i] = HpKpoint(C.sizeof(HpKpoint), (C.c_double * 3)(*[float(x) for x in e.k_frac]), float(e.weight),
-                         int(mil.shape[0]), _ptr(mil, _ip), _ptr(eps), _ptr(u), _ptr(beta), _ptr(phi))
+                         int(mil.shape[0]), _ptr(mil, _ip), _ptr(eps), _ptr(u), _ptr(beta),
+                         _ptr(phi) if phi is not None else None, _ptr(at) if at is not None else None)
     vloc = _f64(gs.vloc)
     rho0 = _f64(gs.rho0)
     nr = int(np.prod([int(x) for x in gs.fft]))
@@ -213,7 +231,8 @@ def hp_ground_state_load(gs, stream: Optional[int] = None) -> Context:
         raise ValueError(f"v_loc/rho0 hold {vloc.size}/{rho0.size} values, the grid {tuple(gs.fft)} has {nr}")
     dkb = _f64(gs.d_kb)
     htau = _f64(gs.hub_tau)
-    keep += [vloc, rho0, dkb, htau]
+    hrows = np.ascontiguousarray(hub_rows, dtype=np.int32) if ortho else None
+    keep += [vloc, rho0, dkb, htau, hrows]
     cell = ((C.c_double * 3) * 3)(*[(C.c_double * 3)(*[float(x) for x in row]) for row in np.asarray(gs.cell)])
     g = HpGroundState()
     g.struct_size = C.sizeof(HpGroundState)
@@ -233,6 +252,9 @@ def hp_ground_state_load(gs, stream: Optional[int] = None) -> Context:
     g.xc = HP_XC_LDA_PZ81
     g.reserved = 0
     g.stream = C.c_void_p(stream) if stream else None
+    g.projectors = HP_PROJ_ORTHO_ATOMIC if ortho else HP_PROJ_ATOMIC
+    g.n_atwfc = n_atwfc
+    g.hub_rows = _ptr(hrows, _ip) if ortho else None
     h = C.c_void_p()
     _check(_lib.hp_ground_state_load(C.byref(g), C.byref(h)), allow_warn=False)
     del keep

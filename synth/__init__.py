@@ -3,12 +3,15 @@
 This package builds the ground-state data that both the CPU oracle and the
 GPU library consume: a periodic cell, a local potential on the FFT grid,
 Kleinman-Bylander projectors, non-orthogonalized atomic d orbitals (the
-Hubbard projectors), plane-wave spheres per k-point and the occupied
+Hubbard projectors), the full atomic orbital set (s, p and d) whose Loewdin
+orthogonalization gives ortho-atomic projectors, plane-wave spheres per k-point and the occupied
 eigenpairs of the unperturbed Hamiltonian.  It holds none of the linear
 response arithmetic: no Sternheimer solve, no response density, no
 occupation response.  The eigenpairs are computed with a Hamiltonian apply
 written here, independently of the oracle and of the GPU kernels.
 """
-from .system import SystemSpec, GroundState, KEntry, build_ground_state, spec_by_name, SPECS
+from .system import (SystemSpec, GroundState, KEntry, build_ground_state, spec_by_name, SPECS, atomic_orbitals,
+                     atomic_orbital_tables)
 
-__all__ = ["SystemSpec", "GroundState", "KEntry", "build_ground_state", "spec_by_name", "SPECS"]
+__all__ = ["SystemSpec", "GroundState", "KEntry", "build_ground_state", "spec_by_name", "SPECS", "atomic_orbitals",
+           "atomic_orbital_tables"]

@@ -377,6 +377,12 @@ def atomic_orbitals(gs, k_frac: np.ndarray, miller: np.ndarray):
     return np.array(rows, dtype=np.complex128) / math.sqrt(omega), hub_rows
 
 
+def atomic_orbital_tables(gs):
+    """atomic_orbitals of every k-entry of gs: ([rows of entry e], hub_rows)."""
+    tabs = [atomic_orbitals(gs, e.k_frac, e.miller) for e in gs.kpts]
+    return [t[0] for t in tabs], tabs[0][1]
+
+
 def _min_image_dist(cell, f1, f2):
     d = f1 - f2
     d -= np.round(d)

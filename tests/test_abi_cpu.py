@@ -78,3 +78,24 @@ def test_load_validation_runs_before_device(hp):
 
 def test_last_error_is_a_string(hp):
     assert isinstance(hp.hp_last_error(), str)
+
+
+def test_ortho_atomic_load_validation_runs_before_device(hp):
+    import synth
+    from conftest import ground_state
+    gs = ground_state("sc1_gamma")
+    atw, hub_rows = synth.atomic_orbital_tables(gs)
+    bad_rows = hub_rows.copy()
+    bad_rows[1] = bad_rows[0]          # repeated row
+    out_of_range = hub_rows.copy()
+    out_of_range[0] = atw[0].shape[0]  # past the last orbital
+    for rows in (bad_rows, out_of_range, -hub_rows - 1):
+        with pytest.raises(hp.HpError) as e:
+            hp.hp_ground_state_load(gs, atwfc=atw, hub_rows=rows)
+        assert e.value.status == hp.HP_ERR_ARG
+    short = [a[:3] for a in atw]       # fewer orbitals than Hubbard d rows
+    with pytest.raises(hp.HpError) as e:
+        hp.hp_ground_state_load(gs, atwfc=short, hub_rows=np.arange(5 * gs.n_hub) % 3)
+    assert e.value.status == hp.HP_ERR_ARG
+    with pytest.raises(ValueError):    # a table whose plane-wave count is not the entry's
+        hp.hp_ground_state_load(gs, atwfc=[a[:, :-1] for a in atw], hub_rows=hub_rows)

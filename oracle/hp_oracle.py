@@ -10,9 +10,15 @@ are listed in the design notes of the repository):
 * the local potential acts on the grid: (V c)(G) = fftn(V psi)/N_r at G, which
   equals the matrix V_hat[(m - m') mod N] with V_hat = fftn(V)/N_r;
 * spin-unpolarized closed shell: occupations and densities carry a factor 2;
+* collinear spin-polarized ground states (nspin = 2; the paper's formalism is
+  written for spin-resolved states, Eqs. 3, 10-15): the k-entries come in two
+  blocks (spin up, then spin down, the same k list in each), every state holds one
+  electron, V_loc and rho0 carry a leading spin index, the response density is
+  spin-resolved and the Hxc response uses the 2 x 2 LSDA kernel; the perturbation of
+  Eq. 16 acts on both spins and the occupation response is summed over spins;
 * time reversal folds the -q partner into the +q term (paper, text after
   Eq. 14), giving the factor 4 = 2 (spin) x 2 (time reversal) in the response
-  density and the two-term form of Eq. 13.
+  density (2 per spin channel when polarized) and the two-term form of Eq. 13.
 """
 from __future__ import annotations
 
@@ -84,7 +90,20 @@ class Oracle:
         self.n_hub = int(gs.n_hub)
         self.kpts = gs.kpts
         self.n_mesh = int(gs.n_mesh)
-        self.fxc = pz81.f_xc(gs.rho0)
+        self.nspin = int(getattr(gs, "nspin", 1))
+        if self.nspin not in (1, 2) or len(self.kpts) % self.nspin:
+            raise ValueError("nspin must be 1 or 2, with one block of k-entries per spin")
+        self.nk_spin = len(self.kpts) // self.nspin          # entries per spin block
+        self.occ = 2.0 / self.nspin                            # electrons per state
+        # mesh entries of every spin (entry index = spin * nk_spin + mesh index)
+        self.mesh = [s * self.nk_spin + i for s in range(self.nspin) for i in range(self.n_mesh)]
+        if self.nspin == 1:
+            self.vloc = np.asarray(gs.vloc, dtype=np.float64)
+            self.fxc = pz81.f_xc(gs.rho0)
+        else:
+            self.vloc = np.asarray(gs.vloc, dtype=np.float64).reshape((2,) + self.fft)
+            rho = np.asarray(gs.rho0, dtype=np.float64).reshape((2,) + self.fft)
+            self.fxc = pz81.f_xc_spin(rho[0], rho[1])          # (2, 2) + grid
         # alpha = 2 (max - min) over the occupied energies of every loaded entry
         # (paper, text after Eq. 18); floor 0.01 Ha.
         emax = max(float(e.eps.max()) for e in self.kpts)
@@ -95,6 +114,13 @@ class Oracle:
         self._cache_limit = cache_limit_bytes
         self._dense: Dict[int, np.ndarray] = {}
         self._kin: Dict[int, np.ndarray] = {}
+
+    def spin_of(self, ie: int) -> int:
+        return ie // self.nk_spin
+
+    def v_of(self, ie: int) -> np.ndarray:
+        """Local potential seen by entry ie (its spin's)."""
+        return self.vloc if self.nspin == 1 else self.vloc[self.spin_of(ie)]
 
     # ------------------------------------------------------------------ grids
     def grid_index(self, ie: int, g0=(0, 0, 0)) -> np.ndarray:
@@ -138,7 +164,7 @@ class Oracle:
         e = self.kpts[ie]
         idx = self.grid_index(ie)
         out = self.kinetic(ie)[None, :] * X
-        out = out + self.to_recip(self.to_real(X, idx) * self.gs.vloc[None], idx)
+        out = out + self.to_recip(self.to_real(X, idx) * self.v_of(ie)[None], idx)
         proj = X @ e.beta.conj().T            # <beta_i|x> for every row
         out = out + (proj * self.gs.d_kb[None, :]) @ e.beta
         return out
@@ -148,7 +174,7 @@ class Oracle:
         if ie in self._dense:
             return self._dense[ie]
         e = self.kpts[ie]
-        vhat = np.fft.fftn(self.gs.vloc) / self.nr
+        vhat = np.fft.fftn(self.v_of(ie)) / self.nr
         dm = (e.miller[:, None, :] - e.miller[None, :, :]) % np.array(self.fft)
         H = vhat[dm[..., 0], dm[..., 1], dm[..., 2]].astype(np.complex128)
         H += np.diag(self.kinetic(ie))
@@ -158,9 +184,11 @@ class Oracle:
 
     # ------------------------------------------------------------ q mapping
     def kq_entry(self, ik: int, q) -> Tuple[int, np.ndarray]:
-        """Entry j holding k+q and the integer shift g0 with k + q = k_j + g0."""
+        """Entry j (of the same spin) holding k+q and the integer shift g0 with k + q = k_j + g0."""
         kq = self.kpts[ik].k_frac + np.asarray(q, dtype=np.float64)
-        for j, e in enumerate(self.kpts):
+        j0 = self.spin_of(ik) * self.nk_spin
+        for j in range(j0, j0 + self.nk_spin):
+            e = self.kpts[j]
             d = kq - e.k_frac
             if np.all(np.abs(d - np.round(d)) < 1e-9):
                 return j, np.round(d).astype(np.int64)
@@ -173,8 +201,9 @@ class Oracle:
         j, g0 = self.kq_entry(ik, q)
         ek, ej = self.kpts[ik], self.kpts[j]
         b = np.zeros((self.n_occ, ej.npw), dtype=np.complex128)
-        if dv is not None:
-            b += self.to_recip(dv[None] * self.psi_r(ik), self.grid_index(j, g0))
+        if dv is not None:  # dv: the grid field, (2,) + grid when spin-polarized
+            dvs = dv if self.nspin == 1 else dv[self.spin_of(ik)]
+            b += self.to_recip(dvs[None] * self.psi_r(ik), self.grid_index(j, g0))
         sl = slice(5 * site, 5 * site + 5)
         A = self.phi[ik][sl].conj() @ ek.u.T    # A[m, v] = <phi_{m,k}|u_vk>
         b += A.T @ self.phi[j][sl]              # sum_m |phi_{m,k+q}> A[m, v]
@@ -207,7 +236,7 @@ class Oracle:
         # Jacobi preconditioner: the exact diagonal of the (positive definite) operator
         j, _ = self.kq_entry(ik, q)
         ej = self.kpts[j]
-        vhat0 = float(np.mean(self.gs.vloc))
+        vhat0 = float(np.mean(self.v_of(j)))
         diag = (self.kinetic(j) + vhat0 + (np.abs(ej.beta) ** 2 * self.gs.d_kb[:, None]).sum(0)
                 + a * (np.abs(ej.u) ** 2).sum(0))
         dinv = 1.0 / (diag[None, :] - self.kpts[ik].eps[:, None])
@@ -239,12 +268,13 @@ class Oracle:
 
     # ------------------------------------------------ response density and Hxc
     def drho_k(self, ik: int, q, du: np.ndarray) -> np.ndarray:
-        """Contribution of mesh point ik to the response density at q:
-        (4 w_k / Omega) sum_v conj(psi_vk(r)) dpsi_vk+q(r)  (spin x time reversal)."""
+        """Contribution of mesh entry ik to the response density at q (of ik's spin):
+        (2 occ w_k / Omega) sum_v conj(psi_vk(r)) dpsi_vk+q(r), occ electrons per state
+        times 2 for time reversal."""
         j, g0 = self.kq_entry(ik, q)
         dpsi = self.to_real(du, self.grid_index(j, g0))
         w = self.kpts[ik].weight
-        return (4.0 * w / self.omega) * np.einsum("vxyz,vxyz->xyz", self.psi_r(ik).conj(), dpsi)
+        return (2.0 * self.occ * w / self.omega) * np.einsum("vxyz,vxyz->xyz", self.psi_r(ik).conj(), dpsi)
 
     def gvec_q(self, q) -> np.ndarray:
         """|q+G|^2 over the FFT grid (G from the centred integer frequencies)."""
@@ -254,19 +284,25 @@ class Oracle:
         return np.einsum("...i,...i->...", p, p)
 
     def dv_hxc(self, drho: np.ndarray, q, hxc: bool = True) -> np.ndarray:
-        """Response Hxc potential: Hartree 4 pi drho(G)/|q+G|^2 (zero at q+G = 0)
-        plus the local LDA kernel f_xc(r) drho(r)."""
+        """Response Hxc potential: Hartree 4 pi drho(G)/|q+G|^2 (zero at q+G = 0) of the
+        total response density plus the local LDA kernel, f_xc(r) drho(r), or per spin
+        sum_t f_xc^{st}(r) drho_t(r) when spin-polarized (drho then (2,) + grid)."""
         if not hxc:
             return np.zeros_like(drho)
         g2 = self.gvec_q(q)
-        dg = np.fft.fftn(drho) / self.nr
+        tot = drho if self.nspin == 1 else drho.sum(axis=0)
+        dg = np.fft.fftn(tot) / self.nr
         vh = np.where(g2 > 1e-12, FOUR_PI * dg / np.where(g2 > 1e-12, g2, 1.0), 0.0)
-        return np.fft.ifftn(vh) * self.nr + self.fxc * drho
+        vh = np.fft.ifftn(vh) * self.nr
+        if self.nspin == 1:
+            return vh + self.fxc * drho
+        return np.stack([vh + self.fxc[s, 0] * drho[0] + self.fxc[s, 1] * drho[1] for s in range(2)])
 
     # ----------------------------------------------------- occupations, Eq. 13
     def dn_k(self, ik: int, q, du: np.ndarray) -> np.ndarray:
-        """Contribution of mesh point ik to Delta_q n^s_{m1 m2} for every site s:
-        2 w_k sum_v [<u|phi_{m2,k}><phi_{m1,k+q}|du> + <u|phi_{m1,k}><phi_{m2,k+q}|du>]."""
+        """Contribution of mesh entry ik to Delta_q n^s_{m1 m2} for every site s (summed over
+        spins by the caller): occ w_k sum_v [<u|phi_{m2,k}><phi_{m1,k+q}|du>
+        + <u|phi_{m1,k}><phi_{m2,k+q}|du>]."""
         j, _ = self.kq_entry(ik, q)
         ek, ej = self.kpts[ik], self.kpts[j]
         A = self.phi[ik].conj() @ ek.u.T         # (n_hub*5, n_occ)
@@ -275,18 +311,19 @@ class Oracle:
         for s in range(self.n_hub):
             sl = slice(5 * s, 5 * s + 5)
             T = B[sl] @ A[sl].conj().T           # T[m1, m2] = sum_v B[m1,v] conj(A[m2,v])
-            out[s] = 2.0 * ek.weight * (T + T.T)
+            out[s] = self.occ * ek.weight * (T + T.T)
         return out
 
     def occupations(self) -> np.ndarray:
-        """Ground-state n^s_{m1 m2} = (2/N_k) sum_kv <u|phi_{m2}><phi_{m1}|u> (Eq. 3, on-site, spin 2)."""
+        """Ground-state n^s_{m1 m2} = (occ/N_k) sum_kv <u|phi_{m2}><phi_{m1}|u> (Eq. 3, on-site,
+        summed over spins)."""
         out = np.zeros((self.n_hub, 5, 5), dtype=np.complex128)
-        for ik in range(self.n_mesh):
+        for ik in self.mesh:
             e = self.kpts[ik]
             A = self.phi[ik].conj() @ e.u.T
             for s in range(self.n_hub):
                 sl = slice(5 * s, 5 * s + 5)
-                out[s] += 2.0 * e.weight * A[sl] @ A[sl].conj().T
+                out[s] += self.occ * e.weight * A[sl] @ A[sl].conj().T
         return out
 
     # ------------------------------------------------------------ SCF loop
@@ -296,8 +333,9 @@ class Oracle:
         response not yet built up: the chi0 column, paper's linear-response
         calculation section) and dn (self-consistent), each (n_hub, 5, 5)."""
         q = np.asarray(q, dtype=np.float64)
-        dv_in = np.zeros(self.fft, dtype=np.complex128)
-        du = [None] * self.n_mesh
+        shape = self.fft if self.nspin == 1 else (2,) + self.fft
+        dv_in = np.zeros(shape, dtype=np.complex128)
+        du = {}
         hist_df: List[np.ndarray] = []
         hist_dv: List[np.ndarray] = []
         prev = None
@@ -307,13 +345,16 @@ class Oracle:
         it_total = 0
         converged = False
         for it in range(1, p.niter_max + 1):
-            drho = np.zeros(self.fft, dtype=np.complex128)
+            drho = np.zeros(shape, dtype=np.complex128)
             dn = np.zeros((self.n_hub, 5, 5), dtype=np.complex128)
-            for ik in range(self.n_mesh):
+            for ik in self.mesh:
                 b = self.rhs(ik, q, site, dv_in if it > 1 else None)
-                du[ik], nit = self.solve(ik, q, b, du[ik], p)
+                du[ik], nit = self.solve(ik, q, b, du.get(ik), p)
                 it_total += nit
-                drho += self.drho_k(ik, q, du[ik])
+                if self.nspin == 1:
+                    drho += self.drho_k(ik, q, du[ik])
+                else:
+                    drho[self.spin_of(ik)] += self.drho_k(ik, q, du[ik])
                 dn += self.dn_k(ik, q, du[ik])
             chi = np.einsum("smm->s", dn)
             if it == 1:
@@ -391,43 +432,52 @@ class Oracle:
     def fd_occupation_response(self, site: int, lam: float, hxc: bool = True, tol: float = 1e-13,
                                maxit: int = 200) -> np.ndarray:
         """Central finite difference [n^I(+lam) - n^I(-lam)] / 2 lam of the self-consistent
-        ground state under lam sum_m |phi^J_m><phi^J_m| (Eq. 7 by its definition).  Gamma-only
-        systems; with hxc=False the Hxc potential is frozen (chi0)."""
-        assert len(self.kpts) == 1 and np.allclose(self.kpts[0].k_frac, 0.0)
+        ground state under lam sum_m |phi^J_m><phi^J_m| on every spin (Eq. 7 by its
+        definition).  Gamma-only systems; with hxc=False the Hxc potential is frozen (chi0)."""
+        assert self.nk_spin == 1 and np.allclose(self.kpts[0].k_frac, 0.0)
         res = []
         for sgn in (+1.0, -1.0):
             res.append(self._perturbed_ground_state(site, sgn * lam, hxc, tol, maxit))
         return (res[0] - res[1]) / (2.0 * lam)
 
     def _perturbed_ground_state(self, site, lam, hxc, tol, maxit):
-        e = self.kpts[0]
-        H0 = self.h_dense(0)
+        ns = self.nspin
         sl = slice(5 * site, 5 * site + 5)
         Pj = self.phi[0][sl].T @ self.phi[0][sl].conj()   # sum_m |phi_m><phi_m|
-        rho0 = self.gs.rho0
-        vxc0 = pz81.v_xc(rho0)
+        rho0 = np.asarray(self.gs.rho0, dtype=np.float64).reshape((ns,) + self.fft)
+
+        def vxc(r):  # per-spin xc potential of spin densities r, (ns,) + grid
+            return pz81.v_xc(r[0])[None] if ns == 1 else pz81.v_xc_spin(r[0], r[1])
+
+        vxc0 = vxc(rho0)
         g2 = self.gvec_q(np.zeros(3))
+        e = self.kpts[0]
         idx = self.grid_index(0)
+        dm = (e.miller[:, None, :] - e.miller[None, :, :]) % np.array(self.fft)
         rho_in = rho0.copy()
         hist_r, hist_f = [], []
         for it in range(maxit):
             if hxc:
-                dg = np.fft.fftn(rho_in - rho0) / self.nr
+                dg = np.fft.fftn(rho_in.sum(0) - rho0.sum(0)) / self.nr
                 vh = np.where(g2 > 1e-12, FOUR_PI * dg / np.where(g2 > 1e-12, g2, 1.0), 0.0)
-                v = (np.fft.ifftn(vh) * self.nr).real + pz81.v_xc(rho_in) - vxc0
+                v = (np.fft.ifftn(vh) * self.nr).real[None] + vxc(rho_in) - vxc0
             else:
-                v = np.zeros(self.fft)
-            vhat = np.fft.fftn(v) / self.nr
-            dm = (e.miller[:, None, :] - e.miller[None, :, :]) % np.array(self.fft)
-            H = H0 + lam * Pj + vhat[dm[..., 0], dm[..., 1], dm[..., 2]]
-            w, V = np.linalg.eigh(0.5 * (H + H.conj().T))
-            U = V[:, :self.n_occ].T
-            psi = self.to_real(U, idx)
-            rho_out = 2.0 * np.sum(np.abs(psi) ** 2, axis=0) / self.omega
+                v = np.zeros((ns,) + self.fft)
+            rho_out = np.zeros_like(rho_in)
+            Us = []
+            for sp in range(ns):
+                ie = sp * self.nk_spin
+                vhat = np.fft.fftn(v[sp]) / self.nr
+                H = self.h_dense(ie) + lam * Pj + vhat[dm[..., 0], dm[..., 1], dm[..., 2]]
+                w, V = np.linalg.eigh(0.5 * (H + H.conj().T))
+                U = V[:, :self.n_occ].T
+                Us.append(U)
+                psi = self.to_real(U, idx)
+                rho_out[sp] = self.occ * np.sum(np.abs(psi) ** 2, axis=0) / self.omega
             f = rho_out - rho_in
             if not hxc or np.abs(f).max() < tol:
                 break
-            # Anderson mixing of the density
+            # Anderson mixing of the (spin) densities
             hist_r.append(rho_in.copy())
             hist_f.append(f.copy())
             if len(hist_r) > 6:
@@ -447,8 +497,10 @@ class Oracle:
                 rho_in = rho_in + 0.3 * f
         else:
             raise RuntimeError("perturbed ground state did not converge")
-        A = self.phi[0].conj() @ U.T
-        n = np.array([2.0 * np.sum(np.abs(A[5 * s:5 * s + 5]) ** 2) for s in range(self.n_hub)])
+        n = np.zeros(self.n_hub)
+        for U in Us:
+            A = self.phi[0].conj() @ U.T
+            n += np.array([self.occ * np.sum(np.abs(A[5 * s:5 * s + 5]) ** 2) for s in range(self.n_hub)])
         return n
 
 

@@ -4,7 +4,9 @@ This package builds the ground-state data that both the CPU oracle and the
 GPU library consume: a periodic cell, a local potential on the FFT grid,
 Kleinman-Bylander projectors, non-orthogonalized atomic d orbitals (the
 Hubbard projectors), the full atomic orbital set (s, p and d) whose Loewdin
-orthogonalization gives ortho-atomic projectors, plane-wave spheres per k-point and the occupied
+orthogonalization gives ortho-atomic projectors, optionally a collinear
+spin-polarized ground state (an exchange field on the d sites, one block of
+k-entries per spin), plane-wave spheres per k-point and the occupied
 eigenpairs of the unperturbed Hamiltonian.  It holds none of the linear
 response arithmetic: no Sternheimer solve, no response density, no
 occupation response.  The eigenpairs are computed with a Hamiltonian apply

@@ -30,7 +30,7 @@ def save(gs: S.GroundState) -> str:
     p = _path(gs.spec.name)
     arrs = {"vloc": gs.vloc, "rho0": gs.rho0, "tau": gs.tau, "hub_atoms": gs.hub_atoms, "hub_zeta": gs.hub_zeta,
             "kb_s": gs.kb_s, "kb_d": gs.kb_d, "d_kb": gs.d_kb, "cell": gs.cell,
-            "meta": np.array([gs.seed_used, gs.n_mesh, len(gs.kpts), gs.gap], dtype=np.float64)}
+            "meta": np.array([gs.seed_used, gs.n_mesh, len(gs.kpts), gs.gap, gs.nspin], dtype=np.float64)}
     for i, e in enumerate(gs.kpts):
         arrs[f"k{i}_kfrac"] = e.k_frac
         arrs[f"k{i}_scal"] = np.array([e.weight, e.ecut, e.eps_next, e.resid])
@@ -51,6 +51,7 @@ def load(name: str):
     z = np.load(p, allow_pickle=False)
     meta = z["meta"]
     seed, n_mesh, nk, gap = int(meta[0]), int(meta[1]), int(meta[2]), float(meta[3])
+    nspin = int(meta[4]) if meta.shape[0] > 4 else 1
     shell = S._Shell(z["cell"], z["tau"], z["hub_atoms"], z["hub_zeta"], z["kb_s"], z["kb_d"])
     kpts = []
     for i in range(nk):
@@ -63,7 +64,8 @@ def load(name: str):
     return S.GroundState(spec=spec, seed_used=seed, cell=z["cell"], fft=tuple(spec.fft), vloc=z["vloc"],
                          rho0=z["rho0"], tau=z["tau"], hub_atoms=z["hub_atoms"], hub_zeta=z["hub_zeta"],
                          kb_s=z["kb_s"], kb_d=z["kb_d"], d_kb=z["d_kb"], n_occ=spec.n_occ, kmesh=tuple(spec.kmesh),
-                         qmesh=tuple(spec.qmesh), kpts=kpts, n_mesh=n_mesh, gap=gap)
+                         qmesh=tuple(spec.qmesh), kpts=kpts, n_mesh=n_mesh, gap=gap,
+                         spin_factor=2 if nspin == 1 else 1, nspin=nspin)
 
 
 def get(name: str, device: str = "auto", verbose: bool = None):

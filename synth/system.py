@@ -65,6 +65,12 @@ class SystemSpec:
     kb_s: Tuple[float, float] = (0.5, 1.0)     # KB Gaussian widths (bohr)
     kb_d: Tuple[float, float] = (0.5, 2.0)     # KB strengths (Ha)
     max_attempts: int = 40
+    # collinear spin polarization: V_up/dn = V_loc -/+ spin_field sum_I sign_I g_I(r), with
+    # g_I a periodic Gaussian of width spin_width on Hubbard site I and sign_I from
+    # spin_signs (default alternating +1, -1, ...: antiferromagnetic order); 0 = unpolarized
+    spin_field: float = 0.0
+    spin_width: float = 0.8
+    spin_signs: Optional[Tuple[int, ...]] = None
 
 
 SPECS = {}
@@ -113,6 +119,13 @@ OLIVINE_K442 = _reg(replace(OLIVINE, name="olivine28_k442", cfg_id=1, kmesh=(4, 
 OLIVINE_SC = _reg(replace(OLIVINE, name="olivine56_sc211", cfg_id=4, cell=(39.2, 11.3, 8.9),
                           n_atoms=56, n_hub=8, fft=(144, 45, 40), ecut=22.45, n_occ=224,
                           base="olivine28", rep=(2, 1, 1)))
+# Collinear spin-polarized variants (the same atoms and wells; an exchange field of
+# 0.15 Ha on the d sites): one site (polarized), two sites and the olivine-shaped cell
+# with antiferromagnetic order (+, -, +, - over the d sites; equal electron counts per
+# spin, zero net moment).
+SC1_FM = _reg(replace(SC1, name="sc1_gamma_spin", spin_field=0.15, spin_signs=(1,)))
+DUO_AFM = _reg(replace(DUO, name="duo_k221_afm", spin_field=0.15))
+OLIVINE_AFM = _reg(replace(OLIVINE, name="olivine28_afm", spin_field=0.15))
 
 
 def spec_by_name(name: str) -> SystemSpec:
@@ -163,6 +176,8 @@ class GroundState:
     n_mesh: int
     spin_factor: int = 2
     gap: float = float("nan")
+    nspin: int = 1              # 2: kpts holds a spin-up then a spin-down block of the same k
+                                # list, vloc/rho0 are (2, N1, N2, N3), one electron per state
 
     @property
     def n_hub(self) -> int:
@@ -182,7 +197,7 @@ class GroundState:
 
     @property
     def n_electrons(self) -> int:
-        return self.spin_factor * self.n_occ
+        return self.spin_factor * self.n_occ * self.nspin
 
     def qpoints(self) -> np.ndarray:
         return mesh_points(self.qmesh)
@@ -458,6 +473,28 @@ def _vloc_grid(spec: SystemSpec, at: _Atoms, rn) -> np.ndarray:
             v -= d * np.einsum("i,j,k->ijk", f[0], f[1], f[2])
     v += rn.uniform(-spec.noise, spec.noise, spec.fft)
     return v
+
+
+def _spin_field_grid(spec: SystemSpec, at: _Atoms) -> np.ndarray:
+    """sum_I sign_I exp(-|r - tau_I|^2 / 2 w^2) over the Hubbard sites (periodic images)."""
+    L = np.diag(at.cell)
+    w = spec.spin_width
+    signs = spec.spin_signs or tuple(1 if i % 2 == 0 else -1 for i in range(len(at.hub_atoms)))
+    axes = [np.arange(n) / n * L[i] for i, n in enumerate(spec.fft)]
+    out = np.zeros(spec.fft)
+    for sgn, a in zip(signs, at.hub_atoms):
+        c = at.tau[a]
+        f = []
+        for i in range(3):
+            nimg = int(math.ceil(8 * w / L[i])) + 1
+            acc = np.zeros(spec.fft[i])
+            for n in range(-nimg, nimg + 1):
+                dx = axes[i] - c[i] - n * L[i]
+                m = np.abs(dx) < 8 * w
+                acc[m] += np.exp(-dx[m] ** 2 / (2 * w * w))
+            f.append(acc)
+        out += sgn * np.einsum("i,j,k->ijk", f[0], f[1], f[2])
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -743,7 +780,7 @@ def _d_kb_of(at):
                            for a in range(at.tau.shape[0])])
 
 
-def _finish(spec, at, vloc, entries, n_mesh, forced_gap_check, verbose, d_kb):
+def _finish(spec, at, vloc, entries, n_mesh, forced_gap_check, verbose, d_kb, nspin=1):
     homo = max(float(e.eps.max()) for e in entries)
     lumo = min(e.eps_next for e in entries)
     gap = lumo - homo
@@ -751,11 +788,17 @@ def _finish(spec, at, vloc, entries, n_mesh, forced_gap_check, verbose, d_kb):
         print(f"{spec.name} attempt {at.seed_used}: gap {gap:.4f} Ha", flush=True)
     if forced_gap_check and gap < spec.gap_min:
         return None
-    rho0 = _density(spec, at.cell, vloc.shape, entries[:n_mesh])
-    return GroundState(spec=spec, seed_used=at.seed_used, cell=at.cell, fft=tuple(spec.fft), vloc=vloc,
+    fft = tuple(spec.fft)
+    if nspin == 1:
+        rho0 = _density(spec, at.cell, fft, entries[:n_mesh])
+    else:  # one electron per state and spin channel
+        nks = len(entries) // 2
+        rho0 = np.stack([0.5 * _density(spec, at.cell, fft, entries[s * nks:s * nks + n_mesh]) for s in range(2)])
+    return GroundState(spec=spec, seed_used=at.seed_used, cell=at.cell, fft=fft, vloc=vloc,
                        rho0=rho0, tau=at.tau, hub_atoms=at.hub_atoms, hub_zeta=at.hub_zeta,
                        kb_s=at.kb_s, kb_d=at.kb_d, d_kb=d_kb, n_occ=spec.n_occ, kmesh=tuple(spec.kmesh),
-                       qmesh=tuple(spec.qmesh), kpts=entries, n_mesh=n_mesh, gap=gap)
+                       qmesh=tuple(spec.qmesh), kpts=entries, n_mesh=n_mesh, gap=gap,
+                       spin_factor=2 if nspin == 1 else 1, nspin=nspin)
 
 
 def _solve_all(spec, at, vloc, rj, backend, device, tol, verbose, forced_gap_check=True):
@@ -769,18 +812,25 @@ def _solve_all(spec, at, vloc, rj, backend, device, tol, verbose, forced_gap_che
     d_kb = _d_kb_of(at)
     shell = _Shell(at.cell, at.tau, at.hub_atoms, at.hub_zeta, at.kb_s, at.kb_d)
     nb = spec.n_occ + spec.n_guard
-    solver = _KSolver(shell, vloc, d_kb, nb, spec.n_occ + 1, backend, device, tol, verbose, spec.fft, spec)
+    if spec.spin_field:
+        m = spec.spin_field * _spin_field_grid(spec, at)
+        vs = [vloc - m, vloc + m]       # spin up is attracted to the sites of sign +1
+    else:
+        vs = [vloc]
     entries = []
-    for i, k in enumerate(ks):
-        ecut = spec.ecut * (1.0 + jit.get(_pair_key(k), 0.0))
-        miller = sphere(at.cell, k, ecut, spec.fft)
-        beta, phi = projector_tables(shell, k, miller)
-        eps_all, U, res = solver.solve(np.asarray(k, dtype=np.float64), miller, beta)
-        w = 1.0 / len(mesh) if i < len(mesh) else 0.0
-        entries.append(KEntry(k_frac=np.array(k, dtype=np.float64), weight=w, ecut=ecut, miller=miller,
-                              eps=np.array(eps_all[:spec.n_occ]), u=np.ascontiguousarray(U[:spec.n_occ]),
-                              beta=beta, phi=phi, eps_next=float(eps_all[spec.n_occ]), resid=res))
-    return _finish(spec, at, vloc, entries, len(mesh), forced_gap_check, verbose, d_kb)
+    for v in vs:
+        solver = _KSolver(shell, v, d_kb, nb, spec.n_occ + 1, backend, device, tol, verbose, spec.fft, spec)
+        for i, k in enumerate(ks):
+            ecut = spec.ecut * (1.0 + jit.get(_pair_key(k), 0.0))
+            miller = sphere(at.cell, k, ecut, spec.fft)
+            beta, phi = projector_tables(shell, k, miller)
+            eps_all, U, res = solver.solve(np.asarray(k, dtype=np.float64), miller, beta)
+            w = 1.0 / len(mesh) if i < len(mesh) else 0.0
+            entries.append(KEntry(k_frac=np.array(k, dtype=np.float64), weight=w, ecut=ecut, miller=miller,
+                                  eps=np.array(eps_all[:spec.n_occ]), u=np.ascontiguousarray(U[:spec.n_occ]),
+                                  beta=beta, phi=phi, eps_next=float(eps_all[spec.n_occ]), resid=res))
+    vout = vloc if len(vs) == 1 else np.stack(vs)
+    return _finish(spec, at, vout, entries, len(mesh), forced_gap_check, verbose, d_kb, nspin=len(vs))
 
 
 @dataclass

@@ -2,7 +2,8 @@
  * hp.h - C ABI of the MI355X Hubbard-response (DFPT) library.
  *
  * The library computes the linear response of the Hubbard-manifold occupations
- * of a periodic, norm-conserving, non-magnetic insulator to monochromatic
+ * of a periodic, norm-conserving insulator (spin-unpolarized, or collinear
+ * spin-polarized with the same number of occupied states per spin) to monochromatic
  * perturbations of those occupations, following Timrov, Marzari and
  * Cococcioni, "HP - A code for the calculation of Hubbard parameters using
  * density-functional perturbation theory":
@@ -22,7 +23,12 @@
  *   [N1][N2][N3] (N3 fastest).  Complex arrays are interleaved (re, im) FP64.
  *   The projector tables are the lattice-periodic Bloch sums
  *   fbar_k(G) = Omega^-1/2 ftilde(k+G) e^{-i(k+G).tau}.
- *   Closed shell: spin factor 2 in the occupations and densities.
+ *   nspin = 1 (closed shell): spin factor 2 in the occupations and densities.
+ *   nspin = 2 (collinear spin-polarized): one electron per state, spin-resolved
+ *   states, local potentials and densities; the perturbation of Eq. 16 acts on
+ *   both spins, the response occupations are summed over spins (the site
+ *   occupation of Eq. 7 is the trace over m and spin), and the Hxc response uses
+ *   the LSDA kernel.
  *
  * Status codes: every call returns hp_status.  0 = success; > 0 = warning,
  * outputs written; < 0 = error, outputs untouched.  hp_last_error() gives a
@@ -89,17 +95,20 @@ typedef struct hp_ground_state {
   uint32_t struct_size;   /* sizeof(hp_ground_state)                               */
   double cell[3][3];      /* rows a1, a2, a3 (bohr)                                */
   int32_t fft[3];         /* N1, N2, N3: each a product of 2, 3 and 5, <= 256      */
-  const double *v_loc;    /* [N1][N2][N3] total local KS potential (Ha)            */
-  const double *rho0;     /* [N1][N2][N3] ground-state density (electrons/bohr^3)  */
+  const double *v_loc;    /* [nspin][N1][N2][N3] total local KS potential (Ha)     */
+  const double *rho0;     /* [nspin][N1][N2][N3] ground-state (spin) density        */
+                          /* (electrons/bohr^3)                                    */
   int32_t n_occ;          /* occupied bands (the same at every k)                  */
   int32_t n_beta;         /* KB projectors                                         */
   int32_t n_hub;          /* Hubbard sites (5 d orbitals each)                     */
   const double *d_kb;     /* [n_beta] KB strengths (Ha)                            */
   const double *hub_tau;  /* [n_hub][3] Hubbard site positions (bohr)              */
-  int32_t spin_factor;    /* must be 2 (closed shell)                              */
-  int32_t n_mesh;         /* the first n_mesh entries of kpts form the k mesh      */
-  int32_t n_kpts;         /* total entries (mesh + extra k+q)                      */
-  const hp_kpoint *kpts;  /* [n_kpts]                                              */
+  int32_t spin_factor;    /* electrons per state: 2 (nspin = 1) or 1 (nspin = 2)   */
+  int32_t n_mesh;         /* the first n_mesh entries of each spin block form the  */
+                          /* k mesh                                                */
+  int32_t n_kpts;         /* total entries: nspin blocks of (mesh + extra k+q)     */
+  const hp_kpoint *kpts;  /* [n_kpts]: spin-up block, then (nspin = 2) a spin-down */
+                          /* block with the same k points and spheres in order     */
   int32_t xc;             /* HP_XC_LDA_PZ81                                        */
   int32_t reserved;       /* must be 0                                             */
   void *stream;           /* hipStream_t to run on, or NULL for a private stream   */
@@ -108,6 +117,7 @@ typedef struct hp_ground_state {
   int32_t n_atwfc;        /* HP_PROJ_ORTHO_ATOMIC: atomic orbitals per entry        */
   const int32_t *hub_rows;/* HP_PROJ_ORTHO_ATOMIC: [n_hub*5] row of atwfc that is d */
                           /* orbital m of Hubbard site s, at 5 s + m                */
+  int32_t nspin;          /* 1 (unpolarized) or 2 (collinear spin-polarized)        */
 } hp_ground_state;
 
 /* Convergence controls (the paper's inputhp keywords conv_thr_chi, niter_max,
@@ -164,8 +174,10 @@ typedef struct hp_ctx hp_ctx;  /* opaque; owns every device buffer */
  * built from its atomic orbitals: the overlaps O_k on the matrix cores, O_k^-1/2
  * on the host (Jacobi), the rows hub_rows of O_k^-1/2 applied on the matrix
  * cores (Eq. 6); phi is then not read.
- * Errors: HP_ERR_ARG (NULL, bad sizes, spin_factor != 2, xc unknown, bad
- * projector settings), HP_ERR_SHAPE (sphere does not fit the grid, FFT size not
+ * With nspin = 2 the LSDA kernel (Perdew-Zunger interpolation between the
+ * unpolarized and polarized fits) is built from the two spin densities.
+ * Errors: HP_ERR_ARG (NULL, bad sizes, nspin not 1 or 2, spin_factor != 3 - nspin,
+ * spin blocks that differ in k points or spheres, xc unknown, bad projector settings), HP_ERR_SHAPE (sphere does not fit the grid, FFT size not
  * 2^a 3^b 5^c), HP_ERR_SINGULAR (linearly dependent atomic orbitals), HP_ERR_OOM,
  * HP_ERR_HIP.  On success *out owns all device memory. */
 hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **out);
@@ -179,7 +191,7 @@ hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **out);
  *                                   the chi0 column of Eq. 7),
  *   dn_out  [n_hub][5][5] complex : at self-consistency (the chi column).
  * Index order [s][m1][m2]; Delta_q n^s_{m1 m2} is per Ha of perturbation and
- * includes the spin factor.  Returns HP_WARN_NOT_CONVERGED when niter_max or
+ * includes the spin factor (nspin = 1) or the sum over both spins (nspin = 2).  Returns HP_WARN_NOT_CONVERGED when niter_max or
  * max_cg_iter was reached (outputs hold the last iterate), HP_ERR_SHAPE when a
  * k+q entry is missing, HP_ERR_NUMERIC on NaN/Inf. */
 hp_status hp_sternheimer_scf(hp_ctx *c, int32_t pert_site, const double q_frac[3],
@@ -228,15 +240,16 @@ const char *hp_last_error(void);
 
 /* ---- Diagnostics: single steps of the path, for parity checks ------------ */
 
-/* y = H_k x for n vectors on entry `entry` (kinetic + local potential on the
- * grid + KB projectors; the operator of Eq. 15 without the alpha shift).
+/* y = H_k x for n vectors on entry `entry` (index into kpts; kinetic + the
+ * entry's spin's local potential on the grid + KB projectors; the operator of
+ * Eq. 15 without the alpha shift).
  * x, y: [n][npw] complex host arrays in the caller's plane-wave order. */
 hp_status hp_apply_h(hp_ctx *c, int32_t entry, int32_t n, const double *x, double *y);
 
 /* One linear solve of Eq. 15 at mesh point mesh_k for every occupied band,
- * with a given response potential dv ([N1][N2][N3] complex host array, or NULL
- * for dV_Hxc = 0): du_out [n_occ][npw(k+q)] complex, in the plane-wave order of
- * the entry holding k+q.  Uses p->cg_tol, p->max_cg_iter, p->precision. */
+ * with a given response potential dv ([nspin][N1][N2][N3] complex host array, or
+ * NULL for dV_Hxc = 0): du_out [n_occ][npw(k+q)] complex, in the plane-wave order
+ * of the entry holding k+q.  mesh_k = spin * n_mesh + k, 0 <= k < n_mesh.  Uses p->cg_tol, p->max_cg_iter, p->precision. */
 hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const double q_frac[3], int32_t mesh_k,
                                const double *dv, const hp_scf_params *p, double *du_out);
 

@@ -762,7 +762,7 @@ __global__ void __launch_bounds__(kThreads) k_plane_vloc(Plane pl, Sticks sk, co
   for (int s = threadIdx.x; s < E.ns; s += blockDim.x) P[pc.pos(sx[s], sy[s], g0x, g0y)] = Sin[so + s];
   __syncthreads();
   pc.template y_lines<true>();
-  pc.x_round_trip_mul(vp + (size_t)z * np);
+  pc.x_round_trip_mul(vp + ((size_t)kp[k].spin * pl.n3 + z) * np);
   pc.template y_lines<false>();
   for (int s = threadIdx.x; s < E.ns; s += blockDim.x) Sout[so + s] = P[pc.pos(sx[s], sy[s], g0x, g0y)];
 }
@@ -795,7 +795,7 @@ __global__ void __launch_bounds__(NT) k_plane_vloc_b(Plane pl, Sticks sk, const 
   }
   __syncthreads();
   pc.template y_lines<true>();
-  pc.x_round_trip_mul(vp + (size_t)z0 * np);
+  pc.x_round_trip_mul(vp + ((size_t)kp[k].spin * pl.n3 + z0) * np);
   pc.template y_lines<false>();
   for (int w = threadIdx.x; w < PB * E.ns; w += NT) {
     const int p = w / E.ns, s = w - p * E.ns;
@@ -845,7 +845,7 @@ __global__ void __launch_bounds__(kThreads) k_plane_mul_fwd(Plane pl, Sticks sk,
   const int np = pc.np();
   C *P = pc.P;
   const C *ps = psi + ((size_t)item * pl.n3 + z) * np;
-  const C *d = dv + (size_t)z * np;
+  const C *d = dv + ((size_t)kp[k].spin * pl.n3 + z) * np;
   for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = cmul(ps[i], d[i]);
   pc.set_active(sk.xa + E.xa_off, E.nxa, g0x);
   pc.template x_lines<false>();
@@ -909,35 +909,42 @@ __global__ void __launch_bounds__(kThreads) k_plane_drho(Plane pl, Sticks sk, co
 }
 
 __global__ void k_drho_reduce(const KPair *kp, int nk, int nsplit, const double2 *__restrict__ part, long nr,
-                              double inv_omega, double2 *__restrict__ drho) {
+                              double inv_omega, double occ, int nspin, double2 *__restrict__ drho) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i >= nr) return;
-  double2 acc = make_double2(0.0, 0.0);
+  double2 acc[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
   for (int k = 0; k < nk; ++k) {
-    const double w = 4.0 * kp[k].weight * inv_omega;
+    const double w = 2.0 * occ * kp[k].weight * inv_omega;
     double2 p = make_double2(0.0, 0.0);
     for (int s = 0; s < nsplit; ++s) {
       const double2 t = part[((size_t)k * nsplit + s) * nr + i];
       p.x += t.x;
       p.y += t.y;
     }
-    acc.x += w * p.x;
-    acc.y += w * p.y;
+    const int sp = kp[k].spin;
+    acc[sp].x += w * p.x;
+    acc[sp].y += w * p.y;
   }
-  drho[i] = acc;
+  drho[i] = acc[0];
+  if (nspin == 2) drho[nr + i] = acc[1];
 }
 
 // Hartree step 1: permuted real-space plane -> natural plane of G_x, G_y (forward).
 template <int N1, int N2>
 __global__ void __launch_bounds__(kThreads) k_hxc_planes_fwd(Plane pl, const double2 *__restrict__ drho,
-                                                             double2 *__restrict__ tmp) {
+                                                             int nspin, double2 *__restrict__ tmp) {
   extern __shared__ __align__(16) unsigned char lds[];
   PlaneCtx<N1, N2> pc(pl, lds);
   const int z = blockIdx.x;
   const int np = pc.np();
   double2 *P = pc.P;
   const double2 *in = drho + (size_t)z * np;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = in[i];
+  const size_t nr = (size_t)np * pl.n3;
+  if (nspin == 2) {  // Hartree of the total response density
+    for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = cadd(in[i], in[nr + i]);
+  } else {
+    for (int i = threadIdx.x; i < np; i += blockDim.x) P[i] = in[i];
+  }
   pc.set_all_x();
   pc.template x_lines<false>();
   pc.template y_lines<false>();
@@ -987,7 +994,7 @@ __global__ void k_hxc_columns(Plane pl, const double2 *__restrict__ tw3, const d
 template <int N1, int N2>
 __global__ void __launch_bounds__(kThreads) k_hxc_planes_inv(Plane pl, const double2 *__restrict__ tmp,
                                                              const double *__restrict__ fxc,
-                                                             const double2 *__restrict__ drho,
+                                                             const double2 *__restrict__ drho, int nspin,
                                                              double2 *__restrict__ dvout) {
   extern __shared__ __align__(16) unsigned char lds[];
   PlaneCtx<N1, N2> pc(pl, lds);
@@ -1000,6 +1007,16 @@ __global__ void __launch_bounds__(kThreads) k_hxc_planes_inv(Plane pl, const dou
   pc.template y_lines<true>();
   pc.template x_lines<true>();
   const size_t o = (size_t)z * np;
+  if (nspin == 2) {  // dv_s = V_H + f_s,up drho_up + f_s,dn drho_dn; fxc = [f_uu, f_ud, f_dd]
+    const size_t nr = (size_t)np * pl.n3;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+      const double fuu = fxc[o + i], fud = fxc[nr + o + i], fdd = fxc[2 * nr + o + i];
+      const double2 du = drho[o + i], dd = drho[nr + o + i];
+      dvout[o + i] = make_double2(P[i].x + fuu * du.x + fud * dd.x, P[i].y + fuu * du.y + fud * dd.y);
+      dvout[nr + o + i] = make_double2(P[i].x + fud * du.x + fdd * dd.x, P[i].y + fud * du.y + fdd * dd.y);
+    }
+    return;
+  }
   for (int i = threadIdx.x; i < np; i += blockDim.x) {
     const double fx = fxc[o + i];
     const double2 d = drho[o + i];
@@ -1059,6 +1076,76 @@ __global__ void k_fxc(const double *__restrict__ rho, double *__restrict__ fxc, 
     dv = A / rs + 2.0 / 3.0 * C * (log(rs) + 1.0) + (2.0 * D - C) / 3.0;
   }
   fxc[i] = fx + dv * (-rs / (3.0 * r));
+}
+
+// One Perdew-Zunger correlation fit (gamma, beta1, beta2 for r_s >= 1; A, B, C, D below):
+// eps and its first two r_s derivatives.
+struct PzFit {
+  double g, b1, b2, a, b, c, d;
+};
+__device__ void pz_fit(const PzFit &f, double rs, double &e0, double &e1, double &e2) {
+  if (rs >= 1.0) {
+    const double sq = sqrt(rs);
+    const double den = 1.0 + f.b1 * sq + f.b2 * rs;
+    const double dd1 = 0.5 * f.b1 / sq + f.b2;
+    const double dd2 = -0.25 * f.b1 / (rs * sq);
+    e0 = f.g / den;
+    e1 = -f.g * dd1 / (den * den);
+    e2 = f.g * (2.0 * dd1 * dd1 / (den * den * den) - dd2 / (den * den));
+  } else {
+    const double l = log(rs);
+    e0 = f.a * l + f.b + f.c * rs * l + f.d * rs;
+    e1 = f.a / rs + f.c * (l + 1.0) + f.d;
+    e2 = -f.a / (rs * rs) + f.c / rs;
+  }
+}
+
+// Collinear spin-polarized LDA kernel d v_s / d rho_t (Hartree units): exchange from the
+// spin-scaling relation (diagonal, -(1/3)(6/pi)^(1/3) rho_s^(-2/3)); Perdew-Zunger
+// correlation interpolated between the unpolarized and the fully polarized fit with
+// f(zeta) = ((1+zeta)^(4/3) + (1-zeta)^(4/3) - 2) / (2^(4/3) - 2), differentiated through
+// (r_s, zeta).  Zero where rho_up + rho_dn <= 1e-10; |zeta| clipped at 1 - 1e-12.
+__global__ void k_fxc_spin(const double *__restrict__ rup, const double *__restrict__ rdn,
+                           double *__restrict__ fxc, long n) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double r = rup[i] + rdn[i];
+  if (!(r > 1e-10)) {
+    fxc[i] = fxc[n + i] = fxc[2 * n + i] = 0.0;
+    return;
+  }
+  const double zmax = 1.0 - 1e-12;
+  const double z = fmin(zmax, fmax(-zmax, (rup[i] - rdn[i]) / r));
+  const double rs = cbrt(3.0 / (4.0 * M_PI * r));
+  const PzFit fu{-0.1423, 1.0529, 0.3334, 0.0311, -0.048, 0.0020, -0.0116};
+  const PzFit fp{-0.0843, 1.3981, 0.2611, 0.01555, -0.0269, 0.0007, -0.0048};
+  double u0, u1, u2, p0, p1, p2;
+  pz_fit(fu, rs, u0, u1, u2);
+  pz_fit(fp, rs, p0, p1, p2);
+  const double den = cbrt(16.0) - 2.0;  // 2^(4/3) - 2
+  const double cp = cbrt(1.0 + z), cm = cbrt(1.0 - z);
+  const double fz = ((1.0 + z) * cp + (1.0 - z) * cm - 2.0) / den;
+  const double fz1 = 4.0 / 3.0 * (cp - cm) / den;
+  const double fz2 = 4.0 / 9.0 * (1.0 / (cp * cp) + 1.0 / (cm * cm)) / den;
+  const double e_r = u1 + fz * (p1 - u1), e_rr = u2 + fz * (p2 - u2);
+  const double e_zz = fz2 * (p0 - u0), e_rz = fz1 * (p1 - u1);
+  const double a_r = 2.0 / 3.0 * e_r - rs / 3.0 * e_rr;
+  const double c6 = cbrt(6.0 / M_PI);
+  double f[2][2];
+  for (int a = 0; a < 2; ++a) {
+    const double sa = a == 0 ? 1.0 : -1.0;
+    const double g_rho = -rs / (3.0 * r) * (a_r + (sa - z) * e_rz);   // d/d rho at fixed zeta
+    const double g_zeta = -rs / 3.0 * e_rz + (sa - z) * e_zz;        // d/d zeta at fixed rho
+    for (int b = 0; b < 2; ++b) {
+      const double sb = b == 0 ? 1.0 : -1.0;
+      f[a][b] = g_rho + (sb - z) / r * g_zeta;
+    }
+    const double rsig = 0.5 * r * (1.0 + sa * z);
+    f[a][a] += -c6 / (3.0 * cbrt(rsig * rsig));
+  }
+  fxc[i] = f[0][0];
+  fxc[n + i] = 0.5 * (f[0][1] + f[1][0]);
+  fxc[2 * n + i] = f[1][1];
 }
 
 }  // namespace
@@ -1269,20 +1356,20 @@ hipError_t launch_plane_drho32(const Plane &pl, const Sticks &sk, const KPair *k
 }
 
 hipError_t launch_drho_reduce(const KPair *kp, int nk, int nsplit, const double2 *part, long nr, double inv_omega,
-                              double2 *drho, hipStream_t st) {
+                              double occ, int nspin, double2 *drho, hipStream_t st) {
   hipLaunchKernelGGL(k_drho_reduce, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, kp, nk, nsplit, part, nr,
-                     inv_omega, drho);
+                     inv_omega, occ, nspin, drho);
   return hipGetLastError();
 }
 
 hipError_t launch_hxc(const Plane &pl, const Axis &az, const double *bvec, const double *q, const double2 *drho,
-                      const double *fxc, double2 *tmp, double2 *dvout, hipStream_t st) {
-  HP_PLANE_DISPATCH(k_hxc_planes_fwd, dim3(pl.n3), plane_lds_t(pl), st, pl, drho, tmp);
+                      const double *fxc, double2 *tmp, double2 *dvout, int nspin, hipStream_t st) {
+  HP_PLANE_DISPATCH(k_hxc_planes_fwd, dim3(pl.n3), plane_lds_t(pl), st, pl, drho, nspin, tmp);
   const int cols = 32;
   const int np = pl.n1 * pl.n2;
   hipLaunchKernelGGL(k_hxc_columns, dim3((np + cols - 1) / cols), dim3(cols), 2 * pl.n3 * cols * sizeof(double2), st,
                      pl, az.tw, bvec, q[0], q[1], q[2], tmp);
-  HP_PLANE_DISPATCH(k_hxc_planes_inv, dim3(pl.n3), plane_lds_t(pl), st, pl, tmp, fxc, drho, dvout);
+  HP_PLANE_DISPATCH(k_hxc_planes_inv, dim3(pl.n3), plane_lds_t(pl), st, pl, tmp, fxc, drho, nspin, dvout);
   return hipGetLastError();
 }
 
@@ -1303,6 +1390,11 @@ hipError_t launch_permute_complex(const Plane &pl, const int *px, const int *py,
 
 hipError_t launch_fxc(const double *rho, double *fxc, long n, hipStream_t st) {
   hipLaunchKernelGGL(k_fxc, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rho, fxc, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fxc_spin(const double *rho_up, const double *rho_dn, double *fxc, long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fxc_spin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rho_up, rho_dn, fxc, n);
   return hipGetLastError();
 }
 

@@ -98,6 +98,7 @@ struct HostEntry {
   std::array<double, 3> k;
   double weight;
   int npw;
+  int spin = 0;
   std::vector<int> order;  // internal position -> caller index
 };
 
@@ -109,6 +110,12 @@ struct hp_ctx {
   int n1 = 0, n2 = 0, n3 = 0;
   long nr = 0, np = 0;
   int n_occ = 0, n_beta = 0, n_hub = 0, n_mesh = 0, n_kpts = 0;
+  // Spin: nspin blocks of entries.  Internally the mesh entries of every spin come first
+  // (entry = spin * n_mesh_spin + k for mesh k), so that n_mesh = nspin * n_mesh_spin pairs
+  // form one batch; internal_of maps a caller entry index to the internal one.
+  int nspin = 1, n_mesh_spin = 0;
+  double occ = 2.0;  // electrons per state
+  std::vector<int> internal_of;
   int ld = 0, ns_pad = 0, ns_max = 0, max_chunk_pw = 0, npw_max = 0, n_proj = 0;
   double cell[9], bvec[9], omega = 0, alpha = 0;
   std::vector<HostEntry> ent;
@@ -528,7 +535,7 @@ hp_status build_rhs(hp_ctx *c, const KPair *kp, int nk, int site, const double2 
   const int nb = c->n_occ, nitems = nk * nb;
   if (dv && lowp) {
     float2 *S1 = reinterpret_cast<float2 *>(c->S1);
-    HPCHK(launch_to_f32((const double *)dv, (float *)c->dv32, 2L * c->nr, c->stream));
+    HPCHK(launch_to_f32((const double *)dv, (float *)c->dv32, 2L * c->nspin * c->nr, c->stream));
     HPCHK(timed(c, K_PLANE_MUL32, [&] {
       return launch_plane_mul_fwd32(c->pl32, c->sk, kp, nb, nitems, c->psi32, c->dv32, S1, c->ns_pad, c->stream);
     }));
@@ -751,8 +758,8 @@ hp_status setup32(hp_ctx *c) {
   HPCHK(launch_to_f32((const double *)c->tw, (float *)c->tw32, 2 * ntw, c->stream));
   HPTRY(c->alloc(&c->T32, (size_t)c->n_kpts * c->t_stride));
   HPCHK(launch_to_f32((const double *)c->d_T, (float *)c->T32, 2L * c->n_kpts * c->t_stride, c->stream));
-  HPTRY(c->alloc(&c->vp32, c->nr));
-  HPCHK(launch_to_f32(c->d_vp, c->vp32, c->nr, c->stream));
+  HPTRY(c->alloc(&c->vp32, (size_t)c->nspin * c->nr));
+  HPCHK(launch_to_f32(c->d_vp, c->vp32, (long)c->nspin * c->nr, c->stream));
   for (float2 **b : {&c->X32, &c->R32, &c->B32, &c->P32, &c->AP32}) {
     HPTRY(c->alloc(b, vec));
     HPCHK(hipMemsetAsync(*b, 0, sizeof(float2) * vec, c->stream));
@@ -767,7 +774,7 @@ hp_status setup32(hp_ctx *c) {
   // RHS product and the response density of iterations solved to >= 1e-6 run in FP32
   HPTRY(c->alloc(&c->psi32, (size_t)c->n_mesh * c->n_occ * c->nr));
   HPCHK(launch_to_f32((const double *)c->d_psi, (float *)c->psi32, 2L * c->n_mesh * c->n_occ * c->nr, c->stream));
-  HPTRY(c->alloc(&c->dv32, (size_t)c->nr));
+  HPTRY(c->alloc(&c->dv32, (size_t)c->nspin * c->nr));
   c->pl32 = c->pl;
   c->pl32.ax.tw32 = c->tw32;
   c->pl32.ay.tw32 = c->tw32 + c->n1;
@@ -1128,8 +1135,10 @@ hp_status upload_pairs(hp_ctx *c, int site, const double q[3], std::vector<KPair
     KPair P{};
     P.ek = k;
     P.ej = -1;
+    P.spin = c->ent[k].spin;
     P.weight = c->ent[k].weight;
     for (int j = 0; j < c->n_kpts && P.ej < 0; ++j) {
+      if (c->ent[j].spin != P.spin) continue;
       double d[3];
       bool ok = true;
       for (int a = 0; a < 3; ++a) {
@@ -1199,12 +1208,13 @@ void apply_call_params(hp_ctx *c, const hp_scf_params *p) {
 // the stick order, their overlaps O_k on the matrix cores (one launch over all entries),
 // O_k^-1/2 on the host (one thread per entry), then phi~_{5s+m} = sum_j (O^-1/2)_{j,r}
 // phi_j with r = hub_rows[5s+m] on the matrix cores (one launch).
-hp_status ortho_atomic_projectors(hp_ctx *c, const hp_ground_state *gs, const std::vector<Layout> &lay) {
+hp_status ortho_atomic_projectors(hp_ctx *c, const hp_ground_state *gs, const std::vector<const hp_kpoint *> &KP,
+                                  const std::vector<Layout> &lay) {
   const int na = gs->n_atwfc, nh5 = 5 * c->n_hub, ne = c->n_kpts;
   const long at_stride = (long)na * c->ld;
   std::vector<double2> h_at((size_t)ne * at_stride, make_double2(0.0, 0.0));
   for (int i = 0; i < ne; ++i) {
-    const hp_kpoint &k = gs->kpts[i];
+    const hp_kpoint &k = *KP[i];
     double2 *A = h_at.data() + (size_t)i * at_stride;
     for (int p = 0; p < k.npw; ++p) {
       const int q = lay[i].order[p];
@@ -1425,7 +1435,9 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   *out = nullptr;
   if (!gs) return fail(HP_ERR_ARG, "gs is NULL");
   if (gs->struct_size != sizeof(hp_ground_state)) return fail(HP_ERR_ARG, "hp_ground_state.struct_size mismatch");
-  if (gs->spin_factor != 2) return fail(HP_ERR_ARG, "spin_factor must be 2 (closed shell)");
+  if (gs->nspin != 1 && gs->nspin != 2) return fail(HP_ERR_ARG, "nspin must be 1 or 2");
+  if (gs->spin_factor != 3 - gs->nspin)
+    return fail(HP_ERR_ARG, "spin_factor must be %d with nspin = %d", 3 - gs->nspin, gs->nspin);
   if (gs->xc != HP_XC_LDA_PZ81) return fail(HP_ERR_ARG, "unknown xc %d", gs->xc);
   if (gs->reserved != 0) return fail(HP_ERR_ARG, "reserved must be 0");
   if (gs->projectors != HP_PROJ_ATOMIC && gs->projectors != HP_PROJ_ORTHO_ATOMIC)
@@ -1441,13 +1453,33 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
       seen[r] = 1;
     }
   }
-  if (gs->n_mesh < 1 || gs->n_kpts < gs->n_mesh) return fail(HP_ERR_ARG, "bad n_mesh/n_kpts");
+  if (gs->n_mesh < 1 || gs->n_kpts % gs->nspin || gs->n_kpts / gs->nspin < gs->n_mesh)
+    return fail(HP_ERR_ARG, "bad n_mesh/n_kpts");
   std::vector<int> rad[3];
   for (int d = 0; d < 3; ++d) {
     if (gs->fft[d] < 2 || gs->fft[d] > 256 || !factor_235(gs->fft[d], rad[d]))
       return fail(HP_ERR_SHAPE, "fft[%d] = %d is not a product of 2, 3, 5 in [2, 256]", d, gs->fft[d]);
   }
   for (int i = 0; i < gs->n_kpts; ++i) HPTRY(check_kpoint(gs->kpts[i], i, gs));
+  // spin blocks: the same k points and spheres in the same order
+  const int nks = gs->n_kpts / gs->nspin;
+  for (int i = 0; gs->nspin == 2 && i < nks; ++i) {
+    const hp_kpoint &a = gs->kpts[i], &b = gs->kpts[nks + i];
+    bool same = a.npw == b.npw;
+    for (int d = 0; d < 3 && same; ++d) same = a.k_frac[d] == b.k_frac[d];
+    for (long j = 0; j < 3L * a.npw && same; ++j) same = a.miller[j] == b.miller[j];
+    if (!same) return fail(HP_ERR_ARG, "kpts[%d] (spin down) differs from kpts[%d] in k or sphere", nks + i, i);
+  }
+  // internal order: mesh entries of every spin, then the extra k+q entries of every spin
+  std::vector<const hp_kpoint *> KP;
+  std::vector<int> internal_of(gs->n_kpts), spin_of;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int sp = 0; sp < gs->nspin; ++sp)
+      for (int i = pass ? gs->n_mesh : 0; i < (pass ? nks : gs->n_mesh); ++i) {
+        internal_of[sp * nks + i] = (int)KP.size();
+        KP.push_back(&gs->kpts[sp * nks + i]);
+        spin_of.push_back(sp);
+      }
   const double det = gs->cell[0][0] * (gs->cell[1][1] * gs->cell[2][2] - gs->cell[1][2] * gs->cell[2][1]) -
                      gs->cell[0][1] * (gs->cell[1][0] * gs->cell[2][2] - gs->cell[1][2] * gs->cell[2][0]) +
                      gs->cell[0][2] * (gs->cell[1][0] * gs->cell[2][1] - gs->cell[1][1] * gs->cell[2][0]);
@@ -1455,13 +1487,13 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   // plane-wave layouts (host), before any GPU call
   std::vector<Layout> lay(gs->n_kpts);
   for (int i = 0; i < gs->n_kpts; ++i)
-    HPTRY(build_layout(gs->kpts[i], gs->fft[0], gs->fft[1], gs->fft[2], lay[i], i));
+    HPTRY(build_layout(*KP[i], gs->fft[0], gs->fft[1], gs->fft[2], lay[i], i));
   for (int i = 0; i < gs->n_kpts; ++i) {
-    const hp_kpoint &k = gs->kpts[i];
+    const hp_kpoint &k = *KP[i];
     for (int v = 0; v < gs->n_occ; ++v)
       if (!std::isfinite(k.eps[v])) return fail(HP_ERR_NUMERIC, "kpts[%d].eps[%d] is not finite", i, v);
   }
-  const long nrr = (long)gs->fft[0] * gs->fft[1] * gs->fft[2];
+  const long nrr = (long)gs->fft[0] * gs->fft[1] * gs->fft[2] * gs->nspin;
   for (long i = 0; i < nrr; ++i)
     if (!std::isfinite(gs->v_loc[i]) || !std::isfinite(gs->rho0[i])) return fail(HP_ERR_NUMERIC, "non-finite v_loc/rho0");
 
@@ -1476,7 +1508,11 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   c->n_occ = gs->n_occ;
   c->n_beta = gs->n_beta;
   c->n_hub = gs->n_hub;
-  c->n_mesh = gs->n_mesh;
+  c->nspin = gs->nspin;
+  c->n_mesh_spin = gs->n_mesh;
+  c->n_mesh = gs->nspin * gs->n_mesh;
+  c->occ = gs->nspin == 2 ? 1.0 : 2.0;
+  c->internal_of = internal_of;
   c->n_kpts = gs->n_kpts;
   c->n_proj = c->n_beta + c->n_occ;
   for (int i = 0; i < 9; ++i) c->cell[i] = gs->cell[i / 3][i % 3];
@@ -1501,14 +1537,14 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   double emax = -1e300, emin = 1e300;
   for (int i = 0; i < gs->n_kpts; ++i)
     for (int v = 0; v < gs->n_occ; ++v) {
-      emax = std::max(emax, gs->kpts[i].eps[v]);
-      emin = std::min(emin, gs->kpts[i].eps[v]);
+      emax = std::max(emax, KP[i]->eps[v]);
+      emin = std::min(emin, KP[i]->eps[v]);
     }
   c->alpha = std::max(2.0 * (emax - emin), 0.01);
 
   int npw_max = 0, ns_max = 0, chunk_max = 0;
   for (int i = 0; i < gs->n_kpts; ++i) {
-    npw_max = std::max(npw_max, gs->kpts[i].npw);
+    npw_max = std::max(npw_max, KP[i]->npw);
     const int ns = (int)lay[i].sx.size();
     ns_max = std::max(ns_max, ns);
     for (int s0 = 0; s0 < ns; s0 += 32) {
@@ -1573,23 +1609,32 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   HPCHK(hipMemcpyAsync(c->d_py, c->py.data(), sizeof(int) * c->n2, hipMemcpyHostToDevice, st));
 
   // local potential and f_xc in the permuted real-space layout
+  // (per spin: [nspin][nr]; the kernel: [nr] unpolarized, [3][nr] = f_uu, f_ud, f_dd polarized)
+  const int ns = c->nspin;
   double *d_nat = nullptr;
-  HPTRY(c->alloc(&d_nat, c->nr));
-  HPTRY(c->alloc(&c->d_vp, c->nr));
-  HPTRY(c->alloc(&c->d_fxc, c->nr));
-  HPCHK(hipMemcpyAsync(d_nat, gs->v_loc, sizeof(double) * c->nr, hipMemcpyHostToDevice, st));
-  HPCHK(launch_permute_real(c->pl, c->d_px, c->d_py, d_nat, c->d_vp, st));
+  HPTRY(c->alloc(&d_nat, (size_t)ns * c->nr));
+  HPTRY(c->alloc(&c->d_vp, (size_t)ns * c->nr));
+  HPTRY(c->alloc(&c->d_fxc, (size_t)(ns == 2 ? 3 : 1) * c->nr));
+  HPCHK(hipMemcpyAsync(d_nat, gs->v_loc, sizeof(double) * ns * c->nr, hipMemcpyHostToDevice, st));
+  for (int sp = 0; sp < ns; ++sp)
+    HPCHK(launch_permute_real(c->pl, c->d_px, c->d_py, d_nat + sp * c->nr, c->d_vp + sp * c->nr, st));
   HPTRY(sync(c.get()));
-  HPCHK(hipMemcpyAsync(d_nat, gs->rho0, sizeof(double) * c->nr, hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(d_nat, gs->rho0, sizeof(double) * ns * c->nr, hipMemcpyHostToDevice, st));
   double *d_rhop = nullptr;
-  HPTRY(c->alloc(&d_rhop, c->nr));
-  HPCHK(launch_permute_real(c->pl, c->d_px, c->d_py, d_nat, d_rhop, st));
-  HPCHK(launch_fxc(d_rhop, c->d_fxc, c->nr, st));
+  HPTRY(c->alloc(&d_rhop, (size_t)ns * c->nr));
+  for (int sp = 0; sp < ns; ++sp)
+    HPCHK(launch_permute_real(c->pl, c->d_px, c->d_py, d_nat + sp * c->nr, d_rhop + sp * c->nr, st));
+  if (ns == 2)
+    HPCHK(launch_fxc_spin(d_rhop, d_rhop + c->nr, c->d_fxc, c->nr, st));
+  else
+    HPCHK(launch_fxc(d_rhop, c->d_fxc, c->nr, st));
   HPTRY(c->alloc(&c->d_bvec, 9));
   HPCHK(hipMemcpyAsync(c->d_bvec, c->bvec, sizeof(double) * 9, hipMemcpyHostToDevice, st));
-  double vmean = 0.0;
-  for (long i = 0; i < c->nr; ++i) vmean += gs->v_loc[i];
-  vmean /= (double)c->nr;
+  double vmean_s[2] = {0.0, 0.0};
+  for (int sp = 0; sp < ns; ++sp) {
+    for (long i = 0; i < c->nr; ++i) vmean_s[sp] += gs->v_loc[sp * c->nr + i];
+    vmean_s[sp] /= (double)c->nr;
+  }
 
   // per-entry tables in the stick order
   std::vector<int> h_sx, h_sy, h_ss, h_sl, h_iz, h_xa, h_npw(c->n_kpts);
@@ -1599,8 +1644,9 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   int pw_off = 0;
   c->ent.resize(c->n_kpts);
   for (int i = 0; i < c->n_kpts; ++i) {
-    const hp_kpoint &k = gs->kpts[i];
+    const hp_kpoint &k = *KP[i];
     const Layout &L = lay[i];
+    const double vmean = vmean_s[spin_of[i]];
     EntryDev E{};
     E.npw = k.npw;
     E.ns = (int)L.sx.size();
@@ -1621,6 +1667,7 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
     for (int a = 0; a < 3; ++a) he.k[a] = k.k_frac[a];
     he.weight = k.weight;
     he.npw = k.npw;
+    he.spin = spin_of[i];
     he.order = L.order;
     double2 *T = h_T.data() + (size_t)i * c->t_stride;
     double2 *F = h_phi.data() + (size_t)i * c->phi_stride;
@@ -1697,7 +1744,7 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   const long nitems = (long)c->n_mesh * nb;
   std::vector<double> eps_items(nitems);
   for (int k = 0; k < c->n_mesh; ++k)
-    for (int v = 0; v < nb; ++v) eps_items[(size_t)k * nb + v] = gs->kpts[k].eps[v];
+    for (int v = 0; v < nb; ++v) eps_items[(size_t)k * nb + v] = KP[k]->eps[v];
   HPTRY(c->alloc(&c->d_eps, nitems));
   HPCHK(hipMemcpyAsync(c->d_eps, eps_items.data(), sizeof(double) * nitems, hipMemcpyHostToDevice, st));
   // pairs
@@ -1707,6 +1754,7 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   for (int i = 0; i < c->n_kpts; ++i) {
     self[i] = KPair{};
     self[i].ek = self[i].ej = i;
+    self[i].spin = c->ent[i].spin;
     self[i].weight = c->ent[i].weight;
   }
   HPCHK(hipMemcpyAsync(c->d_kself, self.data(), sizeof(KPair) * self.size(), hipMemcpyHostToDevice, st));
@@ -1742,15 +1790,16 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   // so that a launch has a few thousand of them
   c->drho_split = std::max(1, std::min(std::min(8, c->n_occ), (4096 + c->n3 * c->n_mesh - 1) / (c->n3 * c->n_mesh)));
   HPTRY(c->alloc(&c->part, (size_t)c->n_mesh * c->drho_split * c->nr));
-  HPTRY(c->alloc(&c->drho, c->nr));
-  HPTRY(c->alloc(&c->dvin, c->nr));
-  HPTRY(c->alloc(&c->dvout, c->nr));
-  HPTRY(c->alloc(&c->f, c->nr));
+  const size_t nv = (size_t)ns * c->nr;  // response fields: [nspin][nr]
+  HPTRY(c->alloc(&c->drho, nv));
+  HPTRY(c->alloc(&c->dvin, nv));
+  HPTRY(c->alloc(&c->dvout, nv));
+  HPTRY(c->alloc(&c->f, nv));
   HPTRY(c->alloc(&c->tmp, c->nr));
-  HPTRY(c->alloc(&c->fprev, c->nr));
-  HPTRY(c->alloc(&c->dvprev, c->nr));
-  HPTRY(c->alloc(&c->hdf, (size_t)kNmixMax * c->nr));
-  HPTRY(c->alloc(&c->hdv, (size_t)kNmixMax * c->nr));
+  HPTRY(c->alloc(&c->fprev, nv));
+  HPTRY(c->alloc(&c->dvprev, nv));
+  HPTRY(c->alloc(&c->hdf, (size_t)kNmixMax * nv));
+  HPTRY(c->alloc(&c->hdv, (size_t)kNmixMax * nv));
   HPTRY(c->alloc(&c->dots_part, (size_t)256 * (2 * kNmixMax + 2)));
   HPTRY(c->alloc(&c->dots, 2 * kNmixMax + 2));
   HPTRY(c->alloc(&c->coef, 2 * kNmixMax + 2));
@@ -1758,7 +1807,7 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   HPTRY(c->alloc(&c->dn, (size_t)25 * c->n_hub));
   HPTRY(c->alloc(&c->d_q, 3));
 
-  if (gs->projectors == HP_PROJ_ORTHO_ATOMIC) HPTRY(ortho_atomic_projectors(c.get(), gs, lay));
+  if (gs->projectors == HP_PROJ_ORTHO_ATOMIC) HPTRY(ortho_atomic_projectors(c.get(), gs, KP, lay));
 
   // A_k[m][v] = <phi_{m,k}|u_vk> for every entry (Eq. 13's ground-state factor)
   HPTRY(c->alloc(&c->d_A, (size_t)c->n_kpts * 5 * c->n_hub * nb));
@@ -1791,7 +1840,8 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
   HPTRY(autotune(c, nk, p->precision == HP_MIXED));
   if (p->precision == HP_MIXED) HPTRY(setup32(c));
   HPCHK(hipMemcpyAsync(c->d_q, q, sizeof(double) * 3, hipMemcpyHostToDevice, c->stream));
-  const long nr = c->nr;
+  // response fields span every spin: [nspin][nr]
+  const long nr = (long)c->nspin * c->nr;
   HPCHK(hipMemsetAsync(c->dvin, 0, sizeof(double2) * nr, c->stream));
   int nhist = 0, hist_head = 0;
   std::vector<std::complex<double>> gram((size_t)kNmixMax * kNmixMax);
@@ -1848,16 +1898,17 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
       }));
     }
     HPCHK(timed(c, K_DRHO_REDUCE, [&] {
-      return launch_drho_reduce(c->d_kp, nk, c->drho_split, c->part, nr, 1.0 / c->omega, c->drho, c->stream);
+      return launch_drho_reduce(c->d_kp, nk, c->drho_split, c->part, c->nr, 1.0 / c->omega, c->occ, c->nspin, c->drho,
+                                c->stream);
     }));
     HPCHK(hipEventRecord(c->ev[3], c->stream));
     HPCHK(timed(c, K_HXC, [&] {
-      return launch_hxc(c->pl, c->az, c->d_bvec, q, c->drho, c->d_fxc, c->tmp, c->dvout, c->stream);
+      return launch_hxc(c->pl, c->az, c->d_bvec, q, c->drho, c->d_fxc, c->tmp, c->dvout, c->nspin, c->stream);
     }));
     HPCHK(hipEventRecord(c->ev[4], c->stream));
     HPTRY(proj(c, c->d_kp, 1, nk, c->d_phi, c->phi_stride, 0, 5 * c->n_hub, c->X, nb, nullptr, 1.0, c->Cphi));
     HPCHK(timed(c, K_DN, [&] {
-      return launch_dn(c->d_kp, nk, c->n_hub, nb, c->d_A, c->Cphi, c->dn, c->stream);
+      return launch_dn(c->d_kp, nk, c->n_hub, nb, c->d_A, c->Cphi, c->occ, c->dn, c->stream);
     }));
     HPCHK(hipMemcpyAsync(dn.data(), c->dn, sizeof(double2) * dn.size(), hipMemcpyDeviceToHost, c->stream));
     HPCHK(hipEventRecord(c->ev[5], c->stream));
@@ -2103,6 +2154,7 @@ extern "C" hp_status hp_apply_h(hp_ctx *c, int32_t entry, int32_t n, const doubl
   if (!x || !y) return fail(HP_ERR_ARG, "NULL argument");
   if (entry < 0 || entry >= c->n_kpts) return fail(HP_ERR_ARG, "entry %d out of range", entry);
   if (n < 1) return fail(HP_ERR_ARG, "n = %d out of range", n);
+  entry = c->internal_of[entry];
   const HostEntry &E = c->ent[entry];
   const int cap = c->n_mesh * c->n_occ;  // vectors per batch (work-buffer capacity)
   std::vector<double2> h((size_t)cap * c->ld);
@@ -2145,8 +2197,11 @@ extern "C" hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const do
   const double2 *psi = c->d_psi + (size_t)mesh_k * nb * c->nr;
   const double *eps = c->d_eps + (size_t)mesh_k * nb;
   if (dv) {
-    HPCHK(hipMemcpyAsync(c->tmp, dv, sizeof(double2) * c->nr, hipMemcpyHostToDevice, c->stream));
-    HPCHK(launch_permute_complex(c->pl, c->d_px, c->d_py, c->tmp, c->dvin, 0, c->stream));
+    for (int sp = 0; sp < c->nspin; ++sp) {
+      HPCHK(hipMemcpyAsync(c->tmp, dv + 2 * (size_t)sp * c->nr, sizeof(double2) * c->nr, hipMemcpyHostToDevice,
+                           c->stream));
+      HPCHK(launch_permute_complex(c->pl, c->d_px, c->d_py, c->tmp, c->dvin + (size_t)sp * c->nr, 0, c->stream));
+    }
   }
   // A for this k: build_rhs indexes d_A by pair index; use a shifted view
   hp_status s = HP_OK;

@@ -44,11 +44,13 @@ struct EntryDev {
 };
 
 // One mesh k of a (site, q) problem: its own entry, the entry holding k+q and the
-// reciprocal vector g0 with k + q = k_j + g0 (the k+q basis is entry j shifted by -g0).
+// reciprocal vector g0 with k + q = k_j + g0 (the k+q basis is entry j shifted by -g0),
+// and the spin channel of both (selects the spin's local and response potentials).
 struct KPair {
   int ek;
   int ej;
   int g0[3];
+  int spin;
   double weight;
 };
 
@@ -117,11 +119,15 @@ hipError_t launch_plane_drho32(const Plane &pl, const Sticks &sk, const KPair *k
 // out[i] = (double) in[i]
 hipError_t launch_to_f64(const float *in, double *out, long n, hipStream_t st);
 // drho = sum_k (4 w_k / Omega) sum_s part[k][s] in fixed order.
+// drho[s][i] = (2 occ / Omega) sum over pairs k of spin s of w_k sum_split part[k][split][i]
+// (occ electrons per state, 2 for time reversal); s < nspin.
 hipError_t launch_drho_reduce(const KPair *kp, int nk, int nsplit, const double2 *part, long nr, double inv_omega,
-                              double2 *drho, hipStream_t st);
-// dvout = IFFT(4 pi FFT(drho) / |q+G|^2) + fxc * drho, permuted layout.
+                              double occ, int nspin, double2 *drho, hipStream_t st);
+// dvout = IFFT(4 pi FFT(drho) / |q+G|^2) + fxc * drho, permuted layout.  nspin = 2: drho,
+// dvout are [2][nr], the Hartree term uses drho[0] + drho[1] and fxc is [3][nr]
+// (f_uu, f_ud, f_dd): dvout[s] = V_H + f_s0 drho[0] + f_s1 drho[1].
 hipError_t launch_hxc(const Plane &pl, const Axis &az, const double *bvec, const double *q, const double2 *drho,
-                      const double *fxc, double2 *tmp, double2 *dvout, hipStream_t st);
+                      const double *fxc, double2 *tmp, double2 *dvout, int nspin, hipStream_t st);
 // natural [N1][N2][N3] <-> permuted [N3][xp][yp]
 hipError_t launch_permute_real(const Plane &pl, const int *px, const int *py, const double *in, double *out,
                                hipStream_t st);
@@ -129,6 +135,8 @@ hipError_t launch_permute_complex(const Plane &pl, const int *px, const int *py,
                                   int inverse, hipStream_t st);
 // PZ81 LDA kernel f_xc(rho) (Ha bohr^3), zero where rho < 1e-10.
 hipError_t launch_fxc(const double *rho, double *fxc, long n, hipStream_t st);
+// Spin-polarized LSDA kernel from rho_up, rho_dn: fxc[0..2][i] = f_uu, f_ud, f_dd.
+hipError_t launch_fxc_spin(const double *rho_up, const double *rho_dn, double *fxc, long n, hipStream_t st);
 
 // proj:   Cpart -> C[k][m][v] = row_scale[m] * gscale * sum_G conj(T_e[m0+m][G]) X[k*nb+v][G]
 hipError_t launch_zproj(const KPair *kp, int use_kq, int nk, const double2 *T, long t_stride, int m0, int M,
@@ -200,8 +208,8 @@ hipError_t launch_refine_update(int nb, int nitems, double2 *X, const float2 *D,
                                 int have_x, hipStream_t st);
 hipError_t launch_to_f32(const double *in, float *out, long n, hipStream_t st);
 // dn[s][m1][m2] = sum_k 2 w_k sum_v (B[k][5s+m1][v] conj(A[ek][5s+m2][v]) + (m1 <-> m2))
-hipError_t launch_dn(const KPair *kp, int nk, int nh, int nb, const double2 *A, const double2 *B, double2 *dn,
-                     hipStream_t st);
+hipError_t launch_dn(const KPair *kp, int nk, int nh, int nb, const double2 *A, const double2 *B, double occ,
+                     double2 *dn, hipStream_t st);
 // mixing helpers
 hipError_t launch_zdots(int nvec, const double2 *const *a, const double2 *b, long n, double2 *partial, double2 *out,
                         hipStream_t st);

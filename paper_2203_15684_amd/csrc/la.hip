@@ -771,15 +771,16 @@ __global__ void k_refine_update(int nb, double2 *__restrict__ X, const float2 *_
   X[o] = x;
 }
 
-// dn[s][m1][m2] = sum_k 2 w_k sum_v (B[k][5s+m1][v] conj(A[k][5s+m2][v]) + B[k][5s+m2][v] conj(A[k][5s+m1][v]))
+// dn[s][m1][m2] = sum_k occ w_k sum_v (B[k][5s+m1][v] conj(A[k][5s+m2][v]) + B[k][5s+m2][v] conj(A[k][5s+m1][v]))
+// (summed over the pairs of every spin)
 __global__ void k_dn(const KPair *kp, int nk, int nh, int nb, const double2 *__restrict__ A,
-                     const double2 *__restrict__ Bm, double2 *__restrict__ dn) {
+                     const double2 *__restrict__ Bm, double occ, double2 *__restrict__ dn) {
   const int M = 5 * nh;
   for (int t = threadIdx.x; t < nh * 25; t += blockDim.x) {
     const int s = t / 25, m1 = (t / 5) % 5, m2 = t % 5;
     double ar = 0.0, ai = 0.0;
     for (int k = 0; k < nk; ++k) {
-      const double w = 2.0 * kp[k].weight;
+      const double w = occ * kp[k].weight;
       const double2 *Ak = A + (size_t)kp[k].ek * M * nb;
       const double2 *Bk = Bm + (size_t)k * M * nb;
       double sr = 0.0, si = 0.0;
@@ -1093,9 +1094,9 @@ hipError_t launch_refine_update(int nb, int nitems, double2 *X, const float2 *D,
   return hipGetLastError();
 }
 
-hipError_t launch_dn(const KPair *kp, int nk, int nh, int nb, const double2 *A, const double2 *B, double2 *dn,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_dn, dim3(1), dim3(256), 0, st, kp, nk, nh, nb, A, B, dn);
+hipError_t launch_dn(const KPair *kp, int nk, int nh, int nb, const double2 *A, const double2 *B, double occ,
+                     double2 *dn, hipStream_t st) {
+  hipLaunchKernelGGL(k_dn, dim3(1), dim3(256), 0, st, kp, nk, nh, nb, A, B, occ, dn);
   return hipGetLastError();
 }
 

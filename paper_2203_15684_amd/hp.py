@@ -58,7 +58,8 @@ class HpGroundState(C.Structure):
                 ("v_loc", _dp), ("rho0", _dp), ("n_occ", C.c_int32), ("n_beta", C.c_int32), ("n_hub", C.c_int32),
                 ("d_kb", _dp), ("hub_tau", _dp), ("spin_factor", C.c_int32), ("n_mesh", C.c_int32),
                 ("n_kpts", C.c_int32), ("kpts", C.POINTER(HpKpoint)), ("xc", C.c_int32), ("reserved", C.c_int32),
-                ("stream", C.c_void_p), ("projectors", C.c_int32), ("n_atwfc", C.c_int32), ("hub_rows", _ip)]
+                ("stream", C.c_void_p), ("projectors", C.c_int32), ("n_atwfc", C.c_int32), ("hub_rows", _ip),
+                ("nspin", C.c_int32)]
 
 
 class HpScfParams(C.Structure):
@@ -181,6 +182,7 @@ class Context:
         self.n_hub = int(gs.n_hub)
         self.npw = [int(e.miller.shape[0]) for e in gs.kpts]
         self.fft = tuple(int(x) for x in gs.fft)
+        self.nspin = int(getattr(gs, "nspin", 1))
 
     def close(self):
         if self.handle is not None and self.handle.value:
@@ -197,7 +199,8 @@ class Context:
 def hp_ground_state_load(gs, stream: Optional[int] = None, atwfc: Optional[Sequence[np.ndarray]] = None,
                          hub_rows: Optional[np.ndarray] = None) -> Context:
     """gs: an object with cell, fft, vloc, rho0, n_occ, d_kb, hub_tau, n_hub, n_mesh, kpts
-    (each k-entry with k_frac, weight, miller, eps, u, beta, phi).  With atwfc (one
+    (each k-entry with k_frac, weight, miller, eps, u, beta, phi), optionally nspin = 2
+    (kpts: a spin-up then a spin-down block; vloc, rho0: (2, N1, N2, N3)).  With atwfc (one
     (n_atwfc, npw) complex array per k-entry: every atomic orbital) and hub_rows (the row of
     d orbital m of Hubbard site s at 5 s + m) the library builds ortho-atomic projectors and
     the entries' phi are not read."""
@@ -226,9 +229,11 @@ def hp_ground_state_load(gs, stream: Optional[int] = None, atwfc: Optional[Seque
                          _ptr(phi) if phi is not None else None, _ptr(at) if at is not None else None)
     vloc = _f64(gs.vloc)
     rho0 = _f64(gs.rho0)
-    nr = int(np.prod([int(x) for x in gs.fft]))
+    nspin = int(getattr(gs, "nspin", 1))
+    nr = int(np.prod([int(x) for x in gs.fft])) * nspin
     if vloc.size != nr or rho0.size != nr:
-        raise ValueError(f"v_loc/rho0 hold {vloc.size}/{rho0.size} values, the grid {tuple(gs.fft)} has {nr}")
+        raise ValueError(f"v_loc/rho0 hold {vloc.size}/{rho0.size} values, {nspin} spin(s) of the grid "
+                         f"{tuple(gs.fft)} hold {nr}")
     dkb = _f64(gs.d_kb)
     htau = _f64(gs.hub_tau)
     hrows = np.ascontiguousarray(hub_rows, dtype=np.int32) if ortho else None
@@ -255,6 +260,7 @@ def hp_ground_state_load(gs, stream: Optional[int] = None, atwfc: Optional[Seque
     g.projectors = HP_PROJ_ORTHO_ATOMIC if ortho else HP_PROJ_ATOMIC
     g.n_atwfc = n_atwfc
     g.hub_rows = _ptr(hrows, _ip) if ortho else None
+    g.nspin = nspin
     h = C.c_void_p()
     _check(_lib.hp_ground_state_load(C.byref(g), C.byref(h)), allow_warn=False)
     del keep
@@ -321,8 +327,9 @@ def hp_solve_first_order(ctx: Context, pert_site: int, q_frac, mesh_k: int, dv: 
     dvp = None
     if dv is not None:
         dva = np.ascontiguousarray(dv, dtype=np.complex128)
-        if dva.shape != ctx.fft:
-            raise ValueError("dv must have the FFT grid shape")
+        want = ctx.fft if ctx.nspin == 1 else (ctx.nspin,) + ctx.fft
+        if dva.shape != want:
+            raise ValueError(f"dv must have the shape {want}")
         dvp = _ptr(dva.view(np.float64))
     s = _check(_lib.hp_solve_first_order(ctx.handle, int(pert_site), _ptr(q), int(mesh_k), dvp, C.byref(p),
                                          _ptr(out.view(np.float64))))

@@ -99,3 +99,26 @@ def test_ortho_atomic_load_validation_runs_before_device(hp):
     assert e.value.status == hp.HP_ERR_ARG
     with pytest.raises(ValueError):    # a table whose plane-wave count is not the entry's
         hp.hp_ground_state_load(gs, atwfc=[a[:, :-1] for a in atw], hub_rows=hub_rows)
+
+
+def test_spin_load_validation_runs_before_device(hp):
+    import copy
+    from conftest import ground_state
+    gs = ground_state("sc1_gamma_spin")
+    for field, val in [("nspin", 3), ("spin_factor", 2)]:
+        g = copy.copy(gs)
+        setattr(g, field, val)
+        if field == "nspin":  # grids consistent with the claimed spin count
+            g.vloc = np.concatenate([gs.vloc, gs.vloc[:1]])
+            g.rho0 = np.concatenate([gs.rho0, gs.rho0[:1]])
+        with pytest.raises(hp.HpError) as e:
+            hp.hp_ground_state_load(g)
+        assert e.value.status == hp.HP_ERR_ARG, (field, e.value)
+    # a spin-down block whose sphere differs from the spin-up one
+    g = copy.copy(gs)
+    dn = copy.copy(gs.kpts[1])
+    dn.miller = gs.kpts[1].miller[::-1].copy()
+    g.kpts = [gs.kpts[0], dn]
+    with pytest.raises(hp.HpError) as e:
+        hp.hp_ground_state_load(g)
+    assert e.value.status == hp.HP_ERR_ARG and "spin down" in str(e.value)

@@ -10,13 +10,17 @@ The oracle is written from the paper (Timrov, Marzari, Cococcioni, "HP - A code
 for the calculation of Hubbard parameters using density-functional
 perturbation theory"): Eqs. 7-9 (susceptibilities and U/V), Eq. 12
 (monochromatic sum over q), Eq. 13 (response occupations), Eq. 6 (ortho-atomic
-projectors by Loewdin orthogonalization), Eqs. 14-18
+projectors by Loewdin orthogonalization), Eq. 5 (the on-site ground-state Hubbard
+potential in the unperturbed Hamiltonian), the spin-resolved forms of Eqs. 3 and
+10-15, the search for equivalent sites and the reconstruction of the response
+matrices (paper, linear-response and post-processing steps), Eqs. 14-18
 (q-specific Sternheimer equation, perturbing potential, valence and
 conduction projectors, the alpha shift).  Each function cites the passage it
 follows.
 """
-from .hp_oracle import Oracle, ScfParams, hubbard_params, assemble_chi, nearest_neighbours, loewdin, ortho_atomic_phi
+from .hp_oracle import (Oracle, ScfParams, hubbard_params, assemble_chi, nearest_neighbours, loewdin,
+                        ortho_atomic_phi, equivalent_sites, supercell_distances, reconstruct_chi)
 from . import pz81
 
 __all__ = ["Oracle", "ScfParams", "hubbard_params", "assemble_chi", "nearest_neighbours", "loewdin",
-           "ortho_atomic_phi", "pz81"]
+           "ortho_atomic_phi", "equivalent_sites", "supercell_distances", "reconstruct_chi", "pz81"]

@@ -104,6 +104,11 @@ class Oracle:
             self.vloc = np.asarray(gs.vloc, dtype=np.float64).reshape((2,) + self.fft)
             rho = np.asarray(gs.rho0, dtype=np.float64).reshape((2,) + self.fft)
             self.fxc = pz81.f_xc_spin(rho[0], rho[1])          # (2, 2) + grid
+        # ground-state Hubbard potential (Eq. 5, on-site part): per spin and site the 5 x 5
+        # matrix M with V_Hub = sum_I sum_{m1 m2} M^I_{m1 m2} |phi^I_{m1}><phi^I_{m2}|, or None
+        hpot = getattr(gs, "hub_pot", None)
+        self.hub_pot = (None if hpot is None else
+                        np.asarray(hpot, dtype=np.complex128).reshape(self.nspin, self.n_hub, 5, 5))
         # alpha = 2 (max - min) over the occupied energies of every loaded entry
         # (paper, text after Eq. 18); floor 0.01 Ha.
         emax = max(float(e.eps.max()) for e in self.kpts)
@@ -167,6 +172,20 @@ class Oracle:
         out = out + self.to_recip(self.to_real(X, idx) * self.v_of(ie)[None], idx)
         proj = X @ e.beta.conj().T            # <beta_i|x> for every row
         out = out + (proj * self.gs.d_kb[None, :]) @ e.beta
+        if self.hub_pot is not None:
+            out = out + self.vhub_apply(ie, X)
+        return out
+
+    def vhub_apply(self, ie: int, X: np.ndarray) -> np.ndarray:
+        """Ground-state Hubbard potential on rows X (Eq. 5, on-site):
+        sum_s sum_{m1 m2} M^s_{m1 m2} |phi_{m1}> <phi_{m2}|x>."""
+        P = self.phi[ie]
+        M = self.hub_pot[self.spin_of(ie)]
+        proj = X @ P.conj().T                 # proj[v, m] = <phi_m|x_v>
+        out = np.zeros_like(X)
+        for s in range(self.n_hub):
+            sl = slice(5 * s, 5 * s + 5)
+            out += (proj[:, sl] @ M[s].T) @ P[sl]
         return out
 
     def h_dense(self, ie: int) -> np.ndarray:
@@ -179,6 +198,11 @@ class Oracle:
         H = vhat[dm[..., 0], dm[..., 1], dm[..., 2]].astype(np.complex128)
         H += np.diag(self.kinetic(ie))
         H += (e.beta.T * self.gs.d_kb[None, :]) @ e.beta.conj()
+        if self.hub_pot is not None:
+            P = self.phi[ie]
+            for s in range(self.n_hub):
+                sl = slice(5 * s, 5 * s + 5)
+                H += P[sl].T @ self.hub_pot[self.spin_of(ie)][s] @ P[sl].conj()
         self._dense[ie] = H
         return H
 
@@ -239,6 +263,12 @@ class Oracle:
         vhat0 = float(np.mean(self.v_of(j)))
         diag = (self.kinetic(j) + vhat0 + (np.abs(ej.beta) ** 2 * self.gs.d_kb[:, None]).sum(0)
                 + a * (np.abs(ej.u) ** 2).sum(0))
+        if self.hub_pot is not None:
+            P = self.phi[j]
+            for s in range(self.n_hub):
+                sl = slice(5 * s, 5 * s + 5)
+                diag = diag + np.einsum("mg,mn,ng->g", P[sl], self.hub_pot[self.spin_of(j)][s],
+                                        P[sl].conj()).real
         dinv = 1.0 / (diag[None, :] - self.kpts[ik].eps[:, None])
         x = np.zeros_like(b) if x0 is None else x0.copy()
         r = b - self.sternheimer_op(ik, q, x, a)
@@ -325,6 +355,18 @@ class Oracle:
                 sl = slice(5 * s, 5 * s + 5)
                 out[s] += self.occ * e.weight * A[sl] @ A[sl].conj().T
         return out
+
+    def site_traces(self) -> Tuple[np.ndarray, np.ndarray]:
+        """Per Hubbard site: the occupation trace summed over spins, sum_s Tr n^{I s} (Eq. 3),
+        and the moment Tr n^{I up} - Tr n^{I dn} (zero when unpolarized)."""
+        tr = np.zeros((self.nspin, self.n_hub))
+        for ik in self.mesh:
+            e = self.kpts[ik]
+            A = self.phi[ik].conj() @ e.u.T
+            w = self.occ * e.weight * np.sum(np.abs(A) ** 2, axis=1)
+            tr[self.spin_of(ik)] += w.reshape(self.n_hub, 5).sum(axis=1)
+        mom = tr[0] - tr[1] if self.nspin == 2 else np.zeros(self.n_hub)
+        return tr.sum(axis=0), mom
 
     # ------------------------------------------------------------ SCF loop
     def scf(self, site: int, q, p: ScfParams = ScfParams(), verbose: bool = False):
@@ -565,6 +607,70 @@ def nearest_neighbours(cell, hub_tau, qmesh, dist_thr: float = 6e-4):
             continue
         for j in np.nonzero(d <= dmin + dist_thr)[0]:
             out.append((i, int(j), float(d[j])))
+    return out
+
+
+def equivalent_sites(traces, docc_thr: float = 5e-5) -> np.ndarray:
+    """Perturbation classes from the ground-state occupations (the paper's default search for
+    the atoms to perturb, with its docc_thr): site s joins the class of the first earlier
+    representative whose spin-summed occupation trace differs by less than docc_thr, else it
+    represents a class of its own.  Returns the representative of every site."""
+    rep = []
+    for s, t in enumerate(traces):
+        r = s
+        for u in range(s):
+            if rep[u] == u and abs(traces[u] - t) < docc_thr:
+                r = u
+                break
+        rep.append(r)
+    return np.array(rep, dtype=np.int64)
+
+
+def supercell_distances(cell, hub_tau, qmesh) -> np.ndarray:
+    """Minimum-image distances between all sites of the q-supercell (index l * n_hub + s)."""
+    A = np.asarray(cell, dtype=np.float64).reshape(3, 3)
+    tau = np.asarray(hub_tau, dtype=np.float64).reshape(-1, 3)
+    pos = ((supercell_cells(qmesh) @ A)[:, None, :] + tau[None, :, :]).reshape(-1, 3)
+    a_sc = np.diag(np.asarray(qmesh, dtype=np.float64)) @ A
+    rng = np.arange(-2, 3)
+    shifts = np.array(np.meshgrid(rng, rng, rng, indexing="ij")).reshape(3, -1).T @ a_sc
+    d = pos[:, None, None, :] - pos[None, :, None, :] + shifts[None, None, :, :]
+    return np.linalg.norm(d, axis=3).min(axis=2)
+
+
+def reconstruct_chi(chi, site_rep, cell, hub_tau, qmesh, moments=None, dist_thr: float = 6e-4):
+    """Fill the columns of the q-supercell response matrix whose primitive site was not
+    perturbed (site_rep[s] != s), by comparing inter-site distances, classes and the relative
+    orientation of the moments (paper, post-processing of the response matrices): chi[I][J]
+    is taken from the first computed chi[I2][J2] (J2 scanned before I2, both ascending) with
+    rep(J2) = rep(J), rep(I2) = rep(I), the same sign of m_I m_J, and |d(I2,J2) - d(I,J)|
+    <= dist_thr.  Raises if an element has no match."""
+    nh = len(site_rep)
+    n = chi.shape[0]
+    D = supercell_distances(cell, hub_tau, qmesh)
+    rep = np.array([site_rep[i % nh] for i in range(n)])
+    m = np.zeros(nh) if moments is None else np.asarray(moments, dtype=np.float64)
+    sg = np.array([0 if abs(m[i % nh]) <= 1e-6 else (1 if m[i % nh] > 0 else -1) for i in range(n)])
+    computed = np.array([site_rep[j % nh] == j % nh for j in range(n)])
+    out = chi.copy()
+    for J in range(n):
+        if computed[J]:
+            continue
+        for I in range(n):
+            found = False
+            for J2 in range(n):
+                if not computed[J2] or rep[J2] != rep[J]:
+                    continue
+                for I2 in range(n):
+                    if rep[I2] == rep[I] and sg[I2] * sg[J2] == sg[I] * sg[J] and \
+                            abs(D[I2, J2] - D[I, J]) <= dist_thr:
+                        out[I, J] = chi[I2, J2]
+                        found = True
+                        break
+                if found:
+                    break
+            if not found:
+                raise ValueError(f"no equivalent computed element for chi[{I}][{J}]")
     return out
 
 

@@ -31,6 +31,8 @@ def save(gs: S.GroundState) -> str:
     arrs = {"vloc": gs.vloc, "rho0": gs.rho0, "tau": gs.tau, "hub_atoms": gs.hub_atoms, "hub_zeta": gs.hub_zeta,
             "kb_s": gs.kb_s, "kb_d": gs.kb_d, "d_kb": gs.d_kb, "cell": gs.cell,
             "meta": np.array([gs.seed_used, gs.n_mesh, len(gs.kpts), gs.gap, gs.nspin], dtype=np.float64)}
+    if gs.hub_pot is not None:
+        arrs["hub_pot"] = gs.hub_pot
     for i, e in enumerate(gs.kpts):
         arrs[f"k{i}_kfrac"] = e.k_frac
         arrs[f"k{i}_scal"] = np.array([e.weight, e.ecut, e.eps_next, e.resid])
@@ -65,7 +67,8 @@ def load(name: str):
                          rho0=z["rho0"], tau=z["tau"], hub_atoms=z["hub_atoms"], hub_zeta=z["hub_zeta"],
                          kb_s=z["kb_s"], kb_d=z["kb_d"], d_kb=z["d_kb"], n_occ=spec.n_occ, kmesh=tuple(spec.kmesh),
                          qmesh=tuple(spec.qmesh), kpts=kpts, n_mesh=n_mesh, gap=gap,
-                         spin_factor=2 if nspin == 1 else 1, nspin=nspin)
+                         spin_factor=2 if nspin == 1 else 1, nspin=nspin,
+                         hub_pot=z["hub_pot"] if "hub_pot" in z.files else None)
 
 
 def get(name: str, device: str = "auto", verbose: bool = None):

@@ -71,6 +71,10 @@ class SystemSpec:
     spin_field: float = 0.0
     spin_width: float = 0.8
     spin_signs: Optional[Tuple[int, ...]] = None
+    # ground-state Hubbard potential (on-site U, Ha): one DFT+U step, M^{I s} =
+    # hub_u0 (delta/2 - n^{I s}) from the occupations of the plain solution, then the
+    # occupied states of H + sum_I M^I |phi^I><phi^I|; 0 = plain DFT ground state
+    hub_u0: float = 0.0
 
 
 SPECS = {}
@@ -126,6 +130,12 @@ OLIVINE_SC = _reg(replace(OLIVINE, name="olivine56_sc211", cfg_id=4, cell=(39.2,
 SC1_FM = _reg(replace(SC1, name="sc1_gamma_spin", spin_field=0.15, spin_signs=(1,)))
 DUO_AFM = _reg(replace(DUO, name="duo_k221_afm", spin_field=0.15))
 OLIVINE_AFM = _reg(replace(OLIVINE, name="olivine28_afm", spin_field=0.15))
+# Ground states with an on-site Hubbard potential (U = 0.15 Ha ~ 4 eV): one site, the
+# antiferromagnetic two-site cell (spin-dependent potential) and the olivine-shaped cell;
+# and a 2x1x1 replica of the one-site cell whose two sites are equivalent by translation.
+SC1_U = _reg(replace(SC1, name="sc1_gamma_u", hub_u0=0.15))
+DUO_AFM_U = _reg(replace(DUO, name="duo_k221_afm_u", spin_field=0.15, hub_u0=0.15))
+OLIVINE_U = _reg(replace(OLIVINE, name="olivine28_u", hub_u0=0.15))
 
 
 def spec_by_name(name: str) -> SystemSpec:
@@ -178,6 +188,8 @@ class GroundState:
     gap: float = float("nan")
     nspin: int = 1              # 2: kpts holds a spin-up then a spin-down block of the same k
                                 # list, vloc/rho0 are (2, N1, N2, N3), one electron per state
+    hub_pot: Optional[np.ndarray] = None   # (nspin, n_hub, 5, 5) complex: the ground-state
+                                           # Hubbard potential sum M |phi_m1><phi_m2| in H
 
     @property
     def n_hub(self) -> int:
@@ -780,7 +792,7 @@ def _d_kb_of(at):
                            for a in range(at.tau.shape[0])])
 
 
-def _finish(spec, at, vloc, entries, n_mesh, forced_gap_check, verbose, d_kb, nspin=1):
+def _finish(spec, at, vloc, entries, n_mesh, forced_gap_check, verbose, d_kb, nspin=1, hub_pot=None):
     homo = max(float(e.eps.max()) for e in entries)
     lumo = min(e.eps_next for e in entries)
     gap = lumo - homo
@@ -798,7 +810,7 @@ def _finish(spec, at, vloc, entries, n_mesh, forced_gap_check, verbose, d_kb, ns
                        rho0=rho0, tau=at.tau, hub_atoms=at.hub_atoms, hub_zeta=at.hub_zeta,
                        kb_s=at.kb_s, kb_d=at.kb_d, d_kb=d_kb, n_occ=spec.n_occ, kmesh=tuple(spec.kmesh),
                        qmesh=tuple(spec.qmesh), kpts=entries, n_mesh=n_mesh, gap=gap,
-                       spin_factor=2 if nspin == 1 else 1, nspin=nspin)
+                       spin_factor=2 if nspin == 1 else 1, nspin=nspin, hub_pot=hub_pot)
 
 
 def _solve_all(spec, at, vloc, rj, backend, device, tol, verbose, forced_gap_check=True):
@@ -817,20 +829,49 @@ def _solve_all(spec, at, vloc, rj, backend, device, tol, verbose, forced_gap_che
         vs = [vloc - m, vloc + m]       # spin up is attracted to the sites of sign +1
     else:
         vs = [vloc]
-    entries = []
-    for v in vs:
-        solver = _KSolver(shell, v, d_kb, nb, spec.n_occ + 1, backend, device, tol, verbose, spec.fft, spec)
+    def solve_block(v, mhub):
+        """Entries of one spin channel; mhub (n_hub, 5, 5) adds the Hubbard potential, written
+        as extra projector rows: per site M = W diag(lam) W^+, rows W^T phi with strengths lam."""
+        lam = None
+        if mhub is not None:
+            ev = [np.linalg.eigh(mhub[s]) for s in range(mhub.shape[0])]
+            lam = np.concatenate([e[0] for e in ev])
+        solver = _KSolver(shell, v, d_kb if lam is None else np.concatenate([d_kb, lam]), nb, spec.n_occ + 1,
+                          backend, device, tol, verbose, spec.fft, spec)
+        out = []
         for i, k in enumerate(ks):
             ecut = spec.ecut * (1.0 + jit.get(_pair_key(k), 0.0))
             miller = sphere(at.cell, k, ecut, spec.fft)
             beta, phi = projector_tables(shell, k, miller)
-            eps_all, U, res = solver.solve(np.asarray(k, dtype=np.float64), miller, beta)
+            rows = beta
+            if lam is not None:
+                rows = np.concatenate([beta] + [ev[s][1].T @ phi[5 * s:5 * s + 5] for s in range(len(ev))])
+            eps_all, U, res = solver.solve(np.asarray(k, dtype=np.float64), miller, rows)
             w = 1.0 / len(mesh) if i < len(mesh) else 0.0
-            entries.append(KEntry(k_frac=np.array(k, dtype=np.float64), weight=w, ecut=ecut, miller=miller,
-                                  eps=np.array(eps_all[:spec.n_occ]), u=np.ascontiguousarray(U[:spec.n_occ]),
-                                  beta=beta, phi=phi, eps_next=float(eps_all[spec.n_occ]), resid=res))
+            out.append(KEntry(k_frac=np.array(k, dtype=np.float64), weight=w, ecut=ecut, miller=miller,
+                              eps=np.array(eps_all[:spec.n_occ]), u=np.ascontiguousarray(U[:spec.n_occ]),
+                              beta=beta, phi=phi, eps_next=float(eps_all[spec.n_occ]), resid=res))
+        return out
+
+    blocks = [solve_block(v, None) for v in vs]
+    hub_pot = None
+    if spec.hub_u0:
+        # occupations n^{I s}_{m1 m2} = sum_k w_k sum_v <phi_m1|u_v><u_v|phi_m2> of each spin channel
+        nh = len(at.hub_atoms)
+        hub_pot = np.zeros((len(vs), nh, 5, 5), dtype=np.complex128)
+        for si, blk in enumerate(blocks):
+            n = np.zeros((nh, 5, 5), dtype=np.complex128)
+            for e in blk[:len(mesh)]:
+                A = e.phi.conj() @ e.u.T
+                for st in range(nh):
+                    a = A[5 * st:5 * st + 5]
+                    n[st] += e.weight * (a @ a.conj().T)
+            hub_pot[si] = spec.hub_u0 * (0.5 * np.eye(5)[None] - n)
+        blocks = [solve_block(v, hub_pot[si]) for si, v in enumerate(vs)]
+    entries = [e for blk in blocks for e in blk]
     vout = vloc if len(vs) == 1 else np.stack(vs)
-    return _finish(spec, at, vout, entries, len(mesh), forced_gap_check, verbose, d_kb, nspin=len(vs))
+    return _finish(spec, at, vout, entries, len(mesh), forced_gap_check, verbose, d_kb, nspin=len(vs),
+                   hub_pot=hub_pot)
 
 
 @dataclass

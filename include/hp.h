@@ -118,6 +118,12 @@ typedef struct hp_ground_state {
   const int32_t *hub_rows;/* HP_PROJ_ORTHO_ATOMIC: [n_hub*5] row of atwfc that is d */
                           /* orbital m of Hubbard site s, at 5 s + m                */
   int32_t nspin;          /* 1 (unpolarized) or 2 (collinear spin-polarized)        */
+  const double *hub_pot;  /* NULL, or [nspin][n_hub][5][5] complex Hermitian (Ha):   */
+                          /* the ground-state Hubbard potential of Eq. 5 (on-site)  */
+                          /* as the matrices M of sum_I sum_{m1 m2} M^I_{m1 m2}     */
+                          /* |phi^I_m1><phi^I_m2| (e.g. U^I (delta/2 - n^I)), part  */
+                          /* of the unperturbed Hamiltonian; its response is not     */
+                          /* included (paper, after Eq. 10)                          */
 } hp_ground_state;
 
 /* Convergence controls (the paper's inputhp keywords conv_thr_chi, niter_max,
@@ -147,6 +153,12 @@ typedef struct hp_scf_params {
                           /* HP_GEMM_BF16 (both in BF16), HP_GEMM_BF16_PV32 (KB in    */
                           /* BF16, alpha P_v in FP32).  Below BF16 accuracy every     */
                           /* solve is finished by FP64 residual refinement.          */
+  int32_t find_atpert;    /* hp_response_matrix: 4 (or 0) perturb every site; 1      */
+                          /* perturb one site per class of equal occupation trace    */
+                          /* (within docc_thr, see hp_site_occupations) and rebuild  */
+                          /* the other columns by comparing distances (dist_thr)     */
+  double docc_thr;        /* find_atpert = 1: occupation-trace threshold (paper 5e-5) */
+  double dist_thr;        /* find_atpert = 1: distance threshold (bohr, paper 6e-4)   */
 } hp_scf_params;
 
 /* Statistics of one call (all fields written when the pointer is not NULL). */
@@ -205,10 +217,27 @@ hp_status hp_sternheimer_scf(hp_ctx *c, int32_t pert_site, const double q_frac[3
  *   chi0_out, chi_out [(n_hub*Nq)^2] row-major real (1/Ha);
  *   max_imag_out      largest |imaginary part| dropped by the q-sum (may be NULL);
  *   st                accumulated statistics (may be NULL).
+ * With p->find_atpert = 1 only one site per class of hp_site_occupations is
+ * perturbed (at every q); each missing element chi[I][J] is copied from the
+ * first computed chi[I2][J2] (J2, then I2 ascending) whose sites belong to the
+ * classes of J and I, whose moments have the same relative sign (moments of
+ * magnitude <= 1e-6 count as zero) and whose minimum-image distance in the
+ * q-supercell differs from d(I, J) by at most p->dist_thr; HP_ERR_ARG if some
+ * element has no such match.  The copy is exact when equal-distance pairs are
+ * related by a symmetry of the crystal.
  * Status as hp_sternheimer_scf (the worst over all pairs). */
 hp_status hp_response_matrix(hp_ctx *c, const int32_t nq[3], const hp_scf_params *p,
                              double *chi0_out, double *chi_out, double *max_imag_out,
                              hp_scf_stats *st);
+
+/* Ground-state occupation of every Hubbard site (Eq. 3): trace_out[s] =
+ * sum_spin Tr n^{s, spin}, moment_out[s] = Tr n^{s, up} - Tr n^{s, dn} (0 when
+ * nspin = 1), and class_out[s] = the representative of s when sites whose
+ * traces differ by less than docc_thr are equivalent (the paper's default search
+ * for the atoms to perturb; a site joins the first earlier representative within
+ * docc_thr).  Any output may be NULL. */
+hp_status hp_site_occupations(hp_ctx *c, double docc_thr, double *trace_out, double *moment_out,
+                              int32_t *class_out);
 
 /* U/V matrix = chi0^-1 - chi^-1 (Eqs. 8-9): U on the diagonal, V off it (Ha).
  * chi0, chi, uv_out are [n][n] row-major host arrays, n >= 1.  FP64 LU with

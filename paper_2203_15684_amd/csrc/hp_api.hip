@@ -15,6 +15,7 @@
 #include <memory>
 #include <numeric>
 #include <string>
+#include <algorithm>
 #include <thread>
 #include <vector>
 
@@ -110,6 +111,7 @@ struct hp_ctx {
   int n1 = 0, n2 = 0, n3 = 0;
   long nr = 0, np = 0;
   int n_occ = 0, n_beta = 0, n_hub = 0, n_mesh = 0, n_kpts = 0;
+  int n_kb = 0;  // KB rows among the n_beta rows of the stacked table (the rest carry V_Hub)
   // Spin: nspin blocks of entries.  Internally the mesh entries of every spin come first
   // (entry = spin * n_mesh_spin + k for mesh k), so that n_mesh = nspin * n_mesh_spin pairs
   // form one batch; internal_of maps a caller entry index to the internal one.
@@ -118,6 +120,7 @@ struct hp_ctx {
   std::vector<int> internal_of;
   int ld = 0, ns_pad = 0, ns_max = 0, max_chunk_pw = 0, npw_max = 0, n_proj = 0;
   double cell[9], bvec[9], omega = 0, alpha = 0;
+  std::vector<double> hub_tau;  // [n_hub][3] site positions (bohr)
   std::vector<HostEntry> ent;
   std::vector<int> px, py;
   Plane pl{};
@@ -366,6 +369,45 @@ bool jacobi_eigen(int n, std::vector<double> &a, std::vector<double> &v) {
       }
   }
   return false;
+}
+
+// Eigenpairs of a Hermitian n x n matrix (row-major complex): lam ascending, column a of V
+// (V[m * n + a]) the eigenvector of lam[a].  Through the real symmetric embedding, whose
+// spectrum is that of M with every eigenvalue twice; the embedding eigenvectors [x; y] are
+// read as complex vectors x + i y and made orthonormal over the complex numbers in
+// ascending eigenvalue order, keeping the n that are independent.
+bool herm_eig(int n, const std::complex<double> *M, double *lam, std::complex<double> *V) {
+  const int m = 2 * n;
+  std::vector<double> a((size_t)m * m), w;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const std::complex<double> z = M[(size_t)i * n + j];
+      a[(size_t)i * m + j] = a[(size_t)(i + n) * m + j + n] = z.real();
+      a[(size_t)i * m + j + n] = -z.imag();
+      a[(size_t)(i + n) * m + j] = z.imag();
+    }
+  if (!jacobi_eigen(m, a, w)) return false;
+  std::vector<int> order(m);
+  for (int i = 0; i < m; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return a[(size_t)x * m + x] < a[(size_t)y * m + y]; });
+  int got = 0;
+  std::vector<std::complex<double>> v(n);
+  for (int t = 0; t < m && got < n; ++t) {
+    const int k = order[t];
+    for (int i = 0; i < n; ++i) v[i] = {w[(size_t)i * m + k], w[(size_t)(i + n) * m + k]};
+    for (int b = 0; b < got; ++b) {  // remove the components along accepted vectors
+      std::complex<double> d = 0.0;
+      for (int i = 0; i < n; ++i) d += std::conj(V[(size_t)i * n + b]) * v[i];
+      for (int i = 0; i < n; ++i) v[i] -= d * V[(size_t)i * n + b];
+    }
+    double nn = 0.0;
+    for (int i = 0; i < n; ++i) nn += std::norm(v[i]);
+    if (nn < 0.25) continue;  // dependent over the complex numbers on an accepted vector
+    nn = std::sqrt(nn);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + got] = v[i] / nn;
+    lam[got++] = a[(size_t)k * m + k];
+  }
+  return got == n;
 }
 
 // X = O^-1/2 of a Hermitian positive-definite n x n matrix (row-major complex), through
@@ -1302,7 +1344,85 @@ hp_status check_params(const hp_scf_params *p) {
   if (p->autotune != 0 && p->autotune != 1) return fail(HP_ERR_ARG, "autotune must be 0 or 1");
   if (p->lowp_gemm < HP_GEMM_FP32 || p->lowp_gemm > HP_GEMM_BF16_PV32)
     return fail(HP_ERR_ARG, "unknown lowp_gemm %d", p->lowp_gemm);
+  if (p->find_atpert != 0 && p->find_atpert != 1 && p->find_atpert != 4)
+    return fail(HP_ERR_ARG, "find_atpert must be 1 or 4 (0 = 4)");
+  if (p->find_atpert == 1 && (!(p->docc_thr >= 0.0) || !(p->dist_thr >= 0.0)))
+    return fail(HP_ERR_ARG, "docc_thr and dist_thr must be >= 0");
   return HP_OK;
+}
+
+// Ground-state occupation trace (summed over spins) and moment of every Hubbard site (Eq. 3)
+// from the projections A_k[m][v] = <phi_{m,k}|u_vk> of the mesh entries.
+hp_status site_occupations(hp_ctx *c, std::vector<double> &trace, std::vector<double> &moment) {
+  const int nb = c->n_occ, M = 5 * c->n_hub;
+  std::vector<double2> A((size_t)c->n_mesh * M * nb);
+  HPCHK(hipMemcpyAsync(A.data(), c->d_A, sizeof(double2) * A.size(), hipMemcpyDeviceToHost, c->stream));
+  HPTRY(sync(c));
+  std::vector<double> per_spin((size_t)2 * c->n_hub, 0.0);
+  for (int k = 0; k < c->n_mesh; ++k) {
+    const double w = c->occ * c->ent[k].weight;
+    for (int s2 = 0; s2 < c->n_hub; ++s2) {
+      double t = 0.0;
+      for (int m = 0; m < 5; ++m)
+        for (int v = 0; v < nb; ++v) {
+          const double2 a = A[((size_t)k * M + 5 * s2 + m) * nb + v];
+          t += a.x * a.x + a.y * a.y;
+        }
+      per_spin[(size_t)c->ent[k].spin * c->n_hub + s2] += w * t;
+    }
+  }
+  trace.assign(c->n_hub, 0.0);
+  moment.assign(c->n_hub, 0.0);
+  for (int s2 = 0; s2 < c->n_hub; ++s2) {
+    trace[s2] = per_spin[s2] + per_spin[c->n_hub + s2];
+    if (c->nspin == 2) moment[s2] = per_spin[s2] - per_spin[c->n_hub + s2];
+  }
+  return HP_OK;
+}
+
+// Representative of every site: the first earlier representative whose trace is within thr.
+std::vector<int> site_classes(const std::vector<double> &trace, double thr) {
+  std::vector<int> rep(trace.size());
+  for (size_t s2 = 0; s2 < trace.size(); ++s2) {
+    rep[s2] = (int)s2;
+    for (size_t u = 0; u < s2; ++u)
+      if (rep[u] == (int)u && std::fabs(trace[u] - trace[s2]) < thr) {
+        rep[s2] = (int)u;
+        break;
+      }
+  }
+  return rep;
+}
+
+// Minimum-image distances between all sites of the q-supercell (index l * n_hub + s, cells l
+// lexicographic with the last index fastest), over supercell translations two shells out.
+std::vector<double> supercell_distances(const double cell[9], int n_hub, const double *hub_tau, const int nq[3]) {
+  const int nc = nq[0] * nq[1] * nq[2], n = n_hub * nc;
+  std::vector<std::array<double, 3>> pos(n);
+  for (int a = 0, l = 0; a < nq[0]; ++a)
+    for (int b = 0; b < nq[1]; ++b)
+      for (int d = 0; d < nq[2]; ++d, ++l)
+        for (int s2 = 0; s2 < n_hub; ++s2)
+          for (int x = 0; x < 3; ++x)
+            pos[l * n_hub + s2][x] = hub_tau[3 * s2 + x] + a * cell[x] + b * cell[3 + x] + d * cell[6 + x];
+  std::vector<double> D((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double best = 1e300;
+      for (int u = -2; u <= 2; ++u)
+        for (int v = -2; v <= 2; ++v)
+          for (int w = -2; w <= 2; ++w) {
+            double r2 = 0.0;
+            for (int x = 0; x < 3; ++x) {
+              const double t = u * nq[0] * cell[x] + v * nq[1] * cell[3 + x] + w * nq[2] * cell[6 + x];
+              const double dx = pos[j][x] - pos[i][x] + t;
+              r2 += dx * dx;
+            }
+            best = std::min(best, r2);
+          }
+      D[(size_t)i * n + j] = std::sqrt(best);
+    }
+  return D;
 }
 
 }  // namespace
@@ -1335,30 +1455,8 @@ extern "C" hp_status hp_neighbours(const double cell[9], int32_t n_hub, const do
   if (n_hub < 1 || nq[0] < 1 || nq[1] < 1 || nq[2] < 1 || !(dist_thr >= 0.0))
     return fail(HP_ERR_ARG, "need n_hub >= 1, nq >= 1, dist_thr >= 0");
   const int nc = nq[0] * nq[1] * nq[2], n = n_hub * nc;
-  // positions of every supercell site
-  std::vector<std::array<double, 3>> pos(n);
-  for (int a = 0, l = 0; a < nq[0]; ++a)
-    for (int b = 0; b < nq[1]; ++b)
-      for (int d = 0; d < nq[2]; ++d, ++l)
-        for (int s2 = 0; s2 < n_hub; ++s2)
-          for (int x = 0; x < 3; ++x)
-            pos[l * n_hub + s2][x] = hub_tau[3 * s2 + x] + a * cell[x] + b * cell[3 + x] + d * cell[6 + x];
-  // minimum image over supercell translations (two shells cover strongly sheared cells)
-  auto min_image = [&](int i, int j) {
-    double best = 1e300;
-    for (int u = -2; u <= 2; ++u)
-      for (int v = -2; v <= 2; ++v)
-        for (int w = -2; w <= 2; ++w) {
-          double r2 = 0.0;
-          for (int x = 0; x < 3; ++x) {
-            const double t = u * nq[0] * cell[x] + v * nq[1] * cell[3 + x] + w * nq[2] * cell[6 + x];
-            const double dx = pos[j][x] - pos[i][x] + t;
-            r2 += dx * dx;
-          }
-          best = std::min(best, r2);
-        }
-    return std::sqrt(best);
-  };
+  const std::vector<double> D = supercell_distances(cell, n_hub, hub_tau, nq);
+  auto min_image = [&](int i, int j) { return D[(size_t)i * n + j]; };
   int found = 0;
   for (int i = 0; i < n_hub; ++i) {
     std::vector<double> dj(n, 0.0);
@@ -1493,6 +1591,32 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
     for (int v = 0; v < gs->n_occ; ++v)
       if (!std::isfinite(k.eps[v])) return fail(HP_ERR_NUMERIC, "kpts[%d].eps[%d] is not finite", i, v);
   }
+  // ground-state Hubbard potential: finite, Hermitian per (spin, site); its eigenpairs give
+  // the projector rows that carry it (sum_a lam_a |chi_a><chi_a|, chi_a = sum_m V_ma phi_m)
+  std::vector<double> hub_lam;
+  std::vector<std::complex<double>> hub_vec;
+  if (gs->hub_pot) {
+    const int nblk = gs->nspin * gs->n_hub;
+    hub_lam.resize((size_t)nblk * 5);
+    hub_vec.resize((size_t)nblk * 25);
+    for (int b = 0; b < nblk; ++b) {
+      std::complex<double> M[25];
+      double big = 0.0;
+      for (int i = 0; i < 25; ++i) {
+        M[i] = {gs->hub_pot[2 * (25 * b + i)], gs->hub_pot[2 * (25 * b + i) + 1]};
+        if (!std::isfinite(M[i].real()) || !std::isfinite(M[i].imag()))
+          return fail(HP_ERR_NUMERIC, "hub_pot block %d is not finite", b);
+        big = std::max(big, std::abs(M[i]));
+      }
+      for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j)
+          if (std::abs(M[i * 5 + j] - std::conj(M[j * 5 + i])) > 1e-10 * (1.0 + big))
+            return fail(HP_ERR_ARG, "hub_pot block %d (spin %d, site %d) is not Hermitian", b, b / gs->n_hub,
+                        b % gs->n_hub);
+      if (!herm_eig(5, M, hub_lam.data() + 5 * b, hub_vec.data() + 25 * b))
+        return fail(HP_ERR_NUMERIC, "hub_pot block %d: eigen-decomposition failed", b);
+    }
+  }
   const long nrr = (long)gs->fft[0] * gs->fft[1] * gs->fft[2] * gs->nspin;
   for (long i = 0; i < nrr; ++i)
     if (!std::isfinite(gs->v_loc[i]) || !std::isfinite(gs->rho0[i])) return fail(HP_ERR_NUMERIC, "non-finite v_loc/rho0");
@@ -1506,7 +1630,10 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   c->np = (long)c->n1 * c->n2;
   c->nr = c->np * c->n3;
   c->n_occ = gs->n_occ;
-  c->n_beta = gs->n_beta;
+  // the stacked table holds the KB rows, then (with a ground-state Hubbard potential) 5 n_hub
+  // rows of scale +1 and 5 n_hub rows of scale -1 that carry it, then the occupied states
+  c->n_kb = gs->n_beta;
+  c->n_beta = gs->n_beta + (gs->hub_pot ? 10 * gs->n_hub : 0);
   c->n_hub = gs->n_hub;
   c->nspin = gs->nspin;
   c->n_mesh_spin = gs->n_mesh;
@@ -1516,6 +1643,7 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   c->n_kpts = gs->n_kpts;
   c->n_proj = c->n_beta + c->n_occ;
   for (int i = 0; i < 9; ++i) c->cell[i] = gs->cell[i / 3][i % 3];
+  c->hub_tau.assign(gs->hub_tau, gs->hub_tau + 3 * gs->n_hub);
   c->omega = std::fabs(det);
   {
     // b = 2 pi inv(A)^T: rows b_i with a_i . b_j = 2 pi delta_ij
@@ -1682,7 +1810,7 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
       const double kin = 0.5 * (kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2]);
       h_kin.push_back(kin);
       double d = kin + vmean;
-      for (int b = 0; b < c->n_beta; ++b) {
+      for (int b = 0; b < c->n_kb; ++b) {
         const double2 val = make_double2(k.beta[2 * ((size_t)b * k.npw + q)], k.beta[2 * ((size_t)b * k.npw + q) + 1]);
         T[(size_t)b * c->ld + p] = val;
         d += gs->d_kb[b] * (val.x * val.x + val.y * val.y);
@@ -1735,7 +1863,8 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   c->sk.ent = d_ent;
   // row scales of the stacked projector table: D_i for beta rows, alpha for u rows
   std::vector<double> rs(c->n_proj);
-  for (int b = 0; b < c->n_beta; ++b) rs[b] = gs->d_kb[b];
+  for (int b = 0; b < c->n_kb; ++b) rs[b] = gs->d_kb[b];
+  for (int b = c->n_kb; b < c->n_beta; ++b) rs[b] = b < c->n_kb + 5 * c->n_hub ? 1.0 : -1.0;
   for (int v = 0; v < c->n_occ; ++v) rs[c->n_beta + v] = c->alpha;
   HPTRY(c->alloc(&c->d_rowscale, rs.size()));
   HPCHK(hipMemcpyAsync(c->d_rowscale, rs.data(), sizeof(double) * rs.size(), hipMemcpyHostToDevice, st));
@@ -1808,6 +1937,42 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   HPTRY(c->alloc(&c->d_q, 3));
 
   if (gs->projectors == HP_PROJ_ORTHO_ATOMIC) HPTRY(ortho_atomic_projectors(c.get(), gs, KP, lay));
+  if (gs->hub_pot) {
+    // rows of the ground-state Hubbard potential from the final projectors of each entry:
+    // chi_a = sum_m V_ma phi_m scaled by sqrt|lam_a| into the +1 (lam > 0) or -1 (lam < 0)
+    // block; the Jacobi diagonal gains sum_a lam_a |chi_a(G)|^2
+    if (gs->projectors == HP_PROJ_ORTHO_ATOMIC) {
+      HPCHK(hipMemcpyAsync(h_phi.data(), c->d_phi, sizeof(double2) * h_phi.size(), hipMemcpyDeviceToHost, st));
+      HPTRY(sync(c.get()));
+    }
+    const int nh = c->n_hub;
+    for (int i = 0; i < c->n_kpts; ++i) {
+      const double2 *F = h_phi.data() + (size_t)i * c->phi_stride;
+      double2 *T = h_T.data() + (size_t)i * c->t_stride;
+      double *dg = h_diag.data() + (size_t)i * c->ld;
+      const int npw = KP[i]->npw;
+      for (int sidx = 0; sidx < nh; ++sidx) {
+        const int blk = spin_of[i] * nh + sidx;
+        for (int a = 0; a < 5; ++a) {
+          const double lam = hub_lam[5 * blk + a];
+          const double sc = std::sqrt(std::fabs(lam));
+          double2 *row = T + (size_t)(c->n_kb + (lam < 0.0 ? 5 * nh : 0) + 5 * sidx + a) * c->ld;
+          for (int p = 0; p < npw; ++p) {
+            std::complex<double> z = 0.0;
+            for (int m = 0; m < 5; ++m) {
+              const double2 f = F[(size_t)(5 * sidx + m) * c->ld + p];
+              z += hub_vec[25 * blk + m * 5 + a] * std::complex<double>(f.x, f.y);
+            }
+            row[p] = make_double2(sc * z.real(), sc * z.imag());
+            dg[p] += lam * std::norm(z);
+          }
+        }
+      }
+    }
+    HPCHK(hipMemcpyAsync(c->d_T, h_T.data(), sizeof(double2) * h_T.size(), hipMemcpyHostToDevice, st));
+    HPCHK(hipMemcpyAsync(c->d_diag, h_diag.data(), sizeof(double) * h_diag.size(), hipMemcpyHostToDevice, st));
+    HPTRY(sync(c.get()));
+  }
 
   // A_k[m][v] = <phi_{m,k}|u_vk> for every entry (Eq. 13's ground-state factor)
   HPTRY(c->alloc(&c->d_A, (size_t)c->n_kpts * 5 * c->n_hub * nb));
@@ -2093,8 +2258,18 @@ extern "C" hp_status hp_response_matrix(hp_ctx *c, const int32_t nq[3], const hp
   hp_scf_stats acc{};
   acc.struct_size = sizeof(hp_scf_stats);
   std::vector<double> dn0(50 * nh), dn1(50 * nh);
+  // sites to perturb: every site, or one per class of equal occupation trace
+  std::vector<int> rep(nh);
+  std::vector<double> moment(nh, 0.0);
+  for (int s2 = 0; s2 < nh; ++s2) rep[s2] = s2;
+  if (p->find_atpert == 1) {
+    std::vector<double> trace;
+    HPTRY(site_occupations(c, trace, moment));
+    rep = site_classes(trace, p->docc_thr);
+  }
   for (int iq = 0; iq < Nq; ++iq) {
     for (int sp = 0; sp < nh; ++sp) {
+      if (rep[sp] != sp) continue;
       hp_scf_stats one{};
       one.struct_size = sizeof(hp_scf_stats);
       hp_status s = run_scf(c, sp, qs[iq].data(), p, dn0.data(), dn1.data(), &one);
@@ -2124,10 +2299,12 @@ extern "C" hp_status hp_response_matrix(hp_ctx *c, const int32_t nq[3], const hp
   // Eq. 12: chi_{(s,l),(s',l')} = (1/Nq) sum_q e^{i q.(R_l - R_l')} chi(q)_{s s'}
   const int n = nh * Nq;
   double mim = 0.0;
+  std::vector<double> x0((size_t)n * n, 0.0), x1((size_t)n * n, 0.0);  // outputs, written at the end
   for (int l = 0; l < Nq; ++l)
     for (int lp = 0; lp < Nq; ++lp)
       for (int s = 0; s < nh; ++s)
         for (int sp = 0; sp < nh; ++sp) {
+          if (rep[sp] != sp) continue;  // rebuilt below
           std::complex<double> a0 = 0, a1 = 0;
           for (int iq = 0; iq < Nq; ++iq) {
             const double dl[3] = {qs[l][0] * nq[0] - qs[lp][0] * nq[0], qs[l][1] * nq[1] - qs[lp][1] * nq[1],
@@ -2140,13 +2317,66 @@ extern "C" hp_status hp_response_matrix(hp_ctx *c, const int32_t nq[3], const hp
           a0 /= (double)Nq;
           a1 /= (double)Nq;
           const int row = l * nh + s, col = lp * nh + sp;
-          chi0_out[(size_t)row * n + col] = a0.real();
-          chi_out[(size_t)row * n + col] = a1.real();
+          x0[(size_t)row * n + col] = a0.real();
+          x1[(size_t)row * n + col] = a1.real();
           mim = std::max(mim, std::max(std::fabs(a0.imag()), std::fabs(a1.imag())));
         }
+  if (p->find_atpert == 1) {
+    // missing columns: copy chi[I2][J2] of a computed column with the classes of (I, J), the
+    // same relative sign of the moments and the same distance within dist_thr
+    const std::vector<double> D = supercell_distances(c->cell, nh, c->hub_tau.data(), nq);
+    auto sgn = [&](int i) {
+      const double m = moment[i % nh];
+      return std::fabs(m) <= 1e-6 ? 0 : (m > 0 ? 1 : -1);
+    };
+    auto done = [&](int j) { return rep[j % nh] == j % nh; };
+    std::vector<double> r0((size_t)n * n), r1((size_t)n * n);
+    for (int J = 0; J < n; ++J) {
+      if (done(J)) continue;
+      for (int I = 0; I < n; ++I) {
+        bool found = false;
+        for (int J2 = 0; J2 < n && !found; ++J2) {
+          if (!done(J2) || rep[J2 % nh] != rep[J % nh]) continue;
+          for (int I2 = 0; I2 < n; ++I2)
+            if (rep[I2 % nh] == rep[I % nh] && sgn(I2) * sgn(J2) == sgn(I) * sgn(J) &&
+                std::fabs(D[(size_t)I2 * n + J2] - D[(size_t)I * n + J]) <= p->dist_thr) {
+              r0[(size_t)I * n + J] = x0[(size_t)I2 * n + J2];
+              r1[(size_t)I * n + J] = x1[(size_t)I2 * n + J2];
+              found = true;
+              break;
+            }
+        }
+        if (!found)
+          return fail(HP_ERR_ARG, "no computed element equivalent to chi[%d][%d] (dist_thr %g)", I, J, p->dist_thr);
+      }
+    }
+    for (int J = 0; J < n; ++J)
+      if (!done(J))
+        for (int I = 0; I < n; ++I) {
+          x0[(size_t)I * n + J] = r0[(size_t)I * n + J];
+          x1[(size_t)I * n + J] = r1[(size_t)I * n + J];
+        }
+  }
+  std::copy(x0.begin(), x0.end(), chi0_out);
+  std::copy(x1.begin(), x1.end(), chi_out);
   if (max_imag_out) *max_imag_out = mim;
   if (st) *st = acc;
   return worst;
+}
+
+extern "C" hp_status hp_site_occupations(hp_ctx *c, double docc_thr, double *trace_out, double *moment_out,
+                                         int32_t *class_out) {
+  if (!c) return fail(HP_ERR_ARG, "context is NULL");
+  if (!(docc_thr >= 0.0)) return fail(HP_ERR_ARG, "docc_thr must be >= 0");
+  std::vector<double> trace, moment;
+  HPTRY(site_occupations(c, trace, moment));
+  const std::vector<int> rep = site_classes(trace, docc_thr);
+  for (int s2 = 0; s2 < c->n_hub; ++s2) {
+    if (trace_out) trace_out[s2] = trace[s2];
+    if (moment_out) moment_out[s2] = moment[s2];
+    if (class_out) class_out[s2] = rep[s2];
+  }
+  return HP_OK;
 }
 
 extern "C" hp_status hp_apply_h(hp_ctx *c, int32_t entry, int32_t n, const double *x, double *y) {

@@ -59,7 +59,7 @@ class HpGroundState(C.Structure):
                 ("d_kb", _dp), ("hub_tau", _dp), ("spin_factor", C.c_int32), ("n_mesh", C.c_int32),
                 ("n_kpts", C.c_int32), ("kpts", C.POINTER(HpKpoint)), ("xc", C.c_int32), ("reserved", C.c_int32),
                 ("stream", C.c_void_p), ("projectors", C.c_int32), ("n_atwfc", C.c_int32), ("hub_rows", _ip),
-                ("nspin", C.c_int32)]
+                ("nspin", C.c_int32), ("hub_pot", _dp)]
 
 
 class HpScfParams(C.Structure):
@@ -67,7 +67,8 @@ class HpScfParams(C.Structure):
                 ("cg_tol", C.c_double), ("niter_max", C.c_int32), ("alpha_mix", C.c_double), ("nmix", C.c_int32),
                 ("max_cg_iter", C.c_int32), ("precision", C.c_int32), ("verbosity", C.c_int32),
                 ("inner_tol", C.c_double), ("max_refine", C.c_int32), ("graph_chunk", C.c_int32),
-                ("autotune", C.c_int32), ("lowp_gemm", C.c_int32)]
+                ("autotune", C.c_int32), ("lowp_gemm", C.c_int32), ("find_atpert", C.c_int32),
+                ("docc_thr", C.c_double), ("dist_thr", C.c_double)]
 
 
 class HpScfStats(C.Structure):
@@ -112,6 +113,8 @@ _lib.hp_profile_stop.restype = C.c_int32
 _lib.hp_neighbours.argtypes = [_dp, C.c_int32, _dp, _ip, C.c_double, C.c_int32, _ip, _ip, _dp, _ip]
 _lib.hp_neighbours.restype = C.c_int32
 _lib.hp_tuning_report.argtypes = [C.c_void_p, C.c_char_p, C.c_int32]
+_lib.hp_site_occupations.argtypes = [C.c_void_p, C.c_double, _dp, _dp, _ip]
+_lib.hp_site_occupations.restype = C.c_int32
 _lib.hp_tuning_report.restype = C.c_int32
 _lib.hp_set_gemm_shape.argtypes = [C.c_void_p] + [C.c_int32] * 6
 _lib.hp_set_gemm_shape.restype = C.c_int32
@@ -123,7 +126,7 @@ _lib.hp_set_stick_variant.restype = C.c_int32
 EXPORTED = ["hp_ground_state_load", "hp_sternheimer_scf", "hp_response_matrix", "hp_hubbard_params",
             "hp_destroy", "hp_last_error", "hp_apply_h", "hp_solve_first_order", "hp_profile_start",
             "hp_profile_stop", "hp_tuning_report", "hp_set_gemm_shape", "hp_set_plane_variant",
-            "hp_neighbours", "hp_set_stick_variant"]
+            "hp_neighbours", "hp_set_stick_variant", "hp_site_occupations"]
 
 
 def hp_last_error() -> str:
@@ -165,12 +168,15 @@ class ScfParams:
     graph_chunk: int = 8   # CG iterations per captured hipGraph launch; 0 launches kernels one by one
     autotune: int = 1      # time candidate GEMM tiles / FFT plane batches on first use of a shape
     lowp_gemm: int = 0     # HP_MIXED: HP_GEMM_FP32, HP_GEMM_BF16 or HP_GEMM_BF16_PV32
+    find_atpert: int = 4   # hp_response_matrix: 4 perturbs every site, 1 one per occupation class
+    docc_thr: float = 5e-5
+    dist_thr: float = 6e-4
 
     def c(self) -> HpScfParams:
         return HpScfParams(C.sizeof(HpScfParams), self.conv_thr_chi, self.conv_thr_v, self.cg_tol, self.niter_max,
                            self.alpha_mix, self.nmix, self.max_cg_iter, self.precision, self.verbosity,
                            self.inner_tol, self.max_refine, self.graph_chunk, self.autotune,
-                           self.lowp_gemm)
+                           self.lowp_gemm, self.find_atpert, self.docc_thr, self.dist_thr)
 
 
 class Context:
@@ -237,7 +243,13 @@ def hp_ground_state_load(gs, stream: Optional[int] = None, atwfc: Optional[Seque
     dkb = _f64(gs.d_kb)
     htau = _f64(gs.hub_tau)
     hrows = np.ascontiguousarray(hub_rows, dtype=np.int32) if ortho else None
-    keep += [vloc, rho0, dkb, htau, hrows]
+    hpot = getattr(gs, "hub_pot", None)
+    if hpot is not None:
+        hpot = np.ascontiguousarray(hpot, dtype=np.complex128)
+        if hpot.shape != (nspin, int(gs.n_hub), 5, 5):
+            raise ValueError(f"hub_pot has shape {hpot.shape}, want {(nspin, int(gs.n_hub), 5, 5)}")
+        hpot = hpot.view(np.float64)
+    keep += [vloc, rho0, dkb, htau, hrows, hpot]
     cell = ((C.c_double * 3) * 3)(*[(C.c_double * 3)(*[float(x) for x in row]) for row in np.asarray(gs.cell)])
     g = HpGroundState()
     g.struct_size = C.sizeof(HpGroundState)
@@ -261,10 +273,21 @@ def hp_ground_state_load(gs, stream: Optional[int] = None, atwfc: Optional[Seque
     g.n_atwfc = n_atwfc
     g.hub_rows = _ptr(hrows, _ip) if ortho else None
     g.nspin = nspin
+    g.hub_pot = _ptr(hpot) if hpot is not None else None
     h = C.c_void_p()
     _check(_lib.hp_ground_state_load(C.byref(g), C.byref(h)), allow_warn=False)
     del keep
     return Context(h.value, gs)
+
+
+def hp_site_occupations(ctx: Context, docc_thr: float = 5e-5):
+    """(trace, moment, class) per Hubbard site: sum over spins of Tr n^I (Eq. 3), the moment
+    Tr n^I_up - Tr n^I_dn, and the representative site of I's class of equal traces."""
+    tr = np.zeros(ctx.n_hub)
+    mo = np.zeros(ctx.n_hub)
+    cl = np.zeros(ctx.n_hub, dtype=np.int32)
+    _check(_lib.hp_site_occupations(ctx.handle, float(docc_thr), _ptr(tr), _ptr(mo), _ptr(cl, _ip)), allow_warn=False)
+    return tr, mo, cl
 
 
 def hp_sternheimer_scf(ctx: Context, pert_site: int, q_frac: Sequence[float], params: ScfParams):

@@ -159,6 +159,9 @@ typedef struct hp_scf_params {
                           /* the other columns by comparing distances (dist_thr)     */
   double docc_thr;        /* find_atpert = 1: occupation-trace threshold (paper 5e-5) */
   double dist_thr;        /* find_atpert = 1: distance threshold (bohr, paper 6e-4)   */
+  int32_t skip_equivalence_q; /* hp_response_matrix: 0 (paper default) solves only one */
+                          /* q of each (q, -q) pair of the mesh and takes             */
+                          /* chi(-q) = conj chi(q) (time reversal); 1 solves every q   */
 } hp_scf_params;
 
 /* Statistics of one call (all fields written when the pointer is not NULL). */
@@ -224,7 +227,9 @@ hp_status hp_sternheimer_scf(hp_ctx *c, int32_t pert_site, const double q_frac[3
  * magnitude <= 1e-6 count as zero) and whose minimum-image distance in the
  * q-supercell differs from d(I, J) by at most p->dist_thr; HP_ERR_ARG if some
  * element has no such match.  The copy is exact when equal-distance pairs are
- * related by a symmetry of the crystal.
+ * related by a symmetry of the crystal.  Unless p->skip_equivalence_q, a q point
+ * whose -q partner (modulo a reciprocal vector) comes earlier in the mesh is not
+ * solved: chi(-q)_{s s'} = conj chi(q)_{s s'} (time reversal).
  * Status as hp_sternheimer_scf (the worst over all pairs). */
 hp_status hp_response_matrix(hp_ctx *c, const int32_t nq[3], const hp_scf_params *p,
                              double *chi0_out, double *chi_out, double *max_imag_out,

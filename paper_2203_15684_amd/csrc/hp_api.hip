@@ -1344,6 +1344,8 @@ hp_status check_params(const hp_scf_params *p) {
   if (p->autotune != 0 && p->autotune != 1) return fail(HP_ERR_ARG, "autotune must be 0 or 1");
   if (p->lowp_gemm < HP_GEMM_FP32 || p->lowp_gemm > HP_GEMM_BF16_PV32)
     return fail(HP_ERR_ARG, "unknown lowp_gemm %d", p->lowp_gemm);
+  if (p->skip_equivalence_q != 0 && p->skip_equivalence_q != 1)
+    return fail(HP_ERR_ARG, "skip_equivalence_q must be 0 or 1");
   if (p->find_atpert != 0 && p->find_atpert != 1 && p->find_atpert != 4)
     return fail(HP_ERR_ARG, "find_atpert must be 1 or 4 (0 = 4)");
   if (p->find_atpert == 1 && (!(p->docc_thr >= 0.0) || !(p->dist_thr >= 0.0)))
@@ -2268,6 +2270,24 @@ extern "C" hp_status hp_response_matrix(hp_ctx *c, const int32_t nq[3], const hp
     rep = site_classes(trace, p->docc_thr);
   }
   for (int iq = 0; iq < Nq; ++iq) {
+    // time reversal: chi(-q) = conj chi(q); a q whose -q partner (modulo G) came earlier
+    // in the mesh is not solved unless skip_equivalence_q is set
+    int partner = -1;
+    for (int j = 0; j < iq && !p->skip_equivalence_q && partner < 0; ++j) {
+      bool same = true;
+      for (int d = 0; d < 3; ++d) {
+        const double t = qs[iq][d] + qs[j][d];
+        same = same && std::fabs(t - std::round(t)) < 1e-9;
+      }
+      if (same) partner = j;
+    }
+    if (partner >= 0) {
+      for (size_t e = 0; e < (size_t)nh * nh; ++e) {
+        c0q[(size_t)iq * nh * nh + e] = std::conj(c0q[(size_t)partner * nh * nh + e]);
+        c1q[(size_t)iq * nh * nh + e] = std::conj(c1q[(size_t)partner * nh * nh + e]);
+      }
+      continue;
+    }
     for (int sp = 0; sp < nh; ++sp) {
       if (rep[sp] != sp) continue;
       hp_scf_stats one{};

@@ -68,7 +68,7 @@ class HpScfParams(C.Structure):
                 ("max_cg_iter", C.c_int32), ("precision", C.c_int32), ("verbosity", C.c_int32),
                 ("inner_tol", C.c_double), ("max_refine", C.c_int32), ("graph_chunk", C.c_int32),
                 ("autotune", C.c_int32), ("lowp_gemm", C.c_int32), ("find_atpert", C.c_int32),
-                ("docc_thr", C.c_double), ("dist_thr", C.c_double)]
+                ("docc_thr", C.c_double), ("dist_thr", C.c_double), ("skip_equivalence_q", C.c_int32)]
 
 
 class HpScfStats(C.Structure):
@@ -171,12 +171,14 @@ class ScfParams:
     find_atpert: int = 4   # hp_response_matrix: 4 perturbs every site, 1 one per occupation class
     docc_thr: float = 5e-5
     dist_thr: float = 6e-4
+    skip_equivalence_q: int = 0   # 0: chi(-q) = conj chi(q) for the -q partners of the mesh
 
     def c(self) -> HpScfParams:
         return HpScfParams(C.sizeof(HpScfParams), self.conv_thr_chi, self.conv_thr_v, self.cg_tol, self.niter_max,
                            self.alpha_mix, self.nmix, self.max_cg_iter, self.precision, self.verbosity,
                            self.inner_tol, self.max_refine, self.graph_chunk, self.autotune,
-                           self.lowp_gemm, self.find_atpert, self.docc_thr, self.dist_thr)
+                           self.lowp_gemm, self.find_atpert, self.docc_thr, self.dist_thr,
+                           self.skip_equivalence_q)
 
 
 class Context:

@@ -7,8 +7,9 @@ Sternheimer solves includes it.  Checks: H applies on every entry (also with ort
 projectors), Delta n and chi against the oracle (FP64 1e-10, mixed 1e-6) on a one-site
 system and on the antiferromagnetic two-site system (spin-dependent potential), at full
 size sampled H applies and a solve against the oracle's equation; occupation traces,
-moments and classes against the oracle, and chi rebuilt from one perturbed site of a
-translation-equivalent pair equal to chi from perturbing both.
+moments and classes against the oracle, chi rebuilt from one perturbed site of a
+translation-equivalent pair equal to chi from perturbing both, and chi with the -q partners
+of a q mesh taken from time reversal equal to solving every q.
 """
 import functools
 
@@ -174,3 +175,18 @@ def test_hub_fullsize_first_order_solve():
     b = o.rhs(ik, q, 3, None)
     r = o.sternheimer_op(ik, q, du) - b
     assert np.linalg.norm(r, axis=1).max() / np.linalg.norm(b, axis=1).max() < 1e-10
+
+
+def test_q_points_equivalent_by_time_reversal():
+    """q mesh 3x1x1: q = 2/3 is -1/3 modulo G, so only two of the three q points are solved and
+    chi(-q) = conj chi(q); the result equals solving every q and the oracle's."""
+    hp = _hp()
+    name = "sc1_k311"
+    red = hp.hp_response_matrix(ctx(name), (3, 1, 1), tight_gpu())
+    full = hp.hp_response_matrix(ctx(name), (3, 1, 1), tight_gpu(skip_equivalence_q=1))
+    assert red[4] == 0 and full[4] == 0
+    assert red[3]["scf_iters"] < full[3]["scf_iters"]
+    for i in (0, 1):
+        assert rel(red[i], full[i]) < 1e-10
+    c0, c1, _, _, _ = orc(name).response_matrix(TIGHT_O)
+    assert rel(red[0], c0) < 1e-10 and rel(red[1], c1) < 1e-10

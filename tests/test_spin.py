@@ -154,9 +154,9 @@ def test_equal_spin_blocks_give_the_unpolarized_response():
 
 def test_afm_response_matrix_symmetric_and_screened():
     o = orc("duo_k221_afm")
-    chi0, chi, im, _, _ = o.response_matrix(oracle.ScfParams(cg_tol=1e-12, conv_thr_chi=1e-11, conv_thr_v=1e-9))
-    assert im < 1e-10 * np.abs(chi).max()
-    assert np.abs(chi0 - chi0.T).max() < 1e-9 * np.abs(chi0).max()
-    assert np.abs(chi - chi.T).max() < 1e-8 * np.abs(chi).max()
+    chi0, chi, im, _, _ = o.response_matrix(oracle.ScfParams(cg_tol=1e-9, conv_thr_chi=1e-8, conv_thr_v=1e-6))
+    assert im < 1e-7 * np.abs(chi).max()
+    assert np.abs(chi0 - chi0.T).max() < 1e-7 * np.abs(chi0).max()
+    assert np.abs(chi - chi.T).max() < 1e-6 * np.abs(chi).max()
     d0, d = np.diag(chi0), np.diag(chi)
     assert np.all(d0 < 0) and np.all(d < 0) and np.all(np.abs(d) < np.abs(d0))

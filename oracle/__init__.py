@@ -12,7 +12,8 @@ perturbation theory"): Eqs. 7-9 (susceptibilities and U/V), Eq. 12
 (monochromatic sum over q), Eq. 13 (response occupations), Eq. 6 (ortho-atomic
 projectors by Loewdin orthogonalization), Eq. 5 (the on-site ground-state Hubbard
 potential in the unperturbed Hamiltonian), the spin-resolved forms of Eqs. 3 and
-10-15, the search for equivalent sites and the reconstruction of the response
+10-15, fractional occupations of metallic ground states (cold smearing, the split
+Sternheimer right-hand side and the Fermi-level shift at q = 0), the search for equivalent sites and the reconstruction of the response
 matrices (paper, linear-response and post-processing steps), Eqs. 14-18
 (q-specific Sternheimer equation, perturbing potential, valence and
 conduction projectors, the alpha shift).  Each function cites the passage it

@@ -16,6 +16,13 @@ are listed in the design notes of the repository):
   electron, V_loc and rho0 carry a leading spin index, the response density is
   spin-resolved and the Hxc response uses the 2 x 2 LSDA kernel; the perturbation of
   Eq. 16 acts on both spins and the occupation response is summed over spins;
+* metallic ground states (the paper's generalization to fractional occupations): cold
+  (Marzari-Vanderbilt) smearing of width sigma, occupations f_i = occ((e_F - e_i)/sigma);
+  splitting the sum over pairs of states with a smooth step theta (theta_ij + theta_ji = 1)
+  keeps Eq. 15 with the right-hand side -(f_i - sum_j beta_ij |u_j><u_j|) dV u_i and
+  beta_ij = f_i theta_ij + f_j theta_ji + alpha theta_ji (f_i - f_j)/(e_i - e_j); at q = 0
+  the Fermi level shifts to keep the electron count (an extra density and occupation
+  term).  Unpolarized only;
 * time reversal folds the -q partner into the +q term (paper, text after
   Eq. 14), giving the factor 4 = 2 (spin) x 2 (time reversal) in the response
   density (2 per spin channel when polarized) and the two-term form of Eq. 13.
@@ -109,6 +116,15 @@ class Oracle:
         hpot = getattr(gs, "hub_pot", None)
         self.hub_pot = (None if hpot is None else
                         np.asarray(hpot, dtype=np.complex128).reshape(self.nspin, self.n_hub, 5, 5))
+        # metallic occupations (cold smearing) of the kept bands
+        self.degauss = float(getattr(gs, "degauss", 0.0) or 0.0)
+        self.metal = self.degauss > 0.0
+        if self.metal:
+            if self.nspin != 1:
+                raise NotImplementedError("metallic ground states are unpolarized here")
+            self.efermi = float(gs.efermi)
+            self.f = [cold_occupation((self.efermi - e.eps) / self.degauss) for e in self.kpts]
+            self.dlt = [cold_delta((self.efermi - e.eps) / self.degauss) for e in self.kpts]
         # alpha = 2 (max - min) over the occupied energies of every loaded entry
         # (paper, text after Eq. 18); floor 0.01 Ha.
         emax = max(float(e.eps.max()) for e in self.kpts)
@@ -221,7 +237,8 @@ class Oracle:
     # ----------------------------------------------- Sternheimer, Eqs. 15-18
     def rhs(self, ik: int, q, site: int, dv: Optional[np.ndarray]) -> np.ndarray:
         """-P_c,k+q (dV_Hxc u_vk + V_pert u_vk) for every occupied v (Eq. 15 RHS,
-        V_pert from Eq. 16, P_c from Eq. 18)."""
+        V_pert from Eq. 16, P_c from Eq. 18); for metals -(f_v - sum_j beta_vj |u_j><u_j|)
+        applied to the same vectors."""
         j, g0 = self.kq_entry(ik, q)
         ek, ej = self.kpts[ik], self.kpts[j]
         b = np.zeros((self.n_occ, ej.npw), dtype=np.complex128)
@@ -231,8 +248,50 @@ class Oracle:
         sl = slice(5 * site, 5 * site + 5)
         A = self.phi[ik][sl].conj() @ ek.u.T    # A[m, v] = <phi_{m,k}|u_vk>
         b += A.T @ self.phi[j][sl]              # sum_m |phi_{m,k+q}> A[m, v]
+        if self.metal:                          # -(f_i - sum_j beta_ij |u_j><u_j|) b_i
+            C = b @ ej.u.conj().T               # C[i, j] = <u_j,k+q|b_i>
+            return -(self.f[ik][:, None] * b - (self.beta_matrix(ik, j) * C) @ ej.u)
         b -= (b @ ej.u.conj().T) @ ej.u         # P_c = 1 - sum_v' |u_v',k+q><u_v',k+q|
         return -b
+
+    def beta_matrix(self, ik: int, j: int) -> np.ndarray:
+        """beta_ij = f_i theta_ij + f_j theta_ji + alpha theta_ji (f_i - f_j)/(e_i - e_j) for band
+        i at entry ik and band j at entry j; theta_ji = step((e_j - e_i)/sigma); equal energies
+        take the derivative of the occupation."""
+        ei, ej = self.kpts[ik].eps, self.kpts[j].eps
+        fi, fj = self.f[ik], self.f[j]
+        sig = self.degauss
+        d = ei[:, None] - ej[None, :]
+        th_ji = smooth_step(-d / sig)
+        close = np.abs(d) < 1e-9
+        mid = 0.5 * (ei[:, None] + ej[None, :])
+        F = np.where(close, -cold_delta((self.efermi - mid) / sig) / sig,
+                     (fi[:, None] - fj[None, :]) / np.where(close, 1.0, d))
+        return fi[:, None] * (1.0 - th_ji) + fj[None, :] * th_ji + self.alpha * th_ji * F
+
+    def fermi_shift(self, X: Dict[int, np.ndarray]) -> float:
+        """Shift of the Fermi level at q = 0 that keeps the electron count:
+        sum_k w sum_i delta_i <u_i|dV|u_i> / sum_k w sum_i delta_i (X[ik] = dV u rows)."""
+        num = den = 0.0
+        for ik in self.mesh:
+            e = self.kpts[ik]
+            m = np.einsum("ig,ig->i", e.u.conj(), X[ik]).real
+            num += e.weight * np.dot(self.dlt[ik], m)
+            den += e.weight * self.dlt[ik].sum()
+        return num / den
+
+    def perturbed_vectors(self, ik: int, q, site: int, dv: Optional[np.ndarray]) -> np.ndarray:
+        """dV_Hxc u_vk + V_pert u_vk in the k+q basis (the right-hand side before projection)."""
+        j, g0 = self.kq_entry(ik, q)
+        ek, ej = self.kpts[ik], self.kpts[j]
+        b = np.zeros((self.n_occ, ej.npw), dtype=np.complex128)
+        if dv is not None:
+            dvs = dv if self.nspin == 1 else dv[self.spin_of(ik)]
+            b += self.to_recip(dvs[None] * self.psi_r(ik), self.grid_index(j, g0))
+        sl = slice(5 * site, 5 * site + 5)
+        A = self.phi[ik][sl].conj() @ ek.u.T
+        b += A.T @ self.phi[j][sl]
+        return b
 
     def sternheimer_op(self, ik: int, q, X: np.ndarray, alpha: Optional[float] = None) -> np.ndarray:
         """(H_k+q + alpha O_k+q - eps_vk) X, row v paired with eps_vk (Eq. 15 LHS, O from Eq. 17)."""
@@ -398,6 +457,18 @@ class Oracle:
                 else:
                     drho[self.spin_of(ik)] += self.drho_k(ik, q, du[ik])
                 dn += self.dn_k(ik, q, du[ik])
+            if self.metal and np.all(np.abs(q - np.round(q)) < 1e-12):
+                # Fermi-level shift: density and occupations of the states at the Fermi level
+                X = {ik: self.perturbed_vectors(ik, q, site, dv_in if it > 1 else None) for ik in self.mesh}
+                def_ = self.fermi_shift(X)
+                for ik in self.mesh:
+                    e = self.kpts[ik]
+                    g = 2.0 * e.weight * self.dlt[ik] / self.degauss * def_   # occupation change per band
+                    drho += np.einsum("i,ixyz->xyz", g, np.abs(self.psi_r(ik)) ** 2) / self.omega
+                    A = self.phi[ik].conj() @ e.u.T
+                    for s2 in range(self.n_hub):
+                        a = A[5 * s2:5 * s2 + 5]
+                        dn[s2] += (a * g[None, :]) @ a.conj().T
             chi = np.einsum("smm->s", dn)
             if it == 1:
                 dn0 = dn.copy()
@@ -512,10 +583,15 @@ class Oracle:
                 vhat = np.fft.fftn(v[sp]) / self.nr
                 H = self.h_dense(ie) + lam * Pj + vhat[dm[..., 0], dm[..., 1], dm[..., 2]]
                 w, V = np.linalg.eigh(0.5 * (H + H.conj().T))
-                U = V[:, :self.n_occ].T
-                Us.append(U)
+                if self.metal:  # Fermi level of the unperturbed electron count, all bands
+                    f = self._occupations_for(w)
+                    keep = f > 1e-15
+                    U, fw = V[:, keep].T, f[keep]
+                else:
+                    U, fw = V[:, :self.n_occ].T, np.ones(self.n_occ)
+                Us.append((U, fw))
                 psi = self.to_real(U, idx)
-                rho_out[sp] = self.occ * np.sum(np.abs(psi) ** 2, axis=0) / self.omega
+                rho_out[sp] = self.occ * np.einsum("i,ixyz->xyz", fw, np.abs(psi) ** 2) / self.omega
             f = rho_out - rho_in
             if not hxc or np.abs(f).max() < tol:
                 break
@@ -540,10 +616,24 @@ class Oracle:
         else:
             raise RuntimeError("perturbed ground state did not converge")
         n = np.zeros(self.n_hub)
-        for U in Us:
+        for U, fw in Us:
             A = self.phi[0].conj() @ U.T
-            n += np.array([self.occ * np.sum(np.abs(A[5 * s:5 * s + 5]) ** 2) for s in range(self.n_hub)])
+            n += np.array([self.occ * np.sum(fw[None, :] * np.abs(A[5 * s:5 * s + 5]) ** 2)
+                           for s in range(self.n_hub)])
         return n
+
+    def _occupations_for(self, w: np.ndarray) -> np.ndarray:
+        """Cold-smearing occupations of the Gamma-only eigenvalues w with the Fermi level that
+        keeps the ground state's electron count (bisection)."""
+        n_el = sum(2.0 * self.kpts[ik].weight * self.f[ik].sum() for ik in self.mesh)
+        lo, hi = w.min() - 20 * self.degauss, w.max() + 20 * self.degauss
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if 2.0 * cold_occupation((mid - w) / self.degauss).sum() < n_el:
+                lo = mid
+            else:
+                hi = mid
+        return cold_occupation((0.5 * (lo + hi) - w) / self.degauss)
 
 
 def loewdin(rows: np.ndarray) -> np.ndarray:
@@ -608,6 +698,26 @@ def nearest_neighbours(cell, hub_tau, qmesh, dist_thr: float = 6e-4):
         for j in np.nonzero(d <= dmin + dist_thr)[0]:
             out.append((i, int(j), float(d[j])))
     return out
+
+
+def cold_occupation(x):
+    """Marzari-Vanderbilt (cold) smearing occupation of x = (e_F - e)/sigma: the integral from
+    -infinity to x of (1/sqrt(pi)) exp(-u^2) (1 - sqrt(2) u), u = t - 1/sqrt(2)."""
+    from scipy.special import erf
+    u = np.asarray(x, dtype=np.float64) - 1.0 / math.sqrt(2.0)
+    return 0.5 * (1.0 + erf(u)) + np.exp(-u * u) / math.sqrt(2.0 * math.pi)
+
+
+def cold_delta(x):
+    """Derivative of cold_occupation: (1/sqrt(pi)) exp(-u^2) (1 - sqrt(2) u), u = x - 1/sqrt(2)."""
+    u = np.asarray(x, dtype=np.float64) - 1.0 / math.sqrt(2.0)
+    return np.exp(-u * u) * (1.0 - math.sqrt(2.0) * u) / math.sqrt(math.pi)
+
+
+def smooth_step(x):
+    """The step that splits pairs of states, (1 + erf(x))/2; step(x) + step(-x) = 1."""
+    from scipy.special import erf
+    return 0.5 * (1.0 + erf(np.asarray(x, dtype=np.float64)))
 
 
 def equivalent_sites(traces, docc_thr: float = 5e-5) -> np.ndarray:

@@ -75,6 +75,11 @@ class SystemSpec:
     # hub_u0 (delta/2 - n^{I s}) from the occupations of the plain solution, then the
     # occupied states of H + sum_I M^I |phi^I><phi^I|; 0 = plain DFT ground state
     hub_u0: float = 0.0
+    # metallic ground state: Marzari-Vanderbilt (cold) smearing of width degauss (Ha) and
+    # n_el electrons per cell; n_occ is then the number of bands kept (partially occupied
+    # ones included); 0 = insulator with 2 n_occ electrons
+    degauss: float = 0.0
+    n_el: float = 0.0
 
 
 SPECS = {}
@@ -136,6 +141,10 @@ OLIVINE_AFM = _reg(replace(OLIVINE, name="olivine28_afm", spin_field=0.15))
 SC1_U = _reg(replace(SC1, name="sc1_gamma_u", hub_u0=0.15))
 DUO_AFM_U = _reg(replace(DUO, name="duo_k221_afm_u", spin_field=0.15, hub_u0=0.15))
 OLIVINE_U = _reg(replace(OLIVINE, name="olivine28_u", hub_u0=0.15))
+# Metallic variants (15 electrons in the 8 kept bands, cold smearing 0.01 Ha): the one-site
+# cell at Gamma (band 8 half filled) and on the 2x1x1 k mesh (bands 7-8 cross the Fermi level).
+SC1_METAL = _reg(replace(SC1, name="sc1_gamma_metal", degauss=0.01, n_el=15.0))
+SC1_K2_METAL = _reg(replace(SC1_K2, name="sc1_k211_metal", degauss=0.01, n_el=15.0))
 
 
 def spec_by_name(name: str) -> SystemSpec:
@@ -190,6 +199,8 @@ class GroundState:
                                 # list, vloc/rho0 are (2, N1, N2, N3), one electron per state
     hub_pot: Optional[np.ndarray] = None   # (nspin, n_hub, 5, 5) complex: the ground-state
                                            # Hubbard potential sum M |phi_m1><phi_m2| in H
+    degauss: float = 0.0        # metallic: cold-smearing width (Ha), 0 = insulator
+    efermi: float = 0.0         # metallic: Fermi energy (Ha)
 
     @property
     def n_hub(self) -> int:
@@ -792,6 +803,39 @@ def _d_kb_of(at):
                            for a in range(at.tau.shape[0])])
 
 
+def _finish_metal(spec, at, vloc, entries, n_mesh, verbose, d_kb):
+    """Metallic ground state: Fermi level of n_el electrons over the kept bands (and the first
+    excluded band, which must stay empty: occupation below 1e-12 and at least 6 widths above
+    every band with occupation above 1e-12, else None and the next seed is tried); density
+    with the cold-smearing weights."""
+    sig = spec.degauss
+    ef = _fermi_level([np.append(e.eps, e.eps_next) for e in entries[:n_mesh]],
+                      [e.weight for e in entries[:n_mesh]], spec.n_el, sig)
+    top = max(float(e.eps[_cold_occupation((ef - e.eps) / sig) > 1e-12].max()) for e in entries)
+    nxt = min(e.eps_next for e in entries)
+    if _cold_occupation((ef - nxt) / sig) > 1e-12 or nxt - top < 6 * sig:
+        if verbose:
+            print(f"{spec.name} attempt {at.seed_used}: first excluded band occupied or too close", flush=True)
+        return None  # the next seed is tried
+    omega = abs(np.linalg.det(at.cell))
+    fft = tuple(spec.fft)
+    N = int(np.prod(fft))
+    rho = np.zeros(fft)
+    for e in entries[:n_mesh]:
+        f = _cold_occupation((ef - e.eps) / sig)
+        idx = np.ravel_multi_index(tuple((e.miller % np.array(fft)).T), fft)
+        g = np.zeros((e.u.shape[0], N), dtype=np.complex128)
+        g[:, idx] = e.u
+        r = np.fft.ifftn(g.reshape((e.u.shape[0],) + fft), axes=(1, 2, 3)) * N
+        rho += 2.0 * e.weight * np.einsum("i,ixyz->xyz", f, np.abs(r) ** 2) / omega
+    if verbose:
+        print(f"{spec.name}: e_F {ef:.6f} Ha, first excluded band {nxt - ef:.4f} Ha above", flush=True)
+    return GroundState(spec=spec, seed_used=at.seed_used, cell=at.cell, fft=fft, vloc=vloc, rho0=rho, tau=at.tau,
+                       hub_atoms=at.hub_atoms, hub_zeta=at.hub_zeta, kb_s=at.kb_s, kb_d=at.kb_d, d_kb=d_kb,
+                       n_occ=spec.n_occ, kmesh=tuple(spec.kmesh), qmesh=tuple(spec.qmesh), kpts=entries,
+                       n_mesh=n_mesh, gap=nxt - top, degauss=sig, efermi=ef)
+
+
 def _finish(spec, at, vloc, entries, n_mesh, forced_gap_check, verbose, d_kb, nspin=1, hub_pot=None):
     homo = max(float(e.eps.max()) for e in entries)
     lumo = min(e.eps_next for e in entries)
@@ -811,6 +855,30 @@ def _finish(spec, at, vloc, entries, n_mesh, forced_gap_check, verbose, d_kb, ns
                        kb_s=at.kb_s, kb_d=at.kb_d, d_kb=d_kb, n_occ=spec.n_occ, kmesh=tuple(spec.kmesh),
                        qmesh=tuple(spec.qmesh), kpts=entries, n_mesh=n_mesh, gap=gap,
                        spin_factor=2 if nspin == 1 else 1, nspin=nspin, hub_pot=hub_pot)
+
+
+def _cold_occupation(x):
+    """Marzari-Vanderbilt occupation of x = (e_F - e) / sigma: the integral of
+    (1/sqrt(pi)) exp(-u^2) (1 - sqrt(2) u), u = t - 1/sqrt(2), from -infinity to x."""
+    from scipy.special import erf
+    u = np.asarray(x, dtype=np.float64) - 1.0 / math.sqrt(2.0)
+    return 0.5 * (1.0 + erf(u)) + np.exp(-u * u) / math.sqrt(2.0 * math.pi)
+
+
+def _fermi_level(eps_mesh, weights, n_el, sigma):
+    """e_F with 2 sum_k w_k sum_i occ((e_F - e_ki) / sigma) = n_el (bisection)."""
+    lo, hi = min(e.min() for e in eps_mesh) - 20 * sigma, max(e.max() for e in eps_mesh) + 20 * sigma
+
+    def count(ef):
+        return sum(2.0 * w * _cold_occupation((ef - e) / sigma).sum() for e, w in zip(eps_mesh, weights))
+
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if count(mid) < n_el:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
 
 
 def _solve_all(spec, at, vloc, rj, backend, device, tol, verbose, forced_gap_check=True):
@@ -870,6 +938,8 @@ def _solve_all(spec, at, vloc, rj, backend, device, tol, verbose, forced_gap_che
         blocks = [solve_block(v, hub_pot[si]) for si, v in enumerate(vs)]
     entries = [e for blk in blocks for e in blk]
     vout = vloc if len(vs) == 1 else np.stack(vs)
+    if spec.degauss:
+        return _finish_metal(spec, at, vout, entries, len(mesh), verbose, d_kb)
     return _finish(spec, at, vout, entries, len(mesh), forced_gap_check, verbose, d_kb, nspin=len(vs),
                    hub_pot=hub_pot)
 

@@ -124,6 +124,12 @@ typedef struct hp_ground_state {
                           /* |phi^I_m1><phi^I_m2| (e.g. U^I (delta/2 - n^I)), part  */
                           /* of the unperturbed Hamiltonian; its response is not     */
                           /* included (paper, after Eq. 10)                          */
+  double degauss;         /* 0: insulator (n_occ fully occupied bands); > 0: metallic  */
+                          /* ground state with cold (Marzari-Vanderbilt) smearing of  */
+                          /* this width (Ha); n_occ is then the number of kept bands  */
+                          /* (the first band above them must be empty and several     */
+                          /* widths away); nspin must be 1                            */
+  double efermi;          /* metallic: the Fermi energy (Ha)                         */
 } hp_ground_state;
 
 /* Convergence controls (the paper's inputhp keywords conv_thr_chi, niter_max,
@@ -191,6 +197,13 @@ typedef struct hp_ctx hp_ctx;  /* opaque; owns every device buffer */
  * cores (Eq. 6); phi is then not read.
  * With nspin = 2 the LSDA kernel (Perdew-Zunger interpolation between the
  * unpolarized and polarized fits) is built from the two spin densities.
+ * With degauss > 0 (metals) the occupations f = occ((efermi - e)/degauss) of cold
+ * smearing enter the Sternheimer right-hand side -(f_i - sum_j beta_ij |u_j><u_j|)
+ * dV u_i, beta_ij = f_i theta_ij + f_j theta_ji + alpha theta_ji (f_i - f_j) /
+ * (e_i - e_j), theta_ji = (1 + erf((e_j - e_i)/degauss))/2, and at q = 0 the
+ * Fermi level shifts to keep the electron count (extra density and occupations
+ * of the states at the Fermi level); the occupied-state density rho0 is then
+ * sum_k w_k sum_i 2 f_ki |u_ki|^2 / Omega.
  * Errors: HP_ERR_ARG (NULL, bad sizes, nspin not 1 or 2, spin_factor != 3 - nspin,
  * spin blocks that differ in k points or spheres, xc unknown, bad projector settings), HP_ERR_SHAPE (sphere does not fit the grid, FFT size not
  * 2^a 3^b 5^c), HP_ERR_SINGULAR (linearly dependent atomic orbitals), HP_ERR_OOM,

@@ -118,9 +118,20 @@ struct hp_ctx {
   int nspin = 1, n_mesh_spin = 0;
   double occ = 2.0;  // electrons per state
   std::vector<int> internal_of;
+  std::vector<double> ent_eps;  // [n_kpts][n_occ] band energies of every entry (internal order)
   int ld = 0, ns_pad = 0, ns_max = 0, max_chunk_pw = 0, npw_max = 0, n_proj = 0;
   double cell[9], bvec[9], omega = 0, alpha = 0;
   std::vector<double> hub_tau;  // [n_hub][3] site positions (bohr)
+  // metallic ground state (cold smearing of width degauss): per entry and kept band the
+  // occupation f and the smearing delta d; per (site, q) the projection weights beta and the
+  // row occupations on the device; the Fermi-level density and occupations for q = 0
+  double degauss = 0.0, efermi = 0.0;
+  std::vector<double> occ_f, occ_d;
+  double *d_beta = nullptr, *d_focc = nullptr;
+  double2 *d_rhoF = nullptr;
+  std::vector<std::complex<double>> n_fermi;
+  bool metal_q0 = false;     // the current right-hand sides are at q = 0 (Fermi-level shift)
+  double fermi_shift = 0.0;  // of the current right-hand sides
   std::vector<HostEntry> ent;
   std::vector<int> px, py;
   Plane pl{};
@@ -371,6 +382,18 @@ bool jacobi_eigen(int n, std::vector<double> &a, std::vector<double> &v) {
   return false;
 }
 
+// Cold (Marzari-Vanderbilt) smearing of x = (e_F - e) / sigma: occupation, its derivative,
+// and the smooth step (1 + erf(x)) / 2 that splits pairs of states.
+double cold_occ(double x) {
+  const double u = x - 1.0 / std::sqrt(2.0);
+  return 0.5 * (1.0 + std::erf(u)) + std::exp(-u * u) / std::sqrt(2.0 * M_PI);
+}
+double cold_delta(double x) {
+  const double u = x - 1.0 / std::sqrt(2.0);
+  return std::exp(-u * u) * (1.0 - std::sqrt(2.0) * u) / std::sqrt(M_PI);
+}
+double split_step(double x) { return 0.5 * (1.0 + std::erf(x)); }
+
 // Eigenpairs of a Hermitian n x n matrix (row-major complex): lam ascending, column a of V
 // (V[m * n + a]) the eigenvector of lam[a].  Through the real symmetric embedding, whose
 // spectrum is that of M with every eigenvalue twice; the embedding eigenvectors [x; y] are
@@ -607,6 +630,24 @@ hp_status build_rhs(hp_ctx *c, const KPair *kp, int nk, int site, const double2 
   }));
   // P_c = 1 - sum_v' |u_v',k+q><u_v',k+q|   (Eq. 18)
   HPTRY(proj(c, kp, 1, nk, c->d_T, c->t_stride, c->n_beta, c->n_occ, c->B, nb, nullptr, 1.0, c->C));
+  if (c->degauss > 0.0) {
+    // metals: B_i = f_i B_i - sum_j beta_ij u_j <u_j|B_i> (B = -(dV + V_pert) u)
+    if (c->metal_q0) {  // Fermi-level shift from <u_i|dV|u_i> = -C[k][i][i]
+      std::vector<double2> h((size_t)nk * nb * nb);
+      HPCHK(hipMemcpyAsync(h.data(), c->C, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, c->stream));
+      HPTRY(sync(c));
+      double num = 0.0, den = 0.0;
+      for (int k = 0; k < nk; ++k)
+        for (int i = 0; i < nb; ++i) {
+          const double w = c->ent[k].weight * c->occ_d[(size_t)k * nb + i];
+          num += w * -h[((size_t)k * nb + i) * nb + i].x;
+          den += w;
+        }
+      c->fermi_shift = den != 0.0 ? num / den : 0.0;
+    }
+    HPCHK(launch_scale_rows((long)nk * nb * nb, 1, c->d_beta, c->C, c->stream));
+    HPCHK(launch_scale_rows((long)nitems * c->ld, c->ld, c->d_focc, c->B, c->stream));
+  }
   HPCHK(timed(c, K_RHS, [&] {
     return launch_zexpand(kp, 1, nk, c->d_T, c->t_stride, c->n_beta, c->n_occ, c->C, (long)c->n_occ * nb, -1.0, c->B,
                           c->ld, c->n_occ, c->d_npw, c->npw_max, nullptr, gemm_shape(c, 64, c->n_occ, nk).bv,
@@ -1200,6 +1241,33 @@ hp_status upload_pairs(hp_ctx *c, int site, const double q[3], std::vector<KPair
   return HP_OK;
 }
 
+// Metallic ground state: per pair (k, k+q) the weights beta_ij = f_i theta_ij + f_j theta_ji +
+// alpha theta_ji (f_i - f_j)/(e_i - e_j) of the projection onto the kept bands j of k+q
+// (equal energies: the occupation derivative), stored [pair][j][i], and the occupations of
+// the right-hand-side rows.
+hp_status upload_metal(hp_ctx *c, const std::vector<KPair> &pairs) {
+  const int nb = c->n_occ;
+  const double sig = c->degauss;
+  std::vector<double> beta((size_t)pairs.size() * nb * nb), focc((size_t)pairs.size() * nb);
+  for (size_t k = 0; k < pairs.size(); ++k) {
+    const double *fi = &c->occ_f[(size_t)pairs[k].ek * nb], *fj = &c->occ_f[(size_t)pairs[k].ej * nb];
+    const double *ei = &c->ent_eps[(size_t)pairs[k].ek * nb], *ej = &c->ent_eps[(size_t)pairs[k].ej * nb];
+    for (int i = 0; i < nb; ++i) {
+      focc[k * nb + i] = fi[i];
+      for (int j = 0; j < nb; ++j) {
+        const double d = ei[i] - ej[j];
+        const double th_ji = split_step(-d / sig);
+        const double F = std::fabs(d) < 1e-9 ? -cold_delta((c->efermi - 0.5 * (ei[i] + ej[j])) / sig) / sig
+                                             : (fi[i] - fj[j]) / d;
+        beta[((size_t)k * nb + j) * nb + i] = fi[i] * (1.0 - th_ji) + fj[j] * th_ji + c->alpha * th_ji * F;
+      }
+    }
+  }
+  HPCHK(hipMemcpyAsync(c->d_beta, beta.data(), sizeof(double) * beta.size(), hipMemcpyHostToDevice, c->stream));
+  HPCHK(hipMemcpyAsync(c->d_focc, focc.data(), sizeof(double) * focc.size(), hipMemcpyHostToDevice, c->stream));
+  return sync(c);  // the host vectors go out of scope
+}
+
 // Small complex Hermitian solve (Gaussian elimination with partial pivoting).
 bool csolve(int n, std::vector<std::complex<double>> A, std::vector<std::complex<double>> &b) {
   for (int i = 0; i < n; ++i) {
@@ -1536,6 +1604,9 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   if (!gs) return fail(HP_ERR_ARG, "gs is NULL");
   if (gs->struct_size != sizeof(hp_ground_state)) return fail(HP_ERR_ARG, "hp_ground_state.struct_size mismatch");
   if (gs->nspin != 1 && gs->nspin != 2) return fail(HP_ERR_ARG, "nspin must be 1 or 2");
+  if (!(gs->degauss >= 0.0) || !std::isfinite(gs->degauss) || !std::isfinite(gs->efermi))
+    return fail(HP_ERR_ARG, "degauss must be >= 0 and efermi finite");
+  if (gs->degauss > 0.0 && gs->nspin != 1) return fail(HP_ERR_ARG, "metallic ground states must be unpolarized");
   if (gs->spin_factor != 3 - gs->nspin)
     return fail(HP_ERR_ARG, "spin_factor must be %d with nspin = %d", 3 - gs->nspin, gs->nspin);
   if (gs->xc != HP_XC_LDA_PZ81) return fail(HP_ERR_ARG, "unknown xc %d", gs->xc);
@@ -1642,6 +1713,20 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   c->n_mesh = gs->nspin * gs->n_mesh;
   c->occ = gs->nspin == 2 ? 1.0 : 2.0;
   c->internal_of = internal_of;
+  c->degauss = gs->degauss;
+  c->efermi = gs->efermi;
+  c->ent_eps.resize((size_t)gs->n_kpts * gs->n_occ);
+  c->occ_f.assign(c->ent_eps.size(), 1.0);
+  c->occ_d.assign(c->ent_eps.size(), 0.0);
+  for (int i = 0; i < gs->n_kpts; ++i)
+    for (int v = 0; v < gs->n_occ; ++v) {
+      const double e = KP[i]->eps[v];
+      c->ent_eps[(size_t)i * gs->n_occ + v] = e;
+      if (gs->degauss > 0.0) {
+        c->occ_f[(size_t)i * gs->n_occ + v] = cold_occ((gs->efermi - e) / gs->degauss);
+        c->occ_d[(size_t)i * gs->n_occ + v] = cold_delta((gs->efermi - e) / gs->degauss);
+      }
+    }
   c->n_kpts = gs->n_kpts;
   c->n_proj = c->n_beta + c->n_occ;
   for (int i = 0; i < 9; ++i) c->cell[i] = gs->cell[i / 3][i % 3];
@@ -1992,6 +2077,42 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
                          c->max_chunk_pw, c->ns_max, nullptr, 0, st));
   HPCHK(launch_plane_to_real(c->pl, c->sk, c->d_kself, 0, nb, (int)nitems, c->S1, c->ns_pad, c->d_psi, st));
   HPTRY(sync(c.get()));
+  if (c->degauss > 0.0) {
+    // metals: projection weights, and for q = 0 the states at the Fermi level:
+    // rho_F = 2 sum_k w sum_i (d_i / sigma) |u_i|^2 / Omega through the response-density
+    // kernels (X = the kept bands scaled by d_i / (2 sigma), paired with themselves), and
+    // n_F[s] = 2 sum_k w sum_i (d_i / sigma) <phi_m1|u_i><u_i|phi_m2>
+    HPTRY(c->alloc(&c->d_beta, (size_t)c->n_mesh * nb * nb));
+    HPTRY(c->alloc(&c->d_focc, (size_t)nitems));
+    HPTRY(c->alloc(&c->d_rhoF, (size_t)c->nr));
+    std::vector<double> cw(nitems);
+    for (int k = 0; k < c->n_mesh; ++k)
+      for (int v = 0; v < nb; ++v) cw[(size_t)k * nb + v] = c->occ_d[(size_t)k * nb + v] / (2.0 * c->degauss);
+    HPCHK(hipMemcpyAsync(c->d_focc, cw.data(), sizeof(double) * cw.size(), hipMemcpyHostToDevice, st));
+    HPCHK(launch_scale_rows((long)nitems * c->ld, c->ld, c->d_focc, c->X, st));
+    HPCHK(launch_stick_inv(c->sk, c->d_kself, 1, nb, (int)nitems, c->X, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
+                           c->max_chunk_pw, c->ns_max, nullptr, 0, st));
+    HPCHK(launch_plane_drho(c->pl, c->sk, c->d_kself, nb, c->n_mesh, c->S1, c->ns_pad, c->d_psi, c->part,
+                            c->drho_split, st));
+    HPCHK(launch_drho_reduce(c->d_kself, c->n_mesh, c->drho_split, c->part, c->nr, 1.0 / c->omega, c->occ, 1,
+                             c->d_rhoF, st));
+    const int M = 5 * c->n_hub;
+    std::vector<double2> A((size_t)c->n_mesh * M * nb);
+    HPCHK(hipMemcpyAsync(A.data(), c->d_A, sizeof(double2) * A.size(), hipMemcpyDeviceToHost, st));
+    HPTRY(sync(c.get()));
+    c->n_fermi.assign((size_t)25 * c->n_hub, 0.0);
+    for (int k = 0; k < c->n_mesh; ++k)
+      for (int v = 0; v < nb; ++v) {
+        const double g = 2.0 * c->ent[k].weight * c->occ_d[(size_t)k * nb + v] / c->degauss;
+        for (int s2 = 0; s2 < c->n_hub; ++s2)
+          for (int m1 = 0; m1 < 5; ++m1)
+            for (int m2 = 0; m2 < 5; ++m2) {
+              const double2 a1 = A[((size_t)k * M + 5 * s2 + m1) * nb + v], a2 = A[((size_t)k * M + 5 * s2 + m2) * nb + v];
+              c->n_fermi[(size_t)s2 * 25 + m1 * 5 + m2] +=
+                  g * std::complex<double>(a1.x, a1.y) * std::conj(std::complex<double>(a2.x, a2.y));
+            }
+      }
+  }
   *out = c.release();
   return HP_OK;
 }
@@ -2004,6 +2125,12 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
   const int nb = c->n_occ, nk = c->n_mesh, nitems = nk * nb;
   std::vector<KPair> pairs;
   HPTRY(upload_pairs(c, site, q, pairs));
+  c->metal_q0 = false;
+  if (c->degauss > 0.0) {
+    HPTRY(upload_metal(c, pairs));
+    c->metal_q0 = std::fabs(q[0] - std::round(q[0])) < 1e-12 && std::fabs(q[1] - std::round(q[1])) < 1e-12 &&
+                  std::fabs(q[2] - std::round(q[2])) < 1e-12;
+  }
   HPTRY(autotune(c, nk, p->precision == HP_MIXED));
   if (p->precision == HP_MIXED) HPTRY(setup32(c));
   HPCHK(hipMemcpyAsync(c->d_q, q, sizeof(double) * 3, hipMemcpyHostToDevice, c->stream));
@@ -2068,6 +2195,14 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
       return launch_drho_reduce(c->d_kp, nk, c->drho_split, c->part, c->nr, 1.0 / c->omega, c->occ, c->nspin, c->drho,
                                 c->stream);
     }));
+    if (c->metal_q0) {  // Fermi-level shift: drho += shift * rho_F
+      const double2 *xs[1] = {c->d_rhoF};
+      const double2 cf[1] = {make_double2(c->fermi_shift, 0.0)};
+      HPCHK(hipMemcpyAsync(c->ptrs, xs, sizeof(xs), hipMemcpyHostToDevice, c->stream));
+      HPCHK(hipMemcpyAsync(c->coef, cf, sizeof(cf), hipMemcpyHostToDevice, c->stream));
+      HPCHK(launch_zaxpy_list(c->nr, c->drho, 1, c->ptrs, c->coef, c->stream));
+      HPTRY(sync(c));  // xs and cf live on this stack frame
+    }
     HPCHK(hipEventRecord(c->ev[3], c->stream));
     HPCHK(timed(c, K_HXC, [&] {
       return launch_hxc(c->pl, c->az, c->d_bvec, q, c->drho, c->d_fxc, c->tmp, c->dvout, c->nspin, c->stream);
@@ -2080,6 +2215,11 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
     HPCHK(hipMemcpyAsync(dn.data(), c->dn, sizeof(double2) * dn.size(), hipMemcpyDeviceToHost, c->stream));
     HPCHK(hipEventRecord(c->ev[5], c->stream));
     HPTRY(sync(c));
+    if (c->metal_q0)  // Fermi-level shift of the occupations
+      for (size_t i = 0; i < dn.size(); ++i) {
+        dn[i].x += c->fermi_shift * c->n_fermi[i].real();
+        dn[i].y += c->fermi_shift * c->n_fermi[i].imag();
+      }
     for (double2 z : dn)
       if (!std::isfinite(z.x) || !std::isfinite(z.y)) return fail(HP_ERR_NUMERIC, "non-finite response occupation");
     std::vector<std::complex<double>> chi(c->n_hub);
@@ -2442,6 +2582,8 @@ extern "C" hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const do
   HPTRY(upload_pairs(c, pert_site, q_frac, pairs));
   const KPair P = pairs[mesh_k];
   HPCHK(hipMemcpyAsync(c->d_kp, &P, sizeof(KPair), hipMemcpyHostToDevice, c->stream));
+  c->metal_q0 = false;  // a single k: no Fermi-level shift here
+  if (c->degauss > 0.0) HPTRY(upload_metal(c, std::vector<KPair>{P}));
   HPTRY(autotune(c, 1, p->precision == HP_MIXED));
   const int nb = c->n_occ;
   const double2 *psi = c->d_psi + (size_t)mesh_k * nb * c->nr;

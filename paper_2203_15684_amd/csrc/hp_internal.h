@@ -217,5 +217,8 @@ hipError_t launch_zaxpy_list(long n, double2 *y, int nvec, const double2 *const 
                              hipStream_t st);
 hipError_t launch_zsub(long n, const double2 *a, const double2 *b, double2 *out, hipStream_t st);
 hipError_t launch_zscale_copy(long n, const double2 *a, double s, double2 *out, hipStream_t st);
+// x[i] *= s[i / per] for i < n: rows of `per` complex values scaled by one real each
+// (the band occupations of right-hand-side rows, or the coefficients of a projection).
+hipError_t launch_scale_rows(long n, long per, const double *s, double2 *x, hipStream_t st);
 
 }  // namespace hp

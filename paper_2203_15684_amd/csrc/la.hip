@@ -1119,6 +1119,22 @@ hipError_t launch_zsub(long n, const double2 *a, const double2 *b, double2 *out,
   return hipGetLastError();
 }
 
+__global__ void k_scale_rows(long n, long per, const double *__restrict__ s, double2 *__restrict__ x) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double f = s[i / per];
+  double2 v = x[i];
+  v.x *= f;
+  v.y *= f;
+  x[i] = v;
+}
+
+hipError_t launch_scale_rows(long n, long per, const double *s, double2 *x, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, per, s, x);
+  return hipGetLastError();
+}
+
 hipError_t launch_zscale_copy(long n, const double2 *a, double s, double2 *out, hipStream_t st) {
   hipLaunchKernelGGL(k_zscale_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, s, out);
   return hipGetLastError();

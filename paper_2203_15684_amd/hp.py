@@ -59,7 +59,7 @@ class HpGroundState(C.Structure):
                 ("d_kb", _dp), ("hub_tau", _dp), ("spin_factor", C.c_int32), ("n_mesh", C.c_int32),
                 ("n_kpts", C.c_int32), ("kpts", C.POINTER(HpKpoint)), ("xc", C.c_int32), ("reserved", C.c_int32),
                 ("stream", C.c_void_p), ("projectors", C.c_int32), ("n_atwfc", C.c_int32), ("hub_rows", _ip),
-                ("nspin", C.c_int32), ("hub_pot", _dp)]
+                ("nspin", C.c_int32), ("hub_pot", _dp), ("degauss", C.c_double), ("efermi", C.c_double)]
 
 
 class HpScfParams(C.Structure):
@@ -276,6 +276,8 @@ def hp_ground_state_load(gs, stream: Optional[int] = None, atwfc: Optional[Seque
     g.hub_rows = _ptr(hrows, _ip) if ortho else None
     g.nspin = nspin
     g.hub_pot = _ptr(hpot) if hpot is not None else None
+    g.degauss = float(getattr(gs, "degauss", 0.0) or 0.0)
+    g.efermi = float(getattr(gs, "efermi", 0.0) or 0.0)
     h = C.c_void_p()
     _check(_lib.hp_ground_state_load(C.byref(g), C.byref(h)), allow_warn=False)
     del keep

@@ -122,3 +122,17 @@ def test_spin_load_validation_runs_before_device(hp):
     with pytest.raises(hp.HpError) as e:
         hp.hp_ground_state_load(g)
     assert e.value.status == hp.HP_ERR_ARG and "spin down" in str(e.value)
+
+
+def test_metal_load_validation_runs_before_device(hp):
+    import copy
+    from conftest import ground_state
+    for name, field, val in [("sc1_gamma_metal", "degauss", -0.01), ("sc1_gamma_metal", "efermi", float("nan")),
+                             ("sc1_gamma_spin", "degauss", 0.01)]:
+        g = copy.copy(ground_state(name))
+        setattr(g, field, val)
+        if field == "degauss" and name == "sc1_gamma_spin":
+            g.efermi = 0.3
+        with pytest.raises(hp.HpError) as e:
+            hp.hp_ground_state_load(g)
+        assert e.value.status == hp.HP_ERR_ARG, (name, field, e.value)

@@ -404,12 +404,14 @@ class Oracle:
         return out
 
     def occupations(self) -> np.ndarray:
-        """Ground-state n^s_{m1 m2} = (occ/N_k) sum_kv <u|phi_{m2}><phi_{m1}|u> (Eq. 3, on-site,
-        summed over spins)."""
+        """Ground-state n^s_{m1 m2} = (occ/N_k) sum_kv f_v <u|phi_{m2}><phi_{m1}|u> (Eq. 3, on-site,
+        summed over spins; f_v = 1 for insulators)."""
         out = np.zeros((self.n_hub, 5, 5), dtype=np.complex128)
         for ik in self.mesh:
             e = self.kpts[ik]
             A = self.phi[ik].conj() @ e.u.T
+            if self.metal:
+                A = A * np.sqrt(self.f[ik])[None, :]
             for s in range(self.n_hub):
                 sl = slice(5 * s, 5 * s + 5)
                 out[s] += self.occ * e.weight * A[sl] @ A[sl].conj().T
@@ -422,7 +424,8 @@ class Oracle:
         for ik in self.mesh:
             e = self.kpts[ik]
             A = self.phi[ik].conj() @ e.u.T
-            w = self.occ * e.weight * np.sum(np.abs(A) ** 2, axis=1)
+            f = self.f[ik] if self.metal else np.ones(self.n_occ)   # occupations of the bands
+            w = self.occ * e.weight * (np.abs(A) ** 2 @ f)
             tr[self.spin_of(ik)] += w.reshape(self.n_hub, 5).sum(axis=1)
         mom = tr[0] - tr[1] if self.nspin == 2 else np.zeros(self.n_hub)
         return tr.sum(axis=0), mom

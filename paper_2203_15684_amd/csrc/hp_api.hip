@@ -1434,9 +1434,9 @@ hp_status site_occupations(hp_ctx *c, std::vector<double> &trace, std::vector<do
     for (int s2 = 0; s2 < c->n_hub; ++s2) {
       double t = 0.0;
       for (int m = 0; m < 5; ++m)
-        for (int v = 0; v < nb; ++v) {
+        for (int v = 0; v < nb; ++v) {  // weighted by the band occupation (1 for insulators)
           const double2 a = A[((size_t)k * M + 5 * s2 + m) * nb + v];
-          t += a.x * a.x + a.y * a.y;
+          t += c->occ_f[(size_t)k * nb + v] * (a.x * a.x + a.y * a.y);
         }
       per_spin[(size_t)c->ent[k].spin * c->n_hub + s2] += w * t;
     }

@@ -136,3 +136,25 @@ def test_metal_load_validation_runs_before_device(hp):
         with pytest.raises(hp.HpError) as e:
             hp.hp_ground_state_load(g)
         assert e.value.status == hp.HP_ERR_ARG, (name, field, e.value)
+
+
+def test_hub_pot_validation_runs_before_device(hp):
+    import copy
+    from conftest import ground_state
+    gs = ground_state("sc1_gamma_u")
+    g = copy.copy(gs)
+    bad = gs.hub_pot.copy()
+    bad[0, 0, 0, 1] += 0.01          # no longer Hermitian
+    g.hub_pot = bad
+    with pytest.raises(hp.HpError) as e:
+        hp.hp_ground_state_load(g)
+    assert e.value.status == hp.HP_ERR_ARG and "Hermitian" in str(e.value)
+    bad = gs.hub_pot.copy()
+    bad[0, 0, 2, 2] = np.nan
+    g.hub_pot = bad
+    with pytest.raises(hp.HpError) as e:
+        hp.hp_ground_state_load(g)
+    assert e.value.status == hp.HP_ERR_NUMERIC
+    g.hub_pot = gs.hub_pot[:, :, :4, :4]   # wrong shape: caught by the binding
+    with pytest.raises(ValueError):
+        hp.hp_ground_state_load(g)

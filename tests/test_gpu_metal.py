@@ -80,3 +80,13 @@ def test_metal_response_matrix_and_u():
     assert rel(chi0, c0) < 1e-10 and rel(chi, c1) < 1e-10
     uv = hp.hp_hubbard_params(chi0, chi)
     assert np.abs(uv - oracle.hubbard_params(c0, c1)).max() * HA_MEV < 1e-3
+
+
+def test_metal_site_occupations():
+    """Ground-state occupation traces of a metal carry the band occupations (Eq. 3)."""
+    hp = _hp()
+    name = "sc1_k211_metal"
+    tr, mo, cl = hp.hp_site_occupations(ctx(name))
+    t_ref, _ = orc(name).site_traces()
+    assert np.abs(tr - t_ref).max() < 1e-12 * np.abs(t_ref).max()
+    assert np.all(mo == 0) and list(cl) == [0]

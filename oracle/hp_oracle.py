@@ -278,7 +278,7 @@ class Oracle:
             m = np.einsum("ig,ig->i", e.u.conj(), X[ik]).real
             num += e.weight * np.dot(self.dlt[ik], m)
             den += e.weight * self.dlt[ik].sum()
-        return num / den
+        return num / den if den != 0.0 else 0.0
 
     def perturbed_vectors(self, ik: int, q, site: int, dv: Optional[np.ndarray]) -> np.ndarray:
         """dV_Hxc u_vk + V_pert u_vk in the k+q basis (the right-hand side before projection)."""

@@ -98,3 +98,23 @@ def test_metal_without_fermi_shift_misses_finite_differences():
     r = o.scf(0, np.zeros(3), oracle.ScfParams(cg_tol=1e-12, hxc=False))
     chi0 = np.trace(r["dn0"][0]).real
     assert abs(chi0 - fd_chi(False)[0]) > 1e-3 * abs(chi0)
+
+
+def test_metal_path_with_full_bands_is_the_insulator():
+    """Fermi level mid-gap, all kept bands fully occupied: the metallic right-hand side and the
+    (vanishing) Fermi shift reproduce the insulating response."""
+    import copy
+    gs = ground_state("sc1_k211")
+    g = copy.copy(gs)
+    top = max(e.eps.max() for e in gs.kpts)
+    nxt = min(e.eps_next for e in gs.kpts)
+    g.degauss = 0.002
+    g.efermi = 0.5 * (top + nxt)
+    om = oracle.Oracle(g)
+    assert om.metal and min(f.min() for f in om.f) > 1 - 1e-12
+    p = oracle.ScfParams(cg_tol=1e-11, conv_thr_chi=1e-10, conv_thr_v=1e-8)   # same path, same stopping
+    for q in ((0.0, 0, 0), (0.5, 0, 0)):
+        a = om.scf(0, np.array(q), p)
+        b = oracle.Oracle(gs).scf(0, np.array(q), p)
+        for key in ("dn0", "dn"):
+            assert np.abs(a[key] - b[key]).max() < 1e-10 * np.abs(b[key]).max(), (q, key)

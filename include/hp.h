@@ -3,7 +3,8 @@
  *
  * The library computes the linear response of the Hubbard-manifold occupations
  * of a periodic, norm-conserving insulator (spin-unpolarized, or collinear
- * spin-polarized with the same number of occupied states per spin) to monochromatic
+ * spin-polarized with the same number of occupied states per spin) or metal
+ * (unpolarized, cold smearing) to monochromatic
  * perturbations of those occupations, following Timrov, Marzari and
  * Cococcioni, "HP - A code for the calculation of Hubbard parameters using
  * density-functional perturbation theory":

@@ -145,6 +145,9 @@ OLIVINE_U = _reg(replace(OLIVINE, name="olivine28_u", hub_u0=0.15))
 # cell at Gamma (band 8 half filled) and on the 2x1x1 k mesh (bands 7-8 cross the Fermi level).
 SC1_METAL = _reg(replace(SC1, name="sc1_gamma_metal", degauss=0.01, n_el=15.0))
 SC1_K2_METAL = _reg(replace(SC1_K2, name="sc1_k211_metal", degauss=0.01, n_el=15.0))
+# The olivine-shaped cell with one electron removed (223 in 112 kept bands, cold smearing
+# 0.01 Ha): the top valence band crosses the Fermi level, the next band stays 1.18 Ha above.
+OLIVINE_METAL = _reg(replace(OLIVINE, name="olivine28_metal", degauss=0.01, n_el=223.0))
 
 
 def spec_by_name(name: str) -> SystemSpec:

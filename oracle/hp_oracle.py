@@ -269,13 +269,16 @@ class Oracle:
                      (fi[:, None] - fj[None, :]) / np.where(close, 1.0, d))
         return fi[:, None] * (1.0 - th_ji) + fj[None, :] * th_ji + self.alpha * th_ji * F
 
-    def fermi_shift(self, X: Dict[int, np.ndarray]) -> float:
+    def fermi_shift(self, X: Dict[int, np.ndarray]) -> complex:
         """Shift of the Fermi level at q = 0 that keeps the electron count:
-        sum_k w sum_i delta_i <u_i|dV|u_i> / sum_k w sum_i delta_i (X[ik] = dV u rows)."""
-        num = den = 0.0
+        sum_k w sum_i delta_i <u_i|dV|u_i> / sum_k w sum_i delta_i (X[ik] = dV u rows).
+        Kept complex: the response is linear over the complex numbers (the iterates of the
+        response potential are complex), and for a physical perturbation the sum over
+        time-reversed k points makes it real."""
+        num, den = 0.0 + 0.0j, 0.0
         for ik in self.mesh:
             e = self.kpts[ik]
-            m = np.einsum("ig,ig->i", e.u.conj(), X[ik]).real
+            m = np.einsum("ig,ig->i", e.u.conj(), X[ik])
             num += e.weight * np.dot(self.dlt[ik], m)
             den += e.weight * self.dlt[ik].sum()
         return num / den if den != 0.0 else 0.0

@@ -131,7 +131,9 @@ struct hp_ctx {
   double2 *d_rhoF = nullptr;
   std::vector<std::complex<double>> n_fermi;
   bool metal_q0 = false;     // the current right-hand sides are at q = 0 (Fermi-level shift)
-  double fermi_shift = 0.0;  // of the current right-hand sides
+  // of the current right-hand sides; complex because the response is linear over the
+  // complex numbers (the response-potential iterates are complex)
+  std::complex<double> fermi_shift = 0.0;
   std::vector<HostEntry> ent;
   std::vector<int> px, py;
   Plane pl{};
@@ -636,14 +638,16 @@ hp_status build_rhs(hp_ctx *c, const KPair *kp, int nk, int site, const double2 
       std::vector<double2> h((size_t)nk * nb * nb);
       HPCHK(hipMemcpyAsync(h.data(), c->C, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, c->stream));
       HPTRY(sync(c));
-      double num = 0.0, den = 0.0;
+      std::complex<double> num = 0.0;
+      double den = 0.0;
       for (int k = 0; k < nk; ++k)
         for (int i = 0; i < nb; ++i) {
           const double w = c->ent[k].weight * c->occ_d[(size_t)k * nb + i];
-          num += w * -h[((size_t)k * nb + i) * nb + i].x;
+          const double2 d = h[((size_t)k * nb + i) * nb + i];
+          num -= w * std::complex<double>(d.x, d.y);
           den += w;
         }
-      c->fermi_shift = den != 0.0 ? num / den : 0.0;
+      c->fermi_shift = den != 0.0 ? num / den : std::complex<double>(0.0);
     }
     HPCHK(launch_scale_rows((long)nk * nb * nb, 1, c->d_beta, c->C, c->stream));
     HPCHK(launch_scale_rows((long)nitems * c->ld, c->ld, c->d_focc, c->B, c->stream));
@@ -2197,7 +2201,7 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
     }));
     if (c->metal_q0) {  // Fermi-level shift: drho += shift * rho_F
       const double2 *xs[1] = {c->d_rhoF};
-      const double2 cf[1] = {make_double2(c->fermi_shift, 0.0)};
+      const double2 cf[1] = {make_double2(c->fermi_shift.real(), c->fermi_shift.imag())};
       HPCHK(hipMemcpyAsync(c->ptrs, xs, sizeof(xs), hipMemcpyHostToDevice, c->stream));
       HPCHK(hipMemcpyAsync(c->coef, cf, sizeof(cf), hipMemcpyHostToDevice, c->stream));
       HPCHK(launch_zaxpy_list(c->nr, c->drho, 1, c->ptrs, c->coef, c->stream));
@@ -2217,8 +2221,9 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
     HPTRY(sync(c));
     if (c->metal_q0)  // Fermi-level shift of the occupations
       for (size_t i = 0; i < dn.size(); ++i) {
-        dn[i].x += c->fermi_shift * c->n_fermi[i].real();
-        dn[i].y += c->fermi_shift * c->n_fermi[i].imag();
+        const std::complex<double> t = c->fermi_shift * c->n_fermi[i];
+        dn[i].x += t.real();
+        dn[i].y += t.imag();
       }
     for (double2 z : dn)
       if (!std::isfinite(z.x) || !std::isfinite(z.y)) return fail(HP_ERR_NUMERIC, "non-finite response occupation");

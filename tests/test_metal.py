@@ -118,3 +118,12 @@ def test_metal_path_with_full_bands_is_the_insulator():
         b = oracle.Oracle(gs).scf(0, np.array(q), p)
         for key in ("dn0", "dn"):
             assert np.abs(a[key] - b[key]).max() < 1e-10 * np.abs(b[key]).max(), (q, key)
+
+
+def test_metal_q0_self_consistency_converges_on_a_k_mesh():
+    """Regression: the Fermi-level shift must keep the response linear over the complex numbers
+    (the mixing extrapolates with complex coefficients); taking its real part stalled the q = 0
+    loop of this metal at a residual of ~1e-3."""
+    o = orc("duo_k221_metal")
+    r = o.scf(0, np.zeros(3), oracle.ScfParams(cg_tol=1e-10, conv_thr_chi=1e-10, conv_thr_v=1e-8, niter_max=60))
+    assert r["converged"] and r["iters"] < 45

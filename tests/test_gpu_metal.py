@@ -1,7 +1,8 @@
 """Metallic ground states (cold smearing; the paper's generalization of Eq. 15 to fractional
 occupations) on the GPU against the oracle: first-order solves at q != 0 with the
 beta-weighted projection, the self-consistent response at q = 0 (where the Fermi level
-shifts) and at q != 0, the response matrix and U; FP64 bar 1e-10, mixed 1e-6.
+shifts; one k point and k meshes) and at q != 0, the response matrix and U, the ground-state
+site occupations; FP64 bar 1e-10, mixed 1e-6.
 """
 import functools
 

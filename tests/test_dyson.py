@@ -1,0 +1,74 @@
+"""Dyson pin of the oracle's self-consistent response (Eq. 15 iterated with the Hxc response,
+mixing, the response density and Eq. 13) on the one-site Gamma system, by a route that
+shares none of that machinery: the full spectrum of the dense Hamiltonian, the bare
+density response chi0_rr(G, G') on the density sphere (sum over all empty states), the
+Hxc kernel K as a dense matrix in the same basis (Hartree diagonal plus the grid
+convolution with f_xc), the exact solve drho = (1 - chi0_rr K)^-1 drho0, and the
+occupation response to the total potential by a sum over states.
+
+The response is the linear map the oracle defines (time reversal folded into the factor
+4; the grid-defined local operators); at Gamma it equals the physical response.
+"""
+import numpy as np
+import scipy.fft as sfft
+
+import oracle
+from oracle import pz81
+from conftest import ground_state
+
+
+def test_dyson_solve_equals_self_consistent_sternheimer():
+    gs = ground_state("sc1_gamma")
+    o = oracle.Oracle(gs)
+    e = gs.kpts[0]
+    fft, nr, omega = o.fft, o.nr, o.omega
+    nocc = gs.n_occ
+    # full spectrum at Gamma
+    w, V = np.linalg.eigh(o.h_dense(0))
+    U = V.T                                               # rows: all states, plane-wave coefficients
+    idx = o.grid_index(0)
+    psi = np.zeros((U.shape[0], nr), dtype=np.complex128)
+    psi[:, idx] = U
+    psi = (sfft.ifftn(psi.reshape((-1,) + fft), axes=(1, 2, 3)) * nr).reshape(U.shape[0], nr)
+    # density sphere: every G of a product of two states (alias-free on this grid)
+    freq = [np.where(np.arange(n) < (n + 1) // 2, np.arange(n), np.arange(n) - n) for n in fft]
+    M = np.stack(np.meshgrid(*freq, indexing="ij"), -1).reshape(-1, 3)
+    gvec = M @ o.bvec
+    gmax = np.sqrt(np.einsum("ij,ij->i", (e.miller @ o.bvec), (e.miller @ o.bvec)).max())
+    S = np.nonzero(np.einsum("ij,ij->i", gvec, gvec) <= (2 * gmax) ** 2 + 1e-9)[0]
+    # P[v, c, G] = (1/N) sum_r exp(-iGr) conj(psi_v) psi_c
+    ne = U.shape[0] - nocc
+    P = np.empty((nocc, ne, S.size), dtype=np.complex128)
+    for v in range(nocc):
+        prod = np.conj(psi[v])[None, :] * psi[nocc:]
+        P[v] = (sfft.fftn(prod.reshape((-1,) + fft), axes=(1, 2, 3)).reshape(ne, nr) / nr)[:, S]
+    den = w[:nocc, None] - w[None, nocc:]                 # e_v - e_c
+    Pw = (P / den[:, :, None]).reshape(-1, S.size)
+    chi0_rr = (4.0 / omega) * Pw.T @ np.conj(P.reshape(-1, S.size))      # (G, G')
+    # Hxc kernel on the sphere: 4 pi / |G|^2 (0 at G = 0) + fhat(G - G') on the grid
+    g2 = np.einsum("ij,ij->i", gvec[S], gvec[S])
+    fhat = sfft.fftn(pz81.f_xc(gs.rho0)) / nr
+    d = (M[S][:, None, :] - M[S][None, :, :]) % np.array(fft)
+    K = fhat[d[..., 0], d[..., 1], d[..., 2]].astype(np.complex128)
+    K[np.diag_indices(S.size)] += np.where(g2 > 1e-12, 4.0 * np.pi / np.where(g2 > 1e-12, g2, 1.0), 0.0)
+    # bare response to the Hubbard projector of site 0 (Eq. 16)
+    phi = e.phi[0:5]
+    Vp = (U[nocc:].conj() @ phi.T) @ (phi.conj() @ U[:nocc].T)      # <c|V_pert|v>
+    drho0 = (4.0 / omega) * np.einsum("vcg,cv->g", P / den[:, :, None], Vp)
+    drho = np.linalg.solve(np.eye(S.size) - chi0_rr @ K, drho0)
+    dv_hxc = K @ drho                                     # Fourier components on the sphere
+    # <c|dV_Hxc|v> = sum_G' dv(G') <c|e^{iG'r}|v> = sum_G' dv(G') conj(P[v, c, G'])
+    Vt = Vp + np.einsum("vcg,g->cv", np.conj(P), dv_hxc)
+    dpsi = ((Vt / den.T).T @ U[nocc:])                    # rows v: sum_c u_c <c|dV|v>/(e_v - e_c)
+    A = phi.conj() @ U[:nocc].T                           # <phi_m|u_v>
+    B = phi.conj() @ dpsi.T                               # <phi_m|du_v>
+    T = B @ A.conj().T
+    dn = 2.0 * (T + T.T)                                  # Eq. 13, two-term form, weight 1
+    ref = o.scf(0, np.zeros(3), oracle.ScfParams(cg_tol=1e-14, conv_thr_chi=1e-14, conv_thr_v=1e-12))
+    assert np.abs(dn - ref["dn"][0]).max() < 1e-12 * np.abs(ref["dn"][0]).max()     # measured 1.1e-14
+    chi, chi_ref = np.trace(dn).real, np.trace(ref["dn"][0]).real
+    assert abs(chi - chi_ref) < 1e-12 * abs(chi_ref)                                  # measured 6.6e-15
+    # and without the Hxc response the same route gives chi0
+    B0 = phi.conj() @ ((Vp / den.T).T @ U[nocc:]).T
+    T0 = B0 @ A.conj().T
+    assert np.abs(2.0 * (T0 + T0.T) - ref["dn0"][0]).max() < 1e-12 * np.abs(ref["dn0"][0]).max()

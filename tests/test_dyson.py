@@ -72,3 +72,65 @@ def test_dyson_solve_equals_self_consistent_sternheimer():
     B0 = phi.conj() @ ((Vp / den.T).T @ U[nocc:]).T
     T0 = B0 @ A.conj().T
     assert np.abs(2.0 * (T0 + T0.T) - ref["dn0"][0]).max() < 1e-12 * np.abs(ref["dn0"][0]).max()
+
+
+def test_dyson_solve_spin_polarized():
+    """The same construction for the polarized one-site system: per-spin bare responses
+    (one electron per state, time reversal 2), the 2 x 2 LSDA kernel and the Hartree
+    kernel of the total density, one joint solve for (drho_up, drho_dn)."""
+    gs = ground_state("sc1_gamma_spin")
+    o = oracle.Oracle(gs)
+    fft, nr, omega = o.fft, o.nr, o.omega
+    nocc = gs.n_occ
+    freq = [np.where(np.arange(n) < (n + 1) // 2, np.arange(n), np.arange(n) - n) for n in fft]
+    M = np.stack(np.meshgrid(*freq, indexing="ij"), -1).reshape(-1, 3)
+    gvec = M @ o.bvec
+    e0 = gs.kpts[0]
+    gmax = np.sqrt(np.einsum("ij,ij->i", (e0.miller @ o.bvec), (e0.miller @ o.bvec)).max())
+    S = np.nonzero(np.einsum("ij,ij->i", gvec, gvec) <= (2 * gmax) ** 2 + 1e-9)[0]
+    ns = S.size
+    blocks = []
+    for sp in range(2):
+        e = gs.kpts[sp]
+        w, V = np.linalg.eigh(o.h_dense(sp))
+        U = V.T
+        psi = np.zeros((U.shape[0], nr), dtype=np.complex128)
+        psi[:, o.grid_index(sp)] = U
+        psi = (sfft.ifftn(psi.reshape((-1,) + fft), axes=(1, 2, 3)) * nr).reshape(U.shape[0], nr)
+        ne = U.shape[0] - nocc
+        P = np.empty((nocc, ne, ns), dtype=np.complex128)
+        for v in range(nocc):
+            prod = np.conj(psi[v])[None, :] * psi[nocc:]
+            P[v] = (sfft.fftn(prod.reshape((-1,) + fft), axes=(1, 2, 3)).reshape(ne, nr) / nr)[:, S]
+        den = w[:nocc, None] - w[None, nocc:]
+        chi0 = (2.0 / omega) * (P / den[:, :, None]).reshape(-1, ns).T @ np.conj(P.reshape(-1, ns))
+        phi = e.phi[0:5]
+        Vp = (U[nocc:].conj() @ phi.T) @ (phi.conj() @ U[:nocc].T)
+        drho0 = (2.0 / omega) * np.einsum("vcg,cv->g", P / den[:, :, None], Vp)
+        blocks.append((U, P, den, chi0, Vp, drho0, phi))
+    g2 = np.einsum("ij,ij->i", gvec[S], gvec[S])
+    vh = np.where(g2 > 1e-12, 4.0 * np.pi / np.where(g2 > 1e-12, g2, 1.0), 0.0)
+    rho = np.asarray(gs.rho0).reshape((2,) + fft)
+    f = pz81.f_xc_spin(rho[0], rho[1])
+    d = (M[S][:, None, :] - M[S][None, :, :]) % np.array(fft)
+    K = np.zeros((2 * ns, 2 * ns), dtype=np.complex128)
+    for a in range(2):
+        for b in range(2):
+            fh = sfft.fftn(f[a, b]) / nr
+            blk = fh[d[..., 0], d[..., 1], d[..., 2]].astype(np.complex128)
+            blk[np.diag_indices(ns)] += vh
+            K[a * ns:(a + 1) * ns, b * ns:(b + 1) * ns] = blk
+    chi0 = np.zeros((2 * ns, 2 * ns), dtype=np.complex128)
+    chi0[:ns, :ns], chi0[ns:, ns:] = blocks[0][3], blocks[1][3]
+    drho0 = np.concatenate([blocks[0][5], blocks[1][5]])
+    drho = np.linalg.solve(np.eye(2 * ns) - chi0 @ K, drho0)
+    dv = K @ drho
+    dn = np.zeros((5, 5), dtype=np.complex128)
+    for sp, (U, P, den, _, Vp, _, phi) in enumerate(blocks):
+        Vt = Vp + np.einsum("vcg,g->cv", np.conj(P), dv[sp * ns:(sp + 1) * ns])
+        dpsi = (Vt / den.T).T @ U[nocc:]
+        A = phi.conj() @ U[:nocc].T
+        T = (phi.conj() @ dpsi.T) @ A.conj().T
+        dn += T + T.T                                     # one electron per state, summed over spins
+    ref = o.scf(0, np.zeros(3), oracle.ScfParams(cg_tol=1e-14, conv_thr_chi=1e-14, conv_thr_v=1e-12))
+    assert np.abs(dn - ref["dn"][0]).max() < 1e-12 * np.abs(ref["dn"][0]).max()

@@ -145,9 +145,9 @@ def _as_polarized(gs):
 
 
 def test_equal_spin_blocks_give_the_unpolarized_response():
-    gs = ground_state("sc1_k211")
-    ref = oracle.Oracle(gs).scf(0, np.array([0.5, 0, 0]), TIGHT)
-    pol = oracle.Oracle(_as_polarized(gs)).scf(0, np.array([0.5, 0, 0]), TIGHT)
+    gs = ground_state("sc1_gamma")
+    ref = oracle.Oracle(gs).scf(0, np.zeros(3), TIGHT)
+    pol = oracle.Oracle(_as_polarized(gs)).scf(0, np.zeros(3), TIGHT)
     for key in ("dn0", "dn"):
         assert np.abs(pol[key] - ref[key]).max() < 1e-11 * np.abs(ref[key]).max()
 

@@ -10,6 +10,7 @@ The response is the linear map the oracle defines (time reversal folded into the
 4; the grid-defined local operators); at Gamma it equals the physical response.
 """
 import numpy as np
+import pytest
 import scipy.fft as sfft
 
 import oracle
@@ -17,9 +18,13 @@ from oracle import pz81
 from conftest import ground_state
 
 
-def test_dyson_solve_equals_self_consistent_sternheimer():
-    gs = ground_state("sc1_gamma")
-    o = oracle.Oracle(gs)
+@pytest.mark.parametrize("name,projectors", [("sc1_gamma", "atomic"), ("sc1_gamma_u", "atomic"),
+                                             ("sc1_gamma", "ortho-atomic")])
+def test_dyson_solve_equals_self_consistent_sternheimer(name, projectors):
+    """Plain, with the ground-state Hubbard potential in H (Eq. 5), and with ortho-atomic
+    projectors (Eq. 6) for the perturbation and the occupations."""
+    gs = ground_state(name)
+    o = oracle.Oracle(gs, projectors=projectors)
     e = gs.kpts[0]
     fft, nr, omega = o.fft, o.nr, o.omega
     nocc = gs.n_occ
@@ -52,7 +57,7 @@ def test_dyson_solve_equals_self_consistent_sternheimer():
     K = fhat[d[..., 0], d[..., 1], d[..., 2]].astype(np.complex128)
     K[np.diag_indices(S.size)] += np.where(g2 > 1e-12, 4.0 * np.pi / np.where(g2 > 1e-12, g2, 1.0), 0.0)
     # bare response to the Hubbard projector of site 0 (Eq. 16)
-    phi = e.phi[0:5]
+    phi = o.phi[0][0:5]
     Vp = (U[nocc:].conj() @ phi.T) @ (phi.conj() @ U[:nocc].T)      # <c|V_pert|v>
     drho0 = (4.0 / omega) * np.einsum("vcg,cv->g", P / den[:, :, None], Vp)
     drho = np.linalg.solve(np.eye(S.size) - chi0_rr @ K, drho0)

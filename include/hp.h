@@ -38,7 +38,9 @@
  *
  * Ownership: input pointers are borrowed for the duration of a call only.
  * hp_ground_state_load copies everything it needs into device memory owned by
- * the returned context; outputs go to caller-allocated host arrays.  A context
+ * the returned context (from host memory, or device to device when
+ * hp_ground_state.inputs_on_device = 1); outputs go to caller-allocated host
+ * arrays.  A context
  * may be used by one host thread at a time; calls on one context are
  * serialized on its stream.
  */
@@ -111,7 +113,17 @@ typedef struct hp_ground_state {
   const hp_kpoint *kpts;  /* [n_kpts]: spin-up block, then (nspin = 2) a spin-down */
                           /* block with the same k points and spheres in order     */
   int32_t xc;             /* HP_XC_LDA_PZ81                                        */
-  int32_t reserved;       /* must be 0                                             */
+  int32_t inputs_on_device; /* 0: every array is host memory.  1: the bulk arrays    */
+                          /* (v_loc, rho0 and, per entry, u, beta, phi, atwfc) are   */
+                          /* device memory on the current device (e.g. torch tensors) */
+                          /* and are copied device to device; the index and scalar   */
+                          /* arrays the load plans from (kpts, miller, eps, d_kb,     */
+                          /* hub_tau, hub_rows, hub_pot) stay host memory.  Host and  */
+                          /* device inputs of equal values give identical contexts    */
+                          /* (the same gathers and reductions run on the device).     */
+                          /* The copies run on `stream`: the caller's writes to the   */
+                          /* device arrays must be complete or ordered before it.     */
+                          /* Other values: HP_ERR_ARG                                 */
   void *stream;           /* hipStream_t to run on, or NULL for a private stream   */
   int32_t projectors;     /* HP_PROJ_ATOMIC: phi as given; HP_PROJ_ORTHO_ATOMIC:   */
                           /* Loewdin-orthogonalized over all atomic orbitals (Eq. 6)*/
@@ -300,6 +312,13 @@ hp_status hp_apply_h(hp_ctx *c, int32_t entry, int32_t n, const double *x, doubl
  * of the entry holding k+q.  mesh_k = spin * n_mesh + k, 0 <= k < n_mesh.  Uses p->cg_tol, p->max_cg_iter, p->precision. */
 hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const double q_frac[3], int32_t mesh_k,
                                const double *dv, const hp_scf_params *p, double *du_out);
+
+/* The library's local xc kernel (the one hp_ground_state_load builds from rho0;
+ * Perdew-Zunger 1981 LDA, zero where the density is below 1e-10) evaluated on the
+ * device at given densities.  nspin = 1: rho [n], fxc_out [n] (Ha bohr^3);
+ * nspin = 2: rho [2][n] (up, down), fxc_out [3][n] (f_uu, f_ud, f_dd, the LSDA
+ * kernel).  Host arrays; HP_ERR_ARG for NULL pointers, n < 1 or nspin not 1 or 2. */
+hp_status hp_xc_kernel(int32_t nspin, int64_t n, const double *rho, double *fxc_out);
 
 /* ---- Per-kernel timing ------------------------------------------------------
  * hp_profile_start enables and resets per-kernel GPU timing on the context's

@@ -10,6 +10,9 @@
 // side is kept in digit-reversed x/y order and no permutation pass is needed:
 // the local potential, the cached occupied states, the response density and
 // potential are all stored in that order.
+#include <algorithm>
+#include <type_traits>
+
 #include "hp_internal.h"
 
 namespace hp {
@@ -803,6 +806,288 @@ __global__ void __launch_bounds__(NT) k_plane_vloc_b(Plane pl, Sticks sk, const 
   }
 }
 
+// ------------------------------------------- register-resident plane round trip (FP32)
+// A thread holds a whole line in registers and runs every radix stage of it there, with the
+// same butterflies, twiddles and order of operations as the LDS stages above (so the
+// results are those of the LDS variants); LDS only carries the two transposes (y columns ->
+// x rows -> y columns).  An x line longer than 72 points whose last radix is 2 is split over
+// two neighbouring lanes by parity: each lane runs the stages before the last on its 72
+// points, and the last radix-2 stage (fused with the multiply by V and the first inverse
+// stage) exchanges values with the partner lane through DPP.
+
+// The partner lane's value (lane ^ 1, DPP quad permutation [1, 0, 3, 2]).
+__device__ __forceinline__ float lane_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+// Stage S of a length-N line held whole in x[0..N): DIF (butterfly, then twiddle) or the
+// reverse-order inverse stage (conjugate twiddle, then butterfly).
+template <int N, int S, bool DIF, class C>
+__device__ __forceinline__ void rstage(C *x, const C *__restrict__ tw) {
+  constexpr int R = crad(N, S), L = cspan(N, S), B = R * L, TSTEP = N / B;
+#pragma unroll
+  for (int blk = 0; blk < N / B; ++blk)
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      C y[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) y[t] = x[blk * B + j + t * L];
+      if constexpr (DIF) {
+        dft_small<R>(y, 1.0);
+        if constexpr (L > 1) {
+#pragma unroll
+          for (int t = 1; t < R; ++t) y[t] = cmul(y[t], tw[j * t * TSTEP]);
+        }
+      } else {
+        if constexpr (L > 1) {
+#pragma unroll
+          for (int t = 1; t < R; ++t) y[t] = cmulc(y[t], tw[j * t * TSTEP]);
+        }
+        dft_small<R>(y, -1.0);
+      }
+#pragma unroll
+      for (int t = 0; t < R; ++t) x[blk * B + j + t * L] = y[t];
+      __builtin_amdgcn_sched_barrier(0);  // one butterfly at a time: bounded register use
+    }
+}
+
+// Stages I..E-1 in DIF order (DIF) or stages E-1..I in inverse order.
+template <int N, int I, int E, bool DIF, class C>
+__device__ __forceinline__ void rstages(C *x, const C *__restrict__ tw) {
+  if constexpr (I < E) {
+    if constexpr (DIF) {
+      rstage<N, I, true>(x, tw);
+      rstages<N, I + 1, E, true>(x, tw);
+    } else {
+      rstage<N, E - 1, false>(x, tw);
+      rstages<N, I, E - 1, false>(x, tw);
+    }
+  }
+}
+
+// Stage S (span >= 2, even) of a length-N line split by parity: this lane holds
+// h[u] = line[2u + par], u < N/2.
+template <int N, int S, bool DIF, class C>
+__device__ __forceinline__ void rstage_half(C *h, const C *__restrict__ tw, int par) {
+  constexpr int R = crad(N, S), L = cspan(N, S), B = R * L, TSTEP = N / B;
+  static_assert(L % 2 == 0, "a split stage needs an even span");
+#pragma unroll
+  for (int blk = 0; blk < N / B; ++blk)
+#pragma unroll
+    for (int jh = 0; jh < L / 2; ++jh) {
+      C y[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) y[t] = h[blk * (B / 2) + jh + t * (L / 2)];
+      // j = 2 jh + par: the twiddle of either parity, chosen per lane
+      auto twid = [&](int t) {
+        const C a = tw[(2 * jh) * t * TSTEP], b = tw[(2 * jh + 1) * t * TSTEP];
+        return par ? b : a;
+      };
+      if constexpr (DIF) {
+        dft_small<R>(y, 1.0);
+#pragma unroll
+        for (int t = 1; t < R; ++t) y[t] = cmul(y[t], twid(t));
+      } else {
+#pragma unroll
+        for (int t = 1; t < R; ++t) y[t] = cmulc(y[t], twid(t));
+        dft_small<R>(y, -1.0);
+      }
+#pragma unroll
+      for (int t = 0; t < R; ++t) h[blk * (B / 2) + jh + t * (L / 2)] = y[t];
+      // keep each butterfly's per-lane twiddles next to it (hoisted, they fill the registers)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int N, int I, int E, bool DIF, class C>
+__device__ __forceinline__ void rstages_half(C *h, const C *__restrict__ tw, int par) {
+  if constexpr (I < E) {
+    if constexpr (DIF) {
+      rstage_half<N, I, true>(h, tw, par);
+      rstages_half<N, I + 1, E, true>(h, tw, par);
+    } else {
+      rstage_half<N, E - 1, false>(h, tw, par);
+      rstages_half<N, I, E - 1, false>(h, tw, par);
+    }
+  }
+}
+
+// Rows of the plane (x lines) handled by one lane, or by a lane pair for long lines.
+template <int N1>
+struct RowSplit {
+  static constexpr int NS = cnst(N1);
+  static constexpr int RS = (N1 > 72 && crad(N1, NS - 1) == 2) ? 2 : 1;
+  static constexpr int H = N1 / RS;
+};
+
+// Workgroup of NT threads: npb consecutive z planes of one band item (set by the launcher
+// so that the lines fill the threads).  LDS holds the list of active x columns and the
+// planes, [plane][N1][N2 | 1] (an odd row stride keeps both the column and the row accesses
+// free of bank conflicts; inactive columns stay zero, so a row is read and written at fixed
+// offsets with no per-x bookkeeping).
+template <int N1, int N2, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_plane_vloc_r(Plane pl, Sticks sk, const KPair *kp, int use_kq, int nb,
+                                                     int npb, const float2 *__restrict__ Sin,
+                                                     float2 *__restrict__ Sout, int ns_pad,
+                                                     const float *__restrict__ vp, const int *active) {
+  using C = float2;
+  constexpr int N2S = N2 | 1, PS = N1 * N2S;
+  constexpr int RS = RowSplit<N1>::RS, H = RowSplit<N1>::H;
+  constexpr int NS1 = cnst(N1), NS2 = cnst(N2);
+  constexpr int NW = (N1 + 63) / 64;
+  static_assert(H <= 72 && N2 <= 72, "line too long for registers");
+  extern __shared__ __align__(16) unsigned char lds[];
+  int *colx = reinterpret_cast<int *>(lds);  // [N1]: flags, then the active x in order
+  C *P = reinterpret_cast<C *>(lds + ((N1 * 4 + 15) / 16) * 16);
+  const int item = blockIdx.y;
+  if (active && !active[item]) return;
+  const int k = item / nb;
+  int e, g0x, g0y, g0z;
+  basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
+  const EntryDev E = sk.ent[e];
+  const int nxa = E.nxa, ns = E.ns;
+  const int z0 = blockIdx.x * npb;
+  const int npl = min(npb, pl.n3 - z0);
+  const C *twx = pl.ax.tw32, *twy = pl.ay.tw32;
+  for (int t = threadIdx.x; t < N1; t += NT) colx[t] = 0;
+  for (int i = threadIdx.x; i < npl * PS; i += NT) P[i] = czero<C>();
+  __syncthreads();
+  const int *xa = sk.xa + E.xa_off;
+  for (int i = threadIdx.x; i < nxa; i += NT) colx[wrap(xa[i] - g0x, N1)] = 1;
+  __syncthreads();
+  if (threadIdx.x < 64) {  // the active x in increasing order (ballot prefix counts)
+    int base = 0, xs[NW], rk[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const int x = 64 * w + (int)threadIdx.x;
+      const int f = x < N1 ? colx[x] : 0;
+      const unsigned long long b = __ballot(f);
+      xs[w] = f ? x : -1;
+      rk[w] = base + __popcll(b & ((1ull << threadIdx.x) - 1ull));
+      base += __popcll(b);
+    }
+    // (every lane of this one wave has read its flags above)
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+      if (xs[w] >= 0) colx[rk[w]] = xs[w];
+  }
+  __syncthreads();
+  const int *sx = sk.sx + E.st_off;
+  const int *sy = sk.sy + E.st_off;
+  const size_t so = ((size_t)item * pl.n3 + z0) * ns_pad;
+  for (int w = threadIdx.x; w < npl * ns; w += NT) {
+    const int p = w / ns, s = w - p * ns;
+    P[p * PS + wrap(sx[s] - g0x, N1) * N2S + wrap(sy[s] - g0y, N2)] = Sin[so + (size_t)p * ns_pad + s];
+  }
+  __syncthreads();
+  // y columns, forward (DIF): natural order in, digit-reversed out
+  for (int w = threadIdx.x; w < npl * nxa; w += NT) {
+    const int p = w / nxa;
+    C *col = P + p * PS + colx[w - p * nxa] * N2S;
+    C y[N2];
+#pragma unroll
+    for (int i = 0; i < N2; ++i) y[i] = col[i];
+    rstages<N2, 0, NS2, true>(y, twy);
+#pragma unroll
+    for (int i = 0; i < N2; ++i) col[i] = y[i];
+  }
+  __syncthreads();
+  // x rows: forward, times V (digit-reversed x and y), inverse
+  const float *vz = vp + ((size_t)kp[k].spin * pl.n3 + z0) * (N1 * N2);
+  for (int w = threadIdx.x; w < npl * N2 * RS; w += NT) {
+    const int p = w / (N2 * RS), rem = w - p * (N2 * RS);
+    const int r = rem / RS, par = rem - r * RS;
+    C *row = P + p * PS + par * N2S + r;  // this lane's points x = RS u + par
+    const float *v = vz + (size_t)p * (N1 * N2) + r;
+    C h[H];
+#pragma unroll
+    for (int u = 0; u < H; ++u) h[u] = row[u * RS * N2S];
+    // V is read in groups of G values, one group ahead of its use: without the schedule
+    // barriers the compiler issues all H loads at once and the row no longer fits the
+    // register file
+    constexpr int G = RS == 1 ? crad(N1, NS1 - 1) : 8;
+    static_assert(H % G == 0, "V groups");
+    float vb[G], vn[G];
+#pragma unroll
+    for (int t = 0; t < G; ++t) vb[t] = v[(RS * t + par) * N2];
+    if constexpr (RS == 1) {
+      rstages<N1, 0, NS1 - 1, true>(h, twx);
+      // last forward stage, times V, first inverse stage (span 1: within the thread)
+#pragma unroll
+      for (int b = 0; b < N1 / G; ++b) {
+        if (b + 1 < N1 / G) {
+#pragma unroll
+          for (int t = 0; t < G; ++t) vn[t] = v[((b + 1) * G + t) * N2];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        C y[G];
+#pragma unroll
+        for (int t = 0; t < G; ++t) y[t] = h[b * G + t];
+        dft_small<G>(y, 1.0);
+#pragma unroll
+        for (int t = 0; t < G; ++t) y[t] = cscale(y[t], vb[t]);
+        dft_small<G>(y, -1.0);
+#pragma unroll
+        for (int t = 0; t < G; ++t) h[b * G + t] = y[t];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int t = 0; t < G; ++t) vb[t] = vn[t];
+      }
+      rstages<N1, 0, NS1 - 1, false>(h, twx);
+    } else {
+      rstages_half<N1, 0, NS1 - 1, true>(h, twx, par);
+      // last stage: radix 2 over the pair (2u, 2u + 1) = (this lane, partner) or reverse
+#pragma unroll
+      for (int b = 0; b < H / G; ++b) {
+        if (b + 1 < H / G) {
+#pragma unroll
+          for (int t = 0; t < G; ++t) vn[t] = v[(2 * ((b + 1) * G + t) + par) * N2];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+          const int u = b * G + t;
+          const C o = h[u];
+          C q;
+          q.x = lane_xor1(o.x);
+          q.y = lane_xor1(o.y);
+          const C a = par ? q : o, bb = par ? o : q;
+          C y = par ? csub(a, bb) : cadd(a, bb);
+          y = cscale(y, vb[t]);
+          C q2;
+          q2.x = lane_xor1(y.x);
+          q2.y = lane_xor1(y.y);
+          const C a2 = par ? q2 : y, b2 = par ? y : q2;
+          h[u] = par ? csub(a2, b2) : cadd(a2, b2);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int t = 0; t < G; ++t) vb[t] = vn[t];
+      }
+      rstages_half<N1, 0, NS1 - 1, false>(h, twx, par);
+    }
+#pragma unroll
+    for (int u = 0; u < H; ++u) row[u * RS * N2S] = h[u];
+  }
+  __syncthreads();
+  // y columns, inverse: digit-reversed in, natural out
+  for (int w = threadIdx.x; w < npl * nxa; w += NT) {
+    const int p = w / nxa;
+    C *col = P + p * PS + colx[w - p * nxa] * N2S;
+    C y[N2];
+#pragma unroll
+    for (int i = 0; i < N2; ++i) y[i] = col[i];
+    rstages<N2, 0, NS2, false>(y, twy);
+#pragma unroll
+    for (int i = 0; i < N2; ++i) col[i] = y[i];
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < npl * ns; w += NT) {
+    const int p = w / ns, s = w - p * ns;
+    Sout[so + (size_t)p * ns_pad + s] = P[p * PS + wrap(sx[s] - g0x, N1) * N2S + wrap(sy[s] - g0y, N2)];
+  }
+}
+
 template <int N1, int N2>
 __global__ void __launch_bounds__(kThreads) k_plane_to_real(Plane pl, Sticks sk, const KPair *kp, int use_kq,
                                                             int nb, const double2 *__restrict__ Sin, int ns_pad,
@@ -1250,12 +1535,39 @@ hipError_t launch_stick_fwd32(const Sticks &sk, const KPair *kp, int use_kq, int
 
 constexpr int kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 
+// Register-resident variants: threads per workgroup, and the LDS header before the planes.
+constexpr int kRegThreads[3] = {128, 192, 256};
+int reg_lds_header(int n1) { return ((n1 * 4 + 15) / 16) * 16; }
+int reg_row_lanes(const Plane &pl) {
+  int n = pl.n1, ns = 0, last = 1;
+  for (; n > 1; ++ns) {
+    last = n % 8 == 0 ? 8 : n % 9 == 0 ? 9 : n % 4 == 0 ? 4 : n % 2 == 0 ? 2 : n % 3 == 0 ? 3 : 5;
+    n /= last;
+  }
+  return (pl.n1 > 72 && last == 2) ? 2 : 1;
+}
+// z planes per workgroup of a register-resident variant: as many as the y columns and the
+// x-row lanes fill the threads, within the LDS.
+int reg_planes(const Plane &pl, int variant) {
+  const int nt = kRegThreads[variant - 4];
+  const int lines = std::max(std::max(pl.nxa_max, 1), pl.n2 * reg_row_lanes(pl));
+  int pb = std::max(1, std::min(nt / lines, pl.n3));
+  const size_t per = (size_t)pl.n1 * (pl.n2 | 1) * sizeof(float2);
+  while (pb > 1 && reg_lds_header(pl.n1) + pb * per > (size_t)kLdsBytes) --pb;
+  return pb;
+}
+
 bool plane_vloc_variant_ok(const Plane &pl, int csize, int variant) {
   const int key = pl.n1 * 1000 + pl.n2;
   const bool shape = key == 72045 || key == 144045 || key == 30024;
   if (variant == 0) return true;
   if (variant == 1 || variant == 2) return shape && pl.n3 % 2 == 0 && plane_lds_t(pl, csize, 2) <= kLdsBytes;
   if (variant == 3) return shape;
+  if (variant >= 4 && variant <= 6) {
+    const bool ct = key == 24024 || key == 30024 || key == 48024 || key == 48048 || key == 72045 || key == 144045;
+    const size_t lds = reg_lds_header(pl.n1) + (size_t)reg_planes(pl, variant) * pl.n1 * (pl.n2 | 1) * sizeof(float2);
+    return csize == (int)sizeof(float2) && ct && pl.nxa_max >= 1 && lds <= (size_t)kLdsBytes;
+  }
   return false;
 }
 
@@ -1283,11 +1595,48 @@ hipError_t plane_vloc_batched(int variant, const Plane &pl, const Sticks &sk, co
   return hipGetLastError();
 }
 
+template <int N1, int N2>
+hipError_t plane_vloc_reg(int variant, const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb,
+                          int nitems, const float2 *Sin, float2 *Sout, int ns_pad, const float *vp, const int *active,
+                          hipStream_t st) {
+  const int pb = reg_planes(pl, variant);
+  const size_t lds = reg_lds_header(N1) + (size_t)pb * N1 * (N2 | 1) * sizeof(float2);
+  const dim3 grid((pl.n3 + pb - 1) / pb, nitems);
+  switch (kRegThreads[variant - 4]) {
+    case 128:
+      hipLaunchKernelGGL((k_plane_vloc_r<N1, N2, 128>), grid, dim3(128), lds, st, pl, sk, kp, use_kq, nb, pb, Sin,
+                         Sout, ns_pad, vp, active);
+      break;
+    case 192:
+      hipLaunchKernelGGL((k_plane_vloc_r<N1, N2, 192>), grid, dim3(192), lds, st, pl, sk, kp, use_kq, nb, pb, Sin,
+                         Sout, ns_pad, vp, active);
+      break;
+    default:
+      hipLaunchKernelGGL((k_plane_vloc_r<N1, N2, 256>), grid, dim3(256), lds, st, pl, sk, kp, use_kq, nb, pb, Sin,
+                         Sout, ns_pad, vp, active);
+      break;
+  }
+  return hipGetLastError();
+}
+
 template <class C>
 hipError_t plane_vloc_t(int variant, const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb,
                         int nitems, const C *Sin, C *Sout, int ns_pad, const RealOf<C> *vp, const int *active,
                         hipStream_t st) {
-  if (variant > 0 && plane_vloc_variant_ok(pl, sizeof(C), variant)) {
+  if constexpr (std::is_same<C, float2>::value) {
+    if (variant >= 4 && plane_vloc_variant_ok(pl, sizeof(C), variant)) {
+      switch (pl.n1 * 1000 + pl.n2) {
+        case 24024: return plane_vloc_reg<24, 24>(variant, pl, sk, kp, use_kq, nb, nitems, Sin, Sout, ns_pad, vp, active, st);
+        case 30024: return plane_vloc_reg<30, 24>(variant, pl, sk, kp, use_kq, nb, nitems, Sin, Sout, ns_pad, vp, active, st);
+        case 48024: return plane_vloc_reg<48, 24>(variant, pl, sk, kp, use_kq, nb, nitems, Sin, Sout, ns_pad, vp, active, st);
+        case 48048: return plane_vloc_reg<48, 48>(variant, pl, sk, kp, use_kq, nb, nitems, Sin, Sout, ns_pad, vp, active, st);
+        case 72045: return plane_vloc_reg<72, 45>(variant, pl, sk, kp, use_kq, nb, nitems, Sin, Sout, ns_pad, vp, active, st);
+        case 144045: return plane_vloc_reg<144, 45>(variant, pl, sk, kp, use_kq, nb, nitems, Sin, Sout, ns_pad, vp, active, st);
+        default: break;
+      }
+    }
+  }
+  if (variant > 0 && variant < 4 && plane_vloc_variant_ok(pl, sizeof(C), variant)) {
     switch (pl.n1 * 1000 + pl.n2) {
       case 72045:
         return plane_vloc_batched<72, 45, C>(variant, pl, sk, kp, use_kq, nb, nitems, Sin, Sout, ns_pad, vp, active,

@@ -218,7 +218,7 @@ struct hp_ctx {
   float stick_ms[2][2][2] = {};
   bool stick_tuned[2] = {false, false};
   int plane_nvar[2] = {0, 0};
-  float plane_ms[2][4] = {};
+  float plane_ms[2][kPlaneVariants] = {};
   bool plane_tuned[2] = {false, false};
   int use_tuned = 0;  // hp_scf_params.autotune of the current call
   double *d_tol = nullptr;  // [0] tolerance of the FP64 CG, [1] of the FP32 inner CG
@@ -553,43 +553,52 @@ GemmShape gemm_shape(const hp_ctx *c, int prec, int M, int nk) {
 int plane_variant(const hp_ctx *c, int prec) { return c->use_tuned ? c->plane_var[prec == 32 ? 1 : 0] : 0; }
 int stick_variant(const hp_ctx *c, int prec, int fwd) { return c->use_tuned ? c->stick_var[prec == 32][fwd] : 0; }
 
-// C[k][m][v] = scale_m * sum_G conj(T[m0+m][G]) X[k,v][G]
+// C[k][m][v] = scale_m * sum_G conj(T[m0+m][G]) X[k,v][G]  (K-split partials in cpart, or the
+// context's buffer)
 hp_status proj(hp_ctx *c, const KPair *kp, int use_kq, int nk, const double2 *T, long tstride, int m0, int M,
                const double2 *X, int nb, const double *row_scale, double gscale, double2 *Cout,
-               const int *active = nullptr) {
+               const int *active = nullptr, double2 *cpart = nullptr) {
   const GemmShape gs = gemm_shape(c, 64, M, nk);
   const int ns = gs.ns;
+  double2 *cp = cpart ? cpart : c->Cpart;
   HPCHK(timed(c, K_ZPROJ, [&] {
-    return launch_zproj(kp, use_kq, nk, T, tstride, m0, M, X, c->ld, nb, c->d_npw, c->Cpart, ns, active, gs.tile,
+    return launch_zproj(kp, use_kq, nk, T, tstride, m0, M, X, c->ld, nb, c->d_npw, cp, ns, active, gs.tile,
                         c->stream);
   }));
   HPCHK(timed(c, K_ZPROJ_REDUCE, [&] {
-    return launch_zproj_reduce(nk, M, nb, ns, c->Cpart, row_scale, gscale, Cout, c->stream);
+    return launch_zproj_reduce(nk, M, nb, ns, cp, row_scale, gscale, Cout, c->stream);
   }));
   return HP_OK;
 }
 
+// Intermediate buffers of one operator apply: z-stick data before and after the plane
+// round trip, projection partial sums (K split) and projections.
+struct OpWork {
+  double2 *S1, *S2, *Cpart, *C;
+};
+
 // Y = (H_{k+q} + alpha P_v - eps_v) X over nitems (or H_k X for diagnostics when eps == nullptr,
-// rows = n_beta only).
+// rows = n_beta only).  w: intermediate buffers (null: the context's).
 hp_status apply_op(hp_ctx *c, const KPair *kp, int use_kq, int nk, int nb, const double2 *Xin, double2 *Y,
-                   const double *eps, int rows, const int *active = nullptr) {
+                   const double *eps, int rows, const int *active = nullptr, const OpWork *w = nullptr) {
   const int nitems = nk * nb;
+  const OpWork wk = w ? *w : OpWork{c->S1, c->S2, c->Cpart, c->C};
   HPCHK(timed(c, K_STICK_INV, [&] {
-    return launch_stick_inv(c->sk, kp, use_kq, nb, nitems, Xin, c->ld, c->S1, c->ns_pad, c->n3, c->az.tw,
+    return launch_stick_inv(c->sk, kp, use_kq, nb, nitems, Xin, c->ld, wk.S1, c->ns_pad, c->n3, c->az.tw,
                             c->max_chunk_pw, c->ns_max, active, stick_variant(c, 64, 0), c->stream);
   }));
   HPCHK(timed(c, K_PLANE_VLOC, [&] {
-    return launch_plane_vloc(c->pl, c->sk, kp, use_kq, nb, nitems, c->S1, c->S2, c->ns_pad, c->d_vp, active,
+    return launch_plane_vloc(c->pl, c->sk, kp, use_kq, nb, nitems, wk.S1, wk.S2, c->ns_pad, c->d_vp, active,
                              plane_variant(c, 64), c->stream);
   }));
   HPCHK(timed(c, K_STICK_FWD, [&] {
-    return launch_stick_fwd(c->sk, kp, use_kq, nb, nitems, c->S2, c->ns_pad, c->n3, c->az.tw, 1.0 / (double)c->nr, Y,
-                            c->ld, 0, c->d_kin, eps, Xin, nb, c->max_chunk_pw, c->ns_max, active,
+    return launch_stick_fwd(c->sk, kp, use_kq, nb, nitems, wk.S2, c->ns_pad, c->n3, c->az.tw, 1.0 / (double)c->nr,
+                            Y, c->ld, 0, c->d_kin, eps, Xin, nb, c->max_chunk_pw, c->ns_max, active,
                             stick_variant(c, 64, 1), c->stream);
   }));
-  HPTRY(proj(c, kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, Xin, nb, c->d_rowscale, 1.0, c->C, active));
+  HPTRY(proj(c, kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, Xin, nb, c->d_rowscale, 1.0, wk.C, active, wk.Cpart));
   HPCHK(timed(c, K_ZEXPAND, [&] {
-    return launch_zexpand(kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, c->C, (long)rows * nb, 1.0, Y, c->ld, nb,
+    return launch_zexpand(kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, wk.C, (long)rows * nb, 1.0, Y, c->ld, nb,
                           c->d_npw, c->npw_max, active, gemm_shape(c, 64, rows, nk).bv, c->stream);
   }));
   return HP_OK;
@@ -1038,7 +1047,7 @@ hp_status tune_plane(hp_ctx *c, int prec, int nk) {
   if (c->plane_tuned[slot]) return HP_OK;
   const int nb = c->n_occ, nitems = nk * nb;
   const int csize = prec == 32 ? (int)sizeof(float2) : (int)sizeof(double2);
-  const int nv = 4;
+  const int nv = kPlaneVariants;
   float best = 1e30f;
   for (int v = 0; v < nv; ++v) {
     c->plane_ms[slot][v] = -1.f;  // not available for this grid
@@ -1168,13 +1177,18 @@ hp_status cg_solve_mixed(hp_ctx *c, const KPair *kp, int nk, const double *eps_i
     if (h_count[kCntResid + 1] > 0) return fail(HP_ERR_NUMERIC, "non-finite residual in the Sternheimer solve");
     nact = h_count[kCntResid];
     if (nact == 0 || ref == max_refine) break;
-    // inner FP32 PCG on the refined items
+    // inner FP32 PCG on the refined items.  Its stopping threshold per item is
+    // max(tol_in ||r0||, floor) with floor = tol ||B|| / 2 (set by the residual kernel).
+    // When the inner result is trusted as the final one, the relative part is dropped
+    // (tol_in = 0): the inner solve then runs to the outer tolerance itself, whatever
+    // inner_tol is, so a cold start with tol < inner_tol is not stopped early.
+    const double tol_in = trust ? 0.0 : inner_tol;
     HPCHK(timed(c, K_CG_INIT, [&] {
       return launch_cg_init32(kp, nb, nitems, c->B32, c->X32, c->R32, c->P32, c->d_diag, eps_items, c->ld, c->d_npw,
-                              c->ld, c->rz_in, c->bn_in, c->rn_in, c->act_in, inner_tol, c->act_out, c->floor_in,
+                              c->ld, c->rz_in, c->bn_in, c->rn_in, c->act_in, tol_in, c->act_out, c->floor_in,
                               c->stream);
     }));
-    HPTRY(set_tol(c, 1, inner_tol));
+    HPTRY(set_tol(c, 1, tol_in));
     int inner_active = nact;  // at most the refined items
     int k_in = 0;
     while (inner_active > 0 && k_in < max_it) {
@@ -1323,27 +1337,17 @@ void apply_call_params(hp_ctx *c, const hp_scf_params *p) {
 // O_k^-1/2 on the host (one thread per entry), then phi~_{5s+m} = sum_j (O^-1/2)_{j,r}
 // phi_j with r = hub_rows[5s+m] on the matrix cores (one launch).
 hp_status ortho_atomic_projectors(hp_ctx *c, const hp_ground_state *gs, const std::vector<const hp_kpoint *> &KP,
-                                  const std::vector<Layout> &lay) {
+                                  const int *d_order, const std::vector<int> &pw_off) {
   const int na = gs->n_atwfc, nh5 = 5 * c->n_hub, ne = c->n_kpts;
   const long at_stride = (long)na * c->ld;
-  std::vector<double2> h_at((size_t)ne * at_stride, make_double2(0.0, 0.0));
-  for (int i = 0; i < ne; ++i) {
-    const hp_kpoint &k = *KP[i];
-    double2 *A = h_at.data() + (size_t)i * at_stride;
-    for (int p = 0; p < k.npw; ++p) {
-      const int q = lay[i].order[p];
-      for (int j = 0; j < na; ++j)
-        A[(size_t)j * c->ld + p] =
-            make_double2(k.atwfc[2 * ((size_t)j * k.npw + q)], k.atwfc[2 * ((size_t)j * k.npw + q) + 1]);
-    }
-  }
+  const bool on_dev = gs->inputs_on_device == 1;
   const int ns = std::max(1, std::min(8, c->npw_max / 512));
-  double2 *d_at = nullptr, *d_part = nullptr, *d_O = nullptr, *d_X = nullptr;
-  HPTRY(dalloc(&d_at, h_at.size()));
+  double2 *d_at = nullptr, *d_part = nullptr, *d_O = nullptr, *d_X = nullptr, *stage = nullptr;
+  HPTRY(dalloc(&d_at, (size_t)ne * at_stride));
   hp_status st = HP_OK;
   auto cleanup = [&] {
     (void)hipStreamSynchronize(c->stream);
-    for (double2 *ptr : {d_at, d_part, d_O, d_X})
+    for (double2 *ptr : {d_at, d_part, d_O, d_X, stage})
       if (ptr) (void)hipFree(ptr);
   };
   std::vector<std::complex<double>> O((size_t)ne * na * na), X((size_t)ne * na * nh5);
@@ -1351,7 +1355,20 @@ hp_status ortho_atomic_projectors(hp_ctx *c, const hp_ground_state *gs, const st
     if ((st = dalloc(&d_part, (size_t)ns * ne * na * na)) != HP_OK) break;
     if ((st = dalloc(&d_O, (size_t)ne * na * na)) != HP_OK) break;
     if ((st = dalloc(&d_X, (size_t)ne * na * nh5)) != HP_OK) break;
-    hipError_t e = hipMemcpyAsync(d_at, h_at.data(), sizeof(double2) * h_at.size(), hipMemcpyHostToDevice, c->stream);
+    if (!on_dev && (st = dalloc(&stage, (size_t)na * c->npw_max)) != HP_OK) break;
+    // every entry's orbitals in the stick order (host arrays staged through one buffer)
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < ne && e == hipSuccess; ++i) {
+      const hp_kpoint &k = *KP[i];
+      const double2 *from = (const double2 *)k.atwfc;
+      if (!on_dev) {
+        e = hipMemcpyAsync(stage, k.atwfc, sizeof(double2) * (size_t)na * k.npw, hipMemcpyHostToDevice, c->stream);
+        from = stage;
+      }
+      if (e == hipSuccess) e = launch_gather_rows(from, k.npw, d_order + pw_off[i], na, d_at + (size_t)i * at_stride,
+                                                  c->ld, c->stream);
+      if (e == hipSuccess && !on_dev) e = hipStreamSynchronize(c->stream);
+    }
     if (e == hipSuccess)
       e = launch_zproj(c->d_kself, 0, ne, d_at, at_stride, 0, na, d_at, c->ld, na, c->d_npw, d_part, ns, nullptr, 0,
                        c->stream);
@@ -1614,7 +1631,8 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   if (gs->spin_factor != 3 - gs->nspin)
     return fail(HP_ERR_ARG, "spin_factor must be %d with nspin = %d", 3 - gs->nspin, gs->nspin);
   if (gs->xc != HP_XC_LDA_PZ81) return fail(HP_ERR_ARG, "unknown xc %d", gs->xc);
-  if (gs->reserved != 0) return fail(HP_ERR_ARG, "reserved must be 0");
+  if (gs->inputs_on_device != 0 && gs->inputs_on_device != 1) return fail(HP_ERR_ARG, "inputs_on_device must be 0 or 1");
+  const bool on_dev = gs->inputs_on_device == 1;
   if (gs->projectors != HP_PROJ_ATOMIC && gs->projectors != HP_PROJ_ORTHO_ATOMIC)
     return fail(HP_ERR_ARG, "unknown projectors %d", gs->projectors);
   if (!gs->v_loc || !gs->rho0 || !gs->d_kb || !gs->hub_tau || !gs->kpts) return fail(HP_ERR_ARG, "NULL array");
@@ -1695,8 +1713,9 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
     }
   }
   const long nrr = (long)gs->fft[0] * gs->fft[1] * gs->fft[2] * gs->nspin;
-  for (long i = 0; i < nrr; ++i)
-    if (!std::isfinite(gs->v_loc[i]) || !std::isfinite(gs->rho0[i])) return fail(HP_ERR_NUMERIC, "non-finite v_loc/rho0");
+  if (!on_dev)  // device inputs are checked on the device below
+    for (long i = 0; i < nrr; ++i)
+      if (!std::isfinite(gs->v_loc[i]) || !std::isfinite(gs->rho0[i])) return fail(HP_ERR_NUMERIC, "non-finite v_loc/rho0");
 
   // on an early error return the partly built context, device memory included, is destroyed
   std::unique_ptr<hp_ctx, void (*)(hp_ctx *)> c(new hp_ctx(), hp_destroy);
@@ -1818,6 +1837,8 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   c->pl.n1 = c->n1;
   c->pl.n2 = c->n2;
   c->pl.n3 = c->n3;
+  c->pl.nxa_max = 0;
+  for (int i = 0; i < gs->n_kpts; ++i) c->pl.nxa_max = std::max(c->pl.nxa_max, (int)lay[i].xa.size());
   c->az = ax[2];
   if (c->np * (long)sizeof(double2) > 160 * 1024) return fail(HP_ERR_SHAPE, "xy plane does not fit in LDS");
   c->px = dif_perm(c->n1, rad[0]);
@@ -1834,11 +1855,20 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   HPTRY(c->alloc(&d_nat, (size_t)ns * c->nr));
   HPTRY(c->alloc(&c->d_vp, (size_t)ns * c->nr));
   HPTRY(c->alloc(&c->d_fxc, (size_t)(ns == 2 ? 3 : 1) * c->nr));
-  HPCHK(hipMemcpyAsync(d_nat, gs->v_loc, sizeof(double) * ns * c->nr, hipMemcpyHostToDevice, st));
+  // host inputs are copied in, device inputs (inputs_on_device) copied device to device
+  const hipMemcpyKind in_kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  // per spin: sum and non-finite count of v_loc, then of rho0 (fixed-order reduction, so
+  // host and device inputs give the same mean potential)
+  double *d_stats = nullptr, *d_vmean = nullptr;
+  HPTRY(c->alloc(&d_stats, (size_t)4 * ns));
+  HPTRY(c->alloc(&d_vmean, 2));
+  HPCHK(hipMemcpyAsync(d_nat, gs->v_loc, sizeof(double) * ns * c->nr, in_kind, st));
+  HPCHK(launch_block_stats(d_nat, ns, c->nr, d_stats, st));
   for (int sp = 0; sp < ns; ++sp)
     HPCHK(launch_permute_real(c->pl, c->d_px, c->d_py, d_nat + sp * c->nr, c->d_vp + sp * c->nr, st));
   HPTRY(sync(c.get()));
-  HPCHK(hipMemcpyAsync(d_nat, gs->rho0, sizeof(double) * ns * c->nr, hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(d_nat, gs->rho0, sizeof(double) * ns * c->nr, in_kind, st));
+  HPCHK(launch_block_stats(d_nat, ns, c->nr, d_stats + 2 * ns, st));
   double *d_rhop = nullptr;
   HPTRY(c->alloc(&d_rhop, (size_t)ns * c->nr));
   for (int sp = 0; sp < ns; ++sp)
@@ -1850,22 +1880,25 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   HPTRY(c->alloc(&c->d_bvec, 9));
   HPCHK(hipMemcpyAsync(c->d_bvec, c->bvec, sizeof(double) * 9, hipMemcpyHostToDevice, st));
   double vmean_s[2] = {0.0, 0.0};
-  for (int sp = 0; sp < ns; ++sp) {
-    for (long i = 0; i < c->nr; ++i) vmean_s[sp] += gs->v_loc[sp * c->nr + i];
-    vmean_s[sp] /= (double)c->nr;
+  {
+    double h_stats[8];
+    HPCHK(hipMemcpyAsync(h_stats, d_stats, sizeof(double) * 4 * ns, hipMemcpyDeviceToHost, st));
+    HPTRY(sync(c.get()));
+    for (int b = 0; b < 2 * ns; ++b)
+      if (h_stats[2 * b + 1] != 0.0) return fail(HP_ERR_NUMERIC, "non-finite v_loc/rho0");
+    for (int sp = 0; sp < ns; ++sp) vmean_s[sp] = h_stats[2 * sp] / (double)c->nr;
+    HPCHK(hipMemcpyAsync(d_vmean, vmean_s, sizeof(double) * 2, hipMemcpyHostToDevice, st));
   }
 
   // per-entry tables in the stick order
-  std::vector<int> h_sx, h_sy, h_ss, h_sl, h_iz, h_xa, h_npw(c->n_kpts);
+  std::vector<int> h_sx, h_sy, h_ss, h_sl, h_iz, h_xa, h_npw(c->n_kpts), h_order;
   std::vector<EntryDev> h_ent(c->n_kpts);
-  std::vector<double> h_kin, h_diag((size_t)c->n_kpts * c->ld, 0.0);
-  std::vector<double2> h_T((size_t)c->n_kpts * c->t_stride), h_phi((size_t)c->n_kpts * c->phi_stride);
+  std::vector<double> h_kin;
   int pw_off = 0;
   c->ent.resize(c->n_kpts);
   for (int i = 0; i < c->n_kpts; ++i) {
     const hp_kpoint &k = *KP[i];
     const Layout &L = lay[i];
-    const double vmean = vmean_s[spin_of[i]];
     EntryDev E{};
     E.npw = k.npw;
     E.ns = (int)L.sx.size();
@@ -1888,9 +1921,7 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
     he.npw = k.npw;
     he.spin = spin_of[i];
     he.order = L.order;
-    double2 *T = h_T.data() + (size_t)i * c->t_stride;
-    double2 *F = h_phi.data() + (size_t)i * c->phi_stride;
-    double *dg = h_diag.data() + (size_t)i * c->ld;
+    h_order.insert(h_order.end(), L.order.begin(), L.order.end());
     for (int p = 0; p < k.npw; ++p) {
       const int q = L.order[p];
       double kv[3];
@@ -1898,26 +1929,8 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
         kv[a] = 0.0;
         for (int b = 0; b < 3; ++b) kv[a] += (k.miller[3 * q + b] + k.k_frac[b]) * c->bvec[b * 3 + a];
       }
-      const double kin = 0.5 * (kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2]);
-      h_kin.push_back(kin);
-      double d = kin + vmean;
-      for (int b = 0; b < c->n_kb; ++b) {
-        const double2 val = make_double2(k.beta[2 * ((size_t)b * k.npw + q)], k.beta[2 * ((size_t)b * k.npw + q) + 1]);
-        T[(size_t)b * c->ld + p] = val;
-        d += gs->d_kb[b] * (val.x * val.x + val.y * val.y);
-      }
-      for (int v = 0; v < c->n_occ; ++v) {
-        const double2 val = make_double2(k.u[2 * ((size_t)v * k.npw + q)], k.u[2 * ((size_t)v * k.npw + q) + 1]);
-        T[(size_t)(c->n_beta + v) * c->ld + p] = val;
-        d += c->alpha * (val.x * val.x + val.y * val.y);
-      }
-      if (gs->projectors == HP_PROJ_ATOMIC)
-        for (int m = 0; m < 5 * c->n_hub; ++m)
-          F[(size_t)m * c->ld + p] =
-              make_double2(k.phi[2 * ((size_t)m * k.npw + q)], k.phi[2 * ((size_t)m * k.npw + q) + 1]);
-      dg[p] = d;
+      h_kin.push_back(0.5 * (kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2]));
     }
-    for (int p = k.npw; p < c->ld; ++p) dg[p] = 1.0;
   }
   int *d_sx, *d_sy, *d_ss, *d_sl, *d_iz, *d_xa;
   EntryDev *d_ent;
@@ -1930,9 +1943,11 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   HPTRY(c->alloc(&d_ent, h_ent.size()));
   HPTRY(c->alloc(&c->d_npw, h_npw.size()));
   HPTRY(c->alloc(&c->d_kin, h_kin.size()));
-  HPTRY(c->alloc(&c->d_diag, h_diag.size()));
-  HPTRY(c->alloc(&c->d_T, h_T.size()));
-  HPTRY(c->alloc(&c->d_phi, h_phi.size()));
+  HPTRY(c->alloc(&c->d_diag, (size_t)c->n_kpts * c->ld));
+  HPTRY(c->alloc(&c->d_T, (size_t)c->n_kpts * c->t_stride));
+  HPTRY(c->alloc(&c->d_phi, (size_t)c->n_kpts * c->phi_stride));
+  int *d_order = nullptr;
+  HPTRY(c->alloc(&d_order, h_order.size()));
   HPCHK(hipMemcpyAsync(d_sx, h_sx.data(), sizeof(int) * h_sx.size(), hipMemcpyHostToDevice, st));
   HPCHK(hipMemcpyAsync(d_sy, h_sy.data(), sizeof(int) * h_sy.size(), hipMemcpyHostToDevice, st));
   HPCHK(hipMemcpyAsync(d_ss, h_ss.data(), sizeof(int) * h_ss.size(), hipMemcpyHostToDevice, st));
@@ -1942,9 +1957,48 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   HPCHK(hipMemcpyAsync(d_ent, h_ent.data(), sizeof(EntryDev) * h_ent.size(), hipMemcpyHostToDevice, st));
   HPCHK(hipMemcpyAsync(c->d_npw, h_npw.data(), sizeof(int) * h_npw.size(), hipMemcpyHostToDevice, st));
   HPCHK(hipMemcpyAsync(c->d_kin, h_kin.data(), sizeof(double) * h_kin.size(), hipMemcpyHostToDevice, st));
-  HPCHK(hipMemcpyAsync(c->d_diag, h_diag.data(), sizeof(double) * h_diag.size(), hipMemcpyHostToDevice, st));
-  HPCHK(hipMemcpyAsync(c->d_T, h_T.data(), sizeof(double2) * h_T.size(), hipMemcpyHostToDevice, st));
-  HPCHK(hipMemcpyAsync(c->d_phi, h_phi.data(), sizeof(double2) * h_phi.size(), hipMemcpyHostToDevice, st));
+  HPCHK(hipMemcpyAsync(d_order, h_order.data(), sizeof(int) * h_order.size(), hipMemcpyHostToDevice, st));
+  HPCHK(hipMemsetAsync(c->d_T, 0, sizeof(double2) * (size_t)c->n_kpts * c->t_stride, st));
+  HPCHK(hipMemsetAsync(c->d_phi, 0, sizeof(double2) * (size_t)c->n_kpts * c->phi_stride, st));
+  {
+    // KB rows, occupied states and (atomic projectors) the d orbitals of every entry, gathered
+    // into the stick order on the device: from the caller's device arrays, or from host
+    // arrays staged through one device buffer
+    const int nphi = gs->projectors == HP_PROJ_ATOMIC ? 5 * c->n_hub : 0;
+    const int nrow = c->n_kb + c->n_occ + nphi;
+    double2 *stage = nullptr;
+    if (!on_dev) HPTRY(dalloc(&stage, (size_t)nrow * c->npw_max));
+    hp_status sst = HP_OK;
+    for (int i = 0; i < c->n_kpts && sst == HP_OK; ++i) {
+      const hp_kpoint &k = *KP[i];
+      const int npw = k.npw;
+      const int *ord = d_order + h_ent[i].pw_off;
+      const double2 *src[3] = {(const double2 *)k.beta, (const double2 *)k.u, (const double2 *)k.phi};
+      const int rows[3] = {c->n_kb, c->n_occ, nphi};
+      double2 *dst[3] = {c->d_T + (size_t)i * c->t_stride, c->d_T + (size_t)i * c->t_stride + (size_t)c->n_beta * c->ld,
+                         c->d_phi + (size_t)i * c->phi_stride};
+      size_t off = 0;
+      hipError_t e = hipSuccess;
+      for (int t = 0; t < 3 && e == hipSuccess; ++t) {
+        if (rows[t] == 0) continue;
+        const double2 *from = src[t];
+        if (!on_dev) {
+          e = hipMemcpyAsync(stage + off, src[t], sizeof(double2) * (size_t)rows[t] * npw, hipMemcpyHostToDevice, st);
+          from = stage + off;
+          off += (size_t)rows[t] * npw;
+        }
+        if (e == hipSuccess) e = launch_gather_rows(from, npw, ord, rows[t], dst[t], c->ld, st);
+      }
+      // the staging buffer is reused by the next entry
+      if (e == hipSuccess && !on_dev) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) sst = fail(HP_ERR_HIP, "loading kpts[%d]: %s", i, hipGetErrorString(e));
+    }
+    if (stage) {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(stage);
+    }
+    if (sst != HP_OK) return sst;
+  }
   c->sk.sx = d_sx;
   c->sk.sy = d_sy;
   c->sk.sstart = d_ss;
@@ -2027,43 +2081,47 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   HPTRY(c->alloc(&c->dn, (size_t)25 * c->n_hub));
   HPTRY(c->alloc(&c->d_q, 3));
 
-  if (gs->projectors == HP_PROJ_ORTHO_ATOMIC) HPTRY(ortho_atomic_projectors(c.get(), gs, KP, lay));
+  if (gs->projectors == HP_PROJ_ORTHO_ATOMIC) {
+    std::vector<int> pw_offs(c->n_kpts);
+    for (int i = 0; i < c->n_kpts; ++i) pw_offs[i] = h_ent[i].pw_off;
+    HPTRY(ortho_atomic_projectors(c.get(), gs, KP, d_order, pw_offs));
+  }
   if (gs->hub_pot) {
     // rows of the ground-state Hubbard potential from the final projectors of each entry:
     // chi_a = sum_m V_ma phi_m scaled by sqrt|lam_a| into the +1 (lam > 0) or -1 (lam < 0)
-    // block; the Jacobi diagonal gains sum_a lam_a |chi_a(G)|^2
-    if (gs->projectors == HP_PROJ_ORTHO_ATOMIC) {
-      HPCHK(hipMemcpyAsync(h_phi.data(), c->d_phi, sizeof(double2) * h_phi.size(), hipMemcpyDeviceToHost, st));
-      HPTRY(sync(c.get()));
-    }
-    const int nh = c->n_hub;
-    for (int i = 0; i < c->n_kpts; ++i) {
-      const double2 *F = h_phi.data() + (size_t)i * c->phi_stride;
-      double2 *T = h_T.data() + (size_t)i * c->t_stride;
-      double *dg = h_diag.data() + (size_t)i * c->ld;
-      const int npw = KP[i]->npw;
+    // block of the stacked table, as one expansion on the matrix cores per entry with the
+    // coefficients Cf[spin][5 s + m][r] (r = row in the 10 n_hub block); the Jacobi
+    // diagonal below then gains sum_a lam_a |chi_a(G)|^2 through the row scales +-1
+    const int nh = c->n_hub, nr10 = 10 * nh, nm = 5 * nh;
+    std::vector<double2> cf((size_t)c->nspin * nm * nr10, make_double2(0.0, 0.0));
+    for (int sp = 0; sp < c->nspin; ++sp)
       for (int sidx = 0; sidx < nh; ++sidx) {
-        const int blk = spin_of[i] * nh + sidx;
+        const int blk = sp * nh + sidx;
         for (int a = 0; a < 5; ++a) {
           const double lam = hub_lam[5 * blk + a];
           const double sc = std::sqrt(std::fabs(lam));
-          double2 *row = T + (size_t)(c->n_kb + (lam < 0.0 ? 5 * nh : 0) + 5 * sidx + a) * c->ld;
-          for (int p = 0; p < npw; ++p) {
-            std::complex<double> z = 0.0;
-            for (int m = 0; m < 5; ++m) {
-              const double2 f = F[(size_t)(5 * sidx + m) * c->ld + p];
-              z += hub_vec[25 * blk + m * 5 + a] * std::complex<double>(f.x, f.y);
-            }
-            row[p] = make_double2(sc * z.real(), sc * z.imag());
-            dg[p] += lam * std::norm(z);
+          const int r = (lam < 0.0 ? nm : 0) + 5 * sidx + a;
+          for (int m = 0; m < 5; ++m) {
+            const std::complex<double> z = sc * hub_vec[25 * blk + m * 5 + a];
+            cf[((size_t)sp * nm + 5 * sidx + m) * nr10 + r] = make_double2(z.real(), z.imag());
           }
         }
       }
-    }
-    HPCHK(hipMemcpyAsync(c->d_T, h_T.data(), sizeof(double2) * h_T.size(), hipMemcpyHostToDevice, st));
-    HPCHK(hipMemcpyAsync(c->d_diag, h_diag.data(), sizeof(double) * h_diag.size(), hipMemcpyHostToDevice, st));
-    HPTRY(sync(c.get()));
+    double2 *d_cf = nullptr;
+    HPTRY(dalloc(&d_cf, cf.size()));
+    hipError_t e = hipMemcpyAsync(d_cf, cf.data(), sizeof(double2) * cf.size(), hipMemcpyHostToDevice, st);
+    for (int i = 0; i < c->n_kpts && e == hipSuccess; ++i)
+      e = launch_zexpand(c->d_kself + i, 0, 1, c->d_phi, c->phi_stride, 0, nm, d_cf + (size_t)spin_of[i] * nm * nr10,
+                         (long)nm * nr10, 1.0, c->d_T + (size_t)i * c->t_stride + (size_t)c->n_kb * c->ld, c->ld, nr10,
+                         c->d_npw, c->npw_max, nullptr, 1, st);
+    const hipError_t e2 = hipStreamSynchronize(st);
+    (void)hipFree(d_cf);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return fail(HP_ERR_HIP, "ground-state Hubbard rows: %s", hipGetErrorString(e));
   }
+  // Jacobi diagonal of every entry from the final stacked table and its row scales
+  HPCHK(launch_diag(c->d_kself, c->sk.ent, c->n_kpts, c->d_T, c->t_stride, c->n_proj, c->d_rowscale, c->d_kin, d_vmean,
+                    c->ld, c->d_diag, st));
 
   // A_k[m][v] = <phi_{m,k}|u_vk> for every entry (Eq. 13's ground-state factor)
   HPTRY(c->alloc(&c->d_A, (size_t)c->n_kpts * 5 * c->n_hub * nb));
@@ -2632,6 +2690,26 @@ extern "C" hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const do
   return nc == 0 ? HP_OK : HP_WARN_NOT_CONVERGED;
 }
 
+extern "C" hp_status hp_xc_kernel(int32_t nspin, int64_t n, const double *rho, double *fxc_out) {
+  if (!rho || !fxc_out) return fail(HP_ERR_ARG, "NULL argument");
+  if (nspin != 1 && nspin != 2) return fail(HP_ERR_ARG, "nspin must be 1 or 2");
+  if (n < 1) return fail(HP_ERR_ARG, "n must be >= 1");
+  const size_t nin = (size_t)nspin * n, nout = (size_t)(nspin == 2 ? 3 : 1) * n;
+  double *d_in = nullptr, *d_out = nullptr;
+  HPTRY(dalloc(&d_in, nin));
+  hp_status s = dalloc(&d_out, nout);
+  if (s == HP_OK) {
+    hipError_t e = hipMemcpy(d_in, rho, sizeof(double) * nin, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = nspin == 2 ? launch_fxc_spin(d_in, d_in + n, d_out, n, nullptr) : launch_fxc(d_in, d_out, n, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(fxc_out, d_out, sizeof(double) * nout, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) s = fail(HP_ERR_HIP, "hp_xc_kernel: %s", hipGetErrorString(e));
+  }
+  (void)hipFree(d_in);
+  if (d_out) (void)hipFree(d_out);
+  return s;
+}
+
 extern "C" hp_status hp_profile_start(hp_ctx *c) {
   if (!c) return fail(HP_ERR_ARG, "context is NULL");
   HPTRY(sync(c));
@@ -2740,7 +2818,7 @@ extern "C" hp_status hp_set_plane_variant(hp_ctx *c, int32_t prec, int32_t varia
   const int slot = prec == 32 ? 1 : 0;
   if (!plane_vloc_variant_ok(c->pl, prec == 32 ? (int)sizeof(float2) : (int)sizeof(double2), variant))
     return fail(HP_ERR_ARG, "plane variant %d is not available for this grid", variant);
-  const int nv = 4;
+  const int nv = kPlaneVariants;
   c->plane_var[slot] = variant;
   c->plane_nvar[slot] = nv;
   c->plane_tuned[slot] = true;

@@ -31,6 +31,7 @@ struct Plane {
   Axis ax;   // x = first grid index, length N1, stride N2
   Axis ay;   // y = second grid index, length N2, stride 1
   int n1, n2, n3;
+  int nxa_max;  // most active x columns (x holding sticks) of any entry
 };
 
 // Per k-entry geometry (device arrays, flat with offsets).
@@ -97,6 +98,10 @@ hipError_t launch_plane_vloc32(const Plane &pl, const Sticks &sk, const KPair *k
 // variant: 0 = one z plane per 256-thread workgroup, 1 = two planes per 256 threads,
 // 2 = two planes per 512 threads (even N3, two planes in LDS), 3 = one plane with the
 // twiddles read from global memory (less LDS per workgroup); 1-3 for some plane sizes.
+// FP32 only, compile-time plane sizes: 4, 5, 6 = register-resident lines (a thread holds a
+// whole y column, then a whole x row or half of it) with LDS only for the transposes, on
+// 128, 192 or 256 threads and as many z planes as fill them.
+constexpr int kPlaneVariants = 7;
 hipError_t launch_plane_vloc(const Plane &pl, const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems,
                              const double2 *Sin, double2 *Sout, int ns_pad, const double *vp, const int *active,
                              int variant, hipStream_t st);
@@ -217,6 +222,20 @@ hipError_t launch_zaxpy_list(long n, double2 *y, int nvec, const double2 *const 
                              hipStream_t st);
 hipError_t launch_zsub(long n, const double2 *a, const double2 *b, double2 *out, hipStream_t st);
 hipError_t launch_zscale_copy(long n, const double2 *a, double s, double2 *out, hipStream_t st);
+// Load time.  dst[r][p] = src[r][order[p]] (p < npw; 0 up to ld) for r < nrows: a row-major
+// [nrows][npw] table in the caller's plane-wave order to the internal stick order.
+hipError_t launch_gather_rows(const double2 *src, int npw, const int *order, int nrows, double2 *dst, int ld,
+                              hipStream_t st);
+// dst[r][order[p]] = src[r][p] (p < npw): rows of length ld in the stick order to rows of
+// length npw in the caller's order.
+hipError_t launch_scatter_rows(const double2 *src, int ld, int npw, const int *order, int nrows, double2 *dst,
+                               hipStream_t st);
+// Jacobi diagonal of every entry e: kin + vmean[spin] + sum_r scale[r] |T_e[r]|^2 (1 on padding).
+hipError_t launch_diag(const KPair *self, const EntryDev *ent, int n_entries, const double2 *T, long t_stride,
+                       int nrows, const double *scale, const double *kin, const double *vmean, int ld, double *diag,
+                       hipStream_t st);
+// out[2b], out[2b+1] = sum and count of non-finite values of x[b*n .. b*n+n) (fixed order).
+hipError_t launch_block_stats(const double *x, int nblocks, long n, double *out, hipStream_t st);
 // x[i] *= s[i / per] for i < n: rows of `per` complex values scaled by one real each
 // (the band occupations of right-hand-side rows, or the coefficients of a projection).
 hipError_t launch_scale_rows(long n, long per, const double *s, double2 *x, hipStream_t st);

@@ -57,7 +57,7 @@ class HpGroundState(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("cell", (C.c_double * 3) * 3), ("fft", C.c_int32 * 3),
                 ("v_loc", _dp), ("rho0", _dp), ("n_occ", C.c_int32), ("n_beta", C.c_int32), ("n_hub", C.c_int32),
                 ("d_kb", _dp), ("hub_tau", _dp), ("spin_factor", C.c_int32), ("n_mesh", C.c_int32),
-                ("n_kpts", C.c_int32), ("kpts", C.POINTER(HpKpoint)), ("xc", C.c_int32), ("reserved", C.c_int32),
+                ("n_kpts", C.c_int32), ("kpts", C.POINTER(HpKpoint)), ("xc", C.c_int32), ("inputs_on_device", C.c_int32),
                 ("stream", C.c_void_p), ("projectors", C.c_int32), ("n_atwfc", C.c_int32), ("hub_rows", _ip),
                 ("nspin", C.c_int32), ("hub_pot", _dp), ("degauss", C.c_double), ("efermi", C.c_double)]
 
@@ -99,6 +99,8 @@ _lib.hp_apply_h.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp]
 _lib.hp_apply_h.restype = C.c_int32
 _lib.hp_solve_first_order.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_int32, _dp, C.POINTER(HpScfParams), _dp]
 _lib.hp_solve_first_order.restype = C.c_int32
+_lib.hp_xc_kernel.argtypes = [C.c_int32, C.c_int64, _dp, _dp]
+_lib.hp_xc_kernel.restype = C.c_int32
 
 
 
@@ -126,7 +128,7 @@ _lib.hp_set_stick_variant.restype = C.c_int32
 EXPORTED = ["hp_ground_state_load", "hp_sternheimer_scf", "hp_response_matrix", "hp_hubbard_params",
             "hp_destroy", "hp_last_error", "hp_apply_h", "hp_solve_first_order", "hp_profile_start",
             "hp_profile_stop", "hp_tuning_report", "hp_set_gemm_shape", "hp_set_plane_variant",
-            "hp_neighbours", "hp_set_stick_variant", "hp_site_occupations"]
+            "hp_neighbours", "hp_set_stick_variant", "hp_site_occupations", "hp_xc_kernel"]
 
 
 def hp_last_error() -> str:
@@ -149,6 +151,20 @@ def _c128_as_f64(a) -> np.ndarray:
 
 def _ptr(a: np.ndarray, t=_dp):
     return a.ctypes.data_as(t)
+
+
+def _is_device(a) -> bool:
+    """A torch tensor in GPU memory (the bulk inputs of hp_ground_state_load may be)."""
+    return type(a).__module__.startswith("torch") and getattr(a, "is_cuda", False)
+
+
+def _dev_ptr(t, dtype_name: str, count: int):
+    """Device address of a contiguous torch tensor of `count` elements of torch.<dtype_name>."""
+    import torch
+    if t.dtype != getattr(torch, dtype_name) or not t.is_contiguous() or t.numel() != count:
+        raise ValueError(f"device array must be a contiguous {dtype_name} tensor of {count} elements, got "
+                         f"{t.dtype} {tuple(t.shape)}")
+    return C.cast(C.c_void_p(t.data_ptr()), _dp)
 
 
 @dataclass
@@ -211,37 +227,69 @@ def hp_ground_state_load(gs, stream: Optional[int] = None, atwfc: Optional[Seque
     (kpts: a spin-up then a spin-down block; vloc, rho0: (2, N1, N2, N3)).  With atwfc (one
     (n_atwfc, npw) complex array per k-entry: every atomic orbital) and hub_rows (the row of
     d orbital m of Hubbard site s at 5 s + m) the library builds ortho-atomic projectors and
-    the entries' phi are not read."""
+    the entries' phi are not read.
+
+    The bulk arrays (vloc, rho0 and every entry's u, beta, phi, atwfc) may all be torch
+    tensors in GPU memory (contiguous float64 / complex128): they are then passed as device
+    pointers (inputs_on_device = 1) and copied device to device on `stream` (torch's
+    current stream when None).  Mixing host and device bulk arrays is an error."""
     ortho = atwfc is not None
     if ortho and (hub_rows is None or len(atwfc) != len(gs.kpts)):
         raise ValueError("ortho-atomic projectors need one atwfc table per k-entry and hub_rows")
+    bulk = [gs.vloc, gs.rho0] + [a for e in gs.kpts for a in (e.u, e.beta)]
+    bulk += list(atwfc) if ortho else [e.phi for e in gs.kpts]
+    flags = {_is_device(a) for a in bulk}
+    if len(flags) != 1:
+        raise ValueError("the bulk arrays must be all host arrays or all GPU tensors")
+    on_dev = flags.pop()
+    if on_dev and stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+
+    def table(a, rows, npw, what):
+        """Pointer to a [>= rows][npw] complex table (host array or GPU tensor); the library
+        reads the first `rows` rows."""
+        if len(a.shape) != 2 or int(a.shape[1]) != npw or int(a.shape[0]) < rows:
+            raise ValueError(f"{what} has shape {tuple(a.shape)}, want ({rows}, {npw})")
+        if on_dev:
+            return a, _dev_ptr(a, "complex128", int(a.shape[0]) * npw)
+        h = _c128_as_f64(a)
+        return h, _ptr(h)
+
     keep = []
     kp = (HpKpoint * len(gs.kpts))()
     n_atwfc = 0
+    n_occ, n_beta, nh5 = int(gs.n_occ), int(np.asarray(gs.d_kb).shape[0]), 5 * int(gs.n_hub)
     for i, e in enumerate(gs.kpts):
         mil = np.ascontiguousarray(e.miller, dtype=np.int32)
+        npw = int(mil.shape[0])
         eps = _f64(e.eps)
-        u = _c128_as_f64(e.u)
-        beta = _c128_as_f64(e.beta)
-        phi = None if ortho else _c128_as_f64(e.phi)
-        at = None
+        u, up = table(e.u, n_occ, npw, f"kpts[{i}].u")
+        beta, bp = table(e.beta, n_beta, npw, f"kpts[{i}].beta")
+        phi, pp = (None, None) if ortho else table(e.phi, nh5, npw, f"kpts[{i}].phi")
+        at, ap = None, None
         if ortho:
-            a = np.asarray(atwfc[i])
-            if a.ndim != 2 or a.shape[1] != mil.shape[0] or (i and a.shape[0] != n_atwfc):
-                raise ValueError(f"atwfc[{i}] has shape {a.shape}, entry {i} has {mil.shape[0]} plane waves")
-            n_atwfc = a.shape[0]
-            at = _c128_as_f64(a)
+            a = atwfc[i]
+            n_a = int(a.shape[0])
+            if len(a.shape) != 2 or int(a.shape[1]) != npw or (i and n_a != n_atwfc):
+                raise ValueError(f"atwfc[{i}] has shape {tuple(a.shape)}, entry {i} has {npw} plane waves")
+            n_atwfc = n_a
+            at, ap = table(a, n_a, npw, f"atwfc[{i}]")
         keep += [mil, eps, u, beta, phi, at]
         kp[i] = HpKpoint(C.sizeof(HpKpoint), (C.c_double * 3)(*[float(x) for x in e.k_frac]), float(e.weight),
-                         int(mil.shape[0]), _ptr(mil, _ip), _ptr(eps), _ptr(u), _ptr(beta),
-                         _ptr(phi) if phi is not None else None, _ptr(at) if at is not None else None)
-    vloc = _f64(gs.vloc)
-    rho0 = _f64(gs.rho0)
+                         npw, _ptr(mil, _ip), _ptr(eps), up, bp, pp, ap)
     nspin = int(getattr(gs, "nspin", 1))
     nr = int(np.prod([int(x) for x in gs.fft])) * nspin
-    if vloc.size != nr or rho0.size != nr:
-        raise ValueError(f"v_loc/rho0 hold {vloc.size}/{rho0.size} values, {nspin} spin(s) of the grid "
-                         f"{tuple(gs.fft)} hold {nr}")
+    if on_dev:
+        vloc, rho0 = gs.vloc, gs.rho0
+        vloc_p, rho0_p = _dev_ptr(vloc, "float64", nr), _dev_ptr(rho0, "float64", nr)
+    else:
+        vloc = _f64(gs.vloc)
+        rho0 = _f64(gs.rho0)
+        if vloc.size != nr or rho0.size != nr:
+            raise ValueError(f"v_loc/rho0 hold {vloc.size}/{rho0.size} values, {nspin} spin(s) of the grid "
+                             f"{tuple(gs.fft)} hold {nr}")
+        vloc_p, rho0_p = _ptr(vloc), _ptr(rho0)
     dkb = _f64(gs.d_kb)
     htau = _f64(gs.hub_tau)
     hrows = np.ascontiguousarray(hub_rows, dtype=np.int32) if ortho else None
@@ -257,8 +305,8 @@ def hp_ground_state_load(gs, stream: Optional[int] = None, atwfc: Optional[Seque
     g.struct_size = C.sizeof(HpGroundState)
     g.cell = cell
     g.fft = (C.c_int32 * 3)(*[int(x) for x in gs.fft])
-    g.v_loc = _ptr(vloc)
-    g.rho0 = _ptr(rho0)
+    g.v_loc = vloc_p
+    g.rho0 = rho0_p
     g.n_occ = int(gs.n_occ)
     g.n_beta = int(dkb.shape[0])
     g.n_hub = int(gs.n_hub)
@@ -269,7 +317,7 @@ def hp_ground_state_load(gs, stream: Optional[int] = None, atwfc: Optional[Seque
     g.n_kpts = len(gs.kpts)
     g.kpts = kp
     g.xc = HP_XC_LDA_PZ81
-    g.reserved = 0
+    g.inputs_on_device = 1 if on_dev else 0
     g.stream = C.c_void_p(stream) if stream else None
     g.projectors = HP_PROJ_ORTHO_ATOMIC if ortho else HP_PROJ_ATOMIC
     g.n_atwfc = n_atwfc
@@ -361,6 +409,19 @@ def hp_solve_first_order(ctx: Context, pert_site: int, q_frac, mesh_k: int, dv: 
     s = _check(_lib.hp_solve_first_order(ctx.handle, int(pert_site), _ptr(q), int(mesh_k), dvp, C.byref(p),
                                          _ptr(out.view(np.float64))))
     return out, s
+
+
+def hp_xc_kernel(rho: np.ndarray) -> np.ndarray:
+    """The library's LDA kernel at the densities rho: shape (n,) -> (n,) unpolarized, or
+    (2, n) (up, down) -> (3, n) (f_uu, f_ud, f_dd)."""
+    r = _f64(rho)
+    nspin = 2 if r.ndim == 2 else 1
+    if r.ndim not in (1, 2) or (nspin == 2 and r.shape[0] != 2):
+        raise ValueError("rho must have the shape (n,) or (2, n)")
+    n = r.shape[-1]
+    out = np.zeros((3, n) if nspin == 2 else (n,))
+    _check(_lib.hp_xc_kernel(nspin, n, _ptr(r), _ptr(out)), allow_warn=False)
+    return out
 
 
 def hp_profile_start(ctx: Context) -> None:

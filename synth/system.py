@@ -80,6 +80,10 @@ class SystemSpec:
     # ones included); 0 = insulator with 2 n_occ electrons
     degauss: float = 0.0
     n_el: float = 0.0
+    # eigen-residual the iterative solver converges the occupied states to; the olivine-shaped
+    # cells use 1e-12 so that states built on different devices (or thread counts) agree to
+    # far below the 1e-10 parity bar (their difference is ~ residual / gap)
+    gs_tol: float = 1e-10
 
 
 SPECS = {}
@@ -110,13 +114,21 @@ DUO = _reg(SystemSpec(name="duo_k221", cfg_id=7, cell=(10.0, 7.5, 7.0), n_atoms=
                       fft=(30, 24, 24), ecut=10.0, n_occ=12, kmesh=(2, 3, 1), qmesh=(1, 2, 1),
                       min_sep=2.5, depth=(5.5, 6.5), width=(0.55, 0.65), center_jitter=0.15,
                       kb_d=(0.2, 0.6)))
+# The two-site cell on a grid with odd edges (25 = 5 x 5 along y, 27 = 9 x 3 along z) and no
+# compile-time plane or stick transform: the runtime-size kernels with odd radix chains.
+DUO_ODD = _reg(replace(DUO, name="duo_odd", fft=(30, 25, 27)))
 # Olivine-shaped cell: 19.6 x 11.3 x 8.9 bohr, 28 atoms, 4 d sites, ~10^4 PWs,
 # FFT 72x45x40, 112 bands, k 2x3x4, q 1x2x2.
 # Each atom's well (three narrow Gaussians, 5.5-6.5 Ha deep) binds one s and three p
 # states well below its other levels, so 28 atoms fill 112 bands below a gap.
 OLIVINE = _reg(SystemSpec(name="olivine28", cfg_id=1, cell=(19.6, 11.3, 8.9), n_atoms=28, n_hub=4,
                           fft=(72, 45, 40), ecut=22.45, n_occ=112, kmesh=(2, 3, 4), qmesh=(1, 2, 2),
-                          depth=(5.5, 6.5), width=(0.55, 0.65), center_jitter=0.15, kb_d=(0.2, 0.6)))
+                          depth=(5.5, 6.5), width=(0.55, 0.65), center_jitter=0.15, kb_d=(0.2, 0.6),
+                          gs_tol=1e-12))
+# The same cell (same seed: atoms, wells, noise, projectors) sampled at Gamma only with a
+# 1x2x1 q mesh (entries Gamma and (0, 1/2, 0)): the full-size grid, sphere and band count at
+# a cost the oracle affords for a stored full-size reference.
+OLIVINE_G = _reg(replace(OLIVINE, name="olivine28_gamma", kmesh=(1, 1, 1), qmesh=(1, 2, 1)))
 # The same system (same seed: atoms, wells, noise, projectors) with a 4x4x2 k-mesh
 # (k+q stays on the mesh) and a cutoff jittered per {k,-k} pair so that PW counts spread
 # over ~9,600-10,400.
@@ -128,6 +140,10 @@ OLIVINE_K442 = _reg(replace(OLIVINE, name="olivine28_k442", cfg_id=1, kmesh=(4, 
 OLIVINE_SC = _reg(replace(OLIVINE, name="olivine56_sc211", cfg_id=4, cell=(39.2, 11.3, 8.9),
                           n_atoms=56, n_hub=8, fft=(144, 45, 40), ecut=22.45, n_occ=224,
                           base="olivine28", rep=(2, 1, 1)))
+# Its Gamma-only form (q mesh 1x2x1): the 144x45x40 grid, ~2x10^4 plane waves and 224 bands
+# for a stored full-size reference, folded from the Gamma-only primitive cell.
+OLIVINE_SC_G = _reg(replace(OLIVINE_SC, name="olivine56_gamma", kmesh=(1, 1, 1), qmesh=(1, 2, 1),
+                            base="olivine28_gamma"))
 # Collinear spin-polarized variants (the same atoms and wells; an exchange field of
 # 0.15 Ha on the d sites): one site (polarized), two sites and the olivine-shaped cell
 # with antiferromagnetic order (+, -, +, - over the d sites; equal electron counts per
@@ -736,13 +752,16 @@ def _pair_key(k):
 
 
 def build_ground_state(spec: SystemSpec | str, *, backend: str = "auto", device: str = "cpu",
-                       tol: float = 1e-10, verbose: bool = False) -> GroundState:
+                       tol: Optional[float] = None, verbose: bool = False) -> GroundState:
     """Build the seeded synthetic system and its occupied eigenpairs at every k-entry.
 
     backend: 'dense' (numpy eigh; small spheres), 'lobpcg' (block iterative solver on
-    torch, CPU or GPU device), or 'auto' (dense below 3000 plane waves)."""
+    torch, CPU or GPU device), or 'auto' (dense below 3000 plane waves).  tol: eigen-residual
+    of the iterative solver (default: the spec's gs_tol)."""
     if isinstance(spec, str):
         spec = SPECS[spec]
+    if tol is None:
+        tol = spec.gs_tol
     if spec.base is not None:
         return _build_replicated(spec, backend=backend, device=device, tol=tol, verbose=verbose)
     last_err = None

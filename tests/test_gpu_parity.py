@@ -4,7 +4,8 @@ Small systems the oracle finishes in seconds, chosen to span several GEMM and
 FFT tiles with ragged tails: sc1_gamma (515 plane waves, 8 bands, 24^3 grid),
 duo_k221 (two Hubbard sites, 6 mesh k + 6 extra k+q entries with 777-796
 plane waves, 12 bands, 30x24x24 grid, q-mesh 1x2x1 whose k+q leave the k
-mesh), sc1_k211 / sc1_k311 (q at the zone boundary and at 1/3).
+mesh), duo_odd (the same cell on a 30x25x27 grid: odd y and z edges through the
+runtime-size transforms), sc1_k211 / sc1_k311 (q at the zone boundary and at 1/3).
 Tolerance for FP64: 1e-10 relative on chi (the stated bar), tighter where the
 step is a plain product.
 """
@@ -45,7 +46,7 @@ def rel(a, b):
     return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
 
 
-@pytest.mark.parametrize("name", ["sc1_gamma", "duo_k221"])
+@pytest.mark.parametrize("name", ["sc1_gamma", "duo_k221", "duo_odd"])
 def test_apply_h_matches_oracle(name):
     hp = _hp()
     o = orc(name)
@@ -56,7 +57,8 @@ def test_apply_h_matches_oracle(name):
         assert rel(Y, o.h_apply(ie, X)) < 1e-13, f"entry {ie}"
 
 
-@pytest.mark.parametrize("name,q", [("sc1_gamma", (0, 0, 0)), ("duo_k221", (0, 0.5, 0)), ("sc1_k311", (1 / 3, 0, 0))])
+@pytest.mark.parametrize("name,q", [("sc1_gamma", (0, 0, 0)), ("duo_k221", (0, 0.5, 0)), ("sc1_k311", (1 / 3, 0, 0)),
+                                    ("duo_odd", (0, 0.5, 0))])
 @pytest.mark.parametrize("with_dv", [False, True])
 def test_first_order_solve_matches_oracle(name, q, with_dv):
     hp = _hp()
@@ -78,7 +80,7 @@ def oracle_scf(name, site, q):
 
 
 @pytest.mark.parametrize("name,site,q", [("sc1_gamma", 0, (0, 0, 0)), ("sc1_k211", 0, (0.5, 0, 0)),
-                                         ("duo_k221", 1, (0, 0.5, 0))])
+                                         ("duo_k221", 1, (0, 0.5, 0)), ("duo_odd", 0, (0, 0.5, 0))])
 def test_scf_response_occupations_match_oracle(name, site, q):
     hp = _hp()
     dn0, dn, st, status = hp.hp_sternheimer_scf(ctx(name), site, q, tight_gpu())

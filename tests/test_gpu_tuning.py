@@ -113,3 +113,35 @@ def test_pinning_rejects_bad_shapes():
         hp.hp_set_plane_variant(ctx, 64, 1)   # 24x24 planes: only variant 0
     with pytest.raises(hp.HpError):
         hp.hp_set_stick_variant(ctx, 64, 2, 0)
+
+
+@pytest.mark.parametrize("name", ["sc1_gamma", "duo_k221", "olivine28_gamma", "olivine56_gamma"])
+def test_register_plane_variants_bitwise(name):
+    """The FP32 register-resident plane round trips (variants 4-6: a y column, then an x row
+    or half of one, in a thread's registers; 144-point rows split over two lanes with a DPP
+    exchange in the last radix-2 stage) run the butterflies of the LDS variants in the same
+    order: mixed-precision solves pinned to each give bit-identical results, on the 24x24,
+    30x24, 72x45 and 144x45 planes."""
+    from paper_2203_15684_amd import hp
+    if name.startswith("olivine"):
+        from synth import cache
+        gs = cache.get(name)
+    else:
+        gs = ground_state(name)
+    ctx = hp.hp_ground_state_load(gs)
+    o_q = (0.0, 0.5, 0.0) if name != "sc1_gamma" else (0.0, 0.0, 0.0)
+    ik = 0
+    k = gs.kpts[ik].k_frac + np.asarray(o_q)
+    npw = next(e.npw for e in gs.kpts if np.allclose(k - e.k_frac, np.round(k - e.k_frac)))
+    ref = None
+    for pv in (0, 4, 5, 6):
+        _pin(ctx, gs, [64, 32], 1, 0, 2, 32, 0)
+        hp.hp_set_plane_variant(ctx, 32, pv)
+        p = hp.ScfParams(cg_tol=1e-11, max_cg_iter=2000, precision=hp.HP_MIXED)
+        du, st = hp.hp_solve_first_order(ctx, 0, o_q, ik, None, p, npw)
+        assert st == 0
+        if ref is None:
+            ref = du
+        else:
+            assert np.array_equal(du, ref), pv
+    ctx.close()

@@ -276,3 +276,48 @@ def test_pz81_fit_is_continuous_at_rs_one_and_exchange_closed_form():
     assert abs(ex + 0.75 * (9 / (4 * math.pi ** 2)) ** (1 / 3)) < 1e-15
     assert abs(ex + 0.458165) < 1e-6
     assert pz81.f_xc(np.array([1e-12]))[0] == 0.0
+
+
+# High-density limit of the correlation energy of the uniform electron gas: the
+# random-phase (Gell-Mann--Brueckner) result eps_c -> A ln r_s + ... with
+# A = (1 - ln 2) / pi^2 Ha for the unpolarized gas and half of it for the fully
+# polarized one.  Perdew and Zunger impose this limit on their r_s < 1 fit and print A to
+# three significant figures, so the fit's slope in ln r_s must equal the exact value to
+# half a unit in that last digit.  This pins A by itself (a swap of A and C, or a sign,
+# fails), in the energy and in the kernel f_xc the response uses.
+A_EXACT = (1.0 - math.log(2.0)) / math.pi ** 2   # 0.0310907 Ha
+A_TOL = 5e-5
+
+
+def _rho_of_rs(r):
+    return 3.0 / (4.0 * math.pi * r ** 3)
+
+
+def test_pz81_high_density_limit_unpolarized_energy():
+    r1, r2 = 1e-7, 1e-6
+    ex = lambda rho: -0.75 * (3.0 * rho / math.pi) ** (1.0 / 3.0)
+    ec = [float(pz81.eps_xc(np.array([_rho_of_rs(r)]))[0] - ex(_rho_of_rs(r))) for r in (r1, r2)]
+    slope = (ec[1] - ec[0]) / math.log(r2 / r1)
+    assert abs(slope - A_EXACT) < A_TOL, slope
+
+
+def test_pz81_high_density_limit_unpolarized_kernel():
+    # f_c = (d v_c / d r_s)(-r_s / (3 rho)) -> -A / (3 rho) as r_s -> 0
+    rs = np.array([1e-8, 1e-7])
+    rho = _rho_of_rs(rs)
+    fx = -(1.0 / 3.0) * (3.0 / math.pi) ** (1.0 / 3.0) * rho ** (-2.0 / 3.0)
+    a_of = -3.0 * rho * (pz81.f_xc(rho) - fx)
+    assert np.all(np.abs(a_of - A_EXACT) < A_TOL), a_of
+
+
+def test_pz81_high_density_limit_polarized():
+    # fully polarized gas (rho_dn = 0): eps_c -> (A / 2) ln r_s; exchange of the polarized gas
+    # -(3/4)(6/pi)^(1/3) rho^(1/3)
+    r1, r2 = 1e-7, 1e-6
+    ec = []
+    for r in (r1, r2):
+        rho = _rho_of_rs(r)
+        ex = -0.75 * (6.0 / math.pi) ** (1.0 / 3.0) * rho ** (1.0 / 3.0)
+        ec.append(float(pz81.eps_xc_spin(np.array([rho]), np.array([0.0]))[0]) - ex)
+    slope = (ec[1] - ec[0]) / math.log(r2 / r1)
+    assert abs(slope - A_EXACT / 2.0) < A_TOL, slope

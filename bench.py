@@ -24,7 +24,7 @@ Forms, all on the same resident inputs and the same pairs:
   mixed_relaxed  the mixed form at the same relaxed tolerances;
   mixed_bf16, mixed_bf16_pv32, mixed_graphs  (optional) BF16 projections, BF16 KB with
                  FP32 P_v, and CG iterations replayed from captured hipGraphs;
-  any form as "<form>@cg_tol,conv_thr_chi,conv_thr_v" for tolerance sweeps.
+  any form as "<form>@cg_tol:conv_thr_chi:conv_thr_v[:inner_tol]" for tolerance sweeps.
 The mixed form is timed over --steps pairs after --warmup pairs; every other form over
 the first --ref-steps of those pairs.  Prints one JSON line.
 """
@@ -69,6 +69,9 @@ def parse():
                     help="CG iterations per captured hipGraph launch in the main forms (0: launch kernels one by "
                          "one, timed with HIP events)")
     ap.add_argument("--verbosity", type=int, default=0, help="1: one line per SCF iteration on stderr")
+    ap.add_argument("--full-response", action="store_true",
+                    help="also run the whole response (hp_response_matrix over every pair, then U/V) once per form "
+                         "and report its wall time, status and the chi and U/V differences from the FP64 form")
     return ap.parse_args()
 
 
@@ -168,7 +171,7 @@ def cpu_baseline(gs, seconds, q, applies_per_pair_fp64, n_pairs):
     o = oracle.Oracle(gs, cache_limit_bytes=0)
     ik = 0
     X = gs.kpts[ik].u
-    o.sternheimer_op(ik, q, X[:2])  # plan caches
+    o.sternheimer_op(ik, q, X)  # plan caches
     t0 = time.perf_counter()
     reps = 0
     while True:
@@ -235,9 +238,9 @@ def main():
             b, tl = f.split("@")
             if b not in named:
                 raise SystemExit(f"unknown form {b}")
-            t = tuple(float(x) for x in tl.split(","))
-            if len(t) != 3:
-                raise SystemExit(f"{f}: want <form>@cg_tol,conv_thr_chi,conv_thr_v")
+            t = tuple(float(x) for x in tl.split(":"))
+            if len(t) not in (3, 4):
+                raise SystemExit(f"{f}: want <form>@cg_tol:conv_thr_chi:conv_thr_v[:inner_tol]")
             form_def[f] = (named[b][0], t, named[b][2], named[b][3])
         elif f in named:
             form_def[f] = named[f]
@@ -247,9 +250,11 @@ def main():
         raise SystemExit("--forms must include fp64 and the --precision form")
 
     def params(form):
-        prec, (tol, thr_chi, thr_v), lowp, chunk = form_def[form]
+        prec, tols, lowp, chunk = form_def[form]
+        tol, thr_chi, thr_v = tols[:3]
+        inner = tols[3] if len(tols) > 3 else args.inner_tol
         return hp.ScfParams(conv_thr_chi=thr_chi, conv_thr_v=thr_v, cg_tol=tol, niter_max=100, max_cg_iter=2000,
-                            inner_tol=args.inner_tol, graph_chunk=chunk,
+                            inner_tol=inner, graph_chunk=chunk,
                             precision=hp.HP_FP64 if prec == "fp64" else hp.HP_MIXED, lowp_gemm=lowp,
                             verbosity=args.verbosity)
 
@@ -286,6 +291,19 @@ def main():
         n = args.steps if f == args.precision else min(args.ref_steps, args.steps)
         runs[f] = timed(f, first, n)
         print(f"[bench] form {f}: {runs[f][0]:.2f} s over {n} pairs", file=sys.stderr, flush=True)
+    full = {}
+    if args.full_response:
+        for f in forms:
+            p = params(f)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            chi0, chi, mim, st, status = hp.hp_response_matrix(ctx, gs.qmesh, p)
+            uv = hp.hp_hubbard_params(chi0, chi)
+            full[f] = {"wall_s": time.perf_counter() - t1, "status": status, "scf_iters": st["scf_iters"],
+                       "h_applies_fp64": st["h_applies_fp64"], "h_applies_lowp": st["h_applies_lowp"],
+                       "chi0": chi0, "chi": chi, "uv": uv}
+            print(f"[bench] full response {f}: {full[f]['wall_s']:.2f} s, status {status}", file=sys.stderr,
+                  flush=True)
     hbm_used = free_before_load - torch.cuda.mem_get_info()[0]
 
     def column(r, key):
@@ -310,6 +328,7 @@ def main():
         t_same = sum(r["wall"] for r in same)
         t_ref_same = sum(ref[r["pair"]]["wall"] for r in same)
         summary[f] = {"precision": prec, "cg_tol": tols[0], "conv_thr_chi": tols[1], "conv_thr_v": tols[2],
+                      "inner_tol": (tols[3] if len(tols) > 3 else args.inner_tol) if prec == "mixed" else None,
                       "graph_chunk": chunk,
                       "kernel_timing": "device-clock stamps in graphs" if chunk else "hip events",
                       "projection_gemms": {0: "fp32", 1: "bf16", 2: "bf16 (KB), fp32 (P_v)"}[lowp]
@@ -366,6 +385,17 @@ def main():
         "hbm_footprint_gb": {"context_after_all_forms": round(hbm_used / 1e9, 2),
                              "loaded_ground_state": round((free_before_load - free_loaded) / 1e9, 2)},
     }
+    if full:
+        r64 = full["fp64"]
+        out["full_response"] = {
+            f: {"wall_s": v["wall_s"], "status": v["status"], "scf_iters": v["scf_iters"],
+                "h_applies_fp64": v["h_applies_fp64"], "h_applies_lowp": v["h_applies_lowp"],
+                "speedup_vs_fp64": r64["wall_s"] / v["wall_s"],
+                "chi_rel_err_vs_fp64": max(float(np.abs(v["chi0"] - r64["chi0"]).max() / np.abs(r64["chi0"]).max()),
+                                           float(np.abs(v["chi"] - r64["chi"]).max() / np.abs(r64["chi"]).max())),
+                "uv_err_meV_vs_fp64": float(np.abs(v["uv"] - r64["uv"]).max() * HA_EV * 1e3),
+                "U_eV": [float(x) * HA_EV for x in np.diag(v["uv"])[:gs.n_hub]]}
+            for f, v in full.items()}
     if not args.no_cpu_baseline:
         s0, q0 = pair(first)
         out["cpu_baseline"] = cpu_baseline(gs, args.cpu_baseline_seconds, np.array(q0),

@@ -306,6 +306,14 @@ const char *hp_last_error(void);
  * x, y: [n][npw] complex host arrays in the caller's plane-wave order. */
 hp_status hp_apply_h(hp_ctx *c, int32_t entry, int32_t n, const double *x, double *y);
 
+/* y = H_k x as hp_apply_h, with the reduced-precision operator the mixed form's inner
+ * solves use: x rounded to FP32, FP32 z-stick and plane transforms and V_loc psi (the
+ * plane variant chosen for FP32), projections per lowp_gemm (HP_GEMM_FP32, HP_GEMM_BF16 or
+ * HP_GEMM_BF16_PV32) with FP32 accumulation; y returned widened to FP64.  For parity checks
+ * of those kernels (the mixed form's answers are FP64-refined, so they do not show the
+ * operator's own accuracy). */
+hp_status hp_apply_h_lowp(hp_ctx *c, int32_t entry, int32_t n, int32_t lowp_gemm, const double *x, double *y);
+
 /* One linear solve of Eq. 15 at mesh point mesh_k for every occupied band,
  * with a given response potential dv ([nspin][N1][N2][N3] complex host array, or
  * NULL for dV_Hxc = 0): du_out [n_occ][npw(k+q)] complex, in the plane-wave order
@@ -343,8 +351,7 @@ hp_status hp_profile_stop(hp_ctx *c, hp_kernel_time *out, int32_t max, int32_t *
  * projection tile, K split and expansion band tile with the measured and the
  * default times (ms), per precision the chosen plane variant of the local-potential
  * FFT with every variant's time (-1: not available for the grid), and per precision the chosen
- * z-transform variants (a workgroup per 32 sticks, or a thread per stick) with
- * their times.  HP_ERR_ARG if buf is too small. */
+ * z-transform variants (see hp_set_stick_variant) with their times (-1: not available).  HP_ERR_ARG if buf is too small. */
 hp_status hp_tuning_report(hp_ctx *c, char *buf, int32_t len);
 
 /* Pin launch shapes instead of timing them (used when hp_scf_params.autotune = 1;
@@ -363,7 +370,9 @@ hp_status hp_set_gemm_shape(hp_ctx *c, int32_t prec, int32_t rows, int32_t batch
                             int32_t expand_bands);
 hp_status hp_set_plane_variant(hp_ctx *c, int32_t prec, int32_t variant);
 /* z-transform variants (inverse: sphere -> sticks, forward: sticks -> sphere):
- * 0 = a workgroup per 32 sticks, 1 = a thread per stick (N3 = 24 or 40 only). */
+ * 0 = a workgroup per 32 sticks, 1 = a thread per stick (N3 = 24 or 40 only), 2 = a thread
+ * per stick with the workgroup's plane waves staged through LDS (N3 = 24 or 40, when the
+ * plane waves of 256 sticks fit in 64 KB).  The three give identical results. */
 hp_status hp_set_stick_variant(hp_ctx *c, int32_t prec, int32_t inverse_variant, int32_t forward_variant);
 
 #ifdef __cplusplus

@@ -741,6 +741,126 @@ __global__ void __launch_bounds__(kThreads) k_stick_fwd_s(Sticks sk, const KPair
   }
 }
 
+// The thread-per-stick transforms with the plane waves of the workgroup's sticks (a
+// contiguous range) staged through LDS, so that global memory is read (inverse) or written
+// (forward) in coalesced rows instead of one stick per lane; the sums are those of
+// k_stick_inv_s / k_stick_fwd_s, term by term.
+template <int N3, class C>
+__global__ void __launch_bounds__(kThreads) k_stick_inv_sl(Sticks sk, const KPair *kp, int use_kq, int nb,
+                                                           const C *__restrict__ X, int ld, C *__restrict__ S,
+                                                           int ns_pad, const C *__restrict__ tw3, const int *active) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);  // [N3]
+  C *cv = tw + N3;                          // [p1 - p0] coefficients
+  const int item = blockIdx.y;
+  if (active && !active[item]) return;
+  const int k = item / nb;
+  int e, g0x, g0y, g0z;
+  basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
+  const EntryDev E = sk.ent[e];
+  const int s0 = blockIdx.x * kThreads;
+  if (s0 >= E.ns) return;
+  const int s1 = min(s0 + kThreads, E.ns);
+  const int *sstart = sk.sstart + E.st_off, *slen = sk.slen + E.st_off;
+  const int p0 = sstart[s0], p1 = sstart[s1 - 1] + slen[s1 - 1];
+  int *zi = reinterpret_cast<int *>(cv + (p1 - p0));  // [p1 - p0] z index (shifted, wrapped)
+  for (int i = threadIdx.x; i < N3; i += kThreads) tw[i] = tw3[i];
+  const C *x = X + (size_t)item * ld;
+  for (int p = p0 + threadIdx.x; p < p1; p += kThreads) {
+    cv[p - p0] = x[p];
+    zi[p - p0] = wrap(sk.iz[E.pw_off + p] - g0z, N3);
+  }
+  __syncthreads();
+  const int s = s0 + threadIdx.x;
+  if (s >= s1) return;
+  const int a = sstart[s] - p0, len = slen[s];
+  C acc[N3];
+#pragma unroll
+  for (int z = 0; z < N3; ++z) acc[z] = czero<C>();
+  for (int t = 0; t < len; ++t) {
+    const C c = cv[a + t];
+    const int zz = zi[a + t];
+    int ix = 0;
+#pragma unroll
+    for (int z = 0; z < N3; ++z) {
+      acc[z] = cadd(acc[z], cmul(c, tw[ix]));
+      ix += zz;
+      if (ix >= N3) ix -= N3;
+    }
+  }
+  C *out = S + (size_t)item * N3 * ns_pad + s;
+#pragma unroll
+  for (int z = 0; z < N3; ++z) out[(size_t)z * ns_pad] = acc[z];
+}
+
+template <int N3, class C>
+__global__ void __launch_bounds__(kThreads) k_stick_fwd_sl(Sticks sk, const KPair *kp, int use_kq, int nb,
+                                                           const C *__restrict__ S, int ns_pad,
+                                                           const C *__restrict__ tw3, double scale,
+                                                           C *__restrict__ Y, int ld, int mode,
+                                                           const double *__restrict__ kin,
+                                                           const double *__restrict__ eps,
+                                                           const C *__restrict__ X, int eps_stride,
+                                                           const int *active) {
+  using R = RealOf<C>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);  // [N3]
+  C *yb = tw + N3;                          // [p1 - p0] stick sums of this workgroup's plane waves
+  const int item = blockIdx.y;
+  if (active && !active[item]) return;
+  const int k = item / nb;
+  const int v = item - k * nb;
+  int e, g0x, g0y, g0z;
+  basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
+  const EntryDev E = sk.ent[e];
+  const int s0 = blockIdx.x * kThreads;
+  if (s0 >= E.ns) return;
+  const int s1 = min(s0 + kThreads, E.ns);
+  const int *sstart = sk.sstart + E.st_off, *slen = sk.slen + E.st_off;
+  const int p0 = sstart[s0], p1 = sstart[s1 - 1] + slen[s1 - 1];
+  for (int i = threadIdx.x; i < N3; i += kThreads) tw[i] = tw3[i];
+  __syncthreads();
+  const int s = s0 + threadIdx.x;
+  if (s < s1) {
+    const int a = sstart[s], len = slen[s];
+    if (S) {
+      C sv[N3];
+      const C *in = S + (size_t)item * N3 * ns_pad + s;
+#pragma unroll
+      for (int z = 0; z < N3; ++z) sv[z] = in[(size_t)z * ns_pad];
+      for (int t = 0; t < len; ++t) {
+        const int p = a + t;
+        const int zz = wrap(sk.iz[E.pw_off + p] - g0z, N3);
+        C acc = czero<C>();
+        int ix = 0;
+#pragma unroll
+        for (int z = 0; z < N3; ++z) {
+          acc = cadd(acc, cmulc(sv[z], tw[ix]));
+          ix += zz;
+          if (ix >= N3) ix -= N3;
+        }
+        yb[p - p0] = cscale(acc, scale);
+      }
+    } else {
+      for (int t = 0; t < len; ++t) yb[a + t - p0] = czero<C>();
+    }
+  }
+  __syncthreads();
+  C *y = Y + (size_t)item * ld;
+  const C *x = X ? X + (size_t)item * ld : nullptr;
+  const double ev = eps ? eps[(size_t)k * eps_stride + v] : 0.0;
+  for (int p = p0 + threadIdx.x; p < p1; p += kThreads) {
+    C acc = yb[p - p0];
+    if (mode == 0) {
+      const C xv = x[p];
+      const R d = (R)(kin[E.pw_off + p] - ev);
+      acc.x += d * xv.x;
+      acc.y += d * xv.y;
+    }
+    y[p] = acc;
+  }
+}
+
 template <int N1, int N2, class C>
 __global__ void __launch_bounds__(kThreads) k_plane_vloc(Plane pl, Sticks sk, const KPair *kp, int use_kq, int nb,
                                                          const C *__restrict__ Sin, C *__restrict__ Sout,
@@ -1467,6 +1587,17 @@ template <class C>
 hipError_t stick_inv_t(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const C *X, int ld, C *S,
                        int ns_pad, int n3, const C *tw3, int max_chunk_pw, int ns_max, const int *active, int variant,
                        hipStream_t st) {
+  if (variant == 2 && (n3 == 24 || n3 == 40)) {
+    dim3 g((ns_max + kThreads - 1) / kThreads, nitems);
+    const size_t lds = (size_t)n3 * sizeof(C) + (size_t)sk.max_pw256 * (sizeof(C) + sizeof(int));
+    if (n3 == 24)
+      hipLaunchKernelGGL((k_stick_inv_sl<24, C>), g, dim3(kThreads), lds, st, sk, kp, use_kq, nb, X, ld, S, ns_pad,
+                         tw3, active);
+    else
+      hipLaunchKernelGGL((k_stick_inv_sl<40, C>), g, dim3(kThreads), lds, st, sk, kp, use_kq, nb, X, ld, S, ns_pad,
+                         tw3, active);
+    return hipGetLastError();
+  }
   if (variant == 1 && (n3 == 24 || n3 == 40)) {
     dim3 g((ns_max + kThreads - 1) / kThreads, nitems);
     if (n3 == 24)
@@ -1488,6 +1619,17 @@ hipError_t stick_fwd_t(const Sticks &sk, const KPair *kp, int use_kq, int nb, in
                        int n3, const C *tw3, double scale, C *Y, int ld, int mode, const double *kin,
                        const double *eps, const C *X, int eps_stride, int max_chunk_pw, int ns_max,
                        const int *active, int variant, hipStream_t st) {
+  if (variant == 2 && (n3 == 24 || n3 == 40)) {
+    dim3 g((ns_max + kThreads - 1) / kThreads, nitems);
+    const size_t lds = (size_t)n3 * sizeof(C) + (size_t)sk.max_pw256 * sizeof(C);
+    if (n3 == 24)
+      hipLaunchKernelGGL((k_stick_fwd_sl<24, C>), g, dim3(kThreads), lds, st, sk, kp, use_kq, nb, S, ns_pad, tw3,
+                         scale, Y, ld, mode, kin, eps, X, eps_stride, active);
+    else
+      hipLaunchKernelGGL((k_stick_fwd_sl<40, C>), g, dim3(kThreads), lds, st, sk, kp, use_kq, nb, S, ns_pad, tw3,
+                         scale, Y, ld, mode, kin, eps, X, eps_stride, active);
+    return hipGetLastError();
+  }
   if (variant == 1 && (n3 == 24 || n3 == 40)) {
     dim3 g((ns_max + kThreads - 1) / kThreads, nitems);
     if (n3 == 24)

@@ -101,6 +101,7 @@ struct HostEntry {
   int npw;
   int spin = 0;
   std::vector<int> order;  // internal position -> caller index
+  int pw_off = 0;          // offset of this entry in the per-plane-wave device arrays
 };
 
 }  // namespace
@@ -145,6 +146,7 @@ struct hp_ctx {
   int *d_px = nullptr, *d_py = nullptr;
   double *d_vp = nullptr, *d_fxc = nullptr, *d_bvec = nullptr, *d_q = nullptr;
   int *d_npw = nullptr;
+  int *d_order = nullptr;  // [pw] internal position -> caller index, per entry at pw_off
   double *d_kin = nullptr, *d_diag = nullptr, *d_rowscale = nullptr, *d_eps = nullptr;
   double2 *d_T = nullptr, *d_phi = nullptr, *d_A = nullptr, *d_psi = nullptr;
   KPair *d_kp = nullptr, *d_kself = nullptr;
@@ -153,6 +155,7 @@ struct hp_ctx {
   double2 *S1 = nullptr, *S2 = nullptr, *Cpart = nullptr, *C = nullptr, *Cphi = nullptr;
   double *rz = nullptr, *bn = nullptr, *rn = nullptr;
   int *active = nullptr, *count = nullptr;
+  int *bmap = nullptr;  // [n_mesh][n_occ + 1] active bands of each pair, packed (GEMM tiles)
   double2 *part = nullptr, *drho = nullptr, *dvin = nullptr, *dvout = nullptr, *f = nullptr, *tmp = nullptr;
   double2 *fprev = nullptr, *dvprev = nullptr, *hdf = nullptr, *hdv = nullptr;
   double2 *dots_part = nullptr, *dots = nullptr, *dn = nullptr, *coef = nullptr;
@@ -215,7 +218,7 @@ struct hp_ctx {
   std::vector<GemmChoice> gemm_tuned;
   int plane_var[2] = {0, 0};  // [0] FP64, [1] FP32
   int stick_var[2][2] = {{0, 0}, {0, 0}};  // [precision][inverse, forward] z-transform variant
-  float stick_ms[2][2][2] = {};
+  float stick_ms[2][2][3] = {};
   bool stick_tuned[2] = {false, false};
   int plane_nvar[2] = {0, 0};
   float plane_ms[2][kPlaneVariants] = {};
@@ -583,6 +586,12 @@ hp_status apply_op(hp_ctx *c, const KPair *kp, int use_kq, int nk, int nb, const
                    const double *eps, int rows, const int *active = nullptr, const OpWork *w = nullptr) {
   const int nitems = nk * nb;
   const OpWork wk = w ? *w : OpWork{c->S1, c->S2, c->Cpart, c->C};
+  // the GEMM tiles cover the active bands only, packed per k
+  const int *gmap = nullptr;
+  if (active) {
+    HPCHK(launch_active_map(active, nk, nb, c->bmap, c->stream));
+    gmap = c->bmap;
+  }
   HPCHK(timed(c, K_STICK_INV, [&] {
     return launch_stick_inv(c->sk, kp, use_kq, nb, nitems, Xin, c->ld, wk.S1, c->ns_pad, c->n3, c->az.tw,
                             c->max_chunk_pw, c->ns_max, active, stick_variant(c, 64, 0), c->stream);
@@ -596,10 +605,10 @@ hp_status apply_op(hp_ctx *c, const KPair *kp, int use_kq, int nk, int nb, const
                             Y, c->ld, 0, c->d_kin, eps, Xin, nb, c->max_chunk_pw, c->ns_max, active,
                             stick_variant(c, 64, 1), c->stream);
   }));
-  HPTRY(proj(c, kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, Xin, nb, c->d_rowscale, 1.0, wk.C, active, wk.Cpart));
+  HPTRY(proj(c, kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, Xin, nb, c->d_rowscale, 1.0, wk.C, gmap, wk.Cpart));
   HPCHK(timed(c, K_ZEXPAND, [&] {
     return launch_zexpand(kp, use_kq, nk, c->d_T, c->t_stride, 0, rows, wk.C, (long)rows * nb, 1.0, Y, c->ld, nb,
-                          c->d_npw, c->npw_max, active, gemm_shape(c, 64, rows, nk).bv, c->stream);
+                          c->d_npw, c->npw_max, gmap, gemm_shape(c, 64, rows, nk).bv, c->stream);
   }));
   return HP_OK;
 }
@@ -896,6 +905,11 @@ hp_status setup16(hp_ctx *c) {
 hp_status apply_op32(hp_ctx *c, const KPair *kp, int nk, int nb, const float2 *Xin, float2 *Y, const double *eps,
                      int rows, const int *active) {
   const int nitems = nk * nb;
+  const int *gmap = nullptr;  // the GEMM tiles cover the active bands only, packed per k
+  if (active) {
+    HPCHK(launch_active_map(active, nk, nb, c->bmap, c->stream));
+    gmap = c->bmap;
+  }
   float2 *S1 = reinterpret_cast<float2 *>(c->S1), *S2 = reinterpret_cast<float2 *>(c->S2);
   float2 *Cpart = reinterpret_cast<float2 *>(c->Cpart), *C = reinterpret_cast<float2 *>(c->C);
   HPCHK(timed(c, K_STICK_INV32, [&] {
@@ -916,7 +930,7 @@ hp_status apply_op32(hp_ctx *c, const KPair *kp, int nk, int nb, const float2 *X
   if (m16 > 0) {
     const GemmShape g16 = gemm_shape(c, 16, m16, nk);
     HPCHK(timed(c, K_ZPROJ16, [&] {
-      return launch_zproj16(kp, 1, nk, c->T16, c->t_stride, 0, m16, Xin, c->ld, nb, c->d_npw, Cpart, g16.ns, active,
+      return launch_zproj16(kp, 1, nk, c->T16, c->t_stride, 0, m16, Xin, c->ld, nb, c->d_npw, Cpart, g16.ns, gmap,
                             g16.tile, c->stream);
     }));
     HPCHK(timed(c, K_ZPROJ_REDUCE, [&] {
@@ -924,14 +938,14 @@ hp_status apply_op32(hp_ctx *c, const KPair *kp, int nk, int nb, const float2 *X
     }));
     HPCHK(timed(c, K_ZEXPAND16, [&] {
       return launch_zexpand16(kp, 1, nk, c->T16, c->t_stride, 0, m16, C, (long)m16 * nb, 1.0, Y, c->ld, nb,
-                              c->d_npw, c->npw_max, active, g16.bv, c->stream);
+                              c->d_npw, c->npw_max, gmap, g16.bv, c->stream);
     }));
   }
   if (m16 < rows) {
     const int M = rows - m16;
     const GemmShape gs = gemm_shape(c, 32, M, nk);
     HPCHK(timed(c, K_ZPROJ32, [&] {
-      return launch_zproj32(kp, 1, nk, c->T32, c->t_stride, m16, M, Xin, c->ld, nb, c->d_npw, Cpart, gs.ns, active,
+      return launch_zproj32(kp, 1, nk, c->T32, c->t_stride, m16, M, Xin, c->ld, nb, c->d_npw, Cpart, gs.ns, gmap,
                             gs.tile, c->stream);
     }));
     HPCHK(timed(c, K_ZPROJ_REDUCE, [&] {
@@ -939,7 +953,7 @@ hp_status apply_op32(hp_ctx *c, const KPair *kp, int nk, int nb, const float2 *X
     }));
     HPCHK(timed(c, K_ZEXPAND32, [&] {
       return launch_zexpand32(kp, 1, nk, c->T32, c->t_stride, m16, M, C, (long)M * nb, 1.0, Y, c->ld, nb, c->d_npw,
-                              c->npw_max, active, gs.bv, c->stream);
+                              c->npw_max, gmap, gs.bv, c->stream);
     }));
   }
   return HP_OK;
@@ -1077,12 +1091,20 @@ hp_status tune_plane(hp_ctx *c, int prec, int nk) {
 }
 
 // z transforms: a workgroup per 32 sticks, or a thread per stick (same sums, same order).
+// z-transform variants available: the register ones need a compile-time N3 (24 or 40) and
+// the staged one the plane waves of 256 sticks in LDS (at most 64 KB here).
+int stick_variants(const hp_ctx *c) {
+  if (c->n3 != 24 && c->n3 != 40) return 1;
+  return (size_t)c->sk.max_pw256 * (sizeof(double2) + sizeof(int)) + c->n3 * sizeof(double2) <= 64 * 1024 ? 3 : 2;
+}
+
 hp_status tune_stick(hp_ctx *c, int prec, int nk) {
   const int slot = prec == 32 ? 1 : 0;
   if (c->stick_tuned[slot]) return HP_OK;
   const int nb = c->n_occ, nitems = nk * nb;
-  const int nv = (c->n3 == 24 || c->n3 == 40) ? 2 : 1;
+  const int nv = stick_variants(c);
   for (int fwd = 0; fwd < 2; ++fwd) {
+    for (int v = nv; v < 3; ++v) c->stick_ms[slot][fwd][v] = -1.f;  // not available
     float best = 1e30f;
     for (int v = 0; v < nv; ++v) {
       float ms = 0.f;
@@ -1790,6 +1812,14 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
       chunk_max = std::max(chunk_max, lay[i].sstart[s1 - 1] + lay[i].slen[s1 - 1] - lay[i].sstart[s0]);
     }
   }
+  int pw256 = 0;  // most plane waves in 256 consecutive sticks (LDS of the staged z transforms)
+  for (int i = 0; i < gs->n_kpts; ++i) {
+    const int ns = (int)lay[i].sx.size();
+    for (int s0 = 0; s0 < ns; s0 += 256) {
+      const int s1 = std::min(s0 + 256, ns);
+      pw256 = std::max(pw256, lay[i].sstart[s1 - 1] + lay[i].slen[s1 - 1] - lay[i].sstart[s0]);
+    }
+  }
   c->npw_max = npw_max;
   c->ld = (npw_max + 63) / 64 * 64;
   c->ns_max = ns_max;
@@ -1921,6 +1951,7 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
     he.npw = k.npw;
     he.spin = spin_of[i];
     he.order = L.order;
+    he.pw_off = E.pw_off;
     h_order.insert(h_order.end(), L.order.begin(), L.order.end());
     for (int p = 0; p < k.npw; ++p) {
       const int q = L.order[p];
@@ -1948,6 +1979,7 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   HPTRY(c->alloc(&c->d_phi, (size_t)c->n_kpts * c->phi_stride));
   int *d_order = nullptr;
   HPTRY(c->alloc(&d_order, h_order.size()));
+  c->d_order = d_order;
   HPCHK(hipMemcpyAsync(d_sx, h_sx.data(), sizeof(int) * h_sx.size(), hipMemcpyHostToDevice, st));
   HPCHK(hipMemcpyAsync(d_sy, h_sy.data(), sizeof(int) * h_sy.size(), hipMemcpyHostToDevice, st));
   HPCHK(hipMemcpyAsync(d_ss, h_ss.data(), sizeof(int) * h_ss.size(), hipMemcpyHostToDevice, st));
@@ -2006,6 +2038,7 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   c->sk.iz = d_iz;
   c->sk.xa = d_xa;
   c->sk.ent = d_ent;
+  c->sk.max_pw256 = pw256;
   // row scales of the stacked projector table: D_i for beta rows, alpha for u rows
   std::vector<double> rs(c->n_proj);
   for (int b = 0; b < c->n_kb; ++b) rs[b] = gs->d_kb[b];
@@ -2050,6 +2083,7 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   HPTRY(c->alloc(&c->bn, nitems));
   HPTRY(c->alloc(&c->rn, nitems));
   HPTRY(c->alloc(&c->active, nitems));
+  HPTRY(c->alloc(&c->bmap, (size_t)c->n_mesh * (nb + 1)));
   HPTRY(c->alloc(&c->count, kCntStep + kMaxChunk));
   HPTRY(c->alloc(&c->d_tol, 2));
   HPTRY(c->alloc(&c->d_stamps, 2 * kMaxStamps));
@@ -2633,6 +2667,43 @@ extern "C" hp_status hp_apply_h(hp_ctx *c, int32_t entry, int32_t n, const doubl
   return HP_OK;
 }
 
+extern "C" hp_status hp_apply_h_lowp(hp_ctx *c, int32_t entry, int32_t n, int32_t lowp_gemm, const double *x,
+                                     double *y) {
+  if (!c) return fail(HP_ERR_ARG, "context is NULL");
+  if (!x || !y) return fail(HP_ERR_ARG, "NULL argument");
+  if (entry < 0 || entry >= c->n_kpts) return fail(HP_ERR_ARG, "entry %d out of range", entry);
+  if (n < 1) return fail(HP_ERR_ARG, "n = %d out of range", n);
+  if (lowp_gemm != HP_GEMM_FP32 && lowp_gemm != HP_GEMM_BF16 && lowp_gemm != HP_GEMM_BF16_PV32)
+    return fail(HP_ERR_ARG, "unknown lowp_gemm %d", lowp_gemm);
+  entry = c->internal_of[entry];
+  const HostEntry &E = c->ent[entry];
+  c->lowp_gemm = lowp_gemm;
+  HPTRY(setup32(c));
+  if (lowp_gemm != HP_GEMM_FP32) HPTRY(setup16(c));
+  const int cap = c->n_mesh * c->n_occ;  // vectors per batch (work-buffer capacity)
+  std::vector<float2> h((size_t)cap * c->ld);
+  for (int v0 = 0; v0 < n; v0 += cap) {
+    const int nv = std::min(cap, n - v0);
+    std::fill(h.begin(), h.end(), make_float2(0.f, 0.f));
+    for (int v = 0; v < nv; ++v)
+      for (int p = 0; p < E.npw; ++p) {
+        const size_t q = (size_t)(v0 + v) * E.npw + E.order[p];
+        h[(size_t)v * c->ld + p] = make_float2((float)x[2 * q], (float)x[2 * q + 1]);
+      }
+    HPCHK(hipMemcpyAsync(c->P32, h.data(), sizeof(float2) * (size_t)nv * c->ld, hipMemcpyHostToDevice, c->stream));
+    HPTRY(apply_op32(c, c->d_kself + entry, 1, nv, c->P32, c->AP32, nullptr, c->n_beta, nullptr));
+    HPCHK(hipMemcpyAsync(h.data(), c->AP32, sizeof(float2) * (size_t)nv * c->ld, hipMemcpyDeviceToHost, c->stream));
+    HPTRY(sync(c));
+    for (int v = 0; v < nv; ++v)
+      for (int p = 0; p < E.npw; ++p) {
+        const size_t q = (size_t)(v0 + v) * E.npw + E.order[p];
+        y[2 * q] = h[(size_t)v * c->ld + p].x;
+        y[2 * q + 1] = h[(size_t)v * c->ld + p].y;
+      }
+  }
+  return HP_OK;
+}
+
 extern "C" hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const double q_frac[3], int32_t mesh_k,
                                           const double *dv, const hp_scf_params *p, double *du_out) {
   if (!c) return fail(HP_ERR_ARG, "context is NULL");
@@ -2772,10 +2843,11 @@ extern "C" hp_status hp_tuning_report(hp_ctx *c, char *buf, int32_t len) {
   for (int slot = 0; slot < 2; ++slot) {
     if (!c->stick_tuned[slot]) continue;
     snprintf(line, sizeof line,
-             "%s{\"prec\": %d, \"inverse_variant\": %d, \"inverse_ms\": [%.4f, %.4f], \"forward_variant\": %d, "
-             "\"forward_ms\": [%.4f, %.4f]}",
+             "%s{\"prec\": %d, \"inverse_variant\": %d, \"inverse_ms\": [%.4f, %.4f, %.4f], "
+             "\"forward_variant\": %d, \"forward_ms\": [%.4f, %.4f, %.4f]}",
              first ? "" : ", ", slot ? 32 : 64, c->stick_var[slot][0], c->stick_ms[slot][0][0], c->stick_ms[slot][0][1],
-             c->stick_var[slot][1], c->stick_ms[slot][1][0], c->stick_ms[slot][1][1]);
+             c->stick_ms[slot][0][2], c->stick_var[slot][1], c->stick_ms[slot][1][0], c->stick_ms[slot][1][1],
+             c->stick_ms[slot][1][2]);
     o += line;
     first = false;
   }
@@ -2829,7 +2901,7 @@ extern "C" hp_status hp_set_plane_variant(hp_ctx *c, int32_t prec, int32_t varia
 extern "C" hp_status hp_set_stick_variant(hp_ctx *c, int32_t prec, int32_t inverse_variant, int32_t forward_variant) {
   if (!c) return fail(HP_ERR_ARG, "context is NULL");
   if (prec != 64 && prec != 32) return fail(HP_ERR_ARG, "prec must be 64 or 32");
-  const int nv = (c->n3 == 24 || c->n3 == 40) ? 2 : 1;
+  const int nv = stick_variants(c);
   if (inverse_variant < 0 || inverse_variant >= nv || forward_variant < 0 || forward_variant >= nv)
     return fail(HP_ERR_ARG, "variants must be in 0..%d for this grid", nv - 1);
   const int slot = prec == 32 ? 1 : 0;

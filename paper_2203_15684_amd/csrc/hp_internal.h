@@ -64,6 +64,7 @@ struct Sticks {
   const int *iz;      // [pw] m3 mod N3
   const int *xa;      // [xa] active x columns
   const EntryDev *ent;
+  int max_pw256;      // most plane waves in 256 consecutive sticks of any entry
 };
 
 // ----------------------------------------------------------------- launchers
@@ -82,7 +83,9 @@ hipError_t launch_stick_fwd(const Sticks &sk, const KPair *kp, int use_kq, int n
                             const double *kin, const double *eps, const double2 *X, int eps_stride, int max_chunk_pw,
                             int ns_max, const int *active, int variant, hipStream_t st);
 // variant (both z transforms): 0 = a workgroup per 32 sticks, threads over (z, stick);
-// 1 = a thread per stick with its N3 values in registers (N3 = 24 or 40; else as 0).
+// 1 = a thread per stick with its N3 values in registers (N3 = 24 or 40; else as 0);
+// 2 = as 1 with the plane waves of the workgroup's 256 sticks staged through LDS by
+// coalesced loads (inverse) or stores (forward).  All three give the same results.
 // FP32 variants of the three operator kernels (mixed-precision inner solves).
 hipError_t launch_stick_inv32(const Sticks &sk, const KPair *kp, int use_kq, int nb, int nitems, const float2 *X,
                               int ld, float2 *S, int ns_pad, int n3, const float2 *tw3, int max_chunk_pw, int ns_max,
@@ -155,7 +158,10 @@ hipError_t launch_zexpand(const KPair *kp, int use_kq, int nk, const double2 *T,
                           const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st);
 // tile (projection): workgroup tile 0 = 32x32, 1 = 64 rows x 32 bands, 2 = 32 x 64, 3 = 64 x 64;
 // bv (expansion): 32 bv bands x 64 plane waves per workgroup, bv in {1, 2, 4}.
-// The `active` arguments (nullable) skip items, or 32-band tiles, whose flag is 0.
+// The GEMMs' `active` argument (nullable) is a band map from launch_active_map: the tiles
+// then cover only the active bands of each k, packed (outputs of other bands untouched).
+// bmap[k][0] = active items of pair k, bmap[k][1 + j] = the band of the j-th ([nk][nb + 1]).
+hipError_t launch_active_map(const int *active, int nk, int nb, int *bmap, hipStream_t st);
 // preconditioned CG (one workgroup per item)
 hipError_t launch_cg_init(const KPair *kp, int nb, int nitems, const double2 *B, double2 *Xv, double2 *R, double2 *P,
                           const double2 *AX, int have_x0, const double *diag, const double *eps, int ld,
@@ -226,10 +232,6 @@ hipError_t launch_zscale_copy(long n, const double2 *a, double s, double2 *out, 
 // [nrows][npw] table in the caller's plane-wave order to the internal stick order.
 hipError_t launch_gather_rows(const double2 *src, int npw, const int *order, int nrows, double2 *dst, int ld,
                               hipStream_t st);
-// dst[r][order[p]] = src[r][p] (p < npw): rows of length ld in the stick order to rows of
-// length npw in the caller's order.
-hipError_t launch_scatter_rows(const double2 *src, int ld, int npw, const int *order, int nrows, double2 *dst,
-                               hipStream_t st);
 // Jacobi diagonal of every entry e: kin + vmean[spin] + sum_r scale[r] |T_e[r]|^2 (1 on padding).
 hipError_t launch_diag(const KPair *self, const EntryDev *ent, int n_entries, const double2 *T, long t_stride,
                        int nrows, const double *scale, const double *kin, const double *vmean, int ld, double *diag,

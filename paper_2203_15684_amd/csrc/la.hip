@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(256) k_zproj(const KPair *kp, int use_kq, cons
                                                long t_stride, int m0, int M,
                                                const typename Mf<T>::c2 *__restrict__ X, int ld, int nb,
                                                const int *__restrict__ npw_of, int nsplit,
-                                               typename Mf<T>::c2 *__restrict__ Cpart, int nk, const int *active,
+                                               typename Mf<T>::c2 *__restrict__ Cpart, int nk, const int *bmap,
                                                int nmt, int nnt) {
   using C2 = typename Mf<T>::c2;
   using A4 = typename Mf<T>::acc;
@@ -82,11 +82,11 @@ __global__ void __launch_bounds__(256) k_zproj(const KPair *kp, int use_kq, cons
   const int split = group - k * nsplit;
   const int mt = (inner % nmt) * TM;
   const int nt = (inner / nmt) * TN;
-  if (active) {  // skip tiles whose bands are all converged (their outputs are not used)
-    int a = 0;
-    for (int i = threadIdx.x; i < TN; i += 256) a |= (nt + i < nb) ? active[k * nb + nt + i] : 0;
-    if (!__syncthreads_or(a)) return;
-  }
+  // band map (nullable): the active bands of each k packed to the front, so tiles cover only
+  // those (column j of the tile computes band bm[j]); tiles past the last one exit
+  const int *bm = bmap ? bmap + (size_t)k * (nb + 1) + 1 : nullptr;
+  const int ncol = bmap ? bm[-1] : nb;
+  if (nt >= ncol) return;
   const KPair P = kp[k];
   const int e = use_kq ? P.ej : P.ek;
   const int npw = npw_of[e];
@@ -109,6 +109,12 @@ __global__ void __launch_bounds__(256) k_zproj(const KPair *kp, int use_kq, cons
   const int lr = threadIdx.x >> 4;  // 0..15: row within a 16-row group
   const int lc = threadIdx.x & 15;  // 0..15: K column
   C2 ra[2 * WM], rb[2 * WN];
+  int vb[2 * WN];  // band of each loaded column (-1: none)
+#pragma unroll
+  for (int i = 0; i < 2 * WN; ++i) {
+    const int col = nt + lr + 16 * i;
+    vb[i] = col < ncol ? (bm ? bm[col] : col) : -1;
+  }
   auto load = [&](int g0) {
     const int g = g0 + lc;
 #pragma unroll
@@ -117,10 +123,7 @@ __global__ void __launch_bounds__(256) k_zproj(const KPair *kp, int use_kq, cons
       ra[i] = (row < M && g < g_end) ? Te[(size_t)row * ld + g] : zc<C2>();
     }
 #pragma unroll
-    for (int i = 0; i < 2 * WN; ++i) {
-      const int col = nt + lr + 16 * i;
-      rb[i] = (col < nb && g < g_end) ? Xk[(size_t)col * ld + g] : zc<C2>();
-    }
+    for (int i = 0; i < 2 * WN; ++i) rb[i] = (vb[i] >= 0 && g < g_end) ? Xk[(size_t)vb[i] * ld + g] : zc<C2>();
   };
   if (g_begin < g_end) load(g_begin);
   for (int g0 = g_begin; g0 < g_end; g0 += kKb) {
@@ -158,11 +161,11 @@ __global__ void __launch_bounds__(256) k_zproj(const KPair *kp, int use_kq, cons
       for (int r = 0; r < 4; ++r) {
         const int m = mt + (wm * WM + i) * 16 + Mf<T>::row(lane, r);
         const int v = nt + (wn * WN + j) * 16 + (lane & 15);
-        if (m < M && v < nb) {
+        if (m < M && v < ncol) {
           C2 o;
           o.x = cr[i][j][r];
           o.y = ci[i][j][r];
-          Cp[(size_t)m * nb + v] = o;
+          Cp[(size_t)m * nb + (bm ? bm[v] : v)] = o;
         }
       }
 }
@@ -194,7 +197,7 @@ __global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, co
                                                  long t_stride, int m0, int M,
                                                  const typename Mf<T>::c2 *__restrict__ C, long c_kstride,
                                                  double cscale, typename Mf<T>::c2 *__restrict__ Y, int ld, int nb,
-                                                 const int *__restrict__ npw_of, const int *active, int nk, int ngt,
+                                                 const int *__restrict__ npw_of, const int *bmap, int nk, int ngt,
                                                  int nvt) {
   using C2 = typename Mf<T>::c2;
   using A4 = typename Mf<T>::acc;
@@ -205,11 +208,9 @@ __global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, co
   if (!xcd_tile(nvt, nk * ngt, inner, group)) return;
   const int k = group / ngt;
   const int vt = inner * TV;
-  if (active) {
-    int a = 0;
-    for (int i = threadIdx.x; i < TV; i += 256) a |= (vt + i < nb) ? active[k * nb + vt + i] : 0;
-    if (!__syncthreads_or(a)) return;
-  }
+  const int *bm = bmap ? bmap + (size_t)k * (nb + 1) + 1 : nullptr;  // packed active bands
+  const int ncol = bmap ? bm[-1] : nb;
+  if (vt >= ncol) return;
   const KPair P = kp[k];
   const int e = use_kq ? P.ej : P.ek;
   const int npw = npw_of[e];
@@ -237,8 +238,8 @@ __global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, co
       const int vv = idx % TV, mm = idx / TV;
       const int m = mb + mm, v = vt + vv;
       C2 val = zc<C2>();
-      if (m < M && v < nb) {
-        val = Ck[(size_t)m * nb + v];
+      if (m < M && v < ncol) {
+        val = Ck[(size_t)m * nb + (bm ? bm[v] : v)];
         val.x *= cs;
         val.y *= cs;
       }
@@ -290,8 +291,9 @@ __global__ void __launch_bounds__(256) k_zexpand(const KPair *kp, int use_kq, co
   for (int i = 0; i < BV; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int v = vt + (wv * BV + i) * 16 + Mf<T>::row(lane, r);
-      if (v >= nb) continue;
+      const int vc = vt + (wv * BV + i) * 16 + Mf<T>::row(lane, r);
+      if (vc >= ncol) continue;
+      const int v = bm ? bm[vc] : vc;
       const int g = gt + wg * 32 + (lane & 15);
       if (g < npw) {
         C2 y = Yk[(size_t)v * ld + g];
@@ -337,7 +339,7 @@ template <int WM, int WN>
 __global__ void __launch_bounds__(256) k_zproj16(const KPair *kp, int use_kq, const unsigned *__restrict__ Tb,
                                                  long t_stride, int m0, int M, const float2 *__restrict__ X, int ld,
                                                  int nb, const int *__restrict__ npw_of, int nsplit,
-                                                 float2 *__restrict__ Cpart, int nk, const int *active, int nmt,
+                                                 float2 *__restrict__ Cpart, int nk, const int *bmap, int nmt,
                                                  int nnt) {
   constexpr int TM = 32 * WM, TN = 32 * WN;
   __shared__ __align__(8) short Ar[TM][kLd16], Ai[TM][kLd16], Br[TN][kLd16], Bi[TN][kLd16];
@@ -347,11 +349,9 @@ __global__ void __launch_bounds__(256) k_zproj16(const KPair *kp, int use_kq, co
   const int split = group - k * nsplit;
   const int mt = (inner % nmt) * TM;
   const int nt = (inner / nmt) * TN;
-  if (active) {
-    int a = 0;
-    for (int i = threadIdx.x; i < TN; i += 256) a |= (nt + i < nb) ? active[k * nb + nt + i] : 0;
-    if (!__syncthreads_or(a)) return;
-  }
+  const int *bm = bmap ? bmap + (size_t)k * (nb + 1) + 1 : nullptr;  // packed active bands
+  const int ncol = bmap ? bm[-1] : nb;
+  if (nt >= ncol) return;
   const KPair P = kp[k];
   const int e = use_kq ? P.ej : P.ek;
   const int npw = npw_of[e];
@@ -375,6 +375,12 @@ __global__ void __launch_bounds__(256) k_zproj16(const KPair *kp, int use_kq, co
   const int lc = threadIdx.x & 31;  // K column
   unsigned ra[4 * WM];
   float2 rb[4 * WN];
+  int vb[4 * WN];  // band of each loaded column (-1: none)
+#pragma unroll
+  for (int i = 0; i < 4 * WN; ++i) {
+    const int col = nt + lr + 8 * i;
+    vb[i] = col < ncol ? (bm ? bm[col] : col) : -1;
+  }
   auto load = [&](int g0) {
     const int g = g0 + lc;
 #pragma unroll
@@ -383,10 +389,8 @@ __global__ void __launch_bounds__(256) k_zproj16(const KPair *kp, int use_kq, co
       ra[i] = (row < M && g < g_end) ? Te[(size_t)row * ld + g] : 0u;
     }
 #pragma unroll
-    for (int i = 0; i < 4 * WN; ++i) {
-      const int col = nt + lr + 8 * i;
-      rb[i] = (col < nb && g < g_end) ? Xk[(size_t)col * ld + g] : make_float2(0.f, 0.f);
-    }
+    for (int i = 0; i < 4 * WN; ++i)
+      rb[i] = (vb[i] >= 0 && g < g_end) ? Xk[(size_t)vb[i] * ld + g] : make_float2(0.f, 0.f);
   };
   if (g_begin < g_end) load(g_begin);
   for (int g0 = g_begin; g0 < g_end; g0 += kKb16) {
@@ -441,7 +445,7 @@ __global__ void __launch_bounds__(256) k_zproj16(const KPair *kp, int use_kq, co
       for (int r = 0; r < 4; ++r) {
         const int m = mt + (wm * WM + i) * 16 + 4 * (lane >> 4) + r;
         const int v = nt + (wn * WN + j) * 16 + (lane & 15);
-        if (m < M && v < nb) Cp[(size_t)m * nb + v] = make_float2(cr[i][j][r], ci[i][j][r]);
+        if (m < M && v < ncol) Cp[(size_t)m * nb + (bm ? bm[v] : v)] = make_float2(cr[i][j][r], ci[i][j][r]);
       }
 }
 
@@ -450,7 +454,7 @@ template <int BV>
 __global__ void __launch_bounds__(256) k_zexpand16(const KPair *kp, int use_kq, const unsigned *__restrict__ Tb,
                                                    long t_stride, int m0, int M, const float2 *__restrict__ C,
                                                    long c_kstride, double cscale, float2 *__restrict__ Y, int ld,
-                                                   int nb, const int *__restrict__ npw_of, const int *active,
+                                                   int nb, const int *__restrict__ npw_of, const int *bmap,
                                                    int nk, int ngt, int nvt) {
   constexpr int TV = 32 * BV;
   __shared__ __align__(8) short Cr[TV][kLd16], Ci[TV][kLd16];  // [v][m]
@@ -459,11 +463,9 @@ __global__ void __launch_bounds__(256) k_zexpand16(const KPair *kp, int use_kq, 
   if (!xcd_tile(nvt, nk * ngt, inner, group)) return;
   const int k = group / ngt;
   const int vt = inner * TV;
-  if (active) {
-    int a = 0;
-    for (int i = threadIdx.x; i < TV; i += 256) a |= (vt + i < nb) ? active[k * nb + vt + i] : 0;
-    if (!__syncthreads_or(a)) return;
-  }
+  const int *bm = bmap ? bmap + (size_t)k * (nb + 1) + 1 : nullptr;  // packed active bands
+  const int ncol = bmap ? bm[-1] : nb;
+  if (vt >= ncol) return;
   const KPair P = kp[k];
   const int e = use_kq ? P.ej : P.ek;
   const int npw = npw_of[e];
@@ -492,8 +494,8 @@ __global__ void __launch_bounds__(256) k_zexpand16(const KPair *kp, int use_kq, 
       const int vv = idx % TV, mm = idx / TV;
       const int m = mb + mm, v = vt + vv;
       float2 val = make_float2(0.f, 0.f);
-      if (m < M && v < nb) {
-        val = Ck[(size_t)m * nb + v];
+      if (m < M && v < ncol) {
+        val = Ck[(size_t)m * nb + (bm ? bm[v] : v)];
         val.x *= cs;
         val.y *= cs;
       }
@@ -555,8 +557,9 @@ __global__ void __launch_bounds__(256) k_zexpand16(const KPair *kp, int use_kq, 
   for (int i = 0; i < BV; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int v = vt + (wv * BV + i) * 16 + 4 * (lane >> 4) + r;
-      if (v >= nb) continue;
+      const int vc = vt + (wv * BV + i) * 16 + 4 * (lane >> 4) + r;
+      if (vc >= ncol) continue;
+      const int v = bm ? bm[vc] : vc;
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int g = gt + wg * 32 + 16 * j + (lane & 15);
@@ -857,26 +860,26 @@ namespace {
 template <class T>
 hipError_t zproj_t(const KPair *kp, int use_kq, int nk, const typename Mf<T>::c2 *Tm, long t_stride, int m0, int M,
                    const typename Mf<T>::c2 *X, int ld, int nb, const int *npw_of, typename Mf<T>::c2 *Cpart,
-                   int nsplit, const int *active, int tile, hipStream_t st) {
+                   int nsplit, const int *bmap, int tile, hipStream_t st) {
   const int wm = (tile & 1) ? 2 : 1, wn = (tile & 2) ? 2 : 1;
   const int nmt = (M + 32 * wm - 1) / (32 * wm), nnt = (nb + 32 * wn - 1) / (32 * wn);
   dim3 grid(xcd_grid(nmt * nnt, nk * nsplit));
   switch (tile) {
     case 1:
       hipLaunchKernelGGL((k_zproj<T, 2, 1>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, X, ld, nb,
-                         npw_of, nsplit, Cpart, nk, active, nmt, nnt);
+                         npw_of, nsplit, Cpart, nk, bmap, nmt, nnt);
       break;
     case 2:
       hipLaunchKernelGGL((k_zproj<T, 1, 2>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, X, ld, nb,
-                         npw_of, nsplit, Cpart, nk, active, nmt, nnt);
+                         npw_of, nsplit, Cpart, nk, bmap, nmt, nnt);
       break;
     case 3:
       hipLaunchKernelGGL((k_zproj<T, 2, 2>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, X, ld, nb,
-                         npw_of, nsplit, Cpart, nk, active, nmt, nnt);
+                         npw_of, nsplit, Cpart, nk, bmap, nmt, nnt);
       break;
     default:
       hipLaunchKernelGGL((k_zproj<T, 1, 1>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, X, ld, nb,
-                         npw_of, nsplit, Cpart, nk, active, nmt, nnt);
+                         npw_of, nsplit, Cpart, nk, bmap, nmt, nnt);
       break;
   }
   return hipGetLastError();
@@ -885,22 +888,22 @@ hipError_t zproj_t(const KPair *kp, int use_kq, int nk, const typename Mf<T>::c2
 template <class T>
 hipError_t zexpand_t(const KPair *kp, int use_kq, int nk, const typename Mf<T>::c2 *Tm, long t_stride, int m0, int M,
                      const typename Mf<T>::c2 *C, long c_kstride, double cscale, typename Mf<T>::c2 *Y, int ld,
-                     int nb, const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st) {
+                     int nb, const int *npw_of, int npw_max, const int *bmap, int bv, hipStream_t st) {
   bv = (bv == 2 || bv == 4) ? bv : 1;
   const int ngt = (npw_max + 63) / 64, nvt = (nb + 32 * bv - 1) / (32 * bv);
   dim3 grid(xcd_grid(nvt, nk * ngt));
   switch (bv) {
     case 2:
       hipLaunchKernelGGL((k_zexpand<T, 2>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, C, c_kstride,
-                         cscale, Y, ld, nb, npw_of, active, nk, ngt, nvt);
+                         cscale, Y, ld, nb, npw_of, bmap, nk, ngt, nvt);
       break;
     case 4:
       hipLaunchKernelGGL((k_zexpand<T, 4>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, C, c_kstride,
-                         cscale, Y, ld, nb, npw_of, active, nk, ngt, nvt);
+                         cscale, Y, ld, nb, npw_of, bmap, nk, ngt, nvt);
       break;
     default:
       hipLaunchKernelGGL((k_zexpand<T, 1>), grid, dim3(256), 0, st, kp, use_kq, Tm, t_stride, m0, M, C, c_kstride,
-                         cscale, Y, ld, nb, npw_of, active, nk, ngt, nvt);
+                         cscale, Y, ld, nb, npw_of, bmap, nk, ngt, nvt);
       break;
   }
   return hipGetLastError();
@@ -909,13 +912,13 @@ hipError_t zexpand_t(const KPair *kp, int use_kq, int nk, const typename Mf<T>::
 
 hipError_t launch_zproj(const KPair *kp, int use_kq, int nk, const double2 *T, long t_stride, int m0, int M,
                         const double2 *X, int ld, int nb, const int *npw_of, double2 *Cpart, int nsplit,
-                        const int *active, int tile, hipStream_t st) {
-  return zproj_t<double>(kp, use_kq, nk, T, t_stride, m0, M, X, ld, nb, npw_of, Cpart, nsplit, active, tile, st);
+                        const int *bmap, int tile, hipStream_t st) {
+  return zproj_t<double>(kp, use_kq, nk, T, t_stride, m0, M, X, ld, nb, npw_of, Cpart, nsplit, bmap, tile, st);
 }
 hipError_t launch_zproj32(const KPair *kp, int use_kq, int nk, const float2 *T, long t_stride, int m0, int M,
                           const float2 *X, int ld, int nb, const int *npw_of, float2 *Cpart, int nsplit,
-                          const int *active, int tile, hipStream_t st) {
-  return zproj_t<float>(kp, use_kq, nk, T, t_stride, m0, M, X, ld, nb, npw_of, Cpart, nsplit, active, tile, st);
+                          const int *bmap, int tile, hipStream_t st) {
+  return zproj_t<float>(kp, use_kq, nk, T, t_stride, m0, M, X, ld, nb, npw_of, Cpart, nsplit, bmap, tile, st);
 }
 
 hipError_t launch_zproj_reduce(int nk, int M, int nb, int nsplit, const double2 *Cpart, const double *row_scale,
@@ -935,39 +938,70 @@ hipError_t launch_zproj_reduce32(int nk, int M, int nb, int nsplit, const float2
 
 hipError_t launch_zproj16(const KPair *kp, int use_kq, int nk, const unsigned *T, long t_stride, int m0, int M,
                           const float2 *X, int ld, int nb, const int *npw_of, float2 *Cpart, int nsplit,
-                          const int *active, int tile, hipStream_t st) {
+                          const int *bmap, int tile, hipStream_t st) {
   const int w = tile == 3 ? 2 : 1;
   const int nmt = (M + 32 * w - 1) / (32 * w), nnt = (nb + 32 * w - 1) / (32 * w);
   dim3 grid(xcd_grid(nmt * nnt, nk * nsplit));
   if (w == 2)
     hipLaunchKernelGGL((k_zproj16<2, 2>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, X, ld, nb, npw_of,
-                       nsplit, Cpart, nk, active, nmt, nnt);
+                       nsplit, Cpart, nk, bmap, nmt, nnt);
   else
     hipLaunchKernelGGL((k_zproj16<1, 1>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, X, ld, nb, npw_of,
-                       nsplit, Cpart, nk, active, nmt, nnt);
+                       nsplit, Cpart, nk, bmap, nmt, nnt);
   return hipGetLastError();
 }
 
 hipError_t launch_zexpand16(const KPair *kp, int use_kq, int nk, const unsigned *T, long t_stride, int m0, int M,
                             const float2 *C, long c_kstride, double cscale, float2 *Y, int ld, int nb,
-                            const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st) {
+                            const int *npw_of, int npw_max, const int *bmap, int bv, hipStream_t st) {
   bv = (bv == 2 || bv == 4) ? bv : 1;
   const int ngt = (npw_max + 63) / 64, nvt = (nb + 32 * bv - 1) / (32 * bv);
   dim3 grid(xcd_grid(nvt, nk * ngt));
   switch (bv) {
     case 2:
       hipLaunchKernelGGL((k_zexpand16<2>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride,
-                         cscale, Y, ld, nb, npw_of, active, nk, ngt, nvt);
+                         cscale, Y, ld, nb, npw_of, bmap, nk, ngt, nvt);
       break;
     case 4:
       hipLaunchKernelGGL((k_zexpand16<4>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride,
-                         cscale, Y, ld, nb, npw_of, active, nk, ngt, nvt);
+                         cscale, Y, ld, nb, npw_of, bmap, nk, ngt, nvt);
       break;
     default:
       hipLaunchKernelGGL((k_zexpand16<1>), grid, dim3(256), 0, st, kp, use_kq, T, t_stride, m0, M, C, c_kstride,
-                         cscale, Y, ld, nb, npw_of, active, nk, ngt, nvt);
+                         cscale, Y, ld, nb, npw_of, bmap, nk, ngt, nvt);
       break;
   }
+  return hipGetLastError();
+}
+
+// bmap[k][0] = number of active items of pair k, bmap[k][1 + j] = band of the j-th of them
+// (increasing band order); one workgroup per k, ballot prefix counts.
+__global__ void __launch_bounds__(256) k_active_map(const int *__restrict__ active, int nb, int *__restrict__ bmap) {
+  __shared__ int wsum[4];
+  __shared__ int base;
+  const int k = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int *out = bmap + (size_t)k * (nb + 1);
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < nb; c0 += 256) {
+    const int j = c0 + (int)threadIdx.x;
+    const int f = j < nb ? active[(size_t)k * nb + j] != 0 : 0;
+    const unsigned long long b = __ballot(f);
+    if (lane == 0) wsum[wave] = __popcll(b);
+    __syncthreads();
+    int off = base;
+    for (int w = 0; w < wave; ++w) off += wsum[w];
+    if (f) out[1 + off + __popcll(b & ((1ull << lane) - 1ull))] = j;
+    __syncthreads();
+    if (threadIdx.x == 0) base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = base;
+}
+
+hipError_t launch_active_map(const int *active, int nk, int nb, int *bmap, hipStream_t st) {
+  hipLaunchKernelGGL(k_active_map, dim3(nk), dim3(256), 0, st, active, nb, bmap);
   return hipGetLastError();
 }
 
@@ -978,15 +1012,15 @@ hipError_t launch_to_bf16_pairs(const double2 *in, unsigned *out, long n, hipStr
 
 hipError_t launch_zexpand(const KPair *kp, int use_kq, int nk, const double2 *T, long t_stride, int m0, int M,
                           const double2 *C, long c_kstride, double cscale, double2 *Y, int ld, int nb,
-                          const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st) {
+                          const int *npw_of, int npw_max, const int *bmap, int bv, hipStream_t st) {
   return zexpand_t<double>(kp, use_kq, nk, T, t_stride, m0, M, C, c_kstride, cscale, Y, ld, nb, npw_of, npw_max,
-                           active, bv, st);
+                           bmap, bv, st);
 }
 hipError_t launch_zexpand32(const KPair *kp, int use_kq, int nk, const float2 *T, long t_stride, int m0, int M,
                             const float2 *C, long c_kstride, double cscale, float2 *Y, int ld, int nb,
-                            const int *npw_of, int npw_max, const int *active, int bv, hipStream_t st) {
+                            const int *npw_of, int npw_max, const int *bmap, int bv, hipStream_t st) {
   return zexpand_t<float>(kp, use_kq, nk, T, t_stride, m0, M, C, c_kstride, cscale, Y, ld, nb, npw_of, npw_max,
-                          active, bv, st);
+                          bmap, bv, st);
 }
 
 hipError_t launch_cg_init(const KPair *kp, int nb, int nitems, const double2 *B, double2 *Xv, double2 *R,

@@ -101,6 +101,8 @@ _lib.hp_solve_first_order.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_int32, _dp
 _lib.hp_solve_first_order.restype = C.c_int32
 _lib.hp_xc_kernel.argtypes = [C.c_int32, C.c_int64, _dp, _dp]
 _lib.hp_xc_kernel.restype = C.c_int32
+_lib.hp_apply_h_lowp.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _dp, _dp]
+_lib.hp_apply_h_lowp.restype = C.c_int32
 
 
 
@@ -128,7 +130,8 @@ _lib.hp_set_stick_variant.restype = C.c_int32
 EXPORTED = ["hp_ground_state_load", "hp_sternheimer_scf", "hp_response_matrix", "hp_hubbard_params",
             "hp_destroy", "hp_last_error", "hp_apply_h", "hp_solve_first_order", "hp_profile_start",
             "hp_profile_stop", "hp_tuning_report", "hp_set_gemm_shape", "hp_set_plane_variant",
-            "hp_neighbours", "hp_set_stick_variant", "hp_site_occupations", "hp_xc_kernel"]
+            "hp_neighbours", "hp_set_stick_variant", "hp_site_occupations", "hp_xc_kernel",
+            "hp_apply_h_lowp"]
 
 
 def hp_last_error() -> str:
@@ -409,6 +412,16 @@ def hp_solve_first_order(ctx: Context, pert_site: int, q_frac, mesh_k: int, dv: 
     s = _check(_lib.hp_solve_first_order(ctx.handle, int(pert_site), _ptr(q), int(mesh_k), dvp, C.byref(p),
                                          _ptr(out.view(np.float64))))
     return out, s
+
+
+def hp_apply_h_lowp(ctx: Context, entry: int, x: np.ndarray, lowp_gemm: int = HP_GEMM_FP32) -> np.ndarray:
+    """H_k x with the mixed form's reduced-precision operator (FP32 FFTs, FP32 or BF16
+    projections), returned in FP64."""
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.complex128)
+    y = np.zeros_like(x)
+    _check(_lib.hp_apply_h_lowp(ctx.handle, int(entry), x.shape[0], int(lowp_gemm), _ptr(x.view(np.float64)),
+                                _ptr(y.view(np.float64))), allow_warn=False)
+    return y
 
 
 def hp_xc_kernel(rho: np.ndarray) -> np.ndarray:

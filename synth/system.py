@@ -133,37 +133,41 @@ OLIVINE_G = _reg(replace(OLIVINE, name="olivine28_gamma", kmesh=(1, 1, 1), qmesh
 # (k+q stays on the mesh) and a cutoff jittered per {k,-k} pair so that PW counts spread
 # over ~9,600-10,400.
 OLIVINE_K442 = _reg(replace(OLIVINE, name="olivine28_k442", cfg_id=1, kmesh=(4, 4, 2),
-                            ecut_jitter=0.0265, base=None))
+                            ecut_jitter=0.0265, base=None, gs_tol=1e-10))
 # 2x1x1 supercell of the olivine-shaped cell: 56 atoms, 8 d sites, ~2x10^4 PWs.
 # (the cutoff stays the base cell's 22.45 Ha so that the supercell is an exact replica:
 # ~2x10^4 plane waves)
 OLIVINE_SC = _reg(replace(OLIVINE, name="olivine56_sc211", cfg_id=4, cell=(39.2, 11.3, 8.9),
                           n_atoms=56, n_hub=8, fft=(144, 45, 40), ecut=22.45, n_occ=224,
-                          base="olivine28", rep=(2, 1, 1)))
+                          base="olivine28", rep=(2, 1, 1), gs_tol=1e-10))
 # Its Gamma-only form (q mesh 1x2x1): the 144x45x40 grid, ~2x10^4 plane waves and 224 bands
 # for a stored full-size reference, folded from the Gamma-only primitive cell.
 OLIVINE_SC_G = _reg(replace(OLIVINE_SC, name="olivine56_gamma", kmesh=(1, 1, 1), qmesh=(1, 2, 1),
-                            base="olivine28_gamma"))
+                            base="olivine28_gamma", gs_tol=1e-12))
 # Collinear spin-polarized variants (the same atoms and wells; an exchange field of
 # 0.15 Ha on the d sites): one site (polarized), two sites and the olivine-shaped cell
 # with antiferromagnetic order (+, -, +, - over the d sites; equal electron counts per
 # spin, zero net moment).
 SC1_FM = _reg(replace(SC1, name="sc1_gamma_spin", spin_field=0.15, spin_signs=(1,)))
 DUO_AFM = _reg(replace(DUO, name="duo_k221_afm", spin_field=0.15))
-OLIVINE_AFM = _reg(replace(OLIVINE, name="olivine28_afm", spin_field=0.15))
+OLIVINE_AFM = _reg(replace(OLIVINE, name="olivine28_afm", spin_field=0.15, gs_tol=1e-10))
+# its Gamma-only form (entries Gamma and (0, 1/2, 0) per spin): full-size checks of the
+# spin-resolved kernels at a small ground-state cost
+OLIVINE_AFM_G = _reg(replace(OLIVINE_AFM, name="olivine28_afm_gamma", kmesh=(1, 1, 1), qmesh=(1, 2, 1)))
 # Ground states with an on-site Hubbard potential (U = 0.15 Ha ~ 4 eV): one site, the
 # antiferromagnetic two-site cell (spin-dependent potential) and the olivine-shaped cell;
 # and a 2x1x1 replica of the one-site cell whose two sites are equivalent by translation.
 SC1_U = _reg(replace(SC1, name="sc1_gamma_u", hub_u0=0.15))
 DUO_AFM_U = _reg(replace(DUO, name="duo_k221_afm_u", spin_field=0.15, hub_u0=0.15))
-OLIVINE_U = _reg(replace(OLIVINE, name="olivine28_u", hub_u0=0.15))
+OLIVINE_U = _reg(replace(OLIVINE, name="olivine28_u", hub_u0=0.15, gs_tol=1e-10))
+OLIVINE_U_G = _reg(replace(OLIVINE_U, name="olivine28_u_gamma", kmesh=(1, 1, 1), qmesh=(1, 2, 1)))
 # Metallic variants (15 electrons in the 8 kept bands, cold smearing 0.01 Ha): the one-site
 # cell at Gamma (band 8 half filled) and on the 2x1x1 k mesh (bands 7-8 cross the Fermi level).
 SC1_METAL = _reg(replace(SC1, name="sc1_gamma_metal", degauss=0.01, n_el=15.0))
 SC1_K2_METAL = _reg(replace(SC1_K2, name="sc1_k211_metal", degauss=0.01, n_el=15.0))
 # The olivine-shaped cell with one electron removed (223 in 112 kept bands, cold smearing
 # 0.01 Ha): the top valence band crosses the Fermi level, the next band stays 1.18 Ha above.
-OLIVINE_METAL = _reg(replace(OLIVINE, name="olivine28_metal", degauss=0.01, n_el=223.0))
+OLIVINE_METAL = _reg(replace(OLIVINE, name="olivine28_metal", degauss=0.01, n_el=223.0, gs_tol=1e-10))
 # The two-site cell with one electron removed (23 in 12 kept bands): a metal on a 2x3x1 k mesh.
 DUO_METAL = _reg(replace(DUO, name="duo_k221_metal", degauss=0.01, n_el=23.0))
 
@@ -1024,9 +1028,12 @@ def _build_replicated(spec, *, backend, device, tol, verbose):
     the union of the folded primitive spheres): no supercell eigensolve is needed."""
     base_spec = SPECS[spec.base]
     from . import cache  # the base cell of a large supercell is usually cached already
-    base = cache.load(base_spec.name) if base_spec.n_occ >= 100 else None
-    if base is None:
-        base = build_ground_state(base_spec, backend=backend, device=device, tol=tol, verbose=verbose)
+    big = base_spec.n_occ >= 100
+    base = cache.load(base_spec.name) if big else None
+    if base is None:  # the base cell at its own tolerance, kept for later users of it
+        base = build_ground_state(base_spec, backend=backend, device=device, verbose=verbose)
+        if big:
+            cache.save(base)
     rep = np.array(spec.rep, dtype=np.int64)
     r1, r2, r3 = spec.rep
     cell = np.diag(np.array(spec.cell, dtype=np.float64))

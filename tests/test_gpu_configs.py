@@ -54,6 +54,14 @@ def test_batching_workload_shapes():
                 assert e.npw == f.npw
 
 
+def test_base_cell_ground_state():
+    """The olivine-shaped cell the supercell replicates (built once here and cached, so that
+    the supercell's own build only folds its states)."""
+    g = gs("olivine28")
+    assert g.n_occ == 112 and len(g.kpts) == 48
+    assert max(e.resid for e in g.kpts) <= 2e-12
+
+
 def test_scaleup_workload_shapes():
     g = gs("olivine56_sc211")
     assert g.n_occ == 224 and g.n_hub == 8 and g.fft == (144, 45, 40)

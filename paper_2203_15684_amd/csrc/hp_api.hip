@@ -19,9 +19,17 @@
 #include <thread>
 #include <vector>
 
+#include <mutex>
+
 #include "hp_internal.h"
 
 using namespace hp;
+
+// Fixed workspace of hp_apply_h_noalloc: the intermediate buffers of its operator apply
+// live here, so that the call allocates nothing.  One copy per GPU the library runs on, held
+// until the process ends.  In host code `scratch` is only a handle: its device address on
+// each device comes from hipGetSymbolAddress (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[HP_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -95,6 +103,26 @@ hp_status dalloc(T **p, size_t count) {
 
 int wrapi(long v, int n) { long r = v % n; return (int)(r < 0 ? r + n : r); }
 
+// Device address of `scratch` on the current device, looked up once per device.
+hp_status noalloc_scratch(unsigned char **out) {
+  static std::mutex mu;
+  static std::vector<unsigned char *> addr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(HP_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(HP_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    addr[dev] = static_cast<unsigned char *>(ptr);
+  }
+  *out = addr[dev];
+  return HP_OK;
+}
+
 struct HostEntry {
   std::array<double, 3> k;
   double weight;
@@ -147,6 +175,8 @@ struct hp_ctx {
   double *d_vp = nullptr, *d_fxc = nullptr, *d_bvec = nullptr, *d_q = nullptr;
   int *d_npw = nullptr;
   int *d_order = nullptr;  // [pw] internal position -> caller index, per entry at pw_off
+  // this device's fixed workspace of hp_apply_h_noalloc (the file-scope `scratch` array)
+  unsigned char *scratch = nullptr;
   double *d_kin = nullptr, *d_diag = nullptr, *d_rowscale = nullptr, *d_eps = nullptr;
   double2 *d_T = nullptr, *d_phi = nullptr, *d_A = nullptr, *d_psi = nullptr;
   KPair *d_kp = nullptr, *d_kself = nullptr;
@@ -1837,6 +1867,7 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   }
   hipStream_t st = c->stream;
   for (int i = 0; i < 16; ++i) HPCHK(hipEventCreate(&c->ev[i]));
+  HPTRY(noalloc_scratch(&c->scratch));
 
   // FFT axes: twiddles and permutations
   const int N[3] = {c->n1, c->n2, c->n3};
@@ -2701,6 +2732,48 @@ extern "C" hp_status hp_apply_h_lowp(hp_ctx *c, int32_t entry, int32_t n, int32_
         y[2 * q + 1] = h[(size_t)v * c->ld + p].y;
       }
   }
+  return HP_OK;
+}
+
+// Bytes of workspace per vector of hp_apply_h_noalloc: X and H X in the stick order, the
+// z-stick data before and after the plane round trip, the projection partial sums (at most
+// nsplit_cap K slices) and the projections.
+static size_t noalloc_bytes_per_vector(const hp_ctx *c) {
+  return sizeof(double2) * (2 * (size_t)c->ld + 2 * (size_t)c->n3 * c->ns_pad +
+                            (size_t)(c->nsplit_cap + 1) * std::max(c->n_beta, 1));
+}
+
+extern "C" hp_status hp_apply_h_noalloc(hp_ctx *c, int32_t entry, int32_t n, const double *x, double *y) {
+  if (!c) return fail(HP_ERR_ARG, "context is NULL");
+  if (!x || !y) return fail(HP_ERR_ARG, "NULL argument");
+  if (entry < 0 || entry >= c->n_kpts) return fail(HP_ERR_ARG, "entry %d out of range", entry);
+  const size_t per = noalloc_bytes_per_vector(c);
+  const long nmax = (long)(HP_NOALLOC_SCRATCH_BYTES / per);
+  if (n < 1 || n > nmax)
+    return fail(HP_ERR_ARG, "n = %d out of range: the fixed %ld-byte workspace holds 1..%ld vectors of %zu bytes",
+                n, (long)HP_NOALLOC_SCRATCH_BYTES, nmax, per);
+  if (!c->scratch) return fail(HP_ERR_STATE, "no workspace for this context's device");
+  for (const void *ptr : {(const void *)x, (const void *)y}) {  // host pointers would fault the kernels
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, ptr) != hipSuccess || at.type != hipMemoryTypeDevice) {
+      (void)hipGetLastError();
+      return fail(HP_ERR_ARG, "x and y must be device memory");
+    }
+  }
+  const int ie = c->internal_of[entry];
+  const HostEntry &E = c->ent[ie];
+  // workspace: X [n][ld] | Y [n][ld] | S1, S2 [n][n3][ns_pad] | Cpart [nsplit_cap][n_beta][n] | C [n_beta][n]
+  double2 *X = reinterpret_cast<double2 *>(c->scratch);
+  double2 *Y = X + (size_t)n * c->ld;
+  OpWork w;
+  w.S1 = Y + (size_t)n * c->ld;
+  w.S2 = w.S1 + (size_t)n * c->n3 * c->ns_pad;
+  w.Cpart = w.S2 + (size_t)n * c->n3 * c->ns_pad;
+  w.C = w.Cpart + (size_t)c->nsplit_cap * std::max(c->n_beta, 1) * n;
+  const int *ord = c->d_order + E.pw_off;
+  HPCHK(launch_gather_rows(reinterpret_cast<const double2 *>(x), E.npw, ord, n, X, c->ld, c->stream));
+  HPTRY(apply_op(c, c->d_kself + ie, 0, 1, n, X, Y, nullptr, c->n_beta, nullptr, &w));
+  HPCHK(launch_scatter_rows(Y, c->ld, E.npw, ord, n, reinterpret_cast<double2 *>(y), c->stream));
   return HP_OK;
 }
 

@@ -232,6 +232,10 @@ hipError_t launch_zscale_copy(long n, const double2 *a, double s, double2 *out, 
 // [nrows][npw] table in the caller's plane-wave order to the internal stick order.
 hipError_t launch_gather_rows(const double2 *src, int npw, const int *order, int nrows, double2 *dst, int ld,
                               hipStream_t st);
+// dst[r][order[p]] = src[r][p] (p < npw): rows of length ld in the stick order to rows of
+// length npw in the caller's order.
+hipError_t launch_scatter_rows(const double2 *src, int ld, int npw, const int *order, int nrows, double2 *dst,
+                               hipStream_t st);
 // Jacobi diagonal of every entry e: kin + vmean[spin] + sum_r scale[r] |T_e[r]|^2 (1 on padding).
 hipError_t launch_diag(const KPair *self, const EntryDev *ent, int n_entries, const double2 *T, long t_stride,
                        int nrows, const double *scale, const double *kin, const double *vmean, int ld, double *diag,

@@ -22,6 +22,16 @@ __global__ void __launch_bounds__(kT) k_gather_rows(const double2 *__restrict__ 
   dst[(size_t)r * ld + p] = p < npw ? src[(size_t)r * npw + order[p]] : make_double2(0.0, 0.0);
 }
 
+// dst[r][order[p]] = src[r][p] for p < npw (src rows of length ld, dst rows of length npw):
+// the internal stick order back to the caller's plane-wave order.
+__global__ void __launch_bounds__(kT) k_scatter_rows(const double2 *__restrict__ src, int ld, int npw,
+                                                     const int *__restrict__ order, double2 *__restrict__ dst) {
+  const int r = blockIdx.y;
+  const int p = blockIdx.x * kT + threadIdx.x;
+  if (p >= npw) return;
+  dst[(size_t)r * npw + order[p]] = src[(size_t)r * ld + p];
+}
+
 // diag[e][p] = kin[e][p] + vmean[spin(e)] + sum_r scale[r] |T_e[r][p]|^2 (rows in order),
 // 1 on the padding p >= npw(e).
 __global__ void __launch_bounds__(kT) k_diag(const KPair *__restrict__ self, const EntryDev *__restrict__ ent,
@@ -81,6 +91,13 @@ hipError_t launch_gather_rows(const double2 *src, int npw, const int *order, int
                               hipStream_t st) {
   if (nrows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_rows, dim3((ld + kT - 1) / kT, nrows), dim3(kT), 0, st, src, npw, order, dst, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(const double2 *src, int ld, int npw, const int *order, int nrows, double2 *dst,
+                               hipStream_t st) {
+  if (nrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_rows, dim3((npw + kT - 1) / kT, nrows), dim3(kT), 0, st, src, ld, npw, order, dst);
   return hipGetLastError();
 }
 

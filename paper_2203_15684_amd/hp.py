@@ -103,6 +103,8 @@ _lib.hp_xc_kernel.argtypes = [C.c_int32, C.c_int64, _dp, _dp]
 _lib.hp_xc_kernel.restype = C.c_int32
 _lib.hp_apply_h_lowp.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _dp, _dp]
 _lib.hp_apply_h_lowp.restype = C.c_int32
+_lib.hp_apply_h_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp]
+_lib.hp_apply_h_noalloc.restype = C.c_int32
 
 
 
@@ -131,7 +133,7 @@ EXPORTED = ["hp_ground_state_load", "hp_sternheimer_scf", "hp_response_matrix", 
             "hp_destroy", "hp_last_error", "hp_apply_h", "hp_solve_first_order", "hp_profile_start",
             "hp_profile_stop", "hp_tuning_report", "hp_set_gemm_shape", "hp_set_plane_variant",
             "hp_neighbours", "hp_set_stick_variant", "hp_site_occupations", "hp_xc_kernel",
-            "hp_apply_h_lowp"]
+            "hp_apply_h_lowp", "hp_apply_h_noalloc"]
 
 
 def hp_last_error() -> str:
@@ -422,6 +424,21 @@ def hp_apply_h_lowp(ctx: Context, entry: int, x: np.ndarray, lowp_gemm: int = HP
     _check(_lib.hp_apply_h_lowp(ctx.handle, int(entry), x.shape[0], int(lowp_gemm), _ptr(x.view(np.float64)),
                                 _ptr(y.view(np.float64))), allow_warn=False)
     return y
+
+
+def hp_apply_h_noalloc(ctx: Context, entry: int, x, y) -> None:
+    """y = H_k x on device arrays with no allocation: x, y contiguous complex128 GPU tensors
+    of shape (n, npw) (entry's plane-wave order).  Enqueued on the context's stream; returns
+    without waiting (synchronize before reading y)."""
+    if not (_is_device(x) and _is_device(y)):
+        raise ValueError("x and y must be GPU tensors")
+    n = int(x.shape[0])
+    npw = ctx.npw[entry] if 0 <= entry < len(ctx.npw) else 0
+    if tuple(x.shape) != (n, npw) or tuple(y.shape) != (n, npw):
+        raise ValueError(f"x and y must have the shape (n, {npw})")
+    xp = _dev_ptr(x, "complex128", n * npw)
+    yp = _dev_ptr(y, "complex128", n * npw)
+    _check(_lib.hp_apply_h_noalloc(ctx.handle, int(entry), n, xp, yp), allow_warn=False)
 
 
 def hp_xc_kernel(rho: np.ndarray) -> np.ndarray:

@@ -69,6 +69,8 @@ def parse():
                     help="CG iterations per captured hipGraph launch in the main forms (0: launch kernels one by "
                          "one, timed with HIP events)")
     ap.add_argument("--verbosity", type=int, default=0, help="1: one line per SCF iteration on stderr")
+    ap.add_argument("--cache-ground-state", action="store_true",
+                    help="write a newly built ground state to the on-disk cache for later runs")
     ap.add_argument("--full-response", action="store_true",
                     help="also run the whole response (hp_response_matrix over every pair, then U/V) once per form "
                          "and report its wall time, status and the chi and U/V differences from the FP64 form")
@@ -205,7 +207,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t0 = time.time()
-    gs = cache.get(args.config)
+    gs = cache.get(args.config, save_built=args.cache_ground_state)
     t_gen = time.time() - t0
     print(f"[bench] ground state {gs.spec.name} ready ({t_gen:.1f} s)", file=sys.stderr, flush=True)
     load_kw = {}

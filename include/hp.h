@@ -391,7 +391,7 @@ hp_status hp_set_plane_variant(hp_ctx *c, int32_t prec, int32_t variant);
 /* z-transform variants (inverse: sphere -> sticks, forward: sticks -> sphere):
  * 0 = a workgroup per 32 sticks, 1 = a thread per stick (N3 = 24 or 40 only), 2 = a thread
  * per stick with the workgroup's plane waves staged through LDS (N3 = 24 or 40, when the
- * plane waves of 256 sticks fit in 64 KB).  The three give identical results. */
+ * plane waves of 256 sticks fit in 96 KB).  The three give identical results. */
 hp_status hp_set_stick_variant(hp_ctx *c, int32_t prec, int32_t inverse_variant, int32_t forward_variant);
 
 #ifdef __cplusplus

@@ -1122,10 +1122,10 @@ hp_status tune_plane(hp_ctx *c, int prec, int nk) {
 
 // z transforms: a workgroup per 32 sticks, or a thread per stick (same sums, same order).
 // z-transform variants available: the register ones need a compile-time N3 (24 or 40) and
-// the staged one the plane waves of 256 sticks in LDS (at most 64 KB here).
+// the staged one the plane waves of 256 sticks in LDS (at most 96 KB here, FP64 sizes).
 int stick_variants(const hp_ctx *c) {
   if (c->n3 != 24 && c->n3 != 40) return 1;
-  return (size_t)c->sk.max_pw256 * (sizeof(double2) + sizeof(int)) + c->n3 * sizeof(double2) <= 64 * 1024 ? 3 : 2;
+  return (size_t)c->sk.max_pw256 * (sizeof(double2) + sizeof(int)) + c->n3 * sizeof(double2) <= 96 * 1024 ? 3 : 2;
 }
 
 hp_status tune_stick(hp_ctx *c, int prec, int nk) {

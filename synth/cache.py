@@ -71,9 +71,9 @@ def load(name: str):
                          hub_pot=z["hub_pot"] if "hub_pot" in z.files else None)
 
 
-def get(name: str, device: str = "auto", verbose: bool = None):
+def get(name: str, device: str = "auto", verbose: bool = None, save_built: bool = True):
     """Cached ground state of a named workload, generated on first use (progress on stderr
-    for the large systems)."""
+    for the large systems); save_built=False skips writing a newly built one to disk."""
     gs = load(name)
     if gs is not None:
         return gs
@@ -96,5 +96,6 @@ def get(name: str, device: str = "auto", verbose: bool = None):
             sys.stdout = _stdout
     if verbose:
         print(f"[synth] built {name} on {device} in {time.time() - t:.1f} s", file=sys.stderr, flush=True)
-    save(gs)
+    if save_built:
+        save(gs)
     return gs

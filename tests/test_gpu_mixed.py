@@ -98,3 +98,21 @@ def test_mixed_response_matrix_and_uv(lowp):
     assert rel(chi0, c0) < 1e-6 and rel(chi, c1) < 1e-6
     uv = hp.hp_hubbard_params(chi0, chi)
     assert np.abs(uv - oracle.hubbard_params(c0, c1)).max() * HA_MEV < 5.0
+
+
+@pytest.mark.parametrize("lowp,bar", [(0, 2e-6), (1, 2e-2), (2, 2e-2)])
+def test_lowp_operator_accuracy(lowp, bar):
+    """The inner solves' operator itself (hp_apply_h_lowp: FP32 transforms and V psi; FP32,
+    BF16, or BF16 KB with FP32 P_v projections) against the FP64 oracle on every entry:
+    FP32 to ~1e-6, BF16 to its 8-bit mantissa (~4e-3)."""
+    hp = _hp()
+    name = "duo_k221"
+    o = oracle.Oracle(ground_state(name))
+    rng = np.random.default_rng(9)
+    worst = 0.0
+    for ie, e in enumerate(o.kpts):
+        X = rng.standard_normal((4, e.npw)) + 1j * rng.standard_normal((4, e.npw))
+        Y = hp.hp_apply_h_lowp(ctx(name), ie, X, lowp)
+        ref = o.h_apply(ie, X)
+        worst = max(worst, np.abs(Y - ref).max() / np.abs(ref).max())
+    assert worst < bar, worst

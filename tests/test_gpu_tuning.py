@@ -112,7 +112,7 @@ def test_pinning_rejects_bad_shapes():
     with pytest.raises(hp.HpError):
         hp.hp_set_plane_variant(ctx, 64, 1)   # 24x24 planes: only variant 0
     with pytest.raises(hp.HpError):
-        hp.hp_set_stick_variant(ctx, 64, 2, 0)
+        hp.hp_set_stick_variant(ctx, 64, 3, 0)
 
 
 @pytest.mark.parametrize("name", ["sc1_gamma", "duo_k221", "olivine28_gamma", "olivine56_gamma"])

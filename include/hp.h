@@ -181,6 +181,12 @@ typedef struct hp_scf_params {
   int32_t skip_equivalence_q; /* hp_response_matrix: 0 (paper default) solves only one */
                           /* q of each (q, -q) pair of the mesh and takes             */
                           /* chi(-q) = conj chi(q) (time reversal); 1 solves every q   */
+  double lowp_trust_tol;  /* HP_MIXED, FP32 GEMMs: Sternheimer solves whose tolerance   */
+                          /* is at or above this are finished in FP32 with no FP64     */
+                          /* refinement, and their right-hand sides and response     */
+                          /* density are formed in FP32 too (the adaptive SCF         */
+                          /* tolerance of later iterations); 0 = the default 1e-6;    */
+                          /* 1 or more refines every solve in FP64 (negative: error)  */
 } hp_scf_params;
 
 /* Statistics of one call (all fields written when the pointer is not NULL). */
@@ -383,7 +389,10 @@ hp_status hp_tuning_report(hp_ctx *c, char *buf, int32_t len);
  * expansion workgroup.  Plane variant 0..3 of the local-potential FFT round trip
  * (0: one z plane per 256-thread workgroup, 1: two per 256, 2: two per 512, 3: one
  * plane with the twiddles read from global memory; 1-3 only for 72x45, 144x45 and
- * 30x24 planes, 1-2 only for even N3 with two planes fitting in LDS).  Errors:
+ * 30x24 planes, 1-2 only for even N3 with two planes fitting in LDS; 4, 5, 6: prec 32
+ * only, whole lines in registers with LDS only for the two transposes, on 128, 192 or
+ * 256 threads holding as many z planes as their lines fill, for 24x24, 30x24, 48x24,
+ * 48x48, 72x45 and 144x45 planes).  Errors:
  * HP_ERR_ARG for values out of range or variants not available for the grid. */
 hp_status hp_set_gemm_shape(hp_ctx *c, int32_t prec, int32_t rows, int32_t batch, int32_t tile, int32_t nsplit,
                             int32_t expand_bands);

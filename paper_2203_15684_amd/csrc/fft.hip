@@ -1032,6 +1032,13 @@ __device__ __forceinline__ void rstages_half(C *h, const C *__restrict__ tw, int
   }
 }
 
+// Register-resident variants: the window [0, W) u [N - W, N) of x columns and y rows that
+// may hold sphere points (even W near N / 3; a grid of at least four times the sphere's
+// radius keeps the sphere inside it), and the LDS header (the active column list).
+__host__ __device__ constexpr int reg_win(int n) { return ((n + 5) / 6) * 2; }
+__host__ __device__ constexpr int reg_lds_header_c(int n1) { return ((n1 * 4 + 15) / 16) * 16; }
+__host__ __device__ constexpr int reg_cols(int n1) { return 2 * reg_win(n1) < n1 ? 2 * reg_win(n1) : n1; }
+
 // Rows of the plane (x lines) handled by one lane, or by a lane pair for long lines.
 template <int N1>
 struct RowSplit {
@@ -1041,87 +1048,91 @@ struct RowSplit {
 };
 
 // Workgroup of NT threads: npb consecutive z planes of one band item (set by the launcher
-// so that the lines fill the threads).  LDS holds the list of active x columns and the
-// planes, [plane][N1][N2 | 1] (an odd row stride keeps both the column and the row accesses
-// free of bank conflicts; inactive columns stay zero, so a row is read and written at fixed
-// offsets with no per-x bookkeeping).
+// so that the lines fill the threads).  Only the x columns and y rows of the window
+// [0, W) u [N - W, N) (reg_win) can hold sphere points (the launcher checks every entry's
+// Miller range, shifted by the k+q pairs' g0, against it), so LDS keeps the planes compacted
+// to the NC = 2 WX window columns, [plane][NC][N2 | 1] (an odd row stride keeps the column
+// and the row accesses free of bank conflicts), after the list of active columns.  Outside
+// the window the row and column inputs are zeros known at compile time (not loaded) and
+// their outputs are not needed (not computed back).
 template <int N1, int N2, int NT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_plane_vloc_r(Plane pl, Sticks sk, const KPair *kp, int use_kq, int nb,
                                                      int npb, const float2 *__restrict__ Sin,
                                                      float2 *__restrict__ Sout, int ns_pad,
                                                      const float *__restrict__ vp, const int *active) {
   using C = float2;
-  constexpr int N2S = N2 | 1, PS = N1 * N2S;
+  constexpr int N2S = N2 | 1;
+  constexpr int WX = reg_win(N1), WY = reg_win(N2);
+  constexpr int NC = 2 * WX < N1 ? 2 * WX : N1, XOFF = N1 - NC;  // window column of x >= N1 - WX: x - XOFF
+  constexpr bool YCUT = 2 * WY < N2;
+  constexpr int PS = NC * N2S;
   constexpr int RS = RowSplit<N1>::RS, H = RowSplit<N1>::H;
   constexpr int NS1 = cnst(N1), NS2 = cnst(N2);
-  constexpr int NW = (N1 + 63) / 64;
   static_assert(H <= 72 && N2 <= 72, "line too long for registers");
+  static_assert(RS == 1 || (WX % 2 == 0 && XOFF % 2 == 0), "a split row needs an even window");
   extern __shared__ __align__(16) unsigned char lds[];
-  int *colx = reinterpret_cast<int *>(lds);  // [N1]: flags, then the active x in order
-  C *P = reinterpret_cast<C *>(lds + ((N1 * 4 + 15) / 16) * 16);
+  int *colc = reinterpret_cast<int *>(lds);  // [NC]: window column of each active x
+  C *P = reinterpret_cast<C *>(lds + reg_lds_header_c(N1));
   const int item = blockIdx.y;
   if (active && !active[item]) return;
   const int k = item / nb;
   int e, g0x, g0y, g0z;
   basis_of(kp, k, use_kq, e, g0x, g0y, g0z);
   const EntryDev E = sk.ent[e];
-  const int nxa = E.nxa, ns = E.ns;
+  const int nxa = min(E.nxa, NC), ns = E.ns;
   const int z0 = blockIdx.x * npb;
   const int npl = min(npb, pl.n3 - z0);
   const C *twx = pl.ax.tw32, *twy = pl.ay.tw32;
-  for (int t = threadIdx.x; t < N1; t += NT) colx[t] = 0;
-  for (int i = threadIdx.x; i < npl * PS; i += NT) P[i] = czero<C>();
-  __syncthreads();
-  const int *xa = sk.xa + E.xa_off;
-  for (int i = threadIdx.x; i < nxa; i += NT) colx[wrap(xa[i] - g0x, N1)] = 1;
-  __syncthreads();
-  if (threadIdx.x < 64) {  // the active x in increasing order (ballot prefix counts)
-    int base = 0, xs[NW], rk[NW];
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      const int x = 64 * w + (int)threadIdx.x;
-      const int f = x < N1 ? colx[x] : 0;
-      const unsigned long long b = __ballot(f);
-      xs[w] = f ? x : -1;
-      rk[w] = base + __popcll(b & ((1ull << threadIdx.x) - 1ull));
-      base += __popcll(b);
-    }
-    // (every lane of this one wave has read its flags above)
-#pragma unroll
-    for (int w = 0; w < NW; ++w)
-      if (xs[w] >= 0) colx[rk[w]] = xs[w];
+  // window column of grid x (x in the window; -1 outside, which the launcher rules out)
+  auto wcol = [](int x) { return x < WX ? x : (x >= N1 - WX ? x - XOFF : -1); };
+  {
+    float4 *P4 = reinterpret_cast<float4 *>(P);  // PS * npl float2, an even count when npl is even
+    const int n4 = (npl * PS) / 2;
+    for (int i = threadIdx.x; i < n4; i += NT) P4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if ((npl * PS) & 1)
+      if (threadIdx.x == 0) P[npl * PS - 1] = czero<C>();
   }
+  const int *xa = sk.xa + E.xa_off;
+  for (int i = threadIdx.x; i < nxa; i += NT) colc[i] = wcol(wrap(xa[i] - g0x, N1));
   __syncthreads();
   const int *sx = sk.sx + E.st_off;
   const int *sy = sk.sy + E.st_off;
   const size_t so = ((size_t)item * pl.n3 + z0) * ns_pad;
   for (int w = threadIdx.x; w < npl * ns; w += NT) {
     const int p = w / ns, s = w - p * ns;
-    P[p * PS + wrap(sx[s] - g0x, N1) * N2S + wrap(sy[s] - g0y, N2)] = Sin[so + (size_t)p * ns_pad + s];
+    const int c = wcol(wrap(sx[s] - g0x, N1));
+    if (c >= 0) P[p * PS + c * N2S + wrap(sy[s] - g0y, N2)] = Sin[so + (size_t)p * ns_pad + s];
   }
   __syncthreads();
-  // y columns, forward (DIF): natural order in, digit-reversed out
+  // y columns, forward (DIF): natural order in (zeros outside the y window), digit-reversed out
   for (int w = threadIdx.x; w < npl * nxa; w += NT) {
     const int p = w / nxa;
-    C *col = P + p * PS + colx[w - p * nxa] * N2S;
+    const int c = colc[w - p * nxa];
+    if (c < 0) continue;
+    C *col = P + p * PS + c * N2S;
     C y[N2];
 #pragma unroll
-    for (int i = 0; i < N2; ++i) y[i] = col[i];
+    for (int i = 0; i < N2; ++i) y[i] = (!YCUT || i < WY || i >= N2 - WY) ? col[i] : czero<C>();
     rstages<N2, 0, NS2, true>(y, twy);
 #pragma unroll
     for (int i = 0; i < N2; ++i) col[i] = y[i];
   }
   __syncthreads();
-  // x rows: forward, times V (digit-reversed x and y), inverse
+  // x rows: forward, times V (digit-reversed x and y), inverse.  This lane holds the points
+  // x = RS u + par of row r: window columns are read and written at fixed offsets, the
+  // rest are zeros in and unused out.
   const float *vz = vp + ((size_t)kp[k].spin * pl.n3 + z0) * (N1 * N2);
   for (int w = threadIdx.x; w < npl * N2 * RS; w += NT) {
     const int p = w / (N2 * RS), rem = w - p * (N2 * RS);
     const int r = rem / RS, par = rem - r * RS;
-    C *row = P + p * PS + par * N2S + r;  // this lane's points x = RS u + par
+    C *row = P + p * PS + par * N2S + r;
     const float *v = vz + (size_t)p * (N1 * N2) + r;
     C h[H];
 #pragma unroll
-    for (int u = 0; u < H; ++u) h[u] = row[u * RS * N2S];
+    for (int u = 0; u < H; ++u) {
+      const int x0 = RS * u;  // x = x0 + par; the window test is the same for both parities
+      h[u] = x0 < WX ? row[x0 * N2S] : (x0 >= N1 - WX ? row[(x0 - XOFF) * N2S] : czero<C>());
+    }
     // V is read in groups of G values, one group ahead of its use: without the schedule
     // barriers the compiler issues all H loads at once and the row no longer fits the
     // register file
@@ -1156,7 +1167,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
       rstages<N1, 0, NS1 - 1, false>(h, twx);
     } else {
       rstages_half<N1, 0, NS1 - 1, true>(h, twx, par);
-      // last stage: radix 2 over the pair (2u, 2u + 1) = (this lane, partner) or reverse
+      // last stage: radix 2 over the pair (2u, 2u + 1) = (this lane o, partner q).  With
+      // sg = +1 on the even lane and -1 on the odd one, the even lane's output is o + q and
+      // the odd lane's q - o: sg o + q, both directions.
+      const float sg = par ? -1.f : 1.f;
 #pragma unroll
       for (int b = 0; b < H / G; ++b) {
         if (b + 1 < H / G) {
@@ -1168,17 +1182,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         for (int t = 0; t < G; ++t) {
           const int u = b * G + t;
           const C o = h[u];
-          C q;
-          q.x = lane_xor1(o.x);
-          q.y = lane_xor1(o.y);
-          const C a = par ? q : o, bb = par ? o : q;
-          C y = par ? csub(a, bb) : cadd(a, bb);
-          y = cscale(y, vb[t]);
-          C q2;
-          q2.x = lane_xor1(y.x);
-          q2.y = lane_xor1(y.y);
-          const C a2 = par ? q2 : y, b2 = par ? y : q2;
-          h[u] = par ? csub(a2, b2) : cadd(a2, b2);
+          C y;
+          y.x = fmaf(sg, o.x, lane_xor1(o.x)) * vb[t];
+          y.y = fmaf(sg, o.y, lane_xor1(o.y)) * vb[t];
+          C z;
+          z.x = fmaf(sg, y.x, lane_xor1(y.x));
+          z.y = fmaf(sg, y.y, lane_xor1(y.y));
+          h[u] = z;
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -1187,24 +1197,34 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
       rstages_half<N1, 0, NS1 - 1, false>(h, twx, par);
     }
 #pragma unroll
-    for (int u = 0; u < H; ++u) row[u * RS * N2S] = h[u];
+    for (int u = 0; u < H; ++u) {
+      const int x0 = RS * u;
+      if (x0 < WX)
+        row[x0 * N2S] = h[u];
+      else if (x0 >= N1 - WX)
+        row[(x0 - XOFF) * N2S] = h[u];
+    }
   }
   __syncthreads();
-  // y columns, inverse: digit-reversed in, natural out
+  // y columns, inverse: digit-reversed in, natural out (only the y window is gathered)
   for (int w = threadIdx.x; w < npl * nxa; w += NT) {
     const int p = w / nxa;
-    C *col = P + p * PS + colx[w - p * nxa] * N2S;
+    const int c = colc[w - p * nxa];
+    if (c < 0) continue;
+    C *col = P + p * PS + c * N2S;
     C y[N2];
 #pragma unroll
     for (int i = 0; i < N2; ++i) y[i] = col[i];
     rstages<N2, 0, NS2, false>(y, twy);
 #pragma unroll
-    for (int i = 0; i < N2; ++i) col[i] = y[i];
+    for (int i = 0; i < N2; ++i)
+      if (!YCUT || i < WY || i >= N2 - WY) col[i] = y[i];
   }
   __syncthreads();
   for (int w = threadIdx.x; w < npl * ns; w += NT) {
     const int p = w / ns, s = w - p * ns;
-    Sout[so + (size_t)p * ns_pad + s] = P[p * PS + wrap(sx[s] - g0x, N1) * N2S + wrap(sy[s] - g0y, N2)];
+    const int c = wcol(wrap(sx[s] - g0x, N1));
+    Sout[so + (size_t)p * ns_pad + s] = c >= 0 ? P[p * PS + c * N2S + wrap(sy[s] - g0y, N2)] : czero<C>();
   }
 }
 
@@ -1679,7 +1699,15 @@ constexpr int kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 
 // Register-resident variants: threads per workgroup, and the LDS header before the planes.
 constexpr int kRegThreads[3] = {128, 192, 256};
-int reg_lds_header(int n1) { return ((n1 * 4 + 15) / 16) * 16; }
+int reg_lds_header(int n1) { return reg_lds_header_c(n1); }
+size_t reg_plane_bytes(const Plane &pl) { return (size_t)reg_cols(pl.n1) * (pl.n2 | 1) * sizeof(float2); }
+// Every entry's sphere, shifted by the current pairs' g0, inside the window on x and y.
+bool reg_window_ok(const Plane &pl) {
+  const int w[2] = {reg_win(pl.n1), reg_win(pl.n2)}, n[2] = {pl.n1, pl.n2};
+  for (int a = 0; a < 2; ++a)
+    if (2 * w[a] < n[a] && pl.mext[a] + pl.g0ext[a] > w[a]) return false;
+  return true;
+}
 int reg_row_lanes(const Plane &pl) {
   int n = pl.n1, ns = 0, last = 1;
   for (; n > 1; ++ns) {
@@ -1694,7 +1722,7 @@ int reg_planes(const Plane &pl, int variant) {
   const int nt = kRegThreads[variant - 4];
   const int lines = std::max(std::max(pl.nxa_max, 1), pl.n2 * reg_row_lanes(pl));
   int pb = std::max(1, std::min(nt / lines, pl.n3));
-  const size_t per = (size_t)pl.n1 * (pl.n2 | 1) * sizeof(float2);
+  const size_t per = reg_plane_bytes(pl);
   while (pb > 1 && reg_lds_header(pl.n1) + pb * per > (size_t)kLdsBytes) --pb;
   return pb;
 }
@@ -1707,8 +1735,8 @@ bool plane_vloc_variant_ok(const Plane &pl, int csize, int variant) {
   if (variant == 3) return shape;
   if (variant >= 4 && variant <= 6) {
     const bool ct = key == 24024 || key == 30024 || key == 48024 || key == 48048 || key == 72045 || key == 144045;
-    const size_t lds = reg_lds_header(pl.n1) + (size_t)reg_planes(pl, variant) * pl.n1 * (pl.n2 | 1) * sizeof(float2);
-    return csize == (int)sizeof(float2) && ct && pl.nxa_max >= 1 && lds <= (size_t)kLdsBytes;
+    const size_t lds = reg_lds_header(pl.n1) + (size_t)reg_planes(pl, variant) * reg_plane_bytes(pl);
+    return csize == (int)sizeof(float2) && ct && pl.nxa_max >= 1 && lds <= (size_t)kLdsBytes && reg_window_ok(pl);
   }
   return false;
 }
@@ -1742,7 +1770,7 @@ hipError_t plane_vloc_reg(int variant, const Plane &pl, const Sticks &sk, const 
                           int nitems, const float2 *Sin, float2 *Sout, int ns_pad, const float *vp, const int *active,
                           hipStream_t st) {
   const int pb = reg_planes(pl, variant);
-  const size_t lds = reg_lds_header(N1) + (size_t)pb * N1 * (N2 | 1) * sizeof(float2);
+  const size_t lds = reg_lds_header(N1) + (size_t)pb * reg_plane_bytes(pl);
   const dim3 grid((pl.n3 + pb - 1) / pb, nitems);
   switch (kRegThreads[variant - 4]) {
     case 128:

@@ -198,6 +198,12 @@ struct hp_ctx {
   int lowp_gemm = 0;        // hp_scf_params.lowp_gemm of the current call
   float *vp32 = nullptr;
   float2 *X32 = nullptr, *R32 = nullptr, *B32 = nullptr, *P32 = nullptr, *AP32 = nullptr;
+  // FP64 A X of the mixed solves' refinement residuals.  ax_valid: it holds A X for the
+  // current X (the last solve ended on an FP64 residual); the next warm start of the same
+  // operator then reuses it instead of applying A again.  Cleared by every solve that
+  // does not end that way.
+  double2 *AX = nullptr;
+  bool ax_valid = false;
   double *bn_in = nullptr, *rn_in = nullptr, *rz_in = nullptr, *floor_in = nullptr;
   int *act_in = nullptr, *act_out = nullptr;
   Plane pl32{};
@@ -272,6 +278,7 @@ constexpr int kNmixMax = 8;
 // Sternheimer tolerance of SCF iteration i > 1: kAdaptiveTol x (mixing residual of i-1).
 constexpr double kAdaptiveTol = 1e-2;
 // Mixed precision: outer tolerances at or above this are met by the FP32 inner solve alone.
+// Default of hp_scf_params.lowp_trust_tol.
 constexpr double kFp32TrustTol = 1e-6;
 
 enum KernelId {
@@ -507,6 +514,7 @@ bool inv_sqrt_hermitian(int n, const std::complex<double> *O, std::complex<doubl
 struct Layout {
   std::vector<int> order;         // internal -> caller
   std::vector<int> sx, sy, sstart, slen, iz, xa;
+  int mext[2] = {0, 0};           // x, y: max(m + 1, -m) over the plane waves
 };
 
 hp_status build_layout(const hp_kpoint &k, int n1, int n2, int n3, Layout &L, int idx) {
@@ -520,6 +528,7 @@ hp_status build_layout(const hp_kpoint &k, int n1, int n2, int n3, Layout &L, in
     }
   }
   const int N[3] = {n1, n2, n3};
+  for (int d = 0; d < 2; ++d) L.mext[d] = npw > 0 ? std::max(mx[d] + 1, -mn[d]) : 0;
   for (int d = 0; d < 3; ++d)
     if (mx[d] - mn[d] + 1 > N[d])
       return fail(HP_ERR_SHAPE, "kpts[%d]: sphere spans %d along axis %d, grid has %d", idx, mx[d] - mn[d] + 1, d, N[d]);
@@ -848,6 +857,7 @@ hp_status cg_solve(hp_ctx *c, const KPair *kp, int nk, const double *eps_items, 
                    int *iters, int *not_conv, double *max_rel, long *happ) {
   const int nb = c->n_occ, nitems = nk * nb;
   const int rows = c->n_beta + c->n_occ;
+  c->ax_valid = false;  // X changes below
   if (warm) HPTRY(apply_op(c, kp, 1, nk, nb, c->X, c->AP, eps_items, rows));
   if (warm) *happ += nitems;
   HPCHK(timed(c, K_CG_INIT, [&] {
@@ -899,6 +909,8 @@ hp_status setup32(hp_ctx *c) {
     HPTRY(c->alloc(b, vec));
     HPCHK(hipMemsetAsync(*b, 0, sizeof(float2) * vec, c->stream));
   }
+  HPTRY(c->alloc(&c->AX, vec));
+  c->ax_valid = false;
   HPTRY(c->alloc(&c->bn_in, nitems));
   HPTRY(c->alloc(&c->rn_in, nitems));
   HPTRY(c->alloc(&c->rz_in, nitems));
@@ -1192,8 +1204,8 @@ hp_status autotune(hp_ctx *c, int nk, int mixed) {
 // Mixed precision: FP64 residual refinement around FP32 PCG inner solves.
 //   r = B - A64 X ; while some ||r|| > tol ||B||: solve A32 d = r to inner_tol in FP32, X += d, recompute r.
 hp_status cg_solve_mixed(hp_ctx *c, const KPair *kp, int nk, const double *eps_items, int warm, double tol,
-                         int max_it, double inner_tol, int max_refine, int *iters, int *not_conv, double *max_rel,
-                         long *happ64, long *happ32, int *refines) {
+                         int max_it, double inner_tol, int max_refine, double trust_tol, int *iters,
+                         int *not_conv, double *max_rel, long *happ64, long *happ32, int *refines) {
   const int nb = c->n_occ, nitems = nk * nb;
   const int rows = c->n_beta + c->n_occ;
   HPTRY(setup32(c));
@@ -1201,27 +1213,35 @@ hp_status cg_solve_mixed(hp_ctx *c, const KPair *kp, int nk, const double *eps_i
   int it_in = 0, nact = 0, ref = 0;
   bool trusted = false;
   int h_count[kCntStep] = {0};
-  // Above kFp32TrustTol the FP32 operator (FP32 GEMMs) is accurate to ~1e-7 of |A X| ~ |B|,
-  // far below the tolerance: the warm-start residual then comes from it, and the inner
-  // solve's own residual stands for the final one (no FP64 operator apply at all).
-  const bool trust = c->lowp_gemm == HP_GEMM_FP32 && tol >= kFp32TrustTol;
+  // At or above trust_tol (default 1e-6) the FP32 operator (FP32 GEMMs) is accurate to
+  // ~1e-7 of |A X| ~ |B|, far below the tolerance: the warm-start residual then comes from
+  // it, and the inner solve's own residual stands for the final one (no FP64 operator
+  // apply at all).
+  const bool trust = c->lowp_gemm == HP_GEMM_FP32 && tol >= trust_tol;
+  // A warm start whose X is the last solve's final one, which ended on an FP64 residual:
+  // A X is already in c->AX (the same operator, bit for bit the same product).
+  const bool reuse_ax = warm && c->ax_valid;
+  c->ax_valid = false;
+  bool ax_fresh = false;  // c->AX = A X for the current X
   for (ref = 0; ref <= max_refine; ++ref) {
     const int have_x = warm || ref > 0;
-    const bool ax32 = have_x && trust && ref == 0;
+    const bool reused = have_x && ref == 0 && reuse_ax;
+    const bool ax32 = have_x && trust && ref == 0 && !reused;
     if (ax32) {
       HPCHK(launch_to_f32((const double *)c->X, (float *)c->X32, 2L * nitems * c->ld, c->stream));
       HPTRY(apply_op32(c, kp, nk, nb, c->X32, c->AP32, eps_items, rows, nullptr));
       *happ32 += nitems;
-    } else if (have_x) {
-      HPTRY(apply_op(c, kp, 1, nk, nb, c->X, c->AP, eps_items, rows));
+    } else if (have_x && !reused) {
+      HPTRY(apply_op(c, kp, 1, nk, nb, c->X, c->AX, eps_items, rows));
       *happ64 += nitems;
     }
+    ax_fresh = have_x && !ax32;
     HPCHK(launch_fill_int(c->count, kCntStep, 0, c->stream));
     HPCHK(timed(c, K_RESIDUAL64, [&] {
       if (ax32)
         return launch_residual64_ax32(kp, nb, nitems, c->B, c->AP32, c->R, c->B32, c->ld, c->d_npw, c->bn, c->rn,
                                       c->act_out, tol, c->count + kCntResid, c->floor_in, c->stream);
-      return launch_residual64(kp, nb, nitems, c->B, c->AP, have_x, c->R, c->B32, c->ld, c->d_npw, c->bn, c->rn,
+      return launch_residual64(kp, nb, nitems, c->B, c->AX, have_x, c->R, c->B32, c->ld, c->d_npw, c->bn, c->rn,
                                c->act_out, tol, c->count + kCntResid, c->floor_in, c->stream);
     }));
     HPCHK(hipMemcpyAsync(h_count, c->count, kCntStep * sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -1256,6 +1276,7 @@ hp_status cg_solve_mixed(hp_ctx *c, const KPair *kp, int nk, const double *eps_i
     HPCHK(timed(c, K_REFINE, [&] {
       return launch_refine_update(nb, nitems, c->X, c->X32, c->ld, c->act_out, have_x, c->stream);
     }));
+    ax_fresh = false;
     // Above ~1e-6 the FP32 operator is exact enough that the inner solve's own residual
     // stands for the FP64 one; the next SCF iteration starts from an FP64 residual anyway.
     if (trust && inner_active == 0) {
@@ -1265,6 +1286,7 @@ hp_status cg_solve_mixed(hp_ctx *c, const KPair *kp, int nk, const double *eps_i
       break;
     }
   }
+  c->ax_valid = ax_fresh;
   *iters = it_in;
   *refines = ref;
   *not_conv = nact;
@@ -1306,6 +1328,13 @@ hp_status upload_pairs(hp_ctx *c, int site, const double q[3], std::vector<KPair
     if (P.ej < 0)
       return fail(HP_ERR_SHAPE, "no loaded entry holds k+q for mesh point %d, q = (%g, %g, %g)", k, q[0], q[1], q[2]);
     pairs.push_back(P);
+  }
+  // the largest shift of a k+q basis, for the plane variants that assume a bounded sphere
+  for (int d = 0; d < 2; ++d) {
+    int g = 0;
+    for (const KPair &P : pairs) g = std::max(g, std::abs(P.g0[d]));
+    c->pl.g0ext[d] = g;
+    c->pl32.g0ext[d] = g;
   }
   HPCHK(hipMemcpyAsync(c->d_kp, pairs.data(), sizeof(KPair) * pairs.size(), hipMemcpyHostToDevice, c->stream));
   return HP_OK;
@@ -1491,6 +1520,7 @@ hp_status check_params(const hp_scf_params *p) {
     return fail(HP_ERR_ARG, "find_atpert must be 1 or 4 (0 = 4)");
   if (p->find_atpert == 1 && (!(p->docc_thr >= 0.0) || !(p->dist_thr >= 0.0)))
     return fail(HP_ERR_ARG, "docc_thr and dist_thr must be >= 0");
+  if (!(p->lowp_trust_tol >= 0.0)) return fail(HP_ERR_ARG, "lowp_trust_tol must be >= 0 (0: the default 1e-6)");
   return HP_OK;
 }
 
@@ -1899,7 +1929,12 @@ extern "C" hp_status hp_ground_state_load(const hp_ground_state *gs, hp_ctx **ou
   c->pl.n2 = c->n2;
   c->pl.n3 = c->n3;
   c->pl.nxa_max = 0;
-  for (int i = 0; i < gs->n_kpts; ++i) c->pl.nxa_max = std::max(c->pl.nxa_max, (int)lay[i].xa.size());
+  c->pl.mext[0] = c->pl.mext[1] = 0;
+  c->pl.g0ext[0] = c->pl.g0ext[1] = 0;
+  for (int i = 0; i < gs->n_kpts; ++i) {
+    c->pl.nxa_max = std::max(c->pl.nxa_max, (int)lay[i].xa.size());
+    for (int d = 0; d < 2; ++d) c->pl.mext[d] = std::max(c->pl.mext[d], lay[i].mext[d]);
+  }
   c->az = ax[2];
   if (c->np * (long)sizeof(double2) > 160 * 1024) return fail(HP_ERR_SHAPE, "xy plane does not fit in LDS");
   c->px = dif_perm(c->n1, rad[0]);
@@ -2278,9 +2313,10 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
     // the accuracy the response potential has reached (a fixed fraction of the last
     // mixing residual), never looser than 1e-3 nor tighter than cg_tol.
     const double tol_it = it == 1 ? p->cg_tol : std::max(p->cg_tol, std::min(1e-3, kAdaptiveTol * vres));
-    // Mixed form, iterations solved no tighter than kFp32TrustTol: the RHS product and the
+    // Mixed form, iterations solved no tighter than lowp_trust_tol: the RHS product and the
     // response density are accurate enough in FP32 (~1e-7 relative).
-    const bool lowp_it = p->precision == HP_MIXED && tol_it >= kFp32TrustTol;
+    const double trust_tol = p->lowp_trust_tol > 0.0 ? p->lowp_trust_tol : kFp32TrustTol;
+    const bool lowp_it = p->precision == HP_MIXED && tol_it >= trust_tol;
     HPCHK(hipEventRecord(c->ev[0], c->stream));
     HPTRY(build_rhs(c, c->d_kp, nk, site, it > 1 ? c->dvin : nullptr, c->d_psi, lowp_it));
     HPCHK(hipEventRecord(c->ev[1], c->stream));
@@ -2288,6 +2324,7 @@ hp_status run_scf(hp_ctx *c, int site, const double q[3], const hp_scf_params *p
     double mr = 0.0;
     if (p->precision == HP_MIXED) {
       HPTRY(cg_solve_mixed(c, c->d_kp, nk, c->d_eps, it > 1, tol_it, p->max_cg_iter, p->inner_tol, p->max_refine,
+                           trust_tol,
                            &iters, &nc, &mr, &happ, &happ32, &nref));
     } else {
       HPTRY(cg_solve(c, c->d_kp, nk, c->d_eps, it > 1, tol_it, p->max_cg_iter, &iters, &nc, &mr, &happ));
@@ -2816,7 +2853,8 @@ extern "C" hp_status hp_solve_first_order(hp_ctx *c, int32_t pert_site, const do
   double mr = 0.0;
   long happ = 0, happ32 = 0;
   if (p->precision == HP_MIXED) {
-    HPTRY(cg_solve_mixed(c, c->d_kp, 1, eps, 0, p->cg_tol, p->max_cg_iter, p->inner_tol, p->max_refine, &iters, &nc,
+    HPTRY(cg_solve_mixed(c, c->d_kp, 1, eps, 0, p->cg_tol, p->max_cg_iter, p->inner_tol, p->max_refine,
+                         p->lowp_trust_tol > 0.0 ? p->lowp_trust_tol : kFp32TrustTol, &iters, &nc,
                          &mr, &happ, &happ32, &nref));
   } else {
     HPTRY(cg_solve(c, c->d_kp, 1, eps, 0, p->cg_tol, p->max_cg_iter, &iters, &nc, &mr, &happ));

@@ -32,6 +32,8 @@ struct Plane {
   Axis ay;   // y = second grid index, length N2, stride 1
   int n1, n2, n3;
   int nxa_max;  // most active x columns (x holding sticks) of any entry
+  int mext[2];  // x and y: largest max(m + 1, -m) of any entry's Miller indices
+  int g0ext[2]; // x and y: largest |g0| of the current k+q pairs (0 before any)
 };
 
 // Per k-entry geometry (device arrays, flat with offsets).

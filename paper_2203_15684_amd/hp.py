@@ -68,7 +68,8 @@ class HpScfParams(C.Structure):
                 ("max_cg_iter", C.c_int32), ("precision", C.c_int32), ("verbosity", C.c_int32),
                 ("inner_tol", C.c_double), ("max_refine", C.c_int32), ("graph_chunk", C.c_int32),
                 ("autotune", C.c_int32), ("lowp_gemm", C.c_int32), ("find_atpert", C.c_int32),
-                ("docc_thr", C.c_double), ("dist_thr", C.c_double), ("skip_equivalence_q", C.c_int32)]
+                ("docc_thr", C.c_double), ("dist_thr", C.c_double), ("skip_equivalence_q", C.c_int32),
+                ("lowp_trust_tol", C.c_double)]
 
 
 class HpScfStats(C.Structure):
@@ -193,13 +194,14 @@ class ScfParams:
     docc_thr: float = 5e-5
     dist_thr: float = 6e-4
     skip_equivalence_q: int = 0   # 0: chi(-q) = conj chi(q) for the -q partners of the mesh
+    lowp_trust_tol: float = 1e-6  # mixed, FP32 GEMMs: solves this loose or looser skip FP64 refinement
 
     def c(self) -> HpScfParams:
         return HpScfParams(C.sizeof(HpScfParams), self.conv_thr_chi, self.conv_thr_v, self.cg_tol, self.niter_max,
                            self.alpha_mix, self.nmix, self.max_cg_iter, self.precision, self.verbosity,
                            self.inner_tol, self.max_refine, self.graph_chunk, self.autotune,
                            self.lowp_gemm, self.find_atpert, self.docc_thr, self.dist_thr,
-                           self.skip_equivalence_q)
+                           self.skip_equivalence_q, self.lowp_trust_tol)
 
 
 class Context:

@@ -100,3 +100,43 @@ def test_metal_q0_on_a_k_mesh_matches_oracle():
     d = hp.hp_sternheimer_scf(ctx(name), 1, (0, 0, 0), tight_gpu())
     assert d[3] == 0, d[2]
     assert rel(d[0], ref["dn0"]) < 1e-10 and rel(d[1], ref["dn"]) < 1e-10
+
+
+@functools.lru_cache(maxsize=None)
+def _full():
+    from synth import cache
+    g = cache.get("olivine28_metal")
+    return g, _hp().hp_ground_state_load(g)
+
+
+def test_metal_fullsize_first_order_one_k():
+    """Full olivine size, metallic (cold smearing, partially filled kept bands, 72x45x40):
+    one mesh k of the first SCF iteration at q = (0, 1/2, 0), all kept bands.  The GPU
+    solution satisfies the oracle's Sternheimer equation (the beta-weighted projection of the
+    metallic right-hand side) and equals the oracle's own CG solution."""
+    hp = _hp()
+    g, c = _full()
+    o = oracle.Oracle(g, cache_limit_bytes=1.0e9)
+    q = (0.0, 0.5, 0.0)
+    ik = 5
+    j, _ = o.kq_entry(ik, q)
+    du, st = hp.hp_solve_first_order(c, 1, q, ik, None, hp.ScfParams(cg_tol=1e-12, max_cg_iter=3000), g.kpts[j].npw)
+    assert st == 0
+    b = o.rhs(ik, q, 1, None)
+    r = o.sternheimer_op(ik, q, du) - b
+    assert np.linalg.norm(r, axis=1).max() / np.linalg.norm(b, axis=1).max() < 1e-10
+    x_ref, _ = o.solve(ik, q, b, None, oracle.ScfParams(cg_tol=1e-12))
+    assert rel(du, x_ref) < 1e-9
+
+
+def test_metal_fullsize_q0_pair_mixed_vs_fp64():
+    """Full olivine size, metallic, q = 0 (the Fermi-level shift enters): one (site, q) SCF in
+    both precisions converges, and the mixed form's response occupations match FP64's to
+    the mixed bar."""
+    hp = _hp()
+    g, c = _full()
+    base = dict(conv_thr_chi=1e-10, conv_thr_v=1e-8, cg_tol=1e-10, niter_max=100, max_cg_iter=3000)
+    d64 = hp.hp_sternheimer_scf(c, 0, (0.0, 0.0, 0.0), hp.ScfParams(**base, precision=hp.HP_FP64))
+    d32 = hp.hp_sternheimer_scf(c, 0, (0.0, 0.0, 0.0), hp.ScfParams(**base, precision=hp.HP_MIXED))
+    assert d64[3] == 0 and d32[3] == 0, (d64[2], d32[2])
+    assert rel(d32[0], d64[0]) < 1e-6 and rel(d32[1], d64[1]) < 1e-6

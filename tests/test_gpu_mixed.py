@@ -116,3 +116,25 @@ def test_lowp_operator_accuracy(lowp, bar):
         ref = o.h_apply(ie, X)
         worst = max(worst, np.abs(Y - ref).max() / np.abs(ref).max())
     assert worst < bar, worst
+
+
+def test_trust_tolerance_ablation():
+    """lowp_trust_tol: solves at or above it are finished in FP32 (no FP64 operator apply);
+    1 refines every solve in FP64.  Both meet the oracle at the mixed bar; refining every
+    solve performs more FP64 applies, and a negative value is rejected."""
+    hp = _hp()
+    name, site, q = "duo_k221", 1, (0, 0.5, 0)
+    ref = orc(name).scf(site, np.array(q), oracle.ScfParams(cg_tol=1e-13, conv_thr_chi=1e-13, conv_thr_v=1e-11))
+    applies = {}
+    for trust in (1e-6, 1.0):
+        p = mixed(1e-10, 1e-10)
+        p.lowp_trust_tol = trust
+        dn0, dn, st, status = hp.hp_sternheimer_scf(ctx(name), site, q, p)
+        assert status == 0
+        assert rel(dn0, ref["dn0"]) < 1e-6 and rel(dn, ref["dn"]) < 1e-6
+        applies[trust] = st["h_applies_fp64"]
+    assert applies[1.0] > applies[1e-6]
+    p = mixed(1e-10, 1e-10)
+    p.lowp_trust_tol = -1.0
+    with pytest.raises(Exception, match="lowp_trust_tol"):
+        hp.hp_sternheimer_scf(ctx(name), site, q, p)

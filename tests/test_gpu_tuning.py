@@ -119,7 +119,9 @@ def test_pinning_rejects_bad_shapes():
 def test_register_plane_variants(name):
     """The FP32 register-resident plane round trips (variants 4-6: a y column, then an x row
     or half of one, in a thread's registers; 144-point rows split over two lanes with a DPP
-    exchange in the last radix-2 stage), on the 24x24, 30x24, 72x45 and 144x45 planes: the
+    exchange in the last radix-2 stage; planes kept in LDS compacted to the window of x
+    columns that can hold sphere points, zero inputs outside the x and y windows not
+    loaded), on the 24x24, 30x24, 72x45 and 144x45 planes: the
     reduced-precision H apply (FP32 transforms and projections) against the FP64 oracle to
     FP32 accuracy, against the LDS variant 0 to within the rounding of the FMA choices (the
     butterflies are the same, the compiler may contract them differently), and the
@@ -159,3 +161,27 @@ def test_register_plane_variants(name):
             assert np.abs(y - y0).max() < 5e-7 * np.abs(y0).max(), pv
             assert np.abs(du - du0).max() < 1e-9 * np.abs(du0).max(), pv
     ctx.close()
+
+
+def test_register_window_guard():
+    """A sphere wider than the register variants' window (|m| up to 8 on 24-point x and y
+    axes, whose window [0, 8) u [16, 24) holds m = -8..7): variants 4-6 are refused for it,
+    and the FP32 apply of the variants that remain still meets the FP64 oracle."""
+    import dataclasses
+    import oracle
+    import synth
+    from paper_2203_15684_amd import hp
+    spec = dataclasses.replace(synth.SPECS["sc1_gamma"], name="sc1_gamma_wide", ecut=20.0)
+    gs = synth.build_ground_state(spec, device="cuda")
+    assert max(int(np.abs(e.miller[:, 0]).max()) for e in gs.kpts) >= 8
+    ctx = hp.hp_ground_state_load(gs)
+    for v in (4, 5, 6):
+        with pytest.raises(hp.HpError, match="not available"):
+            hp.hp_set_plane_variant(ctx, 32, v)
+    o = oracle.Oracle(gs)
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((4, gs.kpts[0].npw)) + 1j * rng.standard_normal((4, gs.kpts[0].npw))
+    ref = o.h_apply(0, X)
+    hp.hp_set_plane_variant(ctx, 32, 0)
+    y = hp.hp_apply_h_lowp(ctx, 0, X)
+    assert np.abs(y - ref).max() / np.abs(ref).max() < 2e-6

@@ -168,6 +168,10 @@ SC1_K2_METAL = _reg(replace(SC1_K2, name="sc1_k211_metal", degauss=0.01, n_el=15
 # The olivine-shaped cell with one electron removed (223 in 112 kept bands, cold smearing
 # 0.01 Ha): the top valence band crosses the Fermi level, the next band stays 1.18 Ha above.
 OLIVINE_METAL = _reg(replace(OLIVINE, name="olivine28_metal", degauss=0.01, n_el=223.0, gs_tol=1e-10))
+# its Gamma-only form (entries Gamma and (0, 1/2, 0)): full-size metallic checks against the
+# oracle at a small ground-state cost
+OLIVINE_METAL_G = _reg(replace(OLIVINE_METAL, name="olivine28_metal_gamma", kmesh=(1, 1, 1), qmesh=(1, 2, 1),
+                               gs_tol=1e-12))
 # The two-site cell with one electron removed (23 in 12 kept bands): a metal on a 2x3x1 k mesh.
 DUO_METAL = _reg(replace(DUO, name="duo_k221_metal", degauss=0.01, n_el=23.0))
 
